@@ -1,0 +1,204 @@
+"""Discrete Helmholtz operators of the CPU oracle (test infrastructure only).
+
+Section 2.3 of the paper: Galerkin discretisation of -Lap u - k^2 u = f with
+tensor-product B-splines on the unit interval / square and homogeneous
+Dirichlet conditions (MP 1-B, MP 2-A, MP 2-B of section 2).  The system matrix
+is A = K - M_k, with K the stiffness matrix and M_k the k^2-weighted mass
+matrix.  The paper prints the variational form with the opposite sign of the
+k^2 term; the model problems and the eigenvalues j^2 pi^2 - k^2 it gives for
+MP 1-B (section 3) fix the sign used here.
+
+A non-constant wave number is constant on each element of the finest mesh
+(its value at the element centroid); M_k = sum_e k_e^2 (m_e^y (x) m_e^x).
+Vectors are ordered with x fastest: index i2 * n1 + i1 over interior
+control points.  All matrices are scipy.sparse in float64.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from . import bspline as bs
+
+
+class Problem:
+    """One Helmholtz problem: dimension, degree p, elements per side, wave number.
+
+    k_elem (optional) holds k (not k^2) per finest element, x fastest, shape
+    (n_el_y, n_el_x) in 2D or (n_el,) in 1D; otherwise the constant k is used.
+    """
+
+    def __init__(self, dim, p, n_el, k, k_elem=None):
+        if dim not in (1, 2):
+            raise ValueError("dim must be 1 or 2")
+        self.dim = dim
+        self.p = int(p)
+        self.n_el = [int(n_el)] * dim if np.isscalar(n_el) else [int(v) for v in n_el]
+        self.k = float(k)
+        if k_elem is not None:
+            k_elem = np.asarray(k_elem, dtype=np.float64)
+            shape = tuple(self.n_el[::-1]) if dim == 2 else (self.n_el[0],)
+            k_elem = k_elem.reshape(shape)
+        self.k_elem = k_elem
+
+    @property
+    def k2_elem(self):
+        """k^2 per finest element (array), or None for a constant wave number."""
+        return None if self.k_elem is None else self.k_elem ** 2
+
+
+def matrices_1d(b, p):
+    """Interior (Dirichlet-eliminated) 1D stiffness and mass as sparse matrices."""
+    K, M = bs.assemble_full(b, p)
+    return sp.csr_matrix(bs.interior(K)), sp.csr_matrix(bs.interior(M))
+
+
+def weighted_mass_1d(b, p, w_elem):
+    """Interior 1D mass with element weights w_e (sum_e w_e m_e)."""
+    _, M = bs.assemble_full(b, p, elem_weight=w_elem)
+    return sp.csr_matrix(bs.interior(M))
+
+
+def weighted_mass_2d(bx, by, p, w_elem):
+    """Interior 2D mass sum_e w_e (m^y_{e2} (x) m^x_{e1}); w_elem shape (n_el_y, n_el_x).
+
+    Each element adds its (p+1)^2 x (p+1)^2 local block at the global indices
+    (e2 + a2 - 1, e1 + a1 - 1) of its local functions (a2, a1); functions 0 and
+    n-1 of either direction are eliminated (Dirichlet).
+    """
+    _, Mex = bs.element_matrices(bx, p)
+    _, Mey = bs.element_matrices(by, p)
+    nelx, nely = len(bx) - 1, len(by) - 1
+    n1, n2 = nelx + p - 2, nely + p - 2
+    q = p + 1
+    rows, cols, vals = [], [], []
+    e1 = np.arange(nelx)
+    for e2 in range(nely):
+        for a2 in range(q):
+            i2 = e2 + a2 - 1
+            if i2 < 0 or i2 >= n2:
+                continue
+            for c2 in range(q):
+                j2 = e2 + c2 - 1
+                if j2 < 0 or j2 >= n2:
+                    continue
+                for a1 in range(q):
+                    i1 = e1 + a1 - 1
+                    for c1 in range(q):
+                        j1 = e1 + c1 - 1
+                        ok = (i1 >= 0) & (i1 < n1) & (j1 >= 0) & (j1 < n1)
+                        v = w_elem[e2, ok] * Mey[e2, a2, c2] * Mex[ok, a1, c1]
+                        rows.append(i2 * n1 + i1[ok])
+                        cols.append(j2 * n1 + j1[ok])
+                        vals.append(v)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n1 * n2, n1 * n2))
+
+
+def fine_operators(prob):
+    """Level-0 stiffness K and k^2-weighted mass M_k (sparse, interior)."""
+    p = prob.p
+    if prob.dim == 1:
+        b = bs.uniform_breakpoints(prob.n_el[0])
+        K, M = matrices_1d(b, p)
+        if prob.k_elem is None:
+            Mk = prob.k ** 2 * M
+        else:
+            Mk = weighted_mass_1d(b, p, prob.k2_elem)
+        return K.tocsr(), Mk.tocsr()
+    bx = bs.uniform_breakpoints(prob.n_el[0])
+    by = bs.uniform_breakpoints(prob.n_el[1])
+    Kx, Mx = matrices_1d(bx, p)
+    Ky, My = matrices_1d(by, p)
+    K = sp.kron(My, Kx) + sp.kron(Ky, Mx)
+    if prob.k_elem is None:
+        Mk = prob.k ** 2 * sp.kron(My, Mx)
+    else:
+        Mk = weighted_mass_2d(bx, by, p, prob.k2_elem)
+    return K.tocsr(), Mk.tocsr()
+
+
+def point_source_rhs(prob, x0, amp=1.0):
+    """f_i = amp * Phi_i(x0): the Galerkin load of a point source delta(x - x0).
+
+    MP 1-B and MP 2-A/2-B (section 2) use a unit point source; tested against a
+    basis function it gives the function's value at the source point.
+    """
+    p = prob.p
+    if prob.dim == 1:
+        b = bs.uniform_breakpoints(prob.n_el[0])
+        e = bs.uniform_span(x0[0], prob.n_el[0])
+        return amp * bs.basis_all(b, p, x0[0], elem=e)[1:-1].astype(np.complex128)
+    bx = bs.uniform_breakpoints(prob.n_el[0])
+    by = bs.uniform_breakpoints(prob.n_el[1])
+    ex = bs.uniform_span(x0[0], prob.n_el[0])
+    ey = bs.uniform_span(x0[1], prob.n_el[1])
+    fx = bs.basis_all(bx, p, x0[0], elem=ex)[1:-1]
+    fy = bs.basis_all(by, p, x0[1], elem=ey)[1:-1]
+    return amp * np.kron(fy, fx).astype(np.complex128)
+
+
+def source_spans(prob, x0):
+    """Element indices (per direction) that hold the source point (span rule)."""
+    return [bs.uniform_span(x0[d], prob.n_el[d]) for d in range(prob.dim)]
+
+
+def manufactured_rhs_2d(prob, a, bfreq, nq=None):
+    """Load vector of f = ((a^2 + b^2) pi^2 - k^2) sin(a pi x) sin(b pi y), constant k.
+
+    Its exact solution is u = sin(a pi x) sin(b pi y) (homogeneous Dirichlet).
+    Integrated element by element with nq-point Gauss-Legendre per direction.
+    """
+    p = prob.p
+    nq = nq or (p + 4)
+    bx = bs.uniform_breakpoints(prob.n_el[0])
+    by = bs.uniform_breakpoints(prob.n_el[1])
+    n1 = prob.n_el[0] + p - 2
+    n2 = prob.n_el[1] + p - 2
+    gx, gw = bs.gauss_legendre(nq)
+    lam = (a * a + bfreq * bfreq) * np.pi ** 2 - prob.k ** 2
+    # 1D load integrals of sin(a pi x) times each basis function factorise.
+    def load_1d(b, freq, n_el):
+        out = np.zeros(n_el + p)
+        for e in range(n_el):
+            lo, hi = b[e], b[e + 1]
+            jac = 0.5 * (hi - lo)
+            for xq, wq in zip(gx, gw):
+                x = lo + (xq + 1) * jac
+                v = bs.basis_all(b, p, x, elem=e)
+                out += wq * jac * np.sin(freq * np.pi * x) * v
+        return out[1:-1]
+    fx = load_1d(bx, a, prob.n_el[0])
+    fy = load_1d(by, bfreq, prob.n_el[1])
+    assert len(fx) == n1 and len(fy) == n2
+    return lam * np.kron(fy, fx)
+
+
+def l2_error_2d(prob, u, exact, nq=None):
+    """Continuous L2 norm of (u_h - exact) over the unit square by Gauss quadrature."""
+    p = prob.p
+    nq = nq or (p + 4)
+    bx = bs.uniform_breakpoints(prob.n_el[0])
+    by = bs.uniform_breakpoints(prob.n_el[1])
+    n1 = prob.n_el[0] + p - 2
+    U = np.zeros((prob.n_el[1] + p, prob.n_el[0] + p), dtype=u.dtype)
+    U[1:-1, 1:-1] = u.reshape(prob.n_el[1] + p - 2, n1)
+    gx, gw = bs.gauss_legendre(nq)
+    err2 = 0.0
+    # tabulate 1D basis values at the quadrature points of every element
+    def tab(b, n_el):
+        out = []
+        for e in range(n_el):
+            lo, hi = b[e], b[e + 1]
+            jac = 0.5 * (hi - lo)
+            xs = lo + (gx + 1) * jac
+            out.append((xs, gw * jac, np.array([bs.basis_all(b, p, x, elem=e) for x in xs])))
+        return out
+    tx = tab(bx, prob.n_el[0])
+    ty = tab(by, prob.n_el[1])
+    for ys, wy, By in ty:
+        for xs, wx, Bx in tx:
+            uh = By @ U @ Bx.T                     # (nq_y, nq_x)
+            ex = exact(xs[None, :], ys[:, None])
+            err2 += np.sum(wy[:, None] * wx[None, :] * np.abs(uh - ex) ** 2)
+    return np.sqrt(err2)

@@ -1,0 +1,322 @@
+"""Deflated, multigrid-approximated CSLP preconditioner and FGMRES: CPU oracle.
+
+Test infrastructure only.  Plain float64/complex128 numpy + scipy.sparse, each
+step written as the paper states it (section 3) with the readings below.
+
+  * CSLP (section 3, the shifted-Laplacian preconditioner): M_beta = K -
+    (beta1 + i beta2) M_k, i.e. the shift multiplies the (k^2-weighted) mass
+    matrix of the discretisation rather than the identity.
+  * Its inverse is approximated by multigrid V-cycles with damped Jacobi
+    smoothing (section 3; section 4.2 writes the two-grid form).  Coarse
+    levels come from knot halving; the transfer is the exact knot-insertion
+    prolongation P and restriction P^T; coarse operators are Galerkin
+    P^T (.) P for K and M_k separately; the coarsest level is solved by dense LU.
+  * Deflation (section 3, equation for P = I - AQ): Q = Z E^-1 Z^T with
+    E = Z^T A Z and Z the same knot-insertion prolongation.  It is combined
+    with the CSLP additively as a right preconditioner
+        T(v) = Mtilde^-1 (v - A Q v) + Q v,
+    which uses the same projection I - AQ and keeps the outer Krylov operator A
+    itself.  Multilevel deflation solves E by a fixed number of inner FGMRES
+    iterations preconditioned by the next level's T; the deepest deflation
+    level is solved by dense LU.
+  * Outer Krylov solver (sections 3 and 4.3): restarted flexible GMRES with
+    modified Gram-Schmidt, complex Givens rotations, x0 = 0, stopping when the
+    true relative residual ||f - A u|| / ||f|| is at most tol.
+"""
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import bspline as bs
+from .helmholtz import fine_operators
+
+
+class Options:
+    """Solver parameters (defaults are the configuration the paper's method is run with)."""
+
+    def __init__(self, beta=(1.0, 0.5), omega=0.8, nu_pre=1, nu_post=1, n_vcycles=1,
+                 mg_min_elems=8, coarse_damping=1, defl_mode=2, defl_direct_max=16384,
+                 defl_inner_its=(8, 4, 2, 1, 1, 1, 1, 1), restart=50, maxit=1000, tol=1e-7):
+        self.beta = complex(beta[0], beta[1])
+        self.omega = float(omega)
+        self.nu_pre = int(nu_pre)
+        self.nu_post = int(nu_post)
+        self.n_vcycles = int(n_vcycles)
+        self.mg_min_elems = int(mg_min_elems)
+        self.coarse_damping = int(coarse_damping)
+        self.defl_mode = int(defl_mode)
+        self.defl_direct_max = int(defl_direct_max)
+        self.defl_inner_its = tuple(int(v) for v in defl_inner_its)
+        self.restart = int(restart)
+        self.maxit = int(maxit)
+        self.tol = float(tol)
+
+
+class Level:
+    pass
+
+
+def build_hierarchy(prob, opts):
+    """Levels 0..L: breakpoints per direction, Galerkin K_l, M_k,l, transfers P_l.
+
+    Level l+1 is made from level l by knot halving in every direction; the
+    coarsening stops once every direction has at most mg_min_elems elements.
+    lev[l].P (l >= 1) maps level-l coefficients to level l-1 (interior rows and
+    columns of the knot-insertion matrix; 2D: P_y (x) P_x).
+    """
+    p = prob.p
+    bks = [bs.uniform_breakpoints(n) for n in prob.n_el]
+    K, Mk = fine_operators(prob)
+    levels = []
+    lv = Level()
+    lv.bks, lv.K, lv.Mk, lv.P = bks, K, Mk, None
+    levels.append(lv)
+    while max(len(b) - 1 for b in levels[-1].bks) > opts.mg_min_elems:
+        prev = levels[-1]
+        cb = [bs.halve_breakpoints(b) for b in prev.bks]
+        Ps = [sp.csr_matrix(bs.knot_insertion_prolongation(fb, c, p)[1:-1, 1:-1])
+              for fb, c in zip(prev.bks, cb)]
+        P = Ps[0] if prob.dim == 1 else sp.kron(Ps[1], Ps[0]).tocsr()
+        lv = Level()
+        lv.bks = cb
+        lv.P = P
+        lv.K = (P.T @ prev.K @ P).tocsr()
+        lv.Mk = (P.T @ prev.Mk @ P).tocsr()
+        levels.append(lv)
+    for l, lv in enumerate(levels):
+        lv.n = [len(b) - 1 + p - 2 for b in lv.bks]
+        lv.N = int(np.prod(lv.n))
+        lv.A = (lv.K - lv.Mk).tocsr()
+        lv.Mb = (lv.K - opts.beta * lv.Mk).tocsr()
+        lv.D = lv.Mb.diagonal().copy()
+        lv.gersh = gershgorin_bound(lv.Mb, lv.D)
+        lv.omega = smoother_damping(l, lv.gersh, opts)
+    # coarsest multigrid level: dense LU of M_beta
+    levels[-1].Mb_lu = sla.lu_factor(levels[-1].Mb.toarray())
+    return levels
+
+
+def gershgorin_bound(Mb, D):
+    """max_i sum_j |M_beta[i, j]| / |D_i|: a bound on the spectral radius of D^-1 M_beta."""
+    rowsum = np.asarray(abs(Mb).sum(axis=1)).ravel()
+    return float(np.max(rowsum / np.abs(D)))
+
+
+def smoother_damping(l, gersh, opts):
+    """Jacobi damping at level l.
+
+    The finest level uses omega as given.  On coarse levels the k^2-weighted
+    B-spline mass dominates M_beta and D^-1 M_beta has eigenvalues beyond
+    2/omega, so omega-Jacobi would amplify instead of smooth; with
+    coarse_damping on, coarse levels use omega_l = min(omega, 2 / g_l), g_l the
+    Gershgorin bound above (keeps |1 - omega_l lambda| bounded for every
+    eigenvalue lambda of D^-1 M_beta in the disc the bound gives).
+    """
+    if l == 0 or opts.coarse_damping == 0:
+        return opts.omega
+    return min(opts.omega, 2.0 / gersh)
+
+
+def deflation_levels(levels, opts):
+    """Index L_z of the deflation level solved directly (0 when deflation is off).
+
+    two-level: L_z = 1.  multilevel: the first level l >= 1 with at most
+    defl_direct_max unknowns (never deeper than the coarsest multigrid level).
+    """
+    L = len(levels) - 1
+    if opts.defl_mode == 0 or L == 0:
+        return 0
+    if opts.defl_mode == 1:
+        return 1
+    for l in range(1, L + 1):
+        if levels[l].N <= opts.defl_direct_max:
+            return l
+    return L
+
+
+class Solver:
+    """The oracle's preconditioned solver for one problem."""
+
+    def __init__(self, prob, opts=None):
+        self.prob = prob
+        self.opts = opts or Options()
+        self.levels = build_hierarchy(prob, self.opts)
+        self.Lz = deflation_levels(self.levels, self.opts)
+        if self.Lz > 0:
+            self.E_lu = sla.lu_factor(self.levels[self.Lz].A.toarray())
+
+    # ---- multigrid on the CSLP --------------------------------------------
+    def jacobi(self, l, b, x):
+        """One damped Jacobi sweep x <- x + omega_l D^-1 (b - M_beta x)."""
+        lv = self.levels[l]
+        return x + lv.omega * (b - lv.Mb @ x) / lv.D
+
+    def vcycle_once(self, l, b):
+        """One V(nu_pre, nu_post) cycle on M_beta,l from a zero initial guess."""
+        lv = self.levels[l]
+        if l == len(self.levels) - 1:
+            return sla.lu_solve(lv.Mb_lu, b)
+        x = np.zeros_like(b)
+        for _ in range(self.opts.nu_pre):
+            x = self.jacobi(l, b, x)
+        r = b - lv.Mb @ x
+        Pn = self.levels[l + 1].P
+        x = x + Pn @ self.vcycle_once(l + 1, Pn.T @ r)
+        for _ in range(self.opts.nu_post):
+            x = self.jacobi(l, b, x)
+        return x
+
+    def vcycle(self, l, b):
+        """n_vcycles V-cycles as the iteration x <- x + V(b - M_beta x), x0 = 0."""
+        x = self.vcycle_once(l, b)
+        for _ in range(self.opts.n_vcycles - 1):
+            x = x + self.vcycle_once(l, b - self.levels[l].Mb @ x)
+        return x
+
+    # ---- deflation ---------------------------------------------------------
+    def coarse_solve(self, l, c):
+        """E^-1 c at deflation level l: dense LU at L_z, else inner FGMRES."""
+        if l == self.Lz:
+            return sla.lu_solve(self.E_lu, c)
+        m = self.opts.defl_inner_its[min(l - 1, len(self.opts.defl_inner_its) - 1)]
+        x, _ = fgmres_fixed(lambda v: self.levels[l].A @ v, lambda v: self.T(l, v), c, m)
+        return x
+
+    def T(self, l, v):
+        """Preconditioner at level l: Mtilde^-1 (v - A Q v) + Q v, Q = P E^-1 P^T."""
+        if self.Lz == 0 or l >= self.Lz:
+            return self.vcycle(l, v)
+        Pn = self.levels[l + 1].P
+        q = Pn @ self.coarse_solve(l + 1, Pn.T @ v)
+        w = v - self.levels[l].A @ q
+        return self.vcycle(l, w) + q
+
+    def solve(self, f, u0=None, history=False):
+        A0 = self.levels[0].A
+        return fgmres(lambda v: A0 @ v, lambda v: self.T(0, v), f, self.opts.restart,
+                      self.opts.tol, self.opts.maxit, u0=u0, history=history)
+
+
+# ---- Krylov ----------------------------------------------------------------
+
+def givens(a, b):
+    """Complex rotation (c real, s complex) with [c s; -conj(s) c] (a, b) = (r, 0).
+
+    b == 0: c = 1, s = 0.  a == 0: c = 0, s = conj(b)/|b|.  Otherwise
+    t = sqrt(|a|^2 + |b|^2), c = |a|/t, s = (a/|a|) conj(b)/t.
+    """
+    if b == 0:
+        return 1.0, 0.0 + 0.0j
+    if a == 0:
+        return 0.0, np.conj(b) / abs(b)
+    t = np.sqrt(abs(a) ** 2 + abs(b) ** 2)
+    return abs(a) / t, (a / abs(a)) * np.conj(b) / t
+
+
+def _arnoldi_cycle(Aop, Top, r0, m, stop_abs, record):
+    """One FGMRES cycle of at most m steps from residual r0; returns the update.
+
+    Arnoldi with modified Gram-Schmidt (h_ij = v_i^H w), Givens QR of the
+    Hessenberg matrix, upper-triangular solve, update sum_i z_i y_i.  The cycle
+    stops early when |g_{j+1}| <= stop_abs or on breakdown (h_{j+1,j} == 0).
+    """
+    n = r0.shape[0]
+    beta = np.linalg.norm(r0)
+    if beta == 0.0:
+        return np.zeros(n, dtype=np.complex128), 0, 0.0
+    V = [r0 / beta]
+    Z = []
+    H = np.zeros((m + 1, m), dtype=np.complex128)
+    cs = np.zeros(m)
+    sn = np.zeros(m, dtype=np.complex128)
+    g = np.zeros(m + 1, dtype=np.complex128)
+    g[0] = beta
+    j_done = 0
+    for j in range(m):
+        z = Top(V[j])
+        Z.append(z)
+        w = Aop(z)
+        for i in range(j + 1):
+            H[i, j] = np.vdot(V[i], w)
+            w = w - H[i, j] * V[i]
+        hn = np.linalg.norm(w)
+        H[j + 1, j] = hn
+        for i in range(j):
+            t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+            H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + cs[i] * H[i + 1, j]
+            H[i, j] = t
+        cs[j], sn[j] = givens(H[j, j], H[j + 1, j])
+        H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+        H[j + 1, j] = 0.0
+        g[j + 1] = -np.conj(sn[j]) * g[j]
+        g[j] = cs[j] * g[j]
+        j_done = j + 1
+        if record is not None:
+            record.append(abs(g[j + 1]))
+        if hn == 0.0 or abs(g[j + 1]) <= stop_abs:
+            break
+        V.append(w / hn)
+    y = np.zeros(j_done, dtype=np.complex128)
+    for i in range(j_done - 1, -1, -1):
+        y[i] = (g[i] - H[i, i + 1:j_done] @ y[i + 1:]) / H[i, i]
+    dx = np.zeros(n, dtype=np.complex128)
+    for i in range(j_done):
+        dx = dx + Z[i] * y[i]
+    return dx, j_done, abs(g[j_done])
+
+
+def fgmres_fixed(Aop, Top, b, m):
+    """Exactly m FGMRES steps from x0 = 0 (fewer only on breakdown); no restart."""
+    dx, its, _ = _arnoldi_cycle(Aop, Top, b.astype(np.complex128), m, -1.0, None)
+    return dx, its
+
+
+class SolveInfo:
+    def __init__(self):
+        self.iters = 0
+        self.restarts = 0
+        self.relres_true = np.nan
+        self.relres_est = np.nan
+        self.converged = False
+        self.history = []
+
+
+def fgmres(Aop, Top, f, restart, tol, maxit, u0=None, history=False):
+    """Restarted FGMRES(restart) on A u = f with right preconditioner T.
+
+    Iterations count Arnoldi steps.  After each cycle the true residual
+    f - A u is recomputed; the solve stops when ||f - A u|| <= tol ||f||, or
+    after maxit steps (not converged).
+    """
+    f = np.asarray(f, dtype=np.complex128)
+    info = SolveInfo()
+    nf = np.linalg.norm(f)
+    u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.complex128)
+    if nf == 0.0:
+        info.relres_true = 0.0
+        info.relres_est = 0.0
+        info.converged = True
+        return np.zeros_like(f), info
+    r = f - Aop(u)
+    rec = [] if history else None
+    while True:
+        if np.linalg.norm(r) <= tol * nf:
+            info.converged = True
+            break
+        if info.iters >= maxit:
+            break
+        m = min(restart, maxit - info.iters)
+        dx, its, gres = _arnoldi_cycle(Aop, Top, r, m, tol * nf, rec)
+        u = u + dx
+        info.iters += its
+        info.relres_est = gres / nf
+        r = f - Aop(u)
+        if its == 0:
+            break
+        info.restarts += 1
+    info.restarts = max(info.restarts - 1, 0)
+    info.relres_true = np.linalg.norm(r) / nf
+    info.converged = info.relres_true <= tol
+    if history:
+        info.history = rec
+    return u, info

@@ -1,0 +1,454 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests retypes an oracle formula: each checks the oracle against
+an independent fact (a worked example printed in the paper, a closed form, an
+identity, a textbook special case or brute force).
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import bspline as bs
+from oracle import helmholtz as hz
+from oracle import solver as osv
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- basis ----
+
+def test_basis_matches_paper_worked_example():
+    """Section 2.3.1 figure: linear and quadratic basis on Xi_1 and Xi_2."""
+    with open(os.path.join(GOLDEN, "bspline_example.json")) as fh:
+        data = json.load(fh)
+    xs = np.linspace(0.0, 3.0, 61)[:-1] + 0.013
+    for case in data["cases"]:
+        p = case["p"]
+        b = np.array(case["breakpoints"], dtype=float)
+        for j, pieces in enumerate(case["functions"]):
+            for x in xs:
+                expect = 0.0
+                for lo, hi, expr in pieces:
+                    if lo <= x < hi:
+                        expect = eval(expr, {"x": x})
+                got = bs.basis_all(b, p, x)[j]
+                assert abs(got - expect) < 1e-14, (p, j, x, got, expect)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_partition_of_unity_and_support(p):
+    """Section 2.3.1: sum_j phi_j = 1; phi_j vanishes outside [xi_j, xi_{j+p+1})."""
+    b = bs.uniform_breakpoints(7)
+    xi = bs.open_knot_vector(b, p)
+    rng = np.random.default_rng(p)
+    for x in np.concatenate([rng.random(50), [0.0, 1.0, 3 / 7]]):
+        v = bs.basis_all(b, p, x)
+        assert abs(v.sum() - 1.0) < 1e-14
+        assert np.all(v >= -1e-15)
+        for j in range(len(v)):
+            if x < xi[j] or (x >= xi[j + p + 1] and x < 1.0):
+                assert v[j] == 0.0
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_continuity_at_simple_knots(p):
+    """Section 2.3.1: C^{p-1} at simple knots; checked for values and first derivatives."""
+    b = bs.uniform_breakpoints(5)
+    for e in range(1, 5):
+        x = b[e]
+        vl, dl = bs.basis_and_derivative_all(b, p, x, elem=e - 1)
+        vr, dr = bs.basis_and_derivative_all(b, p, x, elem=e)
+        assert np.allclose(vl, vr, atol=1e-13)
+        assert np.allclose(dl, dr, atol=1e-11)
+
+
+def test_interpolatory_at_the_ends():
+    for p in range(1, 6):
+        b = bs.uniform_breakpoints(6)
+        v0 = bs.basis_all(b, p, 0.0)
+        v1 = bs.basis_all(b, p, 1.0)
+        assert v0[0] == 1.0 and np.all(v0[1:] == 0)
+        assert abs(v1[-1] - 1.0) < 1e-15 and np.all(np.abs(v1[:-1]) < 1e-15)
+
+
+# ----------------------------------------------------------- stencils ------
+
+def cardinal_bspline(m, x):
+    """Cardinal B-spline of order m (degree m-1) on [0, m], exact in Fractions.
+
+    N_m(x) = 1/(m-1)! sum_k (-1)^k C(m,k) (x-k)_+^{m-1} (explicit formula,
+    independent of the Cox-de Boor recursion and of quadrature).
+    """
+    x = Fraction(x)
+    s = Fraction(0)
+    for k in range(m + 1):
+        t = x - k
+        if t > 0:
+            s += (-1) ** k * math.comb(m, k) * t ** (m - 1)
+    return s / math.factorial(m - 1)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_interior_mass_and_stiffness_stencils(p):
+    """Interior rows of M and K on a uniform mesh equal the cardinal-spline closed forms.
+
+    Mass row offsets d = -p..p: h * N_{2p+2}(p+1+d); stiffness row:
+    -(1/h) * (N_{2p}(p+d-1) - 2 N_{2p}(p+d) + N_{2p}(p+d+1)).
+    """
+    n_el = 4 * p + 6
+    h = 1.0 / n_el
+    b = bs.uniform_breakpoints(n_el)
+    K, M = bs.assemble_full(b, p)
+    i = (n_el + p) // 2
+    for d in range(-p, p + 1):
+        m_exact = float(cardinal_bspline(2 * p + 2, p + 1 + d)) * h
+        c = lambda t: cardinal_bspline(2 * p, t)
+        k_exact = -float(c(p + d - 1) - 2 * c(p + d) + c(p + d + 1)) / h
+        assert abs(M[i, i + d] - m_exact) < 1e-14 * max(1.0, abs(m_exact) / h) * h
+        assert abs(K[i, i + d] - k_exact) < 1e-11 / h
+
+
+def test_p1_stencils_closed_form():
+    """p = 1: stiffness [-1, 2, -1]/h and mass h/6 [1, 4, 1]."""
+    n_el = 10
+    h = 0.1
+    K, M = hz.matrices_1d(bs.uniform_breakpoints(n_el), 1)
+    K, M = K.toarray(), M.toarray()
+    assert np.allclose(np.diag(K), 2 / h) and np.allclose(np.diag(K, 1), -1 / h)
+    assert np.allclose(np.diag(M), 4 * h / 6) and np.allclose(np.diag(M, 1), h / 6)
+    assert np.count_nonzero(np.abs(K) > 1e-12) == 3 * (n_el - 1) - 2
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("n_el", [5, 8, 13])
+def test_full_matrix_identities(p, n_el):
+    """Before elimination: sum_ij M_ij = |Omega| = 1 and K 1 = 0 (constants in the kernel)."""
+    K, M = bs.assemble_full(bs.uniform_breakpoints(n_el), p)
+    assert abs(M.sum() - 1.0) < 1e-13
+    assert np.max(np.abs(K @ np.ones(K.shape[0]))) < 1e-9 * n_el
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_generalized_eigenvalues_approach_j2pi2(p):
+    """Section 3: the eigenvalues of MP 1-B are j^2 pi^2 - k^2; the discrete (K, M) pencil
+    reproduces j^2 pi^2 for the low modes with error O(h^{2p})."""
+    errs = []
+    for n_el in (16, 32):
+        K, M = hz.matrices_1d(bs.uniform_breakpoints(n_el), p)
+        lam = np.sort(sla.eigh(K.toarray(), M.toarray(), eigvals_only=True))[:3]
+        exact = np.array([1, 4, 9]) * np.pi ** 2
+        errs.append(np.abs(lam - exact) / exact)
+    assert np.all(errs[1] < 10.0 ** (-p - 1))
+    rate = np.log2(errs[0][2] / errs[1][2])
+    assert rate > 2 * p - 0.5
+
+
+# ------------------------------------------------------- prolongation ------
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("n_el", [16, 17, 9])
+def test_knot_insertion_prolongation(p, n_el):
+    """phi^c_J = sum_i P_iJ phi^f_i pointwise; rows sum to 1; interior column 2^-p C(p+1, j)."""
+    bf = bs.uniform_breakpoints(n_el)
+    bc = bs.halve_breakpoints(bf)
+    P = bs.knot_insertion_prolongation(bf, bc, p)
+    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-13)
+    rng = np.random.default_rng(0)
+    for x in rng.random(30):
+        assert np.allclose(bs.basis_all(bc, p, x), bs.basis_all(bf, p, x) @ P, atol=1e-13)
+    # an interior coarse function, far from the ends and from a short last element
+    if len(bc) - 1 < 2 * p + 3:
+        return
+    J = (len(bc) - 1 + p) // 2 - 1
+    col = P[:, J]
+    nz = np.nonzero(np.abs(col) > 1e-14)[0]
+    expect = np.array([math.comb(p + 1, j) for j in range(p + 2)]) / 2 ** p
+    assert len(nz) == p + 2
+    assert np.allclose(col[nz], expect, atol=1e-14)
+
+
+def test_p3_interior_stencil_equals_paper_transpose_stencil():
+    """Section 3: the restriction stencil (1/8)[1, 4, 6, 4, 1] printed for Z^T equals the
+    p = 3 knot-insertion interior column."""
+    bf = bs.uniform_breakpoints(24)
+    P = bs.knot_insertion_prolongation(bf, bs.halve_breakpoints(bf), 3)
+    col = P[:, 7]
+    assert np.allclose(col[np.abs(col) > 1e-14], np.array([1, 4, 6, 4, 1]) / 8)
+
+
+def test_halving_odd_counts_keeps_last_breakpoint():
+    b = bs.uniform_breakpoints(7)
+    c = bs.halve_breakpoints(b)
+    assert np.allclose(c, [0, 2 / 7, 4 / 7, 6 / 7, 1.0])
+    c2 = bs.halve_breakpoints(c)
+    assert np.allclose(c2, [0, 4 / 7, 1.0])
+
+
+# -------------------------------------------------------- Galerkin ---------
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("n_el", [12, 13])
+def test_galerkin_equals_rediscretisation_1d(p, n_el):
+    """Nested spline spaces, exact quadrature: P^T K_f P = K_c and P^T M_f P = M_c."""
+    bf = bs.uniform_breakpoints(n_el)
+    bc = bs.halve_breakpoints(bf)
+    Kf, Mf = bs.assemble_full(bf, p)
+    Kc, Mc = bs.assemble_full(bc, p)
+    P = bs.knot_insertion_prolongation(bf, bc, p)
+    assert np.allclose(P.T @ Kf @ P, Kc, atol=1e-11 * n_el)
+    assert np.allclose(P.T @ Mf @ P, Mc, atol=1e-14)
+
+
+def test_galerkin_variable_k_equals_fine_element_quadrature():
+    """Variable k: the Galerkin coarse mass equals sum over FINE elements of k_e^2 times the
+    integral of products of COARSE basis functions (computed here by brute-force quadrature)."""
+    p, n_el = 2, 8
+    rng = np.random.default_rng(3)
+    ke = 5 + 10 * rng.random((n_el, n_el))
+    prob = hz.Problem(2, p, n_el, 1.0, k_elem=ke)
+    lev = osv.build_hierarchy(prob, osv.Options(mg_min_elems=4))
+    Mk1 = lev[1].Mk.toarray()
+    bf = bs.uniform_breakpoints(n_el)
+    bc = bs.halve_breakpoints(bf)
+    gx, gw = np.polynomial.legendre.leggauss(6)
+    nc = len(bc) - 1 + p
+    ref = np.zeros((nc * nc, nc * nc))
+    for e2 in range(n_el):
+        for e1 in range(n_el):
+            for qy, wy in zip(gx, gw):
+                y = bf[e2] + (qy + 1) * 0.5 / n_el
+                vy = bs.basis_all(bc, p, y)
+                for qx, wx in zip(gx, gw):
+                    x = bf[e1] + (qx + 1) * 0.5 / n_el
+                    vx = bs.basis_all(bc, p, x)
+                    phi = np.kron(vy, vx)
+                    ref += ke[e2, e1] ** 2 * wy * wx * 0.25 / n_el ** 2 * np.outer(phi, phi)
+    idx = [i2 * nc + i1 for i2 in range(1, nc - 1) for i1 in range(1, nc - 1)]
+    ref = ref[np.ix_(idx, idx)]
+    assert np.allclose(Mk1, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+# --------------------------------------------------- discretisation --------
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_manufactured_solution_rate(p):
+    """Section 4.1: L2 error O(h^{p+1}); manufactured u = sin(pi x) sin(2 pi y), k = 3."""
+    errs = []
+    for n_el in (8, 16):
+        prob = hz.Problem(2, p, n_el, 3.0)
+        K, Mk = hz.fine_operators(prob)
+        f = hz.manufactured_rhs_2d(prob, 1, 2)
+        u = spla.spsolve((K - Mk).tocsc(), f)
+        errs.append(hz.l2_error_2d(prob, u, lambda x, y: np.sin(np.pi * x) * np.sin(2 * np.pi * y)))
+    rate = np.log2(errs[0] / errs[1])
+    assert rate > p + 1 - 0.35, (errs, rate)
+
+
+def test_green_function_1d():
+    """MP 1-B: the solution of -u'' - k^2 u = delta(x - x') with Dirichlet ends is
+    sin(k min(x,x')) sin(k (1 - max(x,x'))) / (k sin k) (the sum of the paper's series)."""
+    k, xs = 10.0, 0.37
+    g = lambda x: np.sin(k * np.minimum(x, xs)) * np.sin(k * (1 - np.maximum(x, xs))) / (k * np.sin(k))
+    for p in (2, 3):
+        n_el = 256
+        prob = hz.Problem(1, p, n_el, k)
+        K, Mk = hz.fine_operators(prob)
+        f = hz.point_source_rhs(prob, (xs,))
+        u = spla.spsolve((K - Mk).tocsc().astype(complex), f)
+        b = bs.uniform_breakpoints(n_el)
+        for x in (0.1, 0.2, 0.6, 0.9):
+            uh = bs.basis_all(b, p, x)[1:-1] @ u
+            assert abs(uh - g(x)) < 1e-4 * abs(g(np.array(0.2)))
+
+
+def test_green_series_matches_closed_form():
+    """The paper's eigen-series for MP 1-B sums to the closed form used above."""
+    k, xs, x = 10.0, 0.37, 0.8
+    j = np.arange(1, 200001)
+    series = 2 * np.sum(np.sin(j * np.pi * x) * np.sin(j * np.pi * xs) / (j ** 2 * np.pi ** 2 - k ** 2))
+    closed = np.sin(k * xs) * np.sin(k * (1 - x)) / (k * np.sin(k))
+    assert abs(series - closed) < 1e-5
+
+
+def test_point_source_spans_and_values():
+    """f_i = Phi_i(x0); span rule: floor(x n_el) capped at n_el - 1, x = 1 -> last element."""
+    prob = hz.Problem(2, 3, 480, 100.0)
+    assert hz.source_spans(prob, (0.5, 0.95)) == [240, 456]
+    assert hz.source_spans(prob, (1.0, 0.0)) == [479, 0]
+    f = hz.point_source_rhs(prob, (0.3, 0.7)).real
+    # partition of unity of the full tensor basis; interior source -> all mass interior
+    assert abs(f.sum() - 1.0) < 1e-14
+    assert np.count_nonzero(f) <= (3 + 1) ** 2
+
+
+# ---------------------------------------------------------- symmetry -------
+
+def test_operators_real_symmetric():
+    rng = np.random.default_rng(1)
+    prob = hz.Problem(2, 3, 12, 20.0, k_elem=20 + 5 * rng.random((12, 12)))
+    lev = osv.build_hierarchy(prob, osv.Options())
+    for lv in lev:
+        assert abs(lv.A - lv.A.T).max() < 1e-12 * abs(lv.A).max()
+        assert lv.A.dtype == np.float64
+
+
+def test_beta_sign_flip_conjugates_iterates():
+    """A and f real: flipping the sign of beta2 conjugates every iterate (C2 reading)."""
+    prob = hz.Problem(2, 2, 24, 15.0)
+    f = hz.point_source_rhs(prob, (0.5, 0.5))
+    s1 = osv.Solver(prob, osv.Options(beta=(1, 0.5), defl_mode=1))
+    s2 = osv.Solver(prob, osv.Options(beta=(1, -0.5), defl_mode=1))
+    u1, i1 = s1.solve(f)
+    u2, i2 = s2.solve(f)
+    assert i1.iters == i2.iters
+    assert np.allclose(u1, np.conj(u2), rtol=0, atol=1e-12 * np.abs(u1).max())
+
+
+# --------------------------------------------------------- multigrid -------
+
+def test_two_grid_vcycle_closed_form():
+    """Section 4.2 two-grid form: V(b) = (I - E_TG) M^-1 b with
+    E_TG = S^nu2 (I - P M_c^-1 P^T M) S^nu1, S = I - omega D^-1 M (dense, tiny mesh)."""
+    for nu1, nu2 in ((1, 1), (2, 1)):
+        prob = hz.Problem(2, 2, 10, 6.0)
+        opts = osv.Options(mg_min_elems=5, nu_pre=nu1, nu_post=nu2, defl_mode=0)
+        s = osv.Solver(prob, opts)
+        assert len(s.levels) == 2
+        M = s.levels[0].Mb.toarray()
+        Mc = s.levels[1].Mb.toarray()
+        P = s.levels[1].P.toarray()
+        w = s.levels[0].omega
+        S = np.eye(M.shape[0]) - w * np.diag(1 / np.diag(M)) @ M
+        ETG = (np.linalg.matrix_power(S, nu2) @ (np.eye(M.shape[0]) - P @ np.linalg.solve(Mc, P.T @ M))
+               @ np.linalg.matrix_power(S, nu1))
+        b = np.random.default_rng(0).random(M.shape[0]) + 1j * np.random.default_rng(1).random(M.shape[0])
+        ref = (np.eye(M.shape[0]) - ETG) @ np.linalg.solve(M, b)
+        assert np.allclose(s.vcycle(0, b), ref, atol=1e-11 * np.abs(ref).max())
+
+
+def test_coarse_damping_bounds_jacobi():
+    """Coarse-level damping omega_l <= 2/rho(D^-1 M_beta): Gershgorin bound checked by dense eig."""
+    prob = hz.Problem(2, 3, 16, 10.0)
+    s = osv.Solver(prob, osv.Options(defl_mode=0))
+    for l, lv in enumerate(s.levels[:-1]):
+        Mb = lv.Mb.toarray()
+        rho = np.max(np.abs(np.linalg.eigvals(Mb / lv.D[:, None])))
+        assert lv.gersh >= rho * (1 - 1e-12)
+        if l > 0:
+            assert lv.omega <= 2 / rho + 1e-15
+        else:
+            assert lv.omega == 0.8
+
+
+# --------------------------------------------------------- deflation -------
+
+def _tiny_two_level():
+    prob = hz.Problem(2, 2, 12, 9.0)
+    s = osv.Solver(prob, osv.Options(defl_mode=1, mg_min_elems=3))
+    A = s.levels[0].A.toarray()
+    Z = s.levels[1].P.toarray()
+    E = Z.T @ A @ Z
+    Q = Z @ np.linalg.solve(E, Z.T)
+    return s, A, Z, Q
+
+
+def test_deflation_identities():
+    """Section 3: P_D = I - A Q with Q = Z E^-1 Z^T, E = Z^T A Z: P_D A Z = 0, P_D^2 = P_D,
+    Q A Z = Z; and A T(A Z c) = A Z c for the preconditioner T."""
+    s, A, Z, Q = _tiny_two_level()
+    I = np.eye(A.shape[0])
+    PD = I - A @ Q
+    assert np.abs(PD @ A @ Z).max() < 1e-10 * np.abs(A).max()
+    assert np.abs(PD @ PD - PD).max() < 1e-10
+    assert np.abs(Q @ A @ Z - Z).max() < 1e-10
+    c = np.random.default_rng(0).random(Z.shape[1]) + 0j
+    v = A @ Z @ c
+    assert np.allclose(A @ s.T(0, v), v, atol=1e-10 * np.abs(v).max())
+
+
+def test_deflated_operator_zero_eigenvalues():
+    """Section 4.2: deflation maps n_c eigenvalues (n_c = columns of Z) to zero."""
+    s, A, Z, Q = _tiny_two_level()
+    PD = np.eye(A.shape[0]) - A @ Q
+    Mt = np.array([s.vcycle(0, e.astype(complex)) for e in np.eye(A.shape[0])]).T
+    ev = np.linalg.eigvals(PD @ A @ Mt)
+    nz = np.sum(np.abs(ev) < 1e-8 * np.abs(ev).max())
+    assert nz >= Z.shape[1]
+
+
+def test_multilevel_with_exact_inner_equals_two_level():
+    """Inner FGMRES with as many steps as unknowns solves E exactly (breakdown-free, full
+    Krylov space), so the multilevel T equals the two-level T with a direct E."""
+    prob = hz.Problem(2, 2, 12, 9.0)
+    two = osv.Solver(prob, osv.Options(defl_mode=1, mg_min_elems=3))
+    N1 = two.levels[1].N
+    multi = osv.Solver(prob, osv.Options(defl_mode=2, mg_min_elems=3, defl_direct_max=30,
+                                          defl_inner_its=(N1, 100, 100)))
+    assert multi.Lz >= 2
+    v = np.random.default_rng(2).random(two.levels[0].N) + 0.5j
+    a, b = two.T(0, v), multi.T(0, v)
+    assert np.allclose(a, b, atol=1e-8 * np.abs(a).max())
+
+
+# ----------------------------------------------------------- FGMRES --------
+
+def test_givens_special_cases():
+    c, s = osv.givens(3 + 4j, 0.0)
+    assert c == 1 and s == 0
+    c, s = osv.givens(0.0, 2.0)
+    assert c == 0 and abs(s - 1) < 1e-15
+    a, b = 1 - 2j, 0.7
+    c, s = osv.givens(a, b)
+    assert abs(-np.conj(s) * a + c * b) < 1e-15
+    assert abs(abs(c * a + s * b) - np.hypot(abs(a), abs(b))) < 1e-14
+
+
+def test_fgmres_exact_preconditioner_one_step_and_identity_is_lu():
+    rng = np.random.default_rng(4)
+    n = 40
+    A = rng.random((n, n)) + n * np.eye(n)
+    f = rng.random(n) + 1j * rng.random(n)
+    u, info = osv.fgmres(lambda v: A @ v, lambda v: np.linalg.solve(A, v), f, 50, 1e-12, 100)
+    assert info.iters == 1
+    u2, info2 = osv.fgmres(lambda v: A @ v, lambda v: v, f, n, 1e-300, n)
+    assert np.allclose(u2, np.linalg.solve(A, f), rtol=1e-10)
+
+
+def test_fgmres_residual_estimate_is_true_residual():
+    """Right preconditioning: |g_{j+1}| after j steps equals ||f - A u_j|| (exact arithmetic)."""
+    prob = hz.Problem(2, 2, 16, 10.0)
+    s = osv.Solver(prob, osv.Options(defl_mode=1, mg_min_elems=4))
+    f = hz.point_source_rhs(prob, (0.4, 0.6))
+    _, full = s.solve(f, history=True)
+    A = s.levels[0].A
+    for j in range(1, min(full.iters, 6)):
+        s2 = osv.Solver(prob, osv.Options(defl_mode=1, mg_min_elems=4, maxit=j, restart=50))
+        u, _ = s2.solve(f)
+        true = np.linalg.norm(f - A @ u)
+        assert abs(true - full.history[j - 1]) < 1e-9 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("cfg", ["1d", "2d"])
+def test_solver_matches_direct_solve(cfg):
+    """The converged iterate is within kappa * tol of the direct solution."""
+    if cfg == "1d":
+        prob, x0, opts = hz.Problem(1, 2, 80, 50.0), (0.5,), osv.Options(defl_mode=1)
+    else:
+        prob, x0, opts = hz.Problem(2, 3, 32, 20.0), (0.5, 0.5), osv.Options()
+    s = osv.Solver(prob, opts)
+    f = hz.point_source_rhs(prob, x0)
+    u, info = s.solve(f)
+    assert info.converged and info.relres_true <= 1e-7
+    A = s.levels[0].A.toarray()
+    ud = np.linalg.solve(A, f)
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) <= kappa * 1e-7
+    # the exact solution is real (A, f real); the iterate's imaginary part is at tolerance level
+    assert np.linalg.norm(u.imag) <= kappa * 1e-7 * np.linalg.norm(ud)
