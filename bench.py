@@ -1,0 +1,159 @@
+"""Benchmark: deflated, multigrid-approximated CSLP + FGMRES solve of the B-spline
+Helmholtz system on one MI355X.
+
+One step = one complete solve to ||f - A u|| <= 1e-7 ||f|| (every kernel of
+the hot path: operator applies, V-cycles, transfers, deflation, Arnoldi/MGS,
+Givens, updates) on a right-hand side already resident in HBM.  The metric is
+DoF-iterations per second: N x (outer FGMRES iterations) / solve time.
+
+Prints ONE JSON line.  Extra fields: `roofline` for the kernel class that takes
+the most device time in the solve (timed live with HIP events on the library's
+stream inside the timed region) and `cpu_baseline` (the CPU oracle timed on
+the host, same workload, one thread).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from paper_2010_10232_amd import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+CLASS_NAMES = {1: "finest-level operator (stencil) kernel", 2: "dense E^-1 product (direct deflation level)",
+               3: "outer Arnoldi MGS kernel"}
+
+WORKLOADS = {
+    # configs[1]: MP 2-A mesh of the paper's table (k = 100, p = 3, 160 x 160 elements)
+    "mp2a_k100_p3_160": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict()),
+    # configs[0]
+    "mp1b_k50_p2_80": dict(dim=1, p=2, n_el=80, k=50.0, x0=(0.5,), opts=dict(defl_mode=1)),
+    # configs[2] (p = 3 member), FP64 or mixed
+    "wedge_k150_p3_480": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict()),
+    # configs[4] plain form
+    "grf_k300_p4_960": dict(dim=2, p=4, n_el=960, grf=300.0, x0=(0.5, 0.5), opts=dict()),
+}
+
+
+def k_field(w):
+    if "wedge" in w:
+        return W.wedge_k(w["n_el"], w["wedge"])
+    if "grf" in w:
+        return W.grf_k(w["n_el"], kbar=w["grf"], seed=0)
+    return None
+
+
+def cpu_baseline(w, seconds_cap=30.0):
+    """The CPU oracle on the same workload (one thread), solve only (setup excluded)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import helmholtz as hz
+    from oracle import solver as osv
+    with threadpool_limits(limits=1):
+        ke = k_field(w)
+        op = hz.Problem(w["dim"], w["p"], w["n_el"], w.get("k", 1.0), k_elem=ke)
+        s = osv.Solver(op, osv.Options(**w["opts"]))
+        f = hz.point_source_rhs(op, w["x0"])
+        t0 = time.perf_counter()
+        u, info = s.solve(f)
+        dt = time.perf_counter() - t0
+    N = s.levels[0].N
+    return {"value": N * info.iters / dt, "unit": "DoF-iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full solve of the same workload ({info.iters} iterations, {dt:.1f} s, setup excluded)",
+            "iters": info.iters}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mp2a_k100_p3_160", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32 V-cycle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2010_10232_amd import binding as B
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    ke = k_field(w)
+    t0 = time.perf_counter()
+    prob = B.Problem(w["dim"], w["p"], w["n_el"], k=w.get("k"), k_elem=ke)
+    solver = B.Solver(prob, precision=args.precision, **w["opts"])
+    f = prob.point_source(w["x0"])
+    u = torch.empty_like(f)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    N = prob.N
+
+    for _ in range(args.warmup):
+        solver.solve(f, u)
+    # dominant kernel class: the one with the most device time in one solve
+    per_class = {}
+    for cls in (1, 2, 3):
+        solver.set_kernel_timing(cls)
+        _, inf = solver.solve(f, u)
+        per_class[cls] = inf["op_ms_total"]
+    dom = max(per_class, key=per_class.get)
+    solver.set_kernel_timing(dom)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, k_ms, k_n, k_bytes = [], 0.0, 0, 0.0
+    infos = []
+    for _ in range(args.steps):
+        _, inf = solver.solve(f, u)
+        infos.append(inf)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for inf in infos:
+        iters.append(inf["iters"])
+        k_ms += inf["op_ms_total"]
+        k_n += inf["op_launches"]
+        k_bytes += inf["op_bytes_per_launch"] * inf["op_launches"]
+    solver.set_kernel_timing(0)
+    ms_per_step = dt * 1e3 / args.steps
+    value = N * sum(iters) / dt
+    achieved = (k_bytes / (k_ms * 1e-3)) / 1e9 if k_ms > 0 else None
+    out = {
+        "metric": "DoF-iterations/s of the deflated MG-CSLP FGMRES solve to 1e-7 relative residual",
+        "value": value,
+        "unit": "DoF-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dim": w["dim"], "p": w["p"], "n_el": w["n_el"],
+                   "N": N, "precision": "fp64" if args.precision == 0 else "mixed (fp32 V-cycle)",
+                   "iters_per_solve": iters[0], "relres_true": infos[-1]["relres_true"],
+                   "setup_s": round(t_setup, 3), "solve_ms": ms_per_step},
+        "roofline": {"bound": "hbm", "kernel": CLASS_NAMES[dom],
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "launches": k_n, "avg_us": (k_ms * 1e3 / k_n) if k_n else None,
+                     "bytes_per_launch": (k_bytes / k_n) if k_n else None,
+                     "class_ms_per_solve": {CLASS_NAMES[c]: round(v, 4) for c, v in per_class.items()}},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * hh.h - C ABI of the MI355X (gfx950) isogeometric Helmholtz solver.
+ *
+ * Solves A u = f for the B-spline Galerkin discretisation of
+ *     -Lap u - k^2 u = f  on (0,1)^d, d = 1 or 2, u = 0 on the boundary
+ * (the model problems MP 1-B, MP 2-A and MP 2-B, section 2 of Dwarka, Tielen,
+ * Moeller and Vuik, "Towards accuracy and scalability: combining isogeometric
+ * analysis with deflation ...").  A = K - M_k with K the stiffness matrix and
+ * M_k the k^2-weighted mass matrix of section 2.3; A is real symmetric and
+ * indefinite.  The solver is restarted flexible GMRES, right-preconditioned by
+ * the deflated complex shifted Laplacian of section 3: multigrid V-cycles with
+ * damped Jacobi smoothing on M_beta = K - (beta1 + i beta2) M_k, and the
+ * deflation Q = Z E^-1 Z^T, E = Z^T A Z, with Z the knot-insertion prolongation.
+ *
+ * Conventions
+ *  - Vectors are complex double (interleaved re, im; 16 bytes per entry) in
+ *    DEVICE memory owned by the caller, indexed i2 * n1 + i1 over interior
+ *    control points (x fastest; 1D uses n2 = 1).  n_d = n_el_d + p - 2 at the
+ *    finest level; coarse levels are reported by hh_level_info.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *    Calls enqueue on that stream; hh_solve, hh_setup and hh_assemble return
+ *    after the stream has drained.
+ *  - Every entry point returns an hh_status.  Errors are negative and leave
+ *    the objects unchanged; hh_last_error() gives a thread-local message.
+ *    No C++ exception crosses this interface.
+ *  - Objects are not thread-safe; one object may be used by one thread at a
+ *    time.  Calls on different solvers may run concurrently on different
+ *    streams.
+ */
+#ifndef HH_H
+#define HH_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int hh_status;
+#define HH_OK 0
+#define HH_ENOCONV 1       /* warning: maxit reached; the best iterate is returned */
+#define HH_EINVAL (-1)     /* invalid argument */
+#define HH_ENOMEM (-2)     /* device or host allocation failed */
+#define HH_EHIP (-3)       /* a HIP runtime call failed */
+#define HH_ENUMERIC (-4)   /* NaN/Inf met in the Krylov recurrence */
+
+typedef struct hh_problem hh_problem;
+typedef struct hh_solver hh_solver;
+
+/* Problem statement (section 2): unit interval / square, uniform open knot
+ * vectors of degree p (ends repeated p+1 times, section 2.3.1), homogeneous
+ * Dirichlet conditions, constant or element-wise wave number. */
+typedef struct {
+    int dim;               /* 1 or 2 */
+    int p;                 /* B-spline degree, 1..5 */
+    int n_el[2];           /* elements in x and y (n_el[1] ignored when dim == 1); >= 2 */
+    int k_mode;            /* 0: constant k; 1: one k per finest element */
+    double k;              /* the constant wave number (k_mode 0), > 0 */
+    const double* k_elem;  /* k_mode 1: HOST array of k (not k^2) per element,
+                              x fastest, n_el[0] * n_el[1] values (n_el[0] in 1D);
+                              copied, the caller may free it on return */
+} hh_problem_desc;
+
+/* Preconditioner and Krylov parameters (hh_default_opts fills the defaults). */
+typedef struct {
+    double beta[2];          /* CSLP shift beta1 + i beta2 (section 3); default 1, 0.5 */
+    double omega;            /* Jacobi damping on the finest level; default 0.8 */
+    int nu_pre, nu_post;     /* smoothing sweeps; default 1, 1 */
+    int n_vcycles;           /* V-cycles per preconditioner application; default 1 */
+    int mg_min_elems;        /* coarsen while some direction has more elements; default 8 */
+    int coarse_damping;      /* 1: coarse levels use min(omega, 2/g_l), g_l the Gershgorin
+                                bound of D^-1 M_beta,l; 0: omega everywhere; default 1 */
+    int defl_mode;           /* 0 none, 1 two-level, 2 multilevel; default 2 */
+    int defl_direct_max;     /* multilevel: first level with at most this many unknowns is
+                                solved directly; default 16384 */
+    int defl_inner_its[8];   /* fixed inner FGMRES steps at deflation levels 1..8;
+                                default 8, 4, 2, 1, 1, 1, 1, 1 */
+    int restart;             /* outer FGMRES restart length, 1..200; default 50 */
+    int maxit;               /* outer Arnoldi steps cap; default 1000 */
+    double tol;              /* stop at ||f - A u|| <= tol ||f||; default 1e-7 */
+    int precision;           /* 0: all FP64; 1: V-cycle in FP32, rest FP64; default 0 */
+    int time_kernels;        /* kernel class timed with HIP events during hh_solve (results
+                                in hh_solve_info): 0 none (default), 1 finest-level operator
+                                (stencil) kernels, 2 dense E^-1 product of the direct
+                                deflation level, 3 outer Arnoldi MGS kernels */
+} hh_solver_opts;
+
+typedef struct {
+    int iters;               /* outer Arnoldi steps */
+    int restarts;            /* completed restarts */
+    int converged;           /* 1 if ||f - A u|| <= tol ||f|| */
+    double relres_true;      /* ||f - A u|| / ||f||, recomputed in FP64 */
+    double relres_est;       /* |g_{j+1}| / ||f|| of the last Arnoldi step */
+    double t_solve_ms;       /* wall time of hh_solve (host clock, stream drained) */
+    double op_ms_total;      /* time_kernels: summed device time of the timed kernel class */
+    int op_launches;         /* time_kernels: number of such launches */
+    double op_bytes_per_launch; /* algorithmic HBM bytes per launch of that class (mean) */
+} hh_solve_info;
+
+typedef struct {
+    int n[2];                /* interior unknowns per direction at this level */
+    int n_el[2];             /* elements per direction */
+    long long N;             /* n[0] * n[1] */
+    double omega;            /* Jacobi damping used at this level */
+    double gersh;            /* Gershgorin bound g_l of D^-1 M_beta,l */
+    int n_levels;            /* multigrid levels (finest = 0) */
+    int defl_direct_level;   /* L_z: deflation level solved directly (0: no deflation) */
+} hh_level_stats;
+
+/* Debug / parity operators of hh_apply. */
+#define HH_OP_A        0   /* y = A_l x */
+#define HH_OP_MBETA    1   /* y = M_beta,l x */
+#define HH_OP_JACOBI0  2   /* y = omega_l D_l^-1 x (first sweep from a zero guess) */
+#define HH_OP_RESTRICT 3   /* y (level l+1) = P_{l+1}^T x (level l) */
+#define HH_OP_PROLONG  4   /* y (level l) = P_{l+1} x (level l+1) */
+#define HH_OP_VCYCLE   5   /* y = V-cycle(s) from level l applied to x */
+#define HH_OP_T        6   /* y = T_l x: deflated CSLP preconditioner at level l */
+#define HH_OP_EINV     7   /* y = E^-1 x at deflation level l >= 1 (direct or inner FGMRES) */
+
+/* Fills *o with the defaults listed above. */
+void hh_default_opts(hh_solver_opts* o);
+
+/* Thread-local message of the last error ("" if none). */
+const char* hh_last_error(void);
+
+/* Builds the problem: knot vectors, element matrices (Gauss-Legendre,
+ * p+1 points), k^2 per element (section 2.3).  Host work plus small uploads. */
+hh_status hh_assemble(const hh_problem_desc* d, hh_problem** out);
+
+/* Idempotent on NULL. */
+hh_status hh_problem_destroy(hh_problem* pr);
+
+/* Interior unknowns per direction at the finest level (n[1] = 1 in 1D). */
+hh_status hh_problem_size(const hh_problem* pr, int n[2]);
+
+/* Element (knot-span) index holding x0 per direction: floor(x0 * n_el), with
+ * x0 == 1 mapped to the last element (the half-open span rule of section
+ * 2.3.1).  x0 outside [0,1] -> HH_EINVAL. */
+hh_status hh_point_spans(const hh_problem* pr, const double* x0, int* spans);
+
+/* Point source load f_i = amp * Phi_i(x0) (the Galerkin load of amp * delta(x - x0),
+ * MP 1-B / MP 2-A / MP 2-B).  f_dev: device, N complex doubles, overwritten. */
+hh_status hh_rhs_point_source(const hh_problem* pr, const double* x0, double amp,
+                              void* f_dev, void* stream);
+
+/* Builds the multigrid / deflation hierarchy and allocates all device workspace
+ * (section 3): coarse knot vectors by knot halving, knot-insertion transfers,
+ * Galerkin coarse operators, Jacobi diagonals, the dense inverse of the coarsest
+ * M_beta and of the deflation matrix at L_z.  The solver keeps a reference to
+ * the problem, which must outlive it. */
+hh_status hh_setup(const hh_problem* pr, const hh_solver_opts* o, void* stream,
+                   hh_solver** out);
+
+/* Idempotent on NULL. */
+hh_status hh_solver_destroy(hh_solver* s);
+
+/* Solves A u = f.  f_dev, u_dev: device, N complex doubles.  use_u0 = 1 starts
+ * from the contents of u_dev, else from zero.  Returns HH_ENOCONV (with the last
+ * iterate in u_dev) when maxit is reached.  info may be NULL. */
+hh_status hh_solve(hh_solver* s, const void* f_dev, void* u_dev, int use_u0,
+                   hh_solve_info* info, void* stream);
+
+/* Level sizes and parameters; level in [0, n_levels). */
+hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out);
+
+/* Selects the kernel class timed during later hh_solve calls (values as for
+ * hh_solver_opts.time_kernels); 0 turns timing off. */
+hh_status hh_set_kernel_timing(hh_solver* s, int cls);
+
+/* Applies one building block of the preconditioner (HH_OP_*) at `level` to a
+ * device vector: for checking against a reference implementation.  x_dev and
+ * y_dev must not overlap. */
+hh_status hh_apply(hh_solver* s, int op, int level, const void* x_dev, void* y_dev,
+                   void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HH_H */

@@ -10,6 +10,6 @@ ctypes.  The binding is imported lazily so that the input generators in
 
 def __getattr__(name):
     if name == "binding":
-        from . import binding
-        return binding
+        import importlib
+        return importlib.import_module(__name__ + ".binding")
     raise AttributeError(name)

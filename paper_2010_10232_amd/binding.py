@@ -1,0 +1,232 @@
+"""ctypes binding of the C ABI in include/hh.h (argument marshalling only).
+
+Device memory and streams come from PyTorch: vectors are complex128 CUDA
+(HIP) tensors, passed by data pointer; the stream is torch's current stream.
+Every computation runs in libhh.so; there is no fallback path: loading fails
+loudly when the library is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhh.so")
+
+HH_OK, HH_ENOCONV = 0, 1
+HH_EINVAL, HH_ENOMEM, HH_EHIP, HH_ENUMERIC = -1, -2, -3, -4
+
+OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 5, "T": 6, "EINV": 7}
+
+EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
+            "hh_point_spans", "hh_rhs_point_source", "hh_setup", "hh_solver_destroy", "hh_solve",
+            "hh_level_info", "hh_apply", "hh_set_kernel_timing"]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("p", ctypes.c_int), ("n_el", ctypes.c_int * 2),
+                ("k_mode", ctypes.c_int), ("k", ctypes.c_double),
+                ("k_elem", ctypes.POINTER(ctypes.c_double))]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double * 2), ("omega", ctypes.c_double),
+                ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int), ("n_vcycles", ctypes.c_int),
+                ("mg_min_elems", ctypes.c_int), ("coarse_damping", ctypes.c_int),
+                ("defl_mode", ctypes.c_int), ("defl_direct_max", ctypes.c_int),
+                ("defl_inner_its", ctypes.c_int * 8), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
+                ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("time_kernels", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("op_ms_total", ctypes.c_double),
+                ("op_launches", ctypes.c_int), ("op_bytes_per_launch", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LevelStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 2), ("n_el", ctypes.c_int * 2), ("N", ctypes.c_longlong),
+                ("omega", ctypes.c_double), ("gersh", ctypes.c_double), ("n_levels", ctypes.c_int),
+                ("defl_direct_level", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Loads libhh.so once (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_2010_10232_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.hh_default_opts.argtypes = [ctypes.POINTER(SolverOpts)]
+    lib.hh_default_opts.restype = None
+    lib.hh_last_error.restype = ctypes.c_char_p
+    lib.hh_assemble.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(vp)]
+    lib.hh_problem_destroy.argtypes = [vp]
+    lib.hh_problem_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.hh_point_spans.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    lib.hh_rhs_point_source.argtypes = [vp, ctypes.POINTER(ctypes.c_double), dp, vp, vp]
+    lib.hh_setup.argtypes = [vp, ctypes.POINTER(SolverOpts), vp, ctypes.POINTER(vp)]
+    lib.hh_solver_destroy.argtypes = [vp]
+    lib.hh_solve.argtypes = [vp, vp, vp, ip, ctypes.POINTER(SolveInfo), vp]
+    lib.hh_level_info.argtypes = [vp, ip, ctypes.POINTER(LevelStats)]
+    lib.hh_apply.argtypes = [vp, ip, ip, vp, vp, vp]
+    lib.hh_set_kernel_timing.argtypes = [vp, ip]
+    for name in EXPORTED:
+        if name not in ("hh_default_opts", "hh_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class HHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hh error {code}: {msg}")
+        self.code = code
+
+
+def _check(code, allow=(HH_OK,)):
+    if code not in allow:
+        raise HHError(code, load().hh_last_error().decode())
+    return code
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise ValueError("expected a contiguous complex128 device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_opts(**kw):
+    o = SolverOpts()
+    load().hh_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "beta":
+            o.beta[0], o.beta[1] = float(v[0]), float(v[1])
+        elif k == "defl_inner_its":
+            vals = list(v) + [list(v)[-1]] * 8
+            for i in range(8):
+                o.defl_inner_its[i] = int(vals[i])
+        elif hasattr(o, k):
+            setattr(o, k, v)
+        else:
+            raise KeyError(k)
+    return o
+
+
+class Problem:
+    """A Helmholtz problem on (0,1)^dim: degree p, n_el elements per direction,
+    constant k or k_elem (k per finest element, x fastest)."""
+
+    def __init__(self, dim, p, n_el, k=None, k_elem=None):
+        lib = load()
+        d = ProblemDesc()
+        d.dim, d.p = int(dim), int(p)
+        ne = [int(n_el)] * 2 if np.isscalar(n_el) else [int(v) for v in n_el] + [1]
+        d.n_el[0], d.n_el[1] = ne[0], ne[1]
+        self._k_arr = None
+        if k_elem is not None:
+            self._k_arr = np.ascontiguousarray(np.asarray(k_elem, dtype=np.float64).ravel())
+            d.k_mode, d.k = 1, 0.0
+            d.k_elem = self._k_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            d.k_mode, d.k = 0, float(k)
+        h = ctypes.c_void_p()
+        _check(lib.hh_assemble(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        n = (ctypes.c_int * 2)()
+        _check(lib.hh_problem_size(h, n))
+        self.n = (n[0], n[1])
+        self.N = n[0] * n[1]
+        self.dim = dim
+
+    def spans(self, x0):
+        x = (ctypes.c_double * 2)(*(list(x0) + [0.0] * (2 - len(x0))))
+        out = (ctypes.c_int * 2)()
+        _check(load().hh_point_spans(self._h, x, out))
+        return [out[i] for i in range(self.dim)]
+
+    def point_source(self, x0, amp=1.0, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.complex128, device="cuda")
+        x = (ctypes.c_double * 2)(*(list(x0) + [0.0] * (2 - len(x0))))
+        _check(load().hh_rhs_point_source(self._h, x, float(amp), _ptr(out), _stream()))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().hh_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """Multigrid/deflation hierarchy and FGMRES workspace for one Problem."""
+
+    def __init__(self, problem, **opts):
+        self.problem = problem  # keeps the problem alive
+        self.opts = default_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(load().hh_setup(problem._h, ctypes.byref(self.opts), _stream(), ctypes.byref(h)))
+        self._h = h
+        self.levels = [self.level_info(l) for l in range(self.level_info(0)["n_levels"])]
+
+    def level_info(self, level):
+        st = LevelStats()
+        _check(load().hh_level_info(self._h, int(level), ctypes.byref(st)))
+        return {"n": (st.n[0], st.n[1]), "n_el": (st.n_el[0], st.n_el[1]), "N": st.N,
+                "omega": st.omega, "gersh": st.gersh, "n_levels": st.n_levels,
+                "defl_direct_level": st.defl_direct_level}
+
+    def set_kernel_timing(self, cls):
+        """0 off, 1 finest-level operator, 2 dense E^-1 product, 3 outer MGS kernels."""
+        _check(load().hh_set_kernel_timing(self._h, int(cls)))
+
+    def solve(self, f, u=None, use_u0=False):
+        import torch
+        if u is None:
+            u = torch.empty_like(f)
+        info = SolveInfo()
+        code = load().hh_solve(self._h, _ptr(f), _ptr(u), int(use_u0), ctypes.byref(info), _stream())
+        _check(code, allow=(HH_OK, HH_ENOCONV))
+        return u, info.as_dict()
+
+    def apply(self, op, level, x, out_level=None):
+        import torch
+        lvl = level if out_level is None else out_level
+        y = torch.empty(self.levels[lvl]["N"], dtype=torch.complex128, device=x.device)
+        _check(load().hh_apply(self._h, OPS[op], int(level), _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().hh_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,233 @@
+// C ABI entry points (include/hh.h): argument checks, error capture, dispatch.
+#include <cmath>
+#include <cstring>
+
+#include "solver.h"
+
+namespace hh {
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace hh
+
+using namespace hh;
+
+#define HH_TRY try {
+#define HH_CATCH                                          \
+    }                                                     \
+    catch (const Err& e) {                                \
+        set_error(e.msg);                                 \
+        return e.code;                                    \
+    }                                                     \
+    catch (const std::bad_alloc&) {                       \
+        set_error("host allocation failed");              \
+        return HH_ENOMEM;                                 \
+    }                                                     \
+    catch (const std::exception& e) {                     \
+        set_error(e.what());                              \
+        return HH_EINVAL;                                 \
+    }
+
+extern "C" {
+
+void hh_default_opts(hh_solver_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->beta[0] = 1.0;
+    o->beta[1] = 0.5;
+    o->omega = 0.8;
+    o->nu_pre = 1;
+    o->nu_post = 1;
+    o->n_vcycles = 1;
+    o->mg_min_elems = 8;
+    o->coarse_damping = 1;
+    o->defl_mode = 2;
+    o->defl_direct_max = 16384;
+    const int its[8] = {8, 4, 2, 1, 1, 1, 1, 1};
+    for (int i = 0; i < 8; ++i) o->defl_inner_its[i] = its[i];
+    o->restart = 50;
+    o->maxit = 1000;
+    o->tol = 1e-7;
+    o->precision = 0;
+    o->time_kernels = 0;
+}
+
+const char* hh_last_error(void) { return g_err.c_str(); }
+
+hh_status hh_assemble(const hh_problem_desc* d, hh_problem** out) {
+    HH_TRY
+    if (!out) throw Err{HH_EINVAL, "out is NULL"};
+    *out = nullptr;
+    ProblemImpl* P = build_problem(d);
+    auto* h = new hh_problem();
+    h->impl = std::move(*P);
+    delete P;
+    *out = h;
+    set_error("");
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_problem_destroy(hh_problem* pr) {
+    delete pr;
+    return HH_OK;
+}
+
+hh_status hh_problem_size(const hh_problem* pr, int n[2]) {
+    HH_TRY
+    if (!pr || !n) throw Err{HH_EINVAL, "NULL argument"};
+    n[0] = pr->impl.ax0.n;
+    n[1] = pr->impl.ay0.n;
+    return HH_OK;
+    HH_CATCH
+}
+
+static int span_of(double x, int nel) {
+    int e = (int)std::floor(x * nel);
+    return e < nel - 1 ? e : nel - 1;
+}
+
+hh_status hh_point_spans(const hh_problem* pr, const double* x0, int* spans) {
+    HH_TRY
+    if (!pr || !x0 || !spans) throw Err{HH_EINVAL, "NULL argument"};
+    const ProblemImpl& P = pr->impl;
+    for (int d = 0; d < P.dim; ++d) {
+        if (!(x0[d] >= 0.0 && x0[d] <= 1.0)) throw Err{HH_EINVAL, "source point outside [0,1]^d"};
+        spans[d] = span_of(x0[d], P.nel[d]);
+    }
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_rhs_point_source(const hh_problem* pr, const double* x0, double amp, void* f_dev, void* stream) {
+    HH_TRY
+    if (!pr || !x0 || !f_dev) throw Err{HH_EINVAL, "NULL argument"};
+    const ProblemImpl& P = pr->impl;
+    int spans[2] = {0, 0};
+    int st = hh_point_spans(pr, x0, spans);
+    if (st != HH_OK) return st;
+    const int p = P.p;
+    std::vector<double> fx(P.ax0.n, 0.0), fy(P.ay0.n, 0.0);
+    double Nv[8];
+    basis_values(P.ax0.U, p, spans[0] + p, x0[0], Nv, nullptr);
+    for (int a = 0; a <= p; ++a) {
+        int i = spans[0] + a - 1;
+        if (i >= 0 && i < P.ax0.n) fx[i] = Nv[a];
+    }
+    if (P.dim == 2) {
+        basis_values(P.ay0.U, p, spans[1] + p, x0[1], Nv, nullptr);
+        for (int a = 0; a <= p; ++a) {
+            int i = spans[1] + a - 1;
+            if (i >= 0 && i < P.ay0.n) fy[i] = Nv[a];
+        }
+    } else {
+        fy[0] = 1.0;
+    }
+    std::vector<cx<double>> f((size_t)P.N());
+    for (int i2 = 0; i2 < P.ay0.n; ++i2)
+        for (int i1 = 0; i1 < P.ax0.n; ++i1) f[(size_t)i2 * P.ax0.n + i1] = {amp * fy[i2] * fx[i1], 0.0};
+    hipStream_t s = (hipStream_t)stream;
+    HH_HIP(hipMemcpyAsync(f_dev, f.data(), f.size() * sizeof(cx<double>), hipMemcpyHostToDevice, s));
+    HH_HIP(hipStreamSynchronize(s));
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_setup(const hh_problem* pr, const hh_solver_opts* o, void* stream, hh_solver** out) {
+    HH_TRY
+    if (!pr || !out) throw Err{HH_EINVAL, "NULL argument"};
+    *out = nullptr;
+    auto impl = std::make_unique<SolverImpl>();
+    impl->prob = &pr->impl;
+    if (o)
+        impl->o = *o;
+    else
+        hh_default_opts(&impl->o);
+    impl->setup((hipStream_t)stream);
+    auto* h = new hh_solver();
+    h->impl = std::move(impl);
+    *out = h;
+    set_error("");
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_solver_destroy(hh_solver* s) {
+    delete s;
+    return HH_OK;
+}
+
+hh_status hh_solve(hh_solver* s, const void* f_dev, void* u_dev, int use_u0, hh_solve_info* info, void* stream) {
+    HH_TRY
+    if (!s || !f_dev || !u_dev) throw Err{HH_EINVAL, "NULL argument"};
+    if (f_dev == u_dev) throw Err{HH_EINVAL, "f and u must not alias"};
+    return s->impl->solve((const cx<double>*)f_dev, (cx<double>*)u_dev, use_u0, info, (hipStream_t)stream);
+    HH_CATCH
+}
+
+hh_status hh_set_kernel_timing(hh_solver* s, int cls) {
+    HH_TRY
+    if (!s) throw Err{HH_EINVAL, "NULL solver"};
+    if (cls < 0 || cls > 3) throw Err{HH_EINVAL, "timing class must be 0..3"};
+    s->impl->o.time_kernels = cls;
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out) {
+    HH_TRY
+    if (!s || !out) throw Err{HH_EINVAL, "NULL argument"};
+    const SolverImpl& S = *s->impl;
+    if (level < 0 || level > S.L) throw Err{HH_EINVAL, "level out of range"};
+    const LevelDev& lv = *S.lev[level];
+    out->n[0] = lv.n1;
+    out->n[1] = lv.n2;
+    out->n_el[0] = lv.ax.nel;
+    out->n_el[1] = lv.ay.nel;
+    out->N = lv.N;
+    out->omega = lv.omega;
+    out->gersh = lv.gersh;
+    out->n_levels = S.L + 1;
+    out->defl_direct_level = S.Lz;
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_apply(hh_solver* s, int op, int level, const void* x_dev, void* y_dev, void* stream) {
+    HH_TRY
+    if (!s || !x_dev || !y_dev) throw Err{HH_EINVAL, "NULL argument"};
+    if (x_dev == y_dev) throw Err{HH_EINVAL, "x and y must not alias"};
+    SolverImpl& S = *s->impl;
+    hipStream_t st = (hipStream_t)stream;
+    if (level < 0 || level > S.L) throw Err{HH_EINVAL, "level out of range"};
+    auto x = (const cx<double>*)x_dev;
+    auto y = (cx<double>*)y_dev;
+    LevelDev& lv = *S.lev[level];
+    switch (op) {
+        case HH_OP_A: S.op<double>(level, MODE_APPLY, false, x, nullptr, y, st); break;
+        case HH_OP_MBETA: S.op<double>(level, MODE_APPLY, true, x, nullptr, y, st); break;
+        case HH_OP_JACOBI0:
+            launch_jacobi0<double>(lv.N, lv.Dinv64.as<cx<double>>(), lv.omega, x, y, st);
+            break;
+        case HH_OP_RESTRICT:
+            if (level >= S.L) throw Err{HH_EINVAL, "no coarser level"};
+            launch_restrict<double>(lv.tr, x, y, st);
+            break;
+        case HH_OP_PROLONG:
+            if (level >= S.L) throw Err{HH_EINVAL, "no coarser level"};
+            launch_prolong<double>(lv.tr, x, y, 0, st);
+            break;
+        case HH_OP_VCYCLE: S.precond_vcycle(level, x, y, st); break;
+        case HH_OP_T: S.T_apply(level, x, y, st); break;
+        case HH_OP_EINV:
+            if (S.Lz == 0 || level < 1 || level > S.Lz) throw Err{HH_EINVAL, "not a deflation level"};
+            S.coarse_solve(level, x, y, st);
+            break;
+        default: throw Err{HH_EINVAL, "unknown operator"};
+    }
+    HH_HIP(hipGetLastError());
+    HH_HIP(hipStreamSynchronize(st));
+    return HH_OK;
+    HH_CATCH
+}
+
+}  // extern "C"

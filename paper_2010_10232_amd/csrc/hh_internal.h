@@ -1,0 +1,192 @@
+// Internal declarations of the isogeometric Helmholtz library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hh.h"
+
+namespace hh {
+
+// ---------------------------------------------------------------- errors --
+struct Err {
+    int code;
+    std::string msg;
+};
+
+void set_error(const std::string& msg);
+
+#define HH_HIP(x)                                                                   \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess)                                                       \
+            throw ::hh::Err{HH_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define HH_REQUIRE(cond, msg)                                   \
+    do {                                                        \
+        if (!(cond)) throw ::hh::Err{HH_EINVAL, std::string(msg)}; \
+    } while (0)
+
+// --------------------------------------------------------------- complex --
+template <class T>
+struct cx {
+    T re, im;
+};
+
+// Device buffer with owning semantics.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t n) {
+        release();
+        if (n == 0) return;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            p = nullptr;
+            throw Err{HH_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+        }
+        bytes = n;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Upload a host vector into a fresh device buffer (synchronous copy).
+template <class T>
+void upload(DevBuf& b, const std::vector<T>& h) {
+    b.alloc(h.size() * sizeof(T));
+    if (!h.empty()) HH_HIP(hipMemcpy(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// ------------------------------------------------------------ host setup --
+// One coordinate direction at one multigrid level.
+struct Axis {
+    int p = 0;          // degree (0 for the trivial second direction of 1D problems)
+    int nel = 1;        // elements at this level
+    int n = 1;          // interior unknowns
+    int off = 0;        // Dirichlet shift: interior index = full index - off
+    int nel_fine = 1;   // elements of the finest level (k^2 is piecewise on these)
+    int level = 0;
+    std::vector<double> bk;  // breakpoints
+    std::vector<double> U;   // full open knot vector
+    std::vector<double> Kb, Mb;  // interior bands [n][2p+1] (entry (i, i+d) at i*(2p+1)+d+p)
+    std::vector<double> Me;      // element mass blocks [nel][(p+1)^2]
+    std::vector<double> G;       // mass blocks of this level's basis on every finest element
+    // prolongation from the next-coarser level (this axis is the fine side):
+    int pw = 1, rw = 1;          // row width (coarse entries per fine row), column width
+    std::vector<int> prow0;      // per fine row: first coarse index
+    std::vector<double> prow;    // per fine row: pw weights
+    std::vector<int> pcol0;      // per coarse column: first fine index
+    std::vector<double> pcol;    // per coarse column: rw weights
+};
+
+// Host-side builders (setup.cpp).
+void gauss_legendre(int n, double* x, double* w);
+Axis make_axis(int p, int nel_fine, int level);
+Axis make_trivial_axis();
+void make_transfer(Axis& fine, const Axis& coarse);
+// Element-wise k^2-weighted Galerkin mass of `level` as a full stencil, SoA
+// [(2px+1)(2py+1)][N] (k2: finest-element k^2, [nel_fine_y][nel_fine_x]).
+void galerkin_mass_stencil(const Axis& ax, const Axis& ay, const std::vector<double>& k2,
+                           std::vector<double>& S);
+void basis_values(const std::vector<double>& U, int p, int span, double x, double* N, double* dN);
+
+// ------------------------------------------------------ device-side data --
+enum OpKind { KIND_SEP = 0, KIND_VARFINE = 1, KIND_STENCIL = 2 };
+enum OpMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_SMOOTH = 2 };
+
+// Arguments of the level-operator kernels: y = K x - alpha M_k x (+ epilogue).
+template <class T>
+struct OpArgs {
+    int n1, n2;
+    const double* Kx;
+    const double* Mx;
+    const double* Ky;
+    const double* My;
+    double k2c;            // KIND_SEP: constant k^2
+    const double* k2;      // KIND_VARFINE: finest-element k^2 [nel2][nel1]
+    int nel1, nel2, off1, off2;
+    const double* Mex;     // KIND_VARFINE: element mass [nel1][(px+1)^2]
+    const double* Mey;     // [nel2][(py+1)^2]
+    const T* S;            // KIND_STENCIL: [(2px+1)(2py+1)][n1*n2]
+    T are, aim;            // alpha
+    const cx<T>* x;
+    const cx<T>* b;
+    cx<T>* y;
+    const cx<T>* dinv;
+    T omega;
+};
+
+struct Transfer {
+    int nf1, nf2, nc1, nc2;
+    int pw1, pw2, rw1, rw2;
+    const int* prow0x;
+    const double* prowx;
+    const int* prow0y;
+    const double* prowy;
+    const int* pcol0x;
+    const double* pcolx;
+    const int* pcol0y;
+    const double* pcoly;
+};
+
+// State of one FGMRES instance (device memory), m = max Arnoldi steps.
+struct KrylovDev {
+    cx<double>* H;    // (m+1) x m, column j at H + j*(m+1)
+    double* cs;       // m
+    cx<double>* sn;   // m
+    cx<double>* g;    // m+1
+    cx<double>* y;    // m
+    double* scal;     // [0] beta, [1] hn, [2] |g_{j+1}|, [3] norm accumulator
+    int* ints;        // [0] jdone, [1] breakdown flag, [2] reduction counter
+    cx<double>* partials;  // reduction partials (max 1024)
+    int m;
+};
+
+// Kernel launchers (kernels.hip; op_p<degree>.hip for the level operator).
+template <int P, class T>
+void launch_op_deg(int kind, int mode, int py, const OpArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_op(int kind, int mode, int px, int py, const OpArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s);
+template <class T>
+void launch_prolong(const Transfer& t, const cx<T>* e, cx<T>* x, int add, hipStream_t s);
+template <class T>
+void launch_jacobi0(long long N, const cx<T>* dinv, T omega, const cx<T>* b, cx<T>* x, hipStream_t s);
+template <class T>
+void launch_axpy(long long N, const cx<T>* x, cx<T>* y, hipStream_t s);           // y += x
+void launch_add(long long N, const cx<double>* a, const cx<double>* b, cx<double>* y, hipStream_t s);
+void launch_copy(long long N, const cx<double>* x, cx<double>* y, hipStream_t s);
+void launch_zero(long long N, cx<double>* y, hipStream_t s);
+void launch_cast_d2f(long long N, const cx<double>* x, cx<float>* y, hipStream_t s);
+void launch_cast_f2d(long long N, const cx<float>* x, cx<double>* y, hipStream_t s);
+template <class TM, class TV>
+void launch_gemv(int n, const TM* A, const cx<TV>* x, cx<TV>* y, hipStream_t s);
+// Krylov kernels
+int reduction_blocks(long long N);
+void launch_norm_init(long long N, const cx<double>* r, KrylovDev& k, hipStream_t s);  // beta = ||r||, g = [beta,0..], state reset
+void launch_scale_by(long long N, const cx<double>* x, cx<double>* y, const double* by, hipStream_t s);  // y = x / *by (0 -> 0)
+void launch_mgs(long long N, int i, int j, cx<double>* w, const cx<double>* V, long long ldv,
+                KrylovDev& k, hipStream_t s);
+void launch_norm_givens(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv,
+                        KrylovDev& k, hipStream_t s);
+void launch_lsq(KrylovDev& k, hipStream_t s);
+void launch_update(long long N, const cx<double>* Z, long long ldz, KrylovDev& k, cx<double>* u,
+                   int accumulate, hipStream_t s);
+void launch_dot_norm2(long long N, const cx<double>* x, double* out, int* counter, cx<double>* partials,
+                      hipStream_t s);
+
+}  // namespace hh

@@ -1,0 +1,511 @@
+// HIP kernels for gfx950 (CDNA4, wave64): knot-insertion transfers, pointwise
+// updates, dense products of the direct coarse solves, and the deterministic
+// reductions of the Arnoldi process.  The level-operator kernels are in
+// op_kernel.h.
+#include "hh_internal.h"
+
+namespace hh {
+
+template <class T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// --------------------------------------------------------------------------
+// Level operator: kernels live in op_kernel.h, one translation unit per degree.
+// --------------------------------------------------------------------------
+template <class T>
+void launch_op(int kind, int mode, int px, int py, const OpArgs<T>& a, hipStream_t s) {
+    if (a.n1 <= 0 || a.n2 <= 0) return;
+    if (py != 0 && py != px) throw Err{HH_EINVAL, "unsupported degree pair"};
+    switch (px) {
+        case 1: return launch_op_deg<1, T>(kind, mode, py, a, s);
+        case 2: return launch_op_deg<2, T>(kind, mode, py, a, s);
+        case 3: return launch_op_deg<3, T>(kind, mode, py, a, s);
+        case 4: return launch_op_deg<4, T>(kind, mode, py, a, s);
+        case 5: return launch_op_deg<5, T>(kind, mode, py, a, s);
+    }
+    throw Err{HH_EINVAL, "unsupported degree"};
+}
+template void launch_op<double>(int, int, int, int, const OpArgs<double>&, hipStream_t);
+template void launch_op<float>(int, int, int, int, const OpArgs<float>&, hipStream_t);
+
+// --------------------------------------------------------------------------
+// Knot-insertion transfers: restriction c = P^T r, prolongation x (+)= P e,
+// P = P_y (x) P_x stored as per-row / per-column runs.
+// --------------------------------------------------------------------------
+template <class T>
+__global__ void restrict_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* __restrict__ c) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long Nc = (long long)t.nc1 * t.nc2;
+    if (idx >= Nc) return;
+    const int J1 = (int)(idx % t.nc1), J2 = (int)(idx / t.nc1);
+    const int i0x = t.pcol0x[J1], i0y = t.pcol0y[J2];
+    T sr = 0, si = 0;
+    for (int a2 = 0; a2 < t.rw2; ++a2) {
+        const T wy = (T)t.pcoly[(size_t)J2 * t.rw2 + a2];
+        if (wy == T(0)) continue;
+        const cx<T>* row = r + (size_t)(i0y + a2) * t.nf1 + i0x;
+        T rr = 0, ri = 0;
+        for (int a1 = 0; a1 < t.rw1; ++a1) {
+            const T wx = (T)t.pcolx[(size_t)J1 * t.rw1 + a1];
+            const cx<T> v = row[a1];
+            rr += wx * v.re;
+            ri += wx * v.im;
+        }
+        sr += wy * rr;
+        si += wy * ri;
+    }
+    c[idx] = {sr, si};
+}
+
+template <class T>
+__global__ void prolong_kernel(Transfer t, const cx<T>* __restrict__ e, cx<T>* __restrict__ x, int add) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long Nf = (long long)t.nf1 * t.nf2;
+    if (idx >= Nf) return;
+    const int I1 = (int)(idx % t.nf1), I2 = (int)(idx / t.nf1);
+    const int j0x = t.prow0x[I1], j0y = t.prow0y[I2];
+    T sr = 0, si = 0;
+    for (int b2 = 0; b2 < t.pw2; ++b2) {
+        const T wy = (T)t.prowy[(size_t)I2 * t.pw2 + b2];
+        if (wy == T(0)) continue;
+        const cx<T>* row = e + (size_t)(j0y + b2) * t.nc1 + j0x;
+        T rr = 0, ri = 0;
+        for (int b1 = 0; b1 < t.pw1; ++b1) {
+            const T wx = (T)t.prowx[(size_t)I1 * t.pw1 + b1];
+            const cx<T> v = row[b1];
+            rr += wx * v.re;
+            ri += wx * v.im;
+        }
+        sr += wy * rr;
+        si += wy * ri;
+    }
+    if (add) {
+        cx<T> o = x[idx];
+        x[idx] = {o.re + sr, o.im + si};
+    } else {
+        x[idx] = {sr, si};
+    }
+}
+
+static inline unsigned grid1d(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <class T>
+void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s) {
+    const long long Nc = (long long)t.nc1 * t.nc2;
+    hipLaunchKernelGGL(restrict_kernel<T>, dim3(grid1d(Nc, 256)), dim3(256), 0, s, t, r, c);
+}
+template <class T>
+void launch_prolong(const Transfer& t, const cx<T>* e, cx<T>* x, int add, hipStream_t s) {
+    const long long Nf = (long long)t.nf1 * t.nf2;
+    hipLaunchKernelGGL(prolong_kernel<T>, dim3(grid1d(Nf, 256)), dim3(256), 0, s, t, e, x, add);
+}
+template void launch_restrict<double>(const Transfer&, const cx<double>*, cx<double>*, hipStream_t);
+template void launch_restrict<float>(const Transfer&, const cx<float>*, cx<float>*, hipStream_t);
+template void launch_prolong<double>(const Transfer&, const cx<double>*, cx<double>*, int, hipStream_t);
+template void launch_prolong<float>(const Transfer&, const cx<float>*, cx<float>*, int, hipStream_t);
+
+// --------------------------------------------------------------------------
+// Pointwise kernels
+// --------------------------------------------------------------------------
+template <class T>
+__global__ void jacobi0_kernel(long long N, const cx<T>* dinv, T omega, const cx<T>* b, cx<T>* x) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const cx<T> d = dinv[i], v = b[i];
+    x[i] = {omega * (d.re * v.re - d.im * v.im), omega * (d.re * v.im + d.im * v.re)};
+}
+template <class T>
+void launch_jacobi0(long long N, const cx<T>* dinv, T omega, const cx<T>* b, cx<T>* x, hipStream_t s) {
+    hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(grid1d(N, 256)), dim3(256), 0, s, N, dinv, omega, b, x);
+}
+template void launch_jacobi0<double>(long long, const cx<double>*, double, const cx<double>*, cx<double>*, hipStream_t);
+template void launch_jacobi0<float>(long long, const cx<float>*, float, const cx<float>*, cx<float>*, hipStream_t);
+
+template <class T>
+__global__ void axpy_kernel(long long N, const cx<T>* x, cx<T>* y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const cx<T> a = x[i], b = y[i];
+    y[i] = {b.re + a.re, b.im + a.im};
+}
+template <class T>
+void launch_axpy(long long N, const cx<T>* x, cx<T>* y, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_kernel<T>, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y);
+}
+template void launch_axpy<double>(long long, const cx<double>*, cx<double>*, hipStream_t);
+template void launch_axpy<float>(long long, const cx<float>*, cx<float>*, hipStream_t);
+
+__global__ void add_kernel(long long N, const cx<double>* a, const cx<double>* b, cx<double>* y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const cx<double> u = a[i], v = b[i];
+    y[i] = {u.re + v.re, u.im + v.im};
+}
+void launch_add(long long N, const cx<double>* a, const cx<double>* b, cx<double>* y, hipStream_t s) {
+    hipLaunchKernelGGL(add_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, a, b, y);
+}
+
+__global__ void copy_kernel(long long N, const cx<double>* x, cx<double>* y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) y[i] = x[i];
+}
+void launch_copy(long long N, const cx<double>* x, cx<double>* y, hipStream_t s) {
+    hipLaunchKernelGGL(copy_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y);
+}
+__global__ void zero_kernel(long long N, cx<double>* y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) y[i] = {0.0, 0.0};
+}
+void launch_zero(long long N, cx<double>* y, hipStream_t s) {
+    hipLaunchKernelGGL(zero_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, y);
+}
+
+__global__ void cast_d2f_kernel(long long N, const cx<double>* x, cx<float>* y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) y[i] = {(float)x[i].re, (float)x[i].im};
+}
+__global__ void cast_f2d_kernel(long long N, const cx<float>* x, cx<double>* y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) y[i] = {(double)x[i].re, (double)x[i].im};
+}
+void launch_cast_d2f(long long N, const cx<double>* x, cx<float>* y, hipStream_t s) {
+    hipLaunchKernelGGL(cast_d2f_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y);
+}
+void launch_cast_f2d(long long N, const cx<float>* x, cx<double>* y, hipStream_t s) {
+    hipLaunchKernelGGL(cast_f2d_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y);
+}
+
+// --------------------------------------------------------------------------
+// Dense matrix-vector product y = A x (A row-major n x n): one wave per row.
+// --------------------------------------------------------------------------
+template <class TV>
+__device__ __forceinline__ void mac(const double& a, const cx<TV>& x, TV& sr, TV& si) {
+    sr += (TV)a * x.re;
+    si += (TV)a * x.im;
+}
+template <class TV, class TA>
+__device__ __forceinline__ void mac(const cx<TA>& a, const cx<TV>& x, TV& sr, TV& si) {
+    sr += (TV)a.re * x.re - (TV)a.im * x.im;
+    si += (TV)a.re * x.im + (TV)a.im * x.re;
+}
+
+template <class TM, class TV>
+__global__ __launch_bounds__(256) void gemv_kernel(int n, const TM* __restrict__ A, const cx<TV>* __restrict__ x,
+                                                   cx<TV>* __restrict__ y) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + wave;
+    if (row >= n) return;
+    TV sr = 0, si = 0;
+    const TM* a = A + (size_t)row * n;
+    for (int j = lane; j < n; j += 64) mac(a[j], x[j], sr, si);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
+    }
+    if (lane == 0) y[row] = {sr, si};
+}
+template <class TM, class TV>
+void launch_gemv(int n, const TM* A, const cx<TV>* x, cx<TV>* y, hipStream_t s) {
+    hipLaunchKernelGGL((gemv_kernel<TM, TV>), dim3((n + 3) / 4), dim3(256), 0, s, n, A, x, y);
+}
+template void launch_gemv<double, double>(int, const double*, const cx<double>*, cx<double>*, hipStream_t);
+template void launch_gemv<cx<double>, double>(int, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t);
+template void launch_gemv<cx<float>, float>(int, const cx<float>*, const cx<float>*, cx<float>*, hipStream_t);
+
+// --------------------------------------------------------------------------
+// Krylov: deterministic two-stage reductions.  Every block writes its partial
+// sum; the last block to finish (device-scope atomic ticket) sums the partials
+// in index order, so results do not depend on block scheduling.
+// --------------------------------------------------------------------------
+constexpr int RB = 256;  // threads per reduction block
+
+int reduction_blocks(long long N) {
+    long long b = (N + 4 * RB - 1) / (4 * RB);
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+    const int t = threadIdx.x;
+    sh[t] = a;
+    sh[RB + t] = b;
+    __syncthreads();
+#pragma unroll
+    for (int o = RB / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            sh[t] += sh[t + o];
+            sh[RB + t] += sh[RB + t + o];
+        }
+        __syncthreads();
+    }
+    a = sh[0];
+    b = sh[RB];
+}
+
+// Returns true in the one block that sees all partials (after its block_sum2).
+// Memory model: the partial is released with an agent-scope fence before the
+// ticket, and the last block acquires with another fence before it reads the
+// partials (the L2 caches of the XCDs are not coherent with each other
+// otherwise).
+__device__ __forceinline__ bool last_block(int* counter, bool* flag) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ticket = atomicAdd(counter, 1);
+        *flag = (ticket == (int)gridDim.x - 1);
+    }
+    __syncthreads();
+    if (*flag) __threadfence();
+    return *flag;
+}
+
+__device__ __forceinline__ void sum_partials(const cx<double>* partials, int nb, double& re, double& im,
+                                             double* sh) {
+    re = 0.0;
+    im = 0.0;
+    for (int i = threadIdx.x; i < nb; i += RB) {
+        const cx<double> v = partials[i];
+        re += v.re;
+        im += v.im;
+    }
+    block_sum2(re, im, sh);
+}
+
+__device__ __forceinline__ cx<double> hload(const cx<double>* p) {
+    // device-scope coherent read of a value written by another block of an
+    // earlier kernel (plain load; kernels on one stream are ordered)
+    return *p;
+}
+
+// w -= h_{i-1} V[i-1] (i > 0), then H[i, j] = V[i]^H w.
+__global__ __launch_bounds__(RB) void mgs_kernel(long long N, int i, int j, cx<double>* __restrict__ w,
+                                                 const cx<double>* __restrict__ V, long long ldv, KrylovDev k) {
+    __shared__ double sh[2 * RB];
+    __shared__ bool flag;
+    const int ldh = k.m + 1;
+    cx<double> h = {0.0, 0.0};
+    if (i > 0) h = hload(&k.H[(size_t)j * ldh + (i - 1)]);
+    const cx<double>* vp = V + (size_t)(i > 0 ? i - 1 : 0) * ldv;
+    const cx<double>* vc = V + (size_t)i * ldv;
+    double sr = 0.0, si = 0.0;
+    const long long stride = (long long)gridDim.x * RB;
+    for (long long t = (long long)blockIdx.x * RB + threadIdx.x; t < N; t += stride) {
+        cx<double> wv = w[t];
+        if (i > 0) {
+            const cx<double> pv = vp[t];
+            wv.re -= h.re * pv.re - h.im * pv.im;
+            wv.im -= h.re * pv.im + h.im * pv.re;
+            w[t] = wv;
+        }
+        const cx<double> cv = vc[t];
+        sr += cv.re * wv.re + cv.im * wv.im;   // conj(v) w
+        si += cv.re * wv.im - cv.im * wv.re;
+    }
+    block_sum2(sr, si, sh);
+    if (threadIdx.x == 0) k.partials[blockIdx.x] = {sr, si};
+    if (!last_block(&k.ints[2], &flag)) return;
+    double tr, ti;
+    sum_partials(k.partials, gridDim.x, tr, ti, sh);
+    if (threadIdx.x == 0) {
+        k.H[(size_t)j * ldh + i] = {tr, ti};
+        k.ints[2] = 0;
+    }
+}
+
+void launch_mgs(long long N, int i, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
+                hipStream_t s) {
+    hipLaunchKernelGGL(mgs_kernel, dim3(reduction_blocks(N)), dim3(RB), 0, s, N, i, j, w, V, ldv, k);
+}
+
+__device__ void givens_rot(cx<double> a, cx<double> b, double& c, cx<double>& s) {
+    const double ab = hypot(a.re, a.im), bb = hypot(b.re, b.im);
+    if (bb == 0.0) {
+        c = 1.0;
+        s = {0.0, 0.0};
+    } else if (ab == 0.0) {
+        c = 0.0;
+        s = {b.re / bb, -b.im / bb};
+    } else {
+        const double t = sqrt(ab * ab + bb * bb);
+        c = ab / t;
+        const cx<double> u = {a.re / ab, a.im / ab};
+        const cx<double> cb = {b.re / t, -b.im / t};
+        s = cmul(u, cb);
+    }
+}
+
+// w -= H[j,j] V[j]; hn = ||w||; H[j+1,j] = hn; Givens update of column j and g.
+__global__ __launch_bounds__(RB) void norm_givens_kernel(long long N, int j, cx<double>* __restrict__ w,
+                                                         const cx<double>* __restrict__ V, long long ldv,
+                                                         KrylovDev k) {
+    __shared__ double sh[2 * RB];
+    __shared__ bool flag;
+    const int ldh = k.m + 1;
+    const cx<double> h = hload(&k.H[(size_t)j * ldh + j]);
+    const cx<double>* vp = V + (size_t)j * ldv;
+    double sr = 0.0, dummy = 0.0;
+    const long long stride = (long long)gridDim.x * RB;
+    for (long long t = (long long)blockIdx.x * RB + threadIdx.x; t < N; t += stride) {
+        cx<double> wv = w[t];
+        const cx<double> pv = vp[t];
+        wv.re -= h.re * pv.re - h.im * pv.im;
+        wv.im -= h.re * pv.im + h.im * pv.re;
+        w[t] = wv;
+        sr += wv.re * wv.re + wv.im * wv.im;
+    }
+    block_sum2(sr, dummy, sh);
+    if (threadIdx.x == 0) k.partials[blockIdx.x] = {sr, 0.0};
+    if (!last_block(&k.ints[2], &flag)) return;
+    double tr, ti;
+    sum_partials(k.partials, gridDim.x, tr, ti, sh);
+    if (threadIdx.x != 0) return;
+    k.ints[2] = 0;
+    const double hn = sqrt(tr);
+    k.scal[1] = hn;
+    cx<double>* Hc = k.H + (size_t)j * ldh;
+    Hc[j + 1] = {hn, 0.0};
+    for (int ii = 0; ii < j; ++ii) {
+        const double c = k.cs[ii];
+        const cx<double> s = k.sn[ii];
+        const cx<double> a = Hc[ii], b = Hc[ii + 1];
+        const cx<double> sb = cmul(s, b);
+        const cx<double> t = {c * a.re + sb.re, c * a.im + sb.im};
+        const cx<double> cs_ = {s.re, -s.im};
+        const cx<double> ca = cmul(cs_, a);
+        Hc[ii + 1] = {-ca.re + c * b.re, -ca.im + c * b.im};
+        Hc[ii] = t;
+    }
+    double c;
+    cx<double> s;
+    givens_rot(Hc[j], Hc[j + 1], c, s);
+    k.cs[j] = c;
+    k.sn[j] = s;
+    {
+        const cx<double> a = Hc[j], b = Hc[j + 1];
+        const cx<double> sb = cmul(s, b);
+        Hc[j] = {c * a.re + sb.re, c * a.im + sb.im};
+        Hc[j + 1] = {0.0, 0.0};
+    }
+    const cx<double> gj = k.g[j];
+    const cx<double> cs_ = {s.re, -s.im};
+    const cx<double> ng = cmul(cs_, gj);
+    k.g[j + 1] = {-ng.re, -ng.im};
+    k.g[j] = {c * gj.re, c * gj.im};
+    k.scal[2] = hypot(k.g[j + 1].re, k.g[j + 1].im);
+    if (!k.ints[1]) k.ints[0] = j + 1;
+    if (hn == 0.0) k.ints[1] = 1;
+}
+
+void launch_norm_givens(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(norm_givens_kernel, dim3(reduction_blocks(N)), dim3(RB), 0, s, N, j, w, V, ldv, k);
+}
+
+// ||x||^2 into *out (plain reduction).
+__global__ __launch_bounds__(RB) void norm2_kernel(long long N, const cx<double>* __restrict__ x, double* out,
+                                                   int* counter, cx<double>* partials) {
+    __shared__ double sh[2 * RB];
+    __shared__ bool flag;
+    double sr = 0.0, dummy = 0.0;
+    const long long stride = (long long)gridDim.x * RB;
+    for (long long t = (long long)blockIdx.x * RB + threadIdx.x; t < N; t += stride) {
+        const cx<double> v = x[t];
+        sr += v.re * v.re + v.im * v.im;
+    }
+    block_sum2(sr, dummy, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = {sr, 0.0};
+    if (!last_block(counter, &flag)) return;
+    double tr, ti;
+    sum_partials(partials, gridDim.x, tr, ti, sh);
+    if (threadIdx.x == 0) {
+        *out = tr;
+        *counter = 0;
+    }
+}
+
+void launch_dot_norm2(long long N, const cx<double>* x, double* out, int* counter, cx<double>* partials,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(norm2_kernel, dim3(reduction_blocks(N)), dim3(RB), 0, s, N, x, out, counter, partials);
+}
+
+// Start of an Arnoldi cycle: beta = ||r||, g = (beta, 0, ...), counters reset.
+__global__ void cycle_init_kernel(KrylovDev k) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double beta = sqrt(k.scal[3]);
+    k.scal[0] = beta;
+    for (int i = 0; i <= k.m; ++i) k.g[i] = {0.0, 0.0};
+    k.g[0] = {beta, 0.0};
+    k.scal[2] = beta;
+    k.ints[0] = 0;
+    k.ints[1] = (beta == 0.0) ? 1 : 0;
+}
+
+void launch_norm_init(long long N, const cx<double>* r, KrylovDev& k, hipStream_t s) {
+    launch_dot_norm2(N, r, &k.scal[3], &k.ints[2], k.partials, s);
+    hipLaunchKernelGGL(cycle_init_kernel, dim3(1), dim3(1), 0, s, k);
+}
+
+// y = x / *by, with a zero divisor giving y = 0.
+__global__ void scale_by_kernel(long long N, const cx<double>* x, cx<double>* y, const double* by) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double d = *by;
+    if (d == 0.0) {
+        y[i] = {0.0, 0.0};
+        return;
+    }
+    const cx<double> v = x[i];
+    y[i] = {v.re / d, v.im / d};
+}
+void launch_scale_by(long long N, const cx<double>* x, cx<double>* y, const double* by, hipStream_t s) {
+    hipLaunchKernelGGL(scale_by_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y, by);
+}
+
+// Back substitution R y = g on the first jdone rows (R: rotated Hessenberg).
+__global__ void lsq_kernel(KrylovDev k) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int n = k.ints[0], ldh = k.m + 1;
+    for (int i = n - 1; i >= 0; --i) {
+        cx<double> s = k.g[i];
+        for (int c = i + 1; c < n; ++c) {
+            const cx<double> p = cmul(k.H[(size_t)c * ldh + i], k.y[c]);
+            s.re -= p.re;
+            s.im -= p.im;
+        }
+        const cx<double> d = k.H[(size_t)i * ldh + i];
+        const double den = d.re * d.re + d.im * d.im;
+        k.y[i] = {(s.re * d.re + s.im * d.im) / den, (s.im * d.re - s.re * d.im) / den};
+    }
+}
+void launch_lsq(KrylovDev& k, hipStream_t s) { hipLaunchKernelGGL(lsq_kernel, dim3(1), dim3(1), 0, s, k); }
+
+// u (+)= sum_{i < jdone} Z_i y_i, accumulated in increasing i.
+__global__ void update_kernel(long long N, const cx<double>* __restrict__ Z, long long ldz, KrylovDev k,
+                              cx<double>* __restrict__ u, int accumulate) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const int n = k.ints[0];
+    double dr = 0.0, di = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const cx<double> z = Z[(size_t)i * ldz + t];
+        const cx<double> y = k.y[i];
+        dr += z.re * y.re - z.im * y.im;
+        di += z.re * y.im + z.im * y.re;
+    }
+    if (accumulate) {
+        const cx<double> o = u[t];
+        u[t] = {o.re + dr, o.im + di};
+    } else {
+        u[t] = {dr, di};
+    }
+}
+void launch_update(long long N, const cx<double>* Z, long long ldz, KrylovDev& k, cx<double>* u, int accumulate,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(update_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, Z, ldz, k, u, accumulate);
+}
+
+}  // namespace hh

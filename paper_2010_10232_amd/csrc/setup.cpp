@@ -1,0 +1,319 @@
+// Host-side discretisation: knot vectors, B-spline values, Gauss-Legendre
+// element matrices, knot-insertion transfers and Galerkin coarse stencils.
+//
+// Follows section 2.3 of the paper (open uniform knot vectors with the end
+// knots repeated p+1 times, Cox-de Boor B-splines, Galerkin stiffness and mass
+// entries) and section 3 (coarse spaces; the knot-insertion prolongation is the
+// deflation matrix Z and the multigrid transfer).  Coarse levels halve the
+// knot spans: they keep every second breakpoint plus the last one when the
+// element count is odd, so the spaces are nested and only the last element of
+// a level can be short.
+#include <cmath>
+#include <cstring>
+
+#include "hh_internal.h"
+
+namespace hh {
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton iteration on the
+// three-term Legendre recurrence.
+void gauss_legendre(int n, double* x, double* w) {
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+            }
+            dp = n * (z * p0 - p1) / (z * z - 1.0);
+            double dz = p0 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        // final derivative at the converged node
+        double p0 = 1.0, p1 = 0.0;
+        for (int k = 1; k <= n; ++k) {
+            double p2 = p1;
+            p1 = p0;
+            p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+        }
+        dp = n * (z * p0 - p1) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// The p+1 B-splines of degree p that are nonzero on knot span `span`
+// (U[span] <= x < U[span+1]) and their first derivatives, by the triangular
+// form of the Cox-de Boor recursion; N[r] belongs to global function span-p+r.
+void basis_values(const std::vector<double>& U, int p, int span, double x, double* N, double* dN) {
+    double ndu[7][7];
+    double left[7], right[7];
+    ndu[0][0] = 1.0;
+    for (int j = 1; j <= p; ++j) {
+        left[j] = x - U[span + 1 - j];
+        right[j] = U[span + j] - x;
+        double saved = 0.0;
+        for (int r = 0; r < j; ++r) {
+            ndu[j][r] = right[r + 1] + left[j - r];
+            double temp = ndu[r][j - 1] / ndu[j][r];
+            ndu[r][j] = saved + right[r + 1] * temp;
+            saved = left[j - r] * temp;
+        }
+        ndu[j][j] = saved;
+    }
+    for (int r = 0; r <= p; ++r) N[r] = ndu[r][p];
+    if (!dN) return;
+    if (p == 0) {
+        dN[0] = 0.0;
+        return;
+    }
+    // N'_{i,p} = p (N_{i,p-1} / (U_{i+p} - U_i) - N_{i+1,p-1} / (U_{i+p+1} - U_{i+1}))
+    for (int r = 0; r <= p; ++r) {
+        int i = span - p + r;
+        double d = 0.0;
+        if (r >= 1) d += ndu[r - 1][p - 1] / (U[i + p] - U[i]);
+        if (r <= p - 1) d -= ndu[r][p - 1] / (U[i + p + 1] - U[i + 1]);
+        dN[r] = p * d;
+    }
+}
+
+static int level_elems(int nel_fine, int level) {
+    int n = nel_fine;
+    for (int l = 0; l < level; ++l) n = (n + 1) / 2;
+    return n;
+}
+
+Axis make_trivial_axis() {
+    Axis a;
+    a.p = 0;
+    a.nel = 1;
+    a.n = 1;
+    a.off = 0;
+    a.nel_fine = 1;
+    a.bk = {0.0, 1.0};
+    a.U = a.bk;
+    a.Kb = {0.0};
+    a.Mb = {1.0};
+    a.Me = {1.0};
+    a.G = {1.0};
+    a.pw = a.rw = 1;
+    a.prow0 = {0};
+    a.prow = {1.0};
+    a.pcol0 = {0};
+    a.pcol = {1.0};
+    return a;
+}
+
+Axis make_axis(int p, int nel_fine, int level) {
+    Axis a;
+    a.p = p;
+    a.level = level;
+    a.nel_fine = nel_fine;
+    a.nel = level_elems(nel_fine, level);
+    a.n = a.nel + p - 2;
+    a.off = 1;
+    // breakpoints: finest indices j * 2^level (j < nel) and the last one
+    std::vector<int> idx;
+    for (int j = 0; j < a.nel; ++j) idx.push_back(j << level);
+    idx.push_back(nel_fine);
+    for (int i : idx) a.bk.push_back(i / (double)nel_fine);
+    for (int i = 0; i < p; ++i) a.U.push_back(a.bk.front());
+    for (double v : a.bk) a.U.push_back(v);
+    for (int i = 0; i < p; ++i) a.U.push_back(a.bk.back());
+
+    const int q = p + 1, bw = 2 * p + 1;
+    double gx[8], gw[8], N[8], dN[8];
+    gauss_legendre(q, gx, gw);
+    // element matrices and the full banded K, M
+    const int nfull = a.nel + p;
+    std::vector<double> Kf((size_t)nfull * bw, 0.0), Mf((size_t)nfull * bw, 0.0);
+    a.Me.assign((size_t)a.nel * q * q, 0.0);
+    for (int e = 0; e < a.nel; ++e) {
+        double lo = a.bk[e], hi = a.bk[e + 1], jac = 0.5 * (hi - lo);
+        double ke[36] = {0}, me[36] = {0};
+        for (int g = 0; g < q; ++g) {
+            double x = lo + (gx[g] + 1.0) * jac;
+            basis_values(a.U, p, e + p, x, N, dN);
+            for (int i = 0; i < q; ++i)
+                for (int j = 0; j < q; ++j) {
+                    ke[i * q + j] += gw[g] * jac * dN[i] * dN[j];
+                    me[i * q + j] += gw[g] * jac * N[i] * N[j];
+                }
+        }
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < q; ++j) {
+                Kf[(size_t)(e + i) * bw + (j - i + p)] += ke[i * q + j];
+                Mf[(size_t)(e + i) * bw + (j - i + p)] += me[i * q + j];
+                a.Me[(size_t)e * q * q + i * q + j] = me[i * q + j];
+            }
+    }
+    // interior bands: drop the first and last function (homogeneous Dirichlet)
+    a.Kb.assign((size_t)a.n * bw, 0.0);
+    a.Mb.assign((size_t)a.n * bw, 0.0);
+    for (int i = 0; i < a.n; ++i)
+        for (int d = -p; d <= p; ++d) {
+            int j = i + d;
+            if (j < 0 || j >= a.n) continue;
+            a.Kb[(size_t)i * bw + d + p] = Kf[(size_t)(i + 1) * bw + d + p];
+            a.Mb[(size_t)i * bw + d + p] = Mf[(size_t)(i + 1) * bw + d + p];
+        }
+    // this level's basis on every finest element: blocks for the Galerkin
+    // k^2-weighted mass (k^2 is constant on finest elements)
+    a.G.assign((size_t)nel_fine * q * q, 0.0);
+    for (int e = 0; e < nel_fine; ++e) {
+        int E = e >> level;
+        double lo = e / (double)nel_fine, hi = (e + 1) / (double)nel_fine, jac = 0.5 * (hi - lo);
+        double* blk = &a.G[(size_t)e * q * q];
+        for (int g = 0; g < q; ++g) {
+            double x = lo + (gx[g] + 1.0) * jac;
+            basis_values(a.U, p, E + p, x, N, nullptr);
+            for (int i = 0; i < q; ++i)
+                for (int j = 0; j < q; ++j) blk[i * q + j] += gw[g] * jac * N[i] * N[j];
+        }
+    }
+    return a;
+}
+
+// Solve B X = C for X ((q x q) dense, Gaussian elimination with partial pivoting).
+static void small_solve(int q, double* B, double* C) {
+    for (int k = 0; k < q; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < q; ++i)
+            if (std::fabs(B[i * q + k]) > std::fabs(B[piv * q + k])) piv = i;
+        if (piv != k)
+            for (int j = 0; j < q; ++j) {
+                std::swap(B[k * q + j], B[piv * q + j]);
+                std::swap(C[k * q + j], C[piv * q + j]);
+            }
+        for (int i = k + 1; i < q; ++i) {
+            double f = B[i * q + k] / B[k * q + k];
+            for (int j = k; j < q; ++j) B[i * q + j] -= f * B[k * q + j];
+            for (int j = 0; j < q; ++j) C[i * q + j] -= f * C[k * q + j];
+        }
+    }
+    for (int k = q - 1; k >= 0; --k)
+        for (int j = 0; j < q; ++j) {
+            double s = C[k * q + j];
+            for (int i = k + 1; i < q; ++i) s -= B[k * q + i] * C[i * q + j];
+            C[k * q + j] = s / B[k * q + k];
+        }
+}
+
+// Knot-insertion prolongation from `coarse` (level l+1) to `fine` (level l),
+// restricted to interior functions, stored as row and column runs in `fine`.
+// On each fine element the p+1 active coarse B-splines are polynomials, hence
+// exact combinations of the p+1 active fine B-splines; the coefficients come
+// from collocation at p+1 points of that element.
+void make_transfer(Axis& fine, const Axis& coarse) {
+    const int p = fine.p, q = p + 1;
+    const int nff = fine.nel + p, ncf = coarse.nel + p;
+    std::vector<double> P((size_t)nff * ncf, 0.0);
+    double gx[8], gw[8], N[8];
+    gauss_legendre(q, gx, gw);
+    for (int i = 0; i < nff; ++i) {
+        int f = std::min(std::max(i - p / 2, std::max(0, i - p)), std::min(i, fine.nel - 1));
+        int E = f >> 1;
+        double lo = fine.bk[f], hi = fine.bk[f + 1];
+        double B[36], C[36];
+        for (int g = 0; g < q; ++g) {
+            double x = lo + (gx[g] + 1.0) * 0.5 * (hi - lo);
+            basis_values(fine.U, p, f + p, x, N, nullptr);
+            for (int a = 0; a < q; ++a) B[g * q + a] = N[a];
+            basis_values(coarse.U, p, E + p, x, N, nullptr);
+            for (int b = 0; b < q; ++b) C[g * q + b] = N[b];
+        }
+        small_solve(q, B, C);  // C now holds X: X[a][b] = coeff of coarse E+b on fine f+a
+        int a = i - f;
+        for (int b = 0; b < q; ++b) P[(size_t)i * ncf + E + b] = C[a * q + b];
+    }
+    for (double& v : P)
+        if (std::fabs(v) < 1e-12) v = 0.0;
+    // interior part (drop first/last function in both spaces)
+    const int nf = fine.n, nc = coarse.n;
+    auto Pint = [&](int i, int J) { return P[(size_t)(i + 1) * ncf + (J + 1)]; };
+    fine.pw = std::min(p + 1, nc);
+    fine.rw = std::min(p + 2, nf);
+    fine.prow0.assign(nf, 0);
+    fine.prow.assign((size_t)nf * fine.pw, 0.0);
+    for (int i = 0; i < nf; ++i) {
+        int first = -1, last = -1;
+        for (int J = 0; J < nc; ++J)
+            if (Pint(i, J) != 0.0) {
+                if (first < 0) first = J;
+                last = J;
+            }
+        if (first < 0) first = last = 0;
+        HH_REQUIRE(last - first + 1 <= fine.pw, "prolongation row wider than p+1");
+        int j0 = std::min(first, nc - fine.pw);
+        fine.prow0[i] = j0;
+        for (int t = 0; t < fine.pw; ++t) fine.prow[(size_t)i * fine.pw + t] = Pint(i, j0 + t);
+    }
+    fine.pcol0.assign(nc, 0);
+    fine.pcol.assign((size_t)nc * fine.rw, 0.0);
+    for (int J = 0; J < nc; ++J) {
+        int first = -1, last = -1;
+        for (int i = 0; i < nf; ++i)
+            if (Pint(i, J) != 0.0) {
+                if (first < 0) first = i;
+                last = i;
+            }
+        if (first < 0) first = last = 0;
+        HH_REQUIRE(last - first + 1 <= fine.rw, "prolongation column wider than p+2");
+        int i0 = std::min(first, nf - fine.rw);
+        fine.pcol0[J] = i0;
+        for (int t = 0; t < fine.rw; ++t) fine.pcol[(size_t)J * fine.rw + t] = Pint(i0 + t, J);
+    }
+}
+
+// Galerkin k^2-weighted mass of the level of (ax, ay) as a full stencil.
+// M_k = sum over finest elements e of k_e^2 (Gy_e2 (x) Gx_e1), where G are
+// this level's basis mass blocks on finest elements; summed row by row of
+// finest elements through the weighted 1D band B_e2 = sum_e1 k^2 Gx_e1.
+void galerkin_mass_stencil(const Axis& ax, const Axis& ay, const std::vector<double>& k2,
+                           std::vector<double>& S) {
+    const int px = ax.p, py = ay.p, qx = px + 1, qy = py + 1;
+    const int bx = 2 * px + 1, by = 2 * py + 1;
+    const long long N = (long long)ax.n * ay.n;
+    S.assign((size_t)bx * by * N, 0.0);
+    std::vector<double> B((size_t)ax.n * bx);
+    for (int e2 = 0; e2 < ay.nel_fine; ++e2) {
+        std::fill(B.begin(), B.end(), 0.0);
+        for (int e1 = 0; e1 < ax.nel_fine; ++e1) {
+            const int E1 = e1 >> ax.level;
+            const double w = k2[(size_t)e2 * ax.nel_fine + e1];
+            const double* g = &ax.G[(size_t)e1 * qx * qx];
+            for (int a1 = 0; a1 < qx; ++a1) {
+                int I1 = E1 + a1 - ax.off;
+                if (I1 < 0 || I1 >= ax.n) continue;
+                for (int c1 = 0; c1 < qx; ++c1) {
+                    int J1 = E1 + c1 - ax.off;
+                    if (J1 < 0 || J1 >= ax.n) continue;
+                    B[(size_t)I1 * bx + (c1 - a1 + px)] += w * g[a1 * qx + c1];
+                }
+            }
+        }
+        const int E2 = e2 >> ay.level;
+        const double* gy = &ay.G[(size_t)e2 * qy * qy];
+        for (int a2 = 0; a2 < qy; ++a2) {
+            int I2 = E2 + a2 - ay.off;
+            if (I2 < 0 || I2 >= ay.n) continue;
+            for (int c2 = 0; c2 < qy; ++c2) {
+                int J2 = E2 + c2 - ay.off;
+                if (J2 < 0 || J2 >= ay.n) continue;
+                const double gyv = gy[a2 * qy + c2];
+                const int d2 = c2 - a2 + py;
+                for (int I1 = 0; I1 < ax.n; ++I1)
+                    for (int d1 = 0; d1 < bx; ++d1) {
+                        double v = B[(size_t)I1 * bx + d1];
+                        if (v != 0.0) S[(size_t)(d2 * bx + d1) * N + (long long)I2 * ax.n + I1] += gyv * v;
+                    }
+            }
+        }
+    }
+}
+
+}  // namespace hh

@@ -1,0 +1,89 @@
+// Solver objects behind the C ABI.
+#pragma once
+
+#include <memory>
+
+#include "hh_internal.h"
+
+namespace hh {
+
+struct ProblemImpl {
+    int dim = 2, p = 3, nel[2] = {1, 1};
+    int k_mode = 0;
+    double k = 0.0;
+    std::vector<double> k2;   // k^2 per finest element [nel_y][nel_x] (1D: [1][nel_x])
+    Axis ax0, ay0;            // finest-level axes
+    long long N() const { return (long long)ax0.n * ay0.n; }
+};
+
+struct LevelDev {
+    Axis ax, ay;
+    int n1 = 1, n2 = 1;
+    long long N = 1;
+    double omega = 0.8, gersh = 0.0;
+    int kind = KIND_SEP;
+    DevBuf Kx, Mx, Ky, My;
+    DevBuf S64, S32;
+    DevBuf k2, Mex, Mey;
+    DevBuf Dinv64, Dinv32;
+    // transfer to the next-coarser level (this level = fine side)
+    DevBuf prow0x, prowx, pcol0x, pcolx, prow0y, prowy, pcol0y, pcoly;
+    Transfer tr{};
+    // multigrid work vectors
+    DevBuf b64, x64, r64, t64, vr64, vx64;
+    DevBuf b32, x32, r32, t32, vr32, vx32;
+    // deflation work vectors (FP64)
+    DevBuf tc, te, tq, tw, ts;
+    // inner FGMRES (iterative deflation level)
+    int m_inner = 0;
+    DevBuf V, Z, kstate;
+    KrylovDev kd{};
+};
+
+struct SolverImpl {
+    const ProblemImpl* prob = nullptr;
+    hh_solver_opts o{};
+    int L = 0;      // coarsest multigrid level
+    int Lz = 0;     // deflation level solved directly (0: none)
+    std::vector<std::unique_ptr<LevelDev>> lev;
+    DevBuf Minv64, Minv32;   // dense inverse of M_beta at level L (complex)
+    DevBuf Einv;             // dense inverse of A at level Lz (real)
+    int nL = 0, nZ = 0;
+    // outer FGMRES
+    int m_outer = 0;
+    DevBuf V, Z, kstate, r, scratch;
+    KrylovDev kd{};
+    // event timing of one kernel class (non-blocking: events are read after the solve)
+    std::vector<hipEvent_t> evpool;
+    int ev_used = 0;
+    double ev_bytes = 0.0;
+    int ev_pending = -1;
+    void tstart(int cls, hipStream_t s);
+    void tstop(int cls, double bytes, hipStream_t s);
+    double tcollect(int* count);
+    ~SolverImpl();
+
+    void setup(hipStream_t s);
+    // building blocks
+    template <class T>
+    void op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s);
+    template <class T>
+    void vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s);
+    template <class T>
+    void vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s);
+    void precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s);
+    void T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t s);
+    void coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s);
+    int solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s);
+};
+
+ProblemImpl* build_problem(const hh_problem_desc* d);
+
+}  // namespace hh
+
+struct hh_problem {
+    hh::ProblemImpl impl;
+};
+struct hh_solver {
+    std::unique_ptr<hh::SolverImpl> impl;
+};

@@ -1,0 +1,660 @@
+// Solver driver: hierarchy setup, V-cycle, deflation recursion and FGMRES.
+//
+// Section 3 of the paper: the CSLP M_beta = K - (beta1 + i beta2) M_k is
+// approximated by multigrid V-cycles with damped Jacobi smoothing; deflation
+// uses Q = Z E^-1 Z^T with E = Z^T A Z and Z the knot-insertion prolongation.
+// The two are combined as the right preconditioner
+//     T_l(v) = Mtilde_l^-1 (v - A_l Q v) + Q v,    Q v = P_{l+1} E^-1 P_{l+1}^T v,
+// inside restarted flexible GMRES on A itself (section 4.3: relative residual
+// 1e-7).  E^-1 at the deepest deflation level L_z is an explicit dense inverse;
+// between, E_l^-1 is a fixed number of inner FGMRES steps preconditioned by
+// T_l (multilevel deflation).  Every step of a preconditioner application is a
+// kernel on the caller's stream; the host only reads the convergence estimate
+// of each outer Arnoldi step.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "solver.h"
+
+namespace hh {
+
+using zd = std::complex<double>;
+
+// ---------------------------------------------------------------- problem --
+ProblemImpl* build_problem(const hh_problem_desc* d) {
+    HH_REQUIRE(d != nullptr, "null problem descriptor");
+    HH_REQUIRE(d->dim == 1 || d->dim == 2, "dim must be 1 or 2");
+    HH_REQUIRE(d->p >= 1 && d->p <= 5, "p must be in 1..5");
+    const int nx = d->n_el[0], ny = d->dim == 2 ? d->n_el[1] : 1;
+    HH_REQUIRE(nx >= 2 && (d->dim == 1 || ny >= 2), "at least 2 elements per direction");
+    HH_REQUIRE(nx <= (1 << 20) && ny <= (1 << 20), "too many elements");
+    HH_REQUIRE(d->k_mode == 0 || d->k_mode == 1, "k_mode must be 0 or 1");
+    auto* P = new ProblemImpl();
+    P->dim = d->dim;
+    P->p = d->p;
+    P->nel[0] = nx;
+    P->nel[1] = ny;
+    P->k_mode = d->k_mode;
+    P->k = d->k;
+    if (d->k_mode == 0) {
+        if (!(d->k > 0.0) || !std::isfinite(d->k)) {
+            delete P;
+            throw Err{HH_EINVAL, "k must be positive and finite"};
+        }
+    } else {
+        if (!d->k_elem) {
+            delete P;
+            throw Err{HH_EINVAL, "k_elem is NULL with k_mode 1"};
+        }
+        P->k2.resize((size_t)nx * ny);
+        for (size_t i = 0; i < P->k2.size(); ++i) {
+            const double kv = d->k_elem[i];
+            if (!(kv > 0.0) || !std::isfinite(kv)) {
+                delete P;
+                throw Err{HH_EINVAL, "k_elem values must be positive and finite"};
+            }
+            P->k2[i] = kv * kv;
+        }
+    }
+    P->ax0 = make_axis(P->p, nx, 0);
+    P->ay0 = d->dim == 2 ? make_axis(P->p, ny, 0) : make_trivial_axis();
+    return P;
+}
+
+// ------------------------------------------------------------- host math --
+// Visits the nonzero stencil entries of row I of level data (K entries from
+// the bands; M_k entries from k^2 (constant) or the stored stencil S).
+template <class F>
+static void visit_row(const Axis& ax, const Axis& ay, bool const_k, double k2c, const std::vector<double>& S,
+                      long long I, F&& f) {
+    const int px = ax.p, py = ay.p, bx = 2 * px + 1, by = 2 * py + 1;
+    const int n1 = ax.n, n2 = ay.n;
+    const long long N = (long long)n1 * n2;
+    const int I1 = (int)(I % n1), I2 = (int)(I / n1);
+    for (int d2 = -py; d2 <= py; ++d2) {
+        const int J2 = I2 + d2;
+        if (J2 < 0 || J2 >= n2) continue;
+        const double my = ay.Mb[(size_t)I2 * by + d2 + py], ky = ay.Kb[(size_t)I2 * by + d2 + py];
+        for (int d1 = -px; d1 <= px; ++d1) {
+            const int J1 = I1 + d1;
+            if (J1 < 0 || J1 >= n1) continue;
+            const double mxv = ax.Mb[(size_t)I1 * bx + d1 + px], kxv = ax.Kb[(size_t)I1 * bx + d1 + px];
+            const double kv = my * kxv + ky * mxv;
+            const double mv = const_k ? k2c * my * mxv : S[(size_t)((d2 + py) * bx + d1 + px) * N + I];
+            f((long long)J2 * n1 + J1, kv, mv);
+        }
+    }
+}
+
+// In-place inverse of a small dense complex matrix (Gauss-Jordan, partial pivoting).
+static void invert_complex(int n, std::vector<zd>& A) {
+    std::vector<int> piv(n);
+    std::vector<zd> inv((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int pr = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::abs(A[(size_t)r * n + c]) > std::abs(A[(size_t)pr * n + c])) pr = r;
+        if (std::abs(A[(size_t)pr * n + c]) == 0.0) throw Err{HH_ENUMERIC, "singular coarsest matrix"};
+        if (pr != c)
+            for (int j = 0; j < n; ++j) {
+                std::swap(A[(size_t)c * n + j], A[(size_t)pr * n + j]);
+                std::swap(inv[(size_t)c * n + j], inv[(size_t)pr * n + j]);
+            }
+        const zd d = 1.0 / A[(size_t)c * n + c];
+        for (int j = 0; j < n; ++j) {
+            A[(size_t)c * n + j] *= d;
+            inv[(size_t)c * n + j] *= d;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const zd f = A[(size_t)r * n + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < n; ++j) {
+                A[(size_t)r * n + j] -= f * A[(size_t)c * n + j];
+                inv[(size_t)r * n + j] -= f * inv[(size_t)c * n + j];
+            }
+        }
+    }
+    A.swap(inv);
+}
+
+// --------------------------------------------------------------- helpers --
+static void fill_krylov(KrylovDev& k, DevBuf& blob, int m) {
+    const size_t nH = (size_t)(m + 1) * m, nb = 1024;
+    size_t bytes = 16 * nH + 8 * m + 16 * m + 16 * (m + 1) + 16 * m + 8 * 8 + 16 * nb + 4 * 8;
+    blob.alloc(bytes + 256);
+    char* p = blob.as<char>();
+    k.m = m;
+    k.H = (cx<double>*)p;
+    p += 16 * nH;
+    k.sn = (cx<double>*)p;
+    p += 16 * m;
+    k.g = (cx<double>*)p;
+    p += 16 * (m + 1);
+    k.y = (cx<double>*)p;
+    p += 16 * m;
+    k.partials = (cx<double>*)p;
+    p += 16 * nb;
+    k.cs = (double*)p;
+    p += 8 * m;
+    k.scal = (double*)p;
+    p += 8 * 8;
+    k.ints = (int*)p;
+    HH_HIP(hipMemset(blob.p, 0, blob.bytes));
+}
+
+template <class T>
+static DevBuf& pick(DevBuf& a64, DevBuf& a32) {
+    return sizeof(T) == 8 ? a64 : a32;
+}
+
+SolverImpl::~SolverImpl() {
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+}
+
+// Kernel-class timing: a pair of events around each launch of the selected
+// class, recorded on the launch stream and read only once the solve has
+// drained the stream, so the timed region is not serialised by the probes.
+constexpr int kEvPairs = 4096;
+
+void SolverImpl::tstart(int cls, hipStream_t s) {
+    if (o.time_kernels != cls || ev_used >= kEvPairs) return;
+    if (evpool.empty()) {
+        evpool.resize(2 * kEvPairs);
+        for (auto& e : evpool) HH_HIP(hipEventCreate(&e));
+    }
+    HH_HIP(hipEventRecord(evpool[2 * ev_used], s));
+    ev_pending = ev_used;
+}
+
+void SolverImpl::tstop(int cls, double bytes, hipStream_t s) {
+    if (o.time_kernels != cls || ev_pending < 0) return;
+    HH_HIP(hipEventRecord(evpool[2 * ev_pending + 1], s));
+    ev_bytes += bytes;
+    ev_used = ev_pending + 1;
+    ev_pending = -1;
+}
+
+double SolverImpl::tcollect(int* count) {
+    double ms = 0.0;
+    for (int i = 0; i < ev_used; ++i) {
+        float t = 0.f;
+        HH_HIP(hipEventElapsedTime(&t, evpool[2 * i], evpool[2 * i + 1]));
+        ms += t;
+    }
+    *count = ev_used;
+    return ms;
+}
+
+// ----------------------------------------------------------------- setup --
+void SolverImpl::setup(hipStream_t s) {
+    const ProblemImpl& P = *prob;
+    HH_REQUIRE(o.restart >= 1 && o.restart <= 200, "restart must be in 1..200");
+    HH_REQUIRE(o.maxit >= 1, "maxit must be >= 1");
+    HH_REQUIRE(o.nu_pre >= 1 && o.nu_post >= 0 && o.n_vcycles >= 1, "bad smoothing counts");
+    HH_REQUIRE(o.mg_min_elems >= 2, "mg_min_elems must be >= 2");
+    HH_REQUIRE(o.defl_mode >= 0 && o.defl_mode <= 2, "defl_mode must be 0, 1 or 2");
+    HH_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
+    HH_REQUIRE(o.tol >= 0.0 && o.omega > 0.0, "bad tol or omega");
+    HH_REQUIRE(o.defl_direct_max >= 1 && o.defl_direct_max <= 32768, "defl_direct_max must be in 1..32768");
+    for (int i = 0; i < 8; ++i) HH_REQUIRE(o.defl_inner_its[i] >= 1 && o.defl_inner_its[i] <= 64, "defl_inner_its in 1..64");
+
+    const int p = P.p;
+    const bool is2d = P.dim == 2;
+    // multigrid levels by knot halving
+    for (int l = 0;; ++l) {
+        auto lv = std::make_unique<LevelDev>();
+        lv->ax = l == 0 ? P.ax0 : make_axis(p, P.nel[0], l);
+        lv->ay = is2d ? (l == 0 ? P.ay0 : make_axis(p, P.nel[1], l)) : make_trivial_axis();
+        const int mx = std::max(lv->ax.nel, is2d ? lv->ay.nel : 0);
+        HH_REQUIRE(lv->ax.n >= 1 && lv->ay.n >= 1, "level without interior unknowns");
+        lev.push_back(std::move(lv));
+        if (mx <= o.mg_min_elems) break;
+    }
+    L = (int)lev.size() - 1;
+    for (int l = 0; l < L; ++l) {
+        make_transfer(lev[l]->ax, lev[l + 1]->ax);
+        if (is2d) make_transfer(lev[l]->ay, lev[l + 1]->ay);
+    }
+    const bool const_k = P.k_mode == 0;
+    const double k2c = const_k ? P.k * P.k : 0.0;
+    const zd beta(o.beta[0], o.beta[1]);
+    std::vector<std::vector<double>> Sh(lev.size());
+
+    for (int l = 0; l <= L; ++l) {
+        LevelDev& lv = *lev[l];
+        lv.n1 = lv.ax.n;
+        lv.n2 = lv.ay.n;
+        lv.N = (long long)lv.n1 * lv.n2;
+        lv.kind = const_k ? KIND_SEP : (l == 0 ? KIND_VARFINE : KIND_STENCIL);
+        upload(lv.Kx, lv.ax.Kb);
+        upload(lv.Mx, lv.ax.Mb);
+        upload(lv.Ky, lv.ay.Kb);
+        upload(lv.My, lv.ay.Mb);
+        if (!const_k) galerkin_mass_stencil(lv.ax, lv.ay, P.k2, Sh[l]);
+        // Jacobi diagonal of M_beta and the Gershgorin bound of D^-1 M_beta
+        std::vector<cx<double>> dinv((size_t)lv.N);
+        std::vector<cx<float>> dinv32((size_t)lv.N);
+        double g = 0.0;
+        for (long long I = 0; I < lv.N; ++I) {
+            zd diag = 0.0;
+            double rowsum = 0.0;
+            visit_row(lv.ax, lv.ay, const_k, k2c, Sh[l], I, [&](long long J, double kv, double mv) {
+                const zd e = kv - beta * mv;
+                rowsum += std::abs(e);
+                if (J == I) diag = e;
+            });
+            HH_REQUIRE(std::abs(diag) > 0.0, "zero Jacobi diagonal");
+            g = std::max(g, rowsum / std::abs(diag));
+            const zd di = 1.0 / diag;
+            dinv[I] = {di.real(), di.imag()};
+            dinv32[I] = {(float)di.real(), (float)di.imag()};
+        }
+        lv.gersh = g;
+        lv.omega = (l == 0 || o.coarse_damping == 0) ? o.omega : std::min(o.omega, 2.0 / g);
+        upload(lv.Dinv64, dinv);
+        upload(lv.Dinv32, dinv32);
+        if (!const_k && l == 0) {
+            upload(lv.k2, P.k2);
+            upload(lv.Mex, lv.ax.Me);
+            upload(lv.Mey, lv.ay.Me);
+        }
+        if (!const_k && l > 0) {
+            upload(lv.S64, Sh[l]);
+            std::vector<float> s32(Sh[l].begin(), Sh[l].end());
+            upload(lv.S32, s32);
+        }
+        const size_t v64 = (size_t)lv.N * 16, v32 = (size_t)lv.N * 8;
+        lv.b64.alloc(v64);
+        lv.x64.alloc(v64);
+        lv.r64.alloc(v64);
+        lv.t64.alloc(v64);
+        lv.b32.alloc(v32);
+        lv.x32.alloc(v32);
+        lv.r32.alloc(v32);
+        lv.t32.alloc(v32);
+        if (o.n_vcycles > 1) {
+            lv.vr64.alloc(v64);
+            lv.vx64.alloc(v64);
+            lv.vr32.alloc(v32);
+            lv.vx32.alloc(v32);
+        }
+    }
+    for (int l = 0; l < L; ++l) {
+        LevelDev& lv = *lev[l];
+        const LevelDev& lc = *lev[l + 1];
+        upload(lv.prow0x, lv.ax.prow0);
+        upload(lv.prowx, lv.ax.prow);
+        upload(lv.pcol0x, lv.ax.pcol0);
+        upload(lv.pcolx, lv.ax.pcol);
+        upload(lv.prow0y, lv.ay.prow0);
+        upload(lv.prowy, lv.ay.prow);
+        upload(lv.pcol0y, lv.ay.pcol0);
+        upload(lv.pcoly, lv.ay.pcol);
+        Transfer& t = lv.tr;
+        t.nf1 = lv.n1;
+        t.nf2 = lv.n2;
+        t.nc1 = lc.n1;
+        t.nc2 = lc.n2;
+        t.pw1 = lv.ax.pw;
+        t.pw2 = lv.ay.pw;
+        t.rw1 = lv.ax.rw;
+        t.rw2 = lv.ay.rw;
+        t.prow0x = lv.prow0x.as<int>();
+        t.prowx = lv.prowx.as<double>();
+        t.prow0y = lv.prow0y.as<int>();
+        t.prowy = lv.prowy.as<double>();
+        t.pcol0x = lv.pcol0x.as<int>();
+        t.pcolx = lv.pcolx.as<double>();
+        t.pcol0y = lv.pcol0y.as<int>();
+        t.pcoly = lv.pcoly.as<double>();
+    }
+    // coarsest multigrid level: dense inverse of M_beta
+    {
+        LevelDev& lc = *lev[L];
+        nL = (int)lc.N;
+        HH_REQUIRE(nL <= 4096, "coarsest multigrid level too large");
+        std::vector<zd> A((size_t)nL * nL, 0.0);
+        for (long long I = 0; I < lc.N; ++I)
+            visit_row(lc.ax, lc.ay, const_k, k2c, Sh[L], I,
+                      [&](long long J, double kv, double mv) { A[(size_t)I * nL + J] += kv - beta * mv; });
+        invert_complex(nL, A);
+        std::vector<cx<double>> m64((size_t)nL * nL);
+        std::vector<cx<float>> m32((size_t)nL * nL);
+        for (size_t i = 0; i < A.size(); ++i) {
+            m64[i] = {A[i].real(), A[i].imag()};
+            m32[i] = {(float)A[i].real(), (float)A[i].imag()};
+        }
+        upload(Minv64, m64);
+        upload(Minv32, m32);
+    }
+    // deflation levels
+    Lz = 0;
+    if (o.defl_mode == 1 && L >= 1) Lz = 1;
+    if (o.defl_mode == 2 && L >= 1) {
+        Lz = L;
+        for (int l = 1; l <= L; ++l)
+            if (lev[l]->N <= o.defl_direct_max) {
+                Lz = l;
+                break;
+            }
+    }
+    if (Lz > 0) {
+        LevelDev& lz = *lev[Lz];
+        nZ = (int)lz.N;
+        HH_REQUIRE(nZ <= 32768, "direct deflation level too large");
+        std::vector<double> A((size_t)nZ * nZ, 0.0);
+        for (long long I = 0; I < lz.N; ++I)
+            visit_row(lz.ax, lz.ay, const_k, k2c, Sh[Lz], I,
+                      [&](long long J, double kv, double mv) { A[(size_t)I * nZ + J] += kv - mv; });
+        upload(Einv, A);
+        DevBuf ipiv, info;
+        ipiv.alloc((size_t)nZ * sizeof(rocblas_int));
+        info.alloc(sizeof(rocblas_int));
+        rocblas_handle h;
+        if (rocblas_create_handle(&h) != rocblas_status_success) throw Err{HH_EHIP, "rocblas_create_handle failed"};
+        rocblas_set_stream(h, s);
+        // The row-major buffer read column-major is A^T; its column-major
+        // inverse inv(A^T), read back row-major, is inv(A).
+        rocblas_status st = rocsolver_dgetrf(h, nZ, nZ, Einv.as<double>(), nZ, ipiv.as<rocblas_int>(),
+                                             info.as<rocblas_int>());
+        if (st == rocblas_status_success)
+            st = rocsolver_dgetri(h, nZ, Einv.as<double>(), nZ, ipiv.as<rocblas_int>(), info.as<rocblas_int>());
+        HH_HIP(hipStreamSynchronize(s));
+        rocblas_destroy_handle(h);
+        if (st != rocblas_status_success) throw Err{HH_EHIP, "rocsolver LU inverse failed"};
+        rocblas_int hinfo = 0;
+        HH_HIP(hipMemcpy(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost));
+        if (hinfo != 0) throw Err{HH_ENUMERIC, "deflation matrix E is singular"};
+        for (int l = 0; l < Lz; ++l) {
+            LevelDev& lv = *lev[l];
+            const size_t v64 = (size_t)lv.N * 16;
+            lv.tq.alloc(v64);
+            lv.tw.alloc(v64);
+            lv.ts.alloc(v64);
+        }
+        for (int l = 1; l <= Lz; ++l) {
+            LevelDev& lv = *lev[l];
+            const size_t v64 = (size_t)lv.N * 16;
+            lv.tc.alloc(v64);
+            lv.te.alloc(v64);
+            if (l < Lz) {
+                lv.m_inner = o.defl_inner_its[std::min(l - 1, 7)];
+                lv.V.alloc(v64 * (lv.m_inner + 1));
+                lv.Z.alloc(v64 * lv.m_inner);
+                fill_krylov(lv.kd, lv.kstate, lv.m_inner);
+            }
+        }
+    }
+    // outer FGMRES workspace
+    m_outer = o.restart;
+    const size_t v0 = (size_t)lev[0]->N * 16;
+    V.alloc(v0 * (m_outer + 1));
+    Z.alloc(v0 * m_outer);
+    r.alloc(v0);
+    fill_krylov(kd, kstate, m_outer);
+    HH_HIP(hipStreamSynchronize(s));
+}
+
+// ----------------------------------------------------------- hot path ----
+template <class T>
+void SolverImpl::op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s) {
+    LevelDev& lv = *lev[l];
+    OpArgs<T> a{};
+    a.n1 = lv.n1;
+    a.n2 = lv.n2;
+    a.Kx = lv.Kx.as<double>();
+    a.Mx = lv.Mx.as<double>();
+    a.Ky = lv.Ky.as<double>();
+    a.My = lv.My.as<double>();
+    a.k2c = prob->k_mode == 0 ? prob->k * prob->k : 0.0;
+    a.k2 = lv.k2.as<double>();
+    a.nel1 = lv.ax.nel;
+    a.nel2 = lv.ay.nel;
+    a.off1 = lv.ax.off;
+    a.off2 = lv.ay.off;
+    a.Mex = lv.Mex.as<double>();
+    a.Mey = lv.Mey.as<double>();
+    a.S = pick<T>(lv.S64, lv.S32).template as<T>();
+    a.are = cslp ? (T)o.beta[0] : T(1);
+    a.aim = cslp ? (T)o.beta[1] : T(0);
+    a.x = x;
+    a.b = b;
+    a.y = y;
+    a.dinv = pick<T>(lv.Dinv64, lv.Dinv32).template as<cx<T>>();
+    a.omega = (T)lv.omega;
+    const int py = prob->dim == 2 ? prob->p : 0;
+    if (l == 0) tstart(1, s);
+    launch_op<T>(lv.kind, mode, prob->p, py, a, s);
+    if (l == 0) {
+        // algorithmic bytes: x in, y out, b (residual and smoothing) and D^-1
+        // (smoothing) in, plus the k^2 field of a non-constant wave number
+        const double v = (double)lv.N * 2 * sizeof(T);
+        double bytes = 2 * v + (mode != MODE_APPLY ? v : 0.0) + (mode == MODE_SMOOTH ? v : 0.0);
+        if (lv.kind == KIND_VARFINE) bytes += 8.0 * lv.ax.nel * lv.ay.nel;
+        tstop(1, bytes, s);
+    }
+}
+
+template <class T>
+static void copy_t(long long N, const cx<T>* x, cx<T>* y, hipStream_t s) {
+    HH_HIP(hipMemcpyAsync(y, x, (size_t)N * sizeof(cx<T>), hipMemcpyDeviceToDevice, s));
+}
+
+template <class T>
+void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
+    LevelDev& lv = *lev[l];
+    if (l == L) {
+        launch_gemv<cx<T>, T>(nL, pick<T>(Minv64, Minv32).template as<cx<T>>(), b, x, s);
+        return;
+    }
+    cx<T>* t = pick<T>(lv.t64, lv.t32).template as<cx<T>>();
+    cx<T>* r = pick<T>(lv.r64, lv.r32).template as<cx<T>>();
+    const cx<T>* dinv = pick<T>(lv.Dinv64, lv.Dinv32).template as<cx<T>>();
+    launch_jacobi0<T>(lv.N, dinv, (T)lv.omega, b, x, s);
+    cx<T>* cur = x;
+    cx<T>* oth = t;
+    for (int i = 1; i < o.nu_pre; ++i) {
+        op<T>(l, MODE_SMOOTH, true, cur, b, oth, s);
+        std::swap(cur, oth);
+    }
+    if (cur != x) copy_t<T>(lv.N, cur, x, s);
+    op<T>(l, MODE_RESID, true, x, b, r, s);
+    LevelDev& lc = *lev[l + 1];
+    cx<T>* bc = pick<T>(lc.b64, lc.b32).template as<cx<T>>();
+    cx<T>* xc = pick<T>(lc.x64, lc.x32).template as<cx<T>>();
+    launch_restrict<T>(lv.tr, r, bc, s);
+    vcycle_once<T>(l + 1, bc, xc, s);
+    launch_prolong<T>(lv.tr, xc, x, 1, s);
+    cur = x;
+    oth = t;
+    for (int i = 0; i < o.nu_post; ++i) {
+        op<T>(l, MODE_SMOOTH, true, cur, b, oth, s);
+        std::swap(cur, oth);
+    }
+    if (cur != x) copy_t<T>(lv.N, cur, x, s);
+}
+
+template <class T>
+void SolverImpl::vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
+    vcycle_once<T>(l, b, x, s);
+    LevelDev& lv = *lev[l];
+    for (int i = 1; i < o.n_vcycles; ++i) {
+        cx<T>* vr = pick<T>(lv.vr64, lv.vr32).template as<cx<T>>();
+        cx<T>* vx = pick<T>(lv.vx64, lv.vx32).template as<cx<T>>();
+        op<T>(l, MODE_RESID, true, x, b, vr, s);
+        vcycle_once<T>(l, vr, vx, s);
+        launch_axpy<T>(lv.N, vx, x, s);
+    }
+}
+
+void SolverImpl::precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s) {
+    if (o.precision == 0) {
+        vcycle<double>(l, b, x, s);
+        return;
+    }
+    LevelDev& lv = *lev[l];
+    // FP32 V-cycle: the entry level's own multigrid vectors carry the cast data
+    launch_cast_d2f(lv.N, b, lv.b32.as<cx<float>>(), s);
+    vcycle<float>(l, lv.b32.as<cx<float>>(), lv.x32.as<cx<float>>(), s);
+    launch_cast_f2d(lv.N, lv.x32.as<cx<float>>(), x, s);
+}
+
+void SolverImpl::T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t s) {
+    if (Lz == 0 || l >= Lz) {
+        precond_vcycle(l, v, z, s);
+        return;
+    }
+    LevelDev& lv = *lev[l];
+    LevelDev& lc = *lev[l + 1];
+    launch_restrict<double>(lv.tr, v, lc.tc.as<cx<double>>(), s);
+    coarse_solve(l + 1, lc.tc.as<cx<double>>(), lc.te.as<cx<double>>(), s);
+    launch_prolong<double>(lv.tr, lc.te.as<cx<double>>(), lv.tq.as<cx<double>>(), 0, s);
+    op<double>(l, MODE_RESID, false, lv.tq.as<cx<double>>(), v, lv.tw.as<cx<double>>(), s);
+    precond_vcycle(l, lv.tw.as<cx<double>>(), lv.ts.as<cx<double>>(), s);
+    launch_add(lv.N, lv.ts.as<cx<double>>(), lv.tq.as<cx<double>>(), z, s);
+}
+
+void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s) {
+    if (l == Lz) {
+        tstart(2, s);
+        launch_gemv<double, double>(nZ, Einv.as<double>(), c, e, s);
+        tstop(2, 8.0 * nZ * (double)nZ + 32.0 * nZ, s);
+        return;
+    }
+    LevelDev& lv = *lev[l];
+    const long long N = lv.N;
+    const int m = lv.m_inner;
+    cx<double>* Vb = lv.V.as<cx<double>>();
+    cx<double>* Zb = lv.Z.as<cx<double>>();
+    KrylovDev& k = lv.kd;
+    launch_norm_init(N, c, k, s);
+    launch_scale_by(N, c, Vb, &k.scal[0], s);
+    for (int j = 0; j < m; ++j) {
+        cx<double>* vj = Vb + (size_t)j * N;
+        cx<double>* zj = Zb + (size_t)j * N;
+        cx<double>* w = Vb + (size_t)(j + 1) * N;
+        T_apply(l, vj, zj, s);
+        op<double>(l, MODE_APPLY, false, zj, nullptr, w, s);
+        for (int i = 0; i <= j; ++i) launch_mgs(N, i, j, w, Vb, N, k, s);
+        launch_norm_givens(N, j, w, Vb, N, k, s);
+        launch_scale_by(N, w, w, &k.scal[1], s);
+    }
+    launch_lsq(k, s);
+    launch_update(N, Zb, N, k, e, 0, s);
+}
+
+int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s) {
+    auto t0 = std::chrono::steady_clock::now();
+    ev_used = 0;
+    ev_bytes = 0.0;
+    ev_pending = -1;
+    LevelDev& l0 = *lev[0];
+    const long long N = l0.N;
+    cx<double>* Vb = V.as<cx<double>>();
+    cx<double>* Zb = Z.as<cx<double>>();
+    cx<double>* rr = r.as<cx<double>>();
+    double hs[4];
+    int hi[2];
+    // ||f||
+    launch_dot_norm2(N, f, &kd.scal[3], &kd.ints[2], kd.partials, s);
+    HH_HIP(hipMemcpyAsync(hs, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HH_HIP(hipStreamSynchronize(s));
+    const double nf = std::sqrt(hs[3]);
+    hh_solve_info inf{};
+    if (!std::isfinite(nf)) throw Err{HH_ENUMERIC, "right-hand side is not finite"};
+    if (nf == 0.0) {
+        launch_zero(N, u, s);
+        HH_HIP(hipStreamSynchronize(s));
+        inf.converged = 1;
+        if (info) *info = inf;
+        return HH_OK;
+    }
+    if (use_u0) {
+        op<double>(0, MODE_RESID, false, u, f, rr, s);
+    } else {
+        launch_zero(N, u, s);
+        launch_copy(N, f, rr, s);
+    }
+    const double stop = o.tol * nf;
+    int iters = 0, cycles = 0;
+    double rn = 0.0, gabs = 0.0;
+    bool converged = false;
+    for (;;) {
+        launch_norm_init(N, rr, kd, s);
+        HH_HIP(hipMemcpyAsync(hs, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HH_HIP(hipStreamSynchronize(s));
+        rn = hs[0];
+        if (!std::isfinite(rn)) throw Err{HH_ENUMERIC, "residual is not finite"};
+        if (rn <= stop) {
+            converged = true;
+            break;
+        }
+        if (iters >= o.maxit) break;
+        const int m = std::min(m_outer, o.maxit - iters);
+        launch_scale_by(N, rr, Vb, &kd.scal[0], s);
+        int jdone = 0;
+        for (int j = 0; j < m; ++j) {
+            cx<double>* vj = Vb + (size_t)j * N;
+            cx<double>* zj = Zb + (size_t)j * N;
+            cx<double>* w = Vb + (size_t)(j + 1) * N;
+            T_apply(0, vj, zj, s);
+            op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
+            for (int i = 0; i <= j; ++i) {
+                tstart(3, s);
+                launch_mgs(N, i, j, w, Vb, N, kd, s);
+                tstop(3, (i > 0 ? 64.0 : 32.0) * N, s);
+            }
+            launch_norm_givens(N, j, w, Vb, N, kd, s);
+            HH_HIP(hipMemcpyAsync(hs, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HH_HIP(hipMemcpyAsync(hi, kd.ints, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            HH_HIP(hipStreamSynchronize(s));
+            gabs = hs[2];
+            ++iters;
+            jdone = j + 1;
+            if (!std::isfinite(gabs)) throw Err{HH_ENUMERIC, "Arnoldi recurrence produced NaN/Inf"};
+            if (hi[1] || gabs <= stop) break;
+            launch_scale_by(N, w, w, &kd.scal[1], s);
+        }
+        launch_lsq(kd, s);
+        launch_update(N, Zb, N, kd, u, 1, s);
+        op<double>(0, MODE_RESID, false, u, f, rr, s);
+        ++cycles;
+        if (jdone == 0) break;
+    }
+    // true residual of the returned iterate
+    launch_dot_norm2(N, rr, &kd.scal[3], &kd.ints[2], kd.partials, s);
+    HH_HIP(hipMemcpyAsync(hs, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HH_HIP(hipStreamSynchronize(s));
+    const double rtrue = std::sqrt(hs[3]);
+    auto t1 = std::chrono::steady_clock::now();
+    inf.iters = iters;
+    inf.restarts = std::max(cycles - 1, 0);
+    inf.relres_true = rtrue / nf;
+    inf.relres_est = gabs / nf;
+    inf.converged = (rtrue <= stop) ? 1 : 0;
+    inf.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    {
+        int cnt = 0;
+        inf.op_ms_total = tcollect(&cnt);
+        inf.op_launches = cnt;
+        inf.op_bytes_per_launch = cnt ? ev_bytes / cnt : 0.0;
+    }
+    if (info) *info = inf;
+    (void)converged;
+    return inf.converged ? HH_OK : HH_ENOCONV;
+}
+
+template void SolverImpl::op<double>(int, int, bool, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t);
+template void SolverImpl::op<float>(int, int, bool, const cx<float>*, const cx<float>*, cx<float>*, hipStream_t);
+template void SolverImpl::vcycle<double>(int, const cx<double>*, cx<double>*, hipStream_t);
+template void SolverImpl::vcycle<float>(int, const cx<float>*, cx<float>*, hipStream_t);
+
+}  // namespace hh

@@ -1,0 +1,228 @@
+"""GPU (HIP library, through the C ABI) against the CPU oracle, element by element.
+
+Every building block of the preconditioner and the full FGMRES solve are
+compared on the same seeded inputs.  Tolerances: operators and transfers are
+single passes of FP64 arithmetic (1e-13 relative in norm); the V-cycle and the
+deflated preconditioner compose tens of such passes and dense inverses
+(1e-11 / 1e-10); the solve is compared at equal iteration count at 1e-10
+relative, the bar of the FP64 path.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import helmholtz as hz
+from oracle import solver as osv
+from paper_2010_10232_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def to_dev(x):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).to("cuda")
+
+
+def to_host(t):
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def rvec(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+CASES = {
+    "1d_p2_k50_2lev": dict(dim=1, p=2, n_el=80, k=50.0, x0=(0.5,), opts=dict(defl_mode=1)),
+    "1d_p3_odd_multi": dict(dim=1, p=3, n_el=75, k=40.0, x0=(0.3,), opts=dict(defl_direct_max=20)),
+    "2d_p1_k10": dict(dim=2, p=1, n_el=16, k=10.0, x0=(0.5, 0.5), opts=dict()),
+    "2d_p2_odd_multi": dict(dim=2, p=2, n_el=21, k=13.0, x0=(0.4, 0.55), opts=dict(defl_direct_max=100)),
+    "2d_p3_multi": dict(dim=2, p=3, n_el=24, k=15.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=100)),
+    "2d_p4_odd": dict(dim=2, p=4, n_el=19, k=12.0, x0=(0.5, 0.95), opts=dict()),
+    "2d_p5": dict(dim=2, p=5, n_el=20, k=12.0, x0=(0.25, 0.5), opts=dict()),
+    "2d_wedge_p2": dict(dim=2, p=2, n_el=20, wedge=6.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=100)),
+    "2d_grf_p3": dict(dim=2, p=3, n_el=17, grf=10.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=100)),
+    "2d_rand_p4": dict(dim=2, p=4, n_el=16, rand=9.0, x0=(0.31, 0.77), opts=dict()),
+    "2d_tiles_p3": dict(dim=2, p=3, n_el=130, k=40.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=1200)),
+}
+
+
+def k_field(c):
+    n = c["n_el"]
+    if "wedge" in c:
+        return W.wedge_k(n, c["wedge"])
+    if "grf" in c:
+        return W.grf_k(n, kbar=c["grf"], seed=1)
+    if "rand" in c:
+        return c["rand"] * (1 + 0.4 * W.uniforms(7, n * n).reshape(n, n))
+    return None
+
+
+_cache = {}
+
+
+def build(name):
+    if name in _cache:
+        return _cache[name]
+    from paper_2010_10232_amd import binding as B
+    c = CASES[name]
+    ke = k_field(c)
+    k = c.get("k", 1.0)
+    _say(f"[case {name}] oracle setup")
+    op = hz.Problem(c["dim"], c["p"], c["n_el"], k, k_elem=ke)
+    osol = osv.Solver(op, osv.Options(**c["opts"]))
+    _say(f"[case {name}] gpu assemble+setup")
+    gp = B.Problem(c["dim"], c["p"], c["n_el"], k=k, k_elem=ke)
+    gs = B.Solver(gp, **c["opts"])
+    _cache[name] = (c, op, osol, gp, gs)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_and_damping(name):
+    c, op, osol, gp, gs = build(name)
+    _say(f"[case {name}] level info")
+    assert len(gs.levels) == len(osol.levels)
+    assert gs.levels[0]["defl_direct_level"] == osol.Lz
+    for l, (g, o) in enumerate(zip(gs.levels, osol.levels)):
+        assert g["N"] == o.N
+        assert abs(g["gersh"] - o.gersh) <= 1e-12 * o.gersh
+        assert abs(g["omega"] - o.omega) <= 1e-13
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rhs_point_source(name):
+    c, op, osol, gp, gs = build(name)
+    _say(f"[case {name}] point source")
+    f = to_host(gp.point_source(c["x0"]))
+    ref = hz.point_source_rhs(op, c["x0"])
+    assert np.max(np.abs(f - ref)) <= 1e-15
+    assert np.array_equal(np.nonzero(f)[0], np.nonzero(ref)[0])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_level_operators(name):
+    c, op, osol, gp, gs = build(name)
+    for l, lv in enumerate(osol.levels):
+        x = rvec(lv.N, 10 + l)
+        xd = to_dev(x)
+        _say(f"[case {name}] level {l} A / Mbeta / Jacobi")
+        assert rel(to_host(gs.apply("A", l, xd)), lv.A @ x) <= 1e-13
+        assert rel(to_host(gs.apply("MBETA", l, xd)), lv.Mb @ x) <= 1e-13
+        assert rel(to_host(gs.apply("JACOBI0", l, xd)), lv.omega * x / lv.D) <= 1e-14
+        if l + 1 < len(osol.levels):
+            P = osol.levels[l + 1].P
+            _say(f"[case {name}] level {l} restrict / prolong")
+            assert rel(to_host(gs.apply("RESTRICT", l, xd, out_level=l + 1)), P.T @ x) <= 1e-14
+            xc = rvec(P.shape[1], 20 + l)
+            assert rel(to_host(gs.apply("PROLONG", l, to_dev(xc))), P @ xc) <= 1e-14
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vcycle_and_preconditioner(name):
+    c, op, osol, gp, gs = build(name)
+    N0 = osol.levels[0].N
+    x = rvec(N0, 3)
+    xd = to_dev(x)
+    _say(f"[case {name}] V-cycle level 0")
+    assert rel(to_host(gs.apply("VCYCLE", 0, xd)), osol.vcycle(0, x)) <= 1e-11
+    if len(osol.levels) > 2:
+        x1 = rvec(osol.levels[1].N, 4)
+        _say(f"[case {name}] V-cycle level 1")
+        assert rel(to_host(gs.apply("VCYCLE", 1, to_dev(x1))), osol.vcycle(1, x1)) <= 1e-11
+    for l in range(1, osol.Lz + 1):
+        xl = rvec(osol.levels[l].N, 30 + l)
+        _say(f"[case {name}] E^-1 at deflation level {l}")
+        assert rel(to_host(gs.apply("EINV", l, to_dev(xl))), osol.coarse_solve(l, xl)) <= 1e-10
+    _say(f"[case {name}] T level 0")
+    assert rel(to_host(gs.apply("T", 0, xd)), osol.T(0, x)) <= 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_matches_oracle(name):
+    c, op, osol, gp, gs = build(name)
+    f = hz.point_source_rhs(op, c["x0"])
+    _say(f"[case {name}] oracle solve")
+    u_ref, info_ref = osol.solve(f)
+    _say(f"[case {name}] gpu solve")
+    u, info = gs.solve(to_dev(f))
+    u = to_host(u)
+    assert info["converged"] == 1 and info_ref.converged
+    assert info["iters"] == info_ref.iters
+    assert rel(u, u_ref) <= 1e-10
+    assert abs(info["relres_true"] - info_ref.relres_true) <= 1e-3 * info_ref.relres_true + 1e-15
+
+
+def test_zero_rhs_and_initial_guess():
+    c, op, osol, gp, gs = build("2d_p3_multi")
+    torch = _torch()
+    _say("[case 2d_p3_multi] zero rhs")
+    f = torch.zeros(osol.levels[0].N, dtype=torch.complex128, device="cuda")
+    u, info = gs.solve(f)
+    assert info["converged"] == 1 and info["iters"] == 0
+    assert float(torch.abs(u).max()) == 0.0
+    _say("[case 2d_p3_multi] restart from the converged solution")
+    fr = hz.point_source_rhs(op, c["x0"])
+    u, info = gs.solve(to_dev(fr))
+    u2, info2 = gs.solve(to_dev(fr), u=u.clone(), use_u0=True)
+    assert info2["iters"] == 0 and info2["converged"] == 1
+
+
+def test_maxit_reports_noconv():
+    from paper_2010_10232_amd import binding as B
+    c = CASES["2d_p3_multi"]
+    gp = B.Problem(2, 3, 24, k=15.0)
+    gs = B.Solver(gp, maxit=2, defl_direct_max=100)
+    op = hz.Problem(2, 3, 24, 15.0)
+    osol = osv.Solver(op, osv.Options(maxit=2, defl_direct_max=100))
+    f = hz.point_source_rhs(op, c["x0"])
+    _say("[case maxit=2] gpu solve")
+    u, info = gs.solve(to_dev(f))
+    u_ref, info_ref = osol.solve(f)
+    assert info["converged"] == 0 and info["iters"] == 2 == info_ref.iters
+    assert rel(to_host(u), u_ref) <= 1e-10
+
+
+def test_small_restart_matches_oracle():
+    from paper_2010_10232_amd import binding as B
+    gp = B.Problem(2, 2, 21, k=13.0)
+    gs = B.Solver(gp, restart=3, defl_direct_max=100)
+    op = hz.Problem(2, 2, 21, 13.0)
+    osol = osv.Solver(op, osv.Options(restart=3, defl_direct_max=100))
+    f = hz.point_source_rhs(op, (0.4, 0.55))
+    _say("[case restart=3] gpu solve")
+    u, info = gs.solve(to_dev(f))
+    u_ref, info_ref = osol.solve(f)
+    assert info["iters"] == info_ref.iters and info["restarts"] == info_ref.restarts
+    assert rel(to_host(u), u_ref) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["2d_p3_multi", "2d_wedge_p2", "2d_grf_p3", "1d_p2_k50_2lev"])
+def test_mixed_precision_within_1e6(name):
+    """FP32 V-cycle inside FP64 FGMRES/deflation: within 1e-6 of the FP64 oracle."""
+    from paper_2010_10232_amd import binding as B
+    c, op, osol, gp, _ = build(name)
+    gs32 = B.Solver(gp, precision=1, tol=1e-10, **c["opts"])
+    o64 = osv.Solver(op, osv.Options(tol=1e-10, **c["opts"]))
+    f = hz.point_source_rhs(op, c["x0"])
+    _say(f"[case {name}] mixed-precision solve")
+    u, info = gs32.solve(to_dev(f))
+    u_ref, _ = o64.solve(f)
+    assert info["converged"] == 1
+    assert rel(to_host(u), u_ref) <= 1e-6
