@@ -178,63 +178,79 @@ Axis make_axis(int p, int nel_fine, int level) {
     return a;
 }
 
-// Solve B X = C for X ((q x q) dense, Gaussian elimination with partial pivoting).
-static void small_solve(int q, double* B, double* C) {
-    for (int k = 0; k < q; ++k) {
-        int piv = k;
-        for (int i = k + 1; i < q; ++i)
-            if (std::fabs(B[i * q + k]) > std::fabs(B[piv * q + k])) piv = i;
-        if (piv != k)
-            for (int j = 0; j < q; ++j) {
-                std::swap(B[k * q + j], B[piv * q + j]);
-                std::swap(C[k * q + j], C[piv * q + j]);
-            }
-        for (int i = k + 1; i < q; ++i) {
-            double f = B[i * q + k] / B[k * q + k];
-            for (int j = k; j < q; ++j) B[i * q + j] -= f * B[k * q + j];
-            for (int j = 0; j < q; ++j) C[i * q + j] -= f * C[k * q + j];
-        }
-    }
-    for (int k = q - 1; k >= 0; --k)
-        for (int j = 0; j < q; ++j) {
-            double s = C[k * q + j];
-            for (int i = k + 1; i < q; ++i) s -= B[k * q + i] * C[i * q + j];
-            C[k * q + j] = s / B[k * q + k];
-        }
+// A sparse row of the prolongation: coefficients of one fine-space B-spline
+// coefficient in terms of the coarse coefficients (first column j0, values w).
+struct PRow {
+    int j0 = 0;
+    std::vector<double> w;
+};
+
+static PRow row_combine(double a, const PRow& x, double b, const PRow& y) {
+    PRow r;
+    int lo = std::min(x.j0, y.j0);
+    int hi = std::max(x.j0 + (int)x.w.size(), y.j0 + (int)y.w.size());
+    r.j0 = lo;
+    r.w.assign(hi - lo, 0.0);
+    for (size_t t = 0; t < x.w.size(); ++t) r.w[x.j0 - lo + t] += a * x.w[t];
+    for (size_t t = 0; t < y.w.size(); ++t) r.w[y.j0 - lo + t] += b * y.w[t];
+    return r;
 }
 
 // Knot-insertion prolongation from `coarse` (level l+1) to `fine` (level l),
 // restricted to interior functions, stored as row and column runs in `fine`.
-// On each fine element the p+1 active coarse B-splines are polynomials, hence
-// exact combinations of the p+1 active fine B-splines; the coefficients come
-// from collocation at p+1 points of that element.
+// Boehm's algorithm: the knots of the fine vector missing from the coarse one
+// are inserted one at a time; inserting t into span s (U_s <= t < U_{s+1})
+// maps coefficients c to c'_i = c_i (i <= s-p), a_i c_i + (1 - a_i) c_{i-1}
+// with a_i = (t - U_i)/(U_{i+p} - U_i) (s-p < i <= s), c_{i-1} (i > s).  Run on
+// the identity it yields, row by row, the fine coefficients of every coarse
+// B-spline (convex combinations only, so it is exact to rounding).
 void make_transfer(Axis& fine, const Axis& coarse) {
-    const int p = fine.p, q = p + 1;
-    const int nff = fine.nel + p, ncf = coarse.nel + p;
-    std::vector<double> P((size_t)nff * ncf, 0.0);
-    double gx[8], gw[8], N[8];
-    gauss_legendre(q, gx, gw);
-    for (int i = 0; i < nff; ++i) {
-        int f = std::min(std::max(i - p / 2, std::max(0, i - p)), std::min(i, fine.nel - 1));
-        int E = f >> 1;
-        double lo = fine.bk[f], hi = fine.bk[f + 1];
-        double B[36], C[36];
-        for (int g = 0; g < q; ++g) {
-            double x = lo + (gx[g] + 1.0) * 0.5 * (hi - lo);
-            basis_values(fine.U, p, f + p, x, N, nullptr);
-            for (int a = 0; a < q; ++a) B[g * q + a] = N[a];
-            basis_values(coarse.U, p, E + p, x, N, nullptr);
-            for (int b = 0; b < q; ++b) C[g * q + b] = N[b];
-        }
-        small_solve(q, B, C);  // C now holds X: X[a][b] = coeff of coarse E+b on fine f+a
-        int a = i - f;
-        for (int b = 0; b < q; ++b) P[(size_t)i * ncf + E + b] = C[a * q + b];
+    const int p = fine.p;
+    std::vector<double> U = coarse.U;
+    const int ncf = coarse.nel + p;
+    std::vector<PRow> rows(ncf);
+    for (int j = 0; j < ncf; ++j) {
+        rows[j].j0 = j;
+        rows[j].w = {1.0};
     }
-    for (double& v : P)
-        if (std::fabs(v) < 1e-12) v = 0.0;
+    // knots to insert: fine breakpoints that are not coarse breakpoints
+    std::vector<double> ins;
+    {
+        size_t c = 0;
+        for (double b : fine.bk) {
+            while (c < coarse.bk.size() && coarse.bk[c] < b) ++c;
+            if (c < coarse.bk.size() && coarse.bk[c] == b) continue;
+            ins.push_back(b);
+        }
+    }
+    for (double t : ins) {
+        int s = p;
+        while (s + 1 < (int)U.size() && U[s + 1] <= t) ++s;
+        const int n = (int)rows.size();
+        std::vector<PRow> nr(n + 1);
+        for (int i = 0; i <= n; ++i) {
+            if (i <= s - p) {
+                nr[i] = rows[i];
+            } else if (i >= s + 1) {
+                nr[i] = rows[i - 1];
+            } else {
+                const double a = (t - U[i]) / (U[i + p] - U[i]);
+                nr[i] = row_combine(a, rows[i], 1.0 - a, rows[i - 1]);
+            }
+        }
+        rows.swap(nr);
+        U.insert(U.begin() + s + 1, t);
+    }
+    HH_REQUIRE((int)rows.size() == fine.nel + p, "knot insertion produced the wrong dimension");
+    auto Pint = [&](int i, int J) -> double {  // interior entry (fine i, coarse J)
+        const PRow& r = rows[i + 1];
+        const int t = J + 1 - r.j0;
+        if (t < 0 || t >= (int)r.w.size()) return 0.0;
+        const double v = r.w[t];
+        return std::fabs(v) < 1e-15 ? 0.0 : v;
+    };
     // interior part (drop first/last function in both spaces)
     const int nf = fine.n, nc = coarse.n;
-    auto Pint = [&](int i, int J) { return P[(size_t)(i + 1) * ncf + (J + 1)]; };
     fine.pw = std::min(p + 1, nc);
     fine.rw = std::min(p + 2, nf);
     fine.prow0.assign(nf, 0);
