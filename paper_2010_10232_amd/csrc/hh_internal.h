@@ -150,8 +150,9 @@ struct KrylovDev {
     cx<double>* g;    // m+1
     cx<double>* y;    // m
     double* scal;     // [0] beta, [1] hn, [2] |g_{j+1}|, [3] norm accumulator
-    int* ints;        // [0] jdone, [1] breakdown flag, [2] reduction counter
-    cx<double>* partials;  // reduction partials (max 1024)
+    int* ints;        // [0] jdone, [1] breakdown flag, [2] reduction counter,
+                      // [3] barrier arrivals, [4] barrier generation, [5] barrier timeout flag
+    cx<double>* partials;  // reduction partials (2 x 1024, double-buffered)
     int m;
 };
 
@@ -184,6 +185,13 @@ void launch_mgs(long long N, int i, int j, cx<double>* w, const cx<double>* V, l
 void launch_norm_givens(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv,
                         KrylovDev& k, hipStream_t s);
 void launch_lsq(KrylovDev& k, hipStream_t s);
+// fused Arnoldi step (MGS + norm + Givens + normalise): one workgroup for short
+// vectors, a cooperatively launched grid otherwise
+constexpr long long kSmallArnoldi = 4096;
+void launch_arnoldi_coop(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv,
+                         KrylovDev& k, hipStream_t s);
+void launch_arnoldi_small(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv,
+                          KrylovDev& k, hipStream_t s);
 void launch_update(long long N, const cx<double>* Z, long long ldz, KrylovDev& k, cx<double>* u,
                    int accumulate, hipStream_t s);
 void launch_dot_norm2(long long N, const cx<double>* x, double* out, int* counter, cx<double>* partials,

@@ -338,33 +338,10 @@ __device__ void givens_rot(cx<double> a, cx<double> b, double& c, cx<double>& s)
     }
 }
 
-// w -= H[j,j] V[j]; hn = ||w||; H[j+1,j] = hn; Givens update of column j and g.
-__global__ __launch_bounds__(RB) void norm_givens_kernel(long long N, int j, cx<double>* __restrict__ w,
-                                                         const cx<double>* __restrict__ V, long long ldv,
-                                                         KrylovDev k) {
-    __shared__ double sh[2 * RB];
-    __shared__ bool flag;
+// Givens update of Hessenberg column j (previous rotations, then a new one
+// annihilating H[j+1, j]) and of the residual vector g; single thread.
+__device__ void givens_column(KrylovDev& k, int j, double hn) {
     const int ldh = k.m + 1;
-    const cx<double> h = hload(&k.H[(size_t)j * ldh + j]);
-    const cx<double>* vp = V + (size_t)j * ldv;
-    double sr = 0.0, dummy = 0.0;
-    const long long stride = (long long)gridDim.x * RB;
-    for (long long t = (long long)blockIdx.x * RB + threadIdx.x; t < N; t += stride) {
-        cx<double> wv = w[t];
-        const cx<double> pv = vp[t];
-        wv.re -= h.re * pv.re - h.im * pv.im;
-        wv.im -= h.re * pv.im + h.im * pv.re;
-        w[t] = wv;
-        sr += wv.re * wv.re + wv.im * wv.im;
-    }
-    block_sum2(sr, dummy, sh);
-    if (threadIdx.x == 0) k.partials[blockIdx.x] = {sr, 0.0};
-    if (!last_block(&k.ints[2], &flag)) return;
-    double tr, ti;
-    sum_partials(k.partials, gridDim.x, tr, ti, sh);
-    if (threadIdx.x != 0) return;
-    k.ints[2] = 0;
-    const double hn = sqrt(tr);
     k.scal[1] = hn;
     cx<double>* Hc = k.H + (size_t)j * ldh;
     Hc[j + 1] = {hn, 0.0};
@@ -400,9 +377,204 @@ __global__ __launch_bounds__(RB) void norm_givens_kernel(long long N, int j, cx<
     if (hn == 0.0) k.ints[1] = 1;
 }
 
+// w -= H[j,j] V[j]; hn = ||w||; H[j+1,j] = hn; Givens update of column j and g.
+__global__ __launch_bounds__(RB) void norm_givens_kernel(long long N, int j, cx<double>* __restrict__ w,
+                                                         const cx<double>* __restrict__ V, long long ldv,
+                                                         KrylovDev k) {
+    __shared__ double sh[2 * RB];
+    __shared__ bool flag;
+    const int ldh = k.m + 1;
+    const cx<double> h = hload(&k.H[(size_t)j * ldh + j]);
+    const cx<double>* vp = V + (size_t)j * ldv;
+    double sr = 0.0, dummy = 0.0;
+    const long long stride = (long long)gridDim.x * RB;
+    for (long long t = (long long)blockIdx.x * RB + threadIdx.x; t < N; t += stride) {
+        cx<double> wv = w[t];
+        const cx<double> pv = vp[t];
+        wv.re -= h.re * pv.re - h.im * pv.im;
+        wv.im -= h.re * pv.im + h.im * pv.re;
+        w[t] = wv;
+        sr += wv.re * wv.re + wv.im * wv.im;
+    }
+    block_sum2(sr, dummy, sh);
+    if (threadIdx.x == 0) k.partials[blockIdx.x] = {sr, 0.0};
+    if (!last_block(&k.ints[2], &flag)) return;
+    double tr, ti;
+    sum_partials(k.partials, gridDim.x, tr, ti, sh);
+    if (threadIdx.x != 0) return;
+    k.ints[2] = 0;
+    givens_column(k, j, sqrt(tr));
+}
+
 void launch_norm_givens(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
                         hipStream_t s) {
     hipLaunchKernelGGL(norm_givens_kernel, dim3(reduction_blocks(N)), dim3(RB), 0, s, N, j, w, V, ldv, k);
+}
+
+// One whole Arnoldi step on a short vector in a single workgroup: modified
+// Gram-Schmidt of w against V[0..j] (h_ij = V_i^H w, w -= h_ij V_i, in order),
+// hn = ||w||, the Givens update, and w /= hn.  Each thread owns a fixed strided
+// subset of the entries, so only the reductions need barriers.
+constexpr int SB = 1024;
+__global__ __launch_bounds__(SB) void arnoldi_small_kernel(long long N, int j, cx<double>* __restrict__ w,
+                                                           const cx<double>* __restrict__ V, long long ldv,
+                                                           KrylovDev k) {
+    __shared__ double sh[2 * SB];
+    const int tid = threadIdx.x;
+    const int ldh = k.m + 1;
+    for (int i = 0; i <= j; ++i) {
+        const cx<double>* vi = V + (size_t)i * ldv;
+        double sr = 0.0, si = 0.0;
+        for (long long t = tid; t < N; t += SB) {
+            const cx<double> cv = vi[t], wv = w[t];
+            sr += cv.re * wv.re + cv.im * wv.im;
+            si += cv.re * wv.im - cv.im * wv.re;
+        }
+        sh[tid] = sr;
+        sh[SB + tid] = si;
+        __syncthreads();
+        for (int o = SB / 2; o > 0; o >>= 1) {
+            if (tid < o) {
+                sh[tid] += sh[tid + o];
+                sh[SB + tid] += sh[SB + tid + o];
+            }
+            __syncthreads();
+        }
+        const cx<double> h = {sh[0], sh[SB]};
+        __syncthreads();
+        if (tid == 0) k.H[(size_t)j * ldh + i] = h;
+        for (long long t = tid; t < N; t += SB) {
+            const cx<double> cv = vi[t];
+            cx<double> wv = w[t];
+            wv.re -= h.re * cv.re - h.im * cv.im;
+            wv.im -= h.re * cv.im + h.im * cv.re;
+            w[t] = wv;
+        }
+    }
+    double nr = 0.0;
+    for (long long t = tid; t < N; t += SB) {
+        const cx<double> wv = w[t];
+        nr += wv.re * wv.re + wv.im * wv.im;
+    }
+    sh[tid] = nr;
+    __syncthreads();
+    for (int o = SB / 2; o > 0; o >>= 1) {
+        if (tid < o) sh[tid] += sh[tid + o];
+        __syncthreads();
+    }
+    const double hn = sqrt(sh[0]);
+    if (tid == 0) givens_column(k, j, hn);
+    for (long long t = tid; t < N; t += SB) {
+        const cx<double> wv = w[t];
+        w[t] = hn == 0.0 ? cx<double>{0.0, 0.0} : cx<double>{wv.re / hn, wv.im / hn};
+    }
+}
+
+void launch_arnoldi_small(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(arnoldi_small_kernel, dim3(1), dim3(SB), 0, s, N, j, w, V, ldv, k);
+}
+
+// Grid-wide barrier for a cooperatively launched grid (all workgroups are
+// resident).  Arrival counter plus generation number; the last arrival resets
+// the counter and bumps the generation.  The wait is bounded: after ~2^24
+// polls the workgroup sets *abortf and leaves, so every wave always finishes.
+__device__ __forceinline__ void grid_barrier(int* count, int* gen, int* abortf) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (atomicAdd(count, 1) == (int)gridDim.x - 1) {
+            __hip_atomic_store(count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long long spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1LL << 24)) {
+                    atomicExch(abortf, 1);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// Deterministic grid-wide complex sum: block partial -> double-buffered slot ->
+// barrier -> every block sums all slots in index order (same result everywhere).
+__device__ __forceinline__ cx<double> grid_sum(double sr, double si, int round, KrylovDev& k, double* sh) {
+    block_sum2(sr, si, sh);
+    cx<double>* buf = k.partials + (size_t)(round & 1) * 1024;
+    if (threadIdx.x == 0) buf[blockIdx.x] = {sr, si};
+    __syncthreads();
+    grid_barrier(&k.ints[3], &k.ints[4], &k.ints[5]);
+    double tr = 0.0, ti = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += RB) {
+        const cx<double> v = buf[b];
+        tr += v.re;
+        ti += v.im;
+    }
+    block_sum2(tr, ti, sh);
+    return {tr, ti};
+}
+
+// One whole Arnoldi step across a cooperatively launched grid: modified
+// Gram-Schmidt of w against V[0..j] (one grid-wide reduction per basis
+// vector, in order), hn = ||w||, the Givens update (block 0) and w /= hn.
+__global__ __launch_bounds__(RB) void arnoldi_coop_kernel(long long N, int j, cx<double>* __restrict__ w,
+                                                          const cx<double>* __restrict__ V, long long ldv,
+                                                          KrylovDev k) {
+    __shared__ double sh[2 * RB];
+    const long long stride = (long long)gridDim.x * RB;
+    const long long t0 = (long long)blockIdx.x * RB + threadIdx.x;
+    const int ldh = k.m + 1;
+    int round = 0;
+    for (int i = 0; i <= j; ++i, ++round) {
+        const cx<double>* vi = V + (size_t)i * ldv;
+        double sr = 0.0, si = 0.0;
+        for (long long t = t0; t < N; t += stride) {
+            const cx<double> cv = vi[t], wv = w[t];
+            sr += cv.re * wv.re + cv.im * wv.im;
+            si += cv.re * wv.im - cv.im * wv.re;
+        }
+        const cx<double> h = grid_sum(sr, si, round, k, sh);
+        if (blockIdx.x == 0 && threadIdx.x == 0) k.H[(size_t)j * ldh + i] = h;
+        for (long long t = t0; t < N; t += stride) {
+            const cx<double> cv = vi[t];
+            cx<double> wv = w[t];
+            wv.re -= h.re * cv.re - h.im * cv.im;
+            wv.im -= h.re * cv.im + h.im * cv.re;
+            w[t] = wv;
+        }
+    }
+    double nr = 0.0;
+    for (long long t = t0; t < N; t += stride) {
+        const cx<double> wv = w[t];
+        nr += wv.re * wv.re + wv.im * wv.im;
+    }
+    const double hn = sqrt(grid_sum(nr, 0.0, round, k, sh).re);
+    if (blockIdx.x == 0 && threadIdx.x == 0) givens_column(k, j, hn);
+    for (long long t = t0; t < N; t += stride) {
+        const cx<double> wv = w[t];
+        w[t] = hn == 0.0 ? cx<double>{0.0, 0.0} : cx<double>{wv.re / hn, wv.im / hn};
+    }
+}
+
+int coop_blocks(long long N) {
+    long long b = (N + 8 * RB - 1) / (8 * RB);
+    if (b < 1) b = 1;
+    if (b > 256) b = 256;
+    return (int)b;
+}
+
+void launch_arnoldi_coop(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
+                         hipStream_t s) {
+    void* args[] = {&N, &j, &w, &V, &ldv, &k};
+    hipError_t e = hipLaunchCooperativeKernel((const void*)arnoldi_coop_kernel, dim3(coop_blocks(N)), dim3(RB), args,
+                                              0, s);
+    if (e != hipSuccess) throw Err{HH_EHIP, std::string("cooperative Arnoldi launch: ") + hipGetErrorString(e)};
 }
 
 // ||x||^2 into *out (plain reduction).

@@ -31,186 +31,250 @@ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
 // --------------------------------------------------------------------------
 // Level operator
 // --------------------------------------------------------------------------
-template <int PX, int PY, int TY, int KIND, int MODE, class T>
-__global__ __launch_bounds__(64) void op_kernel(OpArgs<T> a) {
+// Row-marching level operator.  A workgroup is one wave of 64 lanes; it owns
+// 64 columns and `ty` output rows, and walks the ty + 2p input rows of its
+// strip once, top to bottom.  Each input row is prefetched into registers one
+// iteration ahead and then written into a circular LDS buffer that holds the
+// last 2p+1 rows (with a p-wide column halo).  Lane c keeps 2p+1 running
+// output rows in registers (a sliding window): input row r feeds output rows
+// r-2p .. r through the y-bands, after which output row r-2p is complete and
+// is written out (with the residual / Jacobi epilogue).
+template <int PX, int PY, int KIND, int MODE, class T>
+__global__ __launch_bounds__(64) void op_kernel(OpArgs<T> a, int ty) {
     constexpr int TX = 64;
     constexpr int BX = 2 * PX + 1, BY = 2 * PY + 1;
-    constexpr int LW = TX + 2 * PX, LH = TY + 2 * PY;
-    __shared__ cx<T> xs[LH][LW];
+    constexpr int QX = PX + 1, QY = PY + 1;
+    constexpr int LW = TX + 2 * PX;
+    constexpr int W = 2 * PY + 1;                       // window rows
+    constexpr int NMEX = (KIND == KIND_VARFINE) ? QX * QX : 1;
+    constexpr int NMEY = (KIND == KIND_VARFINE) ? QY * QY : 1;
+    __shared__ cx<T> xs[W][LW];
+    __shared__ T myS[W][BY], kyS[W][BY];
+    __shared__ T mexS[NMEX][TX];
+    __shared__ T meyS[NMEY];
+
     const int lane = threadIdx.x;
-    const int C0 = blockIdx.x * TX, R0 = blockIdx.y * TY;
+    const int C0 = blockIdx.x * TX, R0 = blockIdx.y * ty;
     const int n1 = a.n1, n2 = a.n2;
-
-    for (int idx = lane; idx < LH * LW; idx += TX) {
-        const int r = idx / LW, c = idx - r * LW;
-        const int J2 = R0 - PY + r, J1 = C0 - PX + c;
-        cx<T> v = {T(0), T(0)};
-        if (J2 >= 0 && J2 < n2 && J1 >= 0 && J1 < n1) v = a.x[(size_t)J2 * n1 + J1];
-        xs[r][c] = v;
-    }
-    __syncthreads();
-
+    const int LH = ty + 2 * PY;
     const int I1 = C0 + lane;
     const int I1c = I1 < n1 ? I1 : n1 - 1;
+
     T kx[BX], mx[BX];
 #pragma unroll
     for (int d = 0; d < BX; ++d) {
         kx[d] = (T)a.Kx[(size_t)I1c * BX + d];
         mx[d] = (T)a.Mx[(size_t)I1c * BX + d];
     }
-    T accr[TY], acci[TY], mr[TY], mi[TY];
+    if (KIND == KIND_VARFINE) {
 #pragma unroll
-    for (int t = 0; t < TY; ++t) accr[t] = acci[t] = mr[t] = mi[t] = T(0);
-
-    const T are = a.are, aim = a.aim;
-    const T k2c = (T)a.k2c;
-    // stiffness part (plus the constant-k mass part)
+        for (int a1 = 0; a1 < QX; ++a1) {
+            const int e1 = min(max(I1c + a.off1 - a1, 0), a.nel1 - 1);
 #pragma unroll
-    for (int r = 0; r < LH; ++r) {
-        T u1r = 0, u1i = 0, u2r = 0, u2i = 0;
-#pragma unroll
-        for (int d = 0; d < BX; ++d) {
-            const cx<T> v = xs[r][lane + d];
-            u1r += kx[d] * v.re;
-            u1i += kx[d] * v.im;
-            u2r += mx[d] * v.re;
-            u2i += mx[d] * v.im;
-        }
-#pragma unroll
-        for (int t = 0; t < TY; ++t) {
-            const int d2 = r - PY - t;
-            if (d2 < -PY || d2 > PY) continue;
-            const int I2 = R0 + t;
-            if (I2 >= n2) continue;
-            const T my = (T)a.My[(size_t)I2 * BY + d2 + PY];
-            const T ky = (T)a.Ky[(size_t)I2 * BY + d2 + PY];
-            if (KIND == KIND_SEP) {
-                const T cr = u1r - k2c * (are * u2r - aim * u2i);
-                const T ci = u1i - k2c * (are * u2i + aim * u2r);
-                accr[t] += my * cr + ky * u2r;
-                acci[t] += my * ci + ky * u2i;
-            } else {
-                accr[t] += my * u1r + ky * u2r;
-                acci[t] += my * u1i + ky * u2i;
-            }
+            for (int c1 = 0; c1 < QX; ++c1) mexS[a1 * QX + c1][lane] = (T)a.Mex[(size_t)e1 * QX * QX + a1 * QX + c1];
         }
     }
 
-    if (KIND == KIND_VARFINE) {
-        constexpr int QX = PX + 1, QY = PY + 1;
-        // element mass rows of this column: local index a1 in element e1 = I1 + off1 - a1
-        T mex[QX][QX];
-        bool ev[QX];
-#pragma unroll
-        for (int a1 = 0; a1 < QX; ++a1) {
-            const int e1 = I1c + a.off1 - a1;
-            ev[a1] = (e1 >= 0 && e1 < a.nel1);
-            const int ec = ev[a1] ? e1 : 0;
-#pragma unroll
-            for (int c1 = 0; c1 < QX; ++c1) mex[a1][c1] = (T)a.Mex[(size_t)ec * QX * QX + a1 * QX + c1];
+    // register prefetch of one input row (two columns per lane), its band row,
+    // and (VARFINE) the k^2 values / y element block of one element row
+    cx<T> px0 = {T(0), T(0)}, px1 = {T(0), T(0)};
+    T pband = T(0), pmey = T(0);
+    T pk2[QX];
+    auto fetch = [&](int r) {
+        const int J2 = R0 - PY + r;
+        const bool rowok = (J2 >= 0 && J2 < n2);
+        const int J1a = C0 - PX + lane, J1b = J1a + TX;
+        px0 = (rowok && J1a >= 0 && J1a < n1) ? a.x[(size_t)J2 * n1 + J1a] : cx<T>{T(0), T(0)};
+        px1 = (rowok && lane < LW - TX && J1b < n1) ? a.x[(size_t)J2 * n1 + J1b] : cx<T>{T(0), T(0)};
+        // band row of output row R0 + r (newest output row fed by input row r)
+        const int I2 = R0 + r;
+        pband = T(0);
+        if (I2 < n2) {
+            if (lane < BY) pband = (T)a.My[(size_t)I2 * BY + lane];
+            else if (lane < 2 * BY) pband = (T)a.Ky[(size_t)I2 * BY + lane - BY];
         }
+        if (KIND == KIND_VARFINE) {
+            // element row processed at iteration r: s = r - PY
+            const int e2 = R0 + a.off2 - PY + (r - PY);
+            const bool eok = (r >= PY && e2 >= 0 && e2 < a.nel2);
 #pragma unroll
-        for (int s = 0; s < TY + PY; ++s) {
-            const int e2 = R0 + a.off2 - PY + s;
-            if (e2 < 0 || e2 >= a.nel2) continue;
+            for (int a1 = 0; a1 < QX; ++a1) {
+                const int e1 = I1 + a.off1 - a1;
+                pk2[a1] = (eok && e1 >= 0 && e1 < a.nel1) ? (T)a.k2[(size_t)e2 * a.nel1 + e1] : T(0);
+            }
+            pmey = (eok && lane < QY * QY) ? (T)a.Mey[(size_t)e2 * QY * QY + lane] : T(0);
+        }
+    };
+
+    T wr[W], wi[W], vr[W], vi[W];   // window: K part and (non-SEP) mass part
+#pragma unroll
+    for (int k = 0; k < W; ++k) wr[k] = wi[k] = vr[k] = vi[k] = T(0);
+    const T are = a.are, aim = a.aim;
+    const T k2c = (T)a.k2c;
+    const size_t N = (size_t)n1 * n2;
+
+    fetch(0);
+    int slot = 0;   // LDS slot of input row r
+#pragma unroll 1
+    for (int r = 0; r < LH; ++r) {
+        xs[slot][lane] = px0;
+        if (lane < LW - TX) xs[slot][lane + TX] = px1;
+        if (lane < BY) myS[slot][lane] = pband;
+        else if (lane < 2 * BY) kyS[slot][lane - BY] = pband;
+        T k2r[QX];
+        if (KIND == KIND_VARFINE) {
+#pragma unroll
+            for (int a1 = 0; a1 < QX; ++a1) k2r[a1] = pk2[a1];
+            if (lane < QY * QY) meyS[lane] = pmey;
+        }
+        __syncthreads();
+        if (r + 1 < LH) fetch(r + 1);
+
+        // stiffness part (+ constant-k mass) from input row r
+        {
+            T u1r = 0, u1i = 0, u2r = 0, u2i = 0;
+#pragma unroll
+            for (int d = 0; d < BX; ++d) {
+                const cx<T> v = xs[slot][lane + d];
+                u1r += kx[d] * v.re;
+                u1i += kx[d] * v.im;
+                u2r += mx[d] * v.re;
+                u2i += mx[d] * v.im;
+            }
+            if (KIND == KIND_SEP) {
+                const T cr = u1r - k2c * (are * u2r - aim * u2i);
+                const T ci = u1i - k2c * (are * u2i + aim * u2r);
+                u1r = cr;
+                u1i = ci;
+            }
+            // window entry k is output row r - 2p + k, whose band slot is
+            // that of input row r - 2p + k; the coupling offset is d2 = p - k
+            int bs = slot + 1;   // slot of row r - 2p  (== (slot - 2p) mod W)
+            if (bs >= W) bs -= W;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const T my = myS[bs][2 * PY - k], ky = kyS[bs][2 * PY - k];
+                wr[k] += my * u1r + ky * u2r;
+                wi[k] += my * u1i + ky * u2i;
+                if (++bs == W) bs = 0;
+            }
+        }
+
+        if (KIND == KIND_VARFINE && r >= PY) {
+            // element row s = r - p: x rows r-p .. r, output rows r-2p .. r-p
             T B[BX];
 #pragma unroll
             for (int d = 0; d < BX; ++d) B[d] = T(0);
 #pragma unroll
-            for (int a1 = 0; a1 < QX; ++a1) {
-                if (!ev[a1]) continue;
-                const T w = (T)a.k2[(size_t)e2 * a.nel1 + (I1c + a.off1 - a1)];
+            for (int a1 = 0; a1 < QX; ++a1)
 #pragma unroll
-                for (int c1 = 0; c1 < QX; ++c1) B[c1 - a1 + PX] += w * mex[a1][c1];
-            }
+                for (int c1 = 0; c1 < QX; ++c1) B[c1 - a1 + PX] += k2r[a1] * mexS[a1 * QX + c1][lane];
             T tr[QY], ti[QY];
+            int xsl = slot + W - PY;   // slot of input row r - p
+            if (xsl >= W) xsl -= W;
 #pragma unroll
             for (int c2 = 0; c2 < QY; ++c2) {
                 T sr = 0, si = 0;
 #pragma unroll
                 for (int d = 0; d < BX; ++d) {
-                    const cx<T> v = xs[s + c2][lane + d];
+                    const cx<T> v = xs[xsl][lane + d];
                     sr += B[d] * v.re;
                     si += B[d] * v.im;
                 }
                 tr[c2] = sr;
                 ti[c2] = si;
+                if (++xsl == W) xsl = 0;
             }
-            const double* mey = a.Mey + (size_t)e2 * QY * QY;
 #pragma unroll
             for (int a2 = 0; a2 < QY; ++a2) {
-                const int t = s + a2 - PY;
-                if (t < 0 || t >= TY) continue;
                 T sr = 0, si = 0;
 #pragma unroll
                 for (int c2 = 0; c2 < QY; ++c2) {
-                    const T g = (T)mey[a2 * QY + c2];
+                    const T g = meyS[a2 * QY + c2];
                     sr += g * tr[c2];
                     si += g * ti[c2];
                 }
-                mr[t] += sr;
-                mi[t] += si;
+                vr[a2] += sr;   // window entry a2 = output row r - 2p + a2
+                vi[a2] += si;
             }
         }
-    }
 
-    if (KIND == KIND_STENCIL) {
-        const size_t N = (size_t)n1 * n2;
-#pragma unroll
-        for (int t = 0; t < TY; ++t) {
+        // output row t = r - 2p is complete
+        const int t = r - 2 * PY;
+        if (t >= 0 && t < ty && I1 < n1 && R0 + t < n2) {
             const int I2 = R0 + t;
-            if (I2 >= n2) continue;
-            const size_t I = (size_t)I2 * n1 + I1c;
-            T sr = 0, si = 0;
+            const size_t I = (size_t)I2 * n1 + I1;
+            T yr = wr[0], yi = wi[0];
+            if (KIND == KIND_STENCIL) {
+                T sr = 0, si = 0;
+                int xsl = slot + 1;   // slot of input row r - 2p (= output row t - p)
+                if (xsl >= W) xsl -= W;
 #pragma unroll
-            for (int d2 = 0; d2 < BY; ++d2)
+                for (int d2 = 0; d2 < BY; ++d2) {
 #pragma unroll
-                for (int d1 = 0; d1 < BX; ++d1) {
-                    const T c = a.S[(size_t)(d2 * BX + d1) * N + I];
-                    const cx<T> v = xs[t + d2][lane + d1];
-                    sr += c * v.re;
-                    si += c * v.im;
+                    for (int d1 = 0; d1 < BX; ++d1) {
+                        const T c = a.S[(size_t)(d2 * BX + d1) * N + I];
+                        const cx<T> v = xs[xsl][lane + d1];
+                        sr += c * v.re;
+                        si += c * v.im;
+                    }
+                    if (++xsl == W) xsl = 0;
                 }
-            mr[t] = sr;
-            mi[t] = si;
-        }
-    }
-
-    if (I1 >= n1) return;
-#pragma unroll
-    for (int t = 0; t < TY; ++t) {
-        const int I2 = R0 + t;
-        if (I2 >= n2) continue;
-        T yr = accr[t], yi = acci[t];
-        if (KIND != KIND_SEP) {
-            yr -= are * mr[t] - aim * mi[t];
-            yi -= are * mi[t] + aim * mr[t];
-        }
-        const size_t I = (size_t)I2 * n1 + I1;
-        cx<T> out;
-        if (MODE == MODE_APPLY) {
-            out = {yr, yi};
-        } else {
-            const cx<T> bv = a.b[I];
-            const T rr = bv.re - yr, ri = bv.im - yi;
-            if (MODE == MODE_RESID) {
-                out = {rr, ri};
-            } else {
-                const cx<T> dv = a.dinv[I];
-                const cx<T> xv = xs[t + PY][lane + PX];
-                out = {xv.re + a.omega * (dv.re * rr - dv.im * ri),
-                       xv.im + a.omega * (dv.re * ri + dv.im * rr)};
+                vr[0] = sr;
+                vi[0] = si;
             }
+            if (KIND != KIND_SEP) {
+                yr -= are * vr[0] - aim * vi[0];
+                yi -= are * vi[0] + aim * vr[0];
+            }
+            cx<T> out;
+            if (MODE == MODE_APPLY) {
+                out = {yr, yi};
+            } else {
+                const cx<T> bv = a.b[I];
+                const T rr = bv.re - yr, ri = bv.im - yi;
+                if (MODE == MODE_RESID) {
+                    out = {rr, ri};
+                } else {
+                    const cx<T> dv = a.dinv[I];
+                    int cs = slot + W - PY;   // slot of input row r - p = output row t
+                    if (cs >= W) cs -= W;
+                    const cx<T> xv = xs[cs][lane + PX];
+                    out = {xv.re + a.omega * (dv.re * rr - dv.im * ri),
+                           xv.im + a.omega * (dv.re * ri + dv.im * rr)};
+                }
+            }
+            a.y[I] = out;
         }
-        a.y[I] = out;
+        // slide the window
+#pragma unroll
+        for (int k = 0; k + 1 < W; ++k) {
+            wr[k] = wr[k + 1];
+            wi[k] = wi[k + 1];
+            vr[k] = vr[k + 1];
+            vi[k] = vi[k + 1];
+        }
+        wr[W - 1] = wi[W - 1] = vr[W - 1] = vi[W - 1] = T(0);
+        if (++slot == W) slot = 0;
+        __syncthreads();
     }
+}
+
+// Strip height: the tallest of 64, 32, 16, 8, 4 rows that still gives at
+// least 2048 waves (eight per CU); tall strips amortise the 2p halo rows.
+inline int op_rows_per_strip(int n1, int n2, int py) {
+    if (py == 0) return 1;
+    const long long cols = (n1 + 63) / 64;
+    int ty = 64;
+    while (ty > 4 && cols * ((n2 + ty - 1) / ty) < 2048) ty >>= 1;
+    return ty;
 }
 
 template <int PX, int PY, int KIND, int MODE, class T>
 static void launch_op_t(const OpArgs<T>& a, hipStream_t s) {
-    constexpr int TY = (PY == 0) ? 1 : (KIND == KIND_SEP ? 16 : 8);
-    dim3 grid((a.n1 + 63) / 64, (a.n2 + TY - 1) / TY);
-    hipLaunchKernelGGL((op_kernel<PX, PY, TY, KIND, MODE, T>), grid, dim3(64), 0, s, a);
+    const int ty = op_rows_per_strip(a.n1, a.n2, PY);
+    dim3 grid((a.n1 + 63) / 64, (a.n2 + ty - 1) / ty);
+    hipLaunchKernelGGL((op_kernel<PX, PY, KIND, MODE, T>), grid, dim3(64), 0, s, a, ty);
 }
 
 template <int PX, int PY, class T>

@@ -127,7 +127,7 @@ static void invert_complex(int n, std::vector<zd>& A) {
 
 // --------------------------------------------------------------- helpers --
 static void fill_krylov(KrylovDev& k, DevBuf& blob, int m) {
-    const size_t nH = (size_t)(m + 1) * m, nb = 1024;
+    const size_t nH = (size_t)(m + 1) * m, nb = 2048;
     size_t bytes = 16 * nH + 8 * m + 16 * m + 16 * (m + 1) + 16 * m + 8 * 8 + 16 * nb + 4 * 8;
     blob.alloc(bytes + 256);
     char* p = blob.as<char>();
@@ -543,9 +543,10 @@ void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStre
         cx<double>* w = Vb + (size_t)(j + 1) * N;
         T_apply(l, vj, zj, s);
         op<double>(l, MODE_APPLY, false, zj, nullptr, w, s);
-        for (int i = 0; i <= j; ++i) launch_mgs(N, i, j, w, Vb, N, k, s);
-        launch_norm_givens(N, j, w, Vb, N, k, s);
-        launch_scale_by(N, w, w, &k.scal[1], s);
+        if (N <= kSmallArnoldi)
+            launch_arnoldi_small(N, j, w, Vb, N, k, s);
+        else
+            launch_arnoldi_coop(N, j, w, Vb, N, k, s);
     }
     launch_lsq(k, s);
     launch_update(N, Zb, N, k, e, 0, s);
@@ -562,7 +563,7 @@ int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_i
     cx<double>* Zb = Z.as<cx<double>>();
     cx<double>* rr = r.as<cx<double>>();
     double hs[4];
-    int hi[2];
+    int hi[6];
     // ||f||
     launch_dot_norm2(N, f, &kd.scal[3], &kd.ints[2], kd.partials, s);
     HH_HIP(hipMemcpyAsync(hs, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -607,27 +608,37 @@ int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_i
             cx<double>* w = Vb + (size_t)(j + 1) * N;
             T_apply(0, vj, zj, s);
             op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
-            for (int i = 0; i <= j; ++i) {
-                tstart(3, s);
-                launch_mgs(N, i, j, w, Vb, N, kd, s);
-                tstop(3, (i > 0 ? 64.0 : 32.0) * N, s);
-            }
-            launch_norm_givens(N, j, w, Vb, N, kd, s);
+            // MGS + norm + Givens + normalisation of w, one launch; algorithmic
+            // bytes: per basis vector read v_i twice and w twice, write w once,
+            // then read w twice and write it once
+            tstart(3, s);
+            if (N <= kSmallArnoldi)
+                launch_arnoldi_small(N, j, w, Vb, N, kd, s);
+            else
+                launch_arnoldi_coop(N, j, w, Vb, N, kd, s);
+            tstop(3, (80.0 * (j + 1) + 48.0) * N, s);
             HH_HIP(hipMemcpyAsync(hs, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-            HH_HIP(hipMemcpyAsync(hi, kd.ints, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            HH_HIP(hipMemcpyAsync(hi, kd.ints, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
             HH_HIP(hipStreamSynchronize(s));
             gabs = hs[2];
             ++iters;
             jdone = j + 1;
+            if (hi[5]) throw Err{HH_EHIP, "grid barrier of the Arnoldi kernel timed out"};
             if (!std::isfinite(gabs)) throw Err{HH_ENUMERIC, "Arnoldi recurrence produced NaN/Inf"};
             if (hi[1] || gabs <= stop) break;
-            launch_scale_by(N, w, w, &kd.scal[1], s);
         }
         launch_lsq(kd, s);
         launch_update(N, Zb, N, kd, u, 1, s);
         op<double>(0, MODE_RESID, false, u, f, rr, s);
         ++cycles;
         if (jdone == 0) break;
+    }
+    // grid-barrier timeouts in the inner (coarse-level) Arnoldi kernels
+    for (int l = 1; l < Lz; ++l) {
+        int flag = 0;
+        HH_HIP(hipMemcpyAsync(&flag, &lev[l]->kd.ints[5], sizeof(int), hipMemcpyDeviceToHost, s));
+        HH_HIP(hipStreamSynchronize(s));
+        if (flag) throw Err{HH_EHIP, "grid barrier of an inner Arnoldi kernel timed out"};
     }
     // true residual of the returned iterate
     launch_dot_norm2(N, rr, &kd.scal[3], &kd.ints[2], kd.partials, s);
