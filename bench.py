@@ -37,6 +37,9 @@ WORKLOADS = {
     "wedge_k150_p3_480": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict()),
     # configs[4] plain form
     "grf_k300_p4_960": dict(dim=2, p=4, n_el=960, grf=300.0, x0=(0.5, 0.5), opts=dict()),
+    # configs[3]: 64 independent constant-k problems, k ~ U[50, 400], n_el = ceil(k / 0.625),
+    # p ~ U{2, 3, 4}, random interior sources; FP32 V-cycle, FP64 Krylov and deflation
+    "batch64_k50_400": dict(batch=64, seed=0, opts=dict(precision=1, maxit=400)),
 }
 
 
@@ -68,6 +71,98 @@ def cpu_baseline(w, seconds_cap=30.0):
             "iters": info.iters}
 
 
+def batch_member_opts(d, base):
+    """Deflation per batch member: two-level (direct E on level 1) when level 1 has at most
+    16384 unknowns, else multilevel with a direct level of at most 8192 unknowns and inner
+    FGMRES steps 16, 8, 4, 2."""
+    n1 = ((d["n_el"] + 1) // 2 + d["p"] - 2) ** 2
+    o = dict(base)
+    if n1 <= 16384:
+        o.update(defl_mode=1)
+    else:
+        o.update(defl_mode=2, defl_direct_max=8192, defl_inner_its=(16, 8, 4, 2))
+    return o
+
+
+def run_batched(args, w):
+    """64-problem lockstep batch: one step = one hh_solve_batched of the whole batch."""
+    import torch
+
+    from paper_2010_10232_amd import binding as B
+    draws = W.batch_draws(n=w["batch"], seed=w["seed"])
+    t0 = time.perf_counter()
+    probs, solvers = [], []
+    for i, d in enumerate(draws):
+        probs.append(B.Problem(2, d["p"], d["n_el"], k=d["k"]))
+        solvers.append(B.Solver(probs[-1], **batch_member_opts(d, w["opts"])))
+        print(f"[bench] setup {i + 1}/{len(draws)}: p={d['p']} n_el={d['n_el']} N={probs[-1].N} "
+              f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    fs = [pr.point_source(d["x0"]) for pr, d in zip(probs, draws)]
+    us = [torch.empty_like(f) for f in fs]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        _, infos = B.solve_batched(solvers, fs, us)
+        print(f"[bench] warm-up batch: iterations {[i['iters'] for i in infos]}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    work = 0
+    for k in range(args.steps):
+        _, infos = B.solve_batched(solvers, fs, us)
+        work += sum(pr.N * inf["iters"] for pr, inf in zip(probs, infos))
+        print(f"[bench] timed batch {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # the same problems one after another (single-solve path) for comparison
+    t1 = time.perf_counter()
+    for s_, f_, u_ in zip(solvers, fs, us):
+        s_.solve(f_, u_)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    out = {
+        "metric": "DoF-iterations/s of the deflated MG-CSLP FGMRES solve to 1e-7 relative residual",
+        "value": work / dt, "unit": "DoF-iter/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": args.workload, "problems": len(probs),
+                   "N_total": int(sum(pr.N for pr in probs)),
+                   "N_range": [int(min(pr.N for pr in probs)), int(max(pr.N for pr in probs))],
+                   "iters_range": [min(i["iters"] for i in infos), max(i["iters"] for i in infos)],
+                   "converged": int(sum(i["converged"] == 1 for i in infos)),
+                   "setup_s": round(t_setup, 2), "sequential_single_solves_ms": round(t_seq * 1e3, 2)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(draws, w["opts"])
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(draws, opts, budget_s=20.0):
+    """The oracle on the smallest problems of the batch until about budget_s of solve time."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import helmholtz as hz
+    from oracle import solver as osv
+    order = sorted(range(len(draws)), key=lambda i: draws[i]["n_el"] * draws[i]["p"])
+    o = {k: v for k, v in opts.items() if k != "precision"}
+    work, spent, done = 0, 0.0, 0
+    with threadpool_limits(limits=1):
+        for i in order:
+            d = draws[i]
+            op = hz.Problem(2, d["p"], d["n_el"], d["k"])
+            s = osv.Solver(op, osv.Options(**batch_member_opts(d, o)))
+            f = hz.point_source_rhs(op, d["x0"])
+            t0 = time.perf_counter()
+            _, info = s.solve(f)
+            spent += time.perf_counter() - t0
+            work += s.levels[0].N * info.iters
+            done += 1
+            if spent >= budget_s:
+                break
+    return {"value": work / spent, "unit": "DoF-iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"the {done} smallest problems of the batch solved one by one in FP64 "
+                      f"({spent:.1f} s of solve time, setup excluded)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +171,8 @@ def main():
     ap.add_argument("--workload", default="mp2a_k100_p3_160", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", type=int, default=0, help="0 FP64, 1 FP32 V-cycle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (PMC traffic calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path",
@@ -86,6 +183,15 @@ def main():
 
     from paper_2010_10232_amd import binding as B
     torch.cuda.set_device(0)
+    if "batch" in WORKLOADS[args.workload]:
+        return run_batched(args, WORKLOADS[args.workload])
+    if args.calibrate_copy_mb:
+        n = args.calibrate_copy_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = WORKLOADS[args.workload]
     ke = k_field(w)
     t0 = time.perf_counter()

@@ -93,6 +93,7 @@ typedef struct {
     double op_ms_total;      /* time_kernels: summed device time of the timed kernel class */
     int op_launches;         /* time_kernels: number of such launches */
     double op_bytes_per_launch; /* algorithmic HBM bytes per launch of that class (mean) */
+    int status;              /* the hh_status of this solve (per problem in hh_solve_batched) */
 } hh_solve_info;
 
 typedef struct {
@@ -157,6 +158,18 @@ hh_status hh_solver_destroy(hh_solver* s);
  * iterate in u_dev) when maxit is reached.  info may be NULL. */
 hh_status hh_solve(hh_solver* s, const void* f_dev, void* u_dev, int use_u0,
                    hh_solve_info* info, void* stream);
+
+/* Batched solve (spec batching form): n independent problems, each with
+ * its own solver (problems may differ in size, degree and wave number), advance
+ * in lockstep - one FGMRES step of every unfinished problem per batch
+ * iteration - on a pool of HIP streams, so that the many small kernels of
+ * different problems run concurrently.  s, f, u, infos: arrays of n entries;
+ * f[i], u[i] device vectors of problem i (as in hh_solve, zero initial guess).
+ * Per-problem results and status are in infos[i]; the return value is the
+ * first negative status, HH_ENOCONV if some problem did not converge, else
+ * HH_OK.  The call returns after all work has finished. */
+hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, void* const* u,
+                           hh_solve_info* infos, void* stream);
 
 /* Level sizes and parameters; level in [0, n_levels). */
 hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out);

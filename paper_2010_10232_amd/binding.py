@@ -20,7 +20,7 @@ OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 
 
 EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
             "hh_point_spans", "hh_rhs_point_source", "hh_setup", "hh_solver_destroy", "hh_solve",
-            "hh_level_info", "hh_apply", "hh_set_kernel_timing"]
+            "hh_level_info", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched"]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -42,7 +42,8 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
                 ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("op_ms_total", ctypes.c_double),
-                ("op_launches", ctypes.c_int), ("op_bytes_per_launch", ctypes.c_double)]
+                ("op_launches", ctypes.c_int), ("op_bytes_per_launch", ctypes.c_double),
+                ("status", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,6 +81,8 @@ def load(path=LIB_PATH):
     lib.hh_level_info.argtypes = [vp, ip, ctypes.POINTER(LevelStats)]
     lib.hh_apply.argtypes = [vp, ip, ip, vp, vp, vp]
     lib.hh_set_kernel_timing.argtypes = [vp, ip]
+    lib.hh_solve_batched.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.POINTER(SolveInfo), vp]
     for name in EXPORTED:
         if name not in ("hh_default_opts", "hh_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -230,3 +233,19 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def solve_batched(solvers, fs, us=None):
+    """Solves every problem of the batch (hh_solve_batched); returns (us, infos)."""
+    import torch
+    n = len(solvers)
+    if us is None:
+        us = [torch.empty_like(f) for f in fs]
+    S = (ctypes.c_void_p * n)(*[s._h.value for s in solvers])
+    F = (ctypes.c_void_p * n)(*[_ptr(f).value for f in fs])
+    U = (ctypes.c_void_p * n)(*[_ptr(u).value for u in us])
+    infos = (SolveInfo * n)()
+    code = load().hh_solve_batched(S, n, F, U, infos, _stream())
+    if code < 0 and all(infos[i].status >= 0 for i in range(n)):
+        _check(code)
+    return us, [infos[i].as_dict() for i in range(n)]

@@ -1,6 +1,8 @@
 // C ABI entry points (include/hh.h): argument checks, error capture, dispatch.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <set>
 
 #include "solver.h"
 
@@ -161,6 +163,95 @@ hh_status hh_solve(hh_solver* s, const void* f_dev, void* u_dev, int use_u0, hh_
     if (!s || !f_dev || !u_dev) throw Err{HH_EINVAL, "NULL argument"};
     if (f_dev == u_dev) throw Err{HH_EINVAL, "f and u must not alias"};
     return s->impl->solve((const cx<double>*)f_dev, (cx<double>*)u_dev, use_u0, info, (hipStream_t)stream);
+    HH_CATCH
+}
+
+// Stream pool of the batched solve (default priority; created on first use and
+// kept for the life of the process).
+static std::vector<hipStream_t> g_pool;
+static std::mutex g_pool_mu;
+
+static std::vector<hipStream_t> pool_streams(int n) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    while ((int)g_pool.size() < n) {
+        hipStream_t st;
+        HH_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        g_pool.push_back(st);
+    }
+    return std::vector<hipStream_t>(g_pool.begin(), g_pool.begin() + n);
+}
+
+hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, void* const* u,
+                           hh_solve_info* infos, void* stream) {
+    HH_TRY
+    if (!s || !f || !u || !infos || n < 1) throw Err{HH_EINVAL, "NULL argument or n < 1"};
+    {
+        std::set<const hh_solver*> seen;
+        for (int i = 0; i < n; ++i) {
+            if (!s[i] || !f[i] || !u[i]) throw Err{HH_EINVAL, "NULL solver or vector in the batch"};
+            if (!seen.insert(s[i]).second) throw Err{HH_EINVAL, "a solver appears twice in the batch"};
+            if (f[i] == u[i]) throw Err{HH_EINVAL, "f and u must not alias"};
+        }
+    }
+    hipStream_t cs = (hipStream_t)stream;
+    const int ns = std::min(n, 8);
+    std::vector<hipStream_t> st = pool_streams(ns);
+    hipEvent_t fork;
+    HH_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    HH_HIP(hipEventRecord(fork, cs));
+    for (int k = 0; k < ns; ++k) HH_HIP(hipStreamWaitEvent(st[k], fork, 0));
+    std::vector<SolveRun> runs(n);
+    std::vector<int> status(n, HH_OK);
+    std::vector<char> active(n, 1);
+    for (int i = 0; i < n; ++i) s[i]->impl->allow_coop = false;
+    auto fail = [&](int i, int code, const std::string& msg) {
+        status[i] = code;
+        active[i] = 0;
+        set_error(msg);
+    };
+    for (int i = 0; i < n; ++i) {
+        try {
+            runs[i].start(s[i]->impl.get(), (const cx<double>*)f[i], (cx<double>*)u[i], 0, st[i % ns]);
+        } catch (const Err& e) {
+            fail(i, e.code, e.msg);
+        }
+    }
+    for (;;) {
+        bool any = false;
+        for (int i = 0; i < n; ++i) any = any || active[i];
+        if (!any) break;
+        for (int k = 0; k < ns; ++k) HH_HIP(hipStreamSynchronize(st[k]));
+        for (int i = 0; i < n; ++i) {
+            if (!active[i]) continue;
+            try {
+                runs[i].step();
+                if (runs[i].phase == SolveRun::P_DONE) {
+                    active[i] = 0;
+                    status[i] = runs[i].status;
+                }
+            } catch (const Err& e) {
+                fail(i, e.code, e.msg);
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i) s[i]->impl->allow_coop = true;
+    hipEvent_t join;
+    HH_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    for (int k = 0; k < ns; ++k) {
+        HH_HIP(hipEventRecord(join, st[k]));
+        HH_HIP(hipStreamWaitEvent(cs, join, 0));
+    }
+    HH_HIP(hipStreamSynchronize(cs));
+    (void)hipEventDestroy(fork);
+    (void)hipEventDestroy(join);
+    int ret = HH_OK;
+    for (int i = 0; i < n; ++i) {
+        infos[i] = runs[i].inf;
+        infos[i].status = status[i];
+        if (status[i] < 0 && ret >= 0) ret = status[i];
+        if (status[i] == HH_ENOCONV && ret == HH_OK) ret = HH_ENOCONV;
+    }
+    return ret;
     HH_CATCH
 }
 

@@ -1,6 +1,7 @@
 // Solver objects behind the C ABI.
 #pragma once
 
+#include <chrono>
 #include <memory>
 
 #include "hh_internal.h"
@@ -40,6 +41,28 @@ struct LevelDev {
     KrylovDev kd{};
 };
 
+struct SolverImpl;
+
+// One FGMRES solve as a resumable state machine (see solver.hip).
+struct SolveRun {
+    enum Phase { P_NF, P_RN, P_STEP, P_FINAL, P_DONE };
+    SolverImpl* S = nullptr;
+    const cx<double>* f = nullptr;
+    cx<double>* u = nullptr;
+    int use_u0 = 0;
+    hipStream_t s = nullptr;
+    Phase phase = P_DONE;
+    double nf = 0, stop = 0, rn = 0, gabs = 0;
+    int iters = 0, cycles = 0, j = 0, m = 0, status = 0;
+    hh_solve_info inf{};
+    std::chrono::steady_clock::time_point t0;
+    void start(SolverImpl* S, const cx<double>* f, cx<double>* u, int use_u0, hipStream_t s);
+    void step();
+    void enqueue_cycle_start();
+    void enqueue_step();
+    void enqueue_final();
+};
+
 struct SolverImpl {
     const ProblemImpl* prob = nullptr;
     hh_solver_opts o{};
@@ -53,6 +76,8 @@ struct SolverImpl {
     int m_outer = 0;
     DevBuf V, Z, kstate, r, scratch;
     KrylovDev kd{};
+    double* pin_d = nullptr;   // pinned host copies of device scalars
+    int* pin_i = nullptr;
     // event timing of one kernel class (non-blocking: events are read after the solve)
     std::vector<hipEvent_t> evpool;
     int ev_used = 0;
@@ -74,6 +99,8 @@ struct SolverImpl {
     void precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s);
     void T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t s);
     void coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s);
+    void arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s);
+    bool allow_coop = true;
     int solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s);
 };
 

@@ -157,6 +157,8 @@ static DevBuf& pick(DevBuf& a64, DevBuf& a32) {
 
 SolverImpl::~SolverImpl() {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+    if (pin_d) (void)hipHostFree(pin_d);
+    if (pin_i) (void)hipHostFree(pin_i);
 }
 
 // Kernel-class timing: a pair of events around each launch of the selected
@@ -400,6 +402,9 @@ void SolverImpl::setup(hipStream_t s) {
     Z.alloc(v0 * m_outer);
     r.alloc(v0);
     fill_krylov(kd, kstate, m_outer);
+    HH_HIP(hipHostMalloc((void**)&pin_d, 8 * sizeof(double), hipHostMallocDefault));
+    HH_HIP(hipHostMalloc((void**)&pin_i, 32 * sizeof(int), hipHostMallocDefault));
+    std::memset(pin_i, 0, 32 * sizeof(int));
     HH_HIP(hipStreamSynchronize(s));
 }
 
@@ -522,6 +527,22 @@ void SolverImpl::T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t 
     launch_add(lv.N, lv.ts.as<cx<double>>(), lv.tq.as<cx<double>>(), z, s);
 }
 
+// One fused Arnoldi step on w = V[j+1]: a single workgroup for short vectors;
+// otherwise a cooperative grid, or (when other problems' kernels share the GPU
+// and co-residency of a cooperative grid cannot be relied on) one kernel per
+// Gram-Schmidt projection followed by the norm/Givens kernel and the scaling.
+void SolverImpl::arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s) {
+    if (N <= kSmallArnoldi) {
+        launch_arnoldi_small(N, j, w, Vb, N, k, s);
+    } else if (allow_coop) {
+        launch_arnoldi_coop(N, j, w, Vb, N, k, s);
+    } else {
+        for (int i = 0; i <= j; ++i) launch_mgs(N, i, j, w, Vb, N, k, s);
+        launch_norm_givens(N, j, w, Vb, N, k, s);
+        launch_scale_by(N, w, w, &k.scal[1], s);
+    }
+}
+
 void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s) {
     if (l == Lz) {
         tstart(2, s);
@@ -543,124 +564,170 @@ void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStre
         cx<double>* w = Vb + (size_t)(j + 1) * N;
         T_apply(l, vj, zj, s);
         op<double>(l, MODE_APPLY, false, zj, nullptr, w, s);
-        if (N <= kSmallArnoldi)
-            launch_arnoldi_small(N, j, w, Vb, N, k, s);
-        else
-            launch_arnoldi_coop(N, j, w, Vb, N, k, s);
+        arnoldi(N, j, w, Vb, k, s);
     }
     launch_lsq(k, s);
     launch_update(N, Zb, N, k, e, 0, s);
 }
 
-int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s) {
-    auto t0 = std::chrono::steady_clock::now();
-    ev_used = 0;
-    ev_bytes = 0.0;
-    ev_pending = -1;
-    LevelDev& l0 = *lev[0];
-    const long long N = l0.N;
-    cx<double>* Vb = V.as<cx<double>>();
-    cx<double>* Zb = Z.as<cx<double>>();
-    cx<double>* rr = r.as<cx<double>>();
-    double hs[4];
-    int hi[6];
-    // ||f||
+// ------------------------------------------------------------- FGMRES ----
+// Restarted FGMRES as a resumable state machine: every call of step() consumes
+// the host copy of the scalars that the previously enqueued work produced (the
+// norm of f, the cycle's starting residual, or one Arnoldi step's |g_{j+1}|),
+// takes the decision the algorithm needs, and enqueues the next unit of work
+// plus the device-to-host copy of its scalars.  One problem alternates
+// "synchronise, step"; a batch of problems on different streams advances in
+// lockstep with one synchronisation per problem per batch iteration.
+void SolveRun::start(SolverImpl* S_, const cx<double>* f_, cx<double>* u_, int use_u0_, hipStream_t s_) {
+    S = S_;
+    f = f_;
+    u = u_;
+    use_u0 = use_u0_;
+    s = s_;
+    t0 = std::chrono::steady_clock::now();
+    S->ev_used = 0;
+    S->ev_bytes = 0.0;
+    S->ev_pending = -1;
+    iters = cycles = j = m = 0;
+    nf = stop = rn = gabs = 0.0;
+    status = HH_OK;
+    inf = hh_solve_info{};
+    KrylovDev& kd = S->kd;
+    const long long N = S->lev[0]->N;
     launch_dot_norm2(N, f, &kd.scal[3], &kd.ints[2], kd.partials, s);
-    HH_HIP(hipMemcpyAsync(hs, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HH_HIP(hipStreamSynchronize(s));
-    const double nf = std::sqrt(hs[3]);
-    hh_solve_info inf{};
-    if (!std::isfinite(nf)) throw Err{HH_ENUMERIC, "right-hand side is not finite"};
-    if (nf == 0.0) {
-        launch_zero(N, u, s);
-        HH_HIP(hipStreamSynchronize(s));
-        inf.converged = 1;
-        if (info) *info = inf;
-        return HH_OK;
-    }
-    if (use_u0) {
-        op<double>(0, MODE_RESID, false, u, f, rr, s);
-    } else {
-        launch_zero(N, u, s);
-        launch_copy(N, f, rr, s);
-    }
-    const double stop = o.tol * nf;
-    int iters = 0, cycles = 0;
-    double rn = 0.0, gabs = 0.0;
-    bool converged = false;
-    for (;;) {
-        launch_norm_init(N, rr, kd, s);
-        HH_HIP(hipMemcpyAsync(hs, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HH_HIP(hipStreamSynchronize(s));
-        rn = hs[0];
-        if (!std::isfinite(rn)) throw Err{HH_ENUMERIC, "residual is not finite"};
-        if (rn <= stop) {
-            converged = true;
-            break;
+    HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    phase = P_NF;
+}
+
+void SolveRun::enqueue_cycle_start() {
+    KrylovDev& kd = S->kd;
+    launch_norm_init(S->lev[0]->N, S->r.as<cx<double>>(), kd, s);
+    HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    phase = P_RN;
+}
+
+void SolveRun::enqueue_step() {
+    KrylovDev& kd = S->kd;
+    const long long N = S->lev[0]->N;
+    cx<double>* Vb = S->V.as<cx<double>>();
+    cx<double>* Zb = S->Z.as<cx<double>>();
+    cx<double>* vj = Vb + (size_t)j * N;
+    cx<double>* zj = Zb + (size_t)j * N;
+    cx<double>* w = Vb + (size_t)(j + 1) * N;
+    S->T_apply(0, vj, zj, s);
+    S->op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
+    // MGS + norm + Givens + normalisation of w in one launch; algorithmic bytes:
+    // per basis vector read v_i twice and w twice and write w once, then read w
+    // twice and write it once
+    S->tstart(3, s);
+    S->arnoldi(N, j, w, Vb, kd, s);
+    S->tstop(3, (80.0 * (j + 1) + 48.0) * N, s);
+    HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HH_HIP(hipMemcpyAsync(S->pin_i, kd.ints, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+    phase = P_STEP;
+}
+
+void SolveRun::enqueue_final() {
+    KrylovDev& kd = S->kd;
+    for (int l = 1; l < S->Lz && l < 16; ++l)
+        HH_HIP(hipMemcpyAsync(&S->pin_i[8 + l], &S->lev[l]->kd.ints[5], sizeof(int), hipMemcpyDeviceToHost, s));
+    launch_dot_norm2(S->lev[0]->N, S->r.as<cx<double>>(), &kd.scal[3], &kd.ints[2], kd.partials, s);
+    HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    phase = P_FINAL;
+}
+
+void SolveRun::step() {
+    const long long N = S->lev[0]->N;
+    const hh_solver_opts& o = S->o;
+    cx<double>* rr = S->r.as<cx<double>>();
+    KrylovDev& kd = S->kd;
+    switch (phase) {
+        case P_NF: {
+            nf = std::sqrt(S->pin_d[3]);
+            if (!std::isfinite(nf)) throw Err{HH_ENUMERIC, "right-hand side is not finite"};
+            if (nf == 0.0) {
+                launch_zero(N, u, s);
+                inf.converged = 1;
+                status = HH_OK;
+                phase = P_DONE;
+                return;
+            }
+            stop = o.tol * nf;
+            if (use_u0) {
+                S->op<double>(0, MODE_RESID, false, u, f, rr, s);
+            } else {
+                launch_zero(N, u, s);
+                launch_copy(N, f, rr, s);
+            }
+            enqueue_cycle_start();
+            return;
         }
-        if (iters >= o.maxit) break;
-        const int m = std::min(m_outer, o.maxit - iters);
-        launch_scale_by(N, rr, Vb, &kd.scal[0], s);
-        int jdone = 0;
-        for (int j = 0; j < m; ++j) {
-            cx<double>* vj = Vb + (size_t)j * N;
-            cx<double>* zj = Zb + (size_t)j * N;
-            cx<double>* w = Vb + (size_t)(j + 1) * N;
-            T_apply(0, vj, zj, s);
-            op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
-            // MGS + norm + Givens + normalisation of w, one launch; algorithmic
-            // bytes: per basis vector read v_i twice and w twice, write w once,
-            // then read w twice and write it once
-            tstart(3, s);
-            if (N <= kSmallArnoldi)
-                launch_arnoldi_small(N, j, w, Vb, N, kd, s);
-            else
-                launch_arnoldi_coop(N, j, w, Vb, N, kd, s);
-            tstop(3, (80.0 * (j + 1) + 48.0) * N, s);
-            HH_HIP(hipMemcpyAsync(hs, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-            HH_HIP(hipMemcpyAsync(hi, kd.ints, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
-            HH_HIP(hipStreamSynchronize(s));
-            gabs = hs[2];
+        case P_RN: {
+            rn = S->pin_d[0];
+            if (!std::isfinite(rn)) throw Err{HH_ENUMERIC, "residual is not finite"};
+            if (rn <= stop || iters >= o.maxit) {
+                enqueue_final();
+                return;
+            }
+            m = std::min(S->m_outer, o.maxit - iters);
+            launch_scale_by(N, rr, S->V.as<cx<double>>(), &kd.scal[0], s);
+            j = 0;
+            enqueue_step();
+            return;
+        }
+        case P_STEP: {
+            gabs = S->pin_d[2];
             ++iters;
-            jdone = j + 1;
-            if (hi[5]) throw Err{HH_EHIP, "grid barrier of the Arnoldi kernel timed out"};
+            if (S->pin_i[5]) throw Err{HH_EHIP, "grid barrier of the Arnoldi kernel timed out"};
             if (!std::isfinite(gabs)) throw Err{HH_ENUMERIC, "Arnoldi recurrence produced NaN/Inf"};
-            if (hi[1] || gabs <= stop) break;
+            if (S->pin_i[1] || gabs <= stop || j + 1 >= m) {
+                // end of the cycle: least squares, update, true residual
+                launch_lsq(kd, s);
+                launch_update(N, S->Z.as<cx<double>>(), N, kd, u, 1, s);
+                S->op<double>(0, MODE_RESID, false, u, f, rr, s);
+                ++cycles;
+                enqueue_cycle_start();
+            } else {
+                ++j;
+                enqueue_step();
+            }
+            return;
         }
-        launch_lsq(kd, s);
-        launch_update(N, Zb, N, kd, u, 1, s);
-        op<double>(0, MODE_RESID, false, u, f, rr, s);
-        ++cycles;
-        if (jdone == 0) break;
+        case P_FINAL: {
+            for (int l = 1; l < S->Lz && l < 16; ++l)
+                if (S->pin_i[8 + l]) throw Err{HH_EHIP, "grid barrier of an inner Arnoldi kernel timed out"};
+            const double rtrue = std::sqrt(S->pin_d[3]);
+            auto t1 = std::chrono::steady_clock::now();
+            inf.iters = iters;
+            inf.restarts = std::max(cycles - 1, 0);
+            inf.relres_true = rtrue / nf;
+            inf.relres_est = gabs / nf;
+            inf.converged = (rtrue <= stop) ? 1 : 0;
+            inf.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            int cnt = 0;
+            inf.op_ms_total = S->tcollect(&cnt);
+            inf.op_launches = cnt;
+            inf.op_bytes_per_launch = cnt ? S->ev_bytes / cnt : 0.0;
+            status = inf.converged ? HH_OK : HH_ENOCONV;
+            phase = P_DONE;
+            return;
+        }
+        case P_DONE:
+            return;
     }
-    // grid-barrier timeouts in the inner (coarse-level) Arnoldi kernels
-    for (int l = 1; l < Lz; ++l) {
-        int flag = 0;
-        HH_HIP(hipMemcpyAsync(&flag, &lev[l]->kd.ints[5], sizeof(int), hipMemcpyDeviceToHost, s));
+}
+
+int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s) {
+    SolveRun run;
+    run.start(this, f, u, use_u0, s);
+    while (run.phase != SolveRun::P_DONE) {
         HH_HIP(hipStreamSynchronize(s));
-        if (flag) throw Err{HH_EHIP, "grid barrier of an inner Arnoldi kernel timed out"};
+        run.step();
     }
-    // true residual of the returned iterate
-    launch_dot_norm2(N, rr, &kd.scal[3], &kd.ints[2], kd.partials, s);
-    HH_HIP(hipMemcpyAsync(hs, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     HH_HIP(hipStreamSynchronize(s));
-    const double rtrue = std::sqrt(hs[3]);
-    auto t1 = std::chrono::steady_clock::now();
-    inf.iters = iters;
-    inf.restarts = std::max(cycles - 1, 0);
-    inf.relres_true = rtrue / nf;
-    inf.relres_est = gabs / nf;
-    inf.converged = (rtrue <= stop) ? 1 : 0;
-    inf.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    {
-        int cnt = 0;
-        inf.op_ms_total = tcollect(&cnt);
-        inf.op_launches = cnt;
-        inf.op_bytes_per_launch = cnt ? ev_bytes / cnt : 0.0;
-    }
-    if (info) *info = inf;
-    (void)converged;
-    return inf.converged ? HH_OK : HH_ENOCONV;
+    run.inf.status = run.status;
+    if (info) *info = run.inf;
+    return run.status;
 }
 
 template void SolverImpl::op<double>(int, int, bool, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t);

@@ -1,0 +1,72 @@
+"""Batched solves (uneven sizes and degrees in lockstep on a stream pool) against
+single solves and the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import helmholtz as hz
+from oracle import solver as osv
+from paper_2010_10232_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _batch_problems(n=6, seed=3):
+    # a scaled-down version of the batch draws: k in [12, 48], n_el = ceil(k / 0.625)
+    return W.batch_draws(n=n, seed=seed, k_lo=12.0, k_hi=48.0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_equals_single(precision):
+    import torch
+    from paper_2010_10232_amd import binding as B
+    draws = _batch_problems()
+    opts = dict(precision=precision, defl_direct_max=400)
+    probs = [B.Problem(2, d["p"], d["n_el"], k=d["k"]) for d in draws]
+    solvers = [B.Solver(pr, **opts) for pr in probs]
+    fs = [pr.point_source(d["x0"]) for pr, d in zip(probs, draws)]
+    _say(f"[batched precision={precision}] sizes", [pr.N for pr in probs], "p", [d["p"] for d in draws])
+    us, infos = B.solve_batched(solvers, fs)
+    torch.cuda.synchronize()
+    for i, (s, f, u, info) in enumerate(zip(solvers, fs, us, infos)):
+        _say(f"[batched precision={precision}] problem {i}: single solve")
+        u1, info1 = s.solve(f)
+        assert info["status"] == 0 and info["converged"] == 1
+        assert info["iters"] == info1["iters"], (i, info["iters"], info1["iters"])
+        d = (torch.linalg.norm(u - u1) / torch.linalg.norm(u1)).item()
+        assert d <= 1e-10, (i, d)
+
+
+def test_batched_matches_oracle():
+    import torch
+    from paper_2010_10232_amd import binding as B
+    draws = _batch_problems(n=4, seed=11)
+    opts = dict(defl_direct_max=400)
+    probs = [B.Problem(2, d["p"], d["n_el"], k=d["k"]) for d in draws]
+    solvers = [B.Solver(pr, **opts) for pr in probs]
+    fs = [pr.point_source(d["x0"]) for pr, d in zip(probs, draws)]
+    _say("[batched vs oracle] gpu")
+    us, infos = B.solve_batched(solvers, fs)
+    for i, d in enumerate(draws):
+        _say(f"[batched vs oracle] problem {i} oracle p={d['p']} n_el={d['n_el']}")
+        op = hz.Problem(2, d["p"], d["n_el"], d["k"])
+        osol = osv.Solver(op, osv.Options(**opts))
+        u_ref, info_ref = osol.solve(hz.point_source_rhs(op, d["x0"]))
+        assert infos[i]["iters"] == info_ref.iters
+        e = np.linalg.norm(us[i].cpu().numpy() - u_ref) / np.linalg.norm(u_ref)
+        assert e <= 1e-10, (i, e)
+
+
+def test_batched_rejects_duplicates():
+    from paper_2010_10232_amd import binding as B
+    pr = B.Problem(2, 2, 16, k=10.0)
+    s = B.Solver(pr)
+    f = pr.point_source((0.5, 0.5))
+    with pytest.raises(B.HHError):
+        B.solve_batched([s, s], [f, f.clone()])
