@@ -44,6 +44,7 @@ typedef int hh_status;
 
 typedef struct hh_problem hh_problem;
 typedef struct hh_solver hh_solver;
+typedef struct hh_cnn hh_cnn;
 
 /* Problem statement (section 2): unit interval / square, uniform open knot
  * vectors of degree p (ends repeated p+1 times, section 2.3.1), homogeneous
@@ -183,6 +184,45 @@ hh_status hh_set_kernel_timing(hh_solver* s, int cls);
  * y_dev must not overlap. */
 hh_status hh_apply(hh_solver* s, int op, int level, const void* x_dev, void* y_dev,
                    void* stream);
+
+/* ---- learned fine-level smoother (spec form 4; not in the paper) ----
+ * A complex 3x3 CNN C (complex channels 2 -> 16 -> 16 -> 16 -> 1, CReLU after
+ * the first three layers, zero padding) on the finest interior control-point
+ * grid.  Inputs: r/||r|| and c = k^2 h^2 (k of the finest element with the
+ * unknown's clamped index).  As the finest-level smoother it adds a learned
+ * correction to the damped Jacobi step: x += omega D^-1 r + ||r|| C(r/||r||, c),
+ * r = b - M_beta x, so zero weights give damped Jacobi exactly.  Weights and
+ * activations are BF16 with FP32 accumulation (MFMA).  Parameters are float
+ * (re, im) pairs, per layer W[co][ci][dy][dx] then b[co]. */
+
+/* Creates a network with seeded random parameters. */
+hh_status hh_cnn_create(unsigned long long seed, hh_cnn** out);
+/* Idempotent on NULL. */
+hh_status hh_cnn_destroy(hh_cnn* c);
+/* Number of floats of the parameter vector (twice the complex parameters). */
+hh_status hh_cnn_num_params(const hh_cnn* c, int* n_floats);
+/* Host copies of the FP32 master parameters (n_floats must match). */
+hh_status hh_cnn_get_params(const hh_cnn* c, float* host, int n_floats);
+/* Replaces the parameters (HH_ENUMERIC if any is not finite; then nothing
+ * changes) and resets the optimiser state. */
+hh_status hh_cnn_set_params(hh_cnn* c, const float* host, int n_floats);
+/* Training loss L = ||r - M_beta s||^2 / ||r||^2 with s the smoother step above for
+ * one finest-level residual r_dev (device, N complex doubles) of solver s, and
+ * (if grad_host != NULL) the gradient dL/dRe + i dL/dIm of every parameter. */
+hh_status hh_cnn_loss_grad(hh_cnn* c, hh_solver* s, const void* r_dev, double* loss, float* grad_host,
+                           int n_floats, void* stream);
+/* One Adam step (beta 0.9 / 0.999) with learning rate lr on the loss above. */
+hh_status hh_cnn_train_step(hh_cnn* c, hh_solver* s, const void* r_dev, double lr, double* loss, void* stream);
+/* Uses the network as the finest-level smoother of s (NULL: damped Jacobi).
+ * The network must outlive its use by s. */
+hh_status hh_solver_set_smoother(hh_solver* s, hh_cnn* c);
+/* Training-sample capture: during later solves, every finest-level V-cycle
+ * input vector is copied into buf_dev (device, max_samples x N complex
+ * doubles) until it is full.  buf_dev NULL stops the capture and keeps the
+ * count; hh_solver_captured reports how many vectors the last capture wrote.
+ * The copies are stream-ordered: read buf_dev after the solve's stream. */
+hh_status hh_solver_capture(hh_solver* s, void* buf_dev, int max_samples);
+hh_status hh_solver_captured(const hh_solver* s, int* n);
 
 #ifdef __cplusplus
 }

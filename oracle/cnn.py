@@ -11,8 +11,10 @@ Network C: 4 complex 3x3 convolution layers on the interior control-point grid
 imaginary part separately) after the first three layers; zero padding.
 Input channels: the normalised residual r/||r|| and the real feature
 c = k^2 h^2 (k of the finest element at the control point's index, clamped).
-Smoother step: s = ||r|| C(r/||r||, c), so the step is homogeneous of degree 1
-in r.  Training loss for one residual r: L = ||r - M_beta s||^2 / ||r||^2.
+Smoother step: the damped Jacobi update plus a learned correction,
+    s = omega D^-1 r + ||r|| C(r/||r||, c),
+homogeneous of degree 1 in r; zero weights give exactly damped Jacobi.
+Training loss for one residual r: L = ||r - M_beta s||^2 / ||r||^2.
 
 Complex gradients follow the convention g_z = dL/dRe(z) + i dL/dIm(z): for
 y = W x, g_x = conj(W) g_y and g_W = g_y conj(x).
@@ -92,19 +94,19 @@ def feature(k2_elem, n_el, n):
     return k2_elem[np.ix_(i2, i1)] * h * h
 
 
-def smoother_step(params, r, c, shape):
-    """s = ||r|| C(r/||r||, c) on the grid `shape` (r flat, x fastest)."""
+def smoother_step(params, r, c, shape, D, omega):
+    """s = omega D^-1 r + ||r|| C(r/||r||, c) on the grid `shape` (r flat, x fastest)."""
     nr = np.linalg.norm(r)
     if nr == 0.0:
         return np.zeros_like(r)
-    return nr * forward(params, (r / nr).reshape(shape), c).reshape(-1)
+    return omega * r / D + nr * forward(params, (r / nr).reshape(shape), c).reshape(-1)
 
 
-def loss_and_grad(params, r, c, shape, Mb):
+def loss_and_grad(params, r, c, shape, Mb, D, omega):
     """L = ||r - Mb s||^2 / ||r||^2 and its gradients with respect to every W, b."""
     nr = np.linalg.norm(r)
     out, acts, pre = forward(params, (r / nr).reshape(shape), c, keep=True)
-    s = nr * out.reshape(-1)
+    s = omega * r / D + nr * out.reshape(-1)
     e = r - Mb @ s
     L = np.vdot(e, e).real / nr ** 2
     g_e = 2.0 * e / nr ** 2

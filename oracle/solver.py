@@ -135,11 +135,16 @@ def deflation_levels(levels, opts):
 
 
 class Solver:
-    """The oracle's preconditioned solver for one problem."""
+    """The oracle's preconditioned solver for one problem.
 
-    def __init__(self, prob, opts=None):
+    cnn_params (optional): learned finest-level smoother (see oracle.cnn); the
+    finest-level Jacobi sweeps become x <- x + omega D^-1 r + ||r|| C(r/||r||, c).
+    """
+
+    def __init__(self, prob, opts=None, cnn_params=None):
         self.prob = prob
         self.opts = opts or Options()
+        self.cnn_params = cnn_params
         self.levels = build_hierarchy(prob, self.opts)
         self.Lz = deflation_levels(self.levels, self.opts)
         if self.Lz > 0:
@@ -147,9 +152,25 @@ class Solver:
 
     # ---- multigrid on the CSLP --------------------------------------------
     def jacobi(self, l, b, x):
-        """One damped Jacobi sweep x <- x + omega_l D^-1 (b - M_beta x)."""
+        """One damped Jacobi sweep x <- x + omega_l D^-1 (b - M_beta x) (learned on level 0)."""
         lv = self.levels[l]
+        if l == 0 and self.cnn_params is not None:
+            from . import cnn
+            shape = (lv.n[1], lv.n[0]) if self.prob.dim == 2 else (1, lv.n[0])
+            r = b - lv.Mb @ x
+            return x + cnn.smoother_step(self.cnn_params, r, self.cnn_feature(), shape, lv.D, lv.omega)
         return x + lv.omega * (b - lv.Mb @ x) / lv.D
+
+    def cnn_feature(self):
+        """c = k^2 h^2 per finest-level unknown (element with the clamped index)."""
+        from . import cnn
+        lv = self.levels[0]
+        p = self.prob
+        if p.dim == 2:
+            k2 = p.k2_elem if p.k_elem is not None else np.full((p.n_el[1], p.n_el[0]), p.k ** 2)
+            return cnn.feature(k2, p.n_el[0], (lv.n[1], lv.n[0]))
+        k2 = (p.k2_elem if p.k_elem is not None else np.full(p.n_el[0], p.k ** 2))[None, :]
+        return cnn.feature(k2, p.n_el[0], (1, lv.n[0]))
 
     def vcycle_once(self, l, b):
         """One V(nu_pre, nu_post) cycle on M_beta,l from a zero initial guess."""

@@ -20,7 +20,9 @@ OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 
 
 EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
             "hh_point_spans", "hh_rhs_point_source", "hh_setup", "hh_solver_destroy", "hh_solve",
-            "hh_level_info", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched"]
+            "hh_level_info", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched", "hh_cnn_create",
+            "hh_cnn_destroy", "hh_cnn_num_params", "hh_cnn_get_params", "hh_cnn_set_params", "hh_cnn_loss_grad",
+            "hh_cnn_train_step", "hh_solver_set_smoother", "hh_solver_capture", "hh_solver_captured"]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -81,6 +83,17 @@ def load(path=LIB_PATH):
     lib.hh_level_info.argtypes = [vp, ip, ctypes.POINTER(LevelStats)]
     lib.hh_apply.argtypes = [vp, ip, ip, vp, vp, vp]
     lib.hh_set_kernel_timing.argtypes = [vp, ip]
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.hh_cnn_create.argtypes = [ctypes.c_ulonglong, ctypes.POINTER(vp)]
+    lib.hh_cnn_destroy.argtypes = [vp]
+    lib.hh_cnn_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.hh_cnn_get_params.argtypes = [vp, fp, ip]
+    lib.hh_cnn_set_params.argtypes = [vp, fp, ip]
+    lib.hh_cnn_loss_grad.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), fp, ip, vp]
+    lib.hh_cnn_train_step.argtypes = [vp, vp, vp, dp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.hh_solver_set_smoother.argtypes = [vp, vp]
+    lib.hh_solver_capture.argtypes = [vp, vp, ip]
+    lib.hh_solver_captured.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.hh_solve_batched.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                      ctypes.POINTER(SolveInfo), vp]
     for name in EXPORTED:
@@ -203,6 +216,21 @@ class Solver:
                 "omega": st.omega, "gersh": st.gersh, "n_levels": st.n_levels,
                 "defl_direct_level": st.defl_direct_level}
 
+    def set_smoother(self, cnn):
+        """cnn: a Cnn (learned finest-level smoother) or None (damped Jacobi)."""
+        self._cnn = cnn
+        _check(load().hh_solver_set_smoother(self._h, cnn._h if cnn is not None else None))
+
+    def capture(self, buf, max_samples):
+        """Copy finest-level V-cycle inputs of later solves into buf (device, complex128)."""
+        self._cap = buf
+        _check(load().hh_solver_capture(self._h, _ptr(buf) if buf is not None else None, int(max_samples)))
+
+    def captured(self):
+        n = ctypes.c_int()
+        _check(load().hh_solver_captured(self._h, ctypes.byref(n)))
+        return n.value
+
     def set_kernel_timing(self, cls):
         """0 off, 1 finest-level operator, 2 dense E^-1 product, 3 outer MGS kernels."""
         _check(load().hh_set_kernel_timing(self._h, int(cls)))
@@ -249,3 +277,47 @@ def solve_batched(solvers, fs, us=None):
     if code < 0 and all(infos[i].status >= 0 for i in range(n)):
         _check(code)
     return us, [infos[i].as_dict() for i in range(n)]
+
+
+class Cnn:
+    """Learned finest-level smoother network (weights on the device)."""
+
+    def __init__(self, seed=0):
+        h = ctypes.c_void_p()
+        _check(load().hh_cnn_create(ctypes.c_ulonglong(seed), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int()
+        _check(load().hh_cnn_num_params(h, ctypes.byref(n)))
+        self.n_floats = n.value
+
+    def get_params(self):
+        out = np.empty(self.n_floats, dtype=np.float32)
+        _check(load().hh_cnn_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), self.n_floats))
+        return out
+
+    def set_params(self, vals):
+        v = np.ascontiguousarray(vals, dtype=np.float32)
+        _check(load().hh_cnn_set_params(self._h, v.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), len(v)))
+
+    def loss_grad(self, solver, r):
+        loss = ctypes.c_double()
+        g = np.empty(self.n_floats, dtype=np.float32)
+        _check(load().hh_cnn_loss_grad(self._h, solver._h, _ptr(r), ctypes.byref(loss),
+                                       g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), self.n_floats, _stream()))
+        return loss.value, g
+
+    def train_step(self, solver, r, lr):
+        loss = ctypes.c_double()
+        _check(load().hh_cnn_train_step(self._h, solver._h, _ptr(r), float(lr), ctypes.byref(loss), _stream()))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().hh_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

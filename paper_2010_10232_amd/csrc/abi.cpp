@@ -255,6 +255,124 @@ hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, voi
     HH_CATCH
 }
 
+hh_status hh_cnn_create(unsigned long long seed, hh_cnn** out) {
+    HH_TRY
+    if (!out) throw Err{HH_EINVAL, "out is NULL"};
+    *out = nullptr;
+    auto* c = new hh_cnn();
+    try {
+        c->impl = std::make_unique<CnnImpl>(seed);
+    } catch (...) {
+        delete c;
+        throw;
+    }
+    *out = c;
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_cnn_destroy(hh_cnn* c) {
+    delete c;
+    return HH_OK;
+}
+
+hh_status hh_cnn_num_params(const hh_cnn* c, int* n) {
+    HH_TRY
+    if (!c || !n) throw Err{HH_EINVAL, "NULL argument"};
+    *n = 2 * c->impl->nparam;
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_cnn_get_params(const hh_cnn* c, float* host, int n) {
+    HH_TRY
+    if (!c || !host) throw Err{HH_EINVAL, "NULL argument"};
+    if (n != 2 * c->impl->nparam) throw Err{HH_EINVAL, "parameter count mismatch"};
+    HH_HIP(hipDeviceSynchronize());
+    HH_HIP(hipMemcpy(host, c->impl->theta.p, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_cnn_set_params(hh_cnn* c, const float* host, int n) {
+    HH_TRY
+    if (!c || !host) throw Err{HH_EINVAL, "NULL argument"};
+    c->impl->set_params(host, n);
+    return HH_OK;
+    HH_CATCH
+}
+
+static MbetaFn finest_mbeta(SolverImpl& S, hipStream_t st) {
+    return [&S, st](const cx<double>* x, const cx<double>* b, cx<double>* y, int conj) {
+        if (conj)
+            S.op_alpha<double>(0, MODE_APPLY, S.o.beta[0], -S.o.beta[1], x, nullptr, y, st);
+        else
+            S.op_alpha<double>(0, MODE_RESID, S.o.beta[0], S.o.beta[1], x, b, y, st);
+    };
+}
+
+hh_status hh_cnn_loss_grad(hh_cnn* c, hh_solver* s, const void* r_dev, double* loss, float* grad_host, int n,
+                           void* stream) {
+    HH_TRY
+    if (!c || !s || !r_dev || !loss) throw Err{HH_EINVAL, "NULL argument"};
+    if (grad_host && n != 2 * c->impl->nparam) throw Err{HH_EINVAL, "parameter count mismatch"};
+    SolverImpl& S = *s->impl;
+    hipStream_t st = (hipStream_t)stream;
+    const LevelDev& l0 = *S.lev[0];
+    *loss = c->impl->loss_grad(l0.n2, l0.n1, (const cx<double>*)r_dev, S.feat.as<float>(),
+                               l0.Dinv64.as<cx<double>>(), l0.omega, finest_mbeta(S, st), st);
+    if (grad_host) {
+        HH_HIP(hipMemcpyAsync(grad_host, c->impl->grad.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+        HH_HIP(hipStreamSynchronize(st));
+    }
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_cnn_train_step(hh_cnn* c, hh_solver* s, const void* r_dev, double lr, double* loss, void* stream) {
+    HH_TRY
+    if (!c || !s || !r_dev) throw Err{HH_EINVAL, "NULL argument"};
+    if (!(lr > 0.0) || !std::isfinite(lr)) throw Err{HH_EINVAL, "learning rate must be positive"};
+    SolverImpl& S = *s->impl;
+    hipStream_t st = (hipStream_t)stream;
+    const LevelDev& l0 = *S.lev[0];
+    const double L = c->impl->loss_grad(l0.n2, l0.n1, (const cx<double>*)r_dev, S.feat.as<float>(),
+                                        l0.Dinv64.as<cx<double>>(), l0.omega, finest_mbeta(S, st), st);
+    if (!std::isfinite(L)) throw Err{HH_ENUMERIC, "training loss is not finite"};
+    c->impl->adam_step(lr, st);
+    HH_HIP(hipStreamSynchronize(st));
+    if (loss) *loss = L;
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_solver_set_smoother(hh_solver* s, hh_cnn* c) {
+    HH_TRY
+    if (!s) throw Err{HH_EINVAL, "NULL solver"};
+    s->impl->cnn = c ? c->impl.get() : nullptr;
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_solver_capture(hh_solver* s, void* buf, int max_samples) {
+    HH_TRY
+    if (!s) throw Err{HH_EINVAL, "NULL solver"};
+    if (buf && max_samples < 1) throw Err{HH_EINVAL, "max_samples must be >= 1"};
+    s->impl->cap_buf = (cx<double>*)buf;
+    s->impl->cap_max = buf ? max_samples : 0;
+    if (buf) s->impl->cap_n = 0;  // a new capture starts empty; stopping keeps the count
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_solver_captured(const hh_solver* s, int* n) {
+    HH_TRY
+    if (!s || !n) throw Err{HH_EINVAL, "NULL argument"};
+    *n = s->impl->cap_n;
+    return HH_OK;
+    HH_CATCH
+}
+
 hh_status hh_set_kernel_timing(hh_solver* s, int cls) {
     HH_TRY
     if (!s) throw Err{HH_EINVAL, "NULL solver"};

@@ -1,0 +1,536 @@
+// Learned fine-level smoother: a complex 3x3 CNN (channels 2 -> 16 -> 16 -> 16
+// -> 1, CReLU) evaluated and trained on the GPU with BF16 MFMA (FP32
+// accumulation).  Not part of the paper's method, which keeps damped Jacobi;
+// Jacobi remains the fallback.
+//
+// Representation.  A complex channel is a pair of real channels (re, im); a
+// complex weight a + ib acting on a complex input becomes the real 2x2 block
+// [[a, -b], [b, a]], and CReLU becomes a ReLU on every real channel.
+// Activations are channel-last BF16 [H][W][C] on the interior control-point
+// grid (C = 8 for the input layer: r.re, r.im, c, 0..., 32 for hidden layers).
+//
+// Convolution = implicit GEMM on v_mfma_f32_16x16x32_bf16: M = pixels (16 per
+// wave), N = output channels (16 per MFMA tile), K = (tap, input channel): one
+// tap of 32 channels per MFMA for hidden layers, four taps of 8 channels for the
+// 8-channel input layer.  A workgroup (4 waves) owns a 64-pixel row segment;
+// its three input rows are staged in LDS, the packed weights sit in registers.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "cnn.h"
+
+namespace hh {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// --------------------------------------------------------------------------
+// Forward / data-gradient convolution
+// --------------------------------------------------------------------------
+enum ConvMode { CONV_RELU = 0, CONV_OUT = 1, CONV_MASK = 2 };
+
+template <int CINP, int COUTP, int MODE>
+__global__ __launch_bounds__(256) void conv3x3_kernel(int H, int Wd, const __bf16* __restrict__ X,
+                                                      const __bf16* __restrict__ Wp, const float* __restrict__ bias,
+                                                      const __bf16* __restrict__ Mk, void* __restrict__ Y) {
+    constexpr int SEG = 64;
+    constexpr int NT = COUTP / 16;
+    constexpr int KSTEPS = (CINP == 32) ? 9 : 3;
+    constexpr int CH = CINP / 8;
+    __shared__ __attribute__((aligned(16))) __bf16 xs[3][SEG + 2][CINP];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int x0 = blockIdx.x * SEG, h = blockIdx.y;
+    for (int idx = tid; idx < 3 * (SEG + 2) * CH; idx += 256) {
+        const int r = idx / ((SEG + 2) * CH);
+        const int rem = idx - r * (SEG + 2) * CH;
+        const int px = rem / CH, ch = rem - px * CH;
+        const int hh = h + r - 1, ww = x0 + px - 1;
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (hh >= 0 && hh < H && ww >= 0 && ww < Wd) v = *(const uint4*)(X + ((size_t)hh * Wd + ww) * CINP + ch * 8);
+        *(uint4*)&xs[r][px][ch * 8] = v;
+    }
+    const int g = lane >> 4, col = lane & 15;
+    bf16x8 bw[KSTEPS][NT];
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s) {
+        const int tap = (CINP == 32) ? s : 4 * s + g;
+        const int ci0 = (CINP == 32) ? 8 * g : 0;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (tap < 9) {
+                bw[s][nt] = *(const bf16x8*)(Wp + ((size_t)tap * COUTP + nt * 16 + col) * CINP + ci0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bw[s][nt][e] = (__bf16)0.0f;
+            }
+        }
+    }
+    __syncthreads();
+    f32x4 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int pxa = wave * 16 + col;   // A-operand row: this lane's pixel
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s) {
+        const int tap = (CINP == 32) ? s : 4 * s + g;
+        const int ci0 = (CINP == 32) ? 8 * g : 0;
+        bf16x8 a;
+        if (tap < 9) {
+            const int dy = tap / 3, dx = tap - 3 * dy;
+            a = *(const bf16x8*)&xs[dy][pxa + dx][ci0];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) a[e] = (__bf16)0.0f;
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][nt], acc[nt], 0, 0, 0);
+    }
+    // D: this lane holds output channel nt*16 + col for pixels 4g .. 4g+3 of the wave
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int co = nt * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int pxo = x0 + wave * 16 + 4 * g + i;
+            if (pxo >= Wd) continue;
+            const size_t p = (size_t)h * Wd + pxo;
+            float v = acc[nt][i];
+            if (MODE == CONV_RELU) {
+                v = fmaxf(v + bias[co], 0.0f);
+                ((__bf16*)Y)[p * COUTP + co] = (__bf16)v;
+            } else if (MODE == CONV_OUT) {
+                if (co < 2) ((float*)Y)[p * 2 + co] = v + bias[co];
+            } else {
+                const float m = (float)Mk[p * COUTP + co];
+                ((__bf16*)Y)[p * COUTP + co] = (m > 0.0f) ? (__bf16)v : (__bf16)0.0f;
+            }
+        }
+    }
+}
+
+template <int CINP, int COUTP, int MODE>
+static void conv_launch(int H, int Wd, const __bf16* X, const __bf16* Wp, const float* bias, const __bf16* Mk, void* Y,
+                        hipStream_t s) {
+    dim3 grid((Wd + 63) / 64, H);
+    hipLaunchKernelGGL((conv3x3_kernel<CINP, COUTP, MODE>), grid, dim3(256), 0, s, H, Wd, X, Wp, bias, Mk, Y);
+}
+
+// --------------------------------------------------------------------------
+// Weight gradient: G[tap][co][ci] = sum_p gY[p][co] X[p + off(tap)][ci] and
+// Gb[co] = sum_p gY[p][co], as per-workgroup partial sums over an 8 x 64 pixel
+// tile, reduced afterwards in block order (deterministic).
+// --------------------------------------------------------------------------
+constexpr int WG_TH = 4, WG_TW = 64;
+
+template <int CINP, int COUTP>
+__global__ __launch_bounds__(256) void wgrad_kernel(int H, int Wd, int ci_n, int co_n, const __bf16* __restrict__ X,
+                                                    const __bf16* __restrict__ gY, float* __restrict__ part) {
+    __shared__ __bf16 xs[WG_TH + 2][WG_TW + 2][CINP];
+    __shared__ __bf16 gs[WG_TH][WG_TW][COUTP > 16 ? COUTP : 16];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * WG_TW, h0 = blockIdx.y * WG_TH;
+    for (int idx = tid; idx < (WG_TH + 2) * (WG_TW + 2) * CINP; idx += 256) {
+        const int c = idx % CINP, rest = idx / CINP;
+        const int px = rest % (WG_TW + 2), r = rest / (WG_TW + 2);
+        const int hh = h0 + r - 1, ww = x0 + px - 1;
+        __bf16 v = (__bf16)0.0f;
+        if (hh >= 0 && hh < H && ww >= 0 && ww < Wd) v = X[((size_t)hh * Wd + ww) * CINP + c];
+        xs[r][px][c] = v;
+    }
+    for (int idx = tid; idx < WG_TH * WG_TW * co_n; idx += 256) {
+        const int c = idx % co_n, rest = idx / co_n;
+        const int px = rest % WG_TW, r = rest / WG_TW;
+        const int hh = h0 + r, ww = x0 + px;
+        __bf16 v = (__bf16)0.0f;
+        if (hh < H && ww < Wd) v = gY[((size_t)hh * Wd + ww) * COUTP + c];
+        gs[r][px][c] = v;
+    }
+    __syncthreads();
+    const int nw = 9 * co_n * ci_n;
+    const int nout = nw + co_n;
+    const size_t base = (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * nout;
+    for (int o = tid; o < nout; o += 256) {
+        float acc = 0.0f;
+        if (o < nw) {
+            const int ci = o % ci_n, rest = o / ci_n;
+            const int co = rest % co_n, tap = rest / co_n;
+            const int dy = tap / 3, dx = tap - 3 * dy;
+            for (int r = 0; r < WG_TH; ++r)
+                for (int px = 0; px < WG_TW; ++px) acc += (float)gs[r][px][co] * (float)xs[r + dy][px + dx][ci];
+        } else {
+            const int co = o - nw;
+            for (int r = 0; r < WG_TH; ++r)
+                for (int px = 0; px < WG_TW; ++px) acc += (float)gs[r][px][co];
+        }
+        part[base + o] = acc;
+    }
+}
+
+__global__ void reduce_parts_kernel(int nblk, int nout, const float* __restrict__ part, float* __restrict__ out) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nout) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * nout + o];
+    out[o] = s;
+}
+
+// --------------------------------------------------------------------------
+// Input packing, output application, loss gradient
+// --------------------------------------------------------------------------
+// X0[p] = (r.re / nr, r.im / nr, c[p], 0, 0, 0, 0, 0) with nr = sqrt(*nr2)
+template <class TV>
+__global__ void pack_input_kernel(long long N, const cx<TV>* __restrict__ r, const double* nr2,
+                                  const float* __restrict__ feat, __bf16* __restrict__ X0) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const double nr = sqrt(*nr2);
+    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    const cx<TV> v = r[p];
+    bf16x8 o;
+    o[0] = (__bf16)(float)(v.re * inv);
+    o[1] = (__bf16)(float)(v.im * inv);
+    o[2] = (__bf16)feat[p];
+#pragma unroll
+    for (int e = 3; e < 8; ++e) o[e] = (__bf16)0.0f;
+    *(bf16x8*)(X0 + p * 8) = o;
+}
+
+// x (+)= omega D^-1 r + nr * out  (smoother step), out: complex FP32 network output
+template <class TV>
+__global__ void apply_step_kernel(long long N, const float* __restrict__ out, const double* nr2,
+                                  const cx<TV>* __restrict__ r, const cx<TV>* __restrict__ dinv, TV omega,
+                                  cx<TV>* __restrict__ x, int accumulate) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const double nr = sqrt(*nr2);
+    const cx<TV> d = dinv[p], v = r[p];
+    const TV sr = omega * (d.re * v.re - d.im * v.im) + (TV)(nr * out[2 * p]);
+    const TV si = omega * (d.re * v.im + d.im * v.re) + (TV)(nr * out[2 * p + 1]);
+    if (accumulate) {
+        const cx<TV> o = x[p];
+        x[p] = {o.re + sr, o.im + si};
+    } else {
+        x[p] = {sr, si};
+    }
+}
+
+// gOut[p] = -(2 / nr) * y[p] (real channels re, im; padded to 8), y = conj(M_beta) r'
+__global__ void loss_grad_pack_kernel(long long N, const cx<double>* __restrict__ y, const double* nr2,
+                                      __bf16* __restrict__ g) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const double nr = sqrt(*nr2);
+    const double f = nr > 0.0 ? -2.0 / nr : 0.0;
+    bf16x8 o;
+    o[0] = (__bf16)(float)(f * y[p].re);
+    o[1] = (__bf16)(float)(f * y[p].im);
+#pragma unroll
+    for (int e = 2; e < 8; ++e) o[e] = (__bf16)0.0f;
+    *(bf16x8*)(g + p * 8) = o;
+}
+
+// s = omega D^-1 r + nr * out (complex FP64) for the loss
+__global__ void scale_out_kernel(long long N, const float* __restrict__ out, const double* nr2,
+                                 const cx<double>* __restrict__ r, const cx<double>* __restrict__ dinv, double omega,
+                                 cx<double>* __restrict__ s) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const double nr = sqrt(*nr2);
+    const cx<double> d = dinv[p], v = r[p];
+    s[p] = {omega * (d.re * v.re - d.im * v.im) + nr * (double)out[2 * p],
+            omega * (d.re * v.im + d.im * v.re) + nr * (double)out[2 * p + 1]};
+}
+
+// --------------------------------------------------------------------------
+// Parameter handling: complex master parameters (float pairs), real-expanded
+// BF16 packing, gradient folding and Adam.
+// --------------------------------------------------------------------------
+// Layer l parameter block: W[co][ci][dy][dx] (complex) then b[co] (complex).
+struct LayerDims {
+    int cin, cout;      // complex channels
+    int cinp, coutp;    // padded real channels of the packed forward weights
+    int off;            // offset of W (in complex entries) in the parameter vector
+};
+
+// dn: output channels of the data-gradient conv (the layer's input channels),
+// dk: its input channels (the layer's output channels, padded)
+__global__ void pack_weights_kernel(LayerDims d, const float* __restrict__ theta, __bf16* __restrict__ Wf,
+                                    __bf16* __restrict__ Wd, int dn, int dk, float* __restrict__ bias) {
+    // forward: Wf[tap][co_r][ci_r]; data-gradient: Wd[8 - tap][ci_r][co_r] ([tap'][dn][dk])
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nf = 9 * d.coutp * d.cinp;
+    if (idx < nf) {
+        const int ci_r = idx % d.cinp, rest = idx / d.cinp;
+        const int co_r = rest % d.coutp, tap = rest / d.coutp;
+        float v = 0.0f;
+        if (ci_r < 2 * d.cin && co_r < 2 * d.cout) {
+            const int o = co_r >> 1, s = co_r & 1, i = ci_r >> 1, t = ci_r & 1;
+            const int dy = tap / 3, dx = tap % 3;
+            const size_t w = (size_t)d.off + (((size_t)o * d.cin + i) * 3 + dy) * 3 + dx;
+            const float a = theta[2 * w], b = theta[2 * w + 1];
+            v = (s == 0) ? (t == 0 ? a : -b) : (t == 0 ? b : a);
+        }
+        Wf[idx] = (__bf16)v;
+        if (Wd && co_r < dk && ci_r < dn) Wd[((size_t)(8 - tap) * dn + ci_r) * dk + co_r] = (__bf16)v;
+    }
+    if (idx < d.coutp) {
+        float v = 0.0f;
+        if (idx < 2 * d.cout) {
+            const size_t bo = (size_t)d.off + (size_t)d.cout * d.cin * 9 + (idx >> 1);
+            v = theta[2 * bo + (idx & 1)];
+        }
+        bias[idx] = v;
+    }
+}
+
+// Complex gradient of layer d from the real-expanded G[tap][co_r][ci_r] (ci_n, co_n
+// real channels) and Gb[co_r]: g_a = G[2o][2i] + G[2o+1][2i+1], g_b = G[2o+1][2i] - G[2o][2i+1].
+__global__ void fold_grad_kernel(LayerDims d, int ci_n, int co_n, const float* __restrict__ G, float* __restrict__ grad) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = d.cout * d.cin * 9;
+    if (idx < nw) {
+        const int tapflat = idx % 9, rest = idx / 9;
+        const int i = rest % d.cin, o = rest / d.cin;
+        auto g = [&](int co_r, int ci_r) { return G[((size_t)tapflat * co_n + co_r) * ci_n + ci_r]; };
+        const float ga = g(2 * o, 2 * i) + g(2 * o + 1, 2 * i + 1);
+        const float gb = g(2 * o + 1, 2 * i) - g(2 * o, 2 * i + 1);
+        const size_t w = (size_t)d.off + idx;
+        grad[2 * w] = ga;
+        grad[2 * w + 1] = gb;
+    } else if (idx < nw + d.cout) {
+        const int o = idx - nw;
+        const float* Gb = G + (size_t)9 * co_n * ci_n;
+        const size_t w = (size_t)d.off + nw + o;
+        grad[2 * w] = Gb[2 * o];
+        grad[2 * w + 1] = Gb[2 * o + 1];
+    }
+}
+
+__global__ void adam_kernel(int n, float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    m[i] = b1 * m[i] + (1.0f - b1) * gi;
+    v[i] = b2 * v[i] + (1.0f - b2) * gi * gi;
+    theta[i] -= lr * (m[i] / c1) / (sqrtf(v[i] / c2) + eps);
+}
+
+// ||x||^2 in one workgroup (FP64 accumulation, deterministic)
+template <class TV>
+__global__ __launch_bounds__(1024) void norm2_small_kernel(long long N, const cx<TV>* __restrict__ x, double* out) {
+    __shared__ double sh[1024];
+    double s = 0.0;
+    for (long long t = threadIdx.x; t < N; t += 1024) {
+        const cx<TV> v = x[t];
+        s += (double)v.re * v.re + (double)v.im * v.im;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+static inline unsigned g1(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// --------------------------------------------------------------------------
+// Host side
+// --------------------------------------------------------------------------
+CnnImpl::CnnImpl(unsigned long long seed) {
+    int off = 0;
+    for (int l = 0; l < 4; ++l) {
+        LayerInfo& L = layers[l];
+        L.cin = kChannels[l];
+        L.cout = kChannels[l + 1];
+        L.cinp = (l == 0) ? 8 : 32;
+        L.coutp = (l == 3) ? 16 : 32;
+        L.off = off;
+        off += L.cout * L.cin * 9 + L.cout;
+    }
+    nparam = off;
+    // seeded initial parameters (SplitMix64 -> Box-Muller), scale 0.5/sqrt(9 cin)
+    std::vector<float> th(2 * (size_t)nparam, 0.0f);
+    unsigned long long st = seed;
+    auto next = [&]() {
+        st += 0x9E3779B97F4A7C15ULL;
+        unsigned long long z = st;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    };
+    auto unif = [&]() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); };
+    auto normal = [&]() { return std::sqrt(-2.0 * std::log(unif())) * std::cos(2.0 * M_PI * unif()); };
+    for (int l = 0; l < 4; ++l) {
+        const LayerInfo& L = layers[l];
+        const double sc = 0.5 / std::sqrt(9.0 * L.cin);
+        for (int i = 0; i < L.cout * L.cin * 9; ++i) {
+            th[2 * (L.off + i)] = (float)(sc * normal());
+            th[2 * (L.off + i) + 1] = (float)(sc * normal());
+        }
+    }
+    upload(theta, th);
+    std::vector<float> z(2 * (size_t)nparam, 0.0f);
+    upload(adam_m, z);
+    upload(adam_v, z);
+    upload(grad, z);
+    for (int l = 0; l < 4; ++l) {
+        LayerInfo& L = layers[l];
+        L.wf.alloc((size_t)9 * L.coutp * L.cinp * 2);
+        L.bias.alloc((size_t)L.coutp * 4);
+        // data-gradient weights map the layer's output channels (padded to 8 or
+        // 32) back to its input channels (32); the input layer needs none
+        if (l > 0) {
+            L.dinp = (l == 3) ? 8 : 32;
+            L.doutp = 32;
+            L.wd.alloc((size_t)9 * L.dinp * L.doutp * 2);
+            HH_HIP(hipMemset(L.wd.p, 0, L.wd.bytes));
+        }
+    }
+    repack(nullptr);
+    HH_HIP(hipDeviceSynchronize());
+}
+
+void CnnImpl::repack(hipStream_t s) {
+    for (int l = 0; l < 4; ++l) {
+        LayerInfo& L = layers[l];
+        LayerDims d{L.cin, L.cout, L.cinp, L.coutp, L.off};
+        const int n = 9 * L.coutp * L.cinp;
+        hipLaunchKernelGGL(pack_weights_kernel, dim3(g1(n, 256)), dim3(256), 0, s, d, theta.as<float>(),
+                           L.wf.as<__bf16>(), l > 0 ? L.wd.as<__bf16>() : nullptr, L.doutp, L.dinp,
+                           L.bias.as<float>());
+    }
+}
+
+void CnnImpl::set_params(const float* host, int n) {
+    HH_REQUIRE(n == 2 * nparam, "parameter count mismatch");
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(host[i])) throw Err{HH_ENUMERIC, "non-finite network parameter"};
+    HH_HIP(hipMemcpy(theta.p, host, (size_t)n * 4, hipMemcpyHostToDevice));
+    HH_HIP(hipMemset(adam_m.p, 0, adam_m.bytes));
+    HH_HIP(hipMemset(adam_v.p, 0, adam_v.bytes));
+    adam_t = 0;
+    repack(nullptr);
+    HH_HIP(hipDeviceSynchronize());
+}
+
+void CnnImpl::ensure(int H, int Wd) {
+    if (H == gH && Wd == gW) return;
+    gH = H;
+    gW = Wd;
+    const size_t P = (size_t)H * Wd;
+    x0.alloc(P * 8 * 2);
+    for (int l = 0; l < 3; ++l) act[l].alloc(P * 32 * 2);
+    out.alloc(P * 2 * 4);
+    gA.alloc(P * 32 * 2);
+    gB.alloc(P * 32 * 2);
+    gOut.alloc(P * 8 * 2);
+    sbuf.alloc(P * 16);
+    rbuf.alloc(P * 16);
+    ybuf.alloc(P * 16);
+    scal.alloc(64);
+    const int nblk = ((Wd + WG_TW - 1) / WG_TW) * ((H + WG_TH - 1) / WG_TH);
+    part.alloc((size_t)nblk * (9 * 32 * 32 + 32) * 4);
+    gfull.alloc((size_t)(9 * 32 * 32 + 32) * 4);
+}
+
+// Network forward on the packed input x0 (activations kept in act[]); output in `out`.
+void CnnImpl::forward(int H, int Wd, hipStream_t s) {
+    conv_launch<8, 32, CONV_RELU>(H, Wd, x0.as<__bf16>(), layers[0].wf.as<__bf16>(), layers[0].bias.as<float>(),
+                                  nullptr, act[0].p, s);
+    conv_launch<32, 32, CONV_RELU>(H, Wd, act[0].as<__bf16>(), layers[1].wf.as<__bf16>(), layers[1].bias.as<float>(),
+                                   nullptr, act[1].p, s);
+    conv_launch<32, 32, CONV_RELU>(H, Wd, act[1].as<__bf16>(), layers[2].wf.as<__bf16>(), layers[2].bias.as<float>(),
+                                   nullptr, act[2].p, s);
+    conv_launch<32, 16, CONV_OUT>(H, Wd, act[2].as<__bf16>(), layers[3].wf.as<__bf16>(), layers[3].bias.as<float>(),
+                                  nullptr, out.p, s);
+}
+
+template <class TV>
+void CnnImpl::step(int H, int Wd, const cx<TV>* r, const float* feat, const cx<TV>* dinv, TV omega, cx<TV>* x,
+                   int accumulate, hipStream_t s) {
+    ensure(H, Wd);
+    const long long N = (long long)H * Wd;
+    double* nr2 = scal.as<double>();
+    hipLaunchKernelGGL(norm2_small_kernel<TV>, dim3(1), dim3(1024), 0, s, N, r, nr2);
+    hipLaunchKernelGGL(pack_input_kernel<TV>, dim3(g1(N, 256)), dim3(256), 0, s, N, r, nr2, feat, x0.as<__bf16>());
+    forward(H, Wd, s);
+    hipLaunchKernelGGL(apply_step_kernel<TV>, dim3(g1(N, 256)), dim3(256), 0, s, N, out.as<float>(), nr2, r, dinv,
+                       omega, x, accumulate);
+}
+template void CnnImpl::step<float>(int, int, const cx<float>*, const float*, const cx<float>*, float, cx<float>*, int,
+                                   hipStream_t);
+template void CnnImpl::step<double>(int, int, const cx<double>*, const float*, const cx<double>*, double, cx<double>*,
+                                    int, hipStream_t);
+
+void CnnImpl::wgrad(int l, int H, int Wd, const __bf16* X, int cinp, const __bf16* gY, int coutp, int ci_n, int co_n,
+                    hipStream_t s) {
+    dim3 grid((Wd + WG_TW - 1) / WG_TW, (H + WG_TH - 1) / WG_TH);
+    const int nblk = grid.x * grid.y;
+    const int nout = 9 * ci_n * co_n + co_n;
+    if (cinp == 8 && coutp == 32)
+        hipLaunchKernelGGL((wgrad_kernel<8, 32>), grid, dim3(256), 0, s, H, Wd, ci_n, co_n, X, gY, part.as<float>());
+    else if (cinp == 32 && coutp == 32)
+        hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, dim3(256), 0, s, H, Wd, ci_n, co_n, X, gY, part.as<float>());
+    else
+        hipLaunchKernelGGL((wgrad_kernel<32, 8>), grid, dim3(256), 0, s, H, Wd, ci_n, co_n, X, gY, part.as<float>());
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(g1(nout, 256)), dim3(256), 0, s, nblk, nout, part.as<float>(),
+                       gfull.as<float>());
+    const LayerInfo& L = layers[l];
+    LayerDims d{L.cin, L.cout, L.cinp, L.coutp, L.off};
+    const int nf = L.cout * L.cin * 9 + L.cout;
+    hipLaunchKernelGGL(fold_grad_kernel, dim3(g1(nf, 256)), dim3(256), 0, s, d, ci_n, co_n, gfull.as<float>(),
+                       grad.as<float>());
+}
+
+// Loss and parameter gradient for one residual sample r on the grid (H, Wd):
+// s = omega D^-1 r + ||r|| C(r/||r||, c), r' = r - M_beta s, L = ||r'||^2 / ||r||^2.
+// `mbeta(x, b, y, conj)` computes y = b - M_beta x (conj = 0) or y = conj(M_beta) x
+// (conj = 1) on the caller's stream.
+double CnnImpl::loss_grad(int H, int Wd, const cx<double>* r, const float* feat, const cx<double>* dinv,
+                          double omega, const MbetaFn& mbeta, hipStream_t s) {
+    ensure(H, Wd);
+    const long long N = (long long)H * Wd;
+    double* nr2 = scal.as<double>();
+    double* rn2 = nr2 + 1;
+    hipLaunchKernelGGL(norm2_small_kernel<double>, dim3(1), dim3(1024), 0, s, N, r, nr2);
+    hipLaunchKernelGGL(pack_input_kernel<double>, dim3(g1(N, 256)), dim3(256), 0, s, N, r, nr2, feat, x0.as<__bf16>());
+    forward(H, Wd, s);
+    hipLaunchKernelGGL(scale_out_kernel, dim3(g1(N, 256)), dim3(256), 0, s, N, out.as<float>(), nr2, r, dinv, omega,
+                       sbuf.as<cx<double>>());
+    mbeta(sbuf.as<cx<double>>(), r, rbuf.as<cx<double>>(), 0);          // r' = r - M s
+    hipLaunchKernelGGL(norm2_small_kernel<double>, dim3(1), dim3(1024), 0, s, N, rbuf.as<cx<double>>(), rn2);
+    mbeta(rbuf.as<cx<double>>(), nullptr, ybuf.as<cx<double>>(), 1);   // y = conj(M) r'
+    hipLaunchKernelGGL(loss_grad_pack_kernel, dim3(g1(N, 256)), dim3(256), 0, s, N, ybuf.as<cx<double>>(), nr2,
+                       gOut.as<__bf16>());
+    // layer 3 (16 complex -> 1): weights, then the data gradient into act[2]'s space
+    wgrad(3, H, Wd, act[2].as<__bf16>(), 32, gOut.as<__bf16>(), 8, 32, 2, s);
+    conv_launch<8, 32, CONV_MASK>(H, Wd, gOut.as<__bf16>(), layers[3].wd.as<__bf16>(), nullptr, act[2].as<__bf16>(),
+                                  gA.p, s);
+    wgrad(2, H, Wd, act[1].as<__bf16>(), 32, gA.as<__bf16>(), 32, 32, 32, s);
+    conv_launch<32, 32, CONV_MASK>(H, Wd, gA.as<__bf16>(), layers[2].wd.as<__bf16>(), nullptr, act[1].as<__bf16>(),
+                                   gB.p, s);
+    wgrad(1, H, Wd, act[0].as<__bf16>(), 32, gB.as<__bf16>(), 32, 32, 32, s);
+    conv_launch<32, 32, CONV_MASK>(H, Wd, gB.as<__bf16>(), layers[1].wd.as<__bf16>(), nullptr, act[0].as<__bf16>(),
+                                   gA.p, s);
+    wgrad(0, H, Wd, x0.as<__bf16>(), 8, gA.as<__bf16>(), 32, 4, 32, s);
+    double h[2];
+    HH_HIP(hipMemcpyAsync(h, nr2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HH_HIP(hipStreamSynchronize(s));
+    return h[0] > 0.0 ? h[1] / h[0] : 0.0;
+}
+
+void CnnImpl::adam_step(double lr, hipStream_t s) {
+    ++adam_t;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)adam_t), c2 = 1.0f - std::pow(b2, (float)adam_t);
+    const int n = 2 * nparam;
+    hipLaunchKernelGGL(adam_kernel, dim3(g1(n, 256)), dim3(256), 0, s, n, theta.as<float>(), adam_m.as<float>(),
+                       adam_v.as<float>(), grad.as<float>(), (float)lr, b1, b2, 1e-8f, c1, c2);
+    repack(s);
+}
+
+}  // namespace hh

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <memory>
 
+#include "cnn.h"
 #include "hh_internal.h"
 
 namespace hh {
@@ -101,6 +102,14 @@ struct SolverImpl {
     void coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s);
     void arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s);
     bool allow_coop = true;
+    // learned fine-level smoother (null: damped Jacobi everywhere)
+    CnnImpl* cnn = nullptr;
+    DevBuf feat;                 // network feature c = k^2 h^2 per finest-level unknown (FP32)
+    // capture of finest-level V-cycle inputs (training samples)
+    cx<double>* cap_buf = nullptr;
+    int cap_max = 0, cap_n = 0;
+    template <class T>
+    void op_alpha(int l, int mode, double are, double aim, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s);
     int solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s);
 };
 
@@ -113,4 +122,7 @@ struct hh_problem {
 };
 struct hh_solver {
     std::unique_ptr<hh::SolverImpl> impl;
+};
+struct hh_cnn {
+    std::unique_ptr<hh::CnnImpl> impl;
 };

@@ -395,6 +395,20 @@ void SolverImpl::setup(hipStream_t s) {
             }
         }
     }
+    // feature of the learned smoother: c = k^2 h^2 of the finest element with the
+    // unknown's (clamped) index
+    {
+        const LevelDev& l0 = *lev[0];
+        std::vector<float> c((size_t)l0.N);
+        const double h2 = 1.0 / ((double)P.nel[0] * P.nel[0]);
+        for (int i2 = 0; i2 < l0.n2; ++i2)
+            for (int i1 = 0; i1 < l0.n1; ++i1) {
+                const int e2 = std::min(i2, l0.ay.nel - 1), e1 = std::min(i1, l0.ax.nel - 1);
+                const double k2 = const_k ? k2c : P.k2[(size_t)e2 * P.nel[0] + e1];
+                c[(size_t)i2 * l0.n1 + i1] = (float)(k2 * h2);
+            }
+        upload(feat, c);
+    }
     // outer FGMRES workspace
     m_outer = o.restart;
     const size_t v0 = (size_t)lev[0]->N * 16;
@@ -411,6 +425,13 @@ void SolverImpl::setup(hipStream_t s) {
 // ----------------------------------------------------------- hot path ----
 template <class T>
 void SolverImpl::op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s) {
+    op_alpha<T>(l, mode, cslp ? o.beta[0] : 1.0, cslp ? o.beta[1] : 0.0, x, b, y, s);
+}
+
+// y = K x - alpha M_k x at level l, with the residual / Jacobi epilogues (mode)
+template <class T>
+void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* x, const cx<T>* b, cx<T>* y,
+                          hipStream_t s) {
     LevelDev& lv = *lev[l];
     OpArgs<T> a{};
     a.n1 = lv.n1;
@@ -428,8 +449,8 @@ void SolverImpl::op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, 
     a.Mex = lv.Mex.as<double>();
     a.Mey = lv.Mey.as<double>();
     a.S = pick<T>(lv.S64, lv.S32).template as<T>();
-    a.are = cslp ? (T)o.beta[0] : T(1);
-    a.aim = cslp ? (T)o.beta[1] : T(0);
+    a.are = (T)are;
+    a.aim = (T)aim;
     a.x = x;
     a.b = b;
     a.y = y;
@@ -463,14 +484,25 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
     cx<T>* t = pick<T>(lv.t64, lv.t32).template as<cx<T>>();
     cx<T>* r = pick<T>(lv.r64, lv.r32).template as<cx<T>>();
     const cx<T>* dinv = pick<T>(lv.Dinv64, lv.Dinv32).template as<cx<T>>();
-    launch_jacobi0<T>(lv.N, dinv, (T)lv.omega, b, x, s);
-    cx<T>* cur = x;
-    cx<T>* oth = t;
-    for (int i = 1; i < o.nu_pre; ++i) {
-        op<T>(l, MODE_SMOOTH, true, cur, b, oth, s);
-        std::swap(cur, oth);
+    const bool learned = (cnn != nullptr && l == 0);
+    if (learned) {
+        // learned smoother from a zero guess: x = omega D^-1 b + ||b|| C(b/||b||, c),
+        // then further sweeps x += omega D^-1 r + ||r|| C(r/||r||, c), r = b - M_beta x
+        cnn->step<T>(lv.n2, lv.n1, b, feat.as<float>(), dinv, (T)lv.omega, x, 0, s);
+        for (int i = 1; i < o.nu_pre; ++i) {
+            op<T>(l, MODE_RESID, true, x, b, r, s);
+            cnn->step<T>(lv.n2, lv.n1, r, feat.as<float>(), dinv, (T)lv.omega, x, 1, s);
+        }
+    } else {
+        launch_jacobi0<T>(lv.N, dinv, (T)lv.omega, b, x, s);
+        cx<T>* cur = x;
+        cx<T>* oth = t;
+        for (int i = 1; i < o.nu_pre; ++i) {
+            op<T>(l, MODE_SMOOTH, true, cur, b, oth, s);
+            std::swap(cur, oth);
+        }
+        if (cur != x) copy_t<T>(lv.N, cur, x, s);
     }
-    if (cur != x) copy_t<T>(lv.N, cur, x, s);
     op<T>(l, MODE_RESID, true, x, b, r, s);
     LevelDev& lc = *lev[l + 1];
     cx<T>* bc = pick<T>(lc.b64, lc.b32).template as<cx<T>>();
@@ -478,8 +510,15 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
     launch_restrict<T>(lv.tr, r, bc, s);
     vcycle_once<T>(l + 1, bc, xc, s);
     launch_prolong<T>(lv.tr, xc, x, 1, s);
-    cur = x;
-    oth = t;
+    if (learned) {
+        for (int i = 0; i < o.nu_post; ++i) {
+            op<T>(l, MODE_RESID, true, x, b, r, s);
+            cnn->step<T>(lv.n2, lv.n1, r, feat.as<float>(), dinv, (T)lv.omega, x, 1, s);
+        }
+        return;
+    }
+    cx<T>* cur = x;
+    cx<T>* oth = t;
     for (int i = 0; i < o.nu_post; ++i) {
         op<T>(l, MODE_SMOOTH, true, cur, b, oth, s);
         std::swap(cur, oth);
@@ -501,6 +540,12 @@ void SolverImpl::vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
 }
 
 void SolverImpl::precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s) {
+    if (l == 0 && cap_buf && cap_n < cap_max) {
+        const long long N = lev[0]->N;
+        HH_HIP(hipMemcpyAsync(cap_buf + (size_t)cap_n * N, b, (size_t)N * sizeof(cx<double>), hipMemcpyDeviceToDevice,
+                              s));
+        ++cap_n;
+    }
     if (o.precision == 0) {
         vcycle<double>(l, b, x, s);
         return;
@@ -732,6 +777,8 @@ int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_i
 
 template void SolverImpl::op<double>(int, int, bool, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t);
 template void SolverImpl::op<float>(int, int, bool, const cx<float>*, const cx<float>*, cx<float>*, hipStream_t);
+template void SolverImpl::op_alpha<double>(int, int, double, double, const cx<double>*, const cx<double>*, cx<double>*,
+                                           hipStream_t);
 template void SolverImpl::vcycle<double>(int, const cx<double>*, cx<double>*, hipStream_t);
 template void SolverImpl::vcycle<float>(int, const cx<float>*, cx<float>*, hipStream_t);
 

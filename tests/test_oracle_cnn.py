@@ -18,7 +18,7 @@ def _tiny():
     c = cnn.feature(np.full((6, 6), 49.0), 6, shape)
     rng = np.random.default_rng(5)
     r = rng.standard_normal(lv.N) + 1j * rng.standard_normal(lv.N)
-    return lv.Mb.toarray(), r, c, shape
+    return lv.Mb.toarray(), r, c, shape, lv.D, lv.omega
 
 
 def test_single_layer_is_a_zero_padded_correlation():
@@ -30,27 +30,29 @@ def test_single_layer_is_a_zero_padded_correlation():
     assert np.allclose(y[0].real, ref, atol=1e-13) and np.allclose(y[0].imag, 0)
 
 
-def test_zero_weights_give_zero_step_and_unit_loss():
-    Mb, r, c, shape = _tiny()
+def test_zero_weights_give_damped_jacobi():
+    Mb, r, c, shape, D, w = _tiny()
     params = [(np.zeros_like(W), np.zeros_like(b)) for W, b in cnn.init_params(1)]
-    assert np.all(cnn.smoother_step(params, r, c, shape) == 0)
-    L, _ = cnn.loss_and_grad(params, r, c, shape, Mb)
-    assert abs(L - 1.0) < 1e-14
+    s = cnn.smoother_step(params, r, c, shape, D, w)
+    assert np.array_equal(s, w * r / D)
+    L, _ = cnn.loss_and_grad(params, r, c, shape, Mb, D, w)
+    ej = r - Mb @ (w * r / D)
+    assert abs(L - np.vdot(ej, ej).real / np.vdot(r, r).real) < 1e-13
 
 
 def test_step_is_homogeneous_of_degree_one():
-    Mb, r, c, shape = _tiny()
+    Mb, r, c, shape, D, w = _tiny()
     params = cnn.init_params(2)
-    a = cnn.smoother_step(params, 3.5 * r, c, shape)
-    b = 3.5 * cnn.smoother_step(params, r, c, shape)
+    a = cnn.smoother_step(params, 3.5 * r, c, shape, D, w)
+    b = 3.5 * cnn.smoother_step(params, r, c, shape, D, w)
     assert np.allclose(a, b, rtol=1e-13, atol=1e-13 * np.abs(b).max())
 
 
 @pytest.mark.parametrize("layer", [0, 1, 3])
 def test_gradients_match_finite_differences(layer):
-    Mb, r, c, shape = _tiny()
+    Mb, r, c, shape, D, w = _tiny()
     params = cnn.init_params(3, scale=1.0)
-    L, grads = cnn.loss_and_grad(params, r, c, shape, Mb)
+    L, grads = cnn.loss_and_grad(params, r, c, shape, Mb, D, w)
     rng = np.random.default_rng(layer)
     W, b = params[layer]
     gW, gb = grads[layer]
@@ -61,7 +63,7 @@ def test_gradients_match_finite_differences(layer):
             def loss_with(delta):
                 P = [(Wl.copy(), bl.copy()) for Wl, bl in params]
                 P[layer][0][idx] += delta * unit
-                return cnn.loss_and_grad(P, r, c, shape, Mb)[0]
+                return cnn.loss_and_grad(P, r, c, shape, Mb, D, w)[0]
             fd = (loss_with(h) - loss_with(-h)) / (2 * h)
             an = gW[idx].real if part == "re" else gW[idx].imag
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (layer, idx, part, fd, an)
@@ -70,6 +72,6 @@ def test_gradients_match_finite_differences(layer):
     def loss_b(delta):
         P = [(Wl.copy(), bl.copy()) for Wl, bl in params]
         P[layer][1][o] += delta
-        return cnn.loss_and_grad(P, r, c, shape, Mb)[0]
+        return cnn.loss_and_grad(P, r, c, shape, Mb, D, w)[0]
     fd = (loss_b(h) - loss_b(-h)) / (2 * h)
     assert abs(fd - gb[o].real) <= 1e-6 * max(1.0, abs(fd))
