@@ -25,7 +25,9 @@ import numpy as np  # noqa: E402
 from paper_2010_10232_amd import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-CLASS_NAMES = {1: "finest-level operator (stencil) kernel", 2: "dense E^-1 product (direct deflation level)",
+# rocprofv3 traffic summaries (written by paper_2010_10232_amd.profiling) per kernel class
+TRAFFIC_PREFIX = {1: "fine_op", 2: "einv", 3: "arnoldi"}
+CLASS_NAMES = {1: "finest-level operator (stencil) kernel", 2: "exact E^-1 solve (direct deflation level)",
                3: "outer Arnoldi MGS kernel"}
 
 WORKLOADS = {
@@ -232,6 +234,10 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     value = N * sum(iters) / dt
     achieved = (k_bytes / (k_ms * 1e-3)) / 1e9 if k_ms > 0 else None
+    from paper_2010_10232_amd import profiling
+    tr = profiling.read_summary(os.path.join(ROOT, "profiles",
+                                             f"{TRAFFIC_PREFIX[dom]}_{args.workload}_traffic.md"))
+    traffic = tr[0] if tr else None
     out = {
         "metric": "DoF-iterations/s of the deflated MG-CSLP FGMRES solve to 1e-7 relative residual",
         "value": value,
@@ -251,7 +257,7 @@ def main():
                    "setup_s": round(t_setup, 3), "solve_ms": ms_per_step},
         "roofline": {"bound": "hbm", "kernel": CLASS_NAMES[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "launches": k_n, "avg_us": (k_ms * 1e3 / k_n) if k_n else None,
                      "bytes_per_launch": (k_bytes / k_n) if k_n else None,
                      "class_ms_per_solve": {CLASS_NAMES[c]: round(v, 4) for c, v in per_class.items()}},

@@ -80,7 +80,7 @@ typedef struct {
     int precision;           /* 0: all FP64; 1: V-cycle in FP32, rest FP64; default 0 */
     int time_kernels;        /* kernel class timed with HIP events during hh_solve (results
                                 in hh_solve_info): 0 none (default), 1 finest-level operator
-                                (stencil) kernels, 2 dense E^-1 product of the direct
+                                (stencil) kernels, 2 exact E^-1 solve of the direct
                                 deflation level, 3 outer Arnoldi MGS kernels */
 } hh_solver_opts;
 
@@ -146,8 +146,12 @@ hh_status hh_rhs_point_source(const hh_problem* pr, const double* x0, double amp
 /* Builds the multigrid / deflation hierarchy and allocates all device workspace
  * (section 3): coarse knot vectors by knot halving, knot-insertion transfers,
  * Galerkin coarse operators, Jacobi diagonals, the dense inverse of the coarsest
- * M_beta and of the deflation matrix at L_z.  The solver keeps a reference to
- * the problem, which must outlive it. */
+ * M_beta, and the exact solver of the deflation matrix E at L_z: for constant k,
+ * E = My (x) Kx + Ky (x) Mx - k^2 My (x) Mx is diagonalised by the generalised
+ * eigenvectors of the two 1D pencils (K, M) (fast diagonalisation: four small
+ * dense passes per solve, no N_z x N_z matrix); for variable k, a dense inverse
+ * (LU).  HH_ENUMERIC if E is singular.  The solver keeps a reference to the
+ * problem, which must outlive it. */
 hh_status hh_setup(const hh_problem* pr, const hh_solver_opts* o, void* stream,
                    hh_solver** out);
 

@@ -220,10 +220,10 @@ hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, voi
         bool any = false;
         for (int i = 0; i < n; ++i) any = any || active[i];
         if (!any) break;
-        for (int k = 0; k < ns; ++k) HH_HIP(hipStreamSynchronize(st[k]));
         for (int i = 0; i < n; ++i) {
             if (!active[i]) continue;
             try {
+                HH_HIP(hipEventSynchronize(runs[i].waiting));
                 runs[i].step();
                 if (runs[i].phase == SolveRun::P_DONE) {
                     active[i] = 0;

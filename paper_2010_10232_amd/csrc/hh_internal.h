@@ -102,6 +102,8 @@ void make_transfer(Axis& fine, const Axis& coarse);
 void galerkin_mass_stencil(const Axis& ax, const Axis& ay, const std::vector<double>& k2,
                            std::vector<double>& S);
 void basis_values(const std::vector<double>& U, int p, int span, double x, double* N, double* dN);
+// K V = M V diag(lam), V^T M V = I for one axis (V row-major [unknown][mode]).
+void axis_eigen(const Axis& a, std::vector<double>& V, std::vector<double>& lam);
 
 // ------------------------------------------------------ device-side data --
 enum OpKind { KIND_SEP = 0, KIND_VARFINE = 1, KIND_STENCIL = 2 };
@@ -156,6 +158,38 @@ struct KrylovDev {
     int m;
 };
 
+// Coarse tail of the V-cycle run by one workgroup with its level vectors in
+// LDS (all levels from some l0 to the coarsest are small): per-level data,
+// filled once at setup and kept in device memory.
+constexpr int kTailLevels = 16;
+template <class T>
+struct TailLevel {
+    int n1, n2, px, py, kind;     // kind: KIND_SEP or KIND_STENCIL
+    T omega;
+    const double* Kx;
+    const double* Mx;
+    const double* Ky;
+    const double* My;
+    const T* S;                   // KIND_STENCIL: [(2px+1)(2py+1)][N]
+    const cx<T>* dinv;
+    cx<T>* b;                     // this level's right-hand side / iterate / residual / spare
+    cx<T>* x;
+    cx<T>* r;
+    cx<T>* t;
+    Transfer tr;                  // to the next-coarser level
+};
+template <class T>
+struct TailDesc {
+    int L, nL, nu_pre, nu_post;
+    T are, aim;                   // M_beta = K - (are + i aim) M_k
+    double k2c;                   // constant k^2 (KIND_SEP)
+    const cx<T>* Minv;            // dense inverse of M_beta at level L
+    int lds_bytes;                // LDS of the tail from level lds_l0 on
+    int lds_l0;
+    int offb[kTailLevels], offx[kTailLevels], offt[kTailLevels];  // byte offsets of b, x, t in LDS
+    TailLevel<T> lv[kTailLevels];
+};
+
 // Kernel launchers (kernels.hip; op_p<degree>.hip for the level operator).
 template <int P, class T>
 void launch_op_deg(int kind, int mode, int py, const OpArgs<T>& a, hipStream_t s);
@@ -165,6 +199,8 @@ template <class T>
 void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s);
 template <class T>
 void launch_prolong(const Transfer& t, const cx<T>* e, cx<T>* x, int add, hipStream_t s);
+template <class T>   // xout = xin + P e (xin may alias xout)
+void launch_prolong_add(const Transfer& t, const cx<T>* e, const cx<T>* xin, cx<T>* xout, hipStream_t s);
 template <class T>
 void launch_jacobi0(long long N, const cx<T>* dinv, T omega, const cx<T>* b, cx<T>* x, hipStream_t s);
 template <class T>
@@ -176,6 +212,15 @@ void launch_cast_d2f(long long N, const cx<double>* x, cx<float>* y, hipStream_t
 void launch_cast_f2d(long long N, const cx<float>* x, cx<double>* y, hipStream_t s);
 template <class TM, class TV>
 void launch_gemv(int n, const TM* A, const cx<TV>* x, cx<TV>* y, hipStream_t s);
+// x = V-cycle(b) from level l0 through the coarsest level in one workgroup
+// (lds_bytes: dynamic LDS of the level vectors; tail_prepare allows that size)
+template <class T>
+void tail_prepare(int lds_bytes);
+template <class T>
+void launch_vcycle_tail(const TailDesc<T>* desc, int l0, int lds_bytes, const cx<T>* b, cx<T>* x, hipStream_t s);
+// e = (Vy (x) Vx) diag(dinv) (Vy (x) Vx)^T c on an [n2][n1] grid (t1, t2: N-vector scratch)
+void launch_fdm_solve(int n2, int n1, const double* Vx, const double* Vy, const double* dinv, const cx<double>* c,
+                      cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s);
 // Krylov kernels
 int reduction_blocks(long long N);
 void launch_norm_init(long long N, const cx<double>* r, KrylovDev& k, hipStream_t s);  // beta = ||r||, g = [beta,0..], state reset
@@ -184,7 +229,7 @@ void launch_mgs(long long N, int i, int j, cx<double>* w, const cx<double>* V, l
                 KrylovDev& k, hipStream_t s);
 void launch_norm_givens(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv,
                         KrylovDev& k, hipStream_t s);
-void launch_lsq(KrylovDev& k, hipStream_t s);
+void launch_lsq(KrylovDev& k, hipStream_t s, int ncols = -1);
 // fused Arnoldi step (MGS + norm + Givens + normalise): one workgroup for short
 // vectors, a cooperatively launched grid otherwise
 constexpr long long kSmallArnoldi = 4096;
@@ -193,7 +238,7 @@ void launch_arnoldi_coop(long long N, int j, cx<double>* w, const cx<double>* V,
 void launch_arnoldi_small(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv,
                           KrylovDev& k, hipStream_t s);
 void launch_update(long long N, const cx<double>* Z, long long ldz, KrylovDev& k, cx<double>* u,
-                   int accumulate, hipStream_t s);
+                   int accumulate, hipStream_t s, int ncols = -1);
 void launch_dot_norm2(long long N, const cx<double>* x, double* out, int* counter, cx<double>* partials,
                       hipStream_t s);
 

@@ -35,10 +35,7 @@ template void launch_op<float>(int, int, int, int, const OpArgs<float>&, hipStre
 // P = P_y (x) P_x stored as per-row / per-column runs.
 // --------------------------------------------------------------------------
 template <class T>
-__global__ void restrict_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* __restrict__ c) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long Nc = (long long)t.nc1 * t.nc2;
-    if (idx >= Nc) return;
+__device__ __forceinline__ cx<T> restrict_one(const Transfer& t, const cx<T>* __restrict__ r, long long idx) {
     const int J1 = (int)(idx % t.nc1), J2 = (int)(idx / t.nc1);
     const int i0x = t.pcol0x[J1], i0y = t.pcol0y[J2];
     T sr = 0, si = 0;
@@ -56,14 +53,11 @@ __global__ void restrict_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* 
         sr += wy * rr;
         si += wy * ri;
     }
-    c[idx] = {sr, si};
+    return {sr, si};
 }
 
 template <class T>
-__global__ void prolong_kernel(Transfer t, const cx<T>* __restrict__ e, cx<T>* __restrict__ x, int add) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long Nf = (long long)t.nf1 * t.nf2;
-    if (idx >= Nf) return;
+__device__ __forceinline__ cx<T> prolong_one(const Transfer& t, const cx<T>* __restrict__ e, long long idx) {
     const int I1 = (int)(idx % t.nf1), I2 = (int)(idx / t.nf1);
     const int j0x = t.prow0x[I1], j0y = t.prow0y[I2];
     T sr = 0, si = 0;
@@ -81,11 +75,27 @@ __global__ void prolong_kernel(Transfer t, const cx<T>* __restrict__ e, cx<T>* _
         sr += wy * rr;
         si += wy * ri;
     }
-    if (add) {
-        cx<T> o = x[idx];
-        x[idx] = {o.re + sr, o.im + si};
+    return {sr, si};
+}
+
+template <class T>
+__global__ void restrict_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* __restrict__ c) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)t.nc1 * t.nc2) return;
+    c[idx] = restrict_one<T>(t, r, idx);
+}
+
+// x = xin + P e (xin may alias x; xin == nullptr: x = P e)
+template <class T>
+__global__ void prolong_kernel(Transfer t, const cx<T>* __restrict__ e, const cx<T>* xin, cx<T>* x) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)t.nf1 * t.nf2) return;
+    const cx<T> v = prolong_one<T>(t, e, idx);
+    if (xin) {
+        const cx<T> o = xin[idx];
+        x[idx] = {o.re + v.re, o.im + v.im};
     } else {
-        x[idx] = {sr, si};
+        x[idx] = v;
     }
 }
 
@@ -99,12 +109,19 @@ void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s)
 template <class T>
 void launch_prolong(const Transfer& t, const cx<T>* e, cx<T>* x, int add, hipStream_t s) {
     const long long Nf = (long long)t.nf1 * t.nf2;
-    hipLaunchKernelGGL(prolong_kernel<T>, dim3(grid1d(Nf, 256)), dim3(256), 0, s, t, e, x, add);
+    hipLaunchKernelGGL(prolong_kernel<T>, dim3(grid1d(Nf, 256)), dim3(256), 0, s, t, e, add ? x : nullptr, x);
+}
+template <class T>
+void launch_prolong_add(const Transfer& t, const cx<T>* e, const cx<T>* xin, cx<T>* xout, hipStream_t s) {
+    const long long Nf = (long long)t.nf1 * t.nf2;
+    hipLaunchKernelGGL(prolong_kernel<T>, dim3(grid1d(Nf, 256)), dim3(256), 0, s, t, e, xin, xout);
 }
 template void launch_restrict<double>(const Transfer&, const cx<double>*, cx<double>*, hipStream_t);
 template void launch_restrict<float>(const Transfer&, const cx<float>*, cx<float>*, hipStream_t);
 template void launch_prolong<double>(const Transfer&, const cx<double>*, cx<double>*, int, hipStream_t);
+template void launch_prolong_add<double>(const Transfer&, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t);
 template void launch_prolong<float>(const Transfer&, const cx<float>*, cx<float>*, int, hipStream_t);
+template void launch_prolong_add<float>(const Transfer&, const cx<float>*, const cx<float>*, cx<float>*, hipStream_t);
 
 // --------------------------------------------------------------------------
 // Pointwise kernels
@@ -214,6 +231,276 @@ void launch_gemv(int n, const TM* A, const cx<TV>* x, cx<TV>* y, hipStream_t s) 
 template void launch_gemv<double, double>(int, const double*, const cx<double>*, cx<double>*, hipStream_t);
 template void launch_gemv<cx<double>, double>(int, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t);
 template void launch_gemv<cx<float>, float>(int, const cx<float>*, const cx<float>*, cx<float>*, hipStream_t);
+
+// Exact inverse of a separable level operator E = My (x) Kx + Ky (x) Mx - k^2 My (x) Mx
+// by fast diagonalisation: with Kx Vx = Mx Vx diag(lx), Vx^T Mx Vx = I (and
+// likewise in y), (Vy (x) Vx)^T E (Vy (x) Vx) = diag(ly_a + lx_b - k^2), so
+// E^-1 c = Vy [ (Vy^T C Vx) ./ D ] Vx^T for c viewed as the [n2][n1] matrix C.
+// Four small dense passes; each output sums in a fixed order (deterministic).
+// Each pass is a small complex x real matrix product Y = A B (one operand real),
+// tiled 32 x 32 outputs per workgroup with K in chunks of 64 staged through
+// LDS (every thread issues all of its tile loads before the first is used);
+// every output sums k in increasing order.  Operand element (r, c) sits at
+// base[r * sr + c * sc], which expresses the transposes.
+constexpr int FDM_KC = 64;
+template <bool LEFT_REAL>
+__global__ __launch_bounds__(256) void fdm_gemm_kernel(int M, int N, int K, const double* __restrict__ W, int wsr,
+                                                       int wsc, const cx<double>* __restrict__ X, int xsr, int xsc,
+                                                       const double* __restrict__ scale, cx<double>* __restrict__ Y) {
+    // LEFT_REAL: Ws[m][k] (32 x KC), Xs[k][n] (KC x 32); else Xs[m][k], Ws[k][n]
+    constexpr int WR = LEFT_REAL ? 32 : FDM_KC, WC = LEFT_REAL ? FDM_KC : 32;
+    constexpr int XR = LEFT_REAL ? FDM_KC : 32, XC = LEFT_REAL ? 32 : FDM_KC;
+    __shared__ double Ws[WR][WC + 1];
+    __shared__ cx<double> Xs[XR][XC + 1];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+    double ar[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, ai[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    constexpr int PER = 32 * FDM_KC / 256;   // tile elements per thread and operand
+    // tile coordinates of element e: the operand's unit-stride index runs fastest
+    auto wpos = [&](int e, int& r, int& c) {
+        r = (wsc == 1) ? e / WC : e % WR;
+        c = (wsc == 1) ? e % WC : e / WR;
+    };
+    auto xpos = [&](int e, int& r, int& c) {
+        r = (xsc == 1) ? e / XC : e % XR;
+        c = (xsc == 1) ? e % XC : e / XR;
+    };
+    for (int k0 = 0; k0 < K; k0 += FDM_KC) {
+        double wv[PER];
+        cx<double> xv[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            int r, c;
+            wpos(e, r, c);
+            int gr = (LEFT_REAL ? m0 : k0) + r, gc = (LEFT_REAL ? k0 : n0) + c;
+            bool ok = LEFT_REAL ? (gr < M && gc < K) : (gr < K && gc < N);
+            wv[q] = ok ? W[(size_t)gr * wsr + (size_t)gc * wsc] : 0.0;
+            xpos(e, r, c);
+            gr = (LEFT_REAL ? k0 : m0) + r;
+            gc = (LEFT_REAL ? n0 : k0) + c;
+            ok = LEFT_REAL ? (gr < K && gc < N) : (gr < M && gc < K);
+            xv[q] = ok ? X[(size_t)gr * xsr + (size_t)gc * xsc] : cx<double>{0.0, 0.0};
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            int r, c;
+            wpos(e, r, c);
+            Ws[r][c] = wv[q];
+            xpos(e, r, c);
+            Xs[r][c] = xv[q];
+        }
+        __syncthreads();
+        const int kn = min(FDM_KC, K - k0);
+        for (int kk = 0; kk < kn; ++kk) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj) {
+                    const int m = ty + 16 * i, n = tx + 16 * jj;
+                    const double a = LEFT_REAL ? Ws[m][kk] : Ws[kk][n];
+                    const cx<double> x = LEFT_REAL ? Xs[kk][n] : Xs[m][kk];
+                    ar[i][jj] += a * x.re;
+                    ai[i][jj] += a * x.im;
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * jj;
+            if (m >= M || n >= N) continue;
+            const size_t o = (size_t)m * N + n;
+            const double d = scale ? scale[o] : 1.0;
+            Y[o] = {ar[i][jj] * d, ai[i][jj] * d};
+        }
+}
+
+void launch_fdm_solve(int n2, int n1, const double* Vx, const double* Vy, const double* dinv, const cx<double>* c,
+                      cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s) {
+    const dim3 g((unsigned)((n1 + 31) / 32), (unsigned)((n2 + 31) / 32)), b(256);
+    // T1 = C Vx
+    hipLaunchKernelGGL(fdm_gemm_kernel<false>, g, b, 0, s, n2, n1, n1, Vx, n1, 1, c, n1, 1, nullptr, t1);
+    // T2 = (Vy^T T1) ./ D
+    hipLaunchKernelGGL(fdm_gemm_kernel<true>, g, b, 0, s, n2, n1, n2, Vy, 1, n2, t1, n1, 1, dinv, t2);
+    // T1 = T2 Vx^T
+    hipLaunchKernelGGL(fdm_gemm_kernel<false>, g, b, 0, s, n2, n1, n1, Vx, 1, n1, t2, n1, 1, nullptr, t1);
+    // e = Vy T1
+    hipLaunchKernelGGL(fdm_gemm_kernel<true>, g, b, 0, s, n2, n1, n2, Vy, n2, 1, t1, n1, 1, nullptr, e);
+}
+
+// --------------------------------------------------------------------------
+// Coarse tail of the V-cycle in one workgroup.  On levels with a few thousand
+// unknowns or fewer every kernel of the V-cycle is a handful of waves and its
+// cost is launch latency.  Here one 1024-thread workgroup runs the whole
+// descent (Jacobi sweeps, residual, restriction), the dense coarsest solve and
+// the ascent (prolongation, Jacobi sweeps) with the right-hand side, iterate
+// and spare vector of every level in LDS, and a block barrier between phases.
+// Coefficients (bands, D^-1, stencils, transfer weights) are read through the
+// caches.  Each stencil sum runs over the (2px+1)(2py+1) neighbours in a fixed
+// order (deterministic).
+// --------------------------------------------------------------------------
+constexpr int TAIL_TB = 1024;
+
+// (K - alpha M_k) x at unknown (I2, I1) of one level (x in LDS); the loops
+// run over the in-range neighbours only
+template <class T>
+__device__ __forceinline__ cx<T> tail_apply(const TailLevel<T>& L, double k2c, T are, T aim, const cx<T>* x, int I2,
+                                            int I1, long long N) {
+    const int bx = 2 * L.px + 1, by = 2 * L.py + 1;
+    T kr = 0, ki = 0, mr = 0, mi = 0;
+    const int d2a = max(-L.py, -I2), d2b = min(L.py, L.n2 - 1 - I2);
+    const int d1a = max(-L.px, -I1), d1b = min(L.px, L.n1 - 1 - I1);
+    const double* kxr = L.Kx + (size_t)I1 * bx + L.px;
+    const double* mxr = L.Mx + (size_t)I1 * bx + L.px;
+    for (int d2 = d2a; d2 <= d2b; ++d2) {
+        const T myv = (T)L.My[(size_t)I2 * by + d2 + L.py], kyv = (T)L.Ky[(size_t)I2 * by + d2 + L.py];
+        const cx<T>* row = x + (size_t)(I2 + d2) * L.n1 + I1;
+        for (int d1 = d1a; d1 <= d1b; ++d1) {
+            const T kxv = (T)kxr[d1], mxv = (T)mxr[d1];
+            const cx<T> v = row[d1];
+            const T kc = myv * kxv + kyv * mxv;
+            const T mc = (L.kind == KIND_SEP) ? (T)k2c * myv * mxv
+                                              : L.S[(size_t)((d2 + L.py) * bx + d1 + L.px) * N + (size_t)I2 * L.n1 + I1];
+            kr += kc * v.re;
+            ki += kc * v.im;
+            mr += mc * v.re;
+            mi += mc * v.im;
+        }
+    }
+    return {kr - (are * mr - aim * mi), ki - (are * mi + aim * mr)};
+}
+
+// y = b - M_beta x (RESID) or y = x + omega D^-1 (b - M_beta x) (SMOOTH), then a block barrier
+template <class T>
+__device__ void tail_op(const TailLevel<T>& L, const TailDesc<T>& D, int mode, const cx<T>* x, const cx<T>* b,
+                        cx<T>* y) {
+    const long long N = (long long)L.n1 * L.n2;
+    for (long long I = threadIdx.x; I < N; I += TAIL_TB) {
+        const int I1 = (int)(I % L.n1), I2 = (int)(I / L.n1);
+        const cx<T> a = tail_apply<T>(L, D.k2c, D.are, D.aim, x, I2, I1, N);
+        const cx<T> bv = b[I];
+        const T rr = bv.re - a.re, ri = bv.im - a.im;
+        if (mode == MODE_RESID) {
+            y[I] = {rr, ri};
+        } else {
+            const cx<T> dv = L.dinv[I], xv = x[I];
+            y[I] = {xv.re + L.omega * (dv.re * rr - dv.im * ri), xv.im + L.omega * (dv.re * ri + dv.im * rr)};
+        }
+    }
+    __syncthreads();
+}
+
+template <class T>
+__global__ __launch_bounds__(TAIL_TB) void vcycle_tail_kernel(const TailDesc<T>* __restrict__ Dp, int l0,
+                                                              const cx<T>* __restrict__ b0, cx<T>* __restrict__ x0) {
+    extern __shared__ __align__(16) unsigned char tail_smem[];
+    const TailDesc<T>& D = *Dp;
+    const int L = D.L;
+    auto vb = [&](int l) { return (cx<T>*)(tail_smem + D.offb[l]); };
+    auto vx = [&](int l) { return (cx<T>*)(tail_smem + D.offx[l]); };
+    auto vt = [&](int l) { return (cx<T>*)(tail_smem + D.offt[l]); };
+    {
+        const long long N0 = (long long)D.lv[l0].n1 * D.lv[l0].n2;
+        cx<T>* b = vb(l0);
+        for (long long I = threadIdx.x; I < N0; I += TAIL_TB) b[I] = b0[I];
+        __syncthreads();
+    }
+    // descent
+    for (int l = l0; l < L; ++l) {
+        const TailLevel<T>& lv = D.lv[l];
+        const long long N = (long long)lv.n1 * lv.n2;
+        const cx<T>* b = vb(l);
+        cx<T>* x = vx(l);
+        cx<T>* t = vt(l);
+        cx<T>* cur = ((D.nu_pre - 1) & 1) ? t : x;
+        cx<T>* oth = ((D.nu_pre - 1) & 1) ? x : t;
+        for (long long I = threadIdx.x; I < N; I += TAIL_TB) {
+            const cx<T> dv = lv.dinv[I], bv = b[I];
+            cur[I] = {lv.omega * (dv.re * bv.re - dv.im * bv.im), lv.omega * (dv.re * bv.im + dv.im * bv.re)};
+        }
+        __syncthreads();
+        for (int i = 1; i < D.nu_pre; ++i) {
+            tail_op<T>(lv, D, MODE_SMOOTH, cur, b, oth);
+            cx<T>* tmp = cur;
+            cur = oth;
+            oth = tmp;
+        }
+        tail_op<T>(lv, D, MODE_RESID, x, b, t);   // the spare vector holds the residual
+        const long long Nc = (long long)lv.tr.nc1 * lv.tr.nc2;
+        cx<T>* bc = vb(l + 1);
+        for (long long I = threadIdx.x; I < Nc; I += TAIL_TB) bc[I] = restrict_one<T>(lv.tr, t, I);
+        __syncthreads();
+    }
+    // coarsest level: x = M_beta^-1 b, one wave per row (lane-strided sums, butterfly)
+    {
+        const cx<T>* b = vb(L);
+        cx<T>* x = vx(L);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        for (int row = wave; row < D.nL; row += TAIL_TB / 64) {
+            T sr = 0, si = 0;
+            const cx<T>* a = D.Minv + (size_t)row * D.nL;
+            for (int j = lane; j < D.nL; j += 64) {
+                const cx<T> av = a[j], xv = b[j];
+                sr += av.re * xv.re - av.im * xv.im;
+                si += av.re * xv.im + av.im * xv.re;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                sr += __shfl_xor(sr, o, 64);
+                si += __shfl_xor(si, o, 64);
+            }
+            if (lane == 0) x[row] = {sr, si};
+        }
+        __syncthreads();
+    }
+    // ascent
+    for (int l = L - 1; l >= l0; --l) {
+        const TailLevel<T>& lv = D.lv[l];
+        const long long N = (long long)lv.n1 * lv.n2;
+        const cx<T>* b = vb(l);
+        cx<T>* x = vx(l);
+        cx<T>* t = vt(l);
+        const cx<T>* xc = vx(l + 1);
+        cx<T>* cur = (D.nu_post & 1) ? t : x;
+        cx<T>* oth = (D.nu_post & 1) ? x : t;
+        for (long long I = threadIdx.x; I < N; I += TAIL_TB) {
+            const cx<T> v = prolong_one<T>(lv.tr, xc, I), o = x[I];
+            cur[I] = {o.re + v.re, o.im + v.im};
+        }
+        __syncthreads();
+        for (int i = 0; i < D.nu_post; ++i) {
+            tail_op<T>(lv, D, MODE_SMOOTH, cur, b, oth);
+            cx<T>* tmp = cur;
+            cur = oth;
+            oth = tmp;
+        }
+    }
+    {
+        const long long N0 = (long long)D.lv[l0].n1 * D.lv[l0].n2;
+        const cx<T>* x = vx(l0);
+        for (long long I = threadIdx.x; I < N0; I += TAIL_TB) x0[I] = x[I];
+    }
+}
+
+template <class T>
+void tail_prepare(int lds_bytes) {
+    HH_HIP(hipFuncSetAttribute((const void*)vcycle_tail_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               lds_bytes));
+}
+template void tail_prepare<double>(int);
+template void tail_prepare<float>(int);
+
+template <class T>
+void launch_vcycle_tail(const TailDesc<T>* desc, int l0, int lds_bytes, const cx<T>* b, cx<T>* x, hipStream_t s) {
+    hipLaunchKernelGGL(vcycle_tail_kernel<T>, dim3(1), dim3(TAIL_TB), (size_t)lds_bytes, s, desc, l0, b, x);
+}
+template void launch_vcycle_tail<double>(const TailDesc<double>*, int, int, const cx<double>*, cx<double>*,
+                                         hipStream_t);
+template void launch_vcycle_tail<float>(const TailDesc<float>*, int, int, const cx<float>*, cx<float>*, hipStream_t);
 
 // --------------------------------------------------------------------------
 // Krylov: deterministic two-stage reductions.  Every block writes its partial
@@ -562,6 +849,102 @@ __global__ __launch_bounds__(RB) void arnoldi_coop_kernel(long long N, int j, cx
     }
 }
 
+// Register-resident variant for N <= 256 * RB * R: every thread keeps its R
+// entries of w and of the current basis vector in registers, prefetches the
+// next basis vector before the reduction's barrier (it does not depend on h),
+// and reduces with wave butterflies (every lane ends with the same bits) plus
+// one ordered pass over the four waves; after the barrier every wave sums the
+// block partials in index order, so all blocks use identical h.  Same MGS
+// order and one grid barrier per projection as arnoldi_coop_kernel.
+__device__ __forceinline__ void wave_sum2(double& a, double& b) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+}
+
+__device__ __forceinline__ cx<double> grid_sum_reg(double sr, double si, int round, KrylovDev& k, double* sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    wave_sum2(sr, si);
+    if (lane == 0) {
+        sh[2 * wave] = sr;
+        sh[2 * wave + 1] = si;
+    }
+    __syncthreads();
+    cx<double>* buf = k.partials + (size_t)(round & 1) * 1024;
+    if (threadIdx.x == 0) {
+        double tr = 0.0, ti = 0.0;
+#pragma unroll
+        for (int w = 0; w < RB / 64; ++w) {
+            tr += sh[2 * w];
+            ti += sh[2 * w + 1];
+        }
+        buf[blockIdx.x] = {tr, ti};
+    }
+    grid_barrier(&k.ints[3], &k.ints[4], &k.ints[5]);
+    double tr = 0.0, ti = 0.0;
+    for (int b = lane; b < (int)gridDim.x; b += 64) {
+        const cx<double> v = buf[b];
+        tr += v.re;
+        ti += v.im;
+    }
+    wave_sum2(tr, ti);
+    return {tr, ti};
+}
+
+template <int R>
+__global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<double>* __restrict__ w,
+                                                         const cx<double>* __restrict__ V, long long ldv,
+                                                         KrylovDev k) {
+    __shared__ double sh[2 * (RB / 64)];
+    const long long stride = (long long)gridDim.x * RB;
+    const long long t0 = (long long)blockIdx.x * RB + threadIdx.x;
+    const int ldh = k.m + 1;
+    cx<double> wr[R], vr[R], vn[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const long long t = t0 + r * stride;
+        wr[r] = t < N ? w[t] : cx<double>{0.0, 0.0};
+        vr[r] = t < N ? V[t] : cx<double>{0.0, 0.0};
+    }
+    int round = 0;
+    for (int i = 0; i <= j; ++i, ++round) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            sr += vr[r].re * wr[r].re + vr[r].im * wr[r].im;
+            si += vr[r].re * wr[r].im - vr[r].im * wr[r].re;
+        }
+        if (i < j) {
+            const cx<double>* vi1 = V + (size_t)(i + 1) * ldv;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const long long t = t0 + r * stride;
+                vn[r] = t < N ? vi1[t] : cx<double>{0.0, 0.0};
+            }
+        }
+        const cx<double> h = grid_sum_reg(sr, si, round, k, sh);
+        if (blockIdx.x == 0 && threadIdx.x == 0) k.H[(size_t)j * ldh + i] = h;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            wr[r].re -= h.re * vr[r].re - h.im * vr[r].im;
+            wr[r].im -= h.re * vr[r].im + h.im * vr[r].re;
+            vr[r] = vn[r];
+        }
+    }
+    double nr = 0.0, zero = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) nr += wr[r].re * wr[r].re + wr[r].im * wr[r].im;
+    const double hn = sqrt(grid_sum_reg(nr, zero, round, k, sh).re);
+    if (blockIdx.x == 0 && threadIdx.x == 0) givens_column(k, j, hn);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const long long t = t0 + r * stride;
+        if (t < N) w[t] = hn == 0.0 ? cx<double>{0.0, 0.0} : cx<double>{wr[r].re / hn, wr[r].im / hn};
+    }
+}
+
 int coop_blocks(long long N) {
     long long b = (N + 8 * RB - 1) / (8 * RB);
     if (b < 1) b = 1;
@@ -572,8 +955,18 @@ int coop_blocks(long long N) {
 void launch_arnoldi_coop(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
                          hipStream_t s) {
     void* args[] = {&N, &j, &w, &V, &ldv, &k};
-    hipError_t e = hipLaunchCooperativeKernel((const void*)arnoldi_coop_kernel, dim3(coop_blocks(N)), dim3(RB), args,
-                                              0, s);
+    const void* fn = (const void*)arnoldi_coop_kernel;
+    long long blocks = coop_blocks(N);
+    // register-resident kernel: R entries per thread, at most 256 blocks
+    auto pick = [&](int R, const void* f) {
+        if (fn != (const void*)arnoldi_coop_kernel || N > 256LL * RB * R) return;
+        fn = f;
+        blocks = std::max(1LL, (N + (long long)RB * R - 1) / ((long long)RB * R));
+    };
+    pick(4, (const void*)arnoldi_reg_kernel<4>);
+    pick(8, (const void*)arnoldi_reg_kernel<8>);
+    pick(16, (const void*)arnoldi_reg_kernel<16>);
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)blocks), dim3(RB), args, 0, s);
     if (e != hipSuccess) throw Err{HH_EHIP, std::string("cooperative Arnoldi launch: ") + hipGetErrorString(e)};
 }
 
@@ -637,10 +1030,11 @@ void launch_scale_by(long long N, const cx<double>* x, cx<double>* y, const doub
     hipLaunchKernelGGL(scale_by_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y, by);
 }
 
-// Back substitution R y = g on the first jdone rows (R: rotated Hessenberg).
-__global__ void lsq_kernel(KrylovDev k) {
+// Back substitution R y = g on the first n rows (R: rotated Hessenberg); n is
+// ncols when given (>= 0), else the device count of completed Arnoldi steps.
+__global__ void lsq_kernel(KrylovDev k, int ncols) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int n = k.ints[0], ldh = k.m + 1;
+    const int n = ncols >= 0 ? ncols : k.ints[0], ldh = k.m + 1;
     for (int i = n - 1; i >= 0; --i) {
         cx<double> s = k.g[i];
         for (int c = i + 1; c < n; ++c) {
@@ -653,14 +1047,16 @@ __global__ void lsq_kernel(KrylovDev k) {
         k.y[i] = {(s.re * d.re + s.im * d.im) / den, (s.im * d.re - s.re * d.im) / den};
     }
 }
-void launch_lsq(KrylovDev& k, hipStream_t s) { hipLaunchKernelGGL(lsq_kernel, dim3(1), dim3(1), 0, s, k); }
+void launch_lsq(KrylovDev& k, hipStream_t s, int ncols) {
+    hipLaunchKernelGGL(lsq_kernel, dim3(1), dim3(1), 0, s, k, ncols);
+}
 
-// u (+)= sum_{i < jdone} Z_i y_i, accumulated in increasing i.
+// u (+)= sum_{i < n} Z_i y_i, accumulated in increasing i (n as in lsq_kernel).
 __global__ void update_kernel(long long N, const cx<double>* __restrict__ Z, long long ldz, KrylovDev k,
-                              cx<double>* __restrict__ u, int accumulate) {
+                              cx<double>* __restrict__ u, int accumulate, int ncols) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
-    const int n = k.ints[0];
+    const int n = ncols >= 0 ? ncols : k.ints[0];
     double dr = 0.0, di = 0.0;
     for (int i = 0; i < n; ++i) {
         const cx<double> z = Z[(size_t)i * ldz + t];
@@ -676,8 +1072,8 @@ __global__ void update_kernel(long long N, const cx<double>* __restrict__ Z, lon
     }
 }
 void launch_update(long long N, const cx<double>* Z, long long ldz, KrylovDev& k, cx<double>* u, int accumulate,
-                   hipStream_t s) {
-    hipLaunchKernelGGL(update_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, Z, ldz, k, u, accumulate);
+                   hipStream_t s, int ncols) {
+    hipLaunchKernelGGL(update_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, Z, ldz, k, u, accumulate, ncols);
 }
 
 }  // namespace hh

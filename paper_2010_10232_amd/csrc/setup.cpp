@@ -332,4 +332,100 @@ void galerkin_mass_stencil(const Axis& ax, const Axis& ay, const std::vector<dou
     }
 }
 
+// Generalised eigenpairs of one axis's symmetric-definite pencil (K, M):
+// K V = M V diag(lam) with V^T M V = I.  M = L L^T (Cholesky), C = L^-1 K L^-T,
+// C = Q diag(lam) Q^T by the cyclic Jacobi method (plane rotations that zero
+// one off-diagonal pair each, row-by-row sweeps until the off-diagonal mass is
+// negligible), V = L^-T Q.  V is row-major [i][a] (unknown i, mode a).
+void axis_eigen(const Axis& a, std::vector<double>& V, std::vector<double>& lam) {
+    const int n = a.n, p = a.p, bw = 2 * p + 1;
+    std::vector<double> K((size_t)n * n, 0.0), L((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int d = -p; d <= p; ++d) {
+            const int j = i + d;
+            if (j < 0 || j >= n) continue;
+            K[(size_t)i * n + j] = a.Kb[(size_t)i * bw + d + p];
+            L[(size_t)i * n + j] = a.Mb[(size_t)i * bw + d + p];
+        }
+    // Cholesky in place (lower triangle of L)
+    for (int j = 0; j < n; ++j) {
+        double d = L[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(d > 0.0)) throw Err{HH_ENUMERIC, "mass matrix is not positive definite"};
+        const double ljj = std::sqrt(d);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double v = L[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) v -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = v / ljj;
+        }
+        for (int i = 0; i < j; ++i) L[(size_t)i * n + j] = 0.0;
+    }
+    // X = L^-1 K (forward substitution per column), C = X L^-T = (L^-1 X^T)^T
+    auto lower_solve_cols = [&](std::vector<double>& B) {
+        for (int c = 0; c < n; ++c)
+            for (int i = 0; i < n; ++i) {
+                double v = B[(size_t)i * n + c];
+                for (int k = 0; k < i; ++k) v -= L[(size_t)i * n + k] * B[(size_t)k * n + c];
+                B[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+            }
+    };
+    std::vector<double> C = K;
+    lower_solve_cols(C);
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) std::swap(C[(size_t)i * n + j], C[(size_t)j * n + i]);
+    lower_solve_cols(C);
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double m = 0.5 * (C[(size_t)i * n + j] + C[(size_t)j * n + i]);
+            C[(size_t)i * n + j] = C[(size_t)j * n + i] = m;
+        }
+    std::vector<double> Q((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    double total = 0.0;
+    for (double v : C) total += v * v;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                if (i != j) off += C[(size_t)i * n + j] * C[(size_t)i * n + j];
+        if (off <= 1e-32 * total) break;
+        for (int pp = 0; pp < n - 1; ++pp)
+            for (int q = pp + 1; q < n; ++q) {
+                const double apq = C[(size_t)pp * n + q];
+                if (apq == 0.0) continue;
+                const double app = C[(size_t)pp * n + pp], aqq = C[(size_t)q * n + q];
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {  // columns pp, q
+                    const double ckp = C[(size_t)k * n + pp], ckq = C[(size_t)k * n + q];
+                    C[(size_t)k * n + pp] = c * ckp - sn * ckq;
+                    C[(size_t)k * n + q] = sn * ckp + c * ckq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows pp, q
+                    const double cpk = C[(size_t)pp * n + k], cqk = C[(size_t)q * n + k];
+                    C[(size_t)pp * n + k] = c * cpk - sn * cqk;
+                    C[(size_t)q * n + k] = sn * cpk + c * cqk;
+                }
+                C[(size_t)pp * n + q] = C[(size_t)q * n + pp] = 0.0;
+                for (int k = 0; k < n; ++k) {
+                    const double qkp = Q[(size_t)k * n + pp], qkq = Q[(size_t)k * n + q];
+                    Q[(size_t)k * n + pp] = c * qkp - sn * qkq;
+                    Q[(size_t)k * n + q] = sn * qkp + c * qkq;
+                }
+            }
+    }
+    lam.resize(n);
+    for (int i = 0; i < n; ++i) lam[i] = C[(size_t)i * n + i];
+    // V = L^-T Q (back substitution per column)
+    V = Q;
+    for (int c = 0; c < n; ++c)
+        for (int i = n - 1; i >= 0; --i) {
+            double v = V[(size_t)i * n + c];
+            for (int k = i + 1; k < n; ++k) v -= L[(size_t)k * n + i] * V[(size_t)k * n + c];
+            V[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+        }
+}
+
 }  // namespace hh

@@ -55,13 +55,16 @@ struct SolveRun {
     Phase phase = P_DONE;
     double nf = 0, stop = 0, rn = 0, gabs = 0;
     int iters = 0, cycles = 0, j = 0, m = 0, status = 0;
+    bool ahead = false;             // Arnoldi step j + 1 is already enqueued
+    hipEvent_t waiting = nullptr;   // completes when the scalars step() reads are on the host
     hh_solve_info inf{};
     std::chrono::steady_clock::time_point t0;
     void start(SolverImpl* S, const cx<double>* f, cx<double>* u, int use_u0, hipStream_t s);
     void step();
     void enqueue_cycle_start();
-    void enqueue_step();
+    void enqueue_step(int jj);
     void enqueue_final();
+    void mark(hipEvent_t e);
 };
 
 struct SolverImpl {
@@ -71,14 +74,24 @@ struct SolverImpl {
     int Lz = 0;     // deflation level solved directly (0: none)
     std::vector<std::unique_ptr<LevelDev>> lev;
     DevBuf Minv64, Minv32;   // dense inverse of M_beta at level L (complex)
-    DevBuf Einv;             // dense inverse of A at level Lz (real)
+    DevBuf Einv;             // dense inverse of A at level Lz (real; variable k)
+    // constant k: E^-1 at level Lz by fast diagonalisation (1D eigenvectors and 1 / D)
+    bool fdm = false;
+    DevBuf fdmVx, fdmVy, fdmDinv, fdmT1, fdmT2;
+    // levels >= tail_start (all small) run their V-cycle in one workgroup
+    int tail_start = 1 << 30;
+    int tail_lds = 0, tail_lds32 = 0;   // dynamic LDS bytes (FP64 / FP32 tail)
+    DevBuf tail64, tail32;              // TailDesc<double>, TailDesc<float>
     int nL = 0, nZ = 0;
     // outer FGMRES
     int m_outer = 0;
     DevBuf V, Z, kstate, r, scratch;
     KrylovDev kd{};
-    double* pin_d = nullptr;   // pinned host copies of device scalars
+    // pinned host copies of device scalars: two slots (Arnoldi steps alternate)
+    // of 8 doubles / 16 ints; inner-level barrier flags at pin_i[32 + l]
+    double* pin_d = nullptr;
     int* pin_i = nullptr;
+    hipEvent_t ev_slot[2] = {nullptr, nullptr}, ev_misc = nullptr;
     // event timing of one kernel class (non-blocking: events are read after the solve)
     std::vector<hipEvent_t> evpool;
     int ev_used = 0;

@@ -159,6 +159,8 @@ SolverImpl::~SolverImpl() {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     if (pin_d) (void)hipHostFree(pin_d);
     if (pin_i) (void)hipHostFree(pin_i);
+    for (hipEvent_t e : {ev_slot[0], ev_slot[1], ev_misc})
+        if (e) (void)hipEventDestroy(e);
 }
 
 // Kernel-class timing: a pair of events around each launch of the selected
@@ -337,6 +339,83 @@ void SolverImpl::setup(hipStream_t s) {
         upload(Minv64, m64);
         upload(Minv32, m32);
     }
+    // coarse tail: the levels from the first one whose right-hand sides,
+    // iterates and spare vectors (FP64) all fit in the LDS of one workgroup,
+    // down to the coarsest, run as one single-workgroup V-cycle
+    {
+        int dev = 0, lds_max = 0;
+        HH_HIP(hipGetDevice(&dev));
+        HH_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const long long budget = std::min<long long>(lds_max, 160 * 1024) - 1024;
+        tail_start = 1 << 30;
+        tail_lds = 0;
+        for (int l = 1; l < L && L < kTailLevels; ++l) {
+            long long bytes = 0;
+            for (int m = l; m <= L; ++m) bytes += 3 * lev[m]->N * (long long)sizeof(cx<double>);
+            if (bytes <= budget) {
+                tail_start = l;
+                tail_lds = (int)bytes;
+                break;
+            }
+        }
+        if (tail_start < L) {
+            auto fill = [&](auto& d, auto tag) {
+                using T = decltype(tag);
+                d.L = L;
+                d.nL = nL;
+                d.nu_pre = o.nu_pre;
+                d.nu_post = o.nu_post;
+                d.are = (T)o.beta[0];
+                d.aim = (T)o.beta[1];
+                d.k2c = k2c;
+                d.Minv = pick<T>(Minv64, Minv32).template as<cx<T>>();
+                d.lds_l0 = tail_start;
+                int off = 0;
+                for (int l = tail_start; l <= L; ++l) {
+                    const int vb = (int)(lev[l]->N * (long long)sizeof(cx<T>));
+                    d.offb[l] = off;
+                    d.offx[l] = off + vb;
+                    d.offt[l] = off + 2 * vb;
+                    off += 3 * vb;
+                }
+                d.lds_bytes = off;
+                for (int l = tail_start; l <= L; ++l) {
+                    LevelDev& lv = *lev[l];
+                    auto& t = d.lv[l];
+                    t.n1 = lv.n1;
+                    t.n2 = lv.n2;
+                    t.px = p;
+                    t.py = is2d ? p : 0;
+                    t.kind = lv.kind;
+                    t.omega = (T)lv.omega;
+                    t.Kx = lv.Kx.as<double>();
+                    t.Mx = lv.Mx.as<double>();
+                    t.Ky = lv.Ky.as<double>();
+                    t.My = lv.My.as<double>();
+                    t.S = pick<T>(lv.S64, lv.S32).template as<T>();
+                    t.dinv = pick<T>(lv.Dinv64, lv.Dinv32).template as<cx<T>>();
+                    t.b = pick<T>(lv.b64, lv.b32).template as<cx<T>>();
+                    t.x = pick<T>(lv.x64, lv.x32).template as<cx<T>>();
+                    t.r = pick<T>(lv.r64, lv.r32).template as<cx<T>>();
+                    t.t = pick<T>(lv.t64, lv.t32).template as<cx<T>>();
+                    t.tr = lv.tr;
+                }
+            };
+            std::vector<TailDesc<double>> d64(1);
+            std::vector<TailDesc<float>> d32(1);
+            std::memset((void*)d64.data(), 0, sizeof(TailDesc<double>));
+            std::memset((void*)d32.data(), 0, sizeof(TailDesc<float>));
+            fill(d64[0], double{});
+            fill(d32[0], float{});
+            for (int l = tail_start; l <= L; ++l)
+                HH_REQUIRE(lev[l]->kind == KIND_SEP || lev[l]->kind == KIND_STENCIL, "tail level kind");
+            upload(tail64, d64);
+            upload(tail32, d32);
+            tail_lds32 = d32[0].lds_bytes;
+            tail_prepare<double>(tail_lds);
+            tail_prepare<float>(tail_lds32);
+        }
+    }
     // deflation levels
     Lz = 0;
     if (o.defl_mode == 1 && L >= 1) Lz = 1;
@@ -348,7 +427,30 @@ void SolverImpl::setup(hipStream_t s) {
                 break;
             }
     }
-    if (Lz > 0) {
+    if (Lz > 0 && const_k) {
+        // separable E: exact inverse by fast diagonalisation, no dense matrix
+        LevelDev& lz = *lev[Lz];
+        nZ = (int)lz.N;
+        std::vector<double> Vx, Vy, lx, ly;
+        axis_eigen(lz.ax, Vx, lx);
+        axis_eigen(lz.ay, Vy, ly);
+        std::vector<double> dinv((size_t)nZ);
+        double scale = k2c;
+        for (double v : lx) scale = std::max(scale, std::fabs(v));
+        for (double v : ly) scale = std::max(scale, std::fabs(v));
+        for (int a = 0; a < lz.n2; ++a)
+            for (int b = 0; b < lz.n1; ++b) {
+                const double d = ly[a] + lx[b] - k2c;
+                if (!(std::fabs(d) > 1e-14 * scale)) throw Err{HH_ENUMERIC, "deflation matrix E is singular"};
+                dinv[(size_t)a * lz.n1 + b] = 1.0 / d;
+            }
+        upload(fdmVx, Vx);
+        upload(fdmVy, Vy);
+        upload(fdmDinv, dinv);
+        fdmT1.alloc((size_t)nZ * 16);
+        fdmT2.alloc((size_t)nZ * 16);
+        fdm = true;
+    } else if (Lz > 0) {
         LevelDev& lz = *lev[Lz];
         nZ = (int)lz.N;
         HH_REQUIRE(nZ <= 32768, "direct deflation level too large");
@@ -375,6 +477,8 @@ void SolverImpl::setup(hipStream_t s) {
         rocblas_int hinfo = 0;
         HH_HIP(hipMemcpy(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost));
         if (hinfo != 0) throw Err{HH_ENUMERIC, "deflation matrix E is singular"};
+    }
+    if (Lz > 0) {
         for (int l = 0; l < Lz; ++l) {
             LevelDev& lv = *lev[l];
             const size_t v64 = (size_t)lv.N * 16;
@@ -416,9 +520,12 @@ void SolverImpl::setup(hipStream_t s) {
     Z.alloc(v0 * m_outer);
     r.alloc(v0);
     fill_krylov(kd, kstate, m_outer);
-    HH_HIP(hipHostMalloc((void**)&pin_d, 8 * sizeof(double), hipHostMallocDefault));
-    HH_HIP(hipHostMalloc((void**)&pin_i, 32 * sizeof(int), hipHostMallocDefault));
-    std::memset(pin_i, 0, 32 * sizeof(int));
+    HH_HIP(hipHostMalloc((void**)&pin_d, 16 * sizeof(double), hipHostMallocDefault));
+    HH_HIP(hipHostMalloc((void**)&pin_i, 64 * sizeof(int), hipHostMallocDefault));
+    std::memset(pin_d, 0, 16 * sizeof(double));
+    std::memset(pin_i, 0, 64 * sizeof(int));
+    for (hipEvent_t* e : {&ev_slot[0], &ev_slot[1], &ev_misc})
+        HH_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     HH_HIP(hipStreamSynchronize(s));
 }
 
@@ -470,15 +577,15 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
 }
 
 template <class T>
-static void copy_t(long long N, const cx<T>* x, cx<T>* y, hipStream_t s) {
-    HH_HIP(hipMemcpyAsync(y, x, (size_t)N * sizeof(cx<T>), hipMemcpyDeviceToDevice, s));
-}
-
-template <class T>
 void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
     LevelDev& lv = *lev[l];
     if (l == L) {
         launch_gemv<cx<T>, T>(nL, pick<T>(Minv64, Minv32).template as<cx<T>>(), b, x, s);
+        return;
+    }
+    if (l >= tail_start) {
+        launch_vcycle_tail<T>(pick<T>(tail64, tail32).template as<TailDesc<T>>(), l,
+                              sizeof(T) == 8 ? tail_lds : tail_lds32, b, x, s);
         return;
     }
     cx<T>* t = pick<T>(lv.t64, lv.t32).template as<cx<T>>();
@@ -494,14 +601,15 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
             cnn->step<T>(lv.n2, lv.n1, r, feat.as<float>(), dinv, (T)lv.omega, x, 1, s);
         }
     } else {
-        launch_jacobi0<T>(lv.N, dinv, (T)lv.omega, b, x, s);
-        cx<T>* cur = x;
-        cx<T>* oth = t;
+        // sweeps alternate between x and t; start where an even count of
+        // further sweeps ends in x
+        cx<T>* cur = ((o.nu_pre - 1) & 1) ? t : x;
+        cx<T>* oth = ((o.nu_pre - 1) & 1) ? x : t;
+        launch_jacobi0<T>(lv.N, dinv, (T)lv.omega, b, cur, s);
         for (int i = 1; i < o.nu_pre; ++i) {
             op<T>(l, MODE_SMOOTH, true, cur, b, oth, s);
             std::swap(cur, oth);
         }
-        if (cur != x) copy_t<T>(lv.N, cur, x, s);
     }
     op<T>(l, MODE_RESID, true, x, b, r, s);
     LevelDev& lc = *lev[l + 1];
@@ -509,21 +617,23 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
     cx<T>* xc = pick<T>(lc.x64, lc.x32).template as<cx<T>>();
     launch_restrict<T>(lv.tr, r, bc, s);
     vcycle_once<T>(l + 1, bc, xc, s);
-    launch_prolong<T>(lv.tr, xc, x, 1, s);
     if (learned) {
+        launch_prolong<T>(lv.tr, xc, x, 1, s);
         for (int i = 0; i < o.nu_post; ++i) {
             op<T>(l, MODE_RESID, true, x, b, r, s);
             cnn->step<T>(lv.n2, lv.n1, r, feat.as<float>(), dinv, (T)lv.omega, x, 1, s);
         }
         return;
     }
-    cx<T>* cur = x;
-    cx<T>* oth = t;
+    // coarse-grid correction into t when an odd number of sweeps follows, so
+    // that the last sweep writes x
+    cx<T>* cur = (o.nu_post & 1) ? t : x;
+    cx<T>* oth = (o.nu_post & 1) ? x : t;
+    launch_prolong_add<T>(lv.tr, xc, x, cur, s);
     for (int i = 0; i < o.nu_post; ++i) {
         op<T>(l, MODE_SMOOTH, true, cur, b, oth, s);
         std::swap(cur, oth);
     }
-    if (cur != x) copy_t<T>(lv.N, cur, x, s);
 }
 
 template <class T>
@@ -591,8 +701,16 @@ void SolverImpl::arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, Kryl
 void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s) {
     if (l == Lz) {
         tstart(2, s);
-        launch_gemv<double, double>(nZ, Einv.as<double>(), c, e, s);
-        tstop(2, 8.0 * nZ * (double)nZ + 32.0 * nZ, s);
+        if (fdm) {
+            const LevelDev& lz = *lev[Lz];
+            launch_fdm_solve(lz.n2, lz.n1, fdmVx.as<double>(), fdmVy.as<double>(), fdmDinv.as<double>(), c,
+                             fdmT1.as<cx<double>>(), fdmT2.as<cx<double>>(), e, s);
+            // c, e, 1/D and both eigenvector matrices once
+            tstop(2, 40.0 * nZ + 8.0 * ((double)lz.n1 * lz.n1 + (double)lz.n2 * lz.n2), s);
+        } else {
+            launch_gemv<double, double>(nZ, Einv.as<double>(), c, e, s);
+            tstop(2, 8.0 * nZ * (double)nZ + 32.0 * nZ, s);
+        }
         return;
     }
     LevelDev& lv = *lev[l];
@@ -617,12 +735,21 @@ void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStre
 
 // ------------------------------------------------------------- FGMRES ----
 // Restarted FGMRES as a resumable state machine: every call of step() consumes
-// the host copy of the scalars that the previously enqueued work produced (the
-// norm of f, the cycle's starting residual, or one Arnoldi step's |g_{j+1}|),
-// takes the decision the algorithm needs, and enqueues the next unit of work
-// plus the device-to-host copy of its scalars.  One problem alternates
-// "synchronise, step"; a batch of problems on different streams advances in
-// lockstep with one synchronisation per problem per batch iteration.
+// the host copy of the scalars that earlier enqueued work produced (the norm of
+// f, the cycle's starting residual, or one Arnoldi step's |g_{j+1}|), takes the
+// decision the algorithm needs, and enqueues the next unit of work plus the
+// device-to-host copy of its scalars.  Arnoldi steps run one ahead: step j + 1
+// is enqueued before step j's scalars are read, so the device never waits for
+// the host.  When step j ends the cycle, the step already enqueued after it
+// only writes basis vector j + 2, Hessenberg column j + 1 and g[j + 1..j + 2],
+// none of which the least-squares solve and update of the first j + 1 columns
+// read (they take the column count from the host).  A batch of problems on
+// several streams advances in lockstep, each waiting on its own event.
+void SolveRun::mark(hipEvent_t e) {
+    HH_HIP(hipEventRecord(e, s));
+    waiting = e;
+}
+
 void SolveRun::start(SolverImpl* S_, const cx<double>* f_, cx<double>* u_, int use_u0_, hipStream_t s_) {
     S = S_;
     f = f_;
@@ -634,6 +761,7 @@ void SolveRun::start(SolverImpl* S_, const cx<double>* f_, cx<double>* u_, int u
     S->ev_bytes = 0.0;
     S->ev_pending = -1;
     iters = cycles = j = m = 0;
+    ahead = false;
     nf = stop = rn = gabs = 0.0;
     status = HH_OK;
     inf = hh_solve_info{};
@@ -641,6 +769,7 @@ void SolveRun::start(SolverImpl* S_, const cx<double>* f_, cx<double>* u_, int u
     const long long N = S->lev[0]->N;
     launch_dot_norm2(N, f, &kd.scal[3], &kd.ints[2], kd.partials, s);
     HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    mark(S->ev_misc);
     phase = P_NF;
 }
 
@@ -648,36 +777,38 @@ void SolveRun::enqueue_cycle_start() {
     KrylovDev& kd = S->kd;
     launch_norm_init(S->lev[0]->N, S->r.as<cx<double>>(), kd, s);
     HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    mark(S->ev_misc);
     phase = P_RN;
 }
 
-void SolveRun::enqueue_step() {
+void SolveRun::enqueue_step(int jj) {
     KrylovDev& kd = S->kd;
     const long long N = S->lev[0]->N;
     cx<double>* Vb = S->V.as<cx<double>>();
     cx<double>* Zb = S->Z.as<cx<double>>();
-    cx<double>* vj = Vb + (size_t)j * N;
-    cx<double>* zj = Zb + (size_t)j * N;
-    cx<double>* w = Vb + (size_t)(j + 1) * N;
+    cx<double>* vj = Vb + (size_t)jj * N;
+    cx<double>* zj = Zb + (size_t)jj * N;
+    cx<double>* w = Vb + (size_t)(jj + 1) * N;
     S->T_apply(0, vj, zj, s);
     S->op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
-    // MGS + norm + Givens + normalisation of w in one launch; algorithmic bytes:
-    // per basis vector read v_i twice and w twice and write w once, then read w
-    // twice and write it once
+    // MGS + norm + Givens + normalisation of w in one launch; algorithmic
+    // bytes: each basis vector v_0..v_jj read once, w read once and written once
     S->tstart(3, s);
-    S->arnoldi(N, j, w, Vb, kd, s);
-    S->tstop(3, (80.0 * (j + 1) + 48.0) * N, s);
-    HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HH_HIP(hipMemcpyAsync(S->pin_i, kd.ints, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
-    phase = P_STEP;
+    S->arnoldi(N, jj, w, Vb, kd, s);
+    S->tstop(3, 16.0 * (jj + 3) * N, s);
+    const int slot = jj & 1;
+    HH_HIP(hipMemcpyAsync(S->pin_d + 8 * slot, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HH_HIP(hipMemcpyAsync(S->pin_i + 16 * slot, kd.ints, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HH_HIP(hipEventRecord(S->ev_slot[slot], s));
 }
 
 void SolveRun::enqueue_final() {
     KrylovDev& kd = S->kd;
     for (int l = 1; l < S->Lz && l < 16; ++l)
-        HH_HIP(hipMemcpyAsync(&S->pin_i[8 + l], &S->lev[l]->kd.ints[5], sizeof(int), hipMemcpyDeviceToHost, s));
+        HH_HIP(hipMemcpyAsync(&S->pin_i[32 + l], &S->lev[l]->kd.ints[5], sizeof(int), hipMemcpyDeviceToHost, s));
     launch_dot_norm2(S->lev[0]->N, S->r.as<cx<double>>(), &kd.scal[3], &kd.ints[2], kd.partials, s);
     HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    mark(S->ev_misc);
     phase = P_FINAL;
 }
 
@@ -694,6 +825,7 @@ void SolveRun::step() {
                 launch_zero(N, u, s);
                 inf.converged = 1;
                 status = HH_OK;
+                waiting = nullptr;
                 phase = P_DONE;
                 return;
             }
@@ -717,30 +849,41 @@ void SolveRun::step() {
             m = std::min(S->m_outer, o.maxit - iters);
             launch_scale_by(N, rr, S->V.as<cx<double>>(), &kd.scal[0], s);
             j = 0;
-            enqueue_step();
+            enqueue_step(0);
+            ahead = (m > 1);
+            if (ahead) enqueue_step(1);
+            waiting = S->ev_slot[0];
+            phase = P_STEP;
             return;
         }
         case P_STEP: {
-            gabs = S->pin_d[2];
+            const int slot = j & 1;
+            gabs = S->pin_d[8 * slot + 2];
+            const int* pi = S->pin_i + 16 * slot;
             ++iters;
-            if (S->pin_i[5]) throw Err{HH_EHIP, "grid barrier of the Arnoldi kernel timed out"};
+            if (pi[5]) throw Err{HH_EHIP, "grid barrier of the Arnoldi kernel timed out"};
             if (!std::isfinite(gabs)) throw Err{HH_ENUMERIC, "Arnoldi recurrence produced NaN/Inf"};
-            if (S->pin_i[1] || gabs <= stop || j + 1 >= m) {
-                // end of the cycle: least squares, update, true residual
-                launch_lsq(kd, s);
-                launch_update(N, S->Z.as<cx<double>>(), N, kd, u, 1, s);
+            if (pi[1] || gabs <= stop || j + 1 >= m) {
+                // end of the cycle: least squares, update, true residual on the
+                // first j + 1 columns
+                launch_lsq(kd, s, j + 1);
+                launch_update(N, S->Z.as<cx<double>>(), N, kd, u, 1, s, j + 1);
                 S->op<double>(0, MODE_RESID, false, u, f, rr, s);
                 ++cycles;
+                ahead = false;
                 enqueue_cycle_start();
             } else {
                 ++j;
-                enqueue_step();
+                if (!ahead) enqueue_step(j);
+                ahead = (j + 1 < m);
+                if (ahead) enqueue_step(j + 1);
+                waiting = S->ev_slot[j & 1];
             }
             return;
         }
         case P_FINAL: {
             for (int l = 1; l < S->Lz && l < 16; ++l)
-                if (S->pin_i[8 + l]) throw Err{HH_EHIP, "grid barrier of an inner Arnoldi kernel timed out"};
+                if (S->pin_i[32 + l]) throw Err{HH_EHIP, "grid barrier of an inner Arnoldi kernel timed out"};
             const double rtrue = std::sqrt(S->pin_d[3]);
             auto t1 = std::chrono::steady_clock::now();
             inf.iters = iters;
@@ -754,6 +897,7 @@ void SolveRun::step() {
             inf.op_launches = cnt;
             inf.op_bytes_per_launch = cnt ? S->ev_bytes / cnt : 0.0;
             status = inf.converged ? HH_OK : HH_ENOCONV;
+            waiting = nullptr;
             phase = P_DONE;
             return;
         }
@@ -766,7 +910,7 @@ int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_i
     SolveRun run;
     run.start(this, f, u, use_u0, s);
     while (run.phase != SolveRun::P_DONE) {
-        HH_HIP(hipStreamSynchronize(s));
+        HH_HIP(hipEventSynchronize(run.waiting));
         run.step();
     }
     HH_HIP(hipStreamSynchronize(s));

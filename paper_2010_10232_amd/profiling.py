@@ -1,0 +1,132 @@
+"""HBM traffic of one kernel from two rocprofv3 counter runs.
+
+`FETCH_SIZE` and `WRITE_SIZE` (KiB per dispatch) are collected in separate
+`rocprofv3 --pmc` runs of the same command.  The command first runs one plain
+device copy of a known size; what the counters read for that copy, divided by
+the bytes it really moves, calibrates each counter.  The kernel's traffic per
+launch is then (FETCH / f_fetch + WRITE / f_write), averaged over its
+dispatches.
+
+The summary written here records a hash of the library sources; the bench
+reports the traffic only while the sources still hash the same (a changed
+kernel needs new counters).
+
+    python -m paper_2010_10232_amd.profiling --fetch F.csv --write W.csv \\
+        --kernel arnoldi_reg_kernel --copy-mib 256 --workload NAME \\
+        --command "..." --out profiles/<kernel>_<workload>_traffic.md
+"""
+import argparse
+import csv
+import hashlib
+import os
+import re
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def source_hash():
+    """sha256 over the library sources (name and contents, sorted by name)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def _per_kernel(path, counter):
+    out = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def _copy_value(vals):
+    """The calibration copy: the largest copy-kernel dispatch of the run."""
+    vs = [v for name, lst in vals.items() if "copy" in name.lower() for v in lst]
+    if not vs:
+        raise SystemExit("no copy dispatch in the counter file")
+    return max(vs)
+
+
+def summarize(fetch_csv, write_csv, kernel, copy_mib):
+    fv = _per_kernel(fetch_csv, "FETCH_SIZE")
+    wv = _per_kernel(write_csv, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    f_fetch = _copy_value(fv) / copy_kib
+    f_write = _copy_value(wv) / copy_kib
+    pat = re.compile(kernel)
+    fk = [v for name, vs in fv.items() if pat.search(name) for v in vs]
+    wk = [v for name, vs in wv.items() if pat.search(name) for v in vs]
+    if not fk or not wk:
+        raise SystemExit(f"kernel {kernel!r} not in the counter files")
+    fetch = sum(fk) / len(fk)
+    write = sum(wk) / len(wk)
+    traffic = 1024.0 * (fetch / f_fetch + write / f_write)
+    return dict(fetch_kib=fetch, write_kib=write, n_fetch=len(fk), n_write=len(wk), f_fetch=f_fetch,
+                f_write=f_write, traffic=traffic)
+
+
+def write_summary(out, kernel, workload, command, s):
+    lines = [
+        f"# HBM traffic of `{kernel}` on {workload}",
+        "",
+        "Commands (repository root on the GPU host; one counter per run):",
+        "",
+        "```",
+        command,
+        "```",
+        "",
+        "| quantity | value |",
+        "|---|---|",
+        f"| FETCH_SIZE per launch (KiB, mean of {s['n_fetch']}) | {s['fetch_kib']:.1f} |",
+        f"| WRITE_SIZE per launch (KiB, mean of {s['n_write']}) | {s['write_kib']:.1f} |",
+        f"| copy calibration: FETCH_SIZE / true bytes | {s['f_fetch']:.4f} |",
+        f"| copy calibration: WRITE_SIZE / true bytes | {s['f_write']:.4f} |",
+        f"| traffic per launch (bytes) | {s['traffic']:.0f} |",
+        "",
+        f"traffic_bytes_per_launch: {s['traffic']:.0f}",
+        f"kernel_regex: {kernel}",
+        f"source_sha256: {source_hash()}",
+        "",
+    ]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+
+
+def read_summary(path):
+    """(traffic bytes per launch, kernel regex) if the summary matches the current sources, else None."""
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            m = re.match(r"^(traffic_bytes_per_launch|kernel_regex|source_sha256): (.+)$", line.strip())
+            if m:
+                vals[m.group(1)] = m.group(2)
+    if vals.get("source_sha256") != source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"]), vals.get("kernel_regex")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--kernel", required=True, help="regular expression matching the kernel name")
+    ap.add_argument("--copy-mib", type=float, required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    s = summarize(a.fetch, a.write, a.kernel, a.copy_mib)
+    write_summary(a.out, a.kernel, a.workload, a.command, s)
+    print(s)
+
+
+if __name__ == "__main__":
+    main()
