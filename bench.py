@@ -36,9 +36,11 @@ WORKLOADS = {
     # configs[0]
     "mp1b_k50_p2_80": dict(dim=1, p=2, n_el=80, k=50.0, x0=(0.5,), opts=dict(defl_mode=1)),
     # configs[2] (p = 3 member), FP64 or mixed
-    "wedge_k150_p3_480": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict()),
-    # configs[4] plain form
-    "grf_k300_p4_960": dict(dim=2, p=4, n_el=960, grf=300.0, x0=(0.5, 0.5), opts=dict()),
+    # (direct deflation level up to 65536 unknowns: level 1, k h <= 1.25 there)
+    "wedge_k150_p3_480": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95),
+                              opts=dict(defl_direct_max=65536)),
+    # configs[4] plain form (direct deflation level 2, 58,564 unknowns)
+    "grf_k300_p4_960": dict(dim=2, p=4, n_el=960, grf=300.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=65536)),
     # configs[3]: 64 independent constant-k problems, k ~ U[50, 400], n_el = ceil(k / 0.625),
     # p ~ U{2, 3, 4}, random interior sources; FP32 V-cycle, FP64 Krylov and deflation
     "batch64_k50_400": dict(batch=64, seed=0, opts=dict(precision=1, maxit=400)),
@@ -204,15 +206,19 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     N = prob.N
+    print(f"[bench] {args.workload}: N = {N}, setup {t_setup:.2f} s", file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
-        solver.solve(f, u)
+    for i in range(args.warmup):
+        _, inf = solver.solve(f, u)
+        print(f"[bench] warm-up solve {i + 1}/{args.warmup}: {inf['iters']} iterations, "
+              f"relres {inf['relres_true']:.2e}", file=sys.stderr, flush=True)
     # dominant kernel class: the one with the most device time in one solve
     per_class = {}
     for cls in (1, 2, 3):
         solver.set_kernel_timing(cls)
         _, inf = solver.solve(f, u)
         per_class[cls] = inf["op_ms_total"]
+        print(f"[bench] kernel class {cls}: {per_class[cls]:.3f} ms per solve", file=sys.stderr, flush=True)
     dom = max(per_class, key=per_class.get)
     solver.set_kernel_timing(dom)
 
@@ -220,9 +226,11 @@ def main():
     t0 = time.perf_counter()
     iters, k_ms, k_n, k_bytes = [], 0.0, 0, 0.0
     infos = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         _, inf = solver.solve(f, u)
         infos.append(inf)
+        if N >= 200000:
+            print(f"[bench] timed solve {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     for inf in infos:

@@ -71,7 +71,8 @@ typedef struct {
                                 bound of D^-1 M_beta,l; 0: omega everywhere; default 1 */
     int defl_mode;           /* 0 none, 1 two-level, 2 multilevel; default 2 */
     int defl_direct_max;     /* multilevel: first level with at most this many unknowns is
-                                solved directly; default 16384 */
+                                solved directly; 1..65536, default 16384 (variable k: a
+                                dense FP64 inverse of N_z^2 entries, 34 GB at 65536) */
     int defl_inner_its[8];   /* fixed inner FGMRES steps at deflation levels 1..8;
                                 default 8, 4, 2, 1, 1, 1, 1, 1 */
     int restart;             /* outer FGMRES restart length, 1..200; default 50 */

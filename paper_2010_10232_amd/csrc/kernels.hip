@@ -502,6 +502,24 @@ template void launch_vcycle_tail<double>(const TailDesc<double>*, int, int, cons
                                          hipStream_t);
 template void launch_vcycle_tail<float>(const TailDesc<float>*, int, int, const cx<float>*, cx<float>*, hipStream_t);
 
+// Dense-matrix set-up helpers: y[idx[i]] = val[i] (distinct indices), and
+// the diagonal of an n x n zero matrix set to one.
+__global__ void scatter_kernel(long long n, const long long* __restrict__ idx, const double* __restrict__ val,
+                               double* __restrict__ y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[idx[i]] = val[i];
+}
+void launch_scatter(long long n, const long long* idx, const double* val, double* y, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(scatter_kernel, dim3(grid1d(n, 256)), dim3(256), 0, s, n, idx, val, y);
+}
+__global__ void set_identity_kernel(long long n, double* __restrict__ a) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i * n + i] = 1.0;
+}
+void launch_set_identity(int n, double* a, hipStream_t s) {
+    hipLaunchKernelGGL(set_identity_kernel, dim3(grid1d(n, 256)), dim3(256), 0, s, (long long)n, a);
+}
+
 // --------------------------------------------------------------------------
 // Krylov: deterministic two-stage reductions.  Every block writes its partial
 // sum; the last block to finish (device-scope atomic ticket) sums the partials

@@ -207,7 +207,7 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(o.defl_mode >= 0 && o.defl_mode <= 2, "defl_mode must be 0, 1 or 2");
     HH_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
     HH_REQUIRE(o.tol >= 0.0 && o.omega > 0.0, "bad tol or omega");
-    HH_REQUIRE(o.defl_direct_max >= 1 && o.defl_direct_max <= 32768, "defl_direct_max must be in 1..32768");
+    HH_REQUIRE(o.defl_direct_max >= 1 && o.defl_direct_max <= 65536, "defl_direct_max must be in 1..65536");
     for (int i = 0; i < 8; ++i) HH_REQUIRE(o.defl_inner_its[i] >= 1 && o.defl_inner_its[i] <= 64, "defl_inner_its in 1..64");
 
     const int p = P.p;
@@ -451,32 +451,79 @@ void SolverImpl::setup(hipStream_t s) {
         fdmT2.alloc((size_t)nZ * 16);
         fdm = true;
     } else if (Lz > 0) {
+        // variable k: dense inverse of E, assembled on the device from its
+        // nonzeros (E and its inverse are symmetric, so row- and column-major
+        // storage coincide)
         LevelDev& lz = *lev[Lz];
         nZ = (int)lz.N;
-        HH_REQUIRE(nZ <= 32768, "direct deflation level too large");
-        std::vector<double> A((size_t)nZ * nZ, 0.0);
-        for (long long I = 0; I < lz.N; ++I)
-            visit_row(lz.ax, lz.ay, const_k, k2c, Sh[Lz], I,
-                      [&](long long J, double kv, double mv) { A[(size_t)I * nZ + J] += kv - mv; });
-        upload(Einv, A);
-        DevBuf ipiv, info;
-        ipiv.alloc((size_t)nZ * sizeof(rocblas_int));
-        info.alloc(sizeof(rocblas_int));
+        HH_REQUIRE(nZ <= 65536, "direct deflation level too large (at most 65536 unknowns)");
+        std::vector<long long> cidx;
+        std::vector<double> cval;
+        std::vector<std::pair<long long, double>> row;
+        for (long long I = 0; I < lz.N; ++I) {
+            row.clear();
+            visit_row(lz.ax, lz.ay, const_k, k2c, Sh[Lz], I, [&](long long J, double kv, double mv) {
+                for (auto& e : row)
+                    if (e.first == J) {
+                        e.second += kv - mv;
+                        return;
+                    }
+                row.emplace_back(J, kv - mv);
+            });
+            for (const auto& e : row) {
+                cidx.push_back(I * nZ + e.first);
+                cval.push_back(e.second);
+            }
+        }
+        const size_t nn = (size_t)nZ * nZ;
+        Einv.alloc(nn * sizeof(double));
+        {
+            DevBuf di, dv;
+            upload(di, cidx);
+            upload(dv, cval);
+            HH_HIP(hipMemsetAsync(Einv.p, 0, nn * sizeof(double), s));
+            launch_scatter(cidx.size(), di.as<long long>(), dv.as<double>(), Einv.as<double>(), s);
+            HH_HIP(hipStreamSynchronize(s));
+        }
         rocblas_handle h;
         if (rocblas_create_handle(&h) != rocblas_status_success) throw Err{HH_EHIP, "rocblas_create_handle failed"};
         rocblas_set_stream(h, s);
-        // The row-major buffer read column-major is A^T; its column-major
-        // inverse inv(A^T), read back row-major, is inv(A).
-        rocblas_status st = rocsolver_dgetrf(h, nZ, nZ, Einv.as<double>(), nZ, ipiv.as<rocblas_int>(),
-                                             info.as<rocblas_int>());
-        if (st == rocblas_status_success)
-            st = rocsolver_dgetri(h, nZ, Einv.as<double>(), nZ, ipiv.as<rocblas_int>(), info.as<rocblas_int>());
-        HH_HIP(hipStreamSynchronize(s));
+        long long singular = 0;
+        rocblas_status st;
+        if (nZ <= 32768) {
+            DevBuf ipiv, info;
+            ipiv.alloc((size_t)nZ * sizeof(rocblas_int));
+            info.alloc(sizeof(rocblas_int));
+            st = rocsolver_dgetrf(h, nZ, nZ, Einv.as<double>(), nZ, ipiv.as<rocblas_int>(), info.as<rocblas_int>());
+            if (st == rocblas_status_success)
+                st = rocsolver_dgetri(h, nZ, Einv.as<double>(), nZ, ipiv.as<rocblas_int>(), info.as<rocblas_int>());
+            HH_HIP(hipStreamSynchronize(s));
+            rocblas_int hinfo = 0;
+            HH_HIP(hipMemcpy(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost));
+            singular = hinfo;
+        } else {
+            // more than 2^31 entries: 64-bit LU, then E^-1 = solve against the identity
+            DevBuf ipiv, info, X;
+            ipiv.alloc((size_t)nZ * sizeof(int64_t));
+            info.alloc(sizeof(int64_t));
+            X.alloc(nn * sizeof(double));
+            HH_HIP(hipMemsetAsync(X.p, 0, nn * sizeof(double), s));
+            launch_set_identity(nZ, X.as<double>(), s);
+            st = rocsolver_dgetrf_64(h, nZ, nZ, Einv.as<double>(), nZ, ipiv.as<int64_t>(), info.as<int64_t>());
+            HH_HIP(hipStreamSynchronize(s));
+            int64_t hinfo = 0;
+            HH_HIP(hipMemcpy(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost));
+            singular = hinfo;
+            if (st == rocblas_status_success && hinfo == 0)
+                st = rocsolver_dgetrs_64(h, rocblas_operation_none, nZ, nZ, Einv.as<double>(), nZ, ipiv.as<int64_t>(),
+                                         X.as<double>(), nZ);
+            HH_HIP(hipStreamSynchronize(s));
+            std::swap(Einv.p, X.p);
+            std::swap(Einv.bytes, X.bytes);
+        }
         rocblas_destroy_handle(h);
         if (st != rocblas_status_success) throw Err{HH_EHIP, "rocsolver LU inverse failed"};
-        rocblas_int hinfo = 0;
-        HH_HIP(hipMemcpy(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost));
-        if (hinfo != 0) throw Err{HH_ENUMERIC, "deflation matrix E is singular"};
+        if (singular != 0) throw Err{HH_ENUMERIC, "deflation matrix E is singular"};
     }
     if (Lz > 0) {
         for (int l = 0; l < Lz; ++l) {
