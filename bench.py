@@ -76,15 +76,10 @@ def cpu_baseline(w, seconds_cap=30.0):
 
 
 def batch_member_opts(d, base):
-    """Deflation per batch member: two-level (direct E on level 1) when level 1 has at most
-    16384 unknowns, else multilevel with a direct level of at most 8192 unknowns and inner
-    FGMRES steps 16, 8, 4, 2."""
-    n1 = ((d["n_el"] + 1) // 2 + d["p"] - 2) ** 2
+    """Deflation per batch member: two-level with the exact E^-1 on level 1 (constant k: fast
+    diagonalisation, affordable at every member size)."""
     o = dict(base)
-    if n1 <= 16384:
-        o.update(defl_mode=1)
-    else:
-        o.update(defl_mode=2, defl_direct_max=8192, defl_inner_its=(16, 8, 4, 2))
+    o.update(defl_mode=1)
     return o
 
 

@@ -195,8 +195,9 @@ hh_status hh_apply(hh_solver* s, int op, int level, const void* x_dev, void* y_d
  * the first three layers, zero padding) on the finest interior control-point
  * grid.  Inputs: r/||r|| and c = k^2 h^2 (k of the finest element with the
  * unknown's clamped index).  As the finest-level smoother it adds a learned
- * correction to the damped Jacobi step: x += omega D^-1 r + ||r|| C(r/||r||, c),
- * r = b - M_beta x, so zero weights give damped Jacobi exactly.  Weights and
+ * correction to the damped Jacobi step: x += omega D^-1 r + rms C(r/rms, c),
+ * r = b - M_beta x, rms = ||r|| / sqrt(N) (inputs of order one on any grid),
+ * so zero weights give damped Jacobi exactly.  Weights and
  * activations are BF16 with FP32 accumulation (MFMA).  Parameters are float
  * (re, im) pairs, per layer W[co][ci][dy][dx] then b[co]. */
 

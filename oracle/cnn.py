@@ -9,10 +9,12 @@ correlation, the zero-weight case); there is no printed value to pin it to.
 Network C: 4 complex 3x3 convolution layers on the interior control-point grid
 [n2][n1]; channels 2 -> 16 -> 16 -> 16 -> 1; CReLU (ReLU of the real and the
 imaginary part separately) after the first three layers; zero padding.
-Input channels: the normalised residual r/||r|| and the real feature
-c = k^2 h^2 (k of the finest element at the control point's index, clamped).
-Smoother step: the damped Jacobi update plus a learned correction,
-    s = omega D^-1 r + ||r|| C(r/||r||, c),
+Input channels: the residual scaled by its root mean square, r/rms(r) with
+rms(r) = ||r|| / sqrt(N) (entries of order one whatever the grid size), and the
+real feature c = k^2 h^2 (k of the finest element at the control point's
+index, clamped).  Smoother step: the damped Jacobi update plus a learned
+correction,
+    s = omega D^-1 r + rms(r) C(r/rms(r), c),
 homogeneous of degree 1 in r; zero weights give exactly damped Jacobi.
 Training loss for one residual r: L = ||r - M_beta s||^2 / ||r||^2.
 
@@ -95,23 +97,24 @@ def feature(k2_elem, n_el, n):
 
 
 def smoother_step(params, r, c, shape, D, omega):
-    """s = omega D^-1 r + ||r|| C(r/||r||, c) on the grid `shape` (r flat, x fastest)."""
-    nr = np.linalg.norm(r)
-    if nr == 0.0:
+    """s = omega D^-1 r + rms(r) C(r/rms(r), c) on the grid `shape` (r flat, x fastest)."""
+    rms = np.linalg.norm(r) / np.sqrt(r.size)
+    if rms == 0.0:
         return np.zeros_like(r)
-    return omega * r / D + nr * forward(params, (r / nr).reshape(shape), c).reshape(-1)
+    return omega * r / D + rms * forward(params, (r / rms).reshape(shape), c).reshape(-1)
 
 
 def loss_and_grad(params, r, c, shape, Mb, D, omega):
     """L = ||r - Mb s||^2 / ||r||^2 and its gradients with respect to every W, b."""
     nr = np.linalg.norm(r)
-    out, acts, pre = forward(params, (r / nr).reshape(shape), c, keep=True)
-    s = omega * r / D + nr * out.reshape(-1)
+    rms = nr / np.sqrt(r.size)
+    out, acts, pre = forward(params, (r / rms).reshape(shape), c, keep=True)
+    s = omega * r / D + rms * out.reshape(-1)
     e = r - Mb @ s
     L = np.vdot(e, e).real / nr ** 2
     g_e = 2.0 * e / nr ** 2
     g_s = -(Mb.conj().T @ g_e)
-    g = (nr * g_s).reshape(shape)[None]          # gradient w.r.t. the output channel
+    g = (rms * g_s).reshape(shape)[None]         # gradient w.r.t. the output channel
     grads = [None] * len(params)
     for l in range(len(params) - 1, -1, -1):
         W, b = params[l]

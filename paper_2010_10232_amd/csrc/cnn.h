@@ -33,7 +33,7 @@ struct CnnImpl {
     void set_params(const float* host, int n);
     void ensure(int H, int W);
     void forward(int H, int W, hipStream_t s);
-    // smoother step on the grid: x (+)= omega D^-1 r + ||r|| C(r/||r||, c)
+    // smoother step on the grid: x (+)= omega D^-1 r + rms C(r/rms, c), rms = ||r|| / sqrt(N)
     template <class TV>
     void step(int H, int W, const cx<TV>* r, const float* feat, const cx<TV>* dinv, TV omega, cx<TV>* x,
               int accumulate, hipStream_t s);

@@ -178,14 +178,15 @@ __global__ void reduce_parts_kernel(int nblk, int nout, const float* __restrict_
 // --------------------------------------------------------------------------
 // Input packing, output application, loss gradient
 // --------------------------------------------------------------------------
-// X0[p] = (r.re / nr, r.im / nr, c[p], 0, 0, 0, 0, 0) with nr = sqrt(*nr2)
+// X0[p] = (r.re / rms, r.im / rms, c[p], 0, 0, 0, 0, 0) with rms = ||r|| / sqrt(N),
+// ||r||^2 = *nr2 (entries of order one whatever the grid size)
 template <class TV>
 __global__ void pack_input_kernel(long long N, const cx<TV>* __restrict__ r, const double* nr2,
                                   const float* __restrict__ feat, __bf16* __restrict__ X0) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const double nr = sqrt(*nr2);
-    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    const double inv = nr > 0.0 ? sqrt((double)N) / nr : 0.0;
     const cx<TV> v = r[p];
     bf16x8 o;
     o[0] = (__bf16)(float)(v.re * inv);
@@ -196,17 +197,17 @@ __global__ void pack_input_kernel(long long N, const cx<TV>* __restrict__ r, con
     *(bf16x8*)(X0 + p * 8) = o;
 }
 
-// x (+)= omega D^-1 r + nr * out  (smoother step), out: complex FP32 network output
+// x (+)= omega D^-1 r + rms * out  (smoother step), out: complex FP32 network output
 template <class TV>
 __global__ void apply_step_kernel(long long N, const float* __restrict__ out, const double* nr2,
                                   const cx<TV>* __restrict__ r, const cx<TV>* __restrict__ dinv, TV omega,
                                   cx<TV>* __restrict__ x, int accumulate) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    const double nr = sqrt(*nr2);
+    const double rms = sqrt(*nr2 / (double)N);
     const cx<TV> d = dinv[p], v = r[p];
-    const TV sr = omega * (d.re * v.re - d.im * v.im) + (TV)(nr * out[2 * p]);
-    const TV si = omega * (d.re * v.im + d.im * v.re) + (TV)(nr * out[2 * p + 1]);
+    const TV sr = omega * (d.re * v.re - d.im * v.im) + (TV)(rms * out[2 * p]);
+    const TV si = omega * (d.re * v.im + d.im * v.re) + (TV)(rms * out[2 * p + 1]);
     if (accumulate) {
         const cx<TV> o = x[p];
         x[p] = {o.re + sr, o.im + si};
@@ -215,13 +216,13 @@ __global__ void apply_step_kernel(long long N, const float* __restrict__ out, co
     }
 }
 
-// gOut[p] = -(2 / nr) * y[p] (real channels re, im; padded to 8), y = conj(M_beta) r'
+// gOut[p] = -(2 rms / nr^2) * y[p] (real channels re, im; padded to 8), y = conj(M_beta) r'
 __global__ void loss_grad_pack_kernel(long long N, const cx<double>* __restrict__ y, const double* nr2,
                                       __bf16* __restrict__ g) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const double nr = sqrt(*nr2);
-    const double f = nr > 0.0 ? -2.0 / nr : 0.0;
+    const double f = nr > 0.0 ? -2.0 / (nr * sqrt((double)N)) : 0.0;
     bf16x8 o;
     o[0] = (__bf16)(float)(f * y[p].re);
     o[1] = (__bf16)(float)(f * y[p].im);
@@ -230,16 +231,16 @@ __global__ void loss_grad_pack_kernel(long long N, const cx<double>* __restrict_
     *(bf16x8*)(g + p * 8) = o;
 }
 
-// s = omega D^-1 r + nr * out (complex FP64) for the loss
+// s = omega D^-1 r + rms * out (complex FP64) for the loss
 __global__ void scale_out_kernel(long long N, const float* __restrict__ out, const double* nr2,
                                  const cx<double>* __restrict__ r, const cx<double>* __restrict__ dinv, double omega,
                                  cx<double>* __restrict__ s) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    const double nr = sqrt(*nr2);
+    const double rms = sqrt(*nr2 / (double)N);
     const cx<double> d = dinv[p], v = r[p];
-    s[p] = {omega * (d.re * v.re - d.im * v.im) + nr * (double)out[2 * p],
-            omega * (d.re * v.im + d.im * v.re) + nr * (double)out[2 * p + 1]};
+    s[p] = {omega * (d.re * v.re - d.im * v.im) + rms * (double)out[2 * p],
+            omega * (d.re * v.im + d.im * v.re) + rms * (double)out[2 * p + 1]};
 }
 
 // --------------------------------------------------------------------------
@@ -487,7 +488,8 @@ void CnnImpl::wgrad(int l, int H, int Wd, const __bf16* X, int cinp, const __bf1
 }
 
 // Loss and parameter gradient for one residual sample r on the grid (H, Wd):
-// s = omega D^-1 r + ||r|| C(r/||r||, c), r' = r - M_beta s, L = ||r'||^2 / ||r||^2.
+// s = omega D^-1 r + rms(r) C(r/rms(r), c), rms(r) = ||r||/sqrt(N), r' = r - M_beta s,
+// L = ||r'||^2 / ||r||^2.
 // `mbeta(x, b, y, conj)` computes y = b - M_beta x (conj = 0) or y = conj(M_beta) x
 // (conj = 1) on the caller's stream.
 double CnnImpl::loss_grad(int H, int Wd, const cx<double>* r, const float* feat, const cx<double>* dinv,

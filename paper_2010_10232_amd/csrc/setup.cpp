@@ -380,8 +380,10 @@ void axis_eigen(const Axis& a, std::vector<double>& V, std::vector<double>& lam)
             const double m = 0.5 * (C[(size_t)i * n + j] + C[(size_t)j * n + i]);
             C[(size_t)i * n + j] = C[(size_t)j * n + i] = m;
         }
-    std::vector<double> Q((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    // QT = Q^T (row a holds eigenvector a) so that rotations touch contiguous rows;
+    // C is kept symmetric: rows pp, q are updated and mirrored into the columns
+    std::vector<double> QT((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) QT[(size_t)i * n + i] = 1.0;
     double total = 0.0;
     for (double v : C) total += v * v;
     for (int sweep = 0; sweep < 60; ++sweep) {
@@ -392,34 +394,40 @@ void axis_eigen(const Axis& a, std::vector<double>& V, std::vector<double>& lam)
         if (off <= 1e-32 * total) break;
         for (int pp = 0; pp < n - 1; ++pp)
             for (int q = pp + 1; q < n; ++q) {
-                const double apq = C[(size_t)pp * n + q];
+                double* Cp = &C[(size_t)pp * n];
+                double* Cq = &C[(size_t)q * n];
+                const double apq = Cp[q];
                 if (apq == 0.0) continue;
-                const double app = C[(size_t)pp * n + pp], aqq = C[(size_t)q * n + q];
+                const double app = Cp[pp], aqq = Cq[q];
                 const double theta = (aqq - app) / (2.0 * apq);
                 const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
                 const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
-                for (int k = 0; k < n; ++k) {  // columns pp, q
-                    const double ckp = C[(size_t)k * n + pp], ckq = C[(size_t)k * n + q];
-                    C[(size_t)k * n + pp] = c * ckp - sn * ckq;
-                    C[(size_t)k * n + q] = sn * ckp + c * ckq;
-                }
-                for (int k = 0; k < n; ++k) {  // rows pp, q
-                    const double cpk = C[(size_t)pp * n + k], cqk = C[(size_t)q * n + k];
-                    C[(size_t)pp * n + k] = c * cpk - sn * cqk;
-                    C[(size_t)q * n + k] = sn * cpk + c * cqk;
-                }
-                C[(size_t)pp * n + q] = C[(size_t)q * n + pp] = 0.0;
                 for (int k = 0; k < n; ++k) {
-                    const double qkp = Q[(size_t)k * n + pp], qkq = Q[(size_t)k * n + q];
-                    Q[(size_t)k * n + pp] = c * qkp - sn * qkq;
-                    Q[(size_t)k * n + q] = sn * qkp + c * qkq;
+                    if (k == pp || k == q) continue;
+                    const double g = Cp[k], h = Cq[k];
+                    Cp[k] = c * g - sn * h;
+                    Cq[k] = sn * g + c * h;
+                    C[(size_t)k * n + pp] = Cp[k];
+                    C[(size_t)k * n + q] = Cq[k];
+                }
+                Cp[pp] = app - t * apq;
+                Cq[q] = aqq + t * apq;
+                Cp[q] = Cq[pp] = 0.0;
+                double* Qp = &QT[(size_t)pp * n];
+                double* Qq = &QT[(size_t)q * n];
+                for (int k = 0; k < n; ++k) {
+                    const double g = Qp[k], h = Qq[k];
+                    Qp[k] = c * g - sn * h;
+                    Qq[k] = sn * g + c * h;
                 }
             }
     }
     lam.resize(n);
     for (int i = 0; i < n; ++i) lam[i] = C[(size_t)i * n + i];
     // V = L^-T Q (back substitution per column)
-    V = Q;
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < n; ++a) V[(size_t)i * n + a] = QT[(size_t)a * n + i];
     for (int c = 0; c < n; ++c)
         for (int i = n - 1; i >= 0; --i) {
             double v = V[(size_t)i * n + c];

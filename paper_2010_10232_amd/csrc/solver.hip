@@ -640,8 +640,9 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
     const cx<T>* dinv = pick<T>(lv.Dinv64, lv.Dinv32).template as<cx<T>>();
     const bool learned = (cnn != nullptr && l == 0);
     if (learned) {
-        // learned smoother from a zero guess: x = omega D^-1 b + ||b|| C(b/||b||, c),
-        // then further sweeps x += omega D^-1 r + ||r|| C(r/||r||, c), r = b - M_beta x
+        // learned smoother from a zero guess: x = omega D^-1 b + rms(b) C(b/rms(b), c),
+        // then further sweeps x += omega D^-1 r + rms(r) C(r/rms(r), c), r = b - M_beta x,
+        // rms(r) = ||r|| / sqrt(N)
         cnn->step<T>(lv.n2, lv.n1, b, feat.as<float>(), dinv, (T)lv.omega, x, 0, s);
         for (int i = 1; i < o.nu_pre; ++i) {
             op<T>(l, MODE_RESID, true, x, b, r, s);

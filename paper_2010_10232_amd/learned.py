@@ -1,0 +1,92 @@
+"""Training of the learned fine-level smoother on the GPU.
+
+Training data are the inputs of the finest-level V-cycle captured while the
+plain method (damped Jacobi smoother) solves a set of training problems:
+seeded Gaussian-random-field wave numbers k = kbar (1 + 0.3 g) with kbar drawn
+so that k spans [100, 500], on grids that resolve k_max with k_max h = 0.625
+(at most 640 elements per side).  The network sees k^2 h^2 as an input, so it
+is applied unchanged on grids of other sizes and resolutions.  The network (forward, backward and Adam) runs in the
+library; this module only schedules problems, samples and steps.
+"""
+import math
+import time
+
+import numpy as np
+
+from . import binding as B
+from . import workloads as W
+
+
+def training_specs(n_problems=4, p=4, kh_max=0.625, kbar_range=(100.0 / 0.7, 500.0 / 1.3), seed=7,
+                   max_n_el=640):
+    """Seeded training problems: (p, n_el, k_elem, source) with k in [100, 500].
+
+    Each grid resolves its largest wave number at k_max h = kh_max; n_el is
+    capped at max_n_el, the kbar draw shrunk accordingly.
+    """
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(n_problems):
+        kbar = float(rng.uniform(*kbar_range))
+        n_el = int(math.ceil(1.3 * kbar / kh_max))
+        if n_el > max_n_el:
+            n_el = max_n_el
+            kbar = kh_max * n_el / 1.3
+        ke = W.grf_k(n_el, kbar=kbar, seed=int(rng.integers(1 << 30)))
+        x0 = tuple(float(v) for v in rng.uniform(0.2, 0.8, size=2))
+        specs.append(dict(p=p, n_el=n_el, kbar=kbar, k_elem=ke, x0=x0))
+    return specs
+
+
+def capture(specs, per_problem=24, maxit=60, solver_opts=None, log=None):
+    """Plain solves of the training problems; returns [(solver, samples)] with
+    samples a device tensor [n, N] of finest-level V-cycle inputs."""
+    import torch
+    out = []
+    for s in specs:
+        prob = B.Problem(2, s["p"], s["n_el"], k=1.0, k_elem=s["k_elem"])
+        sol = B.Solver(prob, maxit=maxit, **(solver_opts or {}))
+        f = prob.point_source(s["x0"])
+        buf = torch.zeros((per_problem, prob.N), dtype=torch.complex128, device="cuda")
+        sol.capture(buf, per_problem)
+        sol.solve(f)
+        sol.capture(None, 0)
+        n = sol.captured()
+        out.append((prob, sol, buf[:n]))
+        if log:
+            log(f"[train] captured {n} samples on a {s['n_el']}^2 p={s['p']} field, kbar {s['kbar']:.0f}")
+    return out
+
+
+def train(net, data, steps=800, lr=3e-4, log=None):
+    """Adam steps cycling over (problem, sample); returns (mean loss before, after, seconds)."""
+    import torch
+    pairs = [(sol, smp[i]) for _, sol, smp in data for i in range(smp.shape[0])]
+    order = np.random.default_rng(0).permutation(len(pairs))
+
+    def mean_loss():
+        return float(np.mean([net.loss_grad(sol, r)[0] for sol, r in pairs]))
+
+    l0 = mean_loss()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        sol, r = pairs[order[it % len(pairs)]]
+        net.train_step(sol, r, lr)
+        if log and (it + 1) % 200 == 0:
+            log(f"[train] step {it + 1}/{steps}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return l0, mean_loss(), dt
+
+
+def trained_smoother(specs=None, steps=800, lr=3e-4, init_scale=0.05, seed=1, log=None, **capture_kw):
+    """A network trained from scratch on the given (default: seeded) training problems."""
+    net = B.Cnn(seed=seed)
+    net.set_params(net.get_params() * (init_scale / 0.5))
+    data = capture(specs or training_specs(), log=log, **capture_kw)
+    l0, l1, dt = train(net, data, steps=steps, lr=lr, log=log)
+    info = dict(loss_before=l0, loss_after=l1, train_s=dt, steps=steps,
+                samples=int(sum(d[2].shape[0] for d in data)), problems=len(data))
+    del data
+    return net, info
