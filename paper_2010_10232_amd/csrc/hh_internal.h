@@ -212,8 +212,10 @@ void launch_cast_d2f(long long N, const cx<double>* x, cx<float>* y, hipStream_t
 void launch_cast_f2d(long long N, const cx<float>* x, cx<double>* y, hipStream_t s);
 template <class TM, class TV>
 void launch_gemv(int n, const TM* A, const cx<TV>* x, cx<TV>* y, hipStream_t s);
+// y = A x for a real n x n matrix with leading dimension ld (even ld: 16-byte rows)
+void launch_gemv_real(int n, long long ld, const double* A, const cx<double>* x, cx<double>* y, hipStream_t s);
 void launch_scatter(long long n, const long long* idx, const double* val, double* y, hipStream_t s);
-void launch_set_identity(int n, double* a, hipStream_t s);   // a: n x n zeros -> identity
+void launch_set_identity(int n, long long ld, double* a, hipStream_t s);   // a: n x n zeros -> identity
 // x = V-cycle(b) from level l0 through the coarsest level in one workgroup
 // (lds_bytes: dynamic LDS of the level vectors; tail_prepare allows that size)
 template <class T>

@@ -2,6 +2,8 @@
 // updates, dense products of the direct coarse solves, and the deterministic
 // reductions of the Arnoldi process.  The level-operator kernels are in
 // op_kernel.h.
+#include <type_traits>
+
 #include "hh_internal.h"
 
 namespace hh {
@@ -209,13 +211,13 @@ __device__ __forceinline__ void mac(const cx<TA>& a, const cx<TV>& x, TV& sr, TV
 }
 
 template <class TM, class TV>
-__global__ __launch_bounds__(256) void gemv_kernel(int n, const TM* __restrict__ A, const cx<TV>* __restrict__ x,
-                                                   cx<TV>* __restrict__ y) {
+__global__ __launch_bounds__(256) void gemv_kernel(int n, long long ld, const TM* __restrict__ A,
+                                                   const cx<TV>* __restrict__ x, cx<TV>* __restrict__ y) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + wave;
     if (row >= n) return;
     TV sr = 0, si = 0;
-    const TM* a = A + (size_t)row * n;
+    const TM* a = A + (size_t)row * ld;
     for (int j = lane; j < n; j += 64) mac(a[j], x[j], sr, si);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -224,9 +226,69 @@ __global__ __launch_bounds__(256) void gemv_kernel(int n, const TM* __restrict__
     }
     if (lane == 0) y[row] = {sr, si};
 }
+// Real FP64 matrix (leading dimension ld, even) times complex vector for
+// large n (the dense E^-1 of a variable-k deflation level): each wave streams
+// four rows at once with 16-byte loads (two columns per lane and step), so
+// every load of x feeds four rows; per row, lane-strided partial sums then a
+// butterfly (fixed order).
+constexpr int GEMV_RPW = 4;
+__global__ __launch_bounds__(256) void gemv4_kernel(int n, long long ld, const double* __restrict__ A,
+                                                    const cx<double>* __restrict__ x, cx<double>* __restrict__ y) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long r0 = ((long long)blockIdx.x * 4 + wave) * GEMV_RPW;
+    if (r0 >= n) return;
+    const double* a[GEMV_RPW];
+#pragma unroll
+    for (int q = 0; q < GEMV_RPW; ++q) a[q] = A + (size_t)min(r0 + q, (long long)n - 1) * ld;
+    double sr[GEMV_RPW], si[GEMV_RPW];
+#pragma unroll
+    for (int q = 0; q < GEMV_RPW; ++q) sr[q] = si[q] = 0.0;
+    const int n2 = n & ~1;   // columns handled in pairs; an odd last column separately
+#pragma unroll 2
+    for (int j = 2 * lane; j < n2; j += 128) {
+        const cx<double> x0 = x[j], x1 = x[j + 1];
+#pragma unroll
+        for (int q = 0; q < GEMV_RPW; ++q) {
+            const double2 v = *(const double2*)(a[q] + j);
+            sr[q] += v.x * x0.re + v.y * x1.re;
+            si[q] += v.x * x0.im + v.y * x1.im;
+        }
+    }
+    if ((n & 1) && lane == 0) {
+        const cx<double> xl = x[n - 1];
+#pragma unroll
+        for (int q = 0; q < GEMV_RPW; ++q) {
+            sr[q] += a[q][n - 1] * xl.re;
+            si[q] += a[q][n - 1] * xl.im;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < GEMV_RPW; ++q) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            sr[q] += __shfl_xor(sr[q], o, 64);
+            si[q] += __shfl_xor(si[q], o, 64);
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < GEMV_RPW; ++q)
+            if (r0 + q < n) y[r0 + q] = {sr[q], si[q]};
+    }
+}
+
 template <class TM, class TV>
 void launch_gemv(int n, const TM* A, const cx<TV>* x, cx<TV>* y, hipStream_t s) {
-    hipLaunchKernelGGL((gemv_kernel<TM, TV>), dim3((n + 3) / 4), dim3(256), 0, s, n, A, x, y);
+    hipLaunchKernelGGL((gemv_kernel<TM, TV>), dim3((n + 3) / 4), dim3(256), 0, s, n, (long long)n, A, x, y);
+}
+void launch_gemv_real(int n, long long ld, const double* A, const cx<double>* x, cx<double>* y, hipStream_t s) {
+    if (n >= 1024 && ld % 2 == 0) {
+        const long long rows_per_block = 4LL * GEMV_RPW;
+        hipLaunchKernelGGL(gemv4_kernel, dim3((unsigned)((n + rows_per_block - 1) / rows_per_block)), dim3(256), 0,
+                           s, n, ld, A, x, y);
+    } else {
+        hipLaunchKernelGGL((gemv_kernel<double, double>), dim3((n + 3) / 4), dim3(256), 0, s, n, ld, A, x, y);
+    }
 }
 template void launch_gemv<double, double>(int, const double*, const cx<double>*, cx<double>*, hipStream_t);
 template void launch_gemv<cx<double>, double>(int, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t);
@@ -512,12 +574,12 @@ __global__ void scatter_kernel(long long n, const long long* __restrict__ idx, c
 void launch_scatter(long long n, const long long* idx, const double* val, double* y, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(scatter_kernel, dim3(grid1d(n, 256)), dim3(256), 0, s, n, idx, val, y);
 }
-__global__ void set_identity_kernel(long long n, double* __restrict__ a) {
+__global__ void set_identity_kernel(long long n, long long ld, double* __restrict__ a) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i * n + i] = 1.0;
+    if (i < n) a[i * ld + i] = 1.0;
 }
-void launch_set_identity(int n, double* a, hipStream_t s) {
-    hipLaunchKernelGGL(set_identity_kernel, dim3(grid1d(n, 256)), dim3(256), 0, s, (long long)n, a);
+void launch_set_identity(int n, long long ld, double* a, hipStream_t s) {
+    hipLaunchKernelGGL(set_identity_kernel, dim3(grid1d(n, 256)), dim3(256), 0, s, (long long)n, ld, a);
 }
 
 // --------------------------------------------------------------------------

@@ -83,6 +83,7 @@ struct SolverImpl {
     int tail_lds = 0, tail_lds32 = 0;   // dynamic LDS bytes (FP64 / FP32 tail)
     DevBuf tail64, tail32;              // TailDesc<double>, TailDesc<float>
     int nL = 0, nZ = 0;
+    long long ldZ = 0;       // leading dimension of Einv (even, >= nZ)
     // outer FGMRES
     int m_outer = 0;
     DevBuf V, Z, kstate, r, scratch;

@@ -457,6 +457,7 @@ void SolverImpl::setup(hipStream_t s) {
         LevelDev& lz = *lev[Lz];
         nZ = (int)lz.N;
         HH_REQUIRE(nZ <= 65536, "direct deflation level too large (at most 65536 unknowns)");
+        ldZ = (nZ + 1) & ~1LL;   // even leading dimension: 16-byte aligned rows
         std::vector<long long> cidx;
         std::vector<double> cval;
         std::vector<std::pair<long long, double>> row;
@@ -471,11 +472,11 @@ void SolverImpl::setup(hipStream_t s) {
                 row.emplace_back(J, kv - mv);
             });
             for (const auto& e : row) {
-                cidx.push_back(I * nZ + e.first);
+                cidx.push_back(I * ldZ + e.first);
                 cval.push_back(e.second);
             }
         }
-        const size_t nn = (size_t)nZ * nZ;
+        const size_t nn = (size_t)ldZ * nZ;
         Einv.alloc(nn * sizeof(double));
         {
             DevBuf di, dv;
@@ -494,9 +495,11 @@ void SolverImpl::setup(hipStream_t s) {
             DevBuf ipiv, info;
             ipiv.alloc((size_t)nZ * sizeof(rocblas_int));
             info.alloc(sizeof(rocblas_int));
-            st = rocsolver_dgetrf(h, nZ, nZ, Einv.as<double>(), nZ, ipiv.as<rocblas_int>(), info.as<rocblas_int>());
+            st = rocsolver_dgetrf(h, nZ, nZ, Einv.as<double>(), (rocblas_int)ldZ, ipiv.as<rocblas_int>(),
+                                  info.as<rocblas_int>());
             if (st == rocblas_status_success)
-                st = rocsolver_dgetri(h, nZ, Einv.as<double>(), nZ, ipiv.as<rocblas_int>(), info.as<rocblas_int>());
+                st = rocsolver_dgetri(h, nZ, Einv.as<double>(), (rocblas_int)ldZ, ipiv.as<rocblas_int>(),
+                                      info.as<rocblas_int>());
             HH_HIP(hipStreamSynchronize(s));
             rocblas_int hinfo = 0;
             HH_HIP(hipMemcpy(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost));
@@ -508,15 +511,15 @@ void SolverImpl::setup(hipStream_t s) {
             info.alloc(sizeof(int64_t));
             X.alloc(nn * sizeof(double));
             HH_HIP(hipMemsetAsync(X.p, 0, nn * sizeof(double), s));
-            launch_set_identity(nZ, X.as<double>(), s);
-            st = rocsolver_dgetrf_64(h, nZ, nZ, Einv.as<double>(), nZ, ipiv.as<int64_t>(), info.as<int64_t>());
+            launch_set_identity(nZ, ldZ, X.as<double>(), s);
+            st = rocsolver_dgetrf_64(h, nZ, nZ, Einv.as<double>(), ldZ, ipiv.as<int64_t>(), info.as<int64_t>());
             HH_HIP(hipStreamSynchronize(s));
             int64_t hinfo = 0;
             HH_HIP(hipMemcpy(&hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost));
             singular = hinfo;
             if (st == rocblas_status_success && hinfo == 0)
-                st = rocsolver_dgetrs_64(h, rocblas_operation_none, nZ, nZ, Einv.as<double>(), nZ, ipiv.as<int64_t>(),
-                                         X.as<double>(), nZ);
+                st = rocsolver_dgetrs_64(h, rocblas_operation_none, nZ, nZ, Einv.as<double>(), ldZ,
+                                         ipiv.as<int64_t>(), X.as<double>(), ldZ);
             HH_HIP(hipStreamSynchronize(s));
             std::swap(Einv.p, X.p);
             std::swap(Einv.bytes, X.bytes);
@@ -756,7 +759,7 @@ void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStre
             // c, e, 1/D and both eigenvector matrices once
             tstop(2, 40.0 * nZ + 8.0 * ((double)lz.n1 * lz.n1 + (double)lz.n2 * lz.n2), s);
         } else {
-            launch_gemv<double, double>(nZ, Einv.as<double>(), c, e, s);
+            launch_gemv_real(nZ, ldZ, Einv.as<double>(), c, e, s);
             tstop(2, 8.0 * nZ * (double)nZ + 32.0 * nZ, s);
         }
         return;
