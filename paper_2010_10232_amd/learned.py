@@ -39,12 +39,14 @@ def training_specs(n_problems=4, p=4, kh_max=0.625, kbar_range=(100.0 / 0.7, 500
 
 
 def capture(specs, per_problem=24, maxit=60, solver_opts=None, log=None):
-    """Plain solves of the training problems; returns [(solver, samples)] with
-    samples a device tensor [n, N] of finest-level V-cycle inputs."""
+    """Plain solves of the training problems; returns [(problem, solver, samples)]
+    with samples a device tensor [n, N] of finest-level V-cycle inputs.  A spec
+    holds p, n_el, x0 and either k_elem (per element) or k (constant); dim
+    defaults to 2."""
     import torch
     out = []
     for s in specs:
-        prob = B.Problem(2, s["p"], s["n_el"], k=1.0, k_elem=s["k_elem"])
+        prob = B.Problem(s.get("dim", 2), s["p"], s["n_el"], k=s.get("k", 1.0), k_elem=s.get("k_elem"))
         sol = B.Solver(prob, maxit=maxit, **(solver_opts or {}))
         f = prob.point_source(s["x0"])
         buf = torch.zeros((per_problem, prob.N), dtype=torch.complex128, device="cuda")
@@ -54,12 +56,13 @@ def capture(specs, per_problem=24, maxit=60, solver_opts=None, log=None):
         n = sol.captured()
         out.append((prob, sol, buf[:n]))
         if log:
-            log(f"[train] captured {n} samples on a {s['n_el']}^2 p={s['p']} field, kbar {s['kbar']:.0f}")
+            log(f"[train] captured {n} samples on a {s['n_el']}-element p={s['p']} problem")
     return out
 
 
 def train(net, data, steps=800, lr=3e-4, log=None):
-    """Adam steps cycling over (problem, sample); returns (mean loss before, after, seconds)."""
+    """Adam steps cycling over (problem, sample) in a seeded order; returns (mean
+    loss before, mean loss after, seconds)."""
     import torch
     pairs = [(sol, smp[i]) for _, sol, smp in data for i in range(smp.shape[0])]
     order = np.random.default_rng(0).permutation(len(pairs))

@@ -14,6 +14,8 @@ kernel needs new counters).
     python -m paper_2010_10232_amd.profiling --fetch F.csv --write W.csv \\
         --kernel arnoldi_reg_kernel --copy-mib 256 --workload NAME \\
         --command "..." --out profiles/<kernel>_<workload>_traffic.md
+
+With --stats it turns a rocprofv3 --stats kernel summary into a markdown table.
 """
 import argparse
 import csv
@@ -113,16 +115,44 @@ def read_summary(path):
     return float(vals["traffic_bytes_per_launch"]), vals.get("kernel_regex")
 
 
+def write_stats(stats_csv, title, command, out, top=18):
+    """Markdown table of a rocprofv3 --stats kernel summary (most device time first)."""
+    with open(stats_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    lines = [f"# {title}", "", "Command (repository root on the GPU host):", "", "```", command, "```", "",
+             "| kernel | calls | total ms | avg us | min us | max us | % of GPU time |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"].split("(")[0].replace("void ", "")
+        if len(name) > 72:
+            name = name[:72] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    rest = rows[top:]
+    if rest:
+        lines.append(f"| ({len(rest)} more kernels) | {sum(int(r['Calls']) for r in rest)} | "
+                     f"{sum(float(r['TotalDurationNs']) for r in rest) / 1e6:.3f} | | | | "
+                     f"{sum(float(r['Percentage']) for r in rest):.2f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--kernel", required=True, help="regular expression matching the kernel name")
-    ap.add_argument("--copy-mib", type=float, required=True)
-    ap.add_argument("--workload", required=True)
+    ap.add_argument("--stats", help="rocprofv3 kernel_stats.csv: write a kernel table instead")
+    ap.add_argument("--title")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--kernel", help="regular expression matching the kernel name")
+    ap.add_argument("--copy-mib", type=float)
+    ap.add_argument("--workload")
     ap.add_argument("--command", required=True)
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
+    if a.stats:
+        write_stats(a.stats, a.title or "Kernel statistics", a.command, a.out)
+        return
     s = summarize(a.fetch, a.write, a.kernel, a.copy_mib)
     write_summary(a.out, a.kernel, a.workload, a.command, s)
     print(s)
