@@ -177,6 +177,11 @@ struct TailLevel {
     cx<T>* r;
     cx<T>* t;
     Transfer tr;                  // to the next-coarser level
+    // LDS byte offsets of this level's coefficient tables (copied at kernel
+    // start): bands Kx, Mx [n1][2px+1], Ky, My [n2][2py+1], and the transfer
+    // tables to the next-coarser level (-1 at the coarsest level)
+    int o_kx, o_mx, o_ky, o_my;
+    int o_prow0x, o_prowx, o_prow0y, o_prowy, o_pcol0x, o_pcolx, o_pcol0y, o_pcoly;
 };
 template <class T>
 struct TailDesc {

@@ -456,6 +456,34 @@ __device__ void tail_op(const TailLevel<T>& L, const TailDesc<T>& D, int mode, c
     __syncthreads();
 }
 
+template <class E>
+__device__ __forceinline__ void tail_stage(unsigned char* smem, int off, const E* src, long long n) {
+    if (off < 0) return;
+    E* dst = (E*)(smem + off);
+    for (long long i = threadIdx.x; i < n; i += TAIL_TB) dst[i] = src[i];
+}
+
+// A level's descriptor with its coefficient pointers redirected to the LDS copies.
+template <class T>
+__device__ __forceinline__ TailLevel<T> tail_level(const TailDesc<T>& D, int l, unsigned char* smem) {
+    TailLevel<T> v = D.lv[l];
+    v.Kx = (const double*)(smem + v.o_kx);
+    v.Mx = (const double*)(smem + v.o_mx);
+    v.Ky = (const double*)(smem + v.o_ky);
+    v.My = (const double*)(smem + v.o_my);
+    if (v.o_prow0x >= 0) {
+        v.tr.prow0x = (const int*)(smem + v.o_prow0x);
+        v.tr.prowx = (const double*)(smem + v.o_prowx);
+        v.tr.prow0y = (const int*)(smem + v.o_prow0y);
+        v.tr.prowy = (const double*)(smem + v.o_prowy);
+        v.tr.pcol0x = (const int*)(smem + v.o_pcol0x);
+        v.tr.pcolx = (const double*)(smem + v.o_pcolx);
+        v.tr.pcol0y = (const int*)(smem + v.o_pcol0y);
+        v.tr.pcoly = (const double*)(smem + v.o_pcoly);
+    }
+    return v;
+}
+
 template <class T>
 __global__ __launch_bounds__(TAIL_TB) void vcycle_tail_kernel(const TailDesc<T>* __restrict__ Dp, int l0,
                                                               const cx<T>* __restrict__ b0, cx<T>* __restrict__ x0) {
@@ -469,11 +497,29 @@ __global__ __launch_bounds__(TAIL_TB) void vcycle_tail_kernel(const TailDesc<T>*
         const long long N0 = (long long)D.lv[l0].n1 * D.lv[l0].n2;
         cx<T>* b = vb(l0);
         for (long long I = threadIdx.x; I < N0; I += TAIL_TB) b[I] = b0[I];
+        // coefficient tables of the levels this cycle visits
+        for (int l = l0; l < L; ++l) {
+            const TailLevel<T>& g = D.lv[l];
+            const int bx = 2 * g.px + 1, by = 2 * g.py + 1;
+            tail_stage<double>(tail_smem, g.o_kx, g.Kx, (long long)g.n1 * bx);
+            tail_stage<double>(tail_smem, g.o_mx, g.Mx, (long long)g.n1 * bx);
+            tail_stage<double>(tail_smem, g.o_ky, g.Ky, (long long)g.n2 * by);
+            tail_stage<double>(tail_smem, g.o_my, g.My, (long long)g.n2 * by);
+            const Transfer& t = g.tr;
+            tail_stage<int>(tail_smem, g.o_prow0x, t.prow0x, t.nf1);
+            tail_stage<double>(tail_smem, g.o_prowx, t.prowx, (long long)t.nf1 * t.pw1);
+            tail_stage<int>(tail_smem, g.o_prow0y, t.prow0y, t.nf2);
+            tail_stage<double>(tail_smem, g.o_prowy, t.prowy, (long long)t.nf2 * t.pw2);
+            tail_stage<int>(tail_smem, g.o_pcol0x, t.pcol0x, t.nc1);
+            tail_stage<double>(tail_smem, g.o_pcolx, t.pcolx, (long long)t.nc1 * t.rw1);
+            tail_stage<int>(tail_smem, g.o_pcol0y, t.pcol0y, t.nc2);
+            tail_stage<double>(tail_smem, g.o_pcoly, t.pcoly, (long long)t.nc2 * t.rw2);
+        }
         __syncthreads();
     }
     // descent
     for (int l = l0; l < L; ++l) {
-        const TailLevel<T>& lv = D.lv[l];
+        const TailLevel<T> lv = tail_level<T>(D, l, tail_smem);
         const long long N = (long long)lv.n1 * lv.n2;
         const cx<T>* b = vb(l);
         cx<T>* x = vx(l);
@@ -521,7 +567,7 @@ __global__ __launch_bounds__(TAIL_TB) void vcycle_tail_kernel(const TailDesc<T>*
     }
     // ascent
     for (int l = L - 1; l >= l0; --l) {
-        const TailLevel<T>& lv = D.lv[l];
+        const TailLevel<T> lv = tail_level<T>(D, l, tail_smem);
         const long long N = (long long)lv.n1 * lv.n2;
         const cx<T>* b = vb(l);
         cx<T>* x = vx(l);

@@ -349,9 +349,21 @@ void SolverImpl::setup(hipStream_t s) {
         const long long budget = std::min<long long>(lds_max, 160 * 1024) - 1024;
         tail_start = 1 << 30;
         tail_lds = 0;
+        // LDS of one level in the tail: its three vectors and (above the coarsest
+        // level) its bands and transfer tables, each region 16-byte aligned
+        auto al16 = [](long long b) { return (b + 15) & ~15LL; };
+        auto coef_bytes = [&](int m) -> long long {
+            if (m >= L) return 0;
+            const LevelDev& v = *lev[m];
+            const int bx = 2 * p + 1, by = is2d ? 2 * p + 1 : 1;
+            const Transfer& t = v.tr;
+            return 2 * al16(8LL * v.n1 * bx) + 2 * al16(8LL * v.n2 * by) + al16(4LL * t.nf1) +
+                   al16(8LL * t.nf1 * t.pw1) + al16(4LL * t.nf2) + al16(8LL * t.nf2 * t.pw2) + al16(4LL * t.nc1) +
+                   al16(8LL * t.nc1 * t.rw1) + al16(4LL * t.nc2) + al16(8LL * t.nc2 * t.rw2);
+        };
         for (int l = 1; l < L && L < kTailLevels; ++l) {
             long long bytes = 0;
-            for (int m = l; m <= L; ++m) bytes += 3 * lev[m]->N * (long long)sizeof(cx<double>);
+            for (int m = l; m <= L; ++m) bytes += 3 * lev[m]->N * (long long)sizeof(cx<double>) + coef_bytes(m);
             if (bytes <= budget) {
                 tail_start = l;
                 tail_lds = (int)bytes;
@@ -372,11 +384,37 @@ void SolverImpl::setup(hipStream_t s) {
                 d.lds_l0 = tail_start;
                 int off = 0;
                 for (int l = tail_start; l <= L; ++l) {
-                    const int vb = (int)(lev[l]->N * (long long)sizeof(cx<T>));
+                    const int vb = (int)al16(lev[l]->N * (long long)sizeof(cx<T>));
                     d.offb[l] = off;
                     d.offx[l] = off + vb;
                     d.offt[l] = off + 2 * vb;
                     off += 3 * vb;
+                    auto& t = d.lv[l];
+                    t.o_kx = t.o_mx = t.o_ky = t.o_my = -1;
+                    t.o_prow0x = t.o_prowx = t.o_prow0y = t.o_prowy = -1;
+                    t.o_pcol0x = t.o_pcolx = t.o_pcol0y = t.o_pcoly = -1;
+                    if (l < L) {
+                        const LevelDev& v = *lev[l];
+                        const int bx = 2 * p + 1, by = is2d ? 2 * p + 1 : 1;
+                        const Transfer& tr = v.tr;
+                        auto take = [&](long long bytes) {
+                            const int o = off;
+                            off += (int)al16(bytes);
+                            return o;
+                        };
+                        t.o_kx = take(8LL * v.n1 * bx);
+                        t.o_mx = take(8LL * v.n1 * bx);
+                        t.o_ky = take(8LL * v.n2 * by);
+                        t.o_my = take(8LL * v.n2 * by);
+                        t.o_prow0x = take(4LL * tr.nf1);
+                        t.o_prowx = take(8LL * tr.nf1 * tr.pw1);
+                        t.o_prow0y = take(4LL * tr.nf2);
+                        t.o_prowy = take(8LL * tr.nf2 * tr.pw2);
+                        t.o_pcol0x = take(4LL * tr.nc1);
+                        t.o_pcolx = take(8LL * tr.nc1 * tr.rw1);
+                        t.o_pcol0y = take(4LL * tr.nc2);
+                        t.o_pcoly = take(8LL * tr.nc2 * tr.rw2);
+                    }
                 }
                 d.lds_bytes = off;
                 for (int l = tail_start; l <= L; ++l) {
@@ -411,6 +449,7 @@ void SolverImpl::setup(hipStream_t s) {
                 HH_REQUIRE(lev[l]->kind == KIND_SEP || lev[l]->kind == KIND_STENCIL, "tail level kind");
             upload(tail64, d64);
             upload(tail32, d32);
+            tail_lds = d64[0].lds_bytes;
             tail_lds32 = d32[0].lds_bytes;
             tail_prepare<double>(tail_lds);
             tail_prepare<float>(tail_lds32);
