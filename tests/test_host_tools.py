@@ -1,0 +1,113 @@
+"""Host-side tools without a GPU: profiling summaries, training-problem
+recipes, and the bench's argument contract."""
+import csv
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from paper_2010_10232_amd import learned  # noqa: E402
+from paper_2010_10232_amd import profiling  # noqa: E402
+
+
+def _write_counters(path, counter, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, v in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_traffic_summary_calibration_and_hash(tmp_path):
+    # copy of 256 MiB reads 0.5x on FETCH_SIZE and 1x on WRITE_SIZE; the kernel
+    # reads 1000 KiB and writes 300 KiB per launch on average
+    f = tmp_path / "f.csv"
+    w = tmp_path / "w.csv"
+    _write_counters(f, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 131072.0), ("__amd_rocclr_copyBuffer", 3.0),
+                                      ("void hh::arnoldi_reg_kernel<4>(...)", 900.0),
+                                      ("void hh::arnoldi_reg_kernel<4>(...)", 1100.0),
+                                      ("void hh::op_kernel<3, 3, 0, 1, double>(...)", 7.0)])
+    _write_counters(w, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 262144.0),
+                                      ("void hh::arnoldi_reg_kernel<4>(...)", 300.0)])
+    s = profiling.summarize(str(f), str(w), "arnoldi_reg_kernel", 256)
+    assert s["n_fetch"] == 2 and s["n_write"] == 1
+    assert abs(s["f_fetch"] - 0.5) < 1e-12 and abs(s["f_write"] - 1.0) < 1e-12
+    assert abs(s["traffic"] - 1024.0 * (1000.0 / 0.5 + 300.0)) < 1e-6
+    out = tmp_path / "arnoldi_x_traffic.md"
+    profiling.write_summary(str(out), "arnoldi_reg_kernel", "x", "cmd", s)
+    got = profiling.read_summary(str(out))
+    assert got is not None and abs(got[0] - s["traffic"]) < 1.0 and got[1] == "arnoldi_reg_kernel"
+    # a summary taken from other sources is not reported
+    text = out.read_text().replace(profiling.source_hash(), "0" * 64)
+    out.write_text(text)
+    assert profiling.read_summary(str(out)) is None
+    assert profiling.read_summary(str(tmp_path / "missing.md")) is None
+
+
+def test_kernel_stats_table(tmp_path):
+    p = tmp_path / "stats.csv"
+    with open(p, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage",
+                                           "MinNs", "MaxNs", "StdDev"])
+        w.writeheader()
+        for i in range(25):
+            w.writerow({"Name": f"void hh::k{i}(int)", "Calls": 2, "TotalDurationNs": 2000.0 * (25 - i),
+                        "AverageNs": 1000.0 * (25 - i), "Percentage": 4.0, "MinNs": 1.0, "MaxNs": 2.0,
+                        "StdDev": 0.0})
+    out = tmp_path / "t.md"
+    profiling.write_stats(str(p), "T", "cmd", str(out), top=18)
+    lines = out.read_text().splitlines()
+    rows = [ln for ln in lines if ln.startswith("| `")]
+    assert len(rows) == 18 and rows[0].startswith("| `hh::k0`")
+    assert any(ln.startswith("| (7 more kernels) | 14 |") for ln in lines)
+
+
+def test_training_specs_seeded_and_in_range():
+    a = learned.training_specs(n_problems=4, seed=7)
+    b = learned.training_specs(n_problems=4, seed=7)
+    assert [s["n_el"] for s in a] == [s["n_el"] for s in b]
+    for s, t in zip(a, b):
+        assert np.array_equal(s["k_elem"], t["k_elem"]) and s["x0"] == t["x0"]
+        k = s["k_elem"]
+        assert k.shape == (s["n_el"], s["n_el"])
+        # k = kbar (1 + 0.3 g), g clipped to [-1, 1]; kbar within the draw range
+        assert k.min() >= 0.7 * 100.0 / 0.7 - 1e-9 and k.max() <= 1.3 * 500.0 / 1.3 + 1e-9
+        assert s["n_el"] <= 640
+        # k_max h stays at or below the target resolution
+        assert k.max() / s["n_el"] <= 0.625 + 1e-12
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+def test_learned_specs_never_the_test_problem():
+    bench = _bench_module()
+    for name in ("mp2a_k100_p3_160", "grf_k300_p4_960", "wedge_k150_p3_480", "mp1b_k50_p2_80"):
+        w = bench.WORKLOADS[name]
+        specs = bench.learned_specs(w)
+        again = bench.learned_specs(w)
+        assert len(specs) == 2
+        for s, t in zip(specs, again):
+            assert s["x0"] == t["x0"] and s["n_el"] == w["n_el"] and s["p"] == w["p"]
+            assert len(s["x0"]) == w["dim"]
+            if "k_elem" in s:
+                assert np.array_equal(s["k_elem"], t["k_elem"])
+                assert not np.array_equal(s["k_elem"], bench.k_field(w))
+            else:
+                assert s["k"] == w["k"] and s["x0"] != tuple(w["x0"])
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout.strip() == ""
