@@ -83,6 +83,10 @@ typedef struct {
                                 in hh_solve_info): 0 none (default), 1 finest-level operator
                                 (stencil) kernels, 2 exact E^-1 solve of the direct
                                 deflation level, 3 outer Arnoldi MGS kernels */
+    int autotune;            /* 1 (default): at setup, time the level-operator kernel of
+                                every level (FP64 and FP32) with strip heights 4..64 rows
+                                and keep the fastest; 0: a fixed rule (the tallest strip
+                                that still gives 2048 waves).  Results do not depend on it. */
 } hh_solver_opts;
 
 typedef struct {
@@ -106,6 +110,7 @@ typedef struct {
     double gersh;            /* Gershgorin bound g_l of D^-1 M_beta,l */
     int n_levels;            /* multigrid levels (finest = 0) */
     int defl_direct_level;   /* L_z: deflation level solved directly (0: no deflation) */
+    int op_rows[2];          /* strip height (rows) of the level-operator kernel, FP64 / FP32 */
 } hh_level_stats;
 
 /* Debug / parity operators of hh_apply. */

@@ -37,7 +37,8 @@ class SolverOpts(ctypes.Structure):
                 ("mg_min_elems", ctypes.c_int), ("coarse_damping", ctypes.c_int),
                 ("defl_mode", ctypes.c_int), ("defl_direct_max", ctypes.c_int),
                 ("defl_inner_its", ctypes.c_int * 8), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
-                ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("time_kernels", ctypes.c_int)]
+                ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("time_kernels", ctypes.c_int),
+                ("autotune", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -54,7 +55,7 @@ class SolveInfo(ctypes.Structure):
 class LevelStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 2), ("n_el", ctypes.c_int * 2), ("N", ctypes.c_longlong),
                 ("omega", ctypes.c_double), ("gersh", ctypes.c_double), ("n_levels", ctypes.c_int),
-                ("defl_direct_level", ctypes.c_int)]
+                ("defl_direct_level", ctypes.c_int), ("op_rows", ctypes.c_int * 2)]
 
 
 _lib = None
@@ -214,7 +215,7 @@ class Solver:
         _check(load().hh_level_info(self._h, int(level), ctypes.byref(st)))
         return {"n": (st.n[0], st.n[1]), "n_el": (st.n_el[0], st.n_el[1]), "N": st.N,
                 "omega": st.omega, "gersh": st.gersh, "n_levels": st.n_levels,
-                "defl_direct_level": st.defl_direct_level}
+                "defl_direct_level": st.defl_direct_level, "op_rows": (st.op_rows[0], st.op_rows[1])}
 
     def set_smoother(self, cnn):
         """cnn: a Cnn (learned finest-level smoother) or None (damped Jacobi)."""

@@ -51,6 +51,7 @@ void hh_default_opts(hh_solver_opts* o) {
     o->tol = 1e-7;
     o->precision = 0;
     o->time_kernels = 0;
+    o->autotune = 1;
 }
 
 const char* hh_last_error(void) { return g_err.c_str(); }
@@ -397,6 +398,8 @@ hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out) {
     out->gersh = lv.gersh;
     out->n_levels = S.L + 1;
     out->defl_direct_level = S.Lz;
+    out->op_rows[0] = lv.ty64;
+    out->op_rows[1] = lv.ty32;
     return HH_OK;
     HH_CATCH
 }

@@ -124,6 +124,7 @@ struct OpArgs {
     const double* Mey;     // [nel2][(py+1)^2]
     const T* S;            // KIND_STENCIL: [(2px+1)(2py+1)][n1*n2]
     T are, aim;            // alpha
+    int ty;                // strip height of the kernel (0: fixed rule)
     const cx<T>* x;
     const cx<T>* b;
     cx<T>* y;

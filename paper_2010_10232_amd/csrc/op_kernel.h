@@ -272,7 +272,9 @@ inline int op_rows_per_strip(int n1, int n2, int py) {
 
 template <int PX, int PY, int KIND, int MODE, class T>
 static void launch_op_t(const OpArgs<T>& a, hipStream_t s) {
-    const int ty = op_rows_per_strip(a.n1, a.n2, PY);
+    // a tuned strip height (a power of two in 4..64) or the fixed rule; 1D always 1
+    const int ty = (PY == 0) ? 1 : (a.ty >= 4 && a.ty <= 64 && (a.ty & (a.ty - 1)) == 0) ? a.ty
+                                                                                         : op_rows_per_strip(a.n1, a.n2, PY);
     dim3 grid((a.n1 + 63) / 64, (a.n2 + ty - 1) / ty);
     hipLaunchKernelGGL((op_kernel<PX, PY, KIND, MODE, T>), grid, dim3(64), 0, s, a, ty);
 }

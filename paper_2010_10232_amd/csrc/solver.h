@@ -24,6 +24,7 @@ struct LevelDev {
     long long N = 1;
     double omega = 0.8, gersh = 0.0;
     int kind = KIND_SEP;
+    int ty64 = 0, ty32 = 0;   // level-operator strip height (0: fixed rule), FP64 / FP32
     DevBuf Kx, Mx, Ky, My;
     DevBuf S64, S32;
     DevBuf k2, Mex, Mey;
@@ -104,6 +105,7 @@ struct SolverImpl {
     ~SolverImpl();
 
     void setup(hipStream_t s);
+    void autotune_ops(hipStream_t s);
     // building blocks
     template <class T>
     void op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s);

@@ -609,6 +609,7 @@ void SolverImpl::setup(hipStream_t s) {
     Z.alloc(v0 * m_outer);
     r.alloc(v0);
     fill_krylov(kd, kstate, m_outer);
+    if (o.autotune) autotune_ops(s);
     HH_HIP(hipHostMalloc((void**)&pin_d, 16 * sizeof(double), hipHostMallocDefault));
     HH_HIP(hipHostMalloc((void**)&pin_i, 64 * sizeof(int), hipHostMallocDefault));
     std::memset(pin_d, 0, 16 * sizeof(double));
@@ -616,6 +617,61 @@ void SolverImpl::setup(hipStream_t s) {
     for (hipEvent_t* e : {&ev_slot[0], &ev_slot[1], &ev_misc})
         HH_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     HH_HIP(hipStreamSynchronize(s));
+}
+
+// Strip-height autotuner of the level-operator kernel: on every level outside
+// the single-workgroup tail (and of at least 4096 unknowns), time the residual
+// kernel with 4, 8, ..., 64 rows per strip (one warm-up, then the best of three
+// launches per candidate, HIP events on the setup stream) in FP64 and FP32 and
+// keep the fastest.  Each output row sums its 2p+1 input rows in the same order
+// whatever the strip height, so the choice changes speed only.
+void SolverImpl::autotune_ops(hipStream_t s) {
+    if (prob->dim != 2) return;
+    hipEvent_t e0, e1;
+    HH_HIP(hipEventCreate(&e0));
+    HH_HIP(hipEventCreate(&e1));
+    auto tune = [&](int l, auto tag) {
+        using T = decltype(tag);
+        LevelDev& lv = *lev[l];
+        int& slot = (sizeof(T) == 8) ? lv.ty64 : lv.ty32;
+        cx<T>* x = pick<T>(lv.x64, lv.x32).template as<cx<T>>();
+        cx<T>* b = pick<T>(lv.b64, lv.b32).template as<cx<T>>();
+        cx<T>* y = pick<T>(lv.r64, lv.r32).template as<cx<T>>();
+        HH_HIP(hipMemsetAsync(x, 0, (size_t)lv.N * sizeof(cx<T>), s));
+        HH_HIP(hipMemsetAsync(b, 0, (size_t)lv.N * sizeof(cx<T>), s));
+        float best = 1e30f;
+        int best_ty = 0;
+        for (int ty = 64; ty >= 4; ty >>= 1) {
+            slot = ty;
+            op<T>(l, MODE_RESID, true, x, b, y, s);
+            float t_min = 1e30f;
+            for (int r = 0; r < 3; ++r) {
+                HH_HIP(hipEventRecord(e0, s));
+                op<T>(l, MODE_RESID, true, x, b, y, s);
+                HH_HIP(hipEventRecord(e1, s));
+                HH_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HH_HIP(hipEventElapsedTime(&ms, e0, e1));
+                t_min = std::min(t_min, ms);
+            }
+            if (t_min < best) {
+                best = t_min;
+                best_ty = ty;
+            }
+        }
+        slot = best_ty;
+    };
+    const int last = std::min(L - 1, tail_start - 1);
+    const bool timing = o.time_kernels;
+    o.time_kernels = 0;
+    for (int l = 0; l <= last; ++l) {
+        if (lev[l]->N < 4096) continue;
+        tune(l, double{});
+        tune(l, float{});
+    }
+    o.time_kernels = timing;
+    HH_HIP(hipEventDestroy(e0));
+    HH_HIP(hipEventDestroy(e1));
 }
 
 // ----------------------------------------------------------- hot path ----
@@ -652,6 +708,7 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
     a.y = y;
     a.dinv = pick<T>(lv.Dinv64, lv.Dinv32).template as<cx<T>>();
     a.omega = (T)lv.omega;
+    a.ty = sizeof(T) == 8 ? lv.ty64 : lv.ty32;
     const int py = prob->dim == 2 ? prob->p : 0;
     if (l == 0) tstart(1, s);
     launch_op<T>(lv.kind, mode, prob->p, py, a, s);

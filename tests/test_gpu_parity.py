@@ -243,3 +243,20 @@ def test_mixed_precision_within_1e6(name):
     e = rel(to_host(u), u_ref)
     _say(f"[case {name}] mixed iters {info['iters']} rel err {e:.2e}")
     assert e <= 1e-6, e
+
+
+def test_autotuned_strips_do_not_change_results():
+    """The strip height of the level-operator kernel changes speed only: a solve
+    with tuned heights and one with the fixed rule give identical iterates."""
+    from paper_2010_10232_amd import binding as B
+    c, op, osol, gp, gs = build("2d_tiles_p3")
+    tuned = gs.levels[0]["op_rows"]
+    _say(f"[autotune] tuned strip heights at level 0: {tuned}")
+    assert all(t in (4, 8, 16, 32, 64) for t in tuned)
+    fixed = B.Solver(gp, autotune=0, **c["opts"])
+    assert fixed.levels[0]["op_rows"] == (0, 0)
+    f = gp.point_source(c["x0"])
+    u1, i1 = gs.solve(f)
+    u2, i2 = fixed.solve(f)
+    assert i1["iters"] == i2["iters"]
+    assert np.array_equal(to_host(u1), to_host(u2))
