@@ -220,6 +220,13 @@ template <class TM, class TV>
 void launch_gemv(int n, const TM* A, const cx<TV>* x, cx<TV>* y, hipStream_t s);
 // y = A x for a real n x n matrix with leading dimension ld (even ld: 16-byte rows)
 void launch_gemv_real(int n, long long ld, const double* A, const cx<double>* x, cx<double>* y, hipStream_t s);
+// symmetric dense matrix as packed upper-triangle 128 x 128 tiles
+long long sym_tiles(int n);
+long long sym_packed_doubles(int n);
+void launch_sym_pack(int n, long long ld, const double* D, double* P, hipStream_t s);
+// y = P x (P packed symmetric; rowpart, colpart: sym_tiles(n) * 128 complex scratch each)
+void launch_symv(int n, const double* P, const cx<double>* x, cx<double>* rowpart, cx<double>* colpart,
+                 cx<double>* y, hipStream_t s);
 void launch_scatter(long long n, const long long* idx, const double* val, double* y, hipStream_t s);
 void launch_set_identity(int n, long long ld, double* a, hipStream_t s);   // a: n x n zeros -> identity
 // x = V-cycle(b) from level l0 through the coarsest level in one workgroup

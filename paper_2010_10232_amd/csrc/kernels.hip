@@ -610,6 +610,144 @@ template void launch_vcycle_tail<double>(const TailDesc<double>*, int, int, cons
                                          hipStream_t);
 template void launch_vcycle_tail<float>(const TailDesc<float>*, int, int, const cx<float>*, cx<float>*, hipStream_t);
 
+// --------------------------------------------------------------------------
+// Symmetric dense E^-1 (variable-k deflation level): only the upper triangle
+// is stored, as 128 x 128 tiles (I <= J) packed in row order of the tile grid,
+// each tile row-major and zero-padded past n.  A product reads every stored
+// entry once and uses it twice (row sums of tile (I, J) go to block I, column
+// sums to block J), halving the bytes of a full-matrix product.  Tile partial
+// sums go to per-tile slots and are added per block in a fixed order, so the
+// result is deterministic.
+// --------------------------------------------------------------------------
+constexpr int SYT = 128;
+__device__ __host__ inline long long sym_tile_index(long long I, long long J, long long nt) {
+    return I * nt - I * (I - 1) / 2 + (J - I);
+}
+long long sym_tiles(int n) {
+    const long long nt = (n + SYT - 1) / SYT;
+    return nt * (nt + 1) / 2;
+}
+long long sym_packed_doubles(int n) { return sym_tiles(n) * SYT * SYT; }
+
+__global__ __launch_bounds__(256) void sym_pack_kernel(int n, long long ld, const double* __restrict__ D,
+                                                       double* __restrict__ P) {
+    const int I = blockIdx.y, J = blockIdx.x;
+    if (J < I) return;
+    const long long nt = (n + SYT - 1) / SYT;
+    double* T = P + sym_tile_index(I, J, nt) * SYT * SYT;
+    for (int e = threadIdx.x; e < SYT * SYT; e += 256) {
+        const int rr = e / SYT, cc = e % SYT;
+        const long long r = (long long)I * SYT + rr, c = (long long)J * SYT + cc;
+        T[e] = (r < n && c < n) ? D[r * ld + c] : 0.0;
+    }
+}
+void launch_sym_pack(int n, long long ld, const double* D, double* P, hipStream_t s) {
+    const unsigned nt = (unsigned)((n + SYT - 1) / SYT);
+    hipLaunchKernelGGL(sym_pack_kernel, dim3(nt, nt), dim3(256), 0, s, n, ld, D, P);
+}
+
+// One workgroup per stored tile (I, J): wave w takes rows 32w .. 32w+31 of
+// the tile, lane l columns 2l, 2l+1 (16-byte loads).  Row sums: every lane
+// keeps its partial for each of the 32 rows, then one reduce-scatter over the
+// wave (five halving exchanges, lane l ends with row l/2, a last exchange adds
+// the lane pair) -- 32 shuffles per lane instead of a butterfly per row.
+// Column sums (off-diagonal tiles): per lane over its rows, then the four
+// waves in order.
+__global__ __launch_bounds__(256) void symv_tiles_kernel(int n, const double* __restrict__ P,
+                                                         const cx<double>* __restrict__ x,
+                                                         cx<double>* __restrict__ rowpart,
+                                                         cx<double>* __restrict__ colpart) {
+    const int I = blockIdx.y, J = blockIdx.x;
+    if (J < I) return;
+    __shared__ cx<double> xs[SYT];
+    __shared__ cx<double> us[SYT];
+    __shared__ double vs[4][SYT][2];
+    const long long nt = (n + SYT - 1) / SYT;
+    const long long tidx = sym_tile_index(I, J, nt);
+    const double* T = P + tidx * SYT * SYT;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x < SYT) {
+        const long long r = (long long)I * SYT + threadIdx.x;
+        xs[threadIdx.x] = r < n ? x[r] : cx<double>{0.0, 0.0};
+    }
+    const long long c0 = (long long)J * SYT + 2 * lane;
+    const cx<double> xj0 = c0 < n ? x[c0] : cx<double>{0.0, 0.0};
+    const cx<double> xj1 = c0 + 1 < n ? x[c0 + 1] : cx<double>{0.0, 0.0};
+    __syncthreads();
+    double vr0 = 0.0, vi0 = 0.0, vr1 = 0.0, vi1 = 0.0;
+    const bool off = (I != J);
+    double ur[32], ui[32];
+    const double* Tw = T + (size_t)(32 * w) * SYT + 2 * lane;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+        const double2 a = *(const double2*)(Tw + (size_t)q * SYT);
+        ur[q] = a.x * xj0.re + a.y * xj1.re;
+        ui[q] = a.x * xj0.im + a.y * xj1.im;
+        if (off) {
+            const cx<double> xi = xs[32 * w + q];
+            vr0 += a.x * xi.re;
+            vi0 += a.x * xi.im;
+            vr1 += a.y * xi.re;
+            vi1 += a.y * xi.im;
+        }
+    }
+#pragma unroll
+    for (int lvl = 0; lvl < 5; ++lvl) {
+        const int o = 32 >> lvl, cnt = 16 >> lvl;
+        const bool hi = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < cnt; ++i) {
+            const double sr = hi ? ur[i] : ur[i + cnt], si = hi ? ui[i] : ui[i + cnt];
+            const double kr = hi ? ur[i + cnt] : ur[i], ki = hi ? ui[i + cnt] : ui[i];
+            ur[i] = kr + __shfl_xor(sr, o, 64);
+            ui[i] = ki + __shfl_xor(si, o, 64);
+        }
+    }
+    ur[0] += __shfl_xor(ur[0], 1, 64);
+    ui[0] += __shfl_xor(ui[0], 1, 64);
+    if ((lane & 1) == 0) us[32 * w + (lane >> 1)] = {ur[0], ui[0]};
+    if (off) {
+        vs[w][2 * lane][0] = vr0;
+        vs[w][2 * lane][1] = vi0;
+        vs[w][2 * lane + 1][0] = vr1;
+        vs[w][2 * lane + 1][1] = vi1;
+    }
+    __syncthreads();
+    if (threadIdx.x < SYT) {
+        const int c = threadIdx.x;
+        rowpart[tidx * SYT + c] = us[c];
+        if (off)
+            colpart[tidx * SYT + c] = {vs[0][c][0] + vs[1][c][0] + vs[2][c][0] + vs[3][c][0],
+                                       vs[0][c][1] + vs[1][c][1] + vs[2][c][1] + vs[3][c][1]};
+    }
+}
+
+// y for block I: sum over J = 0 .. nt-1 of (J < I: column sums of tile (J, I),
+// J >= I: row sums of tile (I, J)), in that order.
+__global__ __launch_bounds__(SYT) void symv_reduce_kernel(int n, const cx<double>* __restrict__ rowpart,
+                                                          const cx<double>* __restrict__ colpart,
+                                                          cx<double>* __restrict__ y) {
+    const int I = blockIdx.x, r = threadIdx.x;
+    const long long gr = (long long)I * SYT + r;
+    if (gr >= n) return;
+    const long long nt = (n + SYT - 1) / SYT;
+    double sr = 0.0, si = 0.0;
+    for (long long J = 0; J < nt; ++J) {
+        const cx<double> v = (J < I) ? colpart[sym_tile_index(J, I, nt) * SYT + r]
+                                     : rowpart[sym_tile_index(I, J, nt) * SYT + r];
+        sr += v.re;
+        si += v.im;
+    }
+    y[gr] = {sr, si};
+}
+
+void launch_symv(int n, const double* P, const cx<double>* x, cx<double>* rowpart, cx<double>* colpart,
+                 cx<double>* y, hipStream_t s) {
+    const unsigned nt = (unsigned)((n + SYT - 1) / SYT);
+    hipLaunchKernelGGL(symv_tiles_kernel, dim3(nt, nt), dim3(256), 0, s, n, P, x, rowpart, colpart);
+    hipLaunchKernelGGL(symv_reduce_kernel, dim3(nt), dim3(SYT), 0, s, n, rowpart, colpart, y);
+}
+
 // Dense-matrix set-up helpers: y[idx[i]] = val[i] (distinct indices), and
 // the diagonal of an n x n zero matrix set to one.
 __global__ void scatter_kernel(long long n, const long long* __restrict__ idx, const double* __restrict__ val,

@@ -85,6 +85,9 @@ struct SolverImpl {
     DevBuf tail64, tail32;              // TailDesc<double>, TailDesc<float>
     int nL = 0, nZ = 0;
     long long ldZ = 0;       // leading dimension of Einv (even, >= nZ)
+    // variable k, nZ >= 2048: E^-1 kept as its packed upper triangle (symmetric)
+    bool sym = false;
+    DevBuf EinvP, symRow, symCol;
     // outer FGMRES
     int m_outer = 0;
     DevBuf V, Z, kstate, r, scratch;

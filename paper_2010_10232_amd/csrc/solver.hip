@@ -566,6 +566,16 @@ void SolverImpl::setup(hipStream_t s) {
         rocblas_destroy_handle(h);
         if (st != rocblas_status_success) throw Err{HH_EHIP, "rocsolver LU inverse failed"};
         if (singular != 0) throw Err{HH_ENUMERIC, "deflation matrix E is singular"};
+        // E^-1 is symmetric: keep only its upper triangle (half the bytes per product)
+        if (nZ >= 2048) {
+            EinvP.alloc((size_t)sym_packed_doubles(nZ) * sizeof(double));
+            launch_sym_pack(nZ, ldZ, Einv.as<double>(), EinvP.as<double>(), s);
+            symRow.alloc((size_t)sym_tiles(nZ) * 128 * sizeof(cx<double>));
+            symCol.alloc((size_t)sym_tiles(nZ) * 128 * sizeof(cx<double>));
+            HH_HIP(hipStreamSynchronize(s));
+            Einv.release();
+            sym = true;
+        }
     }
     if (Lz > 0) {
         for (int l = 0; l < Lz; ++l) {
@@ -855,8 +865,14 @@ void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStre
             // c, e, 1/D and both eigenvector matrices once
             tstop(2, 40.0 * nZ + 8.0 * ((double)lz.n1 * lz.n1 + (double)lz.n2 * lz.n2), s);
         } else {
-            launch_gemv_real(nZ, ldZ, Einv.as<double>(), c, e, s);
-            tstop(2, 8.0 * nZ * (double)nZ + 32.0 * nZ, s);
+            if (sym) {
+                launch_symv(nZ, EinvP.as<double>(), c, symRow.as<cx<double>>(), symCol.as<cx<double>>(), e, s);
+                // the stored triangle once, c and e
+                tstop(2, 8.0 * (double)sym_packed_doubles(nZ) + 32.0 * nZ, s);
+            } else {
+                launch_gemv_real(nZ, ldZ, Einv.as<double>(), c, e, s);
+                tstop(2, 8.0 * nZ * (double)nZ + 32.0 * nZ, s);
+            }
         }
         return;
     }

@@ -60,6 +60,8 @@ CASES = {
     "2d_grf_p3": dict(dim=2, p=3, n_el=17, grf=10.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=100)),
     "2d_rand_p4": dict(dim=2, p=4, n_el=16, rand=9.0, x0=(0.31, 0.77), opts=dict()),
     "2d_tiles_p3": dict(dim=2, p=3, n_el=130, k=40.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=1200)),
+    # variable k, two-level: E^-1 at level 1 (2500 unknowns) stored as its packed upper triangle
+    "2d_grf_p2_2lev_packed": dict(dim=2, p=2, n_el=100, grf=40.0, x0=(0.5, 0.5), opts=dict(defl_mode=1)),
     # MP 2-A at k = 100, p = 3 on 160 x 160 elements with the default (two-level) deflation
     "mp2a_k100_p3_160": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict()),
 }
