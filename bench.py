@@ -34,17 +34,18 @@ CLASS_NAMES = {1: "finest-level operator (stencil) kernel", 2: "exact E^-1 solve
                3: "outer Arnoldi MGS kernel"}
 
 WORKLOADS = {
-    # configs[1]: MP 2-A mesh of the paper's table (k = 100, p = 3, 160 x 160 elements)
+    # MP 2-A mesh of the paper's table (k = 100, p = 3, 160 x 160 elements): the default
     "mp2a_k100_p3_160": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict()),
-    # configs[0]
+    # MP 1-B: 1D, k = 50, p = 2, 80 elements, two-level deflation
     "mp1b_k50_p2_80": dict(dim=1, p=2, n_el=80, k=50.0, x0=(0.5,), opts=dict(defl_mode=1)),
-    # configs[2] (p = 3 member), FP64 or mixed
+    # three-layer wedge, k0 = 150, p = 3, 480 x 480 elements, FP64 or mixed
     # (direct deflation level up to 65536 unknowns: level 1, k h <= 1.25 there)
     "wedge_k150_p3_480": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95),
                               opts=dict(defl_direct_max=65536)),
-    # configs[4] plain form (direct deflation level 2, 58,564 unknowns)
+    # Gaussian random field k = 300 (1 + 0.3 g), p = 4, 960 x 960 elements
+    # (direct deflation level 2, 58,564 unknowns)
     "grf_k300_p4_960": dict(dim=2, p=4, n_el=960, grf=300.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=65536)),
-    # configs[3]: 64 independent constant-k problems, k ~ U[50, 400], n_el = ceil(k / 0.625),
+    # 64 independent constant-k problems, k ~ U[50, 400], n_el = ceil(k / 0.625),
     # p ~ U{2, 3, 4}, random interior sources; FP32 V-cycle, FP64 Krylov and deflation
     "batch64_k50_400": dict(batch=64, seed=0, opts=dict(precision=1, maxit=400)),
 }

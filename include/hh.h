@@ -170,11 +170,12 @@ hh_status hh_solver_destroy(hh_solver* s);
 hh_status hh_solve(hh_solver* s, const void* f_dev, void* u_dev, int use_u0,
                    hh_solve_info* info, void* stream);
 
-/* Batched solve (spec batching form): n independent problems, each with
+/* Batched solve: n independent problems, each with
  * its own solver (problems may differ in size, degree and wave number), advance
  * in lockstep - one FGMRES step of every unfinished problem per batch
- * iteration - on a pool of HIP streams, so that the many small kernels of
- * different problems run concurrently.  s, f, u, infos: arrays of n entries;
+ * iteration - on a pool of up to eight HIP streams (largest problems first,
+ * each to the stream with the fewest unknowns so far), so that the many small
+ * kernels of different problems run concurrently.  s, f, u, infos: arrays of n entries;
  * f[i], u[i] device vectors of problem i (as in hh_solve, zero initial guess).
  * Per-problem results and status are in infos[i]; the return value is the
  * first negative status, HH_ENOCONV if some problem did not converge, else
@@ -195,7 +196,7 @@ hh_status hh_set_kernel_timing(hh_solver* s, int cls);
 hh_status hh_apply(hh_solver* s, int op, int level, const void* x_dev, void* y_dev,
                    void* stream);
 
-/* ---- learned fine-level smoother (spec form 4; not in the paper) ----
+/* ---- learned fine-level smoother (not in the paper) ----
  * A complex 3x3 CNN C (complex channels 2 -> 16 -> 16 -> 16 -> 1, CReLU after
  * the first three layers, zero padding) on the finest interior control-point
  * grid.  Inputs: r/||r|| and c = k^2 h^2 (k of the finest element with the

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <algorithm>
 #include <set>
 
 #include "solver.h"
@@ -210,9 +211,22 @@ hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, voi
         active[i] = 0;
         set_error(msg);
     };
+    // stream of each problem: longest processing time first (largest N first,
+    // each to the stream with the fewest unknowns so far), so that no stream
+    // collects several of the largest problems
+    std::vector<int> order(n), stream_of(n, 0);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return s[a]->impl->lev[0]->N > s[b]->impl->lev[0]->N; });
+    std::vector<long long> load(ns, 0);
+    for (int i : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        stream_of[i] = k;
+        load[k] += s[i]->impl->lev[0]->N;
+    }
     for (int i = 0; i < n; ++i) {
         try {
-            runs[i].start(s[i]->impl.get(), (const cx<double>*)f[i], (cx<double>*)u[i], 0, st[i % ns]);
+            runs[i].start(s[i]->impl.get(), (const cx<double>*)f[i], (cx<double>*)u[i], 0, st[stream_of[i]]);
         } catch (const Err& e) {
             fail(i, e.code, e.msg);
         }
