@@ -205,7 +205,10 @@ hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, voi
     std::vector<SolveRun> runs(n);
     std::vector<int> status(n, HH_OK);
     std::vector<char> active(n, 1);
-    for (int i = 0; i < n; ++i) s[i]->impl->allow_coop = false;
+    for (int i = 0; i < n; ++i) {
+        s[i]->impl->allow_coop = false;
+        s[i]->impl->use_graphs = true;
+    }
     auto fail = [&](int i, int code, const std::string& msg) {
         status[i] = code;
         active[i] = 0;
@@ -249,7 +252,10 @@ hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, voi
             }
         }
     }
-    for (int i = 0; i < n; ++i) s[i]->impl->allow_coop = true;
+    for (int i = 0; i < n; ++i) {
+        s[i]->impl->allow_coop = true;
+        s[i]->impl->use_graphs = false;
+    }
     hipEvent_t join;
     HH_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
     for (int k = 0; k < ns; ++k) {
@@ -365,6 +371,7 @@ hh_status hh_solver_set_smoother(hh_solver* s, hh_cnn* c) {
     HH_TRY
     if (!s) throw Err{HH_EINVAL, "NULL solver"};
     s->impl->cnn = c ? c->impl.get() : nullptr;
+    s->impl->drop_graphs();
     return HH_OK;
     HH_CATCH
 }
@@ -373,6 +380,7 @@ hh_status hh_solver_capture(hh_solver* s, void* buf, int max_samples) {
     HH_TRY
     if (!s) throw Err{HH_EINVAL, "NULL solver"};
     if (buf && max_samples < 1) throw Err{HH_EINVAL, "max_samples must be >= 1"};
+    s->impl->drop_graphs();
     s->impl->cap_buf = (cx<double>*)buf;
     s->impl->cap_max = buf ? max_samples : 0;
     if (buf) s->impl->cap_n = 0;  // a new capture starts empty; stopping keeps the count
@@ -393,6 +401,7 @@ hh_status hh_set_kernel_timing(hh_solver* s, int cls) {
     if (!s) throw Err{HH_EINVAL, "NULL solver"};
     if (cls < 0 || cls > 3) throw Err{HH_EINVAL, "timing class must be 0..3"};
     s->impl->o.time_kernels = cls;
+    s->impl->drop_graphs();
     return HH_OK;
     HH_CATCH
 }

@@ -121,6 +121,13 @@ struct SolverImpl {
     void coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s);
     void arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s);
     bool allow_coop = true;
+    // batched mode: Arnoldi step j (T, operator, MGS, scalar copies) captured
+    // once into a HIP graph and replayed (no timing, learned smoother or sample
+    // capture in that mode; the graphs bake in this solver's buffers)
+    bool use_graphs = false;
+    std::vector<hipGraphExec_t> step_graphs;
+    void drop_graphs();
+    bool graphs_allowed() const { return !allow_coop && o.time_kernels == 0 && cnn == nullptr && cap_buf == nullptr; }
     // learned fine-level smoother (null: damped Jacobi everywhere)
     CnnImpl* cnn = nullptr;
     DevBuf feat;                 // network feature c = k^2 h^2 per finest-level unknown (FP32)

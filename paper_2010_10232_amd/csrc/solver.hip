@@ -155,7 +155,14 @@ static DevBuf& pick(DevBuf& a64, DevBuf& a32) {
     return sizeof(T) == 8 ? a64 : a32;
 }
 
+void SolverImpl::drop_graphs() {
+    for (hipGraphExec_t g : step_graphs)
+        if (g) (void)hipGraphExecDestroy(g);
+    step_graphs.clear();
+}
+
 SolverImpl::~SolverImpl() {
+    drop_graphs();
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     if (pin_d) (void)hipHostFree(pin_d);
     if (pin_i) (void)hipHostFree(pin_i);
@@ -952,16 +959,41 @@ void SolveRun::enqueue_step(int jj) {
     cx<double>* vj = Vb + (size_t)jj * N;
     cx<double>* zj = Zb + (size_t)jj * N;
     cx<double>* w = Vb + (size_t)(jj + 1) * N;
-    S->T_apply(0, vj, zj, s);
-    S->op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
-    // MGS + norm + Givens + normalisation of w in one launch; algorithmic
-    // bytes: each basis vector v_0..v_jj read once, w read once and written once
-    S->tstart(3, s);
-    S->arnoldi(N, jj, w, Vb, kd, s);
-    S->tstop(3, 16.0 * (jj + 3) * N, s);
     const int slot = jj & 1;
-    HH_HIP(hipMemcpyAsync(S->pin_d + 8 * slot, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HH_HIP(hipMemcpyAsync(S->pin_i + 16 * slot, kd.ints, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+    auto body = [&]() {
+        S->T_apply(0, vj, zj, s);
+        S->op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
+        // MGS + norm + Givens + normalisation of w; algorithmic bytes: each
+        // basis vector v_0..v_jj read once, w read once and written once
+        S->tstart(3, s);
+        S->arnoldi(N, jj, w, Vb, kd, s);
+        S->tstop(3, 16.0 * (jj + 3) * N, s);
+        HH_HIP(hipMemcpyAsync(S->pin_d + 8 * slot, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HH_HIP(hipMemcpyAsync(S->pin_i + 16 * slot, kd.ints, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+    };
+    if (S->use_graphs && S->graphs_allowed()) {
+        if ((int)S->step_graphs.size() <= jj) S->step_graphs.resize(jj + 1, nullptr);
+        if (!S->step_graphs[jj]) {
+            hipGraph_t g = nullptr;
+            HH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                body();
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            HH_HIP(hipStreamEndCapture(s, &g));
+            hipGraphExec_t ge = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) throw Err{HH_EHIP, std::string("graph instantiation: ") + hipGetErrorString(e)};
+            S->step_graphs[jj] = ge;
+        }
+        HH_HIP(hipGraphLaunch(S->step_graphs[jj], s));
+    } else {
+        body();
+    }
     HH_HIP(hipEventRecord(S->ev_slot[slot], s));
 }
 

@@ -70,3 +70,33 @@ def test_batched_rejects_duplicates():
     f = pr.point_source((0.5, 0.5))
     with pytest.raises(B.HHError):
         B.solve_batched([s, s], [f, f.clone()])
+
+
+def test_batched_graph_replays_match_single():
+    """In batched mode every Arnoldi step is a captured HIP graph.  A short
+    restart replays each graph several times per solve; three batched calls
+    with eager single solves between them must all reproduce the single
+    solves (same iterations, solutions to 1e-10)."""
+    import torch
+    from paper_2010_10232_amd import binding as B
+    draws = _batch_problems(n=5, seed=21)
+    opts = dict(defl_direct_max=400, restart=6, maxit=120)
+    probs = [B.Problem(2, d["p"], d["n_el"], k=d["k"]) for d in draws]
+    solvers = [B.Solver(pr, **opts) for pr in probs]
+    fs = [pr.point_source(d["x0"]) for pr, d in zip(probs, draws)]
+    ref = [s.solve(f) for s, f in zip(solvers, fs)]
+    assert max(r[1]["restarts"] for r in ref) >= 1
+    for call in range(3):
+        _say(f"[graph replays] batched call {call + 1}")
+        us, infos = B.solve_batched(solvers, fs)
+        torch.cuda.synchronize()
+        for i, (u, info) in enumerate(zip(us, infos)):
+            u1, info1 = ref[i]
+            assert info["status"] in (0, 1) and info["restarts"] == info1["restarts"]
+            assert info["iters"] == info1["iters"], (call, i)
+            d = (torch.linalg.norm(u - u1) / torch.linalg.norm(u1)).item()
+            assert d <= 1e-10, (call, i, d)
+        # eager work between replays (single solves, timing switched on and off)
+        solvers[call].set_kernel_timing(3)
+        solvers[call].solve(fs[call])
+        solvers[call].set_kernel_timing(0)
