@@ -96,6 +96,9 @@ struct SolverImpl {
     // of 8 doubles / 16 ints; inner-level barrier flags at pin_i[32 + l]
     double* pin_d = nullptr;
     int* pin_i = nullptr;
+    // per Arnoldi-step slot: the device scalars (8 doubles) and, right after
+    // them in device memory, the counters (6 ints), copied in one transfer
+    unsigned char* pin_step = nullptr;   // 2 slots x 128 bytes
     hipEvent_t ev_slot[2] = {nullptr, nullptr}, ev_misc = nullptr;
     // event timing of one kernel class (non-blocking: events are read after the solve)
     std::vector<hipEvent_t> evpool;

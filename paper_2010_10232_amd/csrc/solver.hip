@@ -146,7 +146,7 @@ static void fill_krylov(KrylovDev& k, DevBuf& blob, int m) {
     p += 8 * m;
     k.scal = (double*)p;
     p += 8 * 8;
-    k.ints = (int*)p;
+    k.ints = (int*)p;   // directly after scal: both reach the host in one transfer
     HH_HIP(hipMemset(blob.p, 0, blob.bytes));
 }
 
@@ -166,6 +166,7 @@ SolverImpl::~SolverImpl() {
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     if (pin_d) (void)hipHostFree(pin_d);
     if (pin_i) (void)hipHostFree(pin_i);
+    if (pin_step) (void)hipHostFree(pin_step);
     for (hipEvent_t e : {ev_slot[0], ev_slot[1], ev_misc})
         if (e) (void)hipEventDestroy(e);
 }
@@ -346,9 +347,10 @@ void SolverImpl::setup(hipStream_t s) {
         upload(Minv64, m64);
         upload(Minv32, m32);
     }
-    // coarse tail: the levels from the first one whose right-hand sides,
-    // iterates and spare vectors (FP64) all fit in the LDS of one workgroup,
-    // down to the coarsest, run as one single-workgroup V-cycle
+    // coarse tail: the levels from the first one with at most 1024 unknowns
+    // whose right-hand sides, iterates, spare vectors (FP64) and coefficient
+    // tables all fit in the LDS of one workgroup, down to the coarsest, run as
+    // one single-workgroup V-cycle
     {
         int dev = 0, lds_max = 0;
         HH_HIP(hipGetDevice(&dev));
@@ -371,7 +373,9 @@ void SolverImpl::setup(hipStream_t s) {
         for (int l = 1; l < L && L < kTailLevels; ++l) {
             long long bytes = 0;
             for (int m = l; m <= L; ++m) bytes += 3 * lev[m]->N * (long long)sizeof(cx<double>) + coef_bytes(m);
-            if (bytes <= budget) {
+            // measured on MP 2-A: a level of 1681 unknowns runs faster as separate
+            // kernels than inside the one-workgroup tail; from ~1000 down the tail wins
+            if (bytes <= budget && lev[l]->N <= 1024) {
                 tail_start = l;
                 tail_lds = (int)bytes;
                 break;
@@ -631,6 +635,8 @@ void SolverImpl::setup(hipStream_t s) {
     HH_HIP(hipHostMalloc((void**)&pin_i, 64 * sizeof(int), hipHostMallocDefault));
     std::memset(pin_d, 0, 16 * sizeof(double));
     std::memset(pin_i, 0, 64 * sizeof(int));
+    HH_HIP(hipHostMalloc((void**)&pin_step, 256, hipHostMallocDefault));
+    std::memset(pin_step, 0, 256);
     for (hipEvent_t* e : {&ev_slot[0], &ev_slot[1], &ev_misc})
         HH_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     HH_HIP(hipStreamSynchronize(s));
@@ -968,8 +974,9 @@ void SolveRun::enqueue_step(int jj) {
         S->tstart(3, s);
         S->arnoldi(N, jj, w, Vb, kd, s);
         S->tstop(3, 16.0 * (jj + 3) * N, s);
-        HH_HIP(hipMemcpyAsync(S->pin_d + 8 * slot, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HH_HIP(hipMemcpyAsync(S->pin_i + 16 * slot, kd.ints, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+        // scal[0..7] and ints[0..5] are adjacent on the device: one transfer
+        HH_HIP(hipMemcpyAsync(S->pin_step + 128 * slot, kd.scal, 8 * sizeof(double) + 6 * sizeof(int),
+                              hipMemcpyDeviceToHost, s));
     };
     if (S->use_graphs && S->graphs_allowed()) {
         if ((int)S->step_graphs.size() <= jj) S->step_graphs.resize(jj + 1, nullptr);
@@ -1053,8 +1060,9 @@ void SolveRun::step() {
         }
         case P_STEP: {
             const int slot = j & 1;
-            gabs = S->pin_d[8 * slot + 2];
-            const int* pi = S->pin_i + 16 * slot;
+            const double* pd = (const double*)(S->pin_step + 128 * slot);
+            const int* pi = (const int*)(S->pin_step + 128 * slot + 8 * sizeof(double));
+            gabs = pd[2];
             ++iters;
             if (pi[5]) throw Err{HH_EHIP, "grid barrier of the Arnoldi kernel timed out"};
             if (!std::isfinite(gabs)) throw Err{HH_ENUMERIC, "Arnoldi recurrence produced NaN/Inf"};
