@@ -83,10 +83,13 @@ typedef struct {
                                 in hh_solve_info): 0 none (default), 1 finest-level operator
                                 (stencil) kernels, 2 exact E^-1 solve of the direct
                                 deflation level, 3 outer Arnoldi MGS kernels */
-    int autotune;            /* 1 (default): at setup, time the level-operator kernel of
-                                every level (FP64 and FP32) with strip heights 4..64 rows
-                                and keep the fastest; 0: a fixed rule (the tallest strip
-                                that still gives 2048 waves).  Results do not depend on it. */
+    int autotune;            /* 1 (default): at setup, time the strip level-operator kernel
+                                of every level that uses it (FP64 and FP32; levels of at
+                                most 32768 unknowns with constant k or a stored stencil use
+                                a one-thread-per-unknown kernel instead) with strip heights
+                                4..64 rows and keep the fastest; 0: a fixed rule (the
+                                tallest strip that still gives 2048 waves).  Results do
+                                not depend on it. */
 } hh_solver_opts;
 
 typedef struct {

@@ -107,6 +107,12 @@ void axis_eigen(const Axis& a, std::vector<double>& V, std::vector<double>& lam)
 
 // ------------------------------------------------------ device-side data --
 enum OpKind { KIND_SEP = 0, KIND_VARFINE = 1, KIND_STENCIL = 2 };
+// Levels up to this many unknowns (constant k or stored stencil, 2D) use the
+// one-thread-per-unknown operator kernel instead of the strip kernel; measured
+// on MP 2-A (levels of 25,921 / 6,561 / 1,681 unknowns): 5.78 ms per solve with
+// this bound, 5.93 ms with 16384, 6.03 ms with the strip kernel only.
+constexpr long long kOpDirectMax = 32768;
+
 enum OpMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_SMOOTH = 2 };
 
 // Arguments of the level-operator kernels: y = K x - alpha M_k x (+ epilogue).

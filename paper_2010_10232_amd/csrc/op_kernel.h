@@ -260,6 +260,85 @@ __global__ __launch_bounds__(64) void op_kernel(OpArgs<T> a, int ty) {
     }
 }
 
+// Direct level operator for small levels (constant k or stored stencil): one
+// thread per unknown, its bands in registers, the (2px+1)(2py+1) neighbours
+// loaded together through the caches.  Same sums as op_kernel: per input row
+// the x-direction band products, combined through the y bands in input-row
+// order; on small grids this avoids op_kernel's sequential walk over a strip.
+template <int PX, int PY, int KIND, int MODE, class T>
+__global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
+    constexpr int BX = 2 * PX + 1, BY = 2 * PY + 1;
+    const int n1 = a.n1, n2 = a.n2;
+    const long long N = (long long)n1 * n2;
+    const long long I = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (I >= N) return;
+    const int I1 = (int)(I % n1), I2 = (int)(I / n1);
+    T kx[BX], mx[BX], ky[BY], my[BY];
+#pragma unroll
+    for (int d = 0; d < BX; ++d) {
+        kx[d] = (T)a.Kx[(size_t)I1 * BX + d];
+        mx[d] = (T)a.Mx[(size_t)I1 * BX + d];
+    }
+#pragma unroll
+    for (int d = 0; d < BY; ++d) {
+        ky[d] = (T)a.Ky[(size_t)I2 * BY + d];
+        my[d] = (T)a.My[(size_t)I2 * BY + d];
+    }
+    const T are = a.are, aim = a.aim;
+    const T k2c = (T)a.k2c;
+    T wr = 0, wi = 0, vr = 0, vi = 0;
+#pragma unroll
+    for (int d2 = 0; d2 < BY; ++d2) {
+        const int J2 = I2 + d2 - PY;
+        if (J2 < 0 || J2 >= n2) continue;
+        const size_t row = (size_t)J2 * n1;
+        T u1r = 0, u1i = 0, u2r = 0, u2i = 0;
+#pragma unroll
+        for (int d = 0; d < BX; ++d) {
+            const int J1 = I1 + d - PX;
+            const cx<T> v = (J1 >= 0 && J1 < n1) ? a.x[row + J1] : cx<T>{T(0), T(0)};
+            u1r += kx[d] * v.re;
+            u1i += kx[d] * v.im;
+            u2r += mx[d] * v.re;
+            u2i += mx[d] * v.im;
+            if (KIND == KIND_STENCIL) {
+                const T c = a.S[(size_t)(d2 * BX + d) * N + I];
+                vr += c * v.re;
+                vi += c * v.im;
+            }
+        }
+        if (KIND == KIND_SEP) {
+            const T cr = u1r - k2c * (are * u2r - aim * u2i);
+            const T ci = u1i - k2c * (are * u2i + aim * u2r);
+            u1r = cr;
+            u1i = ci;
+        }
+        wr += my[d2] * u1r + ky[d2] * u2r;
+        wi += my[d2] * u1i + ky[d2] * u2i;
+    }
+    T yr = wr, yi = wi;
+    if (KIND == KIND_STENCIL) {
+        yr -= are * vr - aim * vi;
+        yi -= are * vi + aim * vr;
+    }
+    cx<T> out;
+    if (MODE == MODE_APPLY) {
+        out = {yr, yi};
+    } else {
+        const cx<T> bv = a.b[I];
+        const T rr = bv.re - yr, ri = bv.im - yi;
+        if (MODE == MODE_RESID) {
+            out = {rr, ri};
+        } else {
+            const cx<T> dv = a.dinv[I], xv = a.x[I];
+            out = {xv.re + a.omega * (dv.re * rr - dv.im * ri), xv.im + a.omega * (dv.re * ri + dv.im * rr)};
+        }
+    }
+    a.y[I] = out;
+}
+
+
+
 // Strip height: the tallest of 64, 32, 16, 8, 4 rows that still gives at
 // least 2048 waves (eight per CU); tall strips amortise the 2p halo rows.
 inline int op_rows_per_strip(int n1, int n2, int py) {
@@ -272,6 +351,12 @@ inline int op_rows_per_strip(int n1, int n2, int py) {
 
 template <int PX, int PY, int KIND, int MODE, class T>
 static void launch_op_t(const OpArgs<T>& a, hipStream_t s) {
+    if (KIND != KIND_VARFINE && PY > 0 && (long long)a.n1 * a.n2 <= kOpDirectMax) {
+        const long long N = (long long)a.n1 * a.n2;
+        hipLaunchKernelGGL((op_direct_kernel<PX, PY, KIND, MODE, T>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0,
+                           s, a);
+        return;
+    }
     // a tuned strip height (a power of two in 4..64) or the fixed rule; 1D always 1
     const int ty = (PY == 0) ? 1 : (a.ty >= 4 && a.ty <= 64 && (a.ty & (a.ty - 1)) == 0) ? a.ty
                                                                                          : op_rows_per_strip(a.n1, a.n2, PY);

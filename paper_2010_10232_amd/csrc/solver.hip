@@ -688,7 +688,8 @@ void SolverImpl::autotune_ops(hipStream_t s) {
     const bool timing = o.time_kernels;
     o.time_kernels = 0;
     for (int l = 0; l <= last; ++l) {
-        if (lev[l]->N < 4096) continue;
+        // small constant-k / stencil levels use the direct kernel (no strips)
+        if (lev[l]->N <= kOpDirectMax && lev[l]->kind != KIND_VARFINE) continue;
         tune(l, double{});
         tune(l, float{});
     }
