@@ -51,6 +51,27 @@ WORKLOADS = {
 }
 
 
+def measure_copy_gbs(mib=1024, reps=5):
+    """Achieved bandwidth of a plain 1 GiB device-to-device copy (read + write bytes / time), the
+    practical ceiling next to the 8 TB/s vendor peak."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / (best * 1e-3) / 1e9
+
+
 def k_field(w):
     if "wedge" in w:
         return W.wedge_k(w["n_el"], w["wedge"])
@@ -259,6 +280,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = measure_copy_gbs()
     w = WORKLOADS[args.workload]
     ke = k_field(w)
     t0 = time.perf_counter()
@@ -329,6 +351,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": CLASS_NAMES[dom],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                     "copy_GBps_measured": round(copy_gbs, 1),
                      "launches": k_n, "avg_us": (k_ms * 1e3 / k_n) if k_n else None,
                      "bytes_per_launch": (k_bytes / k_n) if k_n else None,
                      "class_ms_per_solve": {CLASS_NAMES[c]: round(v, 4) for c, v in per_class.items()}},

@@ -152,6 +152,17 @@ hh_status hh_point_spans(const hh_problem* pr, const double* x0, int* spans);
 hh_status hh_rhs_point_source(const hh_problem* pr, const double* x0, double amp,
                               void* f_dev, void* stream);
 
+/* Finest-level operators of an assembled problem in CSR form (section 2.3:
+ * stiffness, k^2-weighted mass and A = K - M_k after Dirichlet elimination),
+ * for exact comparisons of sparsity and values on small meshes; host only.
+ * which: 0 K, 1 M_k, 2 A.  Rows and columns are interior indices (x fastest);
+ * every entry of the tensor-product band (|i1 - j1| <= p and |i2 - j2| <= p in
+ * range) is stored, columns ascending within a row.  Call with row_ptr NULL to
+ * get *nnz only; otherwise row_ptr (N + 1), col_idx and val (capacity entries
+ * each, host) are filled and HH_EINVAL is returned if capacity < nnz. */
+hh_status hh_export_csr(const hh_problem* pr, int which, long long* nnz, long long* row_ptr, int* col_idx,
+                        double* val, long long capacity);
+
 /* Builds the multigrid / deflation hierarchy and allocates all device workspace
  * (section 3): coarse knot vectors by knot halving, knot-insertion transfers,
  * Galerkin coarse operators, Jacobi diagonals, the dense inverse of the coarsest

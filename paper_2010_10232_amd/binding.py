@@ -19,7 +19,7 @@ HH_EINVAL, HH_ENOMEM, HH_EHIP, HH_ENUMERIC = -1, -2, -3, -4
 OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 5, "T": 6, "EINV": 7}
 
 EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
-            "hh_point_spans", "hh_rhs_point_source", "hh_setup", "hh_solver_destroy", "hh_solve",
+            "hh_point_spans", "hh_rhs_point_source", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
             "hh_level_info", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched", "hh_cnn_create",
             "hh_cnn_destroy", "hh_cnn_num_params", "hh_cnn_get_params", "hh_cnn_set_params", "hh_cnn_loss_grad",
             "hh_cnn_train_step", "hh_solver_set_smoother", "hh_solver_capture", "hh_solver_captured"]
@@ -78,6 +78,7 @@ def load(path=LIB_PATH):
     lib.hh_problem_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.hh_point_spans.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.hh_rhs_point_source.argtypes = [vp, ctypes.POINTER(ctypes.c_double), dp, vp, vp]
+    lib.hh_export_csr.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong), vp, vp, vp, ctypes.c_longlong]
     lib.hh_setup.argtypes = [vp, ctypes.POINTER(SolverOpts), vp, ctypes.POINTER(vp)]
     lib.hh_solver_destroy.argtypes = [vp]
     lib.hh_solve.argtypes = [vp, vp, vp, ip, ctypes.POINTER(SolveInfo), vp]
@@ -178,6 +179,18 @@ class Problem:
         out = (ctypes.c_int * 2)()
         _check(load().hh_point_spans(self._h, x, out))
         return [out[i] for i in range(self.dim)]
+
+    def export_csr(self, which):
+        """Finest-level K (0), M_k (1) or A (2) on the host: (indptr, indices, data) numpy arrays."""
+        lib = load()
+        nnz = ctypes.c_longlong()
+        _check(lib.hh_export_csr(self._h, int(which), ctypes.byref(nnz), None, None, None, 0))
+        indptr = np.empty(self.N + 1, dtype=np.int64)
+        indices = np.empty(nnz.value, dtype=np.int32)
+        data = np.empty(nnz.value, dtype=np.float64)
+        _check(lib.hh_export_csr(self._h, int(which), ctypes.byref(nnz), indptr.ctypes.data, indices.ctypes.data,
+                                 data.ctypes.data, nnz.value))
+        return indptr, indices, data
 
     def point_source(self, x0, amp=1.0, out=None):
         import torch

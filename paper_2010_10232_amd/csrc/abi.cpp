@@ -102,6 +102,39 @@ hh_status hh_point_spans(const hh_problem* pr, const double* x0, int* spans) {
     HH_CATCH
 }
 
+hh_status hh_export_csr(const hh_problem* pr, int which, long long* nnz, long long* row_ptr, int* col_idx,
+                        double* val, long long capacity) {
+    HH_TRY
+    if (!pr || !nnz) throw Err{HH_EINVAL, "NULL argument"};
+    if (which < 0 || which > 2) throw Err{HH_EINVAL, "which must be 0 (K), 1 (M_k) or 2 (A)"};
+    const ProblemImpl& P = pr->impl;
+    const bool const_k = P.k_mode == 0;
+    std::vector<double> S;
+    if (!const_k) galerkin_mass_stencil(P.ax0, P.ay0, P.k2, S);
+    const double k2c = const_k ? P.k * P.k : 0.0;
+    const long long N = P.N();
+    long long count = 0;
+    for (long long I = 0; I < N; ++I) visit_row(P.ax0, P.ay0, const_k, k2c, S, I, [&](long long, double, double) {
+        ++count;
+    });
+    *nnz = count;
+    if (!row_ptr) return HH_OK;
+    if (!col_idx || !val) throw Err{HH_EINVAL, "NULL col_idx or val"};
+    if (capacity < count) throw Err{HH_EINVAL, "capacity below the number of entries"};
+    long long k = 0;
+    for (long long I = 0; I < N; ++I) {
+        row_ptr[I] = k;
+        visit_row(P.ax0, P.ay0, const_k, k2c, S, I, [&](long long J, double kv, double mv) {
+            col_idx[k] = (int)J;
+            val[k] = which == 0 ? kv : which == 1 ? mv : kv - mv;
+            ++k;
+        });
+    }
+    row_ptr[N] = k;
+    return HH_OK;
+    HH_CATCH
+}
+
 hh_status hh_rhs_point_source(const hh_problem* pr, const double* x0, double amp, void* f_dev, void* stream) {
     HH_TRY
     if (!pr || !x0 || !f_dev) throw Err{HH_EINVAL, "NULL argument"};

@@ -68,30 +68,6 @@ ProblemImpl* build_problem(const hh_problem_desc* d) {
 }
 
 // ------------------------------------------------------------- host math --
-// Visits the nonzero stencil entries of row I of level data (K entries from
-// the bands; M_k entries from k^2 (constant) or the stored stencil S).
-template <class F>
-static void visit_row(const Axis& ax, const Axis& ay, bool const_k, double k2c, const std::vector<double>& S,
-                      long long I, F&& f) {
-    const int px = ax.p, py = ay.p, bx = 2 * px + 1, by = 2 * py + 1;
-    const int n1 = ax.n, n2 = ay.n;
-    const long long N = (long long)n1 * n2;
-    const int I1 = (int)(I % n1), I2 = (int)(I / n1);
-    for (int d2 = -py; d2 <= py; ++d2) {
-        const int J2 = I2 + d2;
-        if (J2 < 0 || J2 >= n2) continue;
-        const double my = ay.Mb[(size_t)I2 * by + d2 + py], ky = ay.Kb[(size_t)I2 * by + d2 + py];
-        for (int d1 = -px; d1 <= px; ++d1) {
-            const int J1 = I1 + d1;
-            if (J1 < 0 || J1 >= n1) continue;
-            const double mxv = ax.Mb[(size_t)I1 * bx + d1 + px], kxv = ax.Kb[(size_t)I1 * bx + d1 + px];
-            const double kv = my * kxv + ky * mxv;
-            const double mv = const_k ? k2c * my * mxv : S[(size_t)((d2 + py) * bx + d1 + px) * N + I];
-            f((long long)J2 * n1 + J1, kv, mv);
-        }
-    }
-}
-
 // In-place inverse of a small dense complex matrix (Gauss-Jordan, partial pivoting).
 static void invert_complex(int n, std::vector<zd>& A) {
     std::vector<int> piv(n);

@@ -75,3 +75,53 @@ def test_point_spans_reject_outside():
     for x0 in [(-0.1, 0.5), (0.5, 1.0000001)]:
         with pytest.raises(B.HHError):
             pr.spans(x0)
+
+
+_CSR_CASES = [
+    dict(dim=1, p=2, n_el=20, k=7.0),
+    dict(dim=1, p=5, n_el=13, rand=True),
+    dict(dim=2, p=1, n_el=6, k=3.0),
+    dict(dim=2, p=3, n_el=12, k=9.0),
+    dict(dim=2, p=2, n_el=9, rand=True),
+    dict(dim=2, p=4, n_el=11, rand=True),
+]
+
+
+@pytest.mark.parametrize("c", _CSR_CASES, ids=lambda c: f"d{c['dim']}p{c['p']}n{c['n_el']}{'rand' if c.get('rand') else ''}")
+def test_export_csr_matches_oracle(c):
+    """Finest-level K, M_k and A exported by the library (host) against the
+    oracle's scipy assembly: identical sparsity (row pointers and column
+    indices bit for bit) against the oracle's nonzero pattern (scipy's kron
+    stores explicit zeros of its block format, removed first), values within
+    1e-13 of the largest entry."""
+    ke = None
+    if c.get("rand"):
+        rng = np.random.default_rng(5)
+        shape = (c["n_el"],) * c["dim"]
+        ke = 4.0 * (1.0 + 0.5 * rng.random(shape))
+    k = c.get("k", 1.0)
+    gp = B.Problem(c["dim"], c["p"], c["n_el"], k=k, k_elem=ke)
+    op = hz.Problem(c["dim"], c["p"], c["n_el"], k, k_elem=ke)
+    K, Mk = hz.fine_operators(op)
+    for which, ref in ((0, K), (1, Mk), (2, (K - Mk))):
+        ref = ref.tocsr()
+        ref.eliminate_zeros()
+        ref.sort_indices()
+        indptr, indices, data = gp.export_csr(which)
+        assert np.array_equal(indptr, ref.indptr.astype(np.int64)), which
+        assert np.array_equal(indices, ref.indices.astype(np.int32)), which
+        scale = np.max(np.abs(ref.data))
+        assert np.max(np.abs(data - ref.data)) <= 1e-13 * scale, which
+
+
+def test_export_csr_capacity_checked():
+    gp = B.Problem(2, 2, 6, k=2.0)
+    lib = B.load()
+    nnz = ctypes.c_longlong()
+    assert lib.hh_export_csr(gp._h, 0, ctypes.byref(nnz), None, None, None, 0) == 0
+    ptr = np.empty(gp.N + 1, dtype=np.int64)
+    idx = np.empty(nnz.value, dtype=np.int32)
+    val = np.empty(nnz.value, dtype=np.float64)
+    assert lib.hh_export_csr(gp._h, 0, ctypes.byref(nnz), ptr.ctypes.data, idx.ctypes.data, val.ctypes.data,
+                             nnz.value - 1) < 0
+    assert lib.hh_export_csr(gp._h, 3, ctypes.byref(nnz), None, None, None, 0) < 0
