@@ -185,8 +185,9 @@ struct KrylovDev {
     cx<double>* y;    // m
     double* scal;     // [0] beta, [1] hn, [2] |g_{j+1}|, [3] norm accumulator
     int* ints;        // [0] jdone, [1] breakdown flag, [2] reduction counter,
-                      // [3] barrier arrivals, [4] barrier generation, [5] barrier timeout flag
+                      // [5] grid-exchange timeout flag, [6] cooperative launch epoch
     cx<double>* partials;  // reduction partials (2 x 1024, double-buffered)
+    unsigned long long* slots;  // grid-exchange words of the cooperative Arnoldi kernels (2 x 256 x 4)
     int m;
 };
 
@@ -223,6 +224,8 @@ struct TailDesc {
     const cx<T>* Minv;            // dense inverse of M_beta at level L
     int lds_bytes;                // LDS of the tail from level lds_l0 on
     int lds_l0;
+    const uint4* img;             // coefficient tables of all tail levels as laid out in LDS
+    int img16;                    // image size in 16-byte units (LDS bytes [0, 16 img16))
     int offb[kTailLevels], offx[kTailLevels], offt[kTailLevels];  // byte offsets of b, x, t in LDS
     TailLevel<T> lv[kTailLevels];
 };
@@ -267,8 +270,8 @@ void tail_prepare(int lds_bytes);
 template <class T>
 void launch_vcycle_tail(const TailDesc<T>* desc, int l0, int lds_bytes, const cx<T>* b, cx<T>* x, hipStream_t s);
 // e = (Vy (x) Vx) diag(dinv) (Vy (x) Vx)^T c on an [n2][n1] grid (t1, t2: N-vector scratch)
-void launch_fdm_solve(int n2, int n1, const double* Vx, const double* Vy, const double* dinv, const cx<double>* c,
-                      cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s);
+void launch_fdm_solve(int n2, int n1, const double* Vx, const double* VxT, const double* Vy, const double* dinv,
+                      const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s);
 // Krylov kernels
 int reduction_blocks(long long N);
 void launch_norm_init(long long N, const cx<double>* r, KrylovDev& k, hipStream_t s);  // beta = ||r||, g = [beta,0..], state reset

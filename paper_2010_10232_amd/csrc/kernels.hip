@@ -381,8 +381,103 @@ __global__ __launch_bounds__(256) void fdm_gemm_kernel(int M, int N, int K, cons
         }
 }
 
-void launch_fdm_solve(int n2, int n1, const double* Vx, const double* Vy, const double* dinv, const cx<double>* c,
-                      cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s) {
+// Small levels (both sides at most 128): two passes, each a pair of products
+// Y[r][:] = scale[r][:] * (sum_k L(r, k) X[k][:]) R for a block of FDM2_RB
+// output rows per workgroup, L and R real.  Every thread issues all its
+// global loads (its column of X over a 32-long k range, its column of R over a
+// 32-long j range, one element of the L rows) before any arithmetic, so a
+// pass costs one memory round trip; partial sums of the k (j) ranges are
+// added in range order in LDS (deterministic).
+constexpr int FDM2_TB = 512, FDM2_RB = 4, FDM2_CH = 32, FDM2_NMAX = 128;
+__global__ __launch_bounds__(FDM2_TB) void fdm_pass_kernel(int n2, int n1, const double* __restrict__ Lm, int lsr,
+                                                           int lsc, const cx<double>* __restrict__ X,
+                                                           const double* __restrict__ R,
+                                                           const double* __restrict__ scale,
+                                                           cx<double>* __restrict__ Y) {
+    __shared__ double Ls[FDM2_RB][FDM2_NMAX];
+    __shared__ cx<double> P[FDM2_NMAX / FDM2_CH][FDM2_RB][FDM2_NMAX];
+    __shared__ cx<double> U[FDM2_RB][FDM2_NMAX];
+    const int tid = threadIdx.x, r0 = blockIdx.x * FDM2_RB;
+    const int g = tid / n1, col = tid % n1;               // k (or j) range g, column col
+    const int G2 = (n2 + FDM2_CH - 1) / FDM2_CH, G1 = (n1 + FDM2_CH - 1) / FDM2_CH;
+    cx<double> xv[FDM2_CH];
+    double rv[FDM2_CH];
+#pragma unroll
+    for (int q = 0; q < FDM2_CH; ++q) {
+        const int k = g * FDM2_CH + q;
+        xv[q] = (g < G2 && k < n2) ? X[(size_t)k * n1 + col] : cx<double>{0.0, 0.0};
+        rv[q] = (g < G1 && k < n1) ? R[(size_t)k * n1 + col] : 0.0;
+    }
+    {
+        const int r = tid / FDM2_NMAX, k = tid % FDM2_NMAX, row = r0 + r;
+        Ls[r][k] = (row < n2 && k < n2) ? Lm[(size_t)row * lsr + (size_t)k * lsc] : 0.0;
+    }
+    __syncthreads();
+    if (g < G2) {
+#pragma unroll
+        for (int r = 0; r < FDM2_RB; ++r) {
+            double ar = 0.0, ai = 0.0;
+#pragma unroll
+            for (int q = 0; q < FDM2_CH; ++q) {
+                const double l = Ls[r][g * FDM2_CH + q];
+                ar += l * xv[q].re;
+                ai += l * xv[q].im;
+            }
+            P[g][r][col] = {ar, ai};
+        }
+    }
+    __syncthreads();
+    {
+        const int r = tid / FDM2_NMAX, c = tid % FDM2_NMAX;
+        double ar = 0.0, ai = 0.0;
+        if (c < n1)
+            for (int gg = 0; gg < G2; ++gg) {
+                ar += P[gg][r][c].re;
+                ai += P[gg][r][c].im;
+            }
+        U[r][c] = {ar, ai};
+    }
+    __syncthreads();
+    if (g < G1) {
+#pragma unroll
+        for (int r = 0; r < FDM2_RB; ++r) {
+            double ar = 0.0, ai = 0.0;
+#pragma unroll
+            for (int q = 0; q < FDM2_CH; ++q) {
+                const cx<double> u = U[r][g * FDM2_CH + q];
+                ar += u.re * rv[q];
+                ai += u.im * rv[q];
+            }
+            P[g][r][col] = {ar, ai};
+        }
+    }
+    __syncthreads();
+    {
+        const int r = tid / FDM2_NMAX, c = tid % FDM2_NMAX, row = r0 + r;
+        if (c < n1 && row < n2) {
+            double ar = 0.0, ai = 0.0;
+            for (int gg = 0; gg < G1; ++gg) {
+                ar += P[gg][r][c].re;
+                ai += P[gg][r][c].im;
+            }
+            const size_t o = (size_t)row * n1 + c;
+            const double d = scale ? scale[o] : 1.0;
+            Y[o] = {ar * d, ai * d};
+        }
+    }
+}
+
+void launch_fdm_solve(int n2, int n1, const double* Vx, const double* VxT, const double* Vy, const double* dinv,
+                      const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s) {
+    static_assert(FDM2_RB * FDM2_NMAX == FDM2_TB, "one L-row element and one output per thread");
+    if (n1 <= FDM2_NMAX && n2 <= FDM2_NMAX) {
+        const dim3 g((unsigned)((n2 + FDM2_RB - 1) / FDM2_RB)), b(FDM2_TB);
+        // T2 = (Vy^T C Vx) ./ D
+        hipLaunchKernelGGL(fdm_pass_kernel, g, b, 0, s, n2, n1, Vy, 1, n2, c, Vx, dinv, t2);
+        // e = Vy T2 Vx^T
+        hipLaunchKernelGGL(fdm_pass_kernel, g, b, 0, s, n2, n1, Vy, n2, 1, t2, VxT, nullptr, e);
+        return;
+    }
     const dim3 g((unsigned)((n1 + 31) / 32), (unsigned)((n2 + 31) / 32)), b(256);
     // T1 = C Vx
     hipLaunchKernelGGL(fdm_gemm_kernel<false>, g, b, 0, s, n2, n1, n1, Vx, n1, 1, c, n1, 1, nullptr, t1);
@@ -401,8 +496,9 @@ void launch_fdm_solve(int n2, int n1, const double* Vx, const double* Vy, const 
 // descent (Jacobi sweeps, residual, restriction), the dense coarsest solve and
 // the ascent (prolongation, Jacobi sweeps) with the right-hand side, iterate
 // and spare vector of every level in LDS, and a block barrier between phases.
-// Coefficients (bands, D^-1, stencils, transfer weights) are read through the
-// caches.  Each stencil sum runs over the (2px+1)(2py+1) neighbours in a fixed
+// The 1D bands and transfer weights of every tail level are copied into LDS
+// at the start from one image prepared at setup; D^-1, the variable-k stencils
+// and the coarsest inverse are read through the caches.  Each stencil sum runs over the (2px+1)(2py+1) neighbours in a fixed
 // order (deterministic).
 // --------------------------------------------------------------------------
 constexpr int TAIL_TB = 1024;
@@ -456,13 +552,6 @@ __device__ void tail_op(const TailLevel<T>& L, const TailDesc<T>& D, int mode, c
     __syncthreads();
 }
 
-template <class E>
-__device__ __forceinline__ void tail_stage(unsigned char* smem, int off, const E* src, long long n) {
-    if (off < 0) return;
-    E* dst = (E*)(smem + off);
-    for (long long i = threadIdx.x; i < n; i += TAIL_TB) dst[i] = src[i];
-}
-
 // A level's descriptor with its coefficient pointers redirected to the LDS copies.
 template <class T>
 __device__ __forceinline__ TailLevel<T> tail_level(const TailDesc<T>& D, int l, unsigned char* smem) {
@@ -494,26 +583,29 @@ __global__ __launch_bounds__(TAIL_TB) void vcycle_tail_kernel(const TailDesc<T>*
     auto vx = [&](int l) { return (cx<T>*)(tail_smem + D.offx[l]); };
     auto vt = [&](int l) { return (cx<T>*)(tail_smem + D.offt[l]); };
     {
+        // the level-l0 right-hand side and the coefficient image (the tables of
+        // every tail level, prepared at setup in their LDS layout): all loads
+        // are issued before the first LDS store, so staging costs one round trip
         const long long N0 = (long long)D.lv[l0].n1 * D.lv[l0].n2;
         cx<T>* b = vb(l0);
-        for (long long I = threadIdx.x; I < N0; I += TAIL_TB) b[I] = b0[I];
-        // coefficient tables of the levels this cycle visits
-        for (int l = l0; l < L; ++l) {
-            const TailLevel<T>& g = D.lv[l];
-            const int bx = 2 * g.px + 1, by = 2 * g.py + 1;
-            tail_stage<double>(tail_smem, g.o_kx, g.Kx, (long long)g.n1 * bx);
-            tail_stage<double>(tail_smem, g.o_mx, g.Mx, (long long)g.n1 * bx);
-            tail_stage<double>(tail_smem, g.o_ky, g.Ky, (long long)g.n2 * by);
-            tail_stage<double>(tail_smem, g.o_my, g.My, (long long)g.n2 * by);
-            const Transfer& t = g.tr;
-            tail_stage<int>(tail_smem, g.o_prow0x, t.prow0x, t.nf1);
-            tail_stage<double>(tail_smem, g.o_prowx, t.prowx, (long long)t.nf1 * t.pw1);
-            tail_stage<int>(tail_smem, g.o_prow0y, t.prow0y, t.nf2);
-            tail_stage<double>(tail_smem, g.o_prowy, t.prowy, (long long)t.nf2 * t.pw2);
-            tail_stage<int>(tail_smem, g.o_pcol0x, t.pcol0x, t.nc1);
-            tail_stage<double>(tail_smem, g.o_pcolx, t.pcolx, (long long)t.nc1 * t.rw1);
-            tail_stage<int>(tail_smem, g.o_pcol0y, t.pcol0y, t.nc2);
-            tail_stage<double>(tail_smem, g.o_pcoly, t.pcoly, (long long)t.nc2 * t.rw2);
+        uint4* dst = (uint4*)tail_smem;
+        const uint4* __restrict__ img = D.img;
+        const int n16 = D.img16;
+        for (long long I0 = threadIdx.x; I0 < N0 || I0 < n16; I0 += 4LL * TAIL_TB) {
+            cx<T> bv[4];
+            uint4 iv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const long long I = I0 + (long long)q * TAIL_TB;
+                if (I < N0) bv[q] = b0[I];
+                if (I < n16) iv[q] = img[I];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const long long I = I0 + (long long)q * TAIL_TB;
+                if (I < N0) b[I] = bv[q];
+                if (I < n16) dst[I] = iv[q];
+            }
         }
         __syncthreads();
     }
@@ -1026,49 +1118,98 @@ void launch_arnoldi_small(long long N, int j, cx<double>* w, const cx<double>* V
     hipLaunchKernelGGL(arnoldi_small_kernel, dim3(1), dim3(SB), 0, s, N, j, w, V, ldv, k);
 }
 
-// Grid-wide barrier for a cooperatively launched grid (all workgroups are
-// resident).  Arrival counter plus generation number; the last arrival resets
-// the counter and bumps the generation.  The wait is bounded: after ~2^24
-// polls the workgroup sets *abortf and leaves, so every wave always finishes.
-__device__ __forceinline__ void grid_barrier(int* count, int* gen, int* abortf) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (atomicAdd(count, 1) == (int)gridDim.x - 1) {
-            __hip_atomic_store(count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(gen, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            long long spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1LL << 24)) {
-                    atomicExch(abortf, 1);
-                    break;
-                }
-            }
-        }
-        __threadfence();
+// Butterfly sum over a wave: every lane ends with the same bits.
+__device__ __forceinline__ void wave_sum2(double& a, double& b) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
     }
-    __syncthreads();
 }
 
-// Deterministic grid-wide complex sum: block partial -> double-buffered slot ->
-// barrier -> every block sums all slots in index order (same result everywhere).
-__device__ __forceinline__ cx<double> grid_sum(double sr, double si, int round, KrylovDev& k, double* sh) {
-    block_sum2(sr, si, sh);
-    cx<double>* buf = k.partials + (size_t)(round & 1) * 1024;
-    if (threadIdx.x == 0) buf[blockIdx.x] = {sr, si};
-    __syncthreads();
-    grid_barrier(&k.ints[3], &k.ints[4], &k.ints[5]);
-    double tr = 0.0, ti = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += RB) {
-        const cx<double> v = buf[b];
-        tr += v.re;
-        ti += v.im;
+// Deterministic grid-wide complex sum for a cooperatively launched grid
+// (all workgroups resident), without a barrier.  Each block publishes its
+// partial as four 64-bit words, each holding 32 bits of the value in its high
+// half and, in its low half, a tag unique to (launch, round).  Wave 0 of every
+// block polls the words of all blocks until every tag matches, adds the
+// partials in block order (lane-strided, then a butterfly, so every block gets
+// identical bits) and hands the sum to the other waves through LDS.  The words
+// are written and read as single-copy-atomic 64-bit accesses at device scope,
+// so a matching tag implies the value bits beside it are current; no other
+// memory is exchanged during the step, so no fence is needed.  Slots are
+// double-buffered by round parity: a block cannot overwrite round r's slot
+// with round r + 2 before every block has published round r + 1, which each
+// does only after reading round r.  The wait is bounded: after ~2^20 polls the
+// lane sets the timeout flag and stops waiting, and every wait that sees the
+// flag stops too, so every wave always finishes.
+constexpr int kSlotBlocks = 256;   // slots per parity (the grid limit of the cooperative kernels)
+
+// rounds per launch <= restart + 1 <= 201 fit the 8-bit round field
+__device__ __forceinline__ unsigned step_tag(int epoch, int round) {
+    return 0x80000000u | (((unsigned)epoch & 0x7fffffu) << 8) | (unsigned)round;
+}
+
+__device__ __forceinline__ cx<double> exchange_sum(double tr, double ti, unsigned tag, KrylovDev& k, double* shb) {
+    unsigned long long* buf = k.slots + (size_t)(tag & 1u) * (4 * kSlotBlocks);
+    if (threadIdx.x == 0) {
+        const unsigned long long br = (unsigned long long)__double_as_longlong(tr);
+        const unsigned long long bi = (unsigned long long)__double_as_longlong(ti);
+        unsigned long long* w = buf + 4 * blockIdx.x;
+        __hip_atomic_store(w + 0, (br & 0xffffffff00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(w + 1, (br << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(w + 2, (bi & 0xffffffff00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(w + 3, (bi << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    block_sum2(tr, ti, sh);
-    return {tr, ti};
+    if (threadIdx.x < 64) {
+        double sr = 0.0, si = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += 64) {
+            const unsigned long long* w = buf + 4 * b;
+            unsigned long long q0, q1, q2, q3;
+            int spins = 0;
+            for (;;) {
+                q0 = __hip_atomic_load(w + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                q1 = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                q2 = __hip_atomic_load(w + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                q3 = __hip_atomic_load(w + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((unsigned)q0 == tag && (unsigned)q1 == tag && (unsigned)q2 == tag && (unsigned)q3 == tag) break;
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1 << 20)) {
+                    atomicExch(&k.ints[5], 1);
+                    break;
+                }
+                // after a timeout anywhere, later waits end quickly too
+                if ((spins & 1023) == 0 && __hip_atomic_load(&k.ints[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    break;
+            }
+            sr += __longlong_as_double((long long)((q0 & 0xffffffff00000000ull) | (q1 >> 32)));
+            si += __longlong_as_double((long long)((q2 & 0xffffffff00000000ull) | (q3 >> 32)));
+        }
+        wave_sum2(sr, si);
+        if (threadIdx.x == 0) {
+            shb[0] = sr;
+            shb[1] = si;
+        }
+    }
+    __syncthreads();
+    return {shb[0], shb[1]};
+}
+
+// Launch epoch of the cooperative Arnoldi kernels: read once at the start
+// (atomically, so it is never re-read), bumped by block 0 after its last
+// round; every block has read it before block 0 can pass round 0.
+__device__ __forceinline__ int step_epoch(KrylovDev& k) {
+    return __hip_atomic_load(&k.ints[6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void next_epoch(KrylovDev& k, int epoch) {
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_store(&k.ints[6], epoch + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block partial (tree in LDS) followed by the grid-wide exchange.
+__device__ __forceinline__ cx<double> grid_sum(double sr, double si, unsigned tag, KrylovDev& k, double* sh,
+                                               double* shb) {
+    block_sum2(sr, si, sh);
+    return exchange_sum(sr, si, tag, k, shb);
 }
 
 // One whole Arnoldi step across a cooperatively launched grid: modified
@@ -1078,9 +1219,11 @@ __global__ __launch_bounds__(RB) void arnoldi_coop_kernel(long long N, int j, cx
                                                           const cx<double>* __restrict__ V, long long ldv,
                                                           KrylovDev k) {
     __shared__ double sh[2 * RB];
+    __shared__ double shb[2];
     const long long stride = (long long)gridDim.x * RB;
     const long long t0 = (long long)blockIdx.x * RB + threadIdx.x;
     const int ldh = k.m + 1;
+    const int epoch = step_epoch(k);
     int round = 0;
     for (int i = 0; i <= j; ++i, ++round) {
         const cx<double>* vi = V + (size_t)i * ldv;
@@ -1090,7 +1233,7 @@ __global__ __launch_bounds__(RB) void arnoldi_coop_kernel(long long N, int j, cx
             sr += cv.re * wv.re + cv.im * wv.im;
             si += cv.re * wv.im - cv.im * wv.re;
         }
-        const cx<double> h = grid_sum(sr, si, round, k, sh);
+        const cx<double> h = grid_sum(sr, si, step_tag(epoch, round), k, sh, shb);
         if (blockIdx.x == 0 && threadIdx.x == 0) k.H[(size_t)j * ldh + i] = h;
         for (long long t = t0; t < N; t += stride) {
             const cx<double> cv = vi[t];
@@ -1105,8 +1248,9 @@ __global__ __launch_bounds__(RB) void arnoldi_coop_kernel(long long N, int j, cx
         const cx<double> wv = w[t];
         nr += wv.re * wv.re + wv.im * wv.im;
     }
-    const double hn = sqrt(grid_sum(nr, 0.0, round, k, sh).re);
+    const double hn = sqrt(grid_sum(nr, 0.0, step_tag(epoch, round), k, sh, shb).re);
     if (blockIdx.x == 0 && threadIdx.x == 0) givens_column(k, j, hn);
+    next_epoch(k, epoch);
     for (long long t = t0; t < N; t += stride) {
         const cx<double> wv = w[t];
         w[t] = hn == 0.0 ? cx<double>{0.0, 0.0} : cx<double>{wv.re / hn, wv.im / hn};
@@ -1115,20 +1259,13 @@ __global__ __launch_bounds__(RB) void arnoldi_coop_kernel(long long N, int j, cx
 
 // Register-resident variant for N <= 256 * RB * R: every thread keeps its R
 // entries of w and of the current basis vector in registers, prefetches the
-// next basis vector before the reduction's barrier (it does not depend on h),
-// and reduces with wave butterflies (every lane ends with the same bits) plus
-// one ordered pass over the four waves; after the barrier every wave sums the
-// block partials in index order, so all blocks use identical h.  Same MGS
-// order and one grid barrier per projection as arnoldi_coop_kernel.
-__device__ __forceinline__ void wave_sum2(double& a, double& b) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o, 64);
-        b += __shfl_xor(b, o, 64);
-    }
-}
+// next basis vector before the grid-wide exchange (it does not depend on h),
+// and forms its block partial with wave butterflies plus one ordered pass over
+// the four waves.  Same MGS order and one grid-wide exchange per projection as
+// arnoldi_coop_kernel.
 
-__device__ __forceinline__ cx<double> grid_sum_reg(double sr, double si, int round, KrylovDev& k, double* sh) {
+__device__ __forceinline__ cx<double> grid_sum_reg(double sr, double si, unsigned tag, KrylovDev& k, double* sh,
+                                                   double* shb) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     wave_sum2(sr, si);
     if (lane == 0) {
@@ -1136,25 +1273,15 @@ __device__ __forceinline__ cx<double> grid_sum_reg(double sr, double si, int rou
         sh[2 * wave + 1] = si;
     }
     __syncthreads();
-    cx<double>* buf = k.partials + (size_t)(round & 1) * 1024;
+    double tr = 0.0, ti = 0.0;
     if (threadIdx.x == 0) {
-        double tr = 0.0, ti = 0.0;
 #pragma unroll
         for (int w = 0; w < RB / 64; ++w) {
             tr += sh[2 * w];
             ti += sh[2 * w + 1];
         }
-        buf[blockIdx.x] = {tr, ti};
     }
-    grid_barrier(&k.ints[3], &k.ints[4], &k.ints[5]);
-    double tr = 0.0, ti = 0.0;
-    for (int b = lane; b < (int)gridDim.x; b += 64) {
-        const cx<double> v = buf[b];
-        tr += v.re;
-        ti += v.im;
-    }
-    wave_sum2(tr, ti);
-    return {tr, ti};
+    return exchange_sum(tr, ti, tag, k, shb);
 }
 
 template <int R>
@@ -1162,9 +1289,11 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
                                                          const cx<double>* __restrict__ V, long long ldv,
                                                          KrylovDev k) {
     __shared__ double sh[2 * (RB / 64)];
+    __shared__ double shb[2];
     const long long stride = (long long)gridDim.x * RB;
     const long long t0 = (long long)blockIdx.x * RB + threadIdx.x;
     const int ldh = k.m + 1;
+    const int epoch = step_epoch(k);
     cx<double> wr[R], vr[R], vn[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1188,7 +1317,7 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
                 vn[r] = t < N ? vi1[t] : cx<double>{0.0, 0.0};
             }
         }
-        const cx<double> h = grid_sum_reg(sr, si, round, k, sh);
+        const cx<double> h = grid_sum_reg(sr, si, step_tag(epoch, round), k, sh, shb);
         if (blockIdx.x == 0 && threadIdx.x == 0) k.H[(size_t)j * ldh + i] = h;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -1200,8 +1329,9 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
     double nr = 0.0, zero = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) nr += wr[r].re * wr[r].re + wr[r].im * wr[r].im;
-    const double hn = sqrt(grid_sum_reg(nr, zero, round, k, sh).re);
+    const double hn = sqrt(grid_sum_reg(nr, zero, step_tag(epoch, round), k, sh, shb).re);
     if (blockIdx.x == 0 && threadIdx.x == 0) givens_column(k, j, hn);
+    next_epoch(k, epoch);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const long long t = t0 + r * stride;
@@ -1230,6 +1360,7 @@ void launch_arnoldi_coop(long long N, int j, cx<double>* w, const cx<double>* V,
     pick(4, (const void*)arnoldi_reg_kernel<4>);
     pick(8, (const void*)arnoldi_reg_kernel<8>);
     pick(16, (const void*)arnoldi_reg_kernel<16>);
+    if (blocks > kSlotBlocks) throw Err{HH_EINVAL, "cooperative Arnoldi grid exceeds the exchange slots"};
     hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)blocks), dim3(RB), args, 0, s);
     if (e != hipSuccess) throw Err{HH_EHIP, std::string("cooperative Arnoldi launch: ") + hipGetErrorString(e)};
 }

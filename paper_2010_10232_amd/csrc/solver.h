@@ -78,11 +78,12 @@ struct SolverImpl {
     DevBuf Einv;             // dense inverse of A at level Lz (real; variable k)
     // constant k: E^-1 at level Lz by fast diagonalisation (1D eigenvectors and 1 / D)
     bool fdm = false;
-    DevBuf fdmVx, fdmVy, fdmDinv, fdmT1, fdmT2;
+    DevBuf fdmVx, fdmVxT, fdmVy, fdmDinv, fdmT1, fdmT2;
     // levels >= tail_start (all small) run their V-cycle in one workgroup
     int tail_start = 1 << 30;
     int tail_lds = 0, tail_lds32 = 0;   // dynamic LDS bytes (FP64 / FP32 tail)
     DevBuf tail64, tail32;              // TailDesc<double>, TailDesc<float>
+    DevBuf tail_img;                    // the tail's coefficient tables in their LDS layout
     int nL = 0, nZ = 0;
     long long ldZ = 0;       // leading dimension of Einv (even, >= nZ)
     // variable k, nZ >= 2048: E^-1 kept as its packed upper triangle (symmetric)

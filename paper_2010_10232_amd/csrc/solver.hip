@@ -104,7 +104,8 @@ static void invert_complex(int n, std::vector<zd>& A) {
 // --------------------------------------------------------------- helpers --
 static void fill_krylov(KrylovDev& k, DevBuf& blob, int m) {
     const size_t nH = (size_t)(m + 1) * m, nb = 2048;
-    size_t bytes = 16 * nH + 8 * m + 16 * m + 16 * (m + 1) + 16 * m + 8 * 8 + 16 * nb + 4 * 8;
+    const size_t nslots = 2 * 256 * 4;
+    size_t bytes = 16 * nH + 8 * m + 16 * m + 16 * (m + 1) + 16 * m + 8 * 8 + 16 * nb + 4 * 8 + 8 * nslots;
     blob.alloc(bytes + 256);
     char* p = blob.as<char>();
     k.m = m;
@@ -123,6 +124,8 @@ static void fill_krylov(KrylovDev& k, DevBuf& blob, int m) {
     k.scal = (double*)p;
     p += 8 * 8;
     k.ints = (int*)p;   // directly after scal: both reach the host in one transfer
+    p += 4 * 8;
+    k.slots = (unsigned long long*)p;   // zero words never carry a valid tag
     HH_HIP(hipMemset(blob.p, 0, blob.bytes));
 }
 
@@ -369,13 +372,10 @@ void SolverImpl::setup(hipStream_t s) {
                 d.k2c = k2c;
                 d.Minv = pick<T>(Minv64, Minv32).template as<cx<T>>();
                 d.lds_l0 = tail_start;
+                // coefficient tables of all tail levels first (one contiguous
+                // image, the same for both precisions), then the level vectors
                 int off = 0;
                 for (int l = tail_start; l <= L; ++l) {
-                    const int vb = (int)al16(lev[l]->N * (long long)sizeof(cx<T>));
-                    d.offb[l] = off;
-                    d.offx[l] = off + vb;
-                    d.offt[l] = off + 2 * vb;
-                    off += 3 * vb;
                     auto& t = d.lv[l];
                     t.o_kx = t.o_mx = t.o_ky = t.o_my = -1;
                     t.o_prow0x = t.o_prowx = t.o_prow0y = t.o_prowy = -1;
@@ -402,6 +402,15 @@ void SolverImpl::setup(hipStream_t s) {
                         t.o_pcol0y = take(4LL * tr.nc2);
                         t.o_pcoly = take(8LL * tr.nc2 * tr.rw2);
                     }
+                }
+                d.img16 = off / 16;
+                d.img = tail_img.as<uint4>();
+                for (int l = tail_start; l <= L; ++l) {
+                    const int vb = (int)al16(lev[l]->N * (long long)sizeof(cx<T>));
+                    d.offb[l] = off;
+                    d.offx[l] = off + vb;
+                    d.offt[l] = off + 2 * vb;
+                    off += 3 * vb;
                 }
                 d.lds_bytes = off;
                 for (int l = tail_start; l <= L; ++l) {
@@ -431,7 +440,39 @@ void SolverImpl::setup(hipStream_t s) {
             std::memset((void*)d64.data(), 0, sizeof(TailDesc<double>));
             std::memset((void*)d32.data(), 0, sizeof(TailDesc<float>));
             fill(d64[0], double{});
+            HH_REQUIRE(d64[0].img16 > 0, "tail coefficient image");
+            tail_img.alloc((size_t)d64[0].img16 * 16);
+            fill(d64[0], double{});
             fill(d32[0], float{});
+            HH_REQUIRE(d32[0].img16 == d64[0].img16, "tail image layout");
+            // the image: every table copied to its LDS offset (alignment gaps zero)
+            HH_HIP(hipMemset(tail_img.p, 0, tail_img.bytes));
+            {
+                unsigned char* img = tail_img.as<unsigned char>();
+                auto put = [&](int o, const void* src, long long bytes) {
+                    if (o < 0 || bytes <= 0) return;
+                    HH_REQUIRE(o + bytes <= (long long)tail_img.bytes, "tail image bounds");
+                    HH_HIP(hipMemcpy(img + o, src, (size_t)bytes, hipMemcpyDeviceToDevice));
+                };
+                for (int l = tail_start; l < L; ++l) {
+                    const LevelDev& v = *lev[l];
+                    const auto& t = d64[0].lv[l];
+                    const int bx = 2 * p + 1, by = is2d ? 2 * p + 1 : 1;
+                    const Transfer& tr = v.tr;
+                    put(t.o_kx, v.Kx.p, 8LL * v.n1 * bx);
+                    put(t.o_mx, v.Mx.p, 8LL * v.n1 * bx);
+                    put(t.o_ky, v.Ky.p, 8LL * v.n2 * by);
+                    put(t.o_my, v.My.p, 8LL * v.n2 * by);
+                    put(t.o_prow0x, tr.prow0x, 4LL * tr.nf1);
+                    put(t.o_prowx, tr.prowx, 8LL * tr.nf1 * tr.pw1);
+                    put(t.o_prow0y, tr.prow0y, 4LL * tr.nf2);
+                    put(t.o_prowy, tr.prowy, 8LL * tr.nf2 * tr.pw2);
+                    put(t.o_pcol0x, tr.pcol0x, 4LL * tr.nc1);
+                    put(t.o_pcolx, tr.pcolx, 8LL * tr.nc1 * tr.rw1);
+                    put(t.o_pcol0y, tr.pcol0y, 4LL * tr.nc2);
+                    put(t.o_pcoly, tr.pcoly, 8LL * tr.nc2 * tr.rw2);
+                }
+            }
             for (int l = tail_start; l <= L; ++l)
                 HH_REQUIRE(lev[l]->kind == KIND_SEP || lev[l]->kind == KIND_STENCIL, "tail level kind");
             upload(tail64, d64);
@@ -471,6 +512,12 @@ void SolverImpl::setup(hipStream_t s) {
                 dinv[(size_t)a * lz.n1 + b] = 1.0 / d;
             }
         upload(fdmVx, Vx);
+        {
+            std::vector<double> VxT(Vx.size());
+            for (int a = 0; a < lz.n1; ++a)
+                for (int b = 0; b < lz.n1; ++b) VxT[(size_t)b * lz.n1 + a] = Vx[(size_t)a * lz.n1 + b];
+            upload(fdmVxT, VxT);
+        }
         upload(fdmVy, Vy);
         upload(fdmDinv, dinv);
         fdmT1.alloc((size_t)nZ * 16);
@@ -850,8 +897,8 @@ void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStre
         tstart(2, s);
         if (fdm) {
             const LevelDev& lz = *lev[Lz];
-            launch_fdm_solve(lz.n2, lz.n1, fdmVx.as<double>(), fdmVy.as<double>(), fdmDinv.as<double>(), c,
-                             fdmT1.as<cx<double>>(), fdmT2.as<cx<double>>(), e, s);
+            launch_fdm_solve(lz.n2, lz.n1, fdmVx.as<double>(), fdmVxT.as<double>(), fdmVy.as<double>(),
+                             fdmDinv.as<double>(), c, fdmT1.as<cx<double>>(), fdmT2.as<cx<double>>(), e, s);
             // c, e, 1/D and both eigenvector matrices once
             tstop(2, 40.0 * nZ + 8.0 * ((double)lz.n1 * lz.n1 + (double)lz.n2 * lz.n2), s);
         } else {
