@@ -2,6 +2,8 @@
 // updates, dense products of the direct coarse solves, and the deterministic
 // reductions of the Arnoldi process.  The level-operator kernels are in
 // op_kernel.h.
+#include <algorithm>
+#include <climits>
 #include <type_traits>
 
 #include "hh_internal.h"
@@ -36,63 +38,118 @@ template void launch_op<float>(int, int, int, int, const OpArgs<float>&, hipStre
 // Knot-insertion transfers: restriction c = P^T r, prolongation x (+)= P e,
 // P = P_y (x) P_x stored as per-row / per-column runs.
 // --------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ cx<T> restrict_one(const Transfer& t, const cx<T>* __restrict__ r, long long idx) {
-    const int J1 = (int)(idx % t.nc1), J2 = (int)(idx / t.nc1);
+// W = 0: loops over the run widths as stored.  W > 0 (a bound on the widths,
+// known at compile time): unrolled loops over W entries with clamped,
+// always-valid addresses and zero weights past the run, so the loads of a
+// thread can be in flight at once; the terms are added in the same order.
+// FULL = false unrolls the inner loop only (fewer registers, for the
+// 1024-thread tail workgroup).
+template <class T, int W = 0, bool FULL = true>
+__device__ __forceinline__ cx<T> restrict_one(const Transfer& t, const cx<T>* __restrict__ r, int idx) {
+    const int J1 = idx % t.nc1, J2 = idx / t.nc1;
     const int i0x = t.pcol0x[J1], i0y = t.pcol0y[J2];
     T sr = 0, si = 0;
-    for (int a2 = 0; a2 < t.rw2; ++a2) {
-        const T wy = (T)t.pcoly[(size_t)J2 * t.rw2 + a2];
-        if (wy == T(0)) continue;
-        const cx<T>* row = r + (size_t)(i0y + a2) * t.nf1 + i0x;
-        T rr = 0, ri = 0;
-        for (int a1 = 0; a1 < t.rw1; ++a1) {
-            const T wx = (T)t.pcolx[(size_t)J1 * t.rw1 + a1];
-            const cx<T> v = row[a1];
-            rr += wx * v.re;
-            ri += wx * v.im;
+    if constexpr (W == 0) {
+        for (int a2 = 0; a2 < t.rw2; ++a2) {
+            const T wy = (T)t.pcoly[(size_t)J2 * t.rw2 + a2];
+            if (wy == T(0)) continue;
+            const cx<T>* row = r + (size_t)(i0y + a2) * t.nf1 + i0x;
+            T rr = 0, ri = 0;
+            for (int a1 = 0; a1 < t.rw1; ++a1) {
+                const T wx = (T)t.pcolx[(size_t)J1 * t.rw1 + a1];
+                const cx<T> v = row[a1];
+                rr += wx * v.re;
+                ri += wx * v.im;
+            }
+            sr += wy * rr;
+            si += wy * ri;
         }
-        sr += wy * rr;
-        si += wy * ri;
+    } else {
+        T wx[W], wy[W];
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const T vx = (T)t.pcolx[(size_t)J1 * t.rw1 + min(a, t.rw1 - 1)];
+            const T vy = (T)t.pcoly[(size_t)J2 * t.rw2 + min(a, t.rw2 - 1)];
+            wx[a] = a < t.rw1 ? vx : T(0);
+            wy[a] = a < t.rw2 ? vy : T(0);
+        }
+#pragma unroll FULL ? W : 1
+        for (int a2 = 0; a2 < W; ++a2) {
+            const cx<T>* row = r + (size_t)(i0y + min(a2, t.rw2 - 1)) * t.nf1 + i0x;
+            T rr = 0, ri = 0;
+#pragma unroll
+            for (int a1 = 0; a1 < W; ++a1) {
+                const cx<T> v = row[min(a1, t.rw1 - 1)];
+                rr += wx[a1] * v.re;
+                ri += wx[a1] * v.im;
+            }
+            sr += wy[a2] * rr;
+            si += wy[a2] * ri;
+        }
     }
     return {sr, si};
 }
 
-template <class T>
-__device__ __forceinline__ cx<T> prolong_one(const Transfer& t, const cx<T>* __restrict__ e, long long idx) {
-    const int I1 = (int)(idx % t.nf1), I2 = (int)(idx / t.nf1);
+template <class T, int W = 0, bool FULL = true>
+__device__ __forceinline__ cx<T> prolong_one(const Transfer& t, const cx<T>* __restrict__ e, int idx) {
+    const int I1 = idx % t.nf1, I2 = idx / t.nf1;
     const int j0x = t.prow0x[I1], j0y = t.prow0y[I2];
     T sr = 0, si = 0;
-    for (int b2 = 0; b2 < t.pw2; ++b2) {
-        const T wy = (T)t.prowy[(size_t)I2 * t.pw2 + b2];
-        if (wy == T(0)) continue;
-        const cx<T>* row = e + (size_t)(j0y + b2) * t.nc1 + j0x;
-        T rr = 0, ri = 0;
-        for (int b1 = 0; b1 < t.pw1; ++b1) {
-            const T wx = (T)t.prowx[(size_t)I1 * t.pw1 + b1];
-            const cx<T> v = row[b1];
-            rr += wx * v.re;
-            ri += wx * v.im;
+    if constexpr (W == 0) {
+        for (int b2 = 0; b2 < t.pw2; ++b2) {
+            const T wy = (T)t.prowy[(size_t)I2 * t.pw2 + b2];
+            if (wy == T(0)) continue;
+            const cx<T>* row = e + (size_t)(j0y + b2) * t.nc1 + j0x;
+            T rr = 0, ri = 0;
+            for (int b1 = 0; b1 < t.pw1; ++b1) {
+                const T wx = (T)t.prowx[(size_t)I1 * t.pw1 + b1];
+                const cx<T> v = row[b1];
+                rr += wx * v.re;
+                ri += wx * v.im;
+            }
+            sr += wy * rr;
+            si += wy * ri;
         }
-        sr += wy * rr;
-        si += wy * ri;
+    } else {
+        T wx[W], wy[W];
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+            const T vx = (T)t.prowx[(size_t)I1 * t.pw1 + min(b, t.pw1 - 1)];
+            const T vy = (T)t.prowy[(size_t)I2 * t.pw2 + min(b, t.pw2 - 1)];
+            wx[b] = b < t.pw1 ? vx : T(0);
+            wy[b] = b < t.pw2 ? vy : T(0);
+        }
+#pragma unroll FULL ? W : 1
+        for (int b2 = 0; b2 < W; ++b2) {
+            const cx<T>* row = e + (size_t)(j0y + min(b2, t.pw2 - 1)) * t.nc1 + j0x;
+            T rr = 0, ri = 0;
+#pragma unroll
+            for (int b1 = 0; b1 < W; ++b1) {
+                const cx<T> v = row[min(b1, t.pw1 - 1)];
+                rr += wx[b1] * v.re;
+                ri += wx[b1] * v.im;
+            }
+            sr += wy[b2] * rr;
+            si += wy[b2] * ri;
+        }
     }
     return {sr, si};
 }
 
-template <class T>
+// (level sizes below 2^31 unknowns, checked by the launchers: 32-bit indices)
+template <class T, int W>
 __global__ void restrict_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* __restrict__ c) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long long)t.nc1 * t.nc2) return;
-    c[idx] = restrict_one<T>(t, r, idx);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= t.nc1 * t.nc2) return;
+    c[idx] = restrict_one<T, W>(t, r, idx);
 }
 
 // x = xin + P e (xin may alias x; xin == nullptr: x = P e)
-template <class T>
+template <class T, int W>
 __global__ void prolong_kernel(Transfer t, const cx<T>* __restrict__ e, const cx<T>* xin, cx<T>* x) {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long long)t.nf1 * t.nf2) return;
-    const cx<T> v = prolong_one<T>(t, e, idx);
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= t.nf1 * t.nf2) return;
+    const cx<T> v = prolong_one<T, W>(t, e, idx);
     if (xin) {
         const cx<T> o = xin[idx];
         x[idx] = {o.re + v.re, o.im + v.im};
@@ -103,20 +160,54 @@ __global__ void prolong_kernel(Transfer t, const cx<T>* __restrict__ e, const cx
 
 static inline unsigned grid1d(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// The unrolled forms for run widths up to 7 (degree 5: restriction runs of
+// p + 2, prolongation runs of p + 1); wider runs take the loop form.
+template <class T>
+static const void* restrict_fn(int w) {
+    switch (w) {
+        case 1: return (const void*)restrict_kernel<T, 1>;
+        case 2: return (const void*)restrict_kernel<T, 2>;
+        case 3: return (const void*)restrict_kernel<T, 3>;
+        case 4: return (const void*)restrict_kernel<T, 4>;
+        case 5: return (const void*)restrict_kernel<T, 5>;
+        case 6: return (const void*)restrict_kernel<T, 6>;
+        case 7: return (const void*)restrict_kernel<T, 7>;
+    }
+    return (const void*)restrict_kernel<T, 0>;
+}
+template <class T>
+static const void* prolong_fn(int w) {
+    switch (w) {
+        case 1: return (const void*)prolong_kernel<T, 1>;
+        case 2: return (const void*)prolong_kernel<T, 2>;
+        case 3: return (const void*)prolong_kernel<T, 3>;
+        case 4: return (const void*)prolong_kernel<T, 4>;
+        case 5: return (const void*)prolong_kernel<T, 5>;
+        case 6: return (const void*)prolong_kernel<T, 6>;
+        case 7: return (const void*)prolong_kernel<T, 7>;
+    }
+    return (const void*)prolong_kernel<T, 0>;
+}
+
 template <class T>
 void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s) {
     const long long Nc = (long long)t.nc1 * t.nc2;
-    hipLaunchKernelGGL(restrict_kernel<T>, dim3(grid1d(Nc, 256)), dim3(256), 0, s, t, r, c);
-}
-template <class T>
-void launch_prolong(const Transfer& t, const cx<T>* e, cx<T>* x, int add, hipStream_t s) {
-    const long long Nf = (long long)t.nf1 * t.nf2;
-    hipLaunchKernelGGL(prolong_kernel<T>, dim3(grid1d(Nf, 256)), dim3(256), 0, s, t, e, add ? x : nullptr, x);
+    if (Nc <= 0) return;
+    if (Nc > INT_MAX || (long long)t.nf1 * t.nf2 > INT_MAX) throw Err{HH_EINVAL, "level too large for a transfer"};
+    void* args[] = {(void*)&t, (void*)&r, (void*)&c};
+    HH_HIP(hipLaunchKernel(restrict_fn<T>(std::max(t.rw1, t.rw2)), dim3(grid1d(Nc, 256)), dim3(256), args, 0, s));
 }
 template <class T>
 void launch_prolong_add(const Transfer& t, const cx<T>* e, const cx<T>* xin, cx<T>* xout, hipStream_t s) {
     const long long Nf = (long long)t.nf1 * t.nf2;
-    hipLaunchKernelGGL(prolong_kernel<T>, dim3(grid1d(Nf, 256)), dim3(256), 0, s, t, e, xin, xout);
+    if (Nf <= 0) return;
+    if (Nf > INT_MAX || (long long)t.nc1 * t.nc2 > INT_MAX) throw Err{HH_EINVAL, "level too large for a transfer"};
+    void* args[] = {(void*)&t, (void*)&e, (void*)&xin, (void*)&xout};
+    HH_HIP(hipLaunchKernel(prolong_fn<T>(std::max(t.pw1, t.pw2)), dim3(grid1d(Nf, 256)), dim3(256), args, 0, s));
+}
+template <class T>
+void launch_prolong(const Transfer& t, const cx<T>* e, cx<T>* x, int add, hipStream_t s) {
+    launch_prolong_add<T>(t, e, add ? x : nullptr, x, s);
 }
 template void launch_restrict<double>(const Transfer&, const cx<double>*, cx<double>*, hipStream_t);
 template void launch_restrict<float>(const Transfer&, const cx<float>*, cx<float>*, hipStream_t);
@@ -502,9 +593,46 @@ void launch_fdm_solve(int n2, int n1, const double* Vx, const double* VxT, const
 // order (deterministic).
 // --------------------------------------------------------------------------
 constexpr int TAIL_TB = 1024;
+// the tail workgroup's dynamic LDS: coefficient image, then the level vectors
+// (declared here so that every helper forms LDS addresses from it directly)
+extern __shared__ __align__(16) unsigned char tail_smem[];
 
-// (K - alpha M_k) x at unknown (I2, I1) of one level (x in LDS); the loops
-// run over the in-range neighbours only
+// Stencil rows r0, r0 + rstep, ... (offsets d2 = r - P) of (K - alpha M_k) x at
+// unknown (I2, I1) of a 2D tail level of degree P (x in LDS): K and M_k parts
+// summed separately.  The loop over a row is unrolled; out-of-range
+// neighbours read a valid entry and get a zero coefficient, so the loads of a
+// row do not wait for each other.
+template <class T, int P, bool SEP>
+__device__ __forceinline__ void tail_rows(const TailLevel<T>& L, double k2c, const cx<T>* x, int I2, int I1, int r0,
+                                          int rstep, T& kr, T& ki, T& mr, T& mi) {
+    constexpr int B = 2 * P + 1;
+    const int n1 = L.n1, N = L.n1 * L.n2, I = I2 * n1 + I1;
+    const double* kxr = L.Kx + I1 * B + P;
+    const double* mxr = L.Mx + I1 * B + P;
+    for (int r = r0; r < B; r += rstep) {
+        const int d2 = r - P;
+        const bool ok2 = (unsigned)(I2 + d2) < (unsigned)L.n2;
+        const T myv = (T)L.My[I2 * B + r], kyv = (T)L.Ky[I2 * B + r];
+        const cx<T>* row = x + (ok2 ? I2 + d2 : I2) * n1;
+#pragma unroll
+        for (int d1 = -P; d1 <= P; ++d1) {
+            const bool ok = ok2 && (unsigned)(I1 + d1) < (unsigned)n1;
+            const cx<T> v = row[ok ? I1 + d1 : I1];
+            const T kxv = (T)kxr[d1], mxv = (T)mxr[d1];
+            T kc = myv * kxv + kyv * mxv;
+            T mc = SEP ? (T)k2c * myv * mxv : L.S[(size_t)(r * B + d1 + P) * N + I];
+            kc = ok ? kc : T(0);
+            mc = ok ? mc : T(0);
+            kr += kc * v.re;
+            ki += kc * v.im;
+            mr += mc * v.re;
+            mi += mc * v.im;
+        }
+    }
+}
+
+// (K - alpha M_k) x at unknown (I2, I1) of one level (x in LDS), any shape:
+// the loops run over the in-range neighbours only.
 template <class T>
 __device__ __forceinline__ cx<T> tail_apply(const TailLevel<T>& L, double k2c, T are, T aim, const cx<T>* x, int I2,
                                             int I1, long long N) {
@@ -532,175 +660,220 @@ __device__ __forceinline__ cx<T> tail_apply(const TailLevel<T>& L, double k2c, T
     return {kr - (are * mr - aim * mi), ki - (are * mi + aim * mr)};
 }
 
-// y = b - M_beta x (RESID) or y = x + omega D^-1 (b - M_beta x) (SMOOTH), then a block barrier
-template <class T>
-__device__ void tail_op(const TailLevel<T>& L, const TailDesc<T>& D, int mode, const cx<T>* x, const cx<T>* b,
-                        cx<T>* y) {
-    const long long N = (long long)L.n1 * L.n2;
-    for (long long I = threadIdx.x; I < N; I += TAIL_TB) {
-        const int I1 = (int)(I % L.n1), I2 = (int)(I / L.n1);
-        const cx<T> a = tail_apply<T>(L, D.k2c, D.are, D.aim, x, I2, I1, N);
-        const cx<T> bv = b[I];
-        const T rr = bv.re - a.re, ri = bv.im - a.im;
-        if (mode == MODE_RESID) {
-            y[I] = {rr, ri};
-        } else {
-            const cx<T> dv = L.dinv[I], xv = x[I];
-            y[I] = {xv.re + L.omega * (dv.re * rr - dv.im * ri), xv.im + L.omega * (dv.re * ri + dv.im * rr)};
+// y = b - M_beta x (RESID) or y = x + omega D^-1 (b - M_beta x) (SMOOTH), then a
+// block barrier.  P > 0: G = 1, 2, 4 or 8 adjacent lanes share an unknown (the
+// most that the level's size allows in one pass of the workgroup), each takes
+// every G-th stencil row, and the partial sums meet in a butterfly over the G
+// lanes (a fixed order, so the result is reproducible).
+template <class T, int P>
+__device__ __forceinline__ void tail_op(const TailLevel<T>& L, const TailDesc<T>& D, int mode, const cx<T>* x,
+                                        const cx<T>* b, cx<T>* y) {
+    const int n1 = L.n1, N = L.n1 * L.n2;
+    if constexpr (P > 0) {
+        const int G = N <= TAIL_TB / 8 ? 8 : N <= TAIL_TB / 4 ? 4 : N <= TAIL_TB / 2 ? 2 : 1;
+        const int sub = threadIdx.x & (G - 1);
+        for (int I = threadIdx.x / G; I < N; I += TAIL_TB / G) {
+            const int I1 = I % n1, I2 = I / n1;
+            T kr = 0, ki = 0, mr = 0, mi = 0;
+            if (L.kind == KIND_SEP)
+                tail_rows<T, P, true>(L, D.k2c, x, I2, I1, sub, G, kr, ki, mr, mi);
+            else
+                tail_rows<T, P, false>(L, D.k2c, x, I2, I1, sub, G, kr, ki, mr, mi);
+            for (int o = G >> 1; o > 0; o >>= 1) {
+                kr += __shfl_xor(kr, o, 64);
+                ki += __shfl_xor(ki, o, 64);
+                mr += __shfl_xor(mr, o, 64);
+                mi += __shfl_xor(mi, o, 64);
+            }
+            if (sub == 0) {
+                const cx<T> bv = b[I];
+                const T rr = bv.re - (kr - (D.are * mr - D.aim * mi)), ri = bv.im - (ki - (D.are * mi + D.aim * mr));
+                if (mode == MODE_RESID) {
+                    y[I] = {rr, ri};
+                } else {
+                    const cx<T> dv = L.dinv[I], xv = x[I];
+                    y[I] = {xv.re + L.omega * (dv.re * rr - dv.im * ri), xv.im + L.omega * (dv.re * ri + dv.im * rr)};
+                }
+            }
+        }
+    } else {
+        for (int I = threadIdx.x; I < N; I += TAIL_TB) {
+            const int I1 = I % n1, I2 = I / n1;
+            const cx<T> a = tail_apply<T>(L, D.k2c, D.are, D.aim, x, I2, I1, N);
+            const cx<T> bv = b[I];
+            const T rr = bv.re - a.re, ri = bv.im - a.im;
+            if (mode == MODE_RESID) {
+                y[I] = {rr, ri};
+            } else {
+                const cx<T> dv = L.dinv[I], xv = x[I];
+                y[I] = {xv.re + L.omega * (dv.re * rr - dv.im * ri), xv.im + L.omega * (dv.re * ri + dv.im * rr)};
+            }
         }
     }
     __syncthreads();
 }
 
-// A level's descriptor with its coefficient pointers redirected to the LDS copies.
+// A level's descriptor (a level above the coarsest) with its bands and
+// transfer tables redirected to the LDS copies.  Every redirected pointer is
+// formed from tail_smem, so the compiler addresses them as LDS.
 template <class T>
-__device__ __forceinline__ TailLevel<T> tail_level(const TailDesc<T>& D, int l, unsigned char* smem) {
+__device__ __forceinline__ TailLevel<T> tail_level(const TailDesc<T>& D, int l) {
     TailLevel<T> v = D.lv[l];
-    v.Kx = (const double*)(smem + v.o_kx);
-    v.Mx = (const double*)(smem + v.o_mx);
-    v.Ky = (const double*)(smem + v.o_ky);
-    v.My = (const double*)(smem + v.o_my);
-    if (v.o_prow0x >= 0) {
-        v.tr.prow0x = (const int*)(smem + v.o_prow0x);
-        v.tr.prowx = (const double*)(smem + v.o_prowx);
-        v.tr.prow0y = (const int*)(smem + v.o_prow0y);
-        v.tr.prowy = (const double*)(smem + v.o_prowy);
-        v.tr.pcol0x = (const int*)(smem + v.o_pcol0x);
-        v.tr.pcolx = (const double*)(smem + v.o_pcolx);
-        v.tr.pcol0y = (const int*)(smem + v.o_pcol0y);
-        v.tr.pcoly = (const double*)(smem + v.o_pcoly);
-    }
+    v.Kx = (const double*)(tail_smem + v.o_kx);
+    v.Mx = (const double*)(tail_smem + v.o_mx);
+    v.Ky = (const double*)(tail_smem + v.o_ky);
+    v.My = (const double*)(tail_smem + v.o_my);
+    v.tr.prow0x = (const int*)(tail_smem + v.o_prow0x);
+    v.tr.prowx = (const double*)(tail_smem + v.o_prowx);
+    v.tr.prow0y = (const int*)(tail_smem + v.o_prow0y);
+    v.tr.prowy = (const double*)(tail_smem + v.o_prowy);
+    v.tr.pcol0x = (const int*)(tail_smem + v.o_pcol0x);
+    v.tr.pcolx = (const double*)(tail_smem + v.o_pcolx);
+    v.tr.pcol0y = (const int*)(tail_smem + v.o_pcol0y);
+    v.tr.pcoly = (const double*)(tail_smem + v.o_pcoly);
     return v;
 }
 
-template <class T>
+// P = 0: any level shapes; P > 0: 2D levels of degree P (unrolled stencils and
+// transfers; restriction runs <= P + 2, prolongation runs <= P + 1)
+template <class T, int P>
 __global__ __launch_bounds__(TAIL_TB) void vcycle_tail_kernel(const TailDesc<T>* __restrict__ Dp, int l0,
+                                                              const uint4* __restrict__ img, int n16,
                                                               const cx<T>* __restrict__ b0, cx<T>* __restrict__ x0) {
-    extern __shared__ __align__(16) unsigned char tail_smem[];
+    constexpr int WR = P > 0 ? P + 2 : 0, WP = P > 0 ? P + 1 : 0;
     const TailDesc<T>& D = *Dp;
     const int L = D.L;
     auto vb = [&](int l) { return (cx<T>*)(tail_smem + D.offb[l]); };
     auto vx = [&](int l) { return (cx<T>*)(tail_smem + D.offx[l]); };
     auto vt = [&](int l) { return (cx<T>*)(tail_smem + D.offt[l]); };
     {
-        // the level-l0 right-hand side and the coefficient image (the tables of
-        // every tail level, prepared at setup in their LDS layout): all loads
-        // are issued before the first LDS store, so staging costs one round trip
-        const long long N0 = (long long)D.lv[l0].n1 * D.lv[l0].n2;
+        // the coefficient image (the tables of every tail level, prepared at
+        // setup in their LDS layout) and the level-l0 right-hand side
+        const int N0 = D.lv[l0].n1 * D.lv[l0].n2;
         cx<T>* b = vb(l0);
         uint4* dst = (uint4*)tail_smem;
-        const uint4* __restrict__ img = D.img;
-        const int n16 = D.img16;
-        for (long long I0 = threadIdx.x; I0 < N0 || I0 < n16; I0 += 4LL * TAIL_TB) {
-            cx<T> bv[4];
-            uint4 iv[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const long long I = I0 + (long long)q * TAIL_TB;
-                if (I < N0) bv[q] = b0[I];
-                if (I < n16) iv[q] = img[I];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const long long I = I0 + (long long)q * TAIL_TB;
-                if (I < N0) b[I] = bv[q];
-                if (I < n16) dst[I] = iv[q];
-            }
-        }
+#pragma unroll 4
+        for (int I = threadIdx.x; I < n16; I += TAIL_TB) dst[I] = img[I];
+        for (int I = threadIdx.x; I < N0; I += TAIL_TB) b[I] = b0[I];
         __syncthreads();
     }
     // descent
     for (int l = l0; l < L; ++l) {
-        const TailLevel<T> lv = tail_level<T>(D, l, tail_smem);
-        const long long N = (long long)lv.n1 * lv.n2;
+        const TailLevel<T> lv = tail_level<T>(D, l);
+        const int N = lv.n1 * lv.n2;
         const cx<T>* b = vb(l);
         cx<T>* x = vx(l);
         cx<T>* t = vt(l);
         cx<T>* cur = ((D.nu_pre - 1) & 1) ? t : x;
         cx<T>* oth = ((D.nu_pre - 1) & 1) ? x : t;
-        for (long long I = threadIdx.x; I < N; I += TAIL_TB) {
+        for (int I = threadIdx.x; I < N; I += TAIL_TB) {
             const cx<T> dv = lv.dinv[I], bv = b[I];
             cur[I] = {lv.omega * (dv.re * bv.re - dv.im * bv.im), lv.omega * (dv.re * bv.im + dv.im * bv.re)};
         }
         __syncthreads();
         for (int i = 1; i < D.nu_pre; ++i) {
-            tail_op<T>(lv, D, MODE_SMOOTH, cur, b, oth);
+            tail_op<T, P>(lv, D, MODE_SMOOTH, cur, b, oth);
             cx<T>* tmp = cur;
             cur = oth;
             oth = tmp;
         }
-        tail_op<T>(lv, D, MODE_RESID, x, b, t);   // the spare vector holds the residual
-        const long long Nc = (long long)lv.tr.nc1 * lv.tr.nc2;
+        tail_op<T, P>(lv, D, MODE_RESID, x, b, t);   // the spare vector holds the residual
+        const int Nc = lv.tr.nc1 * lv.tr.nc2;
         cx<T>* bc = vb(l + 1);
-        for (long long I = threadIdx.x; I < Nc; I += TAIL_TB) bc[I] = restrict_one<T>(lv.tr, t, I);
+        for (int I = threadIdx.x; I < Nc; I += TAIL_TB) bc[I] = restrict_one<T, WR, false>(lv.tr, t, I);
         __syncthreads();
     }
     // coarsest level: x = M_beta^-1 b, one wave per row (lane-strided sums, butterfly)
     {
         const cx<T>* b = vb(L);
         cx<T>* x = vx(L);
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        for (int row = wave; row < D.nL; row += TAIL_TB / 64) {
-            T sr = 0, si = 0;
-            const cx<T>* a = D.Minv + (size_t)row * D.nL;
-            for (int j = lane; j < D.nL; j += 64) {
-                const cx<T> av = a[j], xv = b[j];
-                sr += av.re * xv.re - av.im * xv.im;
-                si += av.re * xv.im + av.im * xv.re;
+        // four rows per wave at a time, their loads issued together
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nL = D.nL;
+        constexpr int NW = TAIL_TB / 64;
+        for (int row0 = wave; row0 < nL; row0 += 4 * NW) {
+            T sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+            for (int j = lane; j < nL; j += 64) {
+                const cx<T> xv = b[j];
+                cx<T> av[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) av[q] = D.Minv[(size_t)min(row0 + q * NW, nL - 1) * nL + j];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sr[q] += av[q].re * xv.re - av[q].im * xv.im;
+                    si[q] += av[q].re * xv.im + av[q].im * xv.re;
+                }
             }
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                sr += __shfl_xor(sr, o, 64);
-                si += __shfl_xor(si, o, 64);
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    sr[q] += __shfl_xor(sr[q], o, 64);
+                    si[q] += __shfl_xor(si[q], o, 64);
+                }
+                if (lane == 0 && row0 + q * NW < nL) x[row0 + q * NW] = {sr[q], si[q]};
             }
-            if (lane == 0) x[row] = {sr, si};
         }
         __syncthreads();
     }
     // ascent
     for (int l = L - 1; l >= l0; --l) {
-        const TailLevel<T> lv = tail_level<T>(D, l, tail_smem);
-        const long long N = (long long)lv.n1 * lv.n2;
+        const TailLevel<T> lv = tail_level<T>(D, l);
+        const int N = lv.n1 * lv.n2;
         const cx<T>* b = vb(l);
         cx<T>* x = vx(l);
         cx<T>* t = vt(l);
         const cx<T>* xc = vx(l + 1);
         cx<T>* cur = (D.nu_post & 1) ? t : x;
         cx<T>* oth = (D.nu_post & 1) ? x : t;
-        for (long long I = threadIdx.x; I < N; I += TAIL_TB) {
-            const cx<T> v = prolong_one<T>(lv.tr, xc, I), o = x[I];
+        for (int I = threadIdx.x; I < N; I += TAIL_TB) {
+            const cx<T> v = prolong_one<T, WP, false>(lv.tr, xc, I), o = x[I];
             cur[I] = {o.re + v.re, o.im + v.im};
         }
         __syncthreads();
         for (int i = 0; i < D.nu_post; ++i) {
-            tail_op<T>(lv, D, MODE_SMOOTH, cur, b, oth);
+            tail_op<T, P>(lv, D, MODE_SMOOTH, cur, b, oth);
             cx<T>* tmp = cur;
             cur = oth;
             oth = tmp;
         }
     }
     {
-        const long long N0 = (long long)D.lv[l0].n1 * D.lv[l0].n2;
+        const int N0 = D.lv[l0].n1 * D.lv[l0].n2;
         const cx<T>* x = vx(l0);
-        for (long long I = threadIdx.x; I < N0; I += TAIL_TB) x0[I] = x[I];
+        for (int I = threadIdx.x; I < N0; I += TAIL_TB) x0[I] = x[I];
     }
 }
 
 template <class T>
+static const void* tail_fn(int P) {
+    switch (P) {
+        case 1: return (const void*)vcycle_tail_kernel<T, 1>;
+        case 2: return (const void*)vcycle_tail_kernel<T, 2>;
+        case 3: return (const void*)vcycle_tail_kernel<T, 3>;
+        case 4: return (const void*)vcycle_tail_kernel<T, 4>;
+        case 5: return (const void*)vcycle_tail_kernel<T, 5>;
+    }
+    return (const void*)vcycle_tail_kernel<T, 0>;
+}
+
+template <class T>
 void tail_prepare(int lds_bytes) {
-    HH_HIP(hipFuncSetAttribute((const void*)vcycle_tail_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               lds_bytes));
+    for (int P = 0; P <= 5; ++P)
+        HH_HIP(hipFuncSetAttribute(tail_fn<T>(P), hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes));
 }
 template void tail_prepare<double>(int);
 template void tail_prepare<float>(int);
 
 template <class T>
-void launch_vcycle_tail(const TailDesc<T>* desc, int l0, int lds_bytes, const cx<T>* b, cx<T>* x, hipStream_t s) {
-    hipLaunchKernelGGL(vcycle_tail_kernel<T>, dim3(1), dim3(TAIL_TB), (size_t)lds_bytes, s, desc, l0, b, x);
+void launch_vcycle_tail(const TailDesc<T>* desc, const void* img, int img16, int P, int l0, int lds_bytes,
+                        const cx<T>* b, cx<T>* x, hipStream_t s) {
+    void* args[] = {(void*)&desc, (void*)&l0, (void*)&img, (void*)&img16, (void*)&b, (void*)&x};
+    HH_HIP(hipLaunchKernel(tail_fn<T>(P), dim3(1), dim3(TAIL_TB), args, (size_t)lds_bytes, s));
 }
-template void launch_vcycle_tail<double>(const TailDesc<double>*, int, int, const cx<double>*, cx<double>*,
-                                         hipStream_t);
-template void launch_vcycle_tail<float>(const TailDesc<float>*, int, int, const cx<float>*, cx<float>*, hipStream_t);
+template void launch_vcycle_tail<double>(const TailDesc<double>*, const void*, int, int, int, int, const cx<double>*,
+                                         cx<double>*, hipStream_t);
+template void launch_vcycle_tail<float>(const TailDesc<float>*, const void*, int, int, int, int, const cx<float>*,
+                                        cx<float>*, hipStream_t);
 
 // --------------------------------------------------------------------------
 // Symmetric dense E^-1 (variable-k deflation level): only the upper triangle

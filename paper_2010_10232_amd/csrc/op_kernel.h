@@ -287,16 +287,20 @@ __global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
     const T are = a.are, aim = a.aim;
     const T k2c = (T)a.k2c;
     T wr = 0, wi = 0, vr = 0, vi = 0;
+    // every neighbour is loaded from a valid (clamped) address and replaced by
+    // zero when it lies outside the level, so no load waits behind a branch
 #pragma unroll
     for (int d2 = 0; d2 < BY; ++d2) {
         const int J2 = I2 + d2 - PY;
-        if (J2 < 0 || J2 >= n2) continue;
-        const size_t row = (size_t)J2 * n1;
+        const bool ok2 = (unsigned)J2 < (unsigned)n2;
+        const size_t row = (size_t)(ok2 ? J2 : I2) * n1;
         T u1r = 0, u1i = 0, u2r = 0, u2i = 0;
 #pragma unroll
         for (int d = 0; d < BX; ++d) {
             const int J1 = I1 + d - PX;
-            const cx<T> v = (J1 >= 0 && J1 < n1) ? a.x[row + J1] : cx<T>{T(0), T(0)};
+            const bool ok = ok2 && (unsigned)J1 < (unsigned)n1;
+            const cx<T> raw = a.x[row + (ok ? J1 : I1)];
+            const cx<T> v = ok ? raw : cx<T>{T(0), T(0)};
             u1r += kx[d] * v.re;
             u1i += kx[d] * v.im;
             u2r += mx[d] * v.re;

@@ -84,6 +84,7 @@ struct SolverImpl {
     int tail_lds = 0, tail_lds32 = 0;   // dynamic LDS bytes (FP64 / FP32 tail)
     DevBuf tail64, tail32;              // TailDesc<double>, TailDesc<float>
     DevBuf tail_img;                    // the tail's coefficient tables in their LDS layout
+    int tail_P = 0;                     // degree of the tail's unrolled form (2D), 0: loop form
     int nL = 0, nZ = 0;
     long long ldZ = 0;       // leading dimension of Einv (even, >= nZ)
     // variable k, nZ >= 2048: E^-1 kept as its packed upper triangle (symmetric)

@@ -159,7 +159,9 @@ void SolverImpl::tstart(int cls, hipStream_t s) {
     if (o.time_kernels != cls || ev_used >= kEvPairs) return;
     if (evpool.empty()) {
         evpool.resize(2 * kEvPairs);
-        for (auto& e : evpool) HH_HIP(hipEventCreate(&e));
+        // timing-only events: no system-scope fence (cache write-back and
+        // invalidation) around the timed kernels; read after the solve's sync
+        for (auto& e : evpool) HH_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     HH_HIP(hipEventRecord(evpool[2 * ev_used], s));
     ev_pending = ev_used;
@@ -404,7 +406,6 @@ void SolverImpl::setup(hipStream_t s) {
                     }
                 }
                 d.img16 = off / 16;
-                d.img = tail_img.as<uint4>();
                 for (int l = tail_start; l <= L; ++l) {
                     const int vb = (int)al16(lev[l]->N * (long long)sizeof(cx<T>));
                     d.offb[l] = off;
@@ -479,6 +480,7 @@ void SolverImpl::setup(hipStream_t s) {
             upload(tail32, d32);
             tail_lds = d64[0].lds_bytes;
             tail_lds32 = d32[0].lds_bytes;
+            tail_P = (is2d && p <= 5) ? p : 0;
             tail_prepare<double>(tail_lds);
             tail_prepare<float>(tail_lds32);
         }
@@ -777,7 +779,8 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
         return;
     }
     if (l >= tail_start) {
-        launch_vcycle_tail<T>(pick<T>(tail64, tail32).template as<TailDesc<T>>(), l,
+        launch_vcycle_tail<T>(pick<T>(tail64, tail32).template as<TailDesc<T>>(), tail_img.p,
+                              (int)(tail_img.bytes / 16), tail_P, l,
                               sizeof(T) == 8 ? tail_lds : tail_lds32, b, x, s);
         return;
     }
