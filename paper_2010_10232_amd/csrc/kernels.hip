@@ -4,6 +4,8 @@
 // op_kernel.h.
 #include <algorithm>
 #include <climits>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "hh_internal.h"
@@ -1512,6 +1514,24 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
     }
 }
 
+// Blocks of RB threads of kernel fn that the current device holds at once
+// (cached per device and kernel).
+static long long resident_capacity(const void* fn) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, long long> cache;
+    int dev = 0;
+    HH_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, fn});
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, cus = 0;
+    HH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, RB, 0));
+    HH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const long long cap = (long long)per_cu * cus;
+    cache[{dev, fn}] = cap;
+    return cap;
+}
+
 int coop_blocks(long long N) {
     long long b = (N + 8 * RB - 1) / (8 * RB);
     if (b < 1) b = 1;
@@ -1534,6 +1554,16 @@ void launch_arnoldi_coop(long long N, int j, cx<double>* w, const cx<double>* V,
     pick(8, (const void*)arnoldi_reg_kernel<8>);
     pick(16, (const void*)arnoldi_reg_kernel<16>);
     if (blocks > kSlotBlocks) throw Err{HH_EINVAL, "cooperative Arnoldi grid exceeds the exchange slots"};
+    // A cooperative launch guarantees that all blocks are resident, but the
+    // runtime serves it from a separate hardware queue: two cross-queue hand-offs
+    // per step.  A grid that needs at most an eighth of the blocks the device
+    // holds at once is launched on the stream's own queue instead: its blocks are
+    // placed as soon as CUs are free, and since the exchange's waits are bounded
+    // a shortage of CUs can only end in the timeout flag, never a hang.
+    if (blocks * 8 <= resident_capacity(fn)) {
+        HH_HIP(hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(RB), args, 0, s));
+        return;
+    }
     hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)blocks), dim3(RB), args, 0, s);
     if (e != hipSuccess) throw Err{HH_EHIP, std::string("cooperative Arnoldi launch: ") + hipGetErrorString(e)};
 }
