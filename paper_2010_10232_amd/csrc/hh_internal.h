@@ -225,6 +225,7 @@ struct TailDesc {
     int lds_bytes;                // LDS of the tail from level lds_l0 on
     int lds_l0;
     int img16;                    // coefficient image size in 16-byte units (LDS bytes [0, 16 img16))
+    int o_minv;                   // LDS offset of the transposed coarsest inverse (-1: read from Minv)
     int offb[kTailLevels], offx[kTailLevels], offt[kTailLevels];  // byte offsets of b, x, t in LDS
     TailLevel<T> lv[kTailLevels];
 };
@@ -267,8 +268,9 @@ void launch_set_identity(int n, long long ld, double* a, hipStream_t s);   // a:
 template <class T>
 void tail_prepare(int lds_bytes);
 template <class T>
-void launch_vcycle_tail(const TailDesc<T>* desc, const void* img, int img16, int P, int l0, int lds_bytes,
-                        const cx<T>* b, cx<T>* x, hipStream_t s);   // P: degree of 2D levels (unrolled form), 0: any
+void launch_vcycle_tail(const TailDesc<T>* desc, const void* img, int img16, const cx<T>* minv, int P, int l0,
+                        int lds_bytes, const cx<T>* b, cx<T>* x,
+                        hipStream_t s);   // P: degree of 2D levels (unrolled form), 0: any
 // e = (Vy (x) Vx) diag(dinv) (Vy (x) Vx)^T c on an [n2][n1] grid (t1, t2: N-vector scratch)
 void launch_fdm_solve(int n2, int n1, const double* Vx, const double* VxT, const double* Vy, const double* dinv,
                       const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s);

@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void fdm_gemm_kernel(int M, int N, int K, cons
 // 32-long j range, one element of the L rows) before any arithmetic, so a
 // pass costs one memory round trip; partial sums of the k (j) ranges are
 // added in range order in LDS (deterministic).
-constexpr int FDM2_TB = 512, FDM2_RB = 4, FDM2_CH = 32, FDM2_NMAX = 128;
+constexpr int FDM2_TB = 512, FDM2_RB = 2, FDM2_CH = 32, FDM2_NMAX = 128;
 __global__ __launch_bounds__(FDM2_TB) void fdm_pass_kernel(int n2, int n1, const double* __restrict__ Lm, int lsr,
                                                            int lsc, const cx<double>* __restrict__ X,
                                                            const double* __restrict__ R,
@@ -501,8 +501,8 @@ __global__ __launch_bounds__(FDM2_TB) void fdm_pass_kernel(int n2, int n1, const
         xv[q] = (g < G2 && k < n2) ? X[(size_t)k * n1 + col] : cx<double>{0.0, 0.0};
         rv[q] = (g < G1 && k < n1) ? R[(size_t)k * n1 + col] : 0.0;
     }
-    {
-        const int r = tid / FDM2_NMAX, k = tid % FDM2_NMAX, row = r0 + r;
+    for (int e = tid; e < FDM2_RB * FDM2_NMAX; e += FDM2_TB) {
+        const int r = e / FDM2_NMAX, k = e % FDM2_NMAX, row = r0 + r;
         Ls[r][k] = (row < n2 && k < n2) ? Lm[(size_t)row * lsr + (size_t)k * lsc] : 0.0;
     }
     __syncthreads();
@@ -520,8 +520,8 @@ __global__ __launch_bounds__(FDM2_TB) void fdm_pass_kernel(int n2, int n1, const
         }
     }
     __syncthreads();
-    {
-        const int r = tid / FDM2_NMAX, c = tid % FDM2_NMAX;
+    for (int e = tid; e < FDM2_RB * FDM2_NMAX; e += FDM2_TB) {
+        const int r = e / FDM2_NMAX, c = e % FDM2_NMAX;
         double ar = 0.0, ai = 0.0;
         if (c < n1)
             for (int gg = 0; gg < G2; ++gg) {
@@ -545,8 +545,8 @@ __global__ __launch_bounds__(FDM2_TB) void fdm_pass_kernel(int n2, int n1, const
         }
     }
     __syncthreads();
-    {
-        const int r = tid / FDM2_NMAX, c = tid % FDM2_NMAX, row = r0 + r;
+    for (int e = tid; e < FDM2_RB * FDM2_NMAX; e += FDM2_TB) {
+        const int r = e / FDM2_NMAX, c = e % FDM2_NMAX, row = r0 + r;
         if (c < n1 && row < n2) {
             double ar = 0.0, ai = 0.0;
             for (int gg = 0; gg < G1; ++gg) {
@@ -562,7 +562,6 @@ __global__ __launch_bounds__(FDM2_TB) void fdm_pass_kernel(int n2, int n1, const
 
 void launch_fdm_solve(int n2, int n1, const double* Vx, const double* VxT, const double* Vy, const double* dinv,
                       const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s) {
-    static_assert(FDM2_RB * FDM2_NMAX == FDM2_TB, "one L-row element and one output per thread");
     if (n1 <= FDM2_NMAX && n2 <= FDM2_NMAX) {
         const dim3 g((unsigned)((n2 + FDM2_RB - 1) / FDM2_RB)), b(FDM2_TB);
         // T2 = (Vy^T C Vx) ./ D
@@ -609,26 +608,50 @@ __device__ __forceinline__ void tail_rows(const TailLevel<T>& L, double k2c, con
                                           int rstep, T& kr, T& ki, T& mr, T& mi) {
     constexpr int B = 2 * P + 1;
     const int n1 = L.n1, N = L.n1 * L.n2, I = I2 * n1 + I1;
-    const double* kxr = L.Kx + I1 * B + P;
-    const double* mxr = L.Mx + I1 * B + P;
+    T kx[B], mx[B];   // this column's x bands, the same for every stencil row
+#pragma unroll
+    for (int d = 0; d < B; ++d) {
+        kx[d] = (T)L.Kx[I1 * B + d];
+        mx[d] = (T)L.Mx[I1 * B + d];
+    }
     for (int r = r0; r < B; r += rstep) {
         const int d2 = r - P;
         const bool ok2 = (unsigned)(I2 + d2) < (unsigned)L.n2;
         const T myv = (T)L.My[I2 * B + r], kyv = (T)L.Ky[I2 * B + r];
         const cx<T>* row = x + (ok2 ? I2 + d2 : I2) * n1;
+        if constexpr (SEP) {
+            // separable row: u1 = Kx-band sum, u2 = Mx-band sum of the row's values;
+            // K part my u1 + ky u2, mass part k^2 my u2
+            T u1r = 0, u1i = 0, u2r = 0, u2i = 0;
 #pragma unroll
-        for (int d1 = -P; d1 <= P; ++d1) {
-            const bool ok = ok2 && (unsigned)(I1 + d1) < (unsigned)n1;
-            const cx<T> v = row[ok ? I1 + d1 : I1];
-            const T kxv = (T)kxr[d1], mxv = (T)mxr[d1];
-            T kc = myv * kxv + kyv * mxv;
-            T mc = SEP ? (T)k2c * myv * mxv : L.S[(size_t)(r * B + d1 + P) * N + I];
-            kc = ok ? kc : T(0);
-            mc = ok ? mc : T(0);
-            kr += kc * v.re;
-            ki += kc * v.im;
-            mr += mc * v.re;
-            mi += mc * v.im;
+            for (int d1 = -P; d1 <= P; ++d1) {
+                const bool ok = ok2 && (unsigned)(I1 + d1) < (unsigned)n1;
+                const cx<T> raw = row[ok ? I1 + d1 : I1];
+                const T vr = ok ? raw.re : T(0), vi = ok ? raw.im : T(0);
+                u1r += kx[d1 + P] * vr;
+                u1i += kx[d1 + P] * vi;
+                u2r += mx[d1 + P] * vr;
+                u2i += mx[d1 + P] * vi;
+            }
+            const T km = (T)k2c * myv;
+            kr += myv * u1r + kyv * u2r;
+            ki += myv * u1i + kyv * u2i;
+            mr += km * u2r;
+            mi += km * u2i;
+        } else {
+#pragma unroll
+            for (int d1 = -P; d1 <= P; ++d1) {
+                const bool ok = ok2 && (unsigned)(I1 + d1) < (unsigned)n1;
+                const cx<T> v = row[ok ? I1 + d1 : I1];
+                T kc = myv * kx[d1 + P] + kyv * mx[d1 + P];
+                T mc = L.S[(size_t)(r * B + d1 + P) * N + I];
+                kc = ok ? kc : T(0);
+                mc = ok ? mc : T(0);
+                kr += kc * v.re;
+                ki += kc * v.im;
+                mr += mc * v.re;
+                mi += mc * v.im;
+            }
         }
     }
 }
@@ -741,6 +764,7 @@ __device__ __forceinline__ TailLevel<T> tail_level(const TailDesc<T>& D, int l) 
 template <class T, int P>
 __global__ __launch_bounds__(TAIL_TB) void vcycle_tail_kernel(const TailDesc<T>* __restrict__ Dp, int l0,
                                                               const uint4* __restrict__ img, int n16,
+                                                              const cx<T>* __restrict__ minv,
                                                               const cx<T>* __restrict__ b0, cx<T>* __restrict__ x0) {
     constexpr int WR = P > 0 ? P + 2 : 0, WP = P > 0 ? P + 1 : 0;
     const TailDesc<T>& D = *Dp;
@@ -757,6 +781,11 @@ __global__ __launch_bounds__(TAIL_TB) void vcycle_tail_kernel(const TailDesc<T>*
 #pragma unroll 4
         for (int I = threadIdx.x; I < n16; I += TAIL_TB) dst[I] = img[I];
         for (int I = threadIdx.x; I < N0; I += TAIL_TB) b[I] = b0[I];
+        if (D.o_minv >= 0) {   // the coarsest inverse, transposed (MT[c][r] = Minv[r][c])
+            cx<T>* MT = (cx<T>*)(tail_smem + D.o_minv);
+            const int nL = D.nL;
+            for (int i = threadIdx.x; i < nL * nL; i += TAIL_TB) MT[(i % nL) * nL + i / nL] = minv[i];
+        }
         __syncthreads();
     }
     // descent
@@ -789,30 +818,36 @@ __global__ __launch_bounds__(TAIL_TB) void vcycle_tail_kernel(const TailDesc<T>*
     {
         const cx<T>* b = vb(L);
         cx<T>* x = vx(L);
-        // four rows per wave at a time, their loads issued together
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nL = D.nL;
-        constexpr int NW = TAIL_TB / 64;
-        for (int row0 = wave; row0 < nL; row0 += 4 * NW) {
-            T sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
-            for (int j = lane; j < nL; j += 64) {
-                const cx<T> xv = b[j];
-                cx<T> av[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) av[q] = D.Minv[(size_t)min(row0 + q * NW, nL - 1) * nL + j];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    sr[q] += av[q].re * xv.re - av[q].im * xv.im;
-                    si[q] += av[q].re * xv.im + av[q].im * xv.re;
+        const int nL = D.nL;
+        if (D.o_minv >= 0) {
+            // transposed copy in LDS: one thread per row, j in increasing order
+            const cx<T>* MT = (const cx<T>*)(tail_smem + D.o_minv);
+            for (int r = threadIdx.x; r < nL; r += TAIL_TB) {
+                T sr = 0, si = 0;
+                for (int j = 0; j < nL; ++j) {
+                    const cx<T> av = MT[j * nL + r], xv = b[j];
+                    sr += av.re * xv.re - av.im * xv.im;
+                    si += av.re * xv.im + av.im * xv.re;
                 }
+                x[r] = {sr, si};
             }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
+        } else {
+            // one wave per row (lane-strided sums, butterfly)
+            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+            for (int row = wave; row < nL; row += TAIL_TB / 64) {
+                T sr = 0, si = 0;
+                const cx<T>* a = minv + (size_t)row * nL;
+                for (int j = lane; j < nL; j += 64) {
+                    const cx<T> av = a[j], xv = b[j];
+                    sr += av.re * xv.re - av.im * xv.im;
+                    si += av.re * xv.im + av.im * xv.re;
+                }
 #pragma unroll
                 for (int o = 32; o > 0; o >>= 1) {
-                    sr[q] += __shfl_xor(sr[q], o, 64);
-                    si[q] += __shfl_xor(si[q], o, 64);
+                    sr += __shfl_xor(sr, o, 64);
+                    si += __shfl_xor(si, o, 64);
                 }
-                if (lane == 0 && row0 + q * NW < nL) x[row0 + q * NW] = {sr[q], si[q]};
+                if (lane == 0) x[row] = {sr, si};
             }
         }
         __syncthreads();
@@ -867,15 +902,15 @@ template void tail_prepare<double>(int);
 template void tail_prepare<float>(int);
 
 template <class T>
-void launch_vcycle_tail(const TailDesc<T>* desc, const void* img, int img16, int P, int l0, int lds_bytes,
-                        const cx<T>* b, cx<T>* x, hipStream_t s) {
-    void* args[] = {(void*)&desc, (void*)&l0, (void*)&img, (void*)&img16, (void*)&b, (void*)&x};
+void launch_vcycle_tail(const TailDesc<T>* desc, const void* img, int img16, const cx<T>* minv, int P, int l0,
+                        int lds_bytes, const cx<T>* b, cx<T>* x, hipStream_t s) {
+    void* args[] = {(void*)&desc, (void*)&l0, (void*)&img, (void*)&img16, (void*)&minv, (void*)&b, (void*)&x};
     HH_HIP(hipLaunchKernel(tail_fn<T>(P), dim3(1), dim3(TAIL_TB), args, (size_t)lds_bytes, s));
 }
-template void launch_vcycle_tail<double>(const TailDesc<double>*, const void*, int, int, int, int, const cx<double>*,
-                                         cx<double>*, hipStream_t);
-template void launch_vcycle_tail<float>(const TailDesc<float>*, const void*, int, int, int, int, const cx<float>*,
-                                        cx<float>*, hipStream_t);
+template void launch_vcycle_tail<double>(const TailDesc<double>*, const void*, int, const cx<double>*, int, int, int,
+                                         const cx<double>*, cx<double>*, hipStream_t);
+template void launch_vcycle_tail<float>(const TailDesc<float>*, const void*, int, const cx<float>*, int, int, int,
+                                        const cx<float>*, cx<float>*, hipStream_t);
 
 // --------------------------------------------------------------------------
 // Symmetric dense E^-1 (variable-k deflation level): only the upper triangle

@@ -413,6 +413,13 @@ void SolverImpl::setup(hipStream_t s) {
                     d.offt[l] = off + 2 * vb;
                     off += 3 * vb;
                 }
+                // the coarsest inverse too, when small and within the budget
+                const long long mb = (long long)nL * nL * (long long)sizeof(cx<T>);
+                d.o_minv = -1;
+                if (mb <= 32 * 1024 && off + al16(mb) <= budget) {
+                    d.o_minv = off;
+                    off += (int)al16(mb);
+                }
                 d.lds_bytes = off;
                 for (int l = tail_start; l <= L; ++l) {
                     LevelDev& lv = *lev[l];
@@ -780,7 +787,7 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
     }
     if (l >= tail_start) {
         launch_vcycle_tail<T>(pick<T>(tail64, tail32).template as<TailDesc<T>>(), tail_img.p,
-                              (int)(tail_img.bytes / 16), tail_P, l,
+                              (int)(tail_img.bytes / 16), pick<T>(Minv64, Minv32).template as<cx<T>>(), tail_P, l,
                               sizeof(T) == 8 ? tail_lds : tail_lds32, b, x, s);
         return;
     }
