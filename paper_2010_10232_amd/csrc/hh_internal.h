@@ -236,7 +236,8 @@ void launch_op_deg(int kind, int mode, int py, const OpArgs<T>& a, hipStream_t s
 template <class T>
 void launch_op(int kind, int mode, int px, int py, const OpArgs<T>& a, hipStream_t s);
 template <class T>
-void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s);
+void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s, const cx<T>* dinv = nullptr,
+                     T omega = T(0), cx<T>* xs = nullptr);   // dinv: also xs = omega D^-1 c
 template <class T>
 void launch_prolong(const Transfer& t, const cx<T>* e, cx<T>* x, int add, hipStream_t s);
 template <class T>   // xout = xin + P e (xin may alias xout)

@@ -139,11 +139,19 @@ __device__ __forceinline__ cx<T> prolong_one(const Transfer& t, const cx<T>* __r
 }
 
 // (level sizes below 2^31 unknowns, checked by the launchers: 32-bit indices)
+// dinv != nullptr: also the coarse level's first damped Jacobi sweep from zero,
+// xs = omega D^-1 c, formed exactly as jacobi0_kernel forms it.
 template <class T, int W>
-__global__ void restrict_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* __restrict__ c) {
+__global__ void restrict_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* __restrict__ c,
+                                const cx<T>* __restrict__ dinv, T omega, cx<T>* __restrict__ xs) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= t.nc1 * t.nc2) return;
-    c[idx] = restrict_one<T, W>(t, r, idx);
+    const cx<T> v = restrict_one<T, W>(t, r, idx);
+    c[idx] = v;
+    if (dinv) {
+        const cx<T> d = dinv[idx];
+        xs[idx] = {omega * (d.re * v.re - d.im * v.im), omega * (d.re * v.im + d.im * v.re)};
+    }
 }
 
 // x = xin + P e (xin may alias x; xin == nullptr: x = P e)
@@ -192,11 +200,12 @@ static const void* prolong_fn(int w) {
 }
 
 template <class T>
-void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s) {
+void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s, const cx<T>* dinv, T omega,
+                     cx<T>* xs) {
     const long long Nc = (long long)t.nc1 * t.nc2;
     if (Nc <= 0) return;
     if (Nc > INT_MAX || (long long)t.nf1 * t.nf2 > INT_MAX) throw Err{HH_EINVAL, "level too large for a transfer"};
-    void* args[] = {(void*)&t, (void*)&r, (void*)&c};
+    void* args[] = {(void*)&t, (void*)&r, (void*)&c, (void*)&dinv, (void*)&omega, (void*)&xs};
     HH_HIP(hipLaunchKernel(restrict_fn<T>(std::max(t.rw1, t.rw2)), dim3(grid1d(Nc, 256)), dim3(256), args, 0, s));
 }
 template <class T>
@@ -211,8 +220,10 @@ template <class T>
 void launch_prolong(const Transfer& t, const cx<T>* e, cx<T>* x, int add, hipStream_t s) {
     launch_prolong_add<T>(t, e, add ? x : nullptr, x, s);
 }
-template void launch_restrict<double>(const Transfer&, const cx<double>*, cx<double>*, hipStream_t);
-template void launch_restrict<float>(const Transfer&, const cx<float>*, cx<float>*, hipStream_t);
+template void launch_restrict<double>(const Transfer&, const cx<double>*, cx<double>*, hipStream_t, const cx<double>*,
+                                      double, cx<double>*);
+template void launch_restrict<float>(const Transfer&, const cx<float>*, cx<float>*, hipStream_t, const cx<float>*,
+                                     float, cx<float>*);
 template void launch_prolong<double>(const Transfer&, const cx<double>*, cx<double>*, int, hipStream_t);
 template void launch_prolong_add<double>(const Transfer&, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t);
 template void launch_prolong<float>(const Transfer&, const cx<float>*, cx<float>*, int, hipStream_t);
@@ -621,17 +632,18 @@ __device__ __forceinline__ void tail_rows(const TailLevel<T>& L, double k2c, con
         const cx<T>* row = x + (ok2 ? I2 + d2 : I2) * n1;
         if constexpr (SEP) {
             // separable row: u1 = Kx-band sum, u2 = Mx-band sum of the row's values;
-            // K part my u1 + ky u2, mass part k^2 my u2
+            // K part my u1 + ky u2, mass part k^2 my u2.  The 1D bands are zero
+            // at neighbours outside the level, so an out-of-range neighbour (read
+            // at a clamped, valid address: a finite value) adds zero unmasked.
             T u1r = 0, u1i = 0, u2r = 0, u2i = 0;
 #pragma unroll
             for (int d1 = -P; d1 <= P; ++d1) {
-                const bool ok = ok2 && (unsigned)(I1 + d1) < (unsigned)n1;
-                const cx<T> raw = row[ok ? I1 + d1 : I1];
-                const T vr = ok ? raw.re : T(0), vi = ok ? raw.im : T(0);
-                u1r += kx[d1 + P] * vr;
-                u1i += kx[d1 + P] * vi;
-                u2r += mx[d1 + P] * vr;
-                u2i += mx[d1 + P] * vi;
+                const bool ok = (unsigned)(I1 + d1) < (unsigned)n1;
+                const cx<T> v = row[ok ? I1 + d1 : I1];
+                u1r += kx[d1 + P] * v.re;
+                u1i += kx[d1 + P] * v.im;
+                u2r += mx[d1 + P] * v.re;
+                u2i += mx[d1 + P] * v.im;
             }
             const T km = (T)k2c * myv;
             kr += myv * u1r + kyv * u2r;

@@ -269,10 +269,10 @@ template <int PX, int PY, int KIND, int MODE, class T>
 __global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
     constexpr int BX = 2 * PX + 1, BY = 2 * PY + 1;
     const int n1 = a.n1, n2 = a.n2;
-    const long long N = (long long)n1 * n2;
-    const long long I = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int N = n1 * n2;   // at most kOpDirectMax: 32-bit indices
+    const int I = blockIdx.x * 256 + threadIdx.x;
     if (I >= N) return;
-    const int I1 = (int)(I % n1), I2 = (int)(I / n1);
+    const int I1 = I % n1, I2 = I / n1;
     T kx[BX], mx[BX], ky[BY], my[BY];
 #pragma unroll
     for (int d = 0; d < BX; ++d) {
@@ -299,6 +299,9 @@ __global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
         for (int d = 0; d < BX; ++d) {
             const int J1 = I1 + d - PX;
             const bool ok = ok2 && (unsigned)J1 < (unsigned)n1;
+            // (masking the value here, although the constant-k bands are zero at
+            // such neighbours, measured faster: the compiler then keeps every
+            // load of the thread in flight)
             const cx<T> raw = a.x[row + (ok ? J1 : I1)];
             const cx<T> v = ok ? raw : cx<T>{T(0), T(0)};
             u1r += kx[d] * v.re;

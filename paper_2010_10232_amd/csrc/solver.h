@@ -118,7 +118,8 @@ struct SolverImpl {
     template <class T>
     void op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s);
     template <class T>
-    void vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s);
+    void vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s,
+                     bool x_swept = false);   // x_swept: x already holds the first sweep from zero
     template <class T>
     void vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s);
     void precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s);

@@ -779,7 +779,7 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
 }
 
 template <class T>
-void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
+void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_swept) {
     LevelDev& lv = *lev[l];
     if (l == L) {
         launch_gemv<cx<T>, T>(nL, pick<T>(Minv64, Minv32).template as<cx<T>>(), b, x, s);
@@ -809,7 +809,7 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
         // further sweeps ends in x
         cx<T>* cur = ((o.nu_pre - 1) & 1) ? t : x;
         cx<T>* oth = ((o.nu_pre - 1) & 1) ? x : t;
-        launch_jacobi0<T>(lv.N, dinv, (T)lv.omega, b, cur, s);
+        if (!x_swept) launch_jacobi0<T>(lv.N, dinv, (T)lv.omega, b, cur, s);
         for (int i = 1; i < o.nu_pre; ++i) {
             op<T>(l, MODE_SMOOTH, true, cur, b, oth, s);
             std::swap(cur, oth);
@@ -819,8 +819,16 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
     LevelDev& lc = *lev[l + 1];
     cx<T>* bc = pick<T>(lc.b64, lc.b32).template as<cx<T>>();
     cx<T>* xc = pick<T>(lc.x64, lc.x32).template as<cx<T>>();
-    launch_restrict<T>(lv.tr, r, bc, s);
-    vcycle_once<T>(l + 1, bc, xc, s);
+    // with one pre-sweep on a coarser level that runs as separate kernels, the
+    // restriction also forms that level's first sweep (x = omega D^-1 b)
+    if (o.nu_pre == 1 && l + 1 < tail_start && l + 1 < L) {
+        const cx<T>* dinvc = pick<T>(lc.Dinv64, lc.Dinv32).template as<cx<T>>();
+        launch_restrict<T>(lv.tr, r, bc, s, dinvc, (T)lc.omega, xc);
+        vcycle_once<T>(l + 1, bc, xc, s, true);
+    } else {
+        launch_restrict<T>(lv.tr, r, bc, s);
+        vcycle_once<T>(l + 1, bc, xc, s);
+    }
     if (learned) {
         launch_prolong<T>(lv.tr, xc, x, 1, s);
         for (int i = 0; i < o.nu_post; ++i) {
