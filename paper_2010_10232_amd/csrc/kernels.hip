@@ -934,6 +934,7 @@ template void launch_vcycle_tail<float>(const TailDesc<float>*, const void*, int
 // result is deterministic.
 // --------------------------------------------------------------------------
 constexpr int SYT = 128;
+constexpr long long SYM_STRIDE = (long long)SYT * SYT;   // tile stride (doubles)
 __device__ __host__ inline long long sym_tile_index(long long I, long long J, long long nt) {
     return I * nt - I * (I - 1) / 2 + (J - I);
 }
@@ -941,14 +942,14 @@ long long sym_tiles(int n) {
     const long long nt = (n + SYT - 1) / SYT;
     return nt * (nt + 1) / 2;
 }
-long long sym_packed_doubles(int n) { return sym_tiles(n) * SYT * SYT; }
+long long sym_packed_doubles(int n) { return sym_tiles(n) * SYM_STRIDE; }
 
 __global__ __launch_bounds__(256) void sym_pack_kernel(int n, long long ld, const double* __restrict__ D,
                                                        double* __restrict__ P) {
     const int I = blockIdx.y, J = blockIdx.x;
     if (J < I) return;
     const long long nt = (n + SYT - 1) / SYT;
-    double* T = P + sym_tile_index(I, J, nt) * SYT * SYT;
+    double* T = P + sym_tile_index(I, J, nt) * SYM_STRIDE;
     for (int e = threadIdx.x; e < SYT * SYT; e += 256) {
         const int rr = e / SYT, cc = e % SYT;
         const long long r = (long long)I * SYT + rr, c = (long long)J * SYT + cc;
@@ -967,18 +968,26 @@ void launch_sym_pack(int n, long long ld, const double* D, double* P, hipStream_
 // the lane pair) -- 32 shuffles per lane instead of a butterfly per row.
 // Column sums (off-diagonal tiles): per lane over its rows, then the four
 // waves in order.
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+
+// One workgroup per stored tile, in storage order (a 1D grid over the
+// triangle: no idle workgroups), the tile streamed with nontemporal loads.
 __global__ __launch_bounds__(256) void symv_tiles_kernel(int n, const double* __restrict__ P,
                                                          const cx<double>* __restrict__ x,
                                                          cx<double>* __restrict__ rowpart,
                                                          cx<double>* __restrict__ colpart) {
-    const int I = blockIdx.y, J = blockIdx.x;
-    if (J < I) return;
     __shared__ cx<double> xs[SYT];
     __shared__ cx<double> us[SYT];
     __shared__ double vs[4][SYT][2];
     const long long nt = (n + SYT - 1) / SYT;
-    const long long tidx = sym_tile_index(I, J, nt);
-    const double* T = P + tidx * SYT * SYT;
+    const long long tidx = blockIdx.x;
+    // tile row I: the last row whose first tile index I nt - I (I - 1) / 2 is <= tidx
+    long long I = (long long)((2.0 * nt + 1.0 - sqrt((2.0 * nt + 1.0) * (2.0 * nt + 1.0) - 8.0 * (double)tidx)) / 2.0);
+    I = I < 0 ? 0 : (I >= nt ? nt - 1 : I);
+    while (I > 0 && sym_tile_index(I, I, nt) > tidx) --I;
+    while (I + 1 < nt && sym_tile_index(I + 1, I + 1, nt) <= tidx) ++I;
+    const long long J = I + (tidx - sym_tile_index(I, I, nt));
+    const double* T = P + tidx * SYM_STRIDE;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (threadIdx.x < SYT) {
         const long long r = (long long)I * SYT + threadIdx.x;
@@ -994,7 +1003,7 @@ __global__ __launch_bounds__(256) void symv_tiles_kernel(int n, const double* __
     const double* Tw = T + (size_t)(32 * w) * SYT + 2 * lane;
 #pragma unroll
     for (int q = 0; q < 32; ++q) {
-        const double2 a = *(const double2*)(Tw + (size_t)q * SYT);
+        const dbl2v a = __builtin_nontemporal_load((const dbl2v*)(Tw + (size_t)q * SYT));
         ur[q] = a.x * xj0.re + a.y * xj1.re;
         ui[q] = a.x * xj0.im + a.y * xj1.im;
         if (off) {
@@ -1058,7 +1067,7 @@ __global__ __launch_bounds__(SYT) void symv_reduce_kernel(int n, const cx<double
 void launch_symv(int n, const double* P, const cx<double>* x, cx<double>* rowpart, cx<double>* colpart,
                  cx<double>* y, hipStream_t s) {
     const unsigned nt = (unsigned)((n + SYT - 1) / SYT);
-    hipLaunchKernelGGL(symv_tiles_kernel, dim3(nt, nt), dim3(256), 0, s, n, P, x, rowpart, colpart);
+    hipLaunchKernelGGL(symv_tiles_kernel, dim3((unsigned)sym_tiles(n)), dim3(256), 0, s, n, P, x, rowpart, colpart);
     hipLaunchKernelGGL(symv_reduce_kernel, dim3(nt), dim3(SYT), 0, s, n, rowpart, colpart, y);
 }
 
@@ -1603,11 +1612,12 @@ void launch_arnoldi_coop(long long N, int j, cx<double>* w, const cx<double>* V,
     if (blocks > kSlotBlocks) throw Err{HH_EINVAL, "cooperative Arnoldi grid exceeds the exchange slots"};
     // A cooperative launch guarantees that all blocks are resident, but the
     // runtime serves it from a separate hardware queue: two cross-queue hand-offs
-    // per step.  A grid that needs at most an eighth of the blocks the device
+    // per step.  A grid that needs at most a quarter of the blocks the device
     // holds at once is launched on the stream's own queue instead: its blocks are
-    // placed as soon as CUs are free, and since the exchange's waits are bounded
-    // a shortage of CUs can only end in the timeout flag, never a hang.
-    if (blocks * 8 <= resident_capacity(fn)) {
+    // placed as soon as CUs are free (four such grids fit side by side), and since
+    // the exchange's waits are bounded a shortage of CUs can only end in the
+    // timeout flag, never a hang.
+    if (blocks * 4 <= resident_capacity(fn)) {
         HH_HIP(hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(RB), args, 0, s));
         return;
     }

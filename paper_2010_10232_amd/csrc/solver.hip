@@ -923,7 +923,7 @@ void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStre
             if (sym) {
                 launch_symv(nZ, EinvP.as<double>(), c, symRow.as<cx<double>>(), symCol.as<cx<double>>(), e, s);
                 // the stored triangle once, c and e
-                tstop(2, 8.0 * (double)sym_packed_doubles(nZ) + 32.0 * nZ, s);
+                tstop(2, 8.0 * 128.0 * 128.0 * (double)sym_tiles(nZ) + 32.0 * nZ, s);
             } else {
                 launch_gemv_real(nZ, ldZ, Einv.as<double>(), c, e, s);
                 tstop(2, 8.0 * nZ * (double)nZ + 32.0 * nZ, s);
