@@ -161,6 +161,7 @@ struct OpArgs {
     cx<T>* y;
     const cx<T>* dinv;
     T omega;
+    cx<T>* xo;             // MODE_RESID: if set, also xo = omega D^-1 y (a first sweep on y)
 };
 
 struct Transfer {
@@ -285,10 +286,12 @@ void launch_norm_givens(long long N, int j, cx<double>* w, const cx<double>* V, 
                         KrylovDev& k, hipStream_t s);
 void launch_lsq(KrylovDev& k, hipStream_t s, int ncols = -1);
 // fused Arnoldi step (MGS + norm + Givens + normalise): one workgroup for short
-// vectors, a cooperatively launched grid otherwise
+// vectors, otherwise a grid of resident workgroups (launch_arnoldi_grid: false
+// when neither a resident launch fits `concurrent` grids nor coop_ok allows a
+// cooperative one; the caller then runs one kernel per projection)
 constexpr long long kSmallArnoldi = 4096;
-void launch_arnoldi_coop(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv,
-                         KrylovDev& k, hipStream_t s);
+bool launch_arnoldi_grid(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
+                         hipStream_t s, int concurrent, bool coop_ok);
 void launch_arnoldi_small(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv,
                           KrylovDev& k, hipStream_t s);
 void launch_update(long long N, const cx<double>* Z, long long ldz, KrylovDev& k, cx<double>* u,

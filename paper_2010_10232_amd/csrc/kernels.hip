@@ -1595,8 +1595,8 @@ int coop_blocks(long long N) {
     return (int)b;
 }
 
-void launch_arnoldi_coop(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
-                         hipStream_t s) {
+bool launch_arnoldi_grid(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
+                         hipStream_t s, int concurrent, bool coop_ok) {
     void* args[] = {&N, &j, &w, &V, &ldv, &k};
     const void* fn = (const void*)arnoldi_coop_kernel;
     long long blocks = coop_blocks(N);
@@ -1612,17 +1612,21 @@ void launch_arnoldi_coop(long long N, int j, cx<double>* w, const cx<double>* V,
     if (blocks > kSlotBlocks) throw Err{HH_EINVAL, "cooperative Arnoldi grid exceeds the exchange slots"};
     // A cooperative launch guarantees that all blocks are resident, but the
     // runtime serves it from a separate hardware queue: two cross-queue hand-offs
-    // per step.  A grid that needs at most a quarter of the blocks the device
-    // holds at once is launched on the stream's own queue instead: its blocks are
-    // placed as soon as CUs are free (four such grids fit side by side), and since
-    // the exchange's waits are bounded a shortage of CUs can only end in the
-    // timeout flag, never a hang.
-    if (blocks * 4 <= resident_capacity(fn)) {
+    // per step.  A grid small enough that `concurrent` such grids (at most that
+    // many Arnoldi steps run at once: 4 for single solves, 16 in batched mode,
+    // whose pools have 8 streams) fit in the blocks the device holds at once is
+    // launched on the stream's own queue instead: its blocks are placed as soon
+    // as CUs are free, and since the exchange's waits are bounded a shortage of
+    // CUs can only end in the timeout flag, never a hang.  Otherwise the
+    // cooperative launch when allowed; else nothing is launched (false).
+    if (blocks * concurrent <= resident_capacity(fn)) {
         HH_HIP(hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(RB), args, 0, s));
-        return;
+        return true;
     }
+    if (!coop_ok) return false;
     hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)blocks), dim3(RB), args, 0, s);
     if (e != hipSuccess) throw Err{HH_EHIP, std::string("cooperative Arnoldi launch: ") + hipGetErrorString(e)};
+    return true;
 }
 
 // ||x||^2 into *out (plain reduction).

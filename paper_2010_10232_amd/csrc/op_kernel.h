@@ -39,6 +39,15 @@ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
 // output rows in registers (a sliding window): input row r feeds output rows
 // r-2p .. r through the y-bands, after which output row r-2p is complete and
 // is written out (with the residual / Jacobi epilogue).
+// MODE_RESID with a.xo set: the next level-solve's first damped Jacobi sweep
+// from zero on the residual just formed, xo = omega D^-1 r, exactly as
+// jacobi0_kernel forms it.
+template <class T>
+__device__ __forceinline__ cx<T> first_sweep(const OpArgs<T>& a, long long I, cx<T> r) {
+    const cx<T> d = a.dinv[I];
+    return {a.omega * (d.re * r.re - d.im * r.im), a.omega * (d.re * r.im + d.im * r.re)};
+}
+
 template <int PX, int PY, int KIND, int MODE, class T>
 __global__ __launch_bounds__(64) void op_kernel(OpArgs<T> a, int ty) {
     constexpr int TX = 64;
@@ -235,6 +244,7 @@ __global__ __launch_bounds__(64) void op_kernel(OpArgs<T> a, int ty) {
                 const T rr = bv.re - yr, ri = bv.im - yi;
                 if (MODE == MODE_RESID) {
                     out = {rr, ri};
+                    if (a.xo) a.xo[I] = first_sweep(a, I, out);
                 } else {
                     const cx<T> dv = a.dinv[I];
                     int cs = slot + W - PY;   // slot of input row r - p = output row t
@@ -336,6 +346,7 @@ __global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
         const T rr = bv.re - yr, ri = bv.im - yi;
         if (MODE == MODE_RESID) {
             out = {rr, ri};
+            if (a.xo) a.xo[I] = first_sweep(a, I, out);
         } else {
             const cx<T> dv = a.dinv[I], xv = a.x[I];
             out = {xv.re + a.omega * (dv.re * rr - dv.im * ri), xv.im + a.omega * (dv.re * ri + dv.im * rr)};

@@ -116,13 +116,14 @@ struct SolverImpl {
     void autotune_ops(hipStream_t s);
     // building blocks
     template <class T>
-    void op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s);
+    void op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s,
+            cx<T>* xo = nullptr);   // xo: MODE_RESID also forms a first sweep on y
     template <class T>
     void vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s,
                      bool x_swept = false);   // x_swept: x already holds the first sweep from zero
     template <class T>
-    void vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s);
-    void precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s);
+    void vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_swept = false);
+    void precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s, bool x_swept = false);
     void T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t s);
     void coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s);
     void arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s);
@@ -141,7 +142,8 @@ struct SolverImpl {
     cx<double>* cap_buf = nullptr;
     int cap_max = 0, cap_n = 0;
     template <class T>
-    void op_alpha(int l, int mode, double are, double aim, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s);
+    void op_alpha(int l, int mode, double are, double aim, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s,
+                  cx<T>* xo = nullptr);
     int solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s);
 };
 

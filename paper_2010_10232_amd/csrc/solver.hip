@@ -732,14 +732,14 @@ void SolverImpl::autotune_ops(hipStream_t s) {
 
 // ----------------------------------------------------------- hot path ----
 template <class T>
-void SolverImpl::op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s) {
-    op_alpha<T>(l, mode, cslp ? o.beta[0] : 1.0, cslp ? o.beta[1] : 0.0, x, b, y, s);
+void SolverImpl::op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s, cx<T>* xo) {
+    op_alpha<T>(l, mode, cslp ? o.beta[0] : 1.0, cslp ? o.beta[1] : 0.0, x, b, y, s, xo);
 }
 
 // y = K x - alpha M_k x at level l, with the residual / Jacobi epilogues (mode)
 template <class T>
 void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* x, const cx<T>* b, cx<T>* y,
-                          hipStream_t s) {
+                          hipStream_t s, cx<T>* xo) {
     LevelDev& lv = *lev[l];
     OpArgs<T> a{};
     a.n1 = lv.n1;
@@ -764,6 +764,7 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
     a.y = y;
     a.dinv = pick<T>(lv.Dinv64, lv.Dinv32).template as<cx<T>>();
     a.omega = (T)lv.omega;
+    a.xo = xo;
     a.ty = sizeof(T) == 8 ? lv.ty64 : lv.ty32;
     const int py = prob->dim == 2 ? prob->p : 0;
     if (l == 0) tstart(1, s);
@@ -772,7 +773,8 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
         // algorithmic bytes: x in, y out, b (residual and smoothing) and D^-1
         // (smoothing) in, plus the k^2 field of a non-constant wave number
         const double v = (double)lv.N * 2 * sizeof(T);
-        double bytes = 2 * v + (mode != MODE_APPLY ? v : 0.0) + (mode == MODE_SMOOTH ? v : 0.0);
+        double bytes = 2 * v + (mode != MODE_APPLY ? v : 0.0) + (mode == MODE_SMOOTH || xo ? v : 0.0) +
+                       (xo ? v : 0.0);
         if (lv.kind == KIND_VARFINE) bytes += 8.0 * lv.ax.nel * lv.ay.nel;
         tstop(1, bytes, s);
     }
@@ -849,8 +851,8 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s, boo
 }
 
 template <class T>
-void SolverImpl::vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
-    vcycle_once<T>(l, b, x, s);
+void SolverImpl::vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_swept) {
+    vcycle_once<T>(l, b, x, s, x_swept);
     LevelDev& lv = *lev[l];
     for (int i = 1; i < o.n_vcycles; ++i) {
         cx<T>* vr = pick<T>(lv.vr64, lv.vr32).template as<cx<T>>();
@@ -861,7 +863,7 @@ void SolverImpl::vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s) {
     }
 }
 
-void SolverImpl::precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s) {
+void SolverImpl::precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s, bool x_swept) {
     if (l == 0 && cap_buf && cap_n < cap_max) {
         const long long N = lev[0]->N;
         HH_HIP(hipMemcpyAsync(cap_buf + (size_t)cap_n * N, b, (size_t)N * sizeof(cx<double>), hipMemcpyDeviceToDevice,
@@ -869,7 +871,7 @@ void SolverImpl::precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipSt
         ++cap_n;
     }
     if (o.precision == 0) {
-        vcycle<double>(l, b, x, s);
+        vcycle<double>(l, b, x, s, x_swept);
         return;
     }
     LevelDev& lv = *lev[l];
@@ -889,20 +891,24 @@ void SolverImpl::T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t 
     launch_restrict<double>(lv.tr, v, lc.tc.as<cx<double>>(), s);
     coarse_solve(l + 1, lc.tc.as<cx<double>>(), lc.te.as<cx<double>>(), s);
     launch_prolong<double>(lv.tr, lc.te.as<cx<double>>(), lv.tq.as<cx<double>>(), 0, s);
-    op<double>(l, MODE_RESID, false, lv.tq.as<cx<double>>(), v, lv.tw.as<cx<double>>(), s);
-    precond_vcycle(l, lv.tw.as<cx<double>>(), lv.ts.as<cx<double>>(), s);
+    // w = v - A q; with an FP64 V-cycle that starts with one Jacobi sweep on
+    // separate kernels, the same kernel also forms that sweep (x = omega D^-1 w)
+    const bool fuse = o.precision == 0 && o.nu_pre == 1 && !(cnn && l == 0) && l < tail_start && l < L;
+    op<double>(l, MODE_RESID, false, lv.tq.as<cx<double>>(), v, lv.tw.as<cx<double>>(), s,
+               fuse ? lv.ts.as<cx<double>>() : nullptr);
+    precond_vcycle(l, lv.tw.as<cx<double>>(), lv.ts.as<cx<double>>(), s, fuse);
     launch_add(lv.N, lv.ts.as<cx<double>>(), lv.tq.as<cx<double>>(), z, s);
 }
 
 // One fused Arnoldi step on w = V[j+1]: a single workgroup for short vectors;
-// otherwise a cooperative grid, or (when other problems' kernels share the GPU
-// and co-residency of a cooperative grid cannot be relied on) one kernel per
-// Gram-Schmidt projection followed by the norm/Givens kernel and the scaling.
+// otherwise a resident grid (or, for single solves, a cooperative one), or (in
+// batched mode, when the grid is too large for up to 16 of them to be resident
+// side by side) one kernel per Gram-Schmidt projection followed by the
+// norm/Givens kernel and the scaling.
 void SolverImpl::arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s) {
     if (N <= kSmallArnoldi) {
         launch_arnoldi_small(N, j, w, Vb, N, k, s);
-    } else if (allow_coop) {
-        launch_arnoldi_coop(N, j, w, Vb, N, k, s);
+    } else if (launch_arnoldi_grid(N, j, w, Vb, N, k, s, allow_coop ? 4 : 16, allow_coop)) {
     } else {
         for (int i = 0; i <= j; ++i) launch_mgs(N, i, j, w, Vb, N, k, s);
         launch_norm_givens(N, j, w, Vb, N, k, s);
@@ -1164,11 +1170,13 @@ int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_i
     return run.status;
 }
 
-template void SolverImpl::op<double>(int, int, bool, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t);
-template void SolverImpl::op<float>(int, int, bool, const cx<float>*, const cx<float>*, cx<float>*, hipStream_t);
+template void SolverImpl::op<double>(int, int, bool, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t,
+                                     cx<double>*);
+template void SolverImpl::op<float>(int, int, bool, const cx<float>*, const cx<float>*, cx<float>*, hipStream_t,
+                                    cx<float>*);
 template void SolverImpl::op_alpha<double>(int, int, double, double, const cx<double>*, const cx<double>*, cx<double>*,
-                                           hipStream_t);
-template void SolverImpl::vcycle<double>(int, const cx<double>*, cx<double>*, hipStream_t);
-template void SolverImpl::vcycle<float>(int, const cx<float>*, cx<float>*, hipStream_t);
+                                           hipStream_t, cx<double>*);
+template void SolverImpl::vcycle<double>(int, const cx<double>*, cx<double>*, hipStream_t, bool);
+template void SolverImpl::vcycle<float>(int, const cx<float>*, cx<float>*, hipStream_t, bool);
 
 }  // namespace hh
