@@ -237,6 +237,11 @@ hh_status hh_cnn_set_params(hh_cnn* c, const float* host, int n_floats);
  * (if grad_host != NULL) the gradient dL/dRe + i dL/dIm of every parameter. */
 hh_status hh_cnn_loss_grad(hh_cnn* c, hh_solver* s, const void* r_dev, double* loss, float* grad_host,
                            int n_floats, void* stream);
+/* Debug / parity (tests only): fused = 1 (default) evaluates the network of
+ * the smoother step in one kernel per step (all four layers on LDS-resident
+ * tiles); 0 uses one kernel per layer, as training does.  Both give
+ * bit-identical results. */
+hh_status hh_cnn_set_fused(hh_cnn* c, int fused);
 /* One Adam step (beta 0.9 / 0.999) with learning rate lr on the loss above. */
 hh_status hh_cnn_train_step(hh_cnn* c, hh_solver* s, const void* r_dev, double lr, double* loss, void* stream);
 /* Uses the network as the finest-level smoother of s (NULL: damped Jacobi).

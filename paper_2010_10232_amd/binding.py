@@ -21,7 +21,7 @@ OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 
 EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
             "hh_point_spans", "hh_rhs_point_source", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
             "hh_level_info", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched", "hh_cnn_create",
-            "hh_cnn_destroy", "hh_cnn_num_params", "hh_cnn_get_params", "hh_cnn_set_params", "hh_cnn_loss_grad",
+            "hh_cnn_destroy", "hh_cnn_num_params", "hh_cnn_get_params", "hh_cnn_set_params", "hh_cnn_set_fused", "hh_cnn_loss_grad",
             "hh_cnn_train_step", "hh_solver_set_smoother", "hh_solver_capture", "hh_solver_captured"]
 
 
@@ -91,6 +91,7 @@ def load(path=LIB_PATH):
     lib.hh_cnn_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.hh_cnn_get_params.argtypes = [vp, fp, ip]
     lib.hh_cnn_set_params.argtypes = [vp, fp, ip]
+    lib.hh_cnn_set_fused.argtypes = [vp, ctypes.c_int]
     lib.hh_cnn_loss_grad.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), fp, ip, vp]
     lib.hh_cnn_train_step.argtypes = [vp, vp, vp, dp, ctypes.POINTER(ctypes.c_double), vp]
     lib.hh_solver_set_smoother.argtypes = [vp, vp]
@@ -312,6 +313,10 @@ class Cnn:
     def set_params(self, vals):
         v = np.ascontiguousarray(vals, dtype=np.float32)
         _check(load().hh_cnn_set_params(self._h, v.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), len(v)))
+
+    def set_fused(self, fused):
+        """Debug / parity: one fused forward kernel per smoother step (True, default) or one per layer."""
+        _check(load().hh_cnn_set_fused(self._h, int(bool(fused))))
 
     def loss_grad(self, solver, r):
         loss = ctypes.c_double()

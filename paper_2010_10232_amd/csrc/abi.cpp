@@ -356,6 +356,14 @@ hh_status hh_cnn_set_params(hh_cnn* c, const float* host, int n) {
     HH_CATCH
 }
 
+hh_status hh_cnn_set_fused(hh_cnn* c, int fused) {
+    HH_TRY
+    if (!c) throw Err{HH_EINVAL, "NULL argument"};
+    c->impl->fused = fused != 0;
+    return HH_OK;
+    HH_CATCH
+}
+
 static MbetaFn finest_mbeta(SolverImpl& S, hipStream_t st) {
     return [&S, st](const cx<double>* x, const cx<double>* b, cx<double>* y, int conj) {
         if (conj)

@@ -117,6 +117,124 @@ static void conv_launch(int H, int Wd, const __bf16* X, const __bf16* Wp, const 
 }
 
 // --------------------------------------------------------------------------
+// Fused forward of all four layers for inference.  A workgroup owns an output
+// tile of FT_H x FT_W pixels and computes every layer on the tile grown by the
+// halo the later layers need (input: +4 pixels on each side, layer 0: +3,
+// layer 1: +2, layer 2: +1), the activations of each stage staying in LDS.
+// Every output pixel of every layer is formed by the same MFMA sequence as
+// conv3x3_kernel (same operand fragments, taps in the same order), so the
+// result is bit-identical to the four separate launches; stage pixels outside
+// the grid are stored as zero, the padding the separate launches read.
+// --------------------------------------------------------------------------
+constexpr int FT_H = 8, FT_W = 16;
+
+// One stage: out[px][COUTP] = act(conv3x3(in)) over a (R x C) pixel region whose
+// source region is (R + 2) x (C + 2), pixels linearised row-major; M-tiles of
+// 16 pixels go to the waves in turn.  (gr0, gc0): grid position of the region's
+// first pixel.  LAST: the network output (2 real channels, FP32, bias, no ReLU)
+// written to Y for pixels of the grid.
+template <int CINP, int COUTP, bool LAST>
+__device__ __forceinline__ void fused_stage(const __bf16* __restrict__ in, __bf16* __restrict__ outs, int R, int C,
+                                            int gr0, int gc0, int H, int Wd, const __bf16* __restrict__ Wp,
+                                            const float* __restrict__ bias, float* __restrict__ Y) {
+    constexpr int NT = COUTP / 16;
+    constexpr int KSTEPS = (CINP == 32) ? 9 : 3;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, col = lane & 15;
+    const int Cs = C + 2;   // source region width
+    bf16x8 bw[KSTEPS][NT];
+#pragma unroll
+    for (int s = 0; s < KSTEPS; ++s) {
+        const int tap = (CINP == 32) ? s : 4 * s + g;
+        const int ci0 = (CINP == 32) ? 8 * g : 0;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (tap < 9) {
+                bw[s][nt] = *(const bf16x8*)(Wp + ((size_t)tap * COUTP + nt * 16 + col) * CINP + ci0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bw[s][nt][e] = (__bf16)0.0f;
+            }
+        }
+    }
+    const int npx = R * C, ntiles = (npx + 15) / 16;
+    for (int mt = wave; mt < ntiles; mt += 4) {
+        // A-operand row of this lane: pixel mt*16 + col (clamped into the region)
+        const int pa = min(mt * 16 + col, npx - 1);
+        const int ra = pa / C, ca = pa - ra * C;
+        f32x4 acc[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KSTEPS; ++s) {
+            const int tap = (CINP == 32) ? s : 4 * s + g;
+            const int ci0 = (CINP == 32) ? 8 * g : 0;
+            bf16x8 a;
+            if (tap < 9) {
+                const int dy = tap / 3, dx = tap - 3 * dy;
+                a = *(const bf16x8*)(in + ((size_t)(ra + dy) * Cs + (ca + dx)) * CINP + ci0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a[e] = (__bf16)0.0f;
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][nt], acc[nt], 0, 0, 0);
+        }
+        // D: output channel nt*16 + col for pixels mt*16 + 4g .. + 3
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int co = nt * 16 + col;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int po = mt * 16 + 4 * g + i;
+                if (po >= npx) continue;
+                const int ro = po / C, cc = po - ro * C;
+                const int gr = gr0 + ro, gc = gc0 + cc;
+                const bool in_grid = gr >= 0 && gr < H && gc >= 0 && gc < Wd;
+                const float v = acc[nt][i];
+                if (LAST) {
+                    if (co < 2 && in_grid) Y[((size_t)gr * Wd + gc) * 2 + co] = v + bias[co];
+                } else {
+                    outs[(size_t)po * COUTP + co] = in_grid ? (__bf16)fmaxf(v + bias[co], 0.0f) : (__bf16)0.0f;
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void cnn_fused_kernel(int H, int Wd, const __bf16* __restrict__ X0,
+                                                        const __bf16* __restrict__ W0, const float* __restrict__ b0,
+                                                        const __bf16* __restrict__ W1, const float* __restrict__ b1,
+                                                        const __bf16* __restrict__ W2, const float* __restrict__ b2,
+                                                        const __bf16* __restrict__ W3, const float* __restrict__ b3,
+                                                        float* __restrict__ Y) {
+    // stage regions: input (FT_H+8) x (FT_W+8) x 8, then (FT_H+6) x (FT_W+6),
+    // (FT_H+4) x (FT_W+4), (FT_H+2) x (FT_W+2) pixels of 32 channels
+    __shared__ __attribute__((aligned(16))) __bf16 s_in[(FT_H + 8) * (FT_W + 8) * 8];
+    __shared__ __attribute__((aligned(16))) __bf16 s_a0[(FT_H + 6) * (FT_W + 6) * 32];
+    __shared__ __attribute__((aligned(16))) __bf16 s_a1[(FT_H + 4) * (FT_W + 4) * 32];
+    __shared__ __attribute__((aligned(16))) __bf16 s_a2[(FT_H + 2) * (FT_W + 2) * 32];
+    const int r0 = blockIdx.y * FT_H, c0 = blockIdx.x * FT_W;
+    {
+        constexpr int RI = FT_H + 8, CI = FT_W + 8;
+        for (int e = threadIdx.x; e < RI * CI; e += 256) {
+            const int rr = e / CI, cc = e - rr * CI;
+            const int gr = r0 - 4 + rr, gc = c0 - 4 + cc;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (gr >= 0 && gr < H && gc >= 0 && gc < Wd) v = *(const uint4*)(X0 + ((size_t)gr * Wd + gc) * 8);
+            *(uint4*)&s_in[(size_t)e * 8] = v;
+        }
+        __syncthreads();
+    }
+    fused_stage<8, 32, false>(s_in, s_a0, FT_H + 6, FT_W + 6, r0 - 3, c0 - 3, H, Wd, W0, b0, nullptr);
+    fused_stage<32, 32, false>(s_a0, s_a1, FT_H + 4, FT_W + 4, r0 - 2, c0 - 2, H, Wd, W1, b1, nullptr);
+    fused_stage<32, 32, false>(s_a1, s_a2, FT_H + 2, FT_W + 2, r0 - 1, c0 - 1, H, Wd, W2, b2, nullptr);
+    fused_stage<32, 16, true>(s_a2, nullptr, FT_H, FT_W, r0, c0, H, Wd, W3, b3, Y);
+}
+
+// --------------------------------------------------------------------------
 // Weight gradient: G[tap][co][ci] = sum_p gY[p][co] X[p + off(tap)][ci] and
 // Gb[co] = sum_p gY[p][co], as per-workgroup partial sums over an 8 x 64 pixel
 // tile, reduced afterwards in block order (deterministic).
@@ -180,12 +298,20 @@ __global__ void reduce_parts_kernel(int nblk, int nout, const float* __restrict_
 // --------------------------------------------------------------------------
 // X0[p] = (r.re / rms, r.im / rms, c[p], 0, 0, 0, 0, 0) with rms = ||r|| / sqrt(N),
 // ||r||^2 = *nr2 (entries of order one whatever the grid size)
+// ||r||^2 as nparts partial sums (added in index order: the same bits in every
+// thread that needs it)
+__device__ __forceinline__ double sum_parts(const double* __restrict__ parts, int nparts) {
+    double s = 0.0;
+    for (int i = 0; i < nparts; ++i) s += parts[i];
+    return s;
+}
+
 template <class TV>
-__global__ void pack_input_kernel(long long N, const cx<TV>* __restrict__ r, const double* nr2,
-                                  const float* __restrict__ feat, __bf16* __restrict__ X0) {
+__global__ void pack_input_kernel(long long N, const cx<TV>* __restrict__ r, const double* __restrict__ nr2,
+                                  int nparts, const float* __restrict__ feat, __bf16* __restrict__ X0) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    const double nr = sqrt(*nr2);
+    const double nr = sqrt(sum_parts(nr2, nparts));
     const double inv = nr > 0.0 ? sqrt((double)N) / nr : 0.0;
     const cx<TV> v = r[p];
     bf16x8 o;
@@ -199,12 +325,12 @@ __global__ void pack_input_kernel(long long N, const cx<TV>* __restrict__ r, con
 
 // x (+)= omega D^-1 r + rms * out  (smoother step), out: complex FP32 network output
 template <class TV>
-__global__ void apply_step_kernel(long long N, const float* __restrict__ out, const double* nr2,
-                                  const cx<TV>* __restrict__ r, const cx<TV>* __restrict__ dinv, TV omega,
-                                  cx<TV>* __restrict__ x, int accumulate) {
+__global__ void apply_step_kernel(long long N, const float* __restrict__ out, const double* __restrict__ nr2,
+                                  int nparts, const cx<TV>* __restrict__ r, const cx<TV>* __restrict__ dinv,
+                                  TV omega, cx<TV>* __restrict__ x, int accumulate) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    const double rms = sqrt(*nr2 / (double)N);
+    const double rms = sqrt(sum_parts(nr2, nparts) / (double)N);
     const cx<TV> d = dinv[p], v = r[p];
     const TV sr = omega * (d.re * v.re - d.im * v.im) + (TV)(rms * out[2 * p]);
     const TV si = omega * (d.re * v.im + d.im * v.re) + (TV)(rms * out[2 * p + 1]);
@@ -316,6 +442,26 @@ __global__ void adam_kernel(int n, float* __restrict__ theta, float* __restrict_
     m[i] = b1 * m[i] + (1.0f - b1) * gi;
     v[i] = b2 * v[i] + (1.0f - b2) * gi * gi;
     theta[i] -= lr * (m[i] / c1) / (sqrtf(v[i] / c2) + eps);
+}
+
+// ||x||^2 as per-workgroup partial sums (FP64, tree in LDS): parts[blockIdx.x]
+constexpr int kNormParts = 64;
+template <class TV>
+__global__ __launch_bounds__(256) void norm2_parts_kernel(long long N, const cx<TV>* __restrict__ x,
+                                                          double* __restrict__ parts) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < N; t += (long long)gridDim.x * 256) {
+        const cx<TV> v = x[t];
+        s += (double)v.re * v.re + (double)v.im * v.im;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) parts[blockIdx.x] = sh[0];
 }
 
 // ||x||^2 in one workgroup (FP64 accumulation, deterministic)
@@ -432,7 +578,7 @@ void CnnImpl::ensure(int H, int Wd) {
     sbuf.alloc(P * 16);
     rbuf.alloc(P * 16);
     ybuf.alloc(P * 16);
-    scal.alloc(64);
+    scal.alloc(8 * (8 + kNormParts));   // [0] ||r||^2, [1] ||r'||^2 (loss); [8..] partial sums
     const int nblk = ((Wd + WG_TW - 1) / WG_TW) * ((H + WG_TH - 1) / WG_TH);
     part.alloc((size_t)nblk * (9 * 32 * 32 + 32) * 4);
     gfull.alloc((size_t)(9 * 32 * 32 + 32) * 4);
@@ -450,17 +596,30 @@ void CnnImpl::forward(int H, int Wd, hipStream_t s) {
                                   nullptr, out.p, s);
 }
 
+void CnnImpl::forward_fused(int H, int Wd, hipStream_t s) {
+    dim3 grid((Wd + FT_W - 1) / FT_W, (H + FT_H - 1) / FT_H);
+    hipLaunchKernelGGL(cnn_fused_kernel, grid, dim3(256), 0, s, H, Wd, x0.as<__bf16>(), layers[0].wf.as<__bf16>(),
+                       layers[0].bias.as<float>(), layers[1].wf.as<__bf16>(), layers[1].bias.as<float>(),
+                       layers[2].wf.as<__bf16>(), layers[2].bias.as<float>(), layers[3].wf.as<__bf16>(),
+                       layers[3].bias.as<float>(), out.as<float>());
+}
+
 template <class TV>
 void CnnImpl::step(int H, int Wd, const cx<TV>* r, const float* feat, const cx<TV>* dinv, TV omega, cx<TV>* x,
                    int accumulate, hipStream_t s) {
     ensure(H, Wd);
     const long long N = (long long)H * Wd;
-    double* nr2 = scal.as<double>();
-    hipLaunchKernelGGL(norm2_small_kernel<TV>, dim3(1), dim3(1024), 0, s, N, r, nr2);
-    hipLaunchKernelGGL(pack_input_kernel<TV>, dim3(g1(N, 256)), dim3(256), 0, s, N, r, nr2, feat, x0.as<__bf16>());
-    forward(H, Wd, s);
-    hipLaunchKernelGGL(apply_step_kernel<TV>, dim3(g1(N, 256)), dim3(256), 0, s, N, out.as<float>(), nr2, r, dinv,
-                       omega, x, accumulate);
+    double* parts = scal.as<double>() + 8;   // kNormParts partial sums of ||r||^2
+    const int np = (int)std::min<long long>(kNormParts, (N + 255) / 256);
+    hipLaunchKernelGGL(norm2_parts_kernel<TV>, dim3(np), dim3(256), 0, s, N, r, parts);
+    hipLaunchKernelGGL(pack_input_kernel<TV>, dim3(g1(N, 256)), dim3(256), 0, s, N, r, parts, np, feat,
+                       x0.as<__bf16>());
+    if (fused)
+        forward_fused(H, Wd, s);
+    else
+        forward(H, Wd, s);
+    hipLaunchKernelGGL(apply_step_kernel<TV>, dim3(g1(N, 256)), dim3(256), 0, s, N, out.as<float>(), parts, np, r,
+                       dinv, omega, x, accumulate);
 }
 template void CnnImpl::step<float>(int, int, const cx<float>*, const float*, const cx<float>*, float, cx<float>*, int,
                                    hipStream_t);
@@ -499,7 +658,8 @@ double CnnImpl::loss_grad(int H, int Wd, const cx<double>* r, const float* feat,
     double* nr2 = scal.as<double>();
     double* rn2 = nr2 + 1;
     hipLaunchKernelGGL(norm2_small_kernel<double>, dim3(1), dim3(1024), 0, s, N, r, nr2);
-    hipLaunchKernelGGL(pack_input_kernel<double>, dim3(g1(N, 256)), dim3(256), 0, s, N, r, nr2, feat, x0.as<__bf16>());
+    hipLaunchKernelGGL(pack_input_kernel<double>, dim3(g1(N, 256)), dim3(256), 0, s, N, r, nr2, 1, feat,
+                       x0.as<__bf16>());
     forward(H, Wd, s);
     hipLaunchKernelGGL(scale_out_kernel, dim3(g1(N, 256)), dim3(256), 0, s, N, out.as<float>(), nr2, r, dinv, omega,
                        sbuf.as<cx<double>>());

@@ -214,3 +214,29 @@ def test_capture_train_and_solve():
     A = osol.levels[0].A
     fh, uh = to_host(f), to_host(u2)
     assert np.linalg.norm(fh - A @ uh) <= 1.01e-7 * np.linalg.norm(fh)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fused_forward_bit_identical(name):
+    """The smoother step's one-kernel forward (LDS-resident tiles of 8 x 16
+    output pixels with a 4-pixel halo) against the per-layer kernels: the
+    learned V-cycle gives identical bits.  The grids (101 x 101, 89 x 89,
+    1 x 299) span several tiles with ragged last tiles and, in 1D, a tile taller
+    than the grid."""
+    from paper_2010_10232_amd import binding as B
+    c, op, osol, gp, gs = build(name)
+    net = B.Cnn()
+    net.set_params(flat(f32_params(21, 0.2)))
+    N = osol.levels[0].N
+    x = np.random.default_rng(8).standard_normal(N) + 1j * np.random.default_rng(9).standard_normal(N)
+    gs.set_smoother(net)
+    try:
+        net.set_fused(True)
+        fused = to_host(gs.apply("VCYCLE", 0, to_dev(x)))
+        net.set_fused(False)
+        layered = to_host(gs.apply("VCYCLE", 0, to_dev(x)))
+    finally:
+        net.set_fused(True)
+        gs.set_smoother(None)
+    _say(f"[cnn case {name}] fused vs per-layer forward: max |diff| {np.max(np.abs(fused - layered)):.3e}")
+    assert np.array_equal(fused, layered)
