@@ -12,8 +12,10 @@
 // Convolution = implicit GEMM on v_mfma_f32_16x16x32_bf16: M = pixels (16 per
 // wave), N = output channels (16 per MFMA tile), K = (tap, input channel): one
 // tap of 32 channels per MFMA for hidden layers, four taps of 8 channels for the
-// 8-channel input layer.  A workgroup (4 waves) owns a 64-pixel row segment;
-// its three input rows are staged in LDS, the packed weights sit in registers.
+// 8-channel input layer.  Per layer (training): a workgroup (4 waves) owns a
+// 64-pixel row segment; its three input rows are staged in LDS, the packed
+// weights sit in registers.  The smoother step runs all layers in one kernel
+// (cnn_fused_kernel).
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -120,25 +122,49 @@ static void conv_launch(int H, int Wd, const __bf16* X, const __bf16* Wp, const 
 // Fused forward of all four layers for inference.  A workgroup owns an output
 // tile of FT_H x FT_W pixels and computes every layer on the tile grown by the
 // halo the later layers need (input: +4 pixels on each side, layer 0: +3,
-// layer 1: +2, layer 2: +1), the activations of each stage staying in LDS.
-// Every output pixel of every layer is formed by the same MFMA sequence as
-// conv3x3_kernel (same operand fragments, taps in the same order), so the
-// result is bit-identical to the four separate launches; stage pixels outside
-// the grid are stored as zero, the padding the separate launches read.
+// layer 1: +2, layer 2: +1), the activations of each stage staying in LDS,
+// with all four layers' packed weights copied into LDS at the start together
+// with the input tile (one round trip to memory).  Every output pixel of every
+// layer is formed by the same MFMA sequence as conv3x3_kernel (same operand
+// fragments, taps in the same order), so the result is bit-identical to the
+// four separate launches; stage pixels outside the grid are stored as zero, the
+// padding the separate launches read.
 // --------------------------------------------------------------------------
-constexpr int FT_H = 8, FT_W = 16;
+constexpr int FT_H = 8, FT_W = 16, FUSED_TB = 512;
+// LDS (BF16 elements): packed weights of layers 0..3, then two activation
+// regions used alternately (input tile / layer-1 output, layer-0 / layer-2 output)
+constexpr int FW0 = 9 * 32 * 8, FW1 = 9 * 32 * 32, FW3 = 9 * 16 * 32;
+constexpr int FIN = (FT_H + 8) * (FT_W + 8) * 8, FA0 = (FT_H + 6) * (FT_W + 6) * 32;
+constexpr int FA1 = (FT_H + 4) * (FT_W + 4) * 32, FA2 = (FT_H + 2) * (FT_W + 2) * 32;
+constexpr int FRA = FIN > FA1 ? FIN : FA1, FRB = FA0 > FA2 ? FA0 : FA2;
+constexpr int FUSED_LDS = 2 * (FW0 + 2 * FW1 + FW3 + FRA + FRB);   // bytes
+
+extern __shared__ __attribute__((aligned(16))) __bf16 cnn_smem[];
+
+// n16 16-byte chunks from global src to LDS dst: clamped addresses (n16 >= 1)
+// and unconditional stores (the last chunk may be written twice with its own
+// value), so all of a thread's loads are issued before its first store
+template <int PER>
+__device__ __forceinline__ void stage_chunks(uint4* dst, const uint4* __restrict__ src, int n16) {
+    uint4 v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = src[min((int)threadIdx.x + q * FUSED_TB, n16 - 1)];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) dst[min((int)threadIdx.x + q * FUSED_TB, n16 - 1)] = v[q];
+}
 
 // One stage: out[px][COUTP] = act(conv3x3(in)) over a (R x C) pixel region whose
 // source region is (R + 2) x (C + 2), pixels linearised row-major; M-tiles of
 // 16 pixels go to the waves in turn.  (gr0, gc0): grid position of the region's
 // first pixel.  LAST: the network output (2 real channels, FP32, bias, no ReLU)
-// written to Y for pixels of the grid.
+// written to Y for pixels of the grid.  Ws: the layer's packed weights in LDS.
 template <int CINP, int COUTP, bool LAST>
-__device__ __forceinline__ void fused_stage(const __bf16* __restrict__ in, __bf16* __restrict__ outs, int R, int C,
-                                            int gr0, int gc0, int H, int Wd, const __bf16* __restrict__ Wp,
-                                            const float* __restrict__ bias, float* __restrict__ Y) {
+__device__ __forceinline__ void fused_stage(const __bf16* in, __bf16* outs, int R, int C, int gr0, int gc0, int H,
+                                            int Wd, const __bf16* Ws, const float* __restrict__ bias,
+                                            float* __restrict__ Y) {
     constexpr int NT = COUTP / 16;
     constexpr int KSTEPS = (CINP == 32) ? 9 : 3;
+    constexpr int NW = FUSED_TB / 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, col = lane & 15;
     const int Cs = C + 2;   // source region width
@@ -150,7 +176,7 @@ __device__ __forceinline__ void fused_stage(const __bf16* __restrict__ in, __bf1
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if (tap < 9) {
-                bw[s][nt] = *(const bf16x8*)(Wp + ((size_t)tap * COUTP + nt * 16 + col) * CINP + ci0);
+                bw[s][nt] = *(const bf16x8*)(Ws + (tap * COUTP + nt * 16 + col) * CINP + ci0);
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) bw[s][nt][e] = (__bf16)0.0f;
@@ -158,7 +184,7 @@ __device__ __forceinline__ void fused_stage(const __bf16* __restrict__ in, __bf1
         }
     }
     const int npx = R * C, ntiles = (npx + 15) / 16;
-    for (int mt = wave; mt < ntiles; mt += 4) {
+    for (int mt = wave; mt < ntiles; mt += NW) {
         // A-operand row of this lane: pixel mt*16 + col (clamped into the region)
         const int pa = min(mt * 16 + col, npx - 1);
         const int ra = pa / C, ca = pa - ra * C;
@@ -172,7 +198,7 @@ __device__ __forceinline__ void fused_stage(const __bf16* __restrict__ in, __bf1
             bf16x8 a;
             if (tap < 9) {
                 const int dy = tap / 3, dx = tap - 3 * dy;
-                a = *(const bf16x8*)(in + ((size_t)(ra + dy) * Cs + (ca + dx)) * CINP + ci0);
+                a = *(const bf16x8*)(in + ((ra + dy) * Cs + (ca + dx)) * CINP + ci0);
             } else {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) a[e] = (__bf16)0.0f;
@@ -196,7 +222,7 @@ __device__ __forceinline__ void fused_stage(const __bf16* __restrict__ in, __bf1
                 if (LAST) {
                     if (co < 2 && in_grid) Y[((size_t)gr * Wd + gc) * 2 + co] = v + bias[co];
                 } else {
-                    outs[(size_t)po * COUTP + co] = in_grid ? (__bf16)fmaxf(v + bias[co], 0.0f) : (__bf16)0.0f;
+                    outs[po * COUTP + co] = in_grid ? (__bf16)fmaxf(v + bias[co], 0.0f) : (__bf16)0.0f;
                 }
             }
         }
@@ -204,34 +230,45 @@ __device__ __forceinline__ void fused_stage(const __bf16* __restrict__ in, __bf1
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void cnn_fused_kernel(int H, int Wd, const __bf16* __restrict__ X0,
-                                                        const __bf16* __restrict__ W0, const float* __restrict__ b0,
-                                                        const __bf16* __restrict__ W1, const float* __restrict__ b1,
-                                                        const __bf16* __restrict__ W2, const float* __restrict__ b2,
-                                                        const __bf16* __restrict__ W3, const float* __restrict__ b3,
-                                                        float* __restrict__ Y) {
-    // stage regions: input (FT_H+8) x (FT_W+8) x 8, then (FT_H+6) x (FT_W+6),
-    // (FT_H+4) x (FT_W+4), (FT_H+2) x (FT_W+2) pixels of 32 channels
-    __shared__ __attribute__((aligned(16))) __bf16 s_in[(FT_H + 8) * (FT_W + 8) * 8];
-    __shared__ __attribute__((aligned(16))) __bf16 s_a0[(FT_H + 6) * (FT_W + 6) * 32];
-    __shared__ __attribute__((aligned(16))) __bf16 s_a1[(FT_H + 4) * (FT_W + 4) * 32];
-    __shared__ __attribute__((aligned(16))) __bf16 s_a2[(FT_H + 2) * (FT_W + 2) * 32];
+__global__ __launch_bounds__(FUSED_TB) void cnn_fused_kernel(int H, int Wd, const __bf16* __restrict__ X0,
+                                                             const __bf16* __restrict__ W0,
+                                                             const float* __restrict__ b0,
+                                                             const __bf16* __restrict__ W1,
+                                                             const float* __restrict__ b1,
+                                                             const __bf16* __restrict__ W2,
+                                                             const float* __restrict__ b2,
+                                                             const __bf16* __restrict__ W3,
+                                                             const float* __restrict__ b3, float* __restrict__ Y) {
+    __bf16* sW0 = cnn_smem;
+    __bf16* sW1 = sW0 + FW0;
+    __bf16* sW2 = sW1 + FW1;
+    __bf16* sW3 = sW2 + FW1;
+    __bf16* rA = sW3 + FW3;
+    __bf16* rB = rA + FRA;
     const int r0 = blockIdx.y * FT_H, c0 = blockIdx.x * FT_W;
+    stage_chunks<1>((uint4*)sW0, (const uint4*)W0, FW0 / 8);
+    stage_chunks<3>((uint4*)sW1, (const uint4*)W1, FW1 / 8);
+    stage_chunks<3>((uint4*)sW2, (const uint4*)W2, FW1 / 8);
+    stage_chunks<2>((uint4*)sW3, (const uint4*)W3, FW3 / 8);
     {
+        // input tile, zero outside the grid (loads from a clamped valid pixel)
         constexpr int RI = FT_H + 8, CI = FT_W + 8;
-        for (int e = threadIdx.x; e < RI * CI; e += 256) {
+        static_assert(RI * CI <= FUSED_TB, "one input pixel per thread");
+        const int e = threadIdx.x;
+        if (e < RI * CI) {
             const int rr = e / CI, cc = e - rr * CI;
             const int gr = r0 - 4 + rr, gc = c0 - 4 + cc;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (gr >= 0 && gr < H && gc >= 0 && gc < Wd) v = *(const uint4*)(X0 + ((size_t)gr * Wd + gc) * 8);
-            *(uint4*)&s_in[(size_t)e * 8] = v;
+            const bool ok = gr >= 0 && gr < H && gc >= 0 && gc < Wd;
+            const int sr = min(max(gr, 0), H - 1), sc = min(max(gc, 0), Wd - 1);
+            const uint4 v = *(const uint4*)(X0 + ((size_t)sr * Wd + sc) * 8);
+            *(uint4*)(rA + e * 8) = ok ? v : uint4{0u, 0u, 0u, 0u};
         }
-        __syncthreads();
     }
-    fused_stage<8, 32, false>(s_in, s_a0, FT_H + 6, FT_W + 6, r0 - 3, c0 - 3, H, Wd, W0, b0, nullptr);
-    fused_stage<32, 32, false>(s_a0, s_a1, FT_H + 4, FT_W + 4, r0 - 2, c0 - 2, H, Wd, W1, b1, nullptr);
-    fused_stage<32, 32, false>(s_a1, s_a2, FT_H + 2, FT_W + 2, r0 - 1, c0 - 1, H, Wd, W2, b2, nullptr);
-    fused_stage<32, 16, true>(s_a2, nullptr, FT_H, FT_W, r0, c0, H, Wd, W3, b3, Y);
+    __syncthreads();
+    fused_stage<8, 32, false>(rA, rB, FT_H + 6, FT_W + 6, r0 - 3, c0 - 3, H, Wd, sW0, b0, nullptr);
+    fused_stage<32, 32, false>(rB, rA, FT_H + 4, FT_W + 4, r0 - 2, c0 - 2, H, Wd, sW1, b1, nullptr);
+    fused_stage<32, 32, false>(rA, rB, FT_H + 2, FT_W + 2, r0 - 1, c0 - 1, H, Wd, sW2, b2, nullptr);
+    fused_stage<32, 16, true>(rB, nullptr, FT_H, FT_W, r0, c0, H, Wd, sW3, b3, Y);
 }
 
 // --------------------------------------------------------------------------
@@ -298,11 +335,14 @@ __global__ void reduce_parts_kernel(int nblk, int nout, const float* __restrict_
 // --------------------------------------------------------------------------
 // X0[p] = (r.re / rms, r.im / rms, c[p], 0, 0, 0, 0, 0) with rms = ||r|| / sqrt(N),
 // ||r||^2 = *nr2 (entries of order one whatever the grid size)
-// ||r||^2 as nparts partial sums (added in index order: the same bits in every
-// thread that needs it)
+// ||r||^2 from nparts <= 64 partial sums: lane l of every wave loads part l and
+// a butterfly adds them; each step adds the same two values in every lane
+// (in either order: the same bits), so every thread gets the same sum
 __device__ __forceinline__ double sum_parts(const double* __restrict__ parts, int nparts) {
-    double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s += parts[i];
+    const int lane = threadIdx.x & 63;
+    double s = lane < nparts ? parts[lane] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     return s;
 }
 
@@ -310,8 +350,8 @@ template <class TV>
 __global__ void pack_input_kernel(long long N, const cx<TV>* __restrict__ r, const double* __restrict__ nr2,
                                   int nparts, const float* __restrict__ feat, __bf16* __restrict__ X0) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const double nr = sqrt(sum_parts(nr2, nparts));   // every lane takes part (butterfly)
     if (p >= N) return;
-    const double nr = sqrt(sum_parts(nr2, nparts));
     const double inv = nr > 0.0 ? sqrt((double)N) / nr : 0.0;
     const cx<TV> v = r[p];
     bf16x8 o;
@@ -329,8 +369,8 @@ __global__ void apply_step_kernel(long long N, const float* __restrict__ out, co
                                   int nparts, const cx<TV>* __restrict__ r, const cx<TV>* __restrict__ dinv,
                                   TV omega, cx<TV>* __restrict__ x, int accumulate) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const double rms = sqrt(sum_parts(nr2, nparts) / (double)N);   // every lane takes part (butterfly)
     if (p >= N) return;
-    const double rms = sqrt(sum_parts(nr2, nparts) / (double)N);
     const cx<TV> d = dinv[p], v = r[p];
     const TV sr = omega * (d.re * v.re - d.im * v.im) + (TV)(rms * out[2 * p]);
     const TV si = omega * (d.re * v.im + d.im * v.re) + (TV)(rms * out[2 * p + 1]);
@@ -597,8 +637,11 @@ void CnnImpl::forward(int H, int Wd, hipStream_t s) {
 }
 
 void CnnImpl::forward_fused(int H, int Wd, hipStream_t s) {
+    HH_HIP(hipFuncSetAttribute((const void*)cnn_fused_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               FUSED_LDS));
     dim3 grid((Wd + FT_W - 1) / FT_W, (H + FT_H - 1) / FT_H);
-    hipLaunchKernelGGL(cnn_fused_kernel, grid, dim3(256), 0, s, H, Wd, x0.as<__bf16>(), layers[0].wf.as<__bf16>(),
+    hipLaunchKernelGGL(cnn_fused_kernel, grid, dim3(FUSED_TB), FUSED_LDS, s, H, Wd, x0.as<__bf16>(),
+                       layers[0].wf.as<__bf16>(),
                        layers[0].bias.as<float>(), layers[1].wf.as<__bf16>(), layers[1].bias.as<float>(),
                        layers[2].wf.as<__bf16>(), layers[2].bias.as<float>(), layers[3].wf.as<__bf16>(),
                        layers[3].bias.as<float>(), out.as<float>());
