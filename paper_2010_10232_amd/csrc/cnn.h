@@ -25,7 +25,7 @@ struct CnnImpl {
     int nparam = 0;             // complex parameters
     DevBuf theta, adam_m, adam_v, grad;   // FP32 (re, im) pairs
     int adam_t = 0;
-    bool fused = true;          // smoother step: one fused forward kernel (else one per layer)
+    bool fused = true;          // smoother step: one fused kernel (else packing, one kernel per layer, update)
     int gH = -1, gW = -1;       // grid of the work buffers
     DevBuf x0, act[3], out, gA, gB, gOut, sbuf, rbuf, ybuf, scal, part, gfull;
 
@@ -33,8 +33,7 @@ struct CnnImpl {
     void repack(hipStream_t s);
     void set_params(const float* host, int n);
     void ensure(int H, int W);
-    void forward(int H, int W, hipStream_t s);         // per layer, activations kept (training)
-    void forward_fused(int H, int W, hipStream_t s);   // all layers in one kernel, output only
+    void forward(int H, int W, hipStream_t s);   // per layer, activations kept (training)
     // smoother step on the grid: x (+)= omega D^-1 r + rms C(r/rms, c), rms = ||r|| / sqrt(N)
     template <class TV>
     void step(int H, int W, const cx<TV>* r, const float* feat, const cx<TV>* dinv, TV omega, cx<TV>* x,

@@ -118,8 +118,20 @@ static void conv_launch(int H, int Wd, const __bf16* X, const __bf16* Wp, const 
     hipLaunchKernelGGL((conv3x3_kernel<CINP, COUTP, MODE>), grid, dim3(256), 0, s, H, Wd, X, Wp, bias, Mk, Y);
 }
 
+// ||r||^2 from nparts <= 64 partial sums: lane l of every wave loads part l and
+// a butterfly adds them; each step adds the same two values in every lane
+// (in either order: the same bits), so every thread gets the same sum
+__device__ __forceinline__ double sum_parts(const double* __restrict__ parts, int nparts) {
+    const int lane = threadIdx.x & 63;
+    double s = lane < nparts ? parts[lane] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
+}
+
 // --------------------------------------------------------------------------
-// Fused forward of all four layers for inference.  A workgroup owns an output
+// Fused smoother step (inference): input packing, the four layers and the
+// update of x in one kernel.  A workgroup owns an output
 // tile of FT_H x FT_W pixels and computes every layer on the tile grown by the
 // halo the later layers need (input: +4 pixels on each side, layer 0: +3,
 // layer 1: +2, layer 2: +1), the activations of each stage staying in LDS,
@@ -157,7 +169,8 @@ __device__ __forceinline__ void stage_chunks(uint4* dst, const uint4* __restrict
 // source region is (R + 2) x (C + 2), pixels linearised row-major; M-tiles of
 // 16 pixels go to the waves in turn.  (gr0, gc0): grid position of the region's
 // first pixel.  LAST: the network output (2 real channels, FP32, bias, no ReLU)
-// written to Y for pixels of the grid.  Ws: the layer's packed weights in LDS.
+// written to Y[pixel][2] (LDS, the region's pixels) for pixels of the grid.  Ws:
+// the layer's packed weights in LDS.
 template <int CINP, int COUTP, bool LAST>
 __device__ __forceinline__ void fused_stage(const __bf16* in, __bf16* outs, int R, int C, int gr0, int gc0, int H,
                                             int Wd, const __bf16* Ws, const float* __restrict__ bias,
@@ -220,7 +233,7 @@ __device__ __forceinline__ void fused_stage(const __bf16* in, __bf16* outs, int 
                 const bool in_grid = gr >= 0 && gr < H && gc >= 0 && gc < Wd;
                 const float v = acc[nt][i];
                 if (LAST) {
-                    if (co < 2 && in_grid) Y[((size_t)gr * Wd + gc) * 2 + co] = v + bias[co];
+                    if (co < 2 && in_grid) Y[po * 2 + co] = v + bias[co];
                 } else {
                     outs[po * COUTP + co] = in_grid ? (__bf16)fmaxf(v + bias[co], 0.0f) : (__bf16)0.0f;
                 }
@@ -230,15 +243,17 @@ __device__ __forceinline__ void fused_stage(const __bf16* in, __bf16* outs, int 
     __syncthreads();
 }
 
-__global__ __launch_bounds__(FUSED_TB) void cnn_fused_kernel(int H, int Wd, const __bf16* __restrict__ X0,
-                                                             const __bf16* __restrict__ W0,
-                                                             const float* __restrict__ b0,
-                                                             const __bf16* __restrict__ W1,
-                                                             const float* __restrict__ b1,
-                                                             const __bf16* __restrict__ W2,
-                                                             const float* __restrict__ b2,
-                                                             const __bf16* __restrict__ W3,
-                                                             const float* __restrict__ b3, float* __restrict__ Y) {
+// The whole smoother step: rms = ||r|| / sqrt(N) from the norm partials, the
+// packed input (r / rms, c) of the tile, the four layers, and
+// x (+)= omega D^-1 r + rms C(r / rms, c) on the tile's pixels, with the same
+// formulas as pack_input_kernel and apply_step_kernel.
+template <class TV>
+__global__ __launch_bounds__(FUSED_TB) void cnn_fused_kernel(
+    int H, int Wd, const cx<TV>* __restrict__ r, const double* __restrict__ nr2, int nparts,
+    const float* __restrict__ feat, const __bf16* __restrict__ W0, const float* __restrict__ b0,
+    const __bf16* __restrict__ W1, const float* __restrict__ b1, const __bf16* __restrict__ W2,
+    const float* __restrict__ b2, const __bf16* __restrict__ W3, const float* __restrict__ b3,
+    const cx<TV>* __restrict__ dinv, TV omega, cx<TV>* __restrict__ x, int accumulate) {
     __bf16* sW0 = cnn_smem;
     __bf16* sW1 = sW0 + FW0;
     __bf16* sW2 = sW1 + FW1;
@@ -246,12 +261,15 @@ __global__ __launch_bounds__(FUSED_TB) void cnn_fused_kernel(int H, int Wd, cons
     __bf16* rA = sW3 + FW3;
     __bf16* rB = rA + FRA;
     const int r0 = blockIdx.y * FT_H, c0 = blockIdx.x * FT_W;
+    const long long N = (long long)H * Wd;
+    const double nrs = sum_parts(nr2, nparts);   // every lane takes part (butterfly)
     stage_chunks<1>((uint4*)sW0, (const uint4*)W0, FW0 / 8);
     stage_chunks<3>((uint4*)sW1, (const uint4*)W1, FW1 / 8);
     stage_chunks<3>((uint4*)sW2, (const uint4*)W2, FW1 / 8);
     stage_chunks<2>((uint4*)sW3, (const uint4*)W3, FW3 / 8);
     {
-        // input tile, zero outside the grid (loads from a clamped valid pixel)
+        // packed input tile (r / rms, c, 0...), zero outside the grid (values
+        // read at a clamped valid pixel)
         constexpr int RI = FT_H + 8, CI = FT_W + 8;
         static_assert(RI * CI <= FUSED_TB, "one input pixel per thread");
         const int e = threadIdx.x;
@@ -259,16 +277,47 @@ __global__ __launch_bounds__(FUSED_TB) void cnn_fused_kernel(int H, int Wd, cons
             const int rr = e / CI, cc = e - rr * CI;
             const int gr = r0 - 4 + rr, gc = c0 - 4 + cc;
             const bool ok = gr >= 0 && gr < H && gc >= 0 && gc < Wd;
-            const int sr = min(max(gr, 0), H - 1), sc = min(max(gc, 0), Wd - 1);
-            const uint4 v = *(const uint4*)(X0 + ((size_t)sr * Wd + sc) * 8);
-            *(uint4*)(rA + e * 8) = ok ? v : uint4{0u, 0u, 0u, 0u};
+            const long long p = (long long)min(max(gr, 0), H - 1) * Wd + min(max(gc, 0), Wd - 1);
+            const double nr = sqrt(nrs);
+            const double inv = nr > 0.0 ? sqrt((double)N) / nr : 0.0;
+            const cx<TV> v = r[p];
+            const float fv = feat[p];
+            bf16x8 o;
+            o[0] = (__bf16)(float)(v.re * inv);
+            o[1] = (__bf16)(float)(v.im * inv);
+            o[2] = (__bf16)fv;
+#pragma unroll
+            for (int k = 3; k < 8; ++k) o[k] = (__bf16)0.0f;
+            if (!ok) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) o[k] = (__bf16)0.0f;
+            }
+            *(bf16x8*)(rA + e * 8) = o;
         }
     }
     __syncthreads();
     fused_stage<8, 32, false>(rA, rB, FT_H + 6, FT_W + 6, r0 - 3, c0 - 3, H, Wd, sW0, b0, nullptr);
     fused_stage<32, 32, false>(rB, rA, FT_H + 4, FT_W + 4, r0 - 2, c0 - 2, H, Wd, sW1, b1, nullptr);
     fused_stage<32, 32, false>(rA, rB, FT_H + 2, FT_W + 2, r0 - 1, c0 - 1, H, Wd, sW2, b2, nullptr);
-    fused_stage<32, 16, true>(rB, nullptr, FT_H, FT_W, r0, c0, H, Wd, sW3, b3, Y);
+    float* outs = (float*)rA;   // the network output of the tile, [pixel][2]
+    fused_stage<32, 16, true>(rB, nullptr, FT_H, FT_W, r0, c0, H, Wd, sW3, b3, outs);
+    // x (+)= omega D^-1 r + rms out on the tile's pixels of the grid
+    if (threadIdx.x < FT_H * FT_W) {
+        const int e = threadIdx.x, gr = r0 + e / FT_W, gc = c0 + e % FT_W;
+        if (gr < H && gc < Wd) {
+            const long long p = (long long)gr * Wd + gc;
+            const double rms = sqrt(nrs / (double)N);
+            const cx<TV> d = dinv[p], v = r[p];
+            const TV sr = omega * (d.re * v.re - d.im * v.im) + (TV)(rms * outs[e * 2]);
+            const TV si = omega * (d.re * v.im + d.im * v.re) + (TV)(rms * outs[e * 2 + 1]);
+            if (accumulate) {
+                const cx<TV> o = x[p];
+                x[p] = {o.re + sr, o.im + si};
+            } else {
+                x[p] = {sr, si};
+            }
+        }
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -335,16 +384,6 @@ __global__ void reduce_parts_kernel(int nblk, int nout, const float* __restrict_
 // --------------------------------------------------------------------------
 // X0[p] = (r.re / rms, r.im / rms, c[p], 0, 0, 0, 0, 0) with rms = ||r|| / sqrt(N),
 // ||r||^2 = *nr2 (entries of order one whatever the grid size)
-// ||r||^2 from nparts <= 64 partial sums: lane l of every wave loads part l and
-// a butterfly adds them; each step adds the same two values in every lane
-// (in either order: the same bits), so every thread gets the same sum
-__device__ __forceinline__ double sum_parts(const double* __restrict__ parts, int nparts) {
-    const int lane = threadIdx.x & 63;
-    double s = lane < nparts ? parts[lane] : 0.0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    return s;
-}
 
 template <class TV>
 __global__ void pack_input_kernel(long long N, const cx<TV>* __restrict__ r, const double* __restrict__ nr2,
@@ -636,17 +675,6 @@ void CnnImpl::forward(int H, int Wd, hipStream_t s) {
                                   nullptr, out.p, s);
 }
 
-void CnnImpl::forward_fused(int H, int Wd, hipStream_t s) {
-    HH_HIP(hipFuncSetAttribute((const void*)cnn_fused_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               FUSED_LDS));
-    dim3 grid((Wd + FT_W - 1) / FT_W, (H + FT_H - 1) / FT_H);
-    hipLaunchKernelGGL(cnn_fused_kernel, grid, dim3(FUSED_TB), FUSED_LDS, s, H, Wd, x0.as<__bf16>(),
-                       layers[0].wf.as<__bf16>(),
-                       layers[0].bias.as<float>(), layers[1].wf.as<__bf16>(), layers[1].bias.as<float>(),
-                       layers[2].wf.as<__bf16>(), layers[2].bias.as<float>(), layers[3].wf.as<__bf16>(),
-                       layers[3].bias.as<float>(), out.as<float>());
-}
-
 template <class TV>
 void CnnImpl::step(int H, int Wd, const cx<TV>* r, const float* feat, const cx<TV>* dinv, TV omega, cx<TV>* x,
                    int accumulate, hipStream_t s) {
@@ -655,12 +683,20 @@ void CnnImpl::step(int H, int Wd, const cx<TV>* r, const float* feat, const cx<T
     double* parts = scal.as<double>() + 8;   // kNormParts partial sums of ||r||^2
     const int np = (int)std::min<long long>(kNormParts, (N + 255) / 256);
     hipLaunchKernelGGL(norm2_parts_kernel<TV>, dim3(np), dim3(256), 0, s, N, r, parts);
+    if (fused) {
+        // the rest of the step in one kernel
+        HH_HIP(hipFuncSetAttribute((const void*)cnn_fused_kernel<TV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   FUSED_LDS));
+        dim3 grid((Wd + FT_W - 1) / FT_W, (H + FT_H - 1) / FT_H);
+        hipLaunchKernelGGL(cnn_fused_kernel<TV>, grid, dim3(FUSED_TB), FUSED_LDS, s, H, Wd, r, parts, np, feat,
+                           layers[0].wf.as<__bf16>(), layers[0].bias.as<float>(), layers[1].wf.as<__bf16>(),
+                           layers[1].bias.as<float>(), layers[2].wf.as<__bf16>(), layers[2].bias.as<float>(),
+                           layers[3].wf.as<__bf16>(), layers[3].bias.as<float>(), dinv, omega, x, accumulate);
+        return;
+    }
     hipLaunchKernelGGL(pack_input_kernel<TV>, dim3(g1(N, 256)), dim3(256), 0, s, N, r, parts, np, feat,
                        x0.as<__bf16>());
-    if (fused)
-        forward_fused(H, Wd, s);
-    else
-        forward(H, Wd, s);
+    forward(H, Wd, s);
     hipLaunchKernelGGL(apply_step_kernel<TV>, dim3(g1(N, 256)), dim3(256), 0, s, N, out.as<float>(), parts, np, r,
                        dinv, omega, x, accumulate);
 }
