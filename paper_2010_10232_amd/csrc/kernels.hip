@@ -1001,9 +1001,16 @@ __global__ __launch_bounds__(256) void symv_tiles_kernel(int n, const double* __
     const bool off = (I != J);
     double ur[32], ui[32];
     const double* Tw = T + (size_t)(32 * w) * SYT + 2 * lane;
+    // all 32 row loads of the wave are issued before any is used (the empty
+    // asm with a memory clobber keeps the compiler from interleaving them with
+    // the arithmetic, which left one or two loads in flight)
+    dbl2v av[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) av[q] = __builtin_nontemporal_load((const dbl2v*)(Tw + (size_t)q * SYT));
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int q = 0; q < 32; ++q) {
-        const dbl2v a = __builtin_nontemporal_load((const dbl2v*)(Tw + (size_t)q * SYT));
+        const dbl2v a = av[q];
         ur[q] = a.x * xj0.re + a.y * xj1.re;
         ui[q] = a.x * xj0.im + a.y * xj1.im;
         if (off) {
