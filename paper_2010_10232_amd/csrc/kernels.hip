@@ -1053,29 +1053,57 @@ __global__ __launch_bounds__(256) void symv_tiles_kernel(int n, const double* __
 }
 
 // y for block I: sum over J = 0 .. nt-1 of (J < I: column sums of tile (J, I),
-// J >= I: row sums of tile (I, J)), in that order.
-__global__ __launch_bounds__(SYT) void symv_reduce_kernel(int n, const cx<double>* __restrict__ rowpart,
-                                                          const cx<double>* __restrict__ colpart,
-                                                          cx<double>* __restrict__ y) {
-    const int I = blockIdx.x, r = threadIdx.x;
-    const long long gr = (long long)I * SYT + r;
-    if (gr >= n) return;
+// J >= I: row sums of tile (I, J)).  SYR_G lane groups of SYT threads take
+// J = g, g + SYR_G, ... in increasing order (four partials loaded at a time),
+// and the group sums are added in group order: a fixed order, deterministic.
+constexpr int SYR_G = 8;
+__global__ __launch_bounds__(SYT * SYR_G) void symv_reduce_kernel(int n, const cx<double>* __restrict__ rowpart,
+                                                                   const cx<double>* __restrict__ colpart,
+                                                                   cx<double>* __restrict__ y) {
+    __shared__ double sr_s[SYR_G][SYT], si_s[SYR_G][SYT];
+    const int I = blockIdx.x, r = threadIdx.x % SYT, grp = threadIdx.x / SYT;
     const long long nt = (n + SYT - 1) / SYT;
+    auto part = [&](long long J) -> cx<double> {
+        return (J < I) ? colpart[sym_tile_index(J, I, nt) * SYT + r] : rowpart[sym_tile_index(I, J, nt) * SYT + r];
+    };
     double sr = 0.0, si = 0.0;
-    for (long long J = 0; J < nt; ++J) {
-        const cx<double> v = (J < I) ? colpart[sym_tile_index(J, I, nt) * SYT + r]
-                                     : rowpart[sym_tile_index(I, J, nt) * SYT + r];
+    long long J = grp;
+    for (; J + 3 * SYR_G < nt; J += 4 * SYR_G) {
+        const cx<double> v0 = part(J), v1 = part(J + SYR_G), v2 = part(J + 2 * SYR_G), v3 = part(J + 3 * SYR_G);
+        sr += v0.re;
+        si += v0.im;
+        sr += v1.re;
+        si += v1.im;
+        sr += v2.re;
+        si += v2.im;
+        sr += v3.re;
+        si += v3.im;
+    }
+    for (; J < nt; J += SYR_G) {
+        const cx<double> v = part(J);
         sr += v.re;
         si += v.im;
     }
-    y[gr] = {sr, si};
+    sr_s[grp][r] = sr;
+    si_s[grp][r] = si;
+    __syncthreads();
+    const long long gr = (long long)I * SYT + threadIdx.x;
+    if (threadIdx.x < SYT && gr < n) {
+        double tr = 0.0, ti = 0.0;
+#pragma unroll
+        for (int g = 0; g < SYR_G; ++g) {
+            tr += sr_s[g][threadIdx.x];
+            ti += si_s[g][threadIdx.x];
+        }
+        y[gr] = {tr, ti};
+    }
 }
 
 void launch_symv(int n, const double* P, const cx<double>* x, cx<double>* rowpart, cx<double>* colpart,
                  cx<double>* y, hipStream_t s) {
     const unsigned nt = (unsigned)((n + SYT - 1) / SYT);
     hipLaunchKernelGGL(symv_tiles_kernel, dim3((unsigned)sym_tiles(n)), dim3(256), 0, s, n, P, x, rowpart, colpart);
-    hipLaunchKernelGGL(symv_reduce_kernel, dim3(nt), dim3(SYT), 0, s, n, rowpart, colpart, y);
+    hipLaunchKernelGGL(symv_reduce_kernel, dim3(nt), dim3(SYT * SYR_G), 0, s, n, rowpart, colpart, y);
 }
 
 // Dense-matrix set-up helpers: y[idx[i]] = val[i] (distinct indices), and
