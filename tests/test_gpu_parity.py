@@ -52,6 +52,8 @@ CASES = {
     "1d_p2_k50_2lev": dict(dim=1, p=2, n_el=80, k=50.0, x0=(0.5,), opts=dict(defl_mode=1)),
     "1d_p3_odd_multi": dict(dim=1, p=3, n_el=75, k=40.0, x0=(0.3,), opts=dict(defl_direct_max=20)),
     "2d_p1_k10": dict(dim=2, p=1, n_el=16, k=10.0, x0=(0.5, 0.5), opts=dict()),
+    # degree 1 with enough levels for the one-workgroup coarse tail (levels 1-3)
+    "2d_p1_k25_tail": dict(dim=2, p=1, n_el=40, k=25.0, x0=(0.45, 0.6), opts=dict()),
     "2d_p2_odd_multi": dict(dim=2, p=2, n_el=21, k=13.0, x0=(0.4, 0.55), opts=dict(defl_direct_max=100)),
     "2d_p3_multi": dict(dim=2, p=3, n_el=24, k=15.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=100)),
     "2d_p4_odd": dict(dim=2, p=4, n_el=19, k=12.0, x0=(0.5, 0.95), opts=dict()),
