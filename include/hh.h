@@ -90,6 +90,14 @@ typedef struct {
                                 4..64 rows and keep the fastest; 0: a fixed rule (the
                                 tallest strip that still gives 2048 waves).  Results do
                                 not depend on it. */
+    int ortho;               /* Arnoldi orthogonalisation, modified Gram-Schmidt in both forms:
+                                0 (default): where the restart length is at most 50 and
+                                the vectors at most 65536 entries, the one-reduction form
+                                (the triangular system (I + L) h = V^H w, L the strictly
+                                lower part of V^H V: equal to the projection-by-projection
+                                coefficients in exact arithmetic, one grid-wide sum per
+                                step instead of j + 1); 1: always one grid-wide sum per
+                                projection.  Results agree to rounding. */
 } hh_solver_opts;
 
 typedef struct {

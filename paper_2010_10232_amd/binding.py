@@ -38,7 +38,7 @@ class SolverOpts(ctypes.Structure):
                 ("defl_mode", ctypes.c_int), ("defl_direct_max", ctypes.c_int),
                 ("defl_inner_its", ctypes.c_int * 8), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("time_kernels", ctypes.c_int),
-                ("autotune", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("ortho", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

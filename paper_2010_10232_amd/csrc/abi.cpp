@@ -53,6 +53,7 @@ void hh_default_opts(hh_solver_opts* o) {
     o->precision = 0;
     o->time_kernels = 0;
     o->autotune = 1;
+    o->ortho = 0;
 }
 
 const char* hh_last_error(void) { return g_err.c_str(); }

@@ -189,8 +189,16 @@ struct KrylovDev {
                       // [5] grid-exchange timeout flag, [6] cooperative launch epoch
     cx<double>* partials;  // reduction partials (2 x 1024, double-buffered)
     unsigned long long* slots;  // grid-exchange words of the cooperative Arnoldi kernels (2 x 256 x 4)
+    cx<double>* gram;           // one-reduction Arnoldi (m <= kOneRedMaxM only, else null): rows 1..m-1
+                                // of the strictly lower part of V^H V, row i packed at i(i-1)/2
+    unsigned long long* vslots; // its vector-exchange words: [block][qcap][4]
+    int qcap;                   // 2m - 1 values per block (0 when not allocated)
     int m;
 };
+
+// One-reduction Arnoldi: restart lengths and grid sizes it serves.
+constexpr int kOneRedMaxM = 50;
+constexpr int kOneRedMaxBlocks = 64;
 
 // Coarse tail of the V-cycle run by one workgroup with its level vectors in
 // LDS (all levels from some l0 to the coarsest are small): per-level data,
@@ -288,10 +296,12 @@ void launch_lsq(KrylovDev& k, hipStream_t s, int ncols = -1);
 // fused Arnoldi step (MGS + norm + Givens + normalise): one workgroup for short
 // vectors, otherwise a grid of resident workgroups (launch_arnoldi_grid: false
 // when neither a resident launch fits `concurrent` grids nor coop_ok allows a
-// cooperative one; the caller then runs one kernel per projection)
+// cooperative one; the caller then runs one kernel per projection).  With
+// one_reduce, a grid the one-reduction kernel serves (k.qcap > 0, at most
+// kOneRedMaxBlocks workgroups, resident) takes that form.
 constexpr long long kSmallArnoldi = 4096;
 bool launch_arnoldi_grid(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
-                         hipStream_t s, int concurrent, bool coop_ok);
+                         hipStream_t s, int concurrent, bool coop_ok, bool one_reduce);
 void launch_arnoldi_small(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv,
                           KrylovDev& k, hipStream_t s);
 void launch_update(long long N, const cx<double>* Z, long long ldz, KrylovDev& k, cx<double>* u,

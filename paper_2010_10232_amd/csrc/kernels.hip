@@ -1605,6 +1605,236 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
     }
 }
 
+// One Arnoldi step in the one-reduction form of modified Gram-Schmidt (the
+// inverse compact-WY form of Swirydowicz, Langou, Ananthan, Yang and Thomas,
+// 2020).  MGS subtracts the projections in order, so its coefficients satisfy
+// h_i = v_i^H w - sum_{k<i} (v_i^H v_k) h_k, that is (I + L) h = V^H w with L
+// the strictly lower part of V^H V; this holds for the computed, not exactly
+// orthonormal, basis too, so solving that triangular system gives the MGS
+// projection w - V h without a chain of j + 1 dependent reductions.  Per step:
+//   pass 1: c = V^H w and the new Gram row v_j^H v_k (k < j), block partials
+//           (each wave takes every fourth basis vector over the block's 1024
+//           entries, w and v_j staged in LDS);
+//   one grid-wide exchange of those 2j + 1 values (tagged words as in
+//           exchange_sum, summed in block order by groups of eight);
+//   forward substitution for h with rows 1..j-1 of L kept from earlier steps
+//           (same operations in every block: identical h everywhere);
+//   pass 2: w -= sum_i h_i v_i in order of i;
+//   hn = ||w|| (scalar exchange), the Givens update, w /= hn.
+// Block 0 stores column j of H and row j of L.  Every launch writes all of its
+// block's qcap exchange slots (zero beyond 2j + 1 values), so a slot never
+// holds an older launch's tag when it is read.
+constexpr int OR_R = 4;                 // entries of w per thread
+constexpr int OR_CH = RB * OR_R;        // entries per block
+constexpr int OR_QMAX = 2 * kOneRedMaxM - 1;
+constexpr int OR_GMAX = kOneRedMaxBlocks / 8;
+
+__global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, cx<double>* __restrict__ w,
+                                                            const cx<double>* __restrict__ V, long long ldv,
+                                                            KrylovDev k) {
+    __shared__ cx<double> sw[OR_CH];    // w's entries of this block; later the group partials
+    __shared__ cx<double> sv[OR_CH];    // v_j's entries of this block
+    __shared__ cx<double> sL[kOneRedMaxM * (kOneRedMaxM - 1) / 2];
+    __shared__ cx<double> sq[OR_QMAX];  // block partials, then grid sums
+    __shared__ cx<double> shh[kOneRedMaxM];
+    __shared__ double sh[2 * (RB / 64)];
+    __shared__ double shb[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long long stride = (long long)gridDim.x * RB;
+    const long long base = (long long)blockIdx.x * RB;
+    const int ldh = k.m + 1;
+    const int epoch = step_epoch(k);
+    const int Q = 2 * j + 1;
+    const cx<double>* vj = V + (size_t)j * ldv;
+    // own entries (p = tid + RB r), clamped reads of valid addresses, zero beyond N
+    cx<double> wr[OR_R];
+#pragma unroll
+    for (int r = 0; r < OR_R; ++r) {
+        const long long t = base + tid + r * stride;
+        const long long tc = t < N ? t : N - 1;
+        const cx<double> a = w[tc], b = vj[tc];
+        wr[r] = t < N ? a : cx<double>{0.0, 0.0};
+        sw[tid + RB * r] = wr[r];
+        sv[tid + RB * r] = t < N ? b : cx<double>{0.0, 0.0};
+    }
+    // rows 1..j-1 of L (packed) for the substitution
+    const int nL = j * (j - 1) / 2;
+    for (int i = tid; i < nL; i += RB) sL[i] = k.gram[i];
+    __syncthreads();
+
+    // pass 1: wave `wave` takes v_i for i = wave, wave + 4, ...; lane covers the
+    // block positions p = lane + 64 q (q = 0..15)
+    constexpr int PQ = OR_CH / 64;
+    auto load_vec = [&](int i, cx<double>* dst) {
+        const cx<double>* vi = V + (size_t)i * ldv;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+            const int p = lane + 64 * q;
+            const long long t = base + (p & (RB - 1)) + (long long)(p / RB) * stride;
+            dst[q] = vi[t < N ? t : N - 1];
+        }
+    };
+    cx<double> cur[PQ], nxt[PQ];
+    if (wave <= j) load_vec(wave, cur);
+    for (int i = wave; i <= j; i += 4) {
+        if (i + 4 <= j) load_vec(i + 4, nxt);
+        double cr = 0.0, ci = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+            // entries beyond N: w and v_j are zero there
+            const int p = lane + 64 * q;
+            const cx<double> a = cur[q], ww = sw[p], vv = sv[p];
+            cr += a.re * ww.re + a.im * ww.im;   // v_i^H w
+            ci += a.re * ww.im - a.im * ww.re;
+            gr += vv.re * a.re + vv.im * a.im;   // v_j^H v_i
+            gi += vv.re * a.im - vv.im * a.re;
+        }
+        wave_sum2(cr, ci);
+        wave_sum2(gr, gi);
+        if (lane == 0) {
+            sq[i] = {cr, ci};
+            if (i < j) sq[j + 1 + i] = {gr, gi};
+        }
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) cur[q] = nxt[q];
+    }
+    __syncthreads();
+
+    // publish this block's values: all qcap slots, four tagged words each
+    const unsigned tag = step_tag(epoch, 0);
+    const int qcap = k.qcap;
+    for (int q = tid; q < qcap; q += RB) {
+        const cx<double> v = q < Q ? sq[q] : cx<double>{0.0, 0.0};
+        const unsigned long long br = (unsigned long long)__double_as_longlong(v.re);
+        const unsigned long long bi = (unsigned long long)__double_as_longlong(v.im);
+        unsigned long long* wd = k.vslots + ((size_t)blockIdx.x * qcap + q) * 4;
+        __hip_atomic_store(wd + 0, (br & 0xffffffff00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(wd + 1, (br << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(wd + 2, (bi & 0xffffffff00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(wd + 3, (bi << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // collect: item (q, g) sums blocks 8g .. 8g + 7 of value q in block order
+    const int G = gridDim.x, NG = (G + 7) / 8;
+    cx<double>* sp = sw;   // [q][OR_GMAX] group partials (sw is no longer needed)
+    for (int it = tid; it < Q * NG; it += RB) {
+        const int q = it / NG, g = it - q * NG;
+        const int b0 = 8 * g, nb = min(8, G - b0);
+        unsigned todo = (1u << nb) - 1u;
+        double vr[8], vi[8];
+        int spins = 0;
+        while (todo) {
+            unsigned long long x[8][4];
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                if (todo & (1u << b)) {
+                    const unsigned long long* wd = k.vslots + ((size_t)(b0 + b) * qcap + q) * 4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        x[b][e] = __hip_atomic_load(wd + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                if ((todo & (1u << b)) && (unsigned)x[b][0] == tag && (unsigned)x[b][1] == tag &&
+                    (unsigned)x[b][2] == tag && (unsigned)x[b][3] == tag) {
+                    vr[b] = __longlong_as_double((long long)((x[b][0] & 0xffffffff00000000ull) | (x[b][1] >> 32)));
+                    vi[b] = __longlong_as_double((long long)((x[b][2] & 0xffffffff00000000ull) | (x[b][3] >> 32)));
+                    todo &= ~(1u << b);
+                }
+            if (!todo) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1 << 20)) {
+                atomicExch(&k.ints[5], 1);
+                break;
+            }
+            if ((spins & 1023) == 0 && __hip_atomic_load(&k.ints[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+        }
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+            if (b < nb) {
+                ar += (todo & (1u << b)) ? 0.0 : vr[b];
+                ai += (todo & (1u << b)) ? 0.0 : vi[b];
+            }
+        sp[q * OR_GMAX + g] = {ar, ai};
+    }
+    __syncthreads();
+    for (int q = tid; q < Q; q += RB) {
+        double ar = 0.0, ai = 0.0;
+        for (int g = 0; g < NG; ++g) {
+            ar += sp[q * OR_GMAX + g].re;
+            ai += sp[q * OR_GMAX + g].im;
+        }
+        sq[q] = {ar, ai};
+    }
+    __syncthreads();
+
+    // (I + L) h = c by forward substitution in wave 0, lane i holding row i
+    if (wave == 0) {
+        cx<double> x = lane <= j ? sq[lane] : cx<double>{0.0, 0.0};
+        for (int kk = 0; kk < j; ++kk) {
+            const long long hr = __double_as_longlong(x.re), hi = __double_as_longlong(x.im);
+            const double h_re = __longlong_as_double(
+                ((long long)__builtin_amdgcn_readlane((int)(hr >> 32), kk) << 32) |
+                (unsigned)__builtin_amdgcn_readlane((int)hr, kk));
+            const double h_im = __longlong_as_double(
+                ((long long)__builtin_amdgcn_readlane((int)(hi >> 32), kk) << 32) |
+                (unsigned)__builtin_amdgcn_readlane((int)hi, kk));
+            if (lane > kk && lane <= j) {
+                const cx<double> l = lane < j ? sL[lane * (lane - 1) / 2 + kk] : sq[j + 1 + kk];
+                x.re -= l.re * h_re - l.im * h_im;
+                x.im -= l.re * h_im + l.im * h_re;
+            }
+        }
+        if (lane <= j) shh[lane] = x;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int kk = tid; kk < j; kk += RB) k.gram[j * (j - 1) / 2 + kk] = sq[j + 1 + kk];
+
+    // pass 2: w -= sum_i h_i v_i over this thread's entries, eight vectors at a time
+    for (int i0 = 0; i0 <= j; i0 += 8) {
+        cx<double> vb[8][OR_R];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + u <= j) {
+                const cx<double>* vi = V + (size_t)(i0 + u) * ldv;
+#pragma unroll
+                for (int r = 0; r < OR_R; ++r) {
+                    const long long t = base + tid + r * stride;
+                    vb[u][r] = vi[t < N ? t : N - 1];
+                }
+            }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + u <= j) {
+                const cx<double> h = shh[i0 + u];
+#pragma unroll
+                for (int r = 0; r < OR_R; ++r) {
+                    wr[r].re -= h.re * vb[u][r].re - h.im * vb[u][r].im;
+                    wr[r].im -= h.re * vb[u][r].im + h.im * vb[u][r].re;
+                }
+            }
+    }
+    double nr = 0.0, zero = 0.0;
+#pragma unroll
+    for (int r = 0; r < OR_R; ++r) {
+        const long long t = base + tid + r * stride;
+        if (t < N) nr += wr[r].re * wr[r].re + wr[r].im * wr[r].im;
+    }
+    const double hn = sqrt(grid_sum_reg(nr, zero, step_tag(epoch, 1), k, sh, shb).re);
+    if (blockIdx.x == 0 && tid == 0) {
+        for (int i = 0; i <= j; ++i) k.H[(size_t)j * ldh + i] = shh[i];
+        givens_column(k, j, hn);
+    }
+    next_epoch(k, epoch);
+#pragma unroll
+    for (int r = 0; r < OR_R; ++r) {
+        const long long t = base + tid + r * stride;
+        if (t < N) w[t] = hn == 0.0 ? cx<double>{0.0, 0.0} : cx<double>{wr[r].re / hn, wr[r].im / hn};
+    }
+}
+
 // Blocks of RB threads of kernel fn that the current device holds at once
 // (cached per device and kernel).
 static long long resident_capacity(const void* fn) {
@@ -1631,8 +1861,16 @@ int coop_blocks(long long N) {
 }
 
 bool launch_arnoldi_grid(long long N, int j, cx<double>* w, const cx<double>* V, long long ldv, KrylovDev& k,
-                         hipStream_t s, int concurrent, bool coop_ok) {
+                         hipStream_t s, int concurrent, bool coop_ok, bool one_reduce) {
     void* args[] = {&N, &j, &w, &V, &ldv, &k};
+    if (one_reduce && k.qcap > 0 && j < k.m && k.m <= kOneRedMaxM) {
+        const long long b1 = (N + OR_CH - 1) / OR_CH;
+        const void* f1 = (const void*)arnoldi_onered_kernel;
+        if (b1 <= kOneRedMaxBlocks && b1 * concurrent <= resident_capacity(f1)) {
+            HH_HIP(hipLaunchKernel(f1, dim3((unsigned)b1), dim3(RB), args, 0, s));
+            return true;
+        }
+    }
     const void* fn = (const void*)arnoldi_coop_kernel;
     long long blocks = coop_blocks(N);
     // register-resident kernel: R entries per thread, at most 256 blocks

@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstring>
 
 #include "solver.h"
@@ -105,7 +106,12 @@ static void invert_complex(int n, std::vector<zd>& A) {
 static void fill_krylov(KrylovDev& k, DevBuf& blob, int m) {
     const size_t nH = (size_t)(m + 1) * m, nb = 2048;
     const size_t nslots = 2 * 256 * 4;
-    size_t bytes = 16 * nH + 8 * m + 16 * m + 16 * (m + 1) + 16 * m + 8 * 8 + 16 * nb + 4 * 8 + 8 * nslots;
+    // one-reduction Arnoldi state: packed Gram rows and the vector-exchange words
+    const int qcap = m <= kOneRedMaxM ? 2 * m - 1 : 0;
+    const size_t ngram = qcap ? (size_t)m * (m - 1) / 2 + 1 : 0;
+    const size_t nvslots = (size_t)kOneRedMaxBlocks * qcap * 4;
+    size_t bytes = 16 * nH + 8 * m + 16 * m + 16 * (m + 1) + 16 * m + 8 * 8 + 16 * nb + 4 * 8 + 8 * nslots +
+                   16 * ngram + 8 * nvslots;
     blob.alloc(bytes + 256);
     char* p = blob.as<char>();
     k.m = m;
@@ -126,6 +132,12 @@ static void fill_krylov(KrylovDev& k, DevBuf& blob, int m) {
     k.ints = (int*)p;   // directly after scal: both reach the host in one transfer
     p += 4 * 8;
     k.slots = (unsigned long long*)p;   // zero words never carry a valid tag
+    p += 8 * nslots;
+    p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+    k.gram = qcap ? (cx<double>*)p : nullptr;
+    p += 16 * ngram;
+    k.vslots = qcap ? (unsigned long long*)p : nullptr;
+    k.qcap = qcap;
     HH_HIP(hipMemset(blob.p, 0, blob.bytes));
 }
 
@@ -192,6 +204,7 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(o.restart >= 1 && o.restart <= 200, "restart must be in 1..200");
     HH_REQUIRE(o.maxit >= 1, "maxit must be >= 1");
     HH_REQUIRE(o.nu_pre >= 1 && o.nu_post >= 0 && o.n_vcycles >= 1, "bad smoothing counts");
+    HH_REQUIRE(o.ortho == 0 || o.ortho == 1, "ortho is 0 or 1");
     HH_REQUIRE(o.mg_min_elems >= 2, "mg_min_elems must be >= 2");
     HH_REQUIRE(o.defl_mode >= 0 && o.defl_mode <= 2, "defl_mode must be 0, 1 or 2");
     HH_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
@@ -908,7 +921,7 @@ void SolverImpl::T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t 
 void SolverImpl::arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s) {
     if (N <= kSmallArnoldi) {
         launch_arnoldi_small(N, j, w, Vb, N, k, s);
-    } else if (launch_arnoldi_grid(N, j, w, Vb, N, k, s, allow_coop ? 4 : 16, allow_coop)) {
+    } else if (launch_arnoldi_grid(N, j, w, Vb, N, k, s, allow_coop ? 4 : 16, allow_coop, o.ortho == 0)) {
     } else {
         for (int i = 0; i <= j; ++i) launch_mgs(N, i, j, w, Vb, N, k, s);
         launch_norm_givens(N, j, w, Vb, N, k, s);

@@ -33,7 +33,7 @@ def test_default_opts():
     assert o.omega == 0.8 and o.restart == 50 and o.tol == 1e-7 and o.maxit == 1000
     assert list(o.defl_inner_its) == [8, 4, 2, 1, 1, 1, 1, 1]
     assert o.defl_direct_max == 16384 and o.coarse_damping == 1 and o.defl_mode == 2
-    assert o.precision == 0 and o.time_kernels == 0 and o.autotune == 1
+    assert o.precision == 0 and o.time_kernels == 0 and o.autotune == 1 and o.ortho == 0
 
 
 @pytest.mark.parametrize("kw", [dict(dim=3, p=2, n_el=8, k=1.0), dict(dim=2, p=0, n_el=8, k=1.0),
