@@ -186,7 +186,8 @@ struct KrylovDev {
     cx<double>* y;    // m
     double* scal;     // [0] beta, [1] hn, [2] |g_{j+1}|, [3] norm accumulator
     int* ints;        // [0] jdone, [1] breakdown flag, [2] reduction counter,
-                      // [5] grid-exchange timeout flag, [6] cooperative launch epoch
+                      // [5] grid-exchange timeout flag, [6] cooperative launch epoch,
+                      // [7] epoch of the last full write of vslots
     cx<double>* partials;  // reduction partials (2 x 1024, double-buffered)
     unsigned long long* slots;  // grid-exchange words of the cooperative Arnoldi kernels (2 x 256 x 4)
     cx<double>* gram;           // one-reduction Arnoldi (m <= kOneRedMaxM only, else null): rows 1..m-1
@@ -196,6 +197,8 @@ struct KrylovDev {
     int m;
 };
 
+// Longest outer restart (Krylov basis length) the solver accepts.
+constexpr int kMaxRestart = 200;
 // One-reduction Arnoldi: restart lengths and grid sizes it serves.
 constexpr int kOneRedMaxM = 50;
 constexpr int kOneRedMaxBlocks = 64;

@@ -1247,43 +1247,57 @@ __device__ void givens_rot(cx<double> a, cx<double> b, double& c, cx<double>& s)
     }
 }
 
-// Givens update of Hessenberg column j (previous rotations, then a new one
-// annihilating H[j+1, j]) and of the residual vector g; single thread.
-__device__ void givens_column(KrylovDev& k, int j, double hn) {
-    const int ldh = k.m + 1;
-    k.scal[1] = hn;
-    cx<double>* Hc = k.H + (size_t)j * ldh;
-    Hc[j + 1] = {hn, 0.0};
+// Givens update of a Hessenberg column Hc[0..j+1] with H[j+1, j] = hn: the
+// previous rotations (cs, sn) in order, then the new one annihilating
+// H[j+1, j], returned in c, s.  Single thread; the same operations wherever
+// the column and the rotations are held (device memory or LDS).
+__device__ __forceinline__ void givens_rotate(cx<double>* Hc, const double* cs, const cx<double>* sn, int j,
+                                              double hn, double& c, cx<double>& s) {
+    // rotation ii acts on entries ii and ii + 1; the rotated entry ii + 1 is
+    // carried to the next rotation in a register
+    cx<double> a = Hc[0];
     for (int ii = 0; ii < j; ++ii) {
-        const double c = k.cs[ii];
-        const cx<double> s = k.sn[ii];
-        const cx<double> a = Hc[ii], b = Hc[ii + 1];
-        const cx<double> sb = cmul(s, b);
-        const cx<double> t = {c * a.re + sb.re, c * a.im + sb.im};
-        const cx<double> cs_ = {s.re, -s.im};
+        const double ci = cs[ii];
+        const cx<double> si = sn[ii];
+        const cx<double> b = Hc[ii + 1];
+        const cx<double> sb = cmul(si, b);
+        const cx<double> t = {ci * a.re + sb.re, ci * a.im + sb.im};
+        const cx<double> cs_ = {si.re, -si.im};
         const cx<double> ca = cmul(cs_, a);
-        Hc[ii + 1] = {-ca.re + c * b.re, -ca.im + c * b.im};
         Hc[ii] = t;
+        a = {-ca.re + ci * b.re, -ca.im + ci * b.im};
     }
-    double c;
-    cx<double> s;
-    givens_rot(Hc[j], Hc[j + 1], c, s);
+    const cx<double> b = {hn, 0.0};
+    givens_rot(a, b, c, s);
+    const cx<double> sb = cmul(s, b);
+    Hc[j] = {c * a.re + sb.re, c * a.im + sb.im};
+    Hc[j + 1] = {0.0, 0.0};
+}
+
+// The rest of step j's update: rotation j stored, g rotated, |g_{j+1}|, the
+// step count and the breakdown flag (gj = g[j], broke = the flag on entry).
+__device__ __forceinline__ void givens_finish(KrylovDev& k, int j, double hn, double c, cx<double> s,
+                                              cx<double> gj, int broke) {
+    k.scal[1] = hn;
     k.cs[j] = c;
     k.sn[j] = s;
-    {
-        const cx<double> a = Hc[j], b = Hc[j + 1];
-        const cx<double> sb = cmul(s, b);
-        Hc[j] = {c * a.re + sb.re, c * a.im + sb.im};
-        Hc[j + 1] = {0.0, 0.0};
-    }
-    const cx<double> gj = k.g[j];
     const cx<double> cs_ = {s.re, -s.im};
     const cx<double> ng = cmul(cs_, gj);
-    k.g[j + 1] = {-ng.re, -ng.im};
+    const cx<double> g1 = {-ng.re, -ng.im};
+    k.g[j + 1] = g1;
     k.g[j] = {c * gj.re, c * gj.im};
-    k.scal[2] = hypot(k.g[j + 1].re, k.g[j + 1].im);
-    if (!k.ints[1]) k.ints[0] = j + 1;
+    k.scal[2] = hypot(g1.re, g1.im);
+    if (!broke) k.ints[0] = j + 1;
     if (hn == 0.0) k.ints[1] = 1;
+}
+
+// Givens update of Hessenberg column j and of the residual vector g, all in
+// device memory; single thread.
+__device__ void givens_column(KrylovDev& k, int j, double hn) {
+    double c;
+    cx<double> s;
+    givens_rotate(k.H + (size_t)j * (k.m + 1), k.cs, k.sn, j, hn, c, s);
+    givens_finish(k, j, hn, c, s, k.g[j], k.ints[1]);
 }
 
 // w -= H[j,j] V[j]; hn = ||w||; H[j+1,j] = hn; Givens update of column j and g.
@@ -1384,13 +1398,45 @@ void launch_arnoldi_small(long long N, int j, cx<double>* w, const cx<double>* V
     hipLaunchKernelGGL(arnoldi_small_kernel, dim3(1), dim3(SB), 0, s, N, j, w, V, ldv, k);
 }
 
-// Butterfly sum over a wave: every lane ends with the same bits.
+// Sum over a wave into lane 63 with DPP lane moves (no LDS traffic): pairs and
+// quads (quad permutations), half rows and rows (mirrors), then row 0 into row
+// 1 and row 2 into row 3 (broadcast of lanes 15 and 47), then rows 0-1 into
+// rows 2-3 (broadcast of lane 31).  Fixed order; only lane 63 holds the total.
+// All 64 lanes must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_last(double v) {
+    v += dpp_f64<0xb1, 0xf>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4e, 0xf>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xf>(v);   // row_half_mirror
+    v += dpp_f64<0x140, 0xf>(v);   // row_mirror
+    v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+__device__ __forceinline__ void wave_sum_last4(double& a, double& b, double& c, double& d) {
+    a = wave_sum_last(a);
+    b = wave_sum_last(b);
+    c = wave_sum_last(c);
+    d = wave_sum_last(d);
+}
+__device__ __forceinline__ double lane63(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over a wave with the same bits in every lane (lane 63's total, read by
+// all lanes).  All 64 lanes must be active.
 __device__ __forceinline__ void wave_sum2(double& a, double& b) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o, 64);
-        b += __shfl_xor(b, o, 64);
-    }
+    a = lane63(wave_sum_last(a));
+    b = lane63(wave_sum_last(b));
 }
 
 // Deterministic grid-wide complex sum for a cooperatively launched grid
@@ -1398,7 +1444,7 @@ __device__ __forceinline__ void wave_sum2(double& a, double& b) {
 // partial as four 64-bit words, each holding 32 bits of the value in its high
 // half and, in its low half, a tag unique to (launch, round).  Wave 0 of every
 // block polls the words of all blocks until every tag matches, adds the
-// partials in block order (lane-strided, then a butterfly, so every block gets
+// partials in block order (lane-strided, then a fixed-order wave sum, so every block gets
 // identical bits) and hands the sum to the other waves through LDS.  The words
 // are written and read as single-copy-atomic 64-bit accesses at device scope,
 // so a matching tag implies the value bits beside it are current; no other
@@ -1526,15 +1572,16 @@ __global__ __launch_bounds__(RB) void arnoldi_coop_kernel(long long N, int j, cx
 // Register-resident variant for N <= 256 * RB * R: every thread keeps its R
 // entries of w and of the current basis vector in registers, prefetches the
 // next basis vector before the grid-wide exchange (it does not depend on h),
-// and forms its block partial with wave butterflies plus one ordered pass over
+// and forms its block partial with wave sums plus one ordered pass over
 // the four waves.  Same MGS order and one grid-wide exchange per projection as
 // arnoldi_coop_kernel.
 
 __device__ __forceinline__ cx<double> grid_sum_reg(double sr, double si, unsigned tag, KrylovDev& k, double* sh,
                                                    double* shb) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    wave_sum2(sr, si);
-    if (lane == 0) {
+    sr = wave_sum_last(sr);
+    si = wave_sum_last(si);
+    if (lane == 63) {
         sh[2 * wave] = sr;
         sh[2 * wave + 1] = si;
     }
@@ -1556,10 +1603,25 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
                                                          KrylovDev k) {
     __shared__ double sh[2 * (RB / 64)];
     __shared__ double shb[2];
+    __shared__ cx<double> shc[kMaxRestart + 1];   // block 0: column j of H
+    __shared__ double scs[kMaxRestart];            // block 0: rotations 0..j-1
+    __shared__ cx<double> ssn[kMaxRestart];
     const long long stride = (long long)gridDim.x * RB;
     const long long t0 = (long long)blockIdx.x * RB + threadIdx.x;
     const int ldh = k.m + 1;
     const int epoch = step_epoch(k);
+    cx<double> gj = {0.0, 0.0};
+    int broke = 0;
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < j; i += RB) {
+            scs[i] = k.cs[i];
+            ssn[i] = k.sn[i];
+        }
+        if (threadIdx.x == 0) {
+            gj = k.g[j];
+            broke = k.ints[1];
+        }
+    }
     cx<double> wr[R], vr[R], vn[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1584,7 +1646,7 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
             }
         }
         const cx<double> h = grid_sum_reg(sr, si, step_tag(epoch, round), k, sh, shb);
-        if (blockIdx.x == 0 && threadIdx.x == 0) k.H[(size_t)j * ldh + i] = h;
+        if (blockIdx.x == 0 && threadIdx.x == 0) shc[i] = h;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             wr[r].re -= h.re * vr[r].re - h.im * vr[r].im;
@@ -1596,7 +1658,13 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
 #pragma unroll
     for (int r = 0; r < R; ++r) nr += wr[r].re * wr[r].re + wr[r].im * wr[r].im;
     const double hn = sqrt(grid_sum_reg(nr, zero, step_tag(epoch, round), k, sh, shb).re);
-    if (blockIdx.x == 0 && threadIdx.x == 0) givens_column(k, j, hn);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double c;
+        cx<double> sg;
+        givens_rotate(shc, scs, ssn, j, hn, c, sg);
+        for (int i = 0; i <= j + 1; ++i) k.H[(size_t)j * ldh + i] = shc[i];
+        givens_finish(k, j, hn, c, sg, gj, broke);
+    }
     next_epoch(k, epoch);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1621,13 +1689,13 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
 //           (same operations in every block: identical h everywhere);
 //   pass 2: w -= sum_i h_i v_i in order of i;
 //   hn = ||w|| (scalar exchange), the Givens update, w /= hn.
-// Block 0 stores column j of H and row j of L.  Every launch writes all of its
-// block's qcap exchange slots (zero beyond 2j + 1 values), so a slot never
-// holds an older launch's tag when it is read.
+// Block 0 stores column j of H and row j of L.  A launch writes the 2j + 1
+// exchange slots it uses and, when 2^20 launches have passed since the last
+// such write, zeros in the rest, so no slot read holds an older launch's word
+// with a matching tag.
 constexpr int OR_R = 4;                 // entries of w per thread
 constexpr int OR_CH = RB * OR_R;        // entries per block
 constexpr int OR_QMAX = 2 * kOneRedMaxM - 1;
-constexpr int OR_GMAX = kOneRedMaxBlocks / 8;
 
 __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, cx<double>* __restrict__ w,
                                                             const cx<double>* __restrict__ V, long long ldv,
@@ -1636,7 +1704,9 @@ __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, 
     __shared__ cx<double> sv[OR_CH];    // v_j's entries of this block
     __shared__ cx<double> sL[kOneRedMaxM * (kOneRedMaxM - 1) / 2];
     __shared__ cx<double> sq[OR_QMAX];  // block partials, then grid sums
-    __shared__ cx<double> shh[kOneRedMaxM];
+    __shared__ cx<double> shh[kOneRedMaxM + 1];  // h, then the rotated column j of H
+    __shared__ double scs[kOneRedMaxM];            // block 0: rotations 0..j-1
+    __shared__ cx<double> ssn[kOneRedMaxM];
     __shared__ double sh[2 * (RB / 64)];
     __shared__ double shb[2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1644,8 +1714,37 @@ __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, 
     const long long base = (long long)blockIdx.x * RB;
     const int ldh = k.m + 1;
     const int epoch = step_epoch(k);
+    const bool refresh = (unsigned)(epoch - __hip_atomic_load(&k.ints[7], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >=
+                         (1u << 20) || epoch == 0;
     const int Q = 2 * j + 1;
     const cx<double>* vj = V + (size_t)j * ldv;
+    // pass 1 reads: wave `wave` takes v_i for i = wave, wave + 4, ...; lane
+    // covers the block positions p = lane + 64 q (q = 0..15)
+    constexpr int PQ = OR_CH / 64;
+    auto load_vec = [&](int i, cx<double>* dst) {
+        const cx<double>* vi = V + (size_t)i * ldv;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+            const int p = lane + 64 * q;
+            const long long t = base + (p & (RB - 1)) + (long long)(p / RB) * stride;
+            dst[q] = vi[t < N ? t : N - 1];
+        }
+    };
+    cx<double> cur[PQ], nxt[PQ];
+    if (wave <= j) load_vec(wave, cur);   // in flight with the loads below
+    // block 0, for the Givens update at the end: rotations, g[j] and the flag
+    cx<double> gj = {0.0, 0.0};
+    int broke = 0;
+    if (blockIdx.x == 0) {
+        for (int i = tid; i < j; i += RB) {
+            scs[i] = k.cs[i];
+            ssn[i] = k.sn[i];
+        }
+        if (tid == 0) {
+            gj = k.g[j];
+            broke = k.ints[1];
+        }
+    }
     // own entries (p = tid + RB r), clamped reads of valid addresses, zero beyond N
     cx<double> wr[OR_R];
 #pragma unroll
@@ -1662,20 +1761,7 @@ __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, 
     for (int i = tid; i < nL; i += RB) sL[i] = k.gram[i];
     __syncthreads();
 
-    // pass 1: wave `wave` takes v_i for i = wave, wave + 4, ...; lane covers the
-    // block positions p = lane + 64 q (q = 0..15)
-    constexpr int PQ = OR_CH / 64;
-    auto load_vec = [&](int i, cx<double>* dst) {
-        const cx<double>* vi = V + (size_t)i * ldv;
-#pragma unroll
-        for (int q = 0; q < PQ; ++q) {
-            const int p = lane + 64 * q;
-            const long long t = base + (p & (RB - 1)) + (long long)(p / RB) * stride;
-            dst[q] = vi[t < N ? t : N - 1];
-        }
-    };
-    cx<double> cur[PQ], nxt[PQ];
-    if (wave <= j) load_vec(wave, cur);
+    // pass 1
     for (int i = wave; i <= j; i += 4) {
         if (i + 4 <= j) load_vec(i + 4, nxt);
         double cr = 0.0, ci = 0.0, gr = 0.0, gi = 0.0;
@@ -1689,9 +1775,8 @@ __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, 
             gr += vv.re * a.re + vv.im * a.im;   // v_j^H v_i
             gi += vv.re * a.im - vv.im * a.re;
         }
-        wave_sum2(cr, ci);
-        wave_sum2(gr, gi);
-        if (lane == 0) {
+        wave_sum_last4(cr, ci, gr, gi);
+        if (lane == 63) {
             sq[i] = {cr, ci};
             if (i < j) sq[j + 1 + i] = {gr, gi};
         }
@@ -1700,101 +1785,24 @@ __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, 
     }
     __syncthreads();
 
-    // publish this block's values: all qcap slots, four tagged words each
+    // publish this block's 2j + 1 values, four tagged words each; slot (q, b) at
+    // q Gp + b (Gp: the grid rounded up to eight blocks)
     const unsigned tag = step_tag(epoch, 0);
     const int qcap = k.qcap;
-    for (int q = tid; q < qcap; q += RB) {
-        const cx<double> v = q < Q ? sq[q] : cx<double>{0.0, 0.0};
+    const int G = gridDim.x, Gp = (G + 7) & ~7, NG = Gp / 8;
+    auto publish = [&](int q, cx<double> v) {
         const unsigned long long br = (unsigned long long)__double_as_longlong(v.re);
         const unsigned long long bi = (unsigned long long)__double_as_longlong(v.im);
-        unsigned long long* wd = k.vslots + ((size_t)blockIdx.x * qcap + q) * 4;
+        unsigned long long* wd = k.vslots + ((size_t)q * Gp + blockIdx.x) * 4;
         __hip_atomic_store(wd + 0, (br & 0xffffffff00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(wd + 1, (br << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(wd + 2, (bi & 0xffffffff00000000ull) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(wd + 3, (bi << 32) | tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    // collect: item (q, g) sums blocks 8g .. 8g + 7 of value q in block order
-    const int G = gridDim.x, NG = (G + 7) / 8;
-    cx<double>* sp = sw;   // [q][OR_GMAX] group partials (sw is no longer needed)
-    for (int it = tid; it < Q * NG; it += RB) {
-        const int q = it / NG, g = it - q * NG;
-        const int b0 = 8 * g, nb = min(8, G - b0);
-        unsigned todo = (1u << nb) - 1u;
-        double vr[8], vi[8];
-        int spins = 0;
-        while (todo) {
-            unsigned long long x[8][4];
-#pragma unroll
-            for (int b = 0; b < 8; ++b)
-                if (todo & (1u << b)) {
-                    const unsigned long long* wd = k.vslots + ((size_t)(b0 + b) * qcap + q) * 4;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        x[b][e] = __hip_atomic_load(wd + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-#pragma unroll
-            for (int b = 0; b < 8; ++b)
-                if ((todo & (1u << b)) && (unsigned)x[b][0] == tag && (unsigned)x[b][1] == tag &&
-                    (unsigned)x[b][2] == tag && (unsigned)x[b][3] == tag) {
-                    vr[b] = __longlong_as_double((long long)((x[b][0] & 0xffffffff00000000ull) | (x[b][1] >> 32)));
-                    vi[b] = __longlong_as_double((long long)((x[b][2] & 0xffffffff00000000ull) | (x[b][3] >> 32)));
-                    todo &= ~(1u << b);
-                }
-            if (!todo) break;
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > (1 << 20)) {
-                atomicExch(&k.ints[5], 1);
-                break;
-            }
-            if ((spins & 1023) == 0 && __hip_atomic_load(&k.ints[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                break;
-        }
-        double ar = 0.0, ai = 0.0;
-#pragma unroll
-        for (int b = 0; b < 8; ++b)
-            if (b < nb) {
-                ar += (todo & (1u << b)) ? 0.0 : vr[b];
-                ai += (todo & (1u << b)) ? 0.0 : vi[b];
-            }
-        sp[q * OR_GMAX + g] = {ar, ai};
-    }
-    __syncthreads();
-    for (int q = tid; q < Q; q += RB) {
-        double ar = 0.0, ai = 0.0;
-        for (int g = 0; g < NG; ++g) {
-            ar += sp[q * OR_GMAX + g].re;
-            ai += sp[q * OR_GMAX + g].im;
-        }
-        sq[q] = {ar, ai};
-    }
-    __syncthreads();
-
-    // (I + L) h = c by forward substitution in wave 0, lane i holding row i
-    if (wave == 0) {
-        cx<double> x = lane <= j ? sq[lane] : cx<double>{0.0, 0.0};
-        for (int kk = 0; kk < j; ++kk) {
-            const long long hr = __double_as_longlong(x.re), hi = __double_as_longlong(x.im);
-            const double h_re = __longlong_as_double(
-                ((long long)__builtin_amdgcn_readlane((int)(hr >> 32), kk) << 32) |
-                (unsigned)__builtin_amdgcn_readlane((int)hr, kk));
-            const double h_im = __longlong_as_double(
-                ((long long)__builtin_amdgcn_readlane((int)(hi >> 32), kk) << 32) |
-                (unsigned)__builtin_amdgcn_readlane((int)hi, kk));
-            if (lane > kk && lane <= j) {
-                const cx<double> l = lane < j ? sL[lane * (lane - 1) / 2 + kk] : sq[j + 1 + kk];
-                x.re -= l.re * h_re - l.im * h_im;
-                x.im -= l.re * h_im + l.im * h_re;
-            }
-        }
-        if (lane <= j) shh[lane] = x;
-    }
-    __syncthreads();
-    if (blockIdx.x == 0)
-        for (int kk = tid; kk < j; kk += RB) k.gram[j * (j - 1) / 2 + kk] = sq[j + 1 + kk];
-
-    // pass 2: w -= sum_i h_i v_i over this thread's entries, eight vectors at a time
-    for (int i0 = 0; i0 <= j; i0 += 8) {
-        cx<double> vb[8][OR_R];
+    };
+    for (int q = tid; q < Q; q += RB) publish(q, sq[q]);
+    // pass 2 reads its first eight basis vectors now (they do not depend on h)
+    cx<double> vb[8][OR_R];
+    auto load_batch = [&](int i0) {
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             if (i0 + u <= j) {
@@ -1805,6 +1813,127 @@ __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, 
                     vb[u][r] = vi[t < N ? t : N - 1];
                 }
             }
+    };
+    load_batch(0);
+    // collect: thread t reads slot it = t + RB u (consecutive lanes, consecutive
+    // blocks of one value: contiguous words), up to eight slots in flight; the
+    // eight lanes of a group of eight blocks then sum them (quad swaps and the
+    // half-row mirror: block order fixed, the same bits in all eight lanes), and
+    // the groups are added in order below
+    const int items = Q * Gp;
+    cx<double>* sp = sw;   // [q][8] group partials (sw is no longer needed)
+    for (int it0 = 0; it0 < items; it0 += RB * 8) {
+        double vr[8], vi[8];
+        unsigned todo = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int it = it0 + tid + RB * u;
+            vr[u] = 0.0;
+            vi[u] = 0.0;
+            if (it < items && it % Gp < G) todo |= 1u << u;
+        }
+        int spins = 0;
+        while (todo) {
+            unsigned long long x[8][4];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (todo & (1u << u)) {
+                    const unsigned long long* wd = k.vslots + (size_t)(it0 + tid + RB * u) * 4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        x[u][e] = __hip_atomic_load(wd + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if ((todo & (1u << u)) && (unsigned)x[u][0] == tag && (unsigned)x[u][1] == tag &&
+                    (unsigned)x[u][2] == tag && (unsigned)x[u][3] == tag) {
+                    vr[u] = __longlong_as_double((long long)((x[u][0] & 0xffffffff00000000ull) | (x[u][1] >> 32)));
+                    vi[u] = __longlong_as_double((long long)((x[u][2] & 0xffffffff00000000ull) | (x[u][3] >> 32)));
+                    todo &= ~(1u << u);
+                }
+            if (!todo) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1 << 20)) {
+                atomicExch(&k.ints[5], 1);
+                break;
+            }
+            if ((spins & 1023) == 0 && __hip_atomic_load(&k.ints[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                break;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            double ar = vr[u], ai = vi[u];
+            ar += dpp_f64<0xb1, 0xf>(ar);    // quad_perm [1,0,3,2]
+            ai += dpp_f64<0xb1, 0xf>(ai);
+            ar += dpp_f64<0x4e, 0xf>(ar);    // quad_perm [2,3,0,1]
+            ai += dpp_f64<0x4e, 0xf>(ai);
+            ar += dpp_f64<0x141, 0xf>(ar);   // row_half_mirror
+            ai += dpp_f64<0x141, 0xf>(ai);
+            const int it = it0 + tid + RB * u;
+            if ((tid & 7) == 0 && it < items) {
+                const int q = it / Gp;
+                sp[q * 8 + (it - q * Gp) / 8] = {ar, ai};
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < Q; q += RB) {
+        double ar = 0.0, ai = 0.0;
+        for (int g = 0; g < NG; ++g) {
+            ar += sp[q * 8 + g].re;
+            ai += sp[q * 8 + g].im;
+        }
+        sq[q] = {ar, ai};
+    }
+    // Once 2^20 launches have passed since the last full write (ints[7]; any
+    // Arnoldi launch advances the epoch), the slots this step does not use get
+    // this launch's tag too (zero values): no slot then goes unwritten for 2^23
+    // launches (the epoch field of the tag), so a launch never reads a word that
+    // carries its own tag from an older launch.
+    if (refresh)
+        for (int q = Q + tid; q < qcap; q += RB) publish(q, cx<double>{0.0, 0.0});
+    __syncthreads();
+
+    // (I + L) h = c by forward substitution in wave 0, lane i holding row i
+    // (row j from the sums); the row entries are read eight columns ahead
+    if (wave == 0) {
+        const bool row = lane <= j;
+        cx<double> x = row ? sq[lane] : cx<double>{0.0, 0.0};
+        const cx<double>* Lrow = lane < j ? sL + lane * (lane - 1) / 2 : sq + j + 1;
+        for (int k0 = 0; k0 < j; k0 += 8) {
+            cx<double> lv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kk = k0 + u;
+                lv[u] = (row && kk < lane) ? Lrow[kk] : cx<double>{0.0, 0.0};
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kk = k0 + u;
+                if (kk >= j) break;
+                const long long hr = __double_as_longlong(x.re), hi = __double_as_longlong(x.im);
+                const double h_re = __longlong_as_double(
+                    ((long long)__builtin_amdgcn_readlane((int)(hr >> 32), kk) << 32) |
+                    (unsigned)__builtin_amdgcn_readlane((int)hr, kk));
+                const double h_im = __longlong_as_double(
+                    ((long long)__builtin_amdgcn_readlane((int)(hi >> 32), kk) << 32) |
+                    (unsigned)__builtin_amdgcn_readlane((int)hi, kk));
+                if (row && lane > kk) {
+                    const cx<double> l = lv[u];
+                    x.re -= l.re * h_re - l.im * h_im;
+                    x.im -= l.re * h_im + l.im * h_re;
+                }
+            }
+        }
+        if (row) shh[lane] = x;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int kk = tid; kk < j; kk += RB) k.gram[j * (j - 1) / 2 + kk] = sq[j + 1 + kk];
+
+    // pass 2: w -= sum_i h_i v_i over this thread's entries, eight vectors at a time
+    for (int i0 = 0; i0 <= j; i0 += 8) {
+        if (i0 > 0) load_batch(i0);
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             if (i0 + u <= j) {
@@ -1824,8 +1953,13 @@ __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, 
     }
     const double hn = sqrt(grid_sum_reg(nr, zero, step_tag(epoch, 1), k, sh, shb).re);
     if (blockIdx.x == 0 && tid == 0) {
-        for (int i = 0; i <= j; ++i) k.H[(size_t)j * ldh + i] = shh[i];
-        givens_column(k, j, hn);
+        double c;
+        cx<double> sg;
+        givens_rotate(shh, scs, ssn, j, hn, c, sg);
+        for (int i = 0; i <= j + 1; ++i) k.H[(size_t)j * ldh + i] = shh[i];
+        givens_finish(k, j, hn, c, sg, gj, broke);
+        // every block read ints[7] before publishing (block 0 is past the exchange)
+        if (refresh) __hip_atomic_store(&k.ints[7], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     next_epoch(k, epoch);
 #pragma unroll
@@ -1964,23 +2098,58 @@ void launch_scale_by(long long N, const cx<double>* x, cx<double>* y, const doub
 
 // Back substitution R y = g on the first n rows (R: rotated Hessenberg); n is
 // ncols when given (>= 0), else the device count of completed Arnoldi steps.
-__global__ void lsq_kernel(KrylovDev k, int ncols) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One wave, column by column from the last: every lane forms y_i from the
+// updated s_i, then lanes r < i subtract R[r][i] y_i from s_r (s in LDS; R's
+// upper triangle staged in LDS, packed by columns, when n <= LSQ_COLS).
+constexpr int LSQ_COLS = 64;
+__global__ __launch_bounds__(64) void lsq_kernel(KrylovDev k, int ncols) {
+    __shared__ cx<double> sR[LSQ_COLS * (LSQ_COLS + 1) / 2];
+    __shared__ cx<double> sS[kMaxRestart];
+    const int lane = threadIdx.x;
     const int n = ncols >= 0 ? ncols : k.ints[0], ldh = k.m + 1;
-    for (int i = n - 1; i >= 0; --i) {
-        cx<double> s = k.g[i];
-        for (int c = i + 1; c < n; ++c) {
-            const cx<double> p = cmul(k.H[(size_t)c * ldh + i], k.y[c]);
-            s.re -= p.re;
-            s.im -= p.im;
+    for (int r = lane; r < n; r += 64) sS[r] = k.g[r];
+    const bool staged = n <= LSQ_COLS;
+    if (staged) {
+        // entry (r, c), r <= c, at c(c+1)/2 + r; eight loads in flight per lane
+        const int T = n * (n + 1) / 2;
+        for (int i0 = 0; i0 < T; i0 += 64 * 8) {
+            cx<double> v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = i0 + lane + 64 * u;
+                if (idx < T) {
+                    int c = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+                    if ((c + 1) * (c + 2) / 2 <= idx) ++c;
+                    if (c * (c + 1) / 2 > idx) --c;
+                    v[u] = k.H[(size_t)c * ldh + (idx - c * (c + 1) / 2)];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = i0 + lane + 64 * u;
+                if (idx < T) sR[idx] = v[u];
+            }
         }
-        const cx<double> d = k.H[(size_t)i * ldh + i];
+    }
+    __syncthreads();
+    for (int i = n - 1; i >= 0; --i) {
+        const cx<double> si = sS[i];
+        const cx<double> d = staged ? sR[i * (i + 1) / 2 + i] : k.H[(size_t)i * ldh + i];
         const double den = d.re * d.re + d.im * d.im;
-        k.y[i] = {(s.re * d.re + s.im * d.im) / den, (s.im * d.re - s.re * d.im) / den};
+        const cx<double> y = {(si.re * d.re + si.im * d.im) / den, (si.im * d.re - si.re * d.im) / den};
+        if (lane == 0) k.y[i] = y;
+        for (int r = lane; r < i; r += 64) {
+            const cx<double> h = staged ? sR[i * (i + 1) / 2 + r] : k.H[(size_t)i * ldh + r];
+            const cx<double> p = cmul(h, y);
+            cx<double> t = sS[r];
+            t.re -= p.re;
+            t.im -= p.im;
+            sS[r] = t;
+        }
     }
 }
 void launch_lsq(KrylovDev& k, hipStream_t s, int ncols) {
-    hipLaunchKernelGGL(lsq_kernel, dim3(1), dim3(1), 0, s, k, ncols);
+    hipLaunchKernelGGL(lsq_kernel, dim3(1), dim3(64), 0, s, k, ncols);
 }
 
 // u (+)= sum_{i < n} Z_i y_i, accumulated in increasing i (n as in lsq_kernel).
@@ -1990,6 +2159,7 @@ __global__ void update_kernel(long long N, const cx<double>* __restrict__ Z, lon
     if (t >= N) return;
     const int n = ncols >= 0 ? ncols : k.ints[0];
     double dr = 0.0, di = 0.0;
+#pragma unroll 8
     for (int i = 0; i < n; ++i) {
         const cx<double> z = Z[(size_t)i * ldz + t];
         const cx<double> y = k.y[i];

@@ -201,7 +201,7 @@ double SolverImpl::tcollect(int* count) {
 // ----------------------------------------------------------------- setup --
 void SolverImpl::setup(hipStream_t s) {
     const ProblemImpl& P = *prob;
-    HH_REQUIRE(o.restart >= 1 && o.restart <= 200, "restart must be in 1..200");
+    HH_REQUIRE(o.restart >= 1 && o.restart <= kMaxRestart, "restart must be in 1..200");
     HH_REQUIRE(o.maxit >= 1, "maxit must be >= 1");
     HH_REQUIRE(o.nu_pre >= 1 && o.nu_post >= 0 && o.n_vcycles >= 1, "bad smoothing counts");
     HH_REQUIRE(o.ortho == 0 || o.ortho == 1, "ortho is 0 or 1");

@@ -37,11 +37,16 @@ def source_hash():
     return h.hexdigest()
 
 
-def _per_kernel(path, counter):
+def _per_kernel(path, counter, grid=None):
+    """Counter values per kernel name; with grid, only dispatches of that grid size
+    (one level's launches of a kernel that also runs on other levels) and the
+    calibration copy."""
     out = {}
     with open(path) as fh:
         for r in csv.DictReader(fh):
             if r["Counter_Name"] != counter:
+                continue
+            if grid is not None and int(r["Grid_Size"]) != grid and "copy" not in r["Kernel_Name"].lower():
                 continue
             out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
     return out
@@ -55,9 +60,9 @@ def _copy_value(vals):
     return max(vs)
 
 
-def summarize(fetch_csv, write_csv, kernel, copy_mib):
-    fv = _per_kernel(fetch_csv, "FETCH_SIZE")
-    wv = _per_kernel(write_csv, "WRITE_SIZE")
+def summarize(fetch_csv, write_csv, kernel, copy_mib, grid=None):
+    fv = _per_kernel(fetch_csv, "FETCH_SIZE", grid)
+    wv = _per_kernel(write_csv, "WRITE_SIZE", grid)
     copy_kib = copy_mib * 1024.0
     f_fetch = _copy_value(fv) / copy_kib
     f_write = _copy_value(wv) / copy_kib
@@ -90,6 +95,10 @@ def write_summary(out, kernel, workload, command, s):
         f"| copy calibration: FETCH_SIZE / true bytes | {s['f_fetch']:.4f} |",
         f"| copy calibration: WRITE_SIZE / true bytes | {s['f_write']:.4f} |",
         f"| traffic per launch (bytes) | {s['traffic']:.0f} |",
+    ]
+    if s.get("grid"):
+        lines.append(f"| dispatches counted | grid size {s['grid']} threads only |")
+    lines += [
         "",
         f"traffic_bytes_per_launch: {s['traffic']:.0f}",
         f"kernel_regex: {kernel}",
@@ -145,6 +154,7 @@ def main():
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--kernel", help="regular expression matching the kernel name")
+    ap.add_argument("--grid", type=int, help="only dispatches of this grid size (threads)")
     ap.add_argument("--copy-mib", type=float)
     ap.add_argument("--workload")
     ap.add_argument("--command", required=True)
@@ -153,7 +163,8 @@ def main():
     if a.stats:
         write_stats(a.stats, a.title or "Kernel statistics", a.command, a.out)
         return
-    s = summarize(a.fetch, a.write, a.kernel, a.copy_mib)
+    s = summarize(a.fetch, a.write, a.kernel, a.copy_mib, a.grid)
+    s["grid"] = a.grid
     write_summary(a.out, a.kernel, a.workload, a.command, s)
     print(s)
 

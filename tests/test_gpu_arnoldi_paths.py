@@ -17,21 +17,48 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("p,n_el,k,form", [
-    # N = 25,921: 26 workgroups, resident in single and in batched mode
-    (3, 160, 100.0, "resident grid (both modes)"),
-    # N = 90,601: 89 workgroups, resident in single mode, per-projection kernels in batched mode
-    (3, 300, 150.0, "resident grid"),
-    # N = 270,400 > 262,144: 133 workgroups of 8 entries, cooperative launch
-    (2, 520, 100.0, "cooperative grid"),
-])
-def test_fused_arnoldi_matches_per_projection_kernels(p, n_el, k, form):
+# Bounds on the relative difference of the iterates and of the true residuals.
+# With an exact solve at the deflation level the preconditioner is one fixed
+# linear map and two forms differ only by the rounding of their sums.  With
+# inner FGMRES solves of fixed length at a deflation level the preconditioner
+# depends nonlinearly on its input and amplifies those differences (3.2e-7
+# measured after 12 steps at k = 150 on 300^2 elements when the sums in one
+# form changed order); a wrong coefficient in either form would show at O(1).
+# Near convergence the true residual is itself a small difference, so its bound
+# has an absolute floor (1e-12 of ||f||, far below the 1e-7 stopping tolerance).
+LINEAR = (1e-10, 1e-9)
+INNER_KRYLOV = (1e-5, 1e-4)
+RELRES_FLOOR = 1e-12
+
+
+def _compare(tag, u_a, i_a, u_b, i_b, bounds):
     import torch
+    torch.cuda.synchronize()
+    assert i_a["iters"] == i_b["iters"], (i_a["iters"], i_b["iters"])
+    d = (torch.linalg.norm(u_a - u_b) / torch.linalg.norm(u_b)).item()
+    _say(f"{tag}: iterations {i_a['iters']}, relative difference {d:.2e}, "
+         f"relres {i_a['relres_true']:.6e} / {i_b['relres_true']:.6e}")
+    assert d <= bounds[0], d
+    assert abs(i_a["relres_true"] - i_b["relres_true"]) <= bounds[1] * i_b["relres_true"] + RELRES_FLOOR
+
+
+@pytest.mark.parametrize("p,n_el,k,extra,bounds,form", [
+    # N = 25,921: 26 workgroups, resident in single and in batched mode
+    (3, 160, 100.0, {}, LINEAR, "resident grid (both modes)"),
+    # N = 90,601: 89 workgroups, resident in single mode, per-projection kernels
+    # in batched mode; level 1 (22,801 unknowns) solved exactly
+    (3, 300, 150.0, {"defl_direct_max": 32768}, LINEAR, "resident grid"),
+    # N = 270,400 > 262,144: 133 workgroups of 8 entries, cooperative launch;
+    # inner FGMRES on level 1 (68,121 unknowns)
+    (2, 520, 100.0, {}, INNER_KRYLOV, "cooperative grid"),
+])
+def test_fused_arnoldi_matches_per_projection_kernels(p, n_el, k, extra, bounds, form):
     from paper_2010_10232_amd import binding as B
     prob = B.Problem(2, p, n_el, k=k)
     if form == "cooperative grid":
         assert prob.N > 262144
     opts = dict(maxit=12, ortho=1)
+    opts.update(extra)
     s1 = B.Solver(prob, **opts)
     s2 = B.Solver(prob, **opts)
     f = prob.point_source((0.5, 0.5))
@@ -39,32 +66,20 @@ def test_fused_arnoldi_matches_per_projection_kernels(p, n_el, k, form):
     u1, i1 = s1.solve(f)
     _say(f"[arnoldi paths] {form}: batched solve (per-projection kernels)")
     us, infos = B.solve_batched([s2], [f])
-    torch.cuda.synchronize()
-    assert i1["iters"] == infos[0]["iters"], (i1["iters"], infos[0]["iters"])
-    d = (torch.linalg.norm(us[0] - u1) / torch.linalg.norm(u1)).item()
-    _say(f"[arnoldi paths] {form}: iterations {i1['iters']}, relative difference {d:.2e}, "
-         f"relres {i1['relres_true']:.3e} / {infos[0]['relres_true']:.3e}")
-    # The two forms add the same products in different orders; the multilevel
-    # preconditioner (inner Krylov solves on ill-conditioned coarse problems)
-    # amplifies such rounding differences (4.7e-9 measured at k = 150 after 12
-    # steps).  The bound is the solve tolerance, far below the iterate's own
-    # error after 12 steps; an error in either form would show at O(1).
-    assert d <= 1e-7, d
-    assert abs(i1["relres_true"] - infos[0]["relres_true"]) <= 1e-6 * i1["relres_true"]
+    _compare(f"[arnoldi paths] {form}", us[0], infos[0], u1, i1, bounds)
 
 
-@pytest.mark.parametrize("p,n_el,k,extra,label", [
+@pytest.mark.parametrize("p,n_el,k,extra,bounds,label", [
     # N = 25,921: 26 workgroups (MP 2-A)
-    (3, 160, 100.0, {}, "26 workgroups"),
-    # N = 63,001: 62 workgroups, a ragged last block
-    (2, 250, 100.0, {}, "62 workgroups"),
+    (3, 160, 100.0, {}, LINEAR, "26 workgroups"),
+    # N = 62,500: 62 workgroups, a ragged last block
+    (2, 250, 100.0, {}, LINEAR, "62 workgroups"),
     # restarts every 8 steps: Gram rows rebuilt in each cycle
-    (3, 160, 100.0, {"restart": 8, "maxit": 30}, "restart 8"),
+    (3, 160, 100.0, {"restart": 8, "maxit": 30}, LINEAR, "restart 8"),
     # inner deflation FGMRES on level 1 (6,561 unknowns, 7 workgroups, m = 8)
-    (3, 160, 100.0, {"defl_direct_max": 1024}, "inner levels"),
+    (3, 160, 100.0, {"defl_direct_max": 1024}, INNER_KRYLOV, "inner levels"),
 ])
-def test_one_reduction_arnoldi_matches_mgs(p, n_el, k, extra, label):
-    import torch
+def test_one_reduction_arnoldi_matches_mgs(p, n_el, k, extra, bounds, label):
     from paper_2010_10232_amd import binding as B
     prob = B.Problem(2, p, n_el, k=k)
     opts = dict(maxit=12)
@@ -74,12 +89,4 @@ def test_one_reduction_arnoldi_matches_mgs(p, n_el, k, extra, label):
     u1, i1 = B.Solver(prob, ortho=1, **opts).solve(f)
     _say(f"[one-reduction] {label}: one sum per step")
     u0, i0 = B.Solver(prob, ortho=0, **opts).solve(f)
-    torch.cuda.synchronize()
-    d = (torch.linalg.norm(u0 - u1) / torch.linalg.norm(u1)).item()
-    _say(f"[one-reduction] {label}: iterations {i0['iters']} / {i1['iters']}, relative difference {d:.2e}, "
-         f"relres {i0['relres_true']:.3e} / {i1['relres_true']:.3e}")
-    assert i0["iters"] == i1["iters"], (i0["iters"], i1["iters"])
-    # same bound and reason as above: rounding-order differences amplified by
-    # the multilevel preconditioner; a wrong coefficient would show at O(1)
-    assert d <= 1e-7, d
-    assert abs(i0["relres_true"] - i1["relres_true"]) <= 1e-6 * i1["relres_true"]
+    _compare(f"[one-reduction] {label}", u0, i0, u1, i1, bounds)
