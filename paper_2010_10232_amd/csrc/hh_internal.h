@@ -37,6 +37,16 @@ struct cx {
     T re, im;
 };
 
+// Workgroups of a launch are dispatched to the eight XCDs (each with its own
+// L2) in turn.  xcd_block maps workgroup b of nb to a logical block so that each
+// XCD takes one contiguous range of logical blocks (a bijection of 0..nb-1): a
+// stencil or transfer kernel then fetches each grid row and its halo into one
+// L2 instead of several.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b & 7, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Device buffer with owning semantics.
 struct DevBuf {
     void* p = nullptr;

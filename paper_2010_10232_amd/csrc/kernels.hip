@@ -144,7 +144,7 @@ __device__ __forceinline__ cx<T> prolong_one(const Transfer& t, const cx<T>* __r
 template <class T, int W>
 __global__ void restrict_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* __restrict__ c,
                                 const cx<T>* __restrict__ dinv, T omega, cx<T>* __restrict__ xs) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (idx >= t.nc1 * t.nc2) return;
     const cx<T> v = restrict_one<T, W>(t, r, idx);
     c[idx] = v;
@@ -157,7 +157,7 @@ __global__ void restrict_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* 
 // x = xin + P e (xin may alias x; xin == nullptr: x = P e)
 template <class T, int W>
 __global__ void prolong_kernel(Transfer t, const cx<T>* __restrict__ e, const cx<T>* xin, cx<T>* x) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (idx >= t.nf1 * t.nf2) return;
     const cx<T> v = prolong_one<T, W>(t, e, idx);
     if (xin) {

@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
     constexpr int BX = 2 * PX + 1, BY = 2 * PY + 1;
     const int n1 = a.n1, n2 = a.n2;
     const int N = n1 * n2;   // at most kOpDirectMax: 32-bit indices
-    const int I = blockIdx.x * 256 + threadIdx.x;
+    const int I = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (I >= N) return;
     const int I1 = I % n1, I2 = I / n1;
     T kx[BX], mx[BX], ky[BY], my[BY];
