@@ -172,6 +172,7 @@ struct OpArgs {
     const cx<T>* dinv;
     T omega;
     cx<T>* xo;             // MODE_RESID: if set, also xo = omega D^-1 y (a first sweep on y)
+    const cx<T>* yadd;     // MODE_SMOOTH: if set, y = the swept x + yadd
 };
 
 struct Transfer {
@@ -273,6 +274,8 @@ void launch_copy(long long N, const cx<double>* x, cx<double>* y, hipStream_t s)
 void launch_zero(long long N, cx<double>* y, hipStream_t s);
 void launch_cast_d2f(long long N, const cx<double>* x, cx<float>* y, hipStream_t s);
 void launch_cast_f2d(long long N, const cx<float>* x, cx<double>* y, hipStream_t s);
+void launch_cast_f2d_add(long long N, const cx<float>* x, const cx<double>* q, cx<double>* y,
+                         hipStream_t s);   // y = x + q
 template <class TM, class TV>
 void launch_gemv(int n, const TM* A, const cx<TV>* x, cx<TV>* y, hipStream_t s);
 // y = A x for a real n x n matrix with leading dimension ld (even ld: 16-byte rows)

@@ -299,6 +299,13 @@ void launch_cast_d2f(long long N, const cx<double>* x, cx<float>* y, hipStream_t
 void launch_cast_f2d(long long N, const cx<float>* x, cx<double>* y, hipStream_t s) {
     hipLaunchKernelGGL(cast_f2d_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y);
 }
+__global__ void cast_f2d_add_kernel(long long N, const cx<float>* x, const cx<double>* q, cx<double>* y) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) y[i] = {(double)x[i].re + q[i].re, (double)x[i].im + q[i].im};
+}
+void launch_cast_f2d_add(long long N, const cx<float>* x, const cx<double>* q, cx<double>* y, hipStream_t s) {
+    hipLaunchKernelGGL(cast_f2d_add_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, q, y);
+}
 
 // --------------------------------------------------------------------------
 // Dense matrix-vector product y = A x (A row-major n x n): one wave per row.

@@ -252,6 +252,10 @@ __global__ __launch_bounds__(64) void op_kernel(OpArgs<T> a, int ty) {
                     const cx<T> xv = xs[cs][lane + PX];
                     out = {xv.re + a.omega * (dv.re * rr - dv.im * ri),
                            xv.im + a.omega * (dv.re * ri + dv.im * rr)};
+                    if (a.yadd) {
+                        const cx<T> q = a.yadd[I];
+                        out = {out.re + q.re, out.im + q.im};
+                    }
                 }
             }
             a.y[I] = out;
@@ -350,6 +354,10 @@ __global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
         } else {
             const cx<T> dv = a.dinv[I], xv = a.x[I];
             out = {xv.re + a.omega * (dv.re * rr - dv.im * ri), xv.im + a.omega * (dv.re * ri + dv.im * rr)};
+            if (a.yadd) {
+                const cx<T> q = a.yadd[I];
+                out = {out.re + q.re, out.im + q.im};
+            }
         }
     }
     a.y[I] = out;

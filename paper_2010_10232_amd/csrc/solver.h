@@ -117,13 +117,19 @@ struct SolverImpl {
     // building blocks
     template <class T>
     void op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s,
-            cx<T>* xo = nullptr);   // xo: MODE_RESID also forms a first sweep on y
+            cx<T>* xo = nullptr,            // xo: MODE_RESID also forms a first sweep on y
+            const cx<T>* yadd = nullptr);   // yadd: MODE_SMOOTH writes the swept x + yadd
+    // x_swept: x already holds the first sweep from zero.  zadd (with zout):
+    // the last smoothing sweep writes zout = x + zadd instead of x, when the
+    // cycle ends with such a sweep (the return value says whether it did).
     template <class T>
-    void vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s,
-                     bool x_swept = false);   // x_swept: x already holds the first sweep from zero
+    bool vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_swept = false, cx<T>* zout = nullptr,
+                     const cx<T>* zadd = nullptr);
     template <class T>
-    void vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_swept = false);
-    void precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s, bool x_swept = false);
+    bool vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_swept = false, cx<T>* zout = nullptr,
+                const cx<T>* zadd = nullptr);
+    bool precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s, bool x_swept = false,
+                        cx<double>* zout = nullptr, const cx<double>* zadd = nullptr);
     void T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t s);
     void coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s);
     void arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s);
@@ -143,7 +149,7 @@ struct SolverImpl {
     int cap_max = 0, cap_n = 0;
     template <class T>
     void op_alpha(int l, int mode, double are, double aim, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s,
-                  cx<T>* xo = nullptr);
+                  cx<T>* xo = nullptr, const cx<T>* yadd = nullptr);
     int solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s);
 };
 

@@ -745,14 +745,15 @@ void SolverImpl::autotune_ops(hipStream_t s) {
 
 // ----------------------------------------------------------- hot path ----
 template <class T>
-void SolverImpl::op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s, cx<T>* xo) {
-    op_alpha<T>(l, mode, cslp ? o.beta[0] : 1.0, cslp ? o.beta[1] : 0.0, x, b, y, s, xo);
+void SolverImpl::op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s, cx<T>* xo,
+                    const cx<T>* yadd) {
+    op_alpha<T>(l, mode, cslp ? o.beta[0] : 1.0, cslp ? o.beta[1] : 0.0, x, b, y, s, xo, yadd);
 }
 
 // y = K x - alpha M_k x at level l, with the residual / Jacobi epilogues (mode)
 template <class T>
 void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* x, const cx<T>* b, cx<T>* y,
-                          hipStream_t s, cx<T>* xo) {
+                          hipStream_t s, cx<T>* xo, const cx<T>* yadd) {
     LevelDev& lv = *lev[l];
     OpArgs<T> a{};
     a.n1 = lv.n1;
@@ -778,6 +779,7 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
     a.dinv = pick<T>(lv.Dinv64, lv.Dinv32).template as<cx<T>>();
     a.omega = (T)lv.omega;
     a.xo = xo;
+    a.yadd = mode == MODE_SMOOTH ? yadd : nullptr;
     a.ty = sizeof(T) == 8 ? lv.ty64 : lv.ty32;
     const int py = prob->dim == 2 ? prob->p : 0;
     if (l == 0) tstart(1, s);
@@ -787,24 +789,25 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
         // (smoothing) in, plus the k^2 field of a non-constant wave number
         const double v = (double)lv.N * 2 * sizeof(T);
         double bytes = 2 * v + (mode != MODE_APPLY ? v : 0.0) + (mode == MODE_SMOOTH || xo ? v : 0.0) +
-                       (xo ? v : 0.0);
+                       (xo ? v : 0.0) + (a.yadd ? v : 0.0);
         if (lv.kind == KIND_VARFINE) bytes += 8.0 * lv.ax.nel * lv.ay.nel;
         tstop(1, bytes, s);
     }
 }
 
 template <class T>
-void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_swept) {
+bool SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_swept, cx<T>* zout,
+                             const cx<T>* zadd) {
     LevelDev& lv = *lev[l];
     if (l == L) {
         launch_gemv<cx<T>, T>(nL, pick<T>(Minv64, Minv32).template as<cx<T>>(), b, x, s);
-        return;
+        return false;
     }
     if (l >= tail_start) {
         launch_vcycle_tail<T>(pick<T>(tail64, tail32).template as<TailDesc<T>>(), tail_img.p,
                               (int)(tail_img.bytes / 16), pick<T>(Minv64, Minv32).template as<cx<T>>(), tail_P, l,
                               sizeof(T) == 8 ? tail_lds : tail_lds32, b, x, s);
-        return;
+        return false;
     }
     cx<T>* t = pick<T>(lv.t64, lv.t32).template as<cx<T>>();
     cx<T>* r = pick<T>(lv.r64, lv.r32).template as<cx<T>>();
@@ -850,21 +853,29 @@ void SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s, boo
             op<T>(l, MODE_RESID, true, x, b, r, s);
             cnn->step<T>(lv.n2, lv.n1, r, feat.as<float>(), dinv, (T)lv.omega, x, 1, s);
         }
-        return;
+        return false;
     }
     // coarse-grid correction into t when an odd number of sweeps follows, so
-    // that the last sweep writes x
+    // that the last sweep writes x (or zout = x + zadd)
     cx<T>* cur = (o.nu_post & 1) ? t : x;
     cx<T>* oth = (o.nu_post & 1) ? x : t;
     launch_prolong_add<T>(lv.tr, xc, x, cur, s);
+    const bool fold = zadd != nullptr && o.nu_post >= 1;
     for (int i = 0; i < o.nu_post; ++i) {
+        if (fold && i + 1 == o.nu_post) {
+            op<T>(l, MODE_SMOOTH, true, cur, b, zout, s, nullptr, zadd);
+            break;
+        }
         op<T>(l, MODE_SMOOTH, true, cur, b, oth, s);
         std::swap(cur, oth);
     }
+    return fold;
 }
 
 template <class T>
-void SolverImpl::vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_swept) {
+bool SolverImpl::vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_swept, cx<T>* zout,
+                        const cx<T>* zadd) {
+    if (o.n_vcycles == 1) return vcycle_once<T>(l, b, x, s, x_swept, zout, zadd);
     vcycle_once<T>(l, b, x, s, x_swept);
     LevelDev& lv = *lev[l];
     for (int i = 1; i < o.n_vcycles; ++i) {
@@ -874,24 +885,28 @@ void SolverImpl::vcycle(int l, const cx<T>* b, cx<T>* x, hipStream_t s, bool x_s
         vcycle_once<T>(l, vr, vx, s);
         launch_axpy<T>(lv.N, vx, x, s);
     }
+    return false;
 }
 
-void SolverImpl::precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s, bool x_swept) {
+bool SolverImpl::precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipStream_t s, bool x_swept,
+                                cx<double>* zout, const cx<double>* zadd) {
     if (l == 0 && cap_buf && cap_n < cap_max) {
         const long long N = lev[0]->N;
         HH_HIP(hipMemcpyAsync(cap_buf + (size_t)cap_n * N, b, (size_t)N * sizeof(cx<double>), hipMemcpyDeviceToDevice,
                               s));
         ++cap_n;
     }
-    if (o.precision == 0) {
-        vcycle<double>(l, b, x, s, x_swept);
-        return;
-    }
+    if (o.precision == 0) return vcycle<double>(l, b, x, s, x_swept, zout, zadd);
     LevelDev& lv = *lev[l];
     // FP32 V-cycle: the entry level's own multigrid vectors carry the cast data
     launch_cast_d2f(lv.N, b, lv.b32.as<cx<float>>(), s);
     vcycle<float>(l, lv.b32.as<cx<float>>(), lv.x32.as<cx<float>>(), s);
+    if (zadd) {
+        launch_cast_f2d_add(lv.N, lv.x32.as<cx<float>>(), zadd, zout, s);
+        return true;
+    }
     launch_cast_f2d(lv.N, lv.x32.as<cx<float>>(), x, s);
+    return false;
 }
 
 void SolverImpl::T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t s) {
@@ -909,8 +924,10 @@ void SolverImpl::T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t 
     const bool fuse = o.precision == 0 && o.nu_pre == 1 && !(cnn && l == 0) && l < tail_start && l < L;
     op<double>(l, MODE_RESID, false, lv.tq.as<cx<double>>(), v, lv.tw.as<cx<double>>(), s,
                fuse ? lv.ts.as<cx<double>>() : nullptr);
-    precond_vcycle(l, lv.tw.as<cx<double>>(), lv.ts.as<cx<double>>(), s, fuse);
-    launch_add(lv.N, lv.ts.as<cx<double>>(), lv.tq.as<cx<double>>(), z, s);
+    // z = s + q, formed by the V-cycle's last step where it can (the last
+    // smoothing sweep's epilogue, or the cast back from FP32)
+    if (!precond_vcycle(l, lv.tw.as<cx<double>>(), lv.ts.as<cx<double>>(), s, fuse, z, lv.tq.as<cx<double>>()))
+        launch_add(lv.N, lv.ts.as<cx<double>>(), lv.tq.as<cx<double>>(), z, s);
 }
 
 // One fused Arnoldi step on w = V[j+1]: a single workgroup for short vectors;
@@ -1184,12 +1201,14 @@ int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_i
 }
 
 template void SolverImpl::op<double>(int, int, bool, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t,
-                                     cx<double>*);
+                                     cx<double>*, const cx<double>*);
 template void SolverImpl::op<float>(int, int, bool, const cx<float>*, const cx<float>*, cx<float>*, hipStream_t,
-                                    cx<float>*);
+                                    cx<float>*, const cx<float>*);
 template void SolverImpl::op_alpha<double>(int, int, double, double, const cx<double>*, const cx<double>*, cx<double>*,
-                                           hipStream_t, cx<double>*);
-template void SolverImpl::vcycle<double>(int, const cx<double>*, cx<double>*, hipStream_t, bool);
-template void SolverImpl::vcycle<float>(int, const cx<float>*, cx<float>*, hipStream_t, bool);
+                                           hipStream_t, cx<double>*, const cx<double>*);
+template bool SolverImpl::vcycle<double>(int, const cx<double>*, cx<double>*, hipStream_t, bool, cx<double>*,
+                                         const cx<double>*);
+template bool SolverImpl::vcycle<float>(int, const cx<float>*, cx<float>*, hipStream_t, bool, cx<float>*,
+                                        const cx<float>*);
 
 }  // namespace hh
