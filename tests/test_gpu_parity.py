@@ -265,3 +265,25 @@ def test_autotuned_strips_do_not_change_results():
     u2, i2 = fixed.solve(f)
     assert i1["iters"] == i2["iters"]
     assert np.array_equal(to_host(u1), to_host(u2))
+
+
+@pytest.mark.parametrize("nu_pre,nu_post,n_vcycles", [(2, 2, 1), (1, 0, 1), (1, 1, 2), (3, 1, 1)])
+def test_smoothing_counts_match_oracle(nu_pre, nu_post, n_vcycles):
+    """Other sweep and cycle counts of the V-cycle (section 3: nu_pre / nu_post damped
+    Jacobi sweeps per level): the fused forms that assume one pre-sweep, one
+    post-sweep and one cycle (the first sweep formed by the residual or the
+    restriction; T's final sum formed by the last sweep or the cast) step aside,
+    and the solve still follows the oracle.  64^2 elements, p = 3: levels 0 and 1
+    (4,225 and 1,089 unknowns) run as separate kernels, the rest in the tail."""
+    from paper_2010_10232_amd import binding as B
+    gp = B.Problem(2, 3, 64, k=20.0)
+    gs = B.Solver(gp, nu_pre=nu_pre, nu_post=nu_post, n_vcycles=n_vcycles)
+    op = hz.Problem(2, 3, 64, 20.0)
+    osol = osv.Solver(op, osv.Options(nu_pre=nu_pre, nu_post=nu_post, n_vcycles=n_vcycles))
+    f = hz.point_source_rhs(op, (0.45, 0.55))
+    _say(f"[smoothing {nu_pre},{nu_post} x{n_vcycles}] gpu solve")
+    u, info = gs.solve(to_dev(f))
+    _say(f"[smoothing {nu_pre},{nu_post} x{n_vcycles}] oracle solve")
+    u_ref, info_ref = osol.solve(f)
+    assert info["converged"] == 1 and info["iters"] == info_ref.iters, (info["iters"], info_ref.iters)
+    assert rel(to_host(u), u_ref) <= 1e-10
