@@ -48,6 +48,28 @@ def test_traffic_summary_calibration_and_hash(tmp_path):
     assert profiling.read_summary(str(tmp_path / "missing.md")) is None
 
 
+def test_traffic_summary_grid_filter(tmp_path):
+    # one kernel template on two levels (grid sizes 26112 and 6656): only the
+    # finest level's dispatches count; the calibration copy counts whatever its grid
+    def write(path, counter, rows):
+        with open(path, "w", newline="") as fh:
+            w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for name, g, v in rows:
+                w.writerow({"Kernel_Name": name, "Grid_Size": g, "Counter_Name": counter, "Counter_Value": v})
+    op = "void hh::op_direct_kernel<3, 3, 0, 1, double>(...)"
+    f = tmp_path / "f.csv"
+    w = tmp_path / "w.csv"
+    write(f, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 131072, 131072.0), (op, 26112, 600.0), (op, 26112, 800.0),
+                            (op, 6656, 5000.0)])
+    write(w, "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 131072, 262144.0), (op, 26112, 400.0), (op, 6656, 9000.0)])
+    s = profiling.summarize(str(f), str(w), "op_direct_kernel<3, 3, 0", 256, grid=26112)
+    assert s["n_fetch"] == 2 and s["n_write"] == 1
+    assert abs(s["traffic"] - 1024.0 * (700.0 / 0.5 + 400.0)) < 1e-6
+    every = profiling.summarize(str(f), str(w), "op_direct_kernel<3, 3, 0", 256)
+    assert every["n_fetch"] == 3 and every["traffic"] > s["traffic"]
+
+
 def test_kernel_stats_table(tmp_path):
     p = tmp_path / "stats.csv"
     with open(p, "w", newline="") as fh:
