@@ -78,6 +78,9 @@ def test_fused_arnoldi_matches_per_projection_kernels(p, n_el, k, extra, bounds,
     (3, 160, 100.0, {"restart": 8, "maxit": 30}, LINEAR, "restart 8"),
     # inner deflation FGMRES on level 1 (6,561 unknowns, 7 workgroups, m = 8)
     (3, 160, 100.0, {"defl_direct_max": 1024}, INNER_KRYLOV, "inner levels"),
+    # no deflation: a whole cycle of 50 steps (j up to 49: 99 values per block,
+    # 3,168 exchange slots, two collection batches) and a restart
+    (3, 160, 100.0, {"defl_mode": 0, "maxit": 55}, LINEAR, "full cycle"),
 ])
 def test_one_reduction_arnoldi_matches_mgs(p, n_el, k, extra, bounds, label):
     from paper_2010_10232_amd import binding as B
