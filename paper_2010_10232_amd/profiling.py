@@ -22,6 +22,8 @@ import csv
 import hashlib
 import os
 import re
+import shutil
+import subprocess
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
@@ -124,15 +126,62 @@ def read_summary(path):
     return float(vals["traffic_bytes_per_launch"]), vals.get("kernel_regex")
 
 
-def write_stats(stats_csv, title, command, out, top=18):
-    """Markdown table of a rocprofv3 --stats kernel summary (most device time first)."""
-    with open(stats_csv) as fh:
-        rows = list(csv.DictReader(fh))
+def stats_from_trace(trace_csv, after):
+    """Rows in the form of a rocprofv3 --stats summary, built from a kernel trace
+    and counting only the dispatches that start after the last one whose name
+    matches the regular expression `after` (one phase of a run)."""
+    with open(trace_csv) as fh:
+        tr = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
+    pat = re.compile(after)
+    last = max((i for i, r in enumerate(tr) if pat.search(r["Kernel_Name"])), default=-1)
+    per = {}
+    for r in tr[last + 1:]:
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        per.setdefault(r["Kernel_Name"], []).append(d)
+    total = sum(sum(v) for v in per.values()) or 1
+    rows = [{"Name": name, "Calls": str(len(v)), "TotalDurationNs": str(sum(v)),
+             "AverageNs": str(sum(v) / len(v)), "MinNs": str(min(v)), "MaxNs": str(max(v)),
+             "Percentage": str(100.0 * sum(v) / total)} for name, v in per.items()]
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    return rows
+
+
+def _demangle(name):
+    """Readable form of a mangled kernel name: c++filt when installed and able,
+    else the nested name of `_ZN<len><id>...` with `<...>` for template arguments."""
+    if not name.startswith("_Z"):
+        return name
+    if shutil.which("c++filt") is not None:
+        r = subprocess.run(["c++filt", name], capture_output=True, text=True)
+        out = r.stdout.strip()
+        if out and out != name:
+            return out
+    if not name.startswith("_ZN"):
+        return name
+    parts, pos = [], 3
+    while pos < len(name) and name[pos].isdigit():
+        end = pos
+        while name[end].isdigit():
+            end += 1
+        k = int(name[pos:end])
+        parts.append(name[end:end + k])
+        pos = end + k
+    if not parts:
+        return name
+    return "::".join(parts) + ("<...>" if name[pos:pos + 1] == "I" else "")
+
+
+def write_stats(stats_csv, title, command, out, top=18, rows=None):
+    """Markdown table of a rocprofv3 --stats kernel summary (most device time
+    first); rows given directly (stats_from_trace) instead of the file."""
+    if rows is None:
+        with open(stats_csv) as fh:
+            rows = list(csv.DictReader(fh))
     lines = [f"# {title}", "", "Command (repository root on the GPU host):", "", "```", command, "```", "",
              "| kernel | calls | total ms | avg us | min us | max us | % of GPU time |",
              "|---|---|---|---|---|---|---|"]
     for r in rows[:top]:
-        name = r["Name"].split("(")[0].replace("void ", "")
+        name = _demangle(r["Name"]).split("(")[0].replace("void ", "")
         if len(name) > 72:
             name = name[:72] + "..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
@@ -150,6 +199,8 @@ def write_stats(stats_csv, title, command, out, top=18):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", help="rocprofv3 kernel_stats.csv: write a kernel table instead")
+    ap.add_argument("--trace", help="rocprofv3 kernel_trace.csv: write a kernel table of the dispatches after --after")
+    ap.add_argument("--after", help="regular expression: the table starts after its last dispatch")
     ap.add_argument("--title")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
@@ -162,6 +213,10 @@ def main():
     a = ap.parse_args()
     if a.stats:
         write_stats(a.stats, a.title or "Kernel statistics", a.command, a.out)
+        return
+    if a.trace:
+        write_stats(None, a.title or "Kernel statistics", a.command, a.out,
+                    rows=stats_from_trace(a.trace, a.after or "^$"))
         return
     s = summarize(a.fetch, a.write, a.kernel, a.copy_mib, a.grid)
     s["grid"] = a.grid

@@ -70,6 +70,27 @@ def test_traffic_summary_grid_filter(tmp_path):
     assert every["n_fetch"] == 3 and every["traffic"] > s["traffic"]
 
 
+def test_kernel_table_of_one_phase(tmp_path):
+    # dispatches after the last training kernel only
+    t = tmp_path / "trace.csv"
+    with open(t, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for name, a, b in [("op_a", 0, 10), ("wgrad_kernel<32>", 20, 120), ("op_a", 130, 140),
+                           ("wgrad_kernel<8>", 150, 200), ("fused", 210, 250), ("op_a", 260, 266), ("fused", 270, 300)]:
+            w.writerow({"Kernel_Name": name, "Start_Timestamp": a, "End_Timestamp": b})
+    rows = profiling.stats_from_trace(str(t), "wgrad_kernel")
+    assert [r["Name"] for r in rows] == ["fused", "op_a"]
+    assert rows[0]["Calls"] == "2" and float(rows[0]["TotalDurationNs"]) == 70.0
+    assert abs(float(rows[0]["Percentage"]) - 100.0 * 70 / 76) < 1e-9
+    out = tmp_path / "t.md"
+    profiling.write_stats(None, "phase", "cmd", str(out), rows=rows)
+    assert "| `fused` | 2 | 0.000 | 0.04 |" in out.read_text()
+    # a kernel name the host's c++filt may not read (a bf16 parameter)
+    nm = profiling._demangle("_ZN2hh16cnn_fused_kernelIfEEviiPKNS_2cxIT_EEPKdiPKfPKDF16bS9_S5_S2_PS3_i")
+    assert "hh::cnn_fused_kernel" in nm and not nm.startswith("_Z")
+
+
 def test_kernel_stats_table(tmp_path):
     p = tmp_path / "stats.csv"
     with open(p, "w", newline="") as fh:
