@@ -205,6 +205,7 @@ struct KrylovDev {
                                 // of the strictly lower part of V^H V, row i packed at i(i-1)/2
     unsigned long long* vslots; // its vector-exchange words: [block][qcap][4]
     int qcap;                   // 2m - 1 values per block (0 when not allocated)
+    unsigned char* hstep;       // outer solve: device address of the pinned step slots (2 x 128 B), else null
     int m;
 };
 

@@ -1283,8 +1283,8 @@ __device__ __forceinline__ void givens_rotate(cx<double>* Hc, const double* cs, 
 
 // The rest of step j's update: rotation j stored, g rotated, |g_{j+1}|, the
 // step count and the breakdown flag (gj = g[j], broke = the flag on entry).
-__device__ __forceinline__ void givens_finish(KrylovDev& k, int j, double hn, double c, cx<double> s,
-                                              cx<double> gj, int broke) {
+__device__ __forceinline__ double givens_finish(KrylovDev& k, int j, double hn, double c, cx<double> s,
+                                                cx<double> gj, int broke) {
     k.scal[1] = hn;
     k.cs[j] = c;
     k.sn[j] = s;
@@ -1293,9 +1293,23 @@ __device__ __forceinline__ void givens_finish(KrylovDev& k, int j, double hn, do
     const cx<double> g1 = {-ng.re, -ng.im};
     k.g[j + 1] = g1;
     k.g[j] = {c * gj.re, c * gj.im};
-    k.scal[2] = hypot(g1.re, g1.im);
+    const double gabs = hypot(g1.re, g1.im);
+    k.scal[2] = gabs;
     if (!broke) k.ints[0] = j + 1;
     if (hn == 0.0) k.ints[1] = 1;
+    return gabs;
+}
+
+// What the host reads after step j, stored by the thread that finished the
+// step straight into the pinned slot j & 1 (when the Krylov state has one):
+// |g_{j+1}| at double 2, the breakdown flag at int 1 and the grid-exchange
+// timeout flag (tmo, read before the Givens update) at int 5 of the slot's
+// integers, which start at byte 64.
+__device__ __forceinline__ void publish_step(KrylovDev& k, int j, double gabs, int breakdown, int tmo) {
+    unsigned char* slot = k.hstep + 128 * (j & 1);
+    ((double*)slot)[2] = gabs;
+    ((int*)(slot + 64))[1] = breakdown;
+    ((int*)(slot + 64))[5] = tmo;
 }
 
 // Givens update of Hessenberg column j and of the residual vector g, all in
@@ -1393,7 +1407,13 @@ __global__ __launch_bounds__(SB) void arnoldi_small_kernel(long long N, int j, c
         __syncthreads();
     }
     const double hn = sqrt(sh[0]);
-    if (tid == 0) givens_column(k, j, hn);
+    if (tid == 0) {
+        givens_column(k, j, hn);
+        if (k.hstep) {
+            const int tmo = __hip_atomic_load(&k.ints[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            publish_step(k, j, k.scal[2], k.ints[1], tmo);
+        }
+    }
     for (long long t = tid; t < N; t += SB) {
         const cx<double> wv = w[t];
         w[t] = hn == 0.0 ? cx<double>{0.0, 0.0} : cx<double>{wv.re / hn, wv.im / hn};
@@ -1568,7 +1588,11 @@ __global__ __launch_bounds__(RB) void arnoldi_coop_kernel(long long N, int j, cx
         nr += wv.re * wv.re + wv.im * wv.im;
     }
     const double hn = sqrt(grid_sum(nr, 0.0, step_tag(epoch, round), k, sh, shb).re);
-    if (blockIdx.x == 0 && threadIdx.x == 0) givens_column(k, j, hn);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int tmo = __hip_atomic_load(&k.ints[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        givens_column(k, j, hn);
+        if (k.hstep) publish_step(k, j, k.scal[2], k.ints[1], tmo);
+    }
     next_epoch(k, epoch);
     for (long long t = t0; t < N; t += stride) {
         const cx<double> wv = w[t];
@@ -1666,11 +1690,13 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
     for (int r = 0; r < R; ++r) nr += wr[r].re * wr[r].re + wr[r].im * wr[r].im;
     const double hn = sqrt(grid_sum_reg(nr, zero, step_tag(epoch, round), k, sh, shb).re);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int tmo = __hip_atomic_load(&k.ints[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         double c;
         cx<double> sg;
         givens_rotate(shc, scs, ssn, j, hn, c, sg);
         for (int i = 0; i <= j + 1; ++i) k.H[(size_t)j * ldh + i] = shc[i];
-        givens_finish(k, j, hn, c, sg, gj, broke);
+        const double gabs = givens_finish(k, j, hn, c, sg, gj, broke);
+        if (k.hstep) publish_step(k, j, gabs, (broke || hn == 0.0) ? 1 : 0, tmo);
     }
     next_epoch(k, epoch);
 #pragma unroll
@@ -1960,11 +1986,13 @@ __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, 
     }
     const double hn = sqrt(grid_sum_reg(nr, zero, step_tag(epoch, 1), k, sh, shb).re);
     if (blockIdx.x == 0 && tid == 0) {
+        const int tmo = __hip_atomic_load(&k.ints[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         double c;
         cx<double> sg;
         givens_rotate(shh, scs, ssn, j, hn, c, sg);
         for (int i = 0; i <= j + 1; ++i) k.H[(size_t)j * ldh + i] = shh[i];
-        givens_finish(k, j, hn, c, sg, gj, broke);
+        const double gabs = givens_finish(k, j, hn, c, sg, gj, broke);
+        if (k.hstep) publish_step(k, j, gabs, (broke || hn == 0.0) ? 1 : 0, tmo);
         // every block read ints[7] before publishing (block 0 is past the exchange)
         if (refresh) __hip_atomic_store(&k.ints[7], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }

@@ -132,7 +132,8 @@ struct SolverImpl {
                         cx<double>* zout = nullptr, const cx<double>* zadd = nullptr);
     void T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t s);
     void coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s);
-    void arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s);
+    // true when the step's kernel stored the host's scalars in the pinned slot itself
+    bool arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s);
     bool allow_coop = true;
     // batched mode: Arnoldi step j (T, operator, MGS, scalar copies) captured
     // once into a HIP graph and replayed (no timing, learned smoother or sample

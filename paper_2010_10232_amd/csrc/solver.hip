@@ -138,6 +138,7 @@ static void fill_krylov(KrylovDev& k, DevBuf& blob, int m) {
     p += 16 * ngram;
     k.vslots = qcap ? (unsigned long long*)p : nullptr;
     k.qcap = qcap;
+    k.hstep = nullptr;
     HH_HIP(hipMemset(blob.p, 0, blob.bytes));
 }
 
@@ -682,6 +683,13 @@ void SolverImpl::setup(hipStream_t s) {
     std::memset(pin_i, 0, 64 * sizeof(int));
     HH_HIP(hipHostMalloc((void**)&pin_step, 256, hipHostMallocDefault));
     std::memset(pin_step, 0, 256);
+    // the outer Arnoldi kernels store the host's step scalars in these slots
+    // through their device address (without one, the driver copies them)
+    void* dstep = nullptr;
+    if (hipHostGetDevicePointer(&dstep, pin_step, 0) == hipSuccess && dstep)
+        kd.hstep = (unsigned char*)dstep;
+    else
+        (void)hipGetLastError();
     for (hipEvent_t* e : {&ev_slot[0], &ev_slot[1], &ev_misc})
         HH_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     HH_HIP(hipStreamSynchronize(s));
@@ -935,15 +943,17 @@ void SolverImpl::T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t 
 // batched mode, when the grid is too large for up to 16 of them to be resident
 // side by side) one kernel per Gram-Schmidt projection followed by the
 // norm/Givens kernel and the scaling.
-void SolverImpl::arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s) {
+bool SolverImpl::arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s) {
     if (N <= kSmallArnoldi) {
         launch_arnoldi_small(N, j, w, Vb, N, k, s);
-    } else if (launch_arnoldi_grid(N, j, w, Vb, N, k, s, allow_coop ? 4 : 16, allow_coop, o.ortho == 0)) {
-    } else {
-        for (int i = 0; i <= j; ++i) launch_mgs(N, i, j, w, Vb, N, k, s);
-        launch_norm_givens(N, j, w, Vb, N, k, s);
-        launch_scale_by(N, w, w, &k.scal[1], s);
+        return k.hstep != nullptr;
     }
+    if (launch_arnoldi_grid(N, j, w, Vb, N, k, s, allow_coop ? 4 : 16, allow_coop, o.ortho == 0))
+        return k.hstep != nullptr;
+    for (int i = 0; i <= j; ++i) launch_mgs(N, i, j, w, Vb, N, k, s);
+    launch_norm_givens(N, j, w, Vb, N, k, s);
+    launch_scale_by(N, w, w, &k.scal[1], s);
+    return false;
 }
 
 void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s) {
@@ -1050,11 +1060,14 @@ void SolveRun::enqueue_step(int jj) {
         // MGS + norm + Givens + normalisation of w; algorithmic bytes: each
         // basis vector v_0..v_jj read once, w read once and written once
         S->tstart(3, s);
-        S->arnoldi(N, jj, w, Vb, kd, s);
+        const bool published = S->arnoldi(N, jj, w, Vb, kd, s);
         S->tstop(3, 16.0 * (jj + 3) * N, s);
-        // scal[0..7] and ints[0..5] are adjacent on the device: one transfer
-        HH_HIP(hipMemcpyAsync(S->pin_step + 128 * slot, kd.scal, 8 * sizeof(double) + 6 * sizeof(int),
-                              hipMemcpyDeviceToHost, s));
+        // the fused step kernels store |g_{j+1}| and the flags in the pinned slot
+        // themselves; otherwise scal[0..7] and ints[0..5] (adjacent on the
+        // device) are copied in one transfer
+        if (!published)
+            HH_HIP(hipMemcpyAsync(S->pin_step + 128 * slot, kd.scal, 8 * sizeof(double) + 6 * sizeof(int),
+                                  hipMemcpyDeviceToHost, s));
     };
     if (S->use_graphs && S->graphs_allowed()) {
         if ((int)S->step_graphs.size() <= jj) S->step_graphs.resize(jj + 1, nullptr);
