@@ -26,6 +26,7 @@ step written as the paper states it (section 3) with the readings below.
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 from . import bspline as bs
 from .helmholtz import fine_operators
@@ -134,6 +135,24 @@ def deflation_levels(levels, opts):
     return L
 
 
+# Deflation matrices up to this many unknowns are factored densely; larger ones
+# (the 58k-unknown levels of the 480^2 and 960^2 workloads would need 27 GB
+# dense) by a sparse LU.  Both are an exact factorisation of the same E, so E^-1 c
+# agrees to rounding whichever is used.
+DENSE_E_MAX = 4096
+
+
+def exact_factor(E):
+    """A function c -> E^-1 c for the real matrix E (complex c: real and imaginary
+    parts solved separately, E being real): dense LU with partial pivoting for small E,
+    SuperLU (scipy.sparse.linalg.splu) otherwise."""
+    if E.shape[0] <= DENSE_E_MAX:
+        lu = sla.lu_factor(E.toarray())
+        return lambda c: sla.lu_solve(lu, c)
+    lu = spla.splu(sp.csc_matrix(E))
+    return lambda c: lu.solve(np.ascontiguousarray(c.real)) + 1j * lu.solve(np.ascontiguousarray(c.imag))
+
+
 class Solver:
     """The oracle's preconditioned solver for one problem.
 
@@ -148,7 +167,7 @@ class Solver:
         self.levels = build_hierarchy(prob, self.opts)
         self.Lz = deflation_levels(self.levels, self.opts)
         if self.Lz > 0:
-            self.E_lu = sla.lu_factor(self.levels[self.Lz].A.toarray())
+            self.E_lu = exact_factor(self.levels[self.Lz].A)
 
     # ---- multigrid on the CSLP --------------------------------------------
     def jacobi(self, l, b, x):
@@ -198,7 +217,7 @@ class Solver:
     def coarse_solve(self, l, c):
         """E^-1 c at deflation level l: dense LU at L_z, else inner FGMRES."""
         if l == self.Lz:
-            return sla.lu_solve(self.E_lu, c)
+            return self.E_lu(c)
         m = self.opts.defl_inner_its[min(l - 1, len(self.opts.defl_inner_its) - 1)]
         x, _ = fgmres_fixed(lambda v: self.levels[l].A @ v, lambda v: self.T(l, v), c, m)
         return x
@@ -234,12 +253,14 @@ def givens(a, b):
     return abs(a) / t, (a / abs(a)) * np.conj(b) / t
 
 
-def _arnoldi_cycle(Aop, Top, r0, m, stop_abs, record):
+def _arnoldi_cycle(Aop, Top, r0, m, stop_abs, record, trace=None):
     """One FGMRES cycle of at most m steps from residual r0; returns the update.
 
     Arnoldi with modified Gram-Schmidt (h_ij = v_i^H w), Givens QR of the
     Hessenberg matrix, upper-triangular solve, update sum_i z_i y_i.  The cycle
     stops early when |g_{j+1}| <= stop_abs or on breakdown (h_{j+1,j} == 0).
+    trace (a dict, optional) receives the basis V, the preconditioned vectors Z
+    and the Hessenberg matrix before rotation ("V", "Z", "H").
     """
     n = r0.shape[0]
     beta = np.linalg.norm(r0)
@@ -262,6 +283,8 @@ def _arnoldi_cycle(Aop, Top, r0, m, stop_abs, record):
             w = w - H[i, j] * V[i]
         hn = np.linalg.norm(w)
         H[j + 1, j] = hn
+        if trace is not None:
+            trace.setdefault("H", np.zeros((m + 1, m), dtype=np.complex128))[:j + 2, j] = H[:j + 2, j]
         for i in range(j):
             t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
             H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + cs[i] * H[i + 1, j]
@@ -277,6 +300,10 @@ def _arnoldi_cycle(Aop, Top, r0, m, stop_abs, record):
         if hn == 0.0 or abs(g[j + 1]) <= stop_abs:
             break
         V.append(w / hn)
+    if trace is not None:
+        trace["V"] = np.array(V + ([w / hn] if hn != 0.0 and len(V) == j_done else []))
+        trace["Z"] = np.array(Z)
+        trace["H"] = trace["H"][:j_done + 1, :j_done]
     y = np.zeros(j_done, dtype=np.complex128)
     for i in range(j_done - 1, -1, -1):
         y[i] = (g[i] - H[i, i + 1:j_done] @ y[i + 1:]) / H[i, i]
@@ -286,9 +313,9 @@ def _arnoldi_cycle(Aop, Top, r0, m, stop_abs, record):
     return dx, j_done, abs(g[j_done])
 
 
-def fgmres_fixed(Aop, Top, b, m):
+def fgmres_fixed(Aop, Top, b, m, trace=None):
     """Exactly m FGMRES steps from x0 = 0 (fewer only on breakdown); no restart."""
-    dx, its, _ = _arnoldi_cycle(Aop, Top, b.astype(np.complex128), m, -1.0, None)
+    dx, its, _ = _arnoldi_cycle(Aop, Top, b.astype(np.complex128), m, -1.0, None, trace)
     return dx, its
 
 
