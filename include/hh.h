@@ -160,6 +160,19 @@ hh_status hh_point_spans(const hh_problem* pr, const double* x0, int* spans);
 hh_status hh_rhs_point_source(const hh_problem* pr, const double* x0, double amp,
                               void* f_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same load as
+ * hh_rhs_point_source, bit-identical, with no device or heap allocation.  The
+ * two 1D basis factors are staged in a fixed device array of 65536 doubles
+ * (512 KB) that each device keeps for the life of the process; HH_EINVAL if
+ * n[0] + n[1] of the finest level exceeds 65536.  The current device must be
+ * the one that holds f_dev and stream.  Every call on a device shares that
+ * array (the last call's contents stay in it): calls that overlap on one
+ * device race; within one process they are serialised by a lock, from several
+ * processes they must not overlap.  Returns after the stream has drained. */
+hh_status hh_rhs_point_source_noalloc(const hh_problem* pr, const double* x0, double amp,
+                                      void* f_dev, void* stream);
+
 /* Finest-level operators of an assembled problem in CSR form (section 2.3:
  * stiffness, k^2-weighted mass and A = K - M_k after Dirichlet elimination),
  * for exact comparisons of sparsity and values on small meshes; host only.

@@ -19,7 +19,7 @@ HH_EINVAL, HH_ENOMEM, HH_EHIP, HH_ENUMERIC = -1, -2, -3, -4
 OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 5, "T": 6, "EINV": 7}
 
 EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
-            "hh_point_spans", "hh_rhs_point_source", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
+            "hh_point_spans", "hh_rhs_point_source", "hh_rhs_point_source_noalloc", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
             "hh_level_info", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched", "hh_cnn_create",
             "hh_cnn_destroy", "hh_cnn_num_params", "hh_cnn_get_params", "hh_cnn_set_params", "hh_cnn_set_fused", "hh_cnn_loss_grad",
             "hh_cnn_train_step", "hh_solver_set_smoother", "hh_solver_capture", "hh_solver_captured"]
@@ -78,6 +78,7 @@ def load(path=LIB_PATH):
     lib.hh_problem_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.hh_point_spans.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.hh_rhs_point_source.argtypes = [vp, ctypes.POINTER(ctypes.c_double), dp, vp, vp]
+    lib.hh_rhs_point_source_noalloc.argtypes = [vp, ctypes.POINTER(ctypes.c_double), dp, vp, vp]
     lib.hh_export_csr.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong), vp, vp, vp, ctypes.c_longlong]
     lib.hh_setup.argtypes = [vp, ctypes.POINTER(SolverOpts), vp, ctypes.POINTER(vp)]
     lib.hh_solver_destroy.argtypes = [vp]
@@ -199,6 +200,12 @@ class Problem:
             out = torch.empty(self.N, dtype=torch.complex128, device="cuda")
         x = (ctypes.c_double * 2)(*(list(x0) + [0.0] * (2 - len(x0))))
         _check(load().hh_rhs_point_source(self._h, x, float(amp), _ptr(out), _stream()))
+        return out
+
+    def point_source_noalloc(self, x0, out, amp=1.0):
+        """hh_rhs_point_source_noalloc: the same load into the caller's `out`, no allocation."""
+        x = (ctypes.c_double * 2)(*(list(x0) + [0.0] * (2 - len(x0))))
+        _check(load().hh_rhs_point_source_noalloc(self._h, x, float(amp), _ptr(out), _stream()))
         return out
 
     def close(self):

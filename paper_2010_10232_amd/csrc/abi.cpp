@@ -139,33 +139,16 @@ hh_status hh_export_csr(const hh_problem* pr, int which, long long* nnz, long lo
 hh_status hh_rhs_point_source(const hh_problem* pr, const double* x0, double amp, void* f_dev, void* stream) {
     HH_TRY
     if (!pr || !x0 || !f_dev) throw Err{HH_EINVAL, "NULL argument"};
-    const ProblemImpl& P = pr->impl;
-    int spans[2] = {0, 0};
-    int st = hh_point_spans(pr, x0, spans);
-    if (st != HH_OK) return st;
-    const int p = P.p;
-    std::vector<double> fx(P.ax0.n, 0.0), fy(P.ay0.n, 0.0);
-    double Nv[8];
-    basis_values(P.ax0.U, p, spans[0] + p, x0[0], Nv, nullptr);
-    for (int a = 0; a <= p; ++a) {
-        int i = spans[0] + a - 1;
-        if (i >= 0 && i < P.ax0.n) fx[i] = Nv[a];
-    }
-    if (P.dim == 2) {
-        basis_values(P.ay0.U, p, spans[1] + p, x0[1], Nv, nullptr);
-        for (int a = 0; a <= p; ++a) {
-            int i = spans[1] + a - 1;
-            if (i >= 0 && i < P.ay0.n) fy[i] = Nv[a];
-        }
-    } else {
-        fy[0] = 1.0;
-    }
-    std::vector<cx<double>> f((size_t)P.N());
-    for (int i2 = 0; i2 < P.ay0.n; ++i2)
-        for (int i1 = 0; i1 < P.ax0.n; ++i1) f[(size_t)i2 * P.ax0.n + i1] = {amp * fy[i2] * fx[i1], 0.0};
-    hipStream_t s = (hipStream_t)stream;
-    HH_HIP(hipMemcpyAsync(f_dev, f.data(), f.size() * sizeof(cx<double>), hipMemcpyHostToDevice, s));
-    HH_HIP(hipStreamSynchronize(s));
+    rhs_point_source(pr->impl, x0, amp, (cx<double>*)f_dev, (hipStream_t)stream);
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_rhs_point_source_noalloc(const hh_problem* pr, const double* x0, double amp, void* f_dev,
+                                      void* stream) {
+    HH_TRY
+    if (!pr || !x0 || !f_dev) throw Err{HH_EINVAL, "NULL argument"};
+    rhs_point_source_noalloc(pr->impl, x0, amp, (cx<double>*)f_dev, (hipStream_t)stream);
     return HH_OK;
     HH_CATCH
 }

@@ -156,6 +156,11 @@ struct SolverImpl {
 
 ProblemImpl* build_problem(const hh_problem_desc* d);
 
+// f = amp * Phi(x0) on the device (rhs.hip): staging allocated per call, or
+// the fixed staging array (no allocation).
+void rhs_point_source(const ProblemImpl& P, const double* x0, double amp, cx<double>* f, hipStream_t s);
+void rhs_point_source_noalloc(const ProblemImpl& P, const double* x0, double amp, cx<double>* f, hipStream_t s);
+
 }  // namespace hh
 
 struct hh_problem {
