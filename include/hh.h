@@ -98,6 +98,15 @@ typedef struct {
                                 coefficients in exact arithmetic, one grid-wide sum per
                                 step instead of j + 1); 1: always one grid-wide sum per
                                 projection.  Results agree to rounding. */
+    int defl_direct_solver;  /* exact E^-1 at the direct deflation level when k varies
+                                (constant k always uses the fast diagonalisation):
+                                0 (default): substructured from 2048 unknowns on, else a
+                                dense inverse; 1: dense inverse (LU, N_z^2 entries);
+                                2: substructured - bands of p grid lines cut the level into
+                                subdomains whose interiors are eliminated exactly (dense
+                                inverse per subdomain) and the separator Schur complement
+                                is inverted densely; HH_EINVAL if no such cut exists.  All
+                                three are exact factorisations of E (section 3). */
 } hh_solver_opts;
 
 typedef struct {
@@ -122,6 +131,14 @@ typedef struct {
     int n_levels;            /* multigrid levels (finest = 0) */
     int defl_direct_level;   /* L_z: deflation level solved directly (0: no deflation) */
     int op_rows[2];          /* strip height (rows) of the level-operator kernel, FP64 / FP32 */
+    int defl_sub[2];         /* substructured E^-1 (defl_direct_solver): subdomains per
+                                direction at the direct deflation level, else 0 */
+    long long defl_sep;      /* separator unknowns of that cut (0 if not substructured) */
+    double defl_check;       /* ||c - E E^-1 c|| / ||c|| for a fixed pseudo-random c, taken
+                                at setup (substructured E^-1 only; -1 otherwise) */
+    int defl_refine;         /* iterative refinement steps per substructured E^-1 (set-up
+                                chooses 0..3 from the residual of one pass; each step costs
+                                one more pass) */
 } hh_level_stats;
 
 /* Debug / parity operators of hh_apply. */

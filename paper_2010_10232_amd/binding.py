@@ -38,7 +38,7 @@ class SolverOpts(ctypes.Structure):
                 ("defl_mode", ctypes.c_int), ("defl_direct_max", ctypes.c_int),
                 ("defl_inner_its", ctypes.c_int * 8), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("time_kernels", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("ortho", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("ortho", ctypes.c_int), ("defl_direct_solver", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -55,7 +55,9 @@ class SolveInfo(ctypes.Structure):
 class LevelStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 2), ("n_el", ctypes.c_int * 2), ("N", ctypes.c_longlong),
                 ("omega", ctypes.c_double), ("gersh", ctypes.c_double), ("n_levels", ctypes.c_int),
-                ("defl_direct_level", ctypes.c_int), ("op_rows", ctypes.c_int * 2)]
+                ("defl_direct_level", ctypes.c_int), ("op_rows", ctypes.c_int * 2),
+                ("defl_sub", ctypes.c_int * 2), ("defl_sep", ctypes.c_longlong), ("defl_check", ctypes.c_double),
+                ("defl_refine", ctypes.c_int)]
 
 
 _lib = None
@@ -236,7 +238,9 @@ class Solver:
         _check(load().hh_level_info(self._h, int(level), ctypes.byref(st)))
         return {"n": (st.n[0], st.n[1]), "n_el": (st.n_el[0], st.n_el[1]), "N": st.N,
                 "omega": st.omega, "gersh": st.gersh, "n_levels": st.n_levels,
-                "defl_direct_level": st.defl_direct_level, "op_rows": (st.op_rows[0], st.op_rows[1])}
+                "defl_direct_level": st.defl_direct_level, "op_rows": (st.op_rows[0], st.op_rows[1]),
+                "defl_sub": (st.defl_sub[0], st.defl_sub[1]), "defl_sep": st.defl_sep, "defl_check": st.defl_check,
+                "defl_refine": st.defl_refine}
 
     def set_smoother(self, cnn):
         """cnn: a Cnn (learned finest-level smoother) or None (damped Jacobi)."""

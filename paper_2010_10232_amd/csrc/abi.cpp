@@ -54,6 +54,7 @@ void hh_default_opts(hh_solver_opts* o) {
     o->time_kernels = 0;
     o->autotune = 1;
     o->ortho = 0;
+    o->defl_direct_solver = 0;
 }
 
 const char* hh_last_error(void) { return g_err.c_str(); }
@@ -448,6 +449,12 @@ hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out) {
     out->defl_direct_level = S.Lz;
     out->op_rows[0] = lv.ty64;
     out->op_rows[1] = lv.ty32;
+    const bool sub_here = S.sub && level == S.Lz;
+    out->defl_sub[0] = sub_here ? S.sub->bx : 0;
+    out->defl_sub[1] = sub_here ? S.sub->by : 0;
+    out->defl_sep = sub_here ? S.sub->nS : 0;
+    out->defl_check = sub_here ? S.sub->self_check : -1.0;
+    out->defl_refine = sub_here ? S.sub->refine : 0;
     return HH_OK;
     HH_CATCH
 }

@@ -6,6 +6,7 @@
 
 #include "cnn.h"
 #include "hh_internal.h"
+#include "substruct.h"
 
 namespace hh {
 
@@ -90,6 +91,11 @@ struct SolverImpl {
     // variable k, nZ >= 2048: E^-1 kept as its packed upper triangle (symmetric)
     bool sym = false;
     DevBuf EinvP, symRow, symCol;
+    // variable k, substructured E^-1 (separator Schur complement)
+    std::unique_ptr<SubstructE> sub;
+    void substruct_pass(const cx<double>* c, cx<double>* e, hipStream_t s);
+    void substruct_apply(const cx<double>* c, cx<double>* e, hipStream_t s);
+    double substruct_check(hipStream_t s);
     // outer FGMRES
     int m_outer = 0;
     DevBuf V, Z, kstate, r, scratch;

@@ -206,6 +206,7 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(o.maxit >= 1, "maxit must be >= 1");
     HH_REQUIRE(o.nu_pre >= 1 && o.nu_post >= 0 && o.n_vcycles >= 1, "bad smoothing counts");
     HH_REQUIRE(o.ortho == 0 || o.ortho == 1, "ortho is 0 or 1");
+    HH_REQUIRE(o.defl_direct_solver >= 0 && o.defl_direct_solver <= 2, "defl_direct_solver is 0, 1 or 2");
     HH_REQUIRE(o.mg_min_elems >= 2, "mg_min_elems must be >= 2");
     HH_REQUIRE(o.defl_mode >= 0 && o.defl_mode <= 2, "defl_mode must be 0, 1 or 2");
     HH_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
@@ -547,11 +548,51 @@ void SolverImpl::setup(hipStream_t s) {
         fdmT2.alloc((size_t)nZ * 16);
         fdm = true;
     } else if (Lz > 0) {
+        LevelDev& lz = *lev[Lz];
+        nZ = (int)lz.N;
+        const bool want_sub = o.defl_direct_solver == 2 || (o.defl_direct_solver == 0 && nZ >= 2048);
+        const auto cands = want_sub ? substruct_partitions(lz.n1, lz.n2, lz.ax.p, lz.ay.p, kSubCandidates)
+                                    : std::vector<std::pair<int, int>>();
+        if (o.defl_direct_solver == 2 && cands.empty())
+            throw Err{HH_EINVAL, "no substructuring cut fits the direct deflation level"};
+        // variable k, substructured: exact E^-1 from per-subdomain inverses and
+        // the dense inverse of the separator Schur complement.  The block
+        // elimination is exact but loses accuracy when a subdomain block is near
+        // a Dirichlet resonance of the Helmholtz operator, so the cheapest cuts
+        // are tried in turn until one passes the set-up check; the best one is
+        // kept, with iterative refinement where it still falls short.
+        const std::vector<double>& Sz = Sh[Lz];
+        std::unique_ptr<SubstructE> best;
+        for (const auto& bxy : cands) {
+            sub = std::make_unique<SubstructE>();
+            substruct_build(
+                *sub, lz.n1, lz.n2, lz.ax.p, lz.ay.p, bxy.first, bxy.second,
+                [&](long long I, const std::function<void(long long, double)>& f) {
+                    visit_row(lz.ax, lz.ay, const_k, k2c, Sz, I,
+                              [&](long long J, double kv, double mv) { f(J, kv - mv); });
+                },
+                s);
+            sub->check0 = substruct_check(s);
+            if (!best || sub->check0 < best->check0) best = std::move(sub);
+            if (best->check0 <= kSubCheckTol) break;
+        }
+        sub = std::move(best);
+        if (sub) {
+            const double c0 = sub->check0;
+            if (!(c0 < 0.5))
+                throw Err{HH_ENUMERIC, "substructured E^-1 check failed (relative residual " + std::to_string(c0) + ")"};
+            // each refinement step multiplies the residual by about c0
+            int m = 0;
+            for (double r = c0; r > kSubCheckTol && m < kSubMaxRefine; r *= c0) ++m;
+            sub->refine = m;
+            sub->self_check = m ? substruct_check(s) : c0;
+        }
+    }
+    if (Lz > 0 && !const_k && !sub) {
         // variable k: dense inverse of E, assembled on the device from its
         // nonzeros (E and its inverse are symmetric, so row- and column-major
         // storage coincide)
         LevelDev& lz = *lev[Lz];
-        nZ = (int)lz.N;
         HH_REQUIRE(nZ <= 65536, "direct deflation level too large (at most 65536 unknowns)");
         ldZ = (nZ + 1) & ~1LL;   // even leading dimension: 16-byte aligned rows
         std::vector<long long> cidx;
@@ -956,6 +997,70 @@ bool SolverImpl::arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, Kryl
     return false;
 }
 
+// Substructured E^-1 (variable k): y_I = E_II^-1 c_I; x_S = S^-1 (c - E [y_I; 0])_S;
+// x_I = E_II^-1 (c - E [0; x_S])_I.  xhat and xt are zero off the interior and
+// separator entries (only those are ever written), so the level operator forms
+// the off-diagonal products.
+void SolverImpl::substruct_pass(const cx<double>* c, cx<double>* e, hipStream_t s) {
+    SubstructE& E = *sub;
+    const int* mp = E.map.as<int>();
+    cx<double>* rp = E.rowpart.as<cx<double>>();
+    cx<double>* cp = E.colpart.as<cx<double>>();
+    cx<double>* xhat = E.xhat.as<cx<double>>();
+    cx<double>* xt = E.xt.as<cx<double>>();
+    cx<double>* rv = E.rvec.as<cx<double>>();
+    launch_symv_batch(E.subMats.as<SymMat>(), E.nsub, E.sub_tiles, E.sub_rows, E.subP.as<double>(), mp, c, rp, cp,
+                      xhat, nullptr, s);
+    op<double>(Lz, MODE_RESID, false, xhat, c, rv, s);
+    launch_symv_batch(E.SMats.as<SymMat>(), 1, E.S_tiles, E.S_rows, E.SP.as<double>(), mp, rv, rp, cp, e, xt, s);
+    op<double>(Lz, MODE_RESID, false, xt, c, rv, s);
+    launch_symv_batch(E.subMats.as<SymMat>(), E.nsub, E.sub_tiles, E.sub_rows, E.subP.as<double>(), mp, rv, rp, cp,
+                      e, nullptr, s);
+}
+
+// One pass, then sub->refine steps of iterative refinement e += pass(c - E e).
+void SolverImpl::substruct_apply(const cx<double>* c, cx<double>* e, hipStream_t s) {
+    substruct_pass(c, e, s);
+    SubstructE& E = *sub;
+    const long long N = lev[Lz]->N;
+    for (int i = 0; i < E.refine; ++i) {
+        op<double>(Lz, MODE_RESID, false, e, c, E.rr.as<cx<double>>(), s);
+        substruct_pass(E.rr.as<cx<double>>(), E.dd.as<cx<double>>(), s);
+        launch_axpy<double>(N, E.dd.as<cx<double>>(), e, s);
+    }
+}
+
+// Set-up check: ||c - E (E^-1 c)|| / ||c|| for a fixed pseudo-random c.
+double SolverImpl::substruct_check(hipStream_t s) {
+    const LevelDev& lz = *lev[Lz];
+    std::vector<cx<double>> hc((size_t)lz.N), hr((size_t)lz.N);
+    uint64_t st = 0x243F6A8885A308D3ull;
+    auto uni = [&st]() {   // SplitMix64, top 53 bits, centred
+        st += 0x9E3779B97F4A7C15ull;
+        uint64_t z = st;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * 0x1.0p-53 - 0.5;
+    };
+    for (auto& v : hc) v = {uni(), uni()};
+    DevBuf dc, de, dr;
+    upload(dc, hc);
+    de.alloc((size_t)lz.N * 16);
+    dr.alloc((size_t)lz.N * 16);
+    substruct_apply(dc.as<cx<double>>(), de.as<cx<double>>(), s);
+    op<double>(Lz, MODE_RESID, false, de.as<cx<double>>(), dc.as<cx<double>>(), dr.as<cx<double>>(), s);
+    HH_HIP(hipMemcpyAsync(hr.data(), dr.p, hr.size() * 16, hipMemcpyDeviceToHost, s));
+    HH_HIP(hipStreamSynchronize(s));
+    double nc = 0.0, nr = 0.0;
+    for (size_t i = 0; i < hc.size(); ++i) {
+        nc += hc[i].re * hc[i].re + hc[i].im * hc[i].im;
+        nr += hr[i].re * hr[i].re + hr[i].im * hr[i].im;
+    }
+    const double v = std::sqrt(nr / nc);
+    return std::isfinite(v) ? v : 1e300;
+}
+
 void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s) {
     if (l == Lz) {
         tstart(2, s);
@@ -965,6 +1070,9 @@ void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStre
                              fdmDinv.as<double>(), c, fdmT1.as<cx<double>>(), fdmT2.as<cx<double>>(), e, s);
             // c, e, 1/D and both eigenvector matrices once
             tstop(2, 40.0 * nZ + 8.0 * ((double)lz.n1 * lz.n1 + (double)lz.n2 * lz.n2), s);
+        } else if (sub) {
+            substruct_apply(c, e, s);
+            tstop(2, sub->bytes_per_apply(), s);
         } else {
             if (sym) {
                 launch_symv(nZ, EinvP.as<double>(), c, symRow.as<cx<double>>(), symCol.as<cx<double>>(), e, s);

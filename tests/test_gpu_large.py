@@ -71,6 +71,9 @@ def test_dense_inverse_variable_k_58k(wedge):
     assert sol.levels[0]["defl_direct_level"] == 1
     n1 = sol.levels[1]["N"]
     assert n1 == 241 * 241 and n1 > 32768
+    lv = sol.levels[1]
+    _say(f"  substructured E^-1: {lv['defl_sub']} subdomains, {lv['defl_sep']} separators, "
+         f"check {lv['defl_check']:.2e}, refinement {lv['defl_refine']}")
     c = torch.from_numpy(_rvec(n1, 2)).to("cuda")
     e = sol.apply("EINV", 1, c)
     back = sol.apply("A", 1, e)

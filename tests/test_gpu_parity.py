@@ -62,8 +62,15 @@ CASES = {
     "2d_grf_p3": dict(dim=2, p=3, n_el=17, grf=10.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=100)),
     "2d_rand_p4": dict(dim=2, p=4, n_el=16, rand=9.0, x0=(0.31, 0.77), opts=dict()),
     "2d_tiles_p3": dict(dim=2, p=3, n_el=130, k=40.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=1200)),
-    # variable k, two-level: E^-1 at level 1 (2500 unknowns) stored as its packed upper triangle
+    # variable k, two-level: E^-1 at level 1 (2500 unknowns), substructured (the default from 2048 on)
     "2d_grf_p2_2lev_packed": dict(dim=2, p=2, n_el=100, grf=40.0, x0=(0.5, 0.5), opts=dict(defl_mode=1)),
+    # the same with the dense inverse of E kept as its packed upper triangle
+    "2d_grf_p2_2lev_dense": dict(dim=2, p=2, n_el=100, grf=40.0, x0=(0.5, 0.5),
+                                 opts=dict(defl_mode=1, defl_direct_solver=1)),
+    # wedge, p = 3, two-level: substructured E^-1 at level 1 (65^2 = 4225 unknowns, many subdomains)
+    "2d_wedge_p3_sub": dict(dim=2, p=3, n_el=128, wedge=30.0, x0=(0.5, 0.95), opts=dict(defl_mode=1)),
+    # 1D random k, two-level: substructured E^-1 (forced) at level 1 (151 unknowns), cut in x only
+    "1d_rand_p3_sub": dict(dim=1, p=3, n_el=300, rand=40.0, x0=(0.37,), opts=dict(defl_mode=1, defl_direct_solver=2)),
     # MP 2-A at k = 100, p = 3 on 160 x 160 elements with the default (two-level) deflation
     "mp2a_k100_p3_160": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict()),
 }
@@ -76,11 +83,20 @@ def k_field(c):
     if "grf" in c:
         return W.grf_k(n, kbar=c["grf"], seed=1)
     if "rand" in c:
+        if c["dim"] == 1:
+            return c["rand"] * (1 + 0.4 * W.uniforms(7, n))
         return c["rand"] * (1 + 0.4 * W.uniforms(7, n * n).reshape(n, n))
     return None
 
 
 _cache = {}
+
+# options of the library that select an implementation, not the method: the oracle has none of them
+GPU_ONLY = ("defl_direct_solver", "autotune", "ortho", "time_kernels")
+
+
+def oracle_opts(opts):
+    return osv.Options(**{k: v for k, v in opts.items() if k not in GPU_ONLY})
 
 
 def build(name):
@@ -92,7 +108,7 @@ def build(name):
     k = c.get("k", 1.0)
     _say(f"[case {name}] oracle setup")
     op = hz.Problem(c["dim"], c["p"], c["n_el"], k, k_elem=ke)
-    osol = osv.Solver(op, osv.Options(**c["opts"]))
+    osol = osv.Solver(op, oracle_opts(c["opts"]))
     _say(f"[case {name}] gpu assemble+setup")
     gp = B.Problem(c["dim"], c["p"], c["n_el"], k=k, k_elem=ke)
     gs = B.Solver(gp, **c["opts"])
@@ -238,7 +254,7 @@ def test_mixed_precision_within_1e6(name):
     from paper_2010_10232_amd import binding as B
     c, op, osol, gp, _ = build(name)
     gs32 = B.Solver(gp, precision=1, tol=1e-10, **c["opts"])
-    o64 = osv.Solver(op, osv.Options(tol=1e-10, **c["opts"]))
+    o64 = osv.Solver(op, oracle_opts(dict(tol=1e-10, **c["opts"])))
     f = hz.point_source_rhs(op, c["x0"])
     _say(f"[case {name}] mixed-precision solve")
     u, info = gs32.solve(to_dev(f))
@@ -287,3 +303,27 @@ def test_smoothing_counts_match_oracle(nu_pre, nu_post, n_vcycles):
     u_ref, info_ref = osol.solve(f)
     assert info["converged"] == 1 and info["iters"] == info_ref.iters, (info["iters"], info_ref.iters)
     assert rel(to_host(u), u_ref) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["2d_grf_p2_2lev_packed", "2d_wedge_p3_sub", "1d_rand_p3_sub"])
+def test_substructured_einv(name):
+    """The substructured E^-1 (separator Schur complement) is an exact inverse:
+    its set-up self-check is at rounding level, and it agrees with the dense
+    inverse of the same E and with the oracle's sparse LU."""
+    from paper_2010_10232_amd import binding as B
+    c, op, osol, gp, gs = build(name)
+    Lz = osol.Lz
+    info = gs.levels[Lz]
+    _say(f"[case {name}] substructured level {Lz}: {info['defl_sub']} subdomains, "
+         f"{info['defl_sep']} separators, check {info['defl_check']:.2e}, refinement {info['defl_refine']}")
+    assert info["defl_sub"][0] * info["defl_sub"][1] >= 2 and info["defl_sep"] > 0
+    assert 0 <= info["defl_check"] <= 1e-11
+    dense = B.Solver(gp, **dict(c["opts"], defl_direct_solver=1))
+    assert dense.levels[Lz]["defl_sub"] == (0, 0) and dense.levels[Lz]["defl_check"] == -1.0
+    xl = rvec(osol.levels[Lz].N, 77)
+    ref = osol.coarse_solve(Lz, xl)
+    e_sub = to_host(gs.apply("EINV", Lz, to_dev(xl)))
+    e_dense = to_host(dense.apply("EINV", Lz, to_dev(xl)))
+    assert rel(e_sub, ref) <= 1e-10
+    assert rel(e_sub, e_dense) <= 1e-10
+    assert np.max(np.abs(e_sub - ref)) <= 1e-10 * np.max(np.abs(ref))
