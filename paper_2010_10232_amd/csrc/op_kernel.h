@@ -365,6 +365,99 @@ __global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
 
 
 
+// Stored-stencil level operator (coarse variable-k levels): the Galerkin mass
+// stencil has (2px+1)(2py+1) FP64 coefficients per unknown, 648 B at p = 4
+// against 16 B for x, so the kernel is a stream of coefficients.  A workgroup
+// of four waves owns a 64-column x 4-row output tile; x of the tile and its
+// p-wide halo is staged in LDS once (zero outside the level), the column and
+// row bands of the tile too, and every thread issues all of its coefficient
+// loads (coalesced per stencil entry across the wave) before it uses any.  The
+// sums are formed in the same order as op_direct_kernel: per input row the
+// band products and the stencil products, combined through the y bands.
+constexpr int STC_ROWS = 4;
+template <int PX, int PY, int MODE, class T>
+__global__ __launch_bounds__(256) void op_stencil_kernel(OpArgs<T> a) {
+    constexpr int BX = 2 * PX + 1, BY = 2 * PY + 1;
+    constexpr int TX = 64, LW = TX + 2 * PX, LH = STC_ROWS + 2 * PY;
+    __shared__ cx<T> xs[LH][LW];
+    __shared__ T kxS[BX][TX], mxS[BX][TX];
+    __shared__ T kyS[STC_ROWS][BY], myS[STC_ROWS][BY];
+    const int n1 = a.n1, n2 = a.n2;
+    const long long N = (long long)n1 * n2;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tiles_x = (n1 + TX - 1) / TX;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int C0 = (b % tiles_x) * TX, R0 = (b / tiles_x) * STC_ROWS;
+    const int I1 = C0 + lane, I2 = R0 + w;
+    const bool active = I1 < n1 && I2 < n2;
+    const long long I = active ? (long long)I2 * n1 + I1 : 0;
+    // coefficients first: every load of the thread in flight at once
+    T c[BY * BX];
+#pragma unroll
+    for (int q = 0; q < BY * BX; ++q) c[q] = a.S[(size_t)q * N + I];
+    // stage x (tile + halo) and the bands
+    for (int e = threadIdx.x; e < LH * LW; e += 256) {
+        const int rr = e / LW, cc = e % LW;
+        const int J2 = R0 - PY + rr, J1 = C0 - PX + cc;
+        xs[rr][cc] = (J2 >= 0 && J2 < n2 && J1 >= 0 && J1 < n1) ? a.x[(size_t)J2 * n1 + J1] : cx<T>{T(0), T(0)};
+    }
+    {
+        const int I1c = I1 < n1 ? I1 : n1 - 1;
+        for (int d = w; d < BX; d += 4) {
+            kxS[d][lane] = (T)a.Kx[(size_t)I1c * BX + d];
+            mxS[d][lane] = (T)a.Mx[(size_t)I1c * BX + d];
+        }
+        if (lane < BY) {
+            const int I2c = I2 < n2 ? I2 : n2 - 1;
+            kyS[w][lane] = (T)a.Ky[(size_t)I2c * BY + lane];
+            myS[w][lane] = (T)a.My[(size_t)I2c * BY + lane];
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    const T are = a.are, aim = a.aim;
+    T wr = 0, wi = 0, vr = 0, vi = 0;
+#pragma unroll
+    for (int d2 = 0; d2 < BY; ++d2) {
+        T u1r = 0, u1i = 0, u2r = 0, u2i = 0;
+#pragma unroll
+        for (int d = 0; d < BX; ++d) {
+            const cx<T> v = xs[w + d2][lane + d];
+            const T kx = kxS[d][lane], mx = mxS[d][lane];
+            u1r += kx * v.re;
+            u1i += kx * v.im;
+            u2r += mx * v.re;
+            u2i += mx * v.im;
+            const T cc = c[d2 * BX + d];
+            vr += cc * v.re;
+            vi += cc * v.im;
+        }
+        wr += myS[w][d2] * u1r + kyS[w][d2] * u2r;
+        wi += myS[w][d2] * u1i + kyS[w][d2] * u2i;
+    }
+    const T yr = wr - (are * vr - aim * vi);
+    const T yi = wi - (are * vi + aim * vr);
+    cx<T> out;
+    if (MODE == MODE_APPLY) {
+        out = {yr, yi};
+    } else {
+        const cx<T> bv = a.b[I];
+        const T rr = bv.re - yr, ri = bv.im - yi;
+        if (MODE == MODE_RESID) {
+            out = {rr, ri};
+            if (a.xo) a.xo[I] = first_sweep(a, I, out);
+        } else {
+            const cx<T> dv = a.dinv[I], xv = xs[w + PY][lane + PX];
+            out = {xv.re + a.omega * (dv.re * rr - dv.im * ri), xv.im + a.omega * (dv.re * ri + dv.im * rr)};
+            if (a.yadd) {
+                const cx<T> q = a.yadd[I];
+                out = {out.re + q.re, out.im + q.im};
+            }
+        }
+    }
+    a.y[I] = out;
+}
+
 // Strip height: the tallest of 64, 32, 16, 8, 4 rows that still gives at
 // least 2048 waves (eight per CU); tall strips amortise the 2p halo rows.
 inline int op_rows_per_strip(int n1, int n2, int py) {
@@ -377,6 +470,11 @@ inline int op_rows_per_strip(int n1, int n2, int py) {
 
 template <int PX, int PY, int KIND, int MODE, class T>
 static void launch_op_t(const OpArgs<T>& a, hipStream_t s) {
+    if (KIND == KIND_STENCIL && PY > 0 && (long long)a.n1 * a.n2 > kOpDirectMax) {
+        const long long tiles = (long long)((a.n1 + 63) / 64) * ((a.n2 + STC_ROWS - 1) / STC_ROWS);
+        hipLaunchKernelGGL((op_stencil_kernel<PX, PY, MODE, T>), dim3((unsigned)tiles), dim3(256), 0, s, a);
+        return;
+    }
     if (KIND != KIND_VARFINE && PY > 0 && (long long)a.n1 * a.n2 <= kOpDirectMax) {
         const long long N = (long long)a.n1 * a.n2;
         hipLaunchKernelGGL((op_direct_kernel<PX, PY, KIND, MODE, T>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0,

@@ -71,6 +71,11 @@ CASES = {
     "2d_wedge_p3_sub": dict(dim=2, p=3, n_el=128, wedge=30.0, x0=(0.5, 0.95), opts=dict(defl_mode=1)),
     # 1D random k, two-level: substructured E^-1 (forced) at level 1 (151 unknowns), cut in x only
     "1d_rand_p3_sub": dict(dim=1, p=3, n_el=300, rand=40.0, x0=(0.37,), opts=dict(defl_mode=1, defl_direct_solver=2)),
+    # variable k, 400^2 elements, p = 2: level 1 (40,000 unknowns) is above the one-thread-per-unknown
+    # bound and takes the tiled stored-stencil kernel; its E^-1 is substructured
+    "2d_grf_p2_400_stencil": dict(dim=2, p=2, n_el=400, grf=60.0, x0=(0.5, 0.5), opts=dict(defl_mode=1)),
+    # constant k, 200^2 elements, p = 2: level 0 (40,000 unknowns) takes the row-marching strip kernel
+    "2d_const_p2_200_strip": dict(dim=2, p=2, n_el=200, k=40.0, x0=(0.5, 0.5), opts=dict()),
     # MP 2-A at k = 100, p = 3 on 160 x 160 elements with the default (two-level) deflation
     "mp2a_k100_p3_160": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict()),
 }
@@ -149,8 +154,10 @@ def test_level_operators(name):
         assert e <= 1e-13, e
         e = rel(to_host(gs.apply("MBETA", l, xd)), lv.Mb @ x)
         assert e <= 1e-13, e
+        # D is the diagonal of the Galerkin M_beta whose products are held to 1e-13 above; the
+        # two sides sum its entries over the finest elements in different orders
         e = rel(to_host(gs.apply("JACOBI0", l, xd)), lv.omega * x / lv.D)
-        assert e <= 1e-14, e
+        assert e <= 1e-13, e
         if l + 1 < len(osol.levels):
             P = osol.levels[l + 1].P
             _say(f"[case {name}] level {l} restrict / prolong")
