@@ -82,7 +82,10 @@ typedef struct {
     int time_kernels;        /* kernel class timed with HIP events during hh_solve (results
                                 in hh_solve_info): 0 none (default), 1 finest-level operator
                                 (stencil) kernels, 2 exact E^-1 solve of the direct
-                                deflation level, 3 outer Arnoldi MGS kernels */
+                                deflation level (all its kernels), 3 outer Arnoldi MGS
+                                kernels, 4 the tiled stored-stencil operator of coarse
+                                variable-k levels, 5 the packed symmetric tile products of
+                                the substructured E^-1 */
     int autotune;            /* 1 (default): at setup, time the strip level-operator kernel
                                 of every level that uses it (FP64 and FP32; levels of at
                                 most 32768 unknowns with constant k or a stored stencil use
@@ -120,6 +123,16 @@ typedef struct {
     int op_launches;         /* time_kernels: number of such launches */
     double op_bytes_per_launch; /* algorithmic HBM bytes per launch of that class (mean) */
     int status;              /* the hh_status of this solve (per problem in hh_solve_batched) */
+    double model_bytes;      /* algorithmic HBM bytes of the work the solve used: every kernel's
+                                operands counted once per launch (vectors, stencil or k^2
+                                coefficients, stored factors of E^-1, Krylov basis); the
+                                whole-solve HBM fraction is model_bytes / t_solve / peak */
+    double model_flops;      /* floating-point operations of the same work (a complex x real
+                                multiply-add counts 4, complex x complex 8) */
+    int arnoldi_fallback;    /* hh_solve: 1 if a grid-wide Arnoldi kernel gave up waiting for
+                                other workgroups (bounded wait) and the solve, started from
+                                zero, was run again with the per-projection kernels (which
+                                the solver keeps using); 0 otherwise */
 } hh_solve_info;
 
 typedef struct {
@@ -241,6 +254,13 @@ hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out);
 /* Selects the kernel class timed during later hh_solve calls (values as for
  * hh_solver_opts.time_kernels); 0 turns timing off. */
 hh_status hh_set_kernel_timing(hh_solver* s, int cls);
+
+/* Debug / tests only: polls a grid-exchange wait of the Arnoldi kernels makes
+ * before it gives up and flags a timeout (spins >= 1; 0 restores the default,
+ * about a second).  A tiny value forces the timeout path while every kernel
+ * still exits normally.  Also re-enables the grid-wide Arnoldi kernels after a
+ * fallback. */
+hh_status hh_debug_set_spin_limit(hh_solver* s, int spins);
 
 /* Applies one building block of the preconditioner (HH_OP_*) at `level` to a
  * device vector: for checking against a reference implementation.  x_dev and

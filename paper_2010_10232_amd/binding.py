@@ -22,7 +22,8 @@ EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destr
             "hh_point_spans", "hh_rhs_point_source", "hh_rhs_point_source_noalloc", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
             "hh_level_info", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched", "hh_cnn_create",
             "hh_cnn_destroy", "hh_cnn_num_params", "hh_cnn_get_params", "hh_cnn_set_params", "hh_cnn_set_fused", "hh_cnn_loss_grad",
-            "hh_cnn_train_step", "hh_solver_set_smoother", "hh_solver_capture", "hh_solver_captured"]
+            "hh_cnn_train_step", "hh_solver_set_smoother", "hh_solver_capture", "hh_solver_captured",
+            "hh_debug_set_spin_limit"]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -46,7 +47,8 @@ class SolveInfo(ctypes.Structure):
                 ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("op_ms_total", ctypes.c_double),
                 ("op_launches", ctypes.c_int), ("op_bytes_per_launch", ctypes.c_double),
-                ("status", ctypes.c_int)]
+                ("status", ctypes.c_int), ("model_bytes", ctypes.c_double), ("model_flops", ctypes.c_double),
+                ("arnoldi_fallback", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -88,6 +90,7 @@ def load(path=LIB_PATH):
     lib.hh_level_info.argtypes = [vp, ip, ctypes.POINTER(LevelStats)]
     lib.hh_apply.argtypes = [vp, ip, ip, vp, vp, vp]
     lib.hh_set_kernel_timing.argtypes = [vp, ip]
+    lib.hh_debug_set_spin_limit.argtypes = [vp, ip]
     fp = ctypes.POINTER(ctypes.c_float)
     lib.hh_cnn_create.argtypes = [ctypes.c_ulonglong, ctypes.POINTER(vp)]
     lib.hh_cnn_destroy.argtypes = [vp]
@@ -256,6 +259,10 @@ class Solver:
         n = ctypes.c_int()
         _check(load().hh_solver_captured(self._h, ctypes.byref(n)))
         return n.value
+
+    def debug_set_spin_limit(self, spins):
+        """Tests only: polls before a grid-exchange wait gives up (0: the default)."""
+        _check(load().hh_debug_set_spin_limit(self._h, int(spins)))
 
     def set_kernel_timing(self, cls):
         """0 off, 1 finest-level operator, 2 dense E^-1 product, 3 outer MGS kernels."""

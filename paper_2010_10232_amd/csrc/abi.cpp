@@ -425,9 +425,18 @@ hh_status hh_solver_captured(const hh_solver* s, int* n) {
 hh_status hh_set_kernel_timing(hh_solver* s, int cls) {
     HH_TRY
     if (!s) throw Err{HH_EINVAL, "NULL solver"};
-    if (cls < 0 || cls > 3) throw Err{HH_EINVAL, "timing class must be 0..3"};
+    if (cls < 0 || cls > 5) throw Err{HH_EINVAL, "timing class must be 0..5"};
     s->impl->o.time_kernels = cls;
     s->impl->drop_graphs();
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_debug_set_spin_limit(hh_solver* s, int spins) {
+    HH_TRY
+    if (!s) throw Err{HH_EINVAL, "NULL solver"};
+    if (spins < 0) throw Err{HH_EINVAL, "spins must be >= 0"};
+    s->impl->set_spin_limit(spins == 0 ? kSpinLimit : spins);
     return HH_OK;
     HH_CATCH
 }

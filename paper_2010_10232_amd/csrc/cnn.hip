@@ -680,6 +680,11 @@ void CnnImpl::step(int H, int Wd, const cx<TV>* r, const float* feat, const cx<T
                    int accumulate, hipStream_t s) {
     ensure(H, Wd);
     const long long N = (long long)H * Wd;
+    // r read twice (norm, network input), D^-1 and the feature once, x read
+    // (accumulate) and written; the network: 9 taps of complex channels
+    // 2 -> 16 -> 16 -> 16 -> 1 (a complex MAC counts 8) per pixel
+    meter((double)N * (3.0 * sizeof(cx<TV>) + 4.0 + (accumulate ? 2.0 : 1.0) * sizeof(cx<TV>)),
+          8.0 * 9.0 * (2 * 16 + 16 * 16 + 16 * 16 + 16 * 1) * (double)N + 16.0 * N);
     double* parts = scal.as<double>() + 8;   // kNormParts partial sums of ||r||^2
     const int np = (int)std::min<long long>(kNormParts, (N + 255) / 256);
     hipLaunchKernelGGL(norm2_parts_kernel<TV>, dim3(np), dim3(256), 0, s, N, r, parts);

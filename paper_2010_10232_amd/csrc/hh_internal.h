@@ -47,6 +47,29 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// Algorithmic traffic and arithmetic of the work a solve enqueues: every
+// launcher adds the bytes of its operands (each streamed once per kernel) and
+// its flops (a complex x real multiply-add counts 4) to the meter installed on
+// the calling thread, if any.  This is the model the whole-solve HBM fraction
+// is measured against.
+struct Meter {
+    double bytes = 0.0, flops = 0.0;
+};
+extern thread_local Meter* g_meter;
+inline void meter(double bytes, double flops) {
+    if (g_meter) {
+        g_meter->bytes += bytes;
+        g_meter->flops += flops;
+    }
+}
+struct MeterScope {
+    Meter* prev;
+    explicit MeterScope(Meter* m) : prev(g_meter) { g_meter = m; }
+    ~MeterScope() { g_meter = prev; }
+    MeterScope(const MeterScope&) = delete;
+    MeterScope& operator=(const MeterScope&) = delete;
+};
+
 // Device buffer with owning semantics.
 struct DevBuf {
     void* p = nullptr;
@@ -207,7 +230,11 @@ struct KrylovDev {
     int qcap;                   // 2m - 1 values per block (0 when not allocated)
     unsigned char* hstep;       // outer solve: device address of the pinned step slots (2 x 128 B), else null
     int m;
+    int spin_limit;             // polls before a grid-exchange wait gives up and sets ints[5]
 };
+
+// Polls of a grid-exchange wait before it gives up (about a second of sleeps).
+constexpr int kSpinLimit = 1 << 20;
 
 // Longest outer restart (Krylov basis length) the solver accepts.
 constexpr int kMaxRestart = 200;

@@ -199,11 +199,15 @@ static const void* prolong_fn(int w) {
     return (const void*)prolong_kernel<T, 0>;
 }
 
+thread_local Meter* g_meter = nullptr;
+
 template <class T>
 void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s, const cx<T>* dinv, T omega,
                      cx<T>* xs) {
     const long long Nc = (long long)t.nc1 * t.nc2;
     if (Nc <= 0) return;
+    meter(sizeof(cx<T>) * ((double)t.nf1 * t.nf2 + Nc * (dinv ? 3.0 : 1.0)),
+          4.0 * t.rw1 * t.rw2 * (double)Nc + (dinv ? 8.0 * Nc : 0.0));
     if (Nc > INT_MAX || (long long)t.nf1 * t.nf2 > INT_MAX) throw Err{HH_EINVAL, "level too large for a transfer"};
     void* args[] = {(void*)&t, (void*)&r, (void*)&c, (void*)&dinv, (void*)&omega, (void*)&xs};
     HH_HIP(hipLaunchKernel(restrict_fn<T>(std::max(t.rw1, t.rw2)), dim3(grid1d(Nc, 256)), dim3(256), args, 0, s));
@@ -212,6 +216,8 @@ template <class T>
 void launch_prolong_add(const Transfer& t, const cx<T>* e, const cx<T>* xin, cx<T>* xout, hipStream_t s) {
     const long long Nf = (long long)t.nf1 * t.nf2;
     if (Nf <= 0) return;
+    meter(sizeof(cx<T>) * ((double)t.nc1 * t.nc2 + Nf * (xin ? 2.0 : 1.0)),
+          4.0 * t.pw1 * t.pw2 * (double)Nf + (xin ? 2.0 * Nf : 0.0));
     if (Nf > INT_MAX || (long long)t.nc1 * t.nc2 > INT_MAX) throw Err{HH_EINVAL, "level too large for a transfer"};
     void* args[] = {(void*)&t, (void*)&e, (void*)&xin, (void*)&xout};
     HH_HIP(hipLaunchKernel(prolong_fn<T>(std::max(t.pw1, t.pw2)), dim3(grid1d(Nf, 256)), dim3(256), args, 0, s));
@@ -241,6 +247,7 @@ __global__ void jacobi0_kernel(long long N, const cx<T>* dinv, T omega, const cx
 }
 template <class T>
 void launch_jacobi0(long long N, const cx<T>* dinv, T omega, const cx<T>* b, cx<T>* x, hipStream_t s) {
+    meter(3.0 * sizeof(cx<T>) * N, 8.0 * N);
     hipLaunchKernelGGL(jacobi0_kernel<T>, dim3(grid1d(N, 256)), dim3(256), 0, s, N, dinv, omega, b, x);
 }
 template void launch_jacobi0<double>(long long, const cx<double>*, double, const cx<double>*, cx<double>*, hipStream_t);
@@ -255,6 +262,7 @@ __global__ void axpy_kernel(long long N, const cx<T>* x, cx<T>* y) {
 }
 template <class T>
 void launch_axpy(long long N, const cx<T>* x, cx<T>* y, hipStream_t s) {
+    meter(3.0 * sizeof(cx<T>) * N, 2.0 * N);
     hipLaunchKernelGGL(axpy_kernel<T>, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y);
 }
 template void launch_axpy<double>(long long, const cx<double>*, cx<double>*, hipStream_t);
@@ -267,6 +275,7 @@ __global__ void add_kernel(long long N, const cx<double>* a, const cx<double>* b
     y[i] = {u.re + v.re, u.im + v.im};
 }
 void launch_add(long long N, const cx<double>* a, const cx<double>* b, cx<double>* y, hipStream_t s) {
+    meter(48.0 * N, 2.0 * N);
     hipLaunchKernelGGL(add_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, a, b, y);
 }
 
@@ -275,6 +284,7 @@ __global__ void copy_kernel(long long N, const cx<double>* x, cx<double>* y) {
     if (i < N) y[i] = x[i];
 }
 void launch_copy(long long N, const cx<double>* x, cx<double>* y, hipStream_t s) {
+    meter(32.0 * N, 0.0);
     hipLaunchKernelGGL(copy_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y);
 }
 __global__ void zero_kernel(long long N, cx<double>* y) {
@@ -282,6 +292,7 @@ __global__ void zero_kernel(long long N, cx<double>* y) {
     if (i < N) y[i] = {0.0, 0.0};
 }
 void launch_zero(long long N, cx<double>* y, hipStream_t s) {
+    meter(16.0 * N, 0.0);
     hipLaunchKernelGGL(zero_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, y);
 }
 
@@ -294,9 +305,11 @@ __global__ void cast_f2d_kernel(long long N, const cx<float>* x, cx<double>* y) 
     if (i < N) y[i] = {(double)x[i].re, (double)x[i].im};
 }
 void launch_cast_d2f(long long N, const cx<double>* x, cx<float>* y, hipStream_t s) {
+    meter(24.0 * N, 0.0);
     hipLaunchKernelGGL(cast_d2f_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y);
 }
 void launch_cast_f2d(long long N, const cx<float>* x, cx<double>* y, hipStream_t s) {
+    meter(24.0 * N, 0.0);
     hipLaunchKernelGGL(cast_f2d_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y);
 }
 __global__ void cast_f2d_add_kernel(long long N, const cx<float>* x, const cx<double>* q, cx<double>* y) {
@@ -304,6 +317,7 @@ __global__ void cast_f2d_add_kernel(long long N, const cx<float>* x, const cx<do
     if (i < N) y[i] = {(double)x[i].re + q[i].re, (double)x[i].im + q[i].im};
 }
 void launch_cast_f2d_add(long long N, const cx<float>* x, const cx<double>* q, cx<double>* y, hipStream_t s) {
+    meter(40.0 * N, 2.0 * N);
     hipLaunchKernelGGL(cast_f2d_add_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, q, y);
 }
 
@@ -390,9 +404,11 @@ __global__ __launch_bounds__(256) void gemv4_kernel(int n, long long ld, const d
 
 template <class TM, class TV>
 void launch_gemv(int n, const TM* A, const cx<TV>* x, cx<TV>* y, hipStream_t s) {
+    meter((double)sizeof(TM) * n * n + 2.0 * sizeof(cx<TV>) * n, 8.0 * n * (double)n);
     hipLaunchKernelGGL((gemv_kernel<TM, TV>), dim3((n + 3) / 4), dim3(256), 0, s, n, (long long)n, A, x, y);
 }
 void launch_gemv_real(int n, long long ld, const double* A, const cx<double>* x, cx<double>* y, hipStream_t s) {
+    meter(8.0 * n * (double)n + 32.0 * n, 4.0 * n * (double)n);
     if (n >= 1024 && ld % 2 == 0) {
         const long long rows_per_block = 4LL * GEMV_RPW;
         hipLaunchKernelGGL(gemv4_kernel, dim3((unsigned)((n + rows_per_block - 1) / rows_per_block)), dim3(256), 0,
@@ -580,6 +596,8 @@ __global__ __launch_bounds__(FDM2_TB) void fdm_pass_kernel(int n2, int n1, const
 
 void launch_fdm_solve(int n2, int n1, const double* Vx, const double* VxT, const double* Vy, const double* dinv,
                       const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s) {
+    meter(40.0 * n1 * (double)n2 + 8.0 * ((double)n1 * n1 + (double)n2 * n2),
+          8.0 * n1 * (double)n2 * (n1 + n2) + 8.0 * n1 * (double)n2);
     if (n1 <= FDM2_NMAX && n2 <= FDM2_NMAX) {
         const dim3 g((unsigned)((n2 + FDM2_RB - 1) / FDM2_RB)), b(FDM2_TB);
         // T2 = (Vy^T C Vx) ./ D
@@ -1109,6 +1127,7 @@ __global__ __launch_bounds__(SYT * SYR_G) void symv_reduce_kernel(int n, const c
 void launch_symv(int n, const double* P, const cx<double>* x, cx<double>* rowpart, cx<double>* colpart,
                  cx<double>* y, hipStream_t s) {
     const unsigned nt = (unsigned)((n + SYT - 1) / SYT);
+    meter(8.0 * SYM_STRIDE * (double)sym_tiles(n) + 32.0 * n, 4.0 * n * (double)n);
     hipLaunchKernelGGL(symv_tiles_kernel, dim3((unsigned)sym_tiles(n)), dim3(256), 0, s, n, P, x, rowpart, colpart);
     hipLaunchKernelGGL(symv_reduce_kernel, dim3(nt), dim3(SYT * SYR_G), 0, s, n, rowpart, colpart, y);
 }
@@ -1512,7 +1531,7 @@ __device__ __forceinline__ cx<double> exchange_sum(double tr, double ti, unsigne
                 q3 = __hip_atomic_load(w + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if ((unsigned)q0 == tag && (unsigned)q1 == tag && (unsigned)q2 == tag && (unsigned)q3 == tag) break;
                 __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1 << 20)) {
+                if (++spins > k.spin_limit) {
                     atomicExch(&k.ints[5], 1);
                     break;
                 }
@@ -1886,7 +1905,7 @@ __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, 
                 }
             if (!todo) break;
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > (1 << 20)) {
+            if (++spins > k.spin_limit) {
                 atomicExch(&k.ints[5], 1);
                 break;
             }
@@ -2095,6 +2114,7 @@ __global__ __launch_bounds__(RB) void norm2_kernel(long long N, const cx<double>
 
 void launch_dot_norm2(long long N, const cx<double>* x, double* out, int* counter, cx<double>* partials,
                       hipStream_t s) {
+    meter(16.0 * N, 4.0 * N);
     hipLaunchKernelGGL(norm2_kernel, dim3(reduction_blocks(N)), dim3(RB), 0, s, N, x, out, counter, partials);
 }
 
@@ -2128,6 +2148,7 @@ __global__ void scale_by_kernel(long long N, const cx<double>* x, cx<double>* y,
     y[i] = {v.re / d, v.im / d};
 }
 void launch_scale_by(long long N, const cx<double>* x, cx<double>* y, const double* by, hipStream_t s) {
+    meter(32.0 * N, 2.0 * N);
     hipLaunchKernelGGL(scale_by_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, x, y, by);
 }
 
@@ -2210,6 +2231,8 @@ __global__ void update_kernel(long long N, const cx<double>* __restrict__ Z, lon
 }
 void launch_update(long long N, const cx<double>* Z, long long ldz, KrylovDev& k, cx<double>* u, int accumulate,
                    hipStream_t s, int ncols) {
+    const double n = ncols >= 0 ? ncols : k.m;
+    meter(16.0 * N * (n + (accumulate ? 2.0 : 1.0)), 8.0 * N * n);
     hipLaunchKernelGGL(update_kernel, dim3(grid1d(N, 256)), dim3(256), 0, s, N, Z, ldz, k, u, accumulate, ncols);
 }
 

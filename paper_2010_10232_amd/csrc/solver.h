@@ -59,6 +59,9 @@ struct SolveRun {
     int iters = 0, cycles = 0, j = 0, m = 0, status = 0;
     bool ahead = false;             // Arnoldi step j + 1 is already enqueued
     hipEvent_t waiting = nullptr;   // completes when the scalars step() reads are on the host
+    bool exchange_timeout = false;  // the error thrown was a grid-exchange timeout
+    Meter meter;                    // algorithmic bytes / flops of the work this solve used
+    double step_bytes[2] = {0, 0}, step_flops[2] = {0, 0};   // per Arnoldi-step slot
     hh_solve_info inf{};
     std::chrono::steady_clock::time_point t0;
     void start(SolverImpl* S, const cx<double>* f, cx<double>* u, int use_u0, hipStream_t s);
@@ -141,11 +144,16 @@ struct SolverImpl {
     // true when the step's kernel stored the host's scalars in the pinned slot itself
     bool arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s);
     bool allow_coop = true;
+    // set after a grid-exchange timeout: Arnoldi steps use the per-projection
+    // kernels (no wait on other workgroups) from then on
+    bool grid_arnoldi_off = false;
+    void set_spin_limit(int spins);
     // batched mode: Arnoldi step j (T, operator, MGS, scalar copies) captured
     // once into a HIP graph and replayed (no timing, learned smoother or sample
     // capture in that mode; the graphs bake in this solver's buffers)
     bool use_graphs = false;
     std::vector<hipGraphExec_t> step_graphs;
+    std::vector<Meter> step_graph_meter;   // what each captured step meters when replayed
     void drop_graphs();
     bool graphs_allowed() const { return !allow_coop && o.time_kernels == 0 && cnn == nullptr && cap_buf == nullptr; }
     // learned fine-level smoother (null: damped Jacobi everywhere)

@@ -115,6 +115,7 @@ static void fill_krylov(KrylovDev& k, DevBuf& blob, int m) {
     blob.alloc(bytes + 256);
     char* p = blob.as<char>();
     k.m = m;
+    k.spin_limit = kSpinLimit;
     k.H = (cx<double>*)p;
     p += 16 * nH;
     k.sn = (cx<double>*)p;
@@ -151,6 +152,7 @@ void SolverImpl::drop_graphs() {
     for (hipGraphExec_t g : step_graphs)
         if (g) (void)hipGraphExecDestroy(g);
     step_graphs.clear();
+    step_graph_meter.clear();
 }
 
 SolverImpl::~SolverImpl() {
@@ -831,17 +833,34 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
     a.yadd = mode == MODE_SMOOTH ? yadd : nullptr;
     a.ty = sizeof(T) == 8 ? lv.ty64 : lv.ty32;
     const int py = prob->dim == 2 ? prob->p : 0;
-    if (l == 0) tstart(1, s);
-    launch_op<T>(lv.kind, mode, prob->p, py, a, s);
-    if (l == 0) {
-        // algorithmic bytes: x in, y out, b (residual and smoothing) and D^-1
-        // (smoothing) in, plus the k^2 field of a non-constant wave number
-        const double v = (double)lv.N * 2 * sizeof(T);
+    double st_bytes = 0.0;
+    {
+        // operands once: x, y, b (residual / sweep), D^-1 (sweep), the first-sweep
+        // and added vectors, and the mass coefficients: the stored stencil or
+        // k^2 per finest element
+        const int p = prob->p, bx = 2 * p + 1, by = py ? 2 * py + 1 : 1;
+        const double v = (double)lv.N * sizeof(cx<T>);
         double bytes = 2 * v + (mode != MODE_APPLY ? v : 0.0) + (mode == MODE_SMOOTH || xo ? v : 0.0) +
                        (xo ? v : 0.0) + (a.yadd ? v : 0.0);
-        if (lv.kind == KIND_VARFINE) bytes += 8.0 * lv.ax.nel * lv.ay.nel;
-        tstop(1, bytes, s);
+        double macs = 2.0 * bx * by + 2.0 * by;
+        if (lv.kind == KIND_STENCIL) {
+            bytes += (double)lv.N * bx * by * sizeof(T);
+            macs += bx * by;
+        } else if (lv.kind == KIND_VARFINE) {
+            bytes += 8.0 * (double)lv.ax.nel * lv.ay.nel;
+            macs += (py + 1) * (2.0 * (p + 1) * (p + 1) + (p + 1) * bx);
+        }
+        meter(bytes, 4.0 * macs * lv.N + (mode == MODE_SMOOTH ? 10.0 : 2.0) * lv.N);
+        st_bytes = bytes;
     }
+    // timing class 4: the tiled stored-stencil kernel (coarse variable-k levels
+    // above the one-thread-per-unknown bound)
+    const bool st_kernel = lv.kind == KIND_STENCIL && py > 0 && lv.N > kOpDirectMax;
+    if (st_kernel) tstart(4, s);
+    if (l == 0) tstart(1, s);
+    launch_op<T>(lv.kind, mode, prob->p, py, a, s);
+    if (l == 0) tstop(1, st_bytes, s);
+    if (st_kernel) tstop(4, st_bytes, s);
 }
 
 template <class T>
@@ -853,6 +872,15 @@ bool SolverImpl::vcycle_once(int l, const cx<T>* b, cx<T>* x, hipStream_t s, boo
         return false;
     }
     if (l >= tail_start) {
+        // the tail reads b and its coefficient tables once and writes x; its
+        // levels live in LDS.  Flops: residual, two sweeps and transfers per level.
+        {
+            double fl = 0.0;
+            const int p = prob->p, bx = 2 * p + 1, by = prob->dim == 2 ? bx : 1;
+            for (int q = l; q <= L; ++q)
+                fl += (q == L ? 8.0 * (double)nL * nL : 3.0 * 4.0 * (2.0 * bx * by + 2.0 * by) * lev[q]->N);
+            meter(2.0 * sizeof(cx<T>) * lv.N + (double)tail_img.bytes + (double)nL * nL * sizeof(cx<T>), fl);
+        }
         launch_vcycle_tail<T>(pick<T>(tail64, tail32).template as<TailDesc<T>>(), tail_img.p,
                               (int)(tail_img.bytes / 16), pick<T>(Minv64, Minv32).template as<cx<T>>(), tail_P, l,
                               sizeof(T) == 8 ? tail_lds : tail_lds32, b, x, s);
@@ -985,11 +1013,15 @@ void SolverImpl::T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t 
 // side by side) one kernel per Gram-Schmidt projection followed by the
 // norm/Givens kernel and the scaling.
 bool SolverImpl::arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s) {
+    // MGS step j: v_0..v_j read once, w read and written once; j + 1 dots and
+    // axpys, the norm and the scaling
+    meter(16.0 * (j + 3) * N, 16.0 * (j + 1) * N + 6.0 * N);
+    MeterScope quiet(nullptr);
     if (N <= kSmallArnoldi) {
         launch_arnoldi_small(N, j, w, Vb, N, k, s);
         return k.hstep != nullptr;
     }
-    if (launch_arnoldi_grid(N, j, w, Vb, N, k, s, allow_coop ? 4 : 16, allow_coop, o.ortho == 0))
+    if (!grid_arnoldi_off && launch_arnoldi_grid(N, j, w, Vb, N, k, s, allow_coop ? 4 : 16, allow_coop, o.ortho == 0))
         return k.hstep != nullptr;
     for (int i = 0; i <= j; ++i) launch_mgs(N, i, j, w, Vb, N, k, s);
     launch_norm_givens(N, j, w, Vb, N, k, s);
@@ -1009,13 +1041,20 @@ void SolverImpl::substruct_pass(const cx<double>* c, cx<double>* e, hipStream_t 
     cx<double>* xhat = E.xhat.as<cx<double>>();
     cx<double>* xt = E.xt.as<cx<double>>();
     cx<double>* rv = E.rvec.as<cx<double>>();
-    launch_symv_batch(E.subMats.as<SymMat>(), E.nsub, E.sub_tiles, E.sub_rows, E.subP.as<double>(), mp, c, rp, cp,
-                      xhat, nullptr, s);
+    // the tile launches are timing class 5 (the kernel that streams the stored factors)
+    auto tiles = [&](const DevBuf& mats, int nmat, long long nt, int rows, const DevBuf& P, const cx<double>* x) {
+        tstart(5, s);
+        launch_symv_batch_tiles(mats.as<SymMat>(), nmat, nt, rows, P.as<double>(), mp, x, rp, cp, s);
+        tstop(5, symv_batch_tile_bytes(nt), s);
+    };
+    tiles(E.subMats, E.nsub, E.sub_tiles, E.sub_rows, E.subP, c);
+    launch_symv_batch_reduce(E.subMats.as<SymMat>(), E.nsub, E.sub_rows, mp, rp, cp, xhat, nullptr, s);
     op<double>(Lz, MODE_RESID, false, xhat, c, rv, s);
-    launch_symv_batch(E.SMats.as<SymMat>(), 1, E.S_tiles, E.S_rows, E.SP.as<double>(), mp, rv, rp, cp, e, xt, s);
+    tiles(E.SMats, 1, E.S_tiles, E.S_rows, E.SP, rv);
+    launch_symv_batch_reduce(E.SMats.as<SymMat>(), 1, E.S_rows, mp, rp, cp, e, xt, s);
     op<double>(Lz, MODE_RESID, false, xt, c, rv, s);
-    launch_symv_batch(E.subMats.as<SymMat>(), E.nsub, E.sub_tiles, E.sub_rows, E.subP.as<double>(), mp, rv, rp, cp,
-                      e, nullptr, s);
+    tiles(E.subMats, E.nsub, E.sub_tiles, E.sub_rows, E.subP, rv);
+    launch_symv_batch_reduce(E.subMats.as<SymMat>(), E.nsub, E.sub_rows, mp, rp, cp, e, nullptr, s);
 }
 
 // One pass, then sub->refine steps of iterative refinement e += pass(c - E e).
@@ -1132,6 +1171,8 @@ void SolveRun::start(SolverImpl* S_, const cx<double>* f_, cx<double>* u_, int u
     S->ev_used = 0;
     S->ev_bytes = 0.0;
     S->ev_pending = -1;
+    meter = Meter{};
+    MeterScope ms(&meter);
     iters = cycles = j = m = 0;
     ahead = false;
     nf = stop = rn = gabs = 0.0;
@@ -1139,6 +1180,11 @@ void SolveRun::start(SolverImpl* S_, const cx<double>* f_, cx<double>* u_, int u
     inf = hh_solve_info{};
     KrylovDev& kd = S->kd;
     const long long N = S->lev[0]->N;
+    // a grid-exchange timeout of an earlier solve is reported there: this
+    // solve starts with the flags of its Krylov states clear
+    HH_HIP(hipMemsetAsync(&kd.ints[5], 0, sizeof(int), s));
+    for (int l = 1; l < S->Lz; ++l)
+        if (S->lev[l]->m_inner > 0) HH_HIP(hipMemsetAsync(&S->lev[l]->kd.ints[5], 0, sizeof(int), s));
     launch_dot_norm2(N, f, &kd.scal[3], &kd.ints[2], kd.partials, s);
     HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     mark(S->ev_misc);
@@ -1154,6 +1200,7 @@ void SolveRun::enqueue_cycle_start() {
 }
 
 void SolveRun::enqueue_step(int jj) {
+    const Meter before = meter;
     KrylovDev& kd = S->kd;
     const long long N = S->lev[0]->N;
     cx<double>* Vb = S->V.as<cx<double>>();
@@ -1178,8 +1225,13 @@ void SolveRun::enqueue_step(int jj) {
                                   hipMemcpyDeviceToHost, s));
     };
     if (S->use_graphs && S->graphs_allowed()) {
-        if ((int)S->step_graphs.size() <= jj) S->step_graphs.resize(jj + 1, nullptr);
+        if ((int)S->step_graphs.size() <= jj) {
+            S->step_graphs.resize(jj + 1, nullptr);
+            S->step_graph_meter.resize(jj + 1);
+        }
         if (!S->step_graphs[jj]) {
+            Meter cap;
+            MeterScope ms(&cap);
             hipGraph_t g = nullptr;
             HH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             try {
@@ -1195,18 +1247,25 @@ void SolveRun::enqueue_step(int jj) {
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) throw Err{HH_EHIP, std::string("graph instantiation: ") + hipGetErrorString(e)};
             S->step_graphs[jj] = ge;
+            S->step_graph_meter[jj] = cap;
         }
         HH_HIP(hipGraphLaunch(S->step_graphs[jj], s));
+        hh::meter(S->step_graph_meter[jj].bytes, S->step_graph_meter[jj].flops);
     } else {
         body();
     }
     HH_HIP(hipEventRecord(S->ev_slot[slot], s));
+    step_bytes[slot] = meter.bytes - before.bytes;
+    step_flops[slot] = meter.flops - before.flops;
 }
 
 void SolveRun::enqueue_final() {
     KrylovDev& kd = S->kd;
     for (int l = 1; l < S->Lz && l < 16; ++l)
         HH_HIP(hipMemcpyAsync(&S->pin_i[32 + l], &S->lev[l]->kd.ints[5], sizeof(int), hipMemcpyDeviceToHost, s));
+    // the outer flag once more after the last step: a block that timed out in
+    // the step's last exchange sets it after block 0 has published the step
+    HH_HIP(hipMemcpyAsync(&S->pin_i[31], &kd.ints[5], sizeof(int), hipMemcpyDeviceToHost, s));
     launch_dot_norm2(S->lev[0]->N, S->r.as<cx<double>>(), &kd.scal[3], &kd.ints[2], kd.partials, s);
     HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     mark(S->ev_misc);
@@ -1214,6 +1273,7 @@ void SolveRun::enqueue_final() {
 }
 
 void SolveRun::step() {
+    MeterScope ms(&meter);
     const long long N = S->lev[0]->N;
     const hh_solver_opts& o = S->o;
     cx<double>* rr = S->r.as<cx<double>>();
@@ -1263,11 +1323,19 @@ void SolveRun::step() {
             const int* pi = (const int*)(S->pin_step + 128 * slot + 8 * sizeof(double));
             gabs = pd[2];
             ++iters;
-            if (pi[5]) throw Err{HH_EHIP, "grid barrier of the Arnoldi kernel timed out"};
+            if (pi[5]) {
+                exchange_timeout = true;
+                throw Err{HH_EHIP, "grid barrier of the Arnoldi kernel timed out"};
+            }
             if (!std::isfinite(gabs)) throw Err{HH_ENUMERIC, "Arnoldi recurrence produced NaN/Inf"};
             if (pi[1] || gabs <= stop || j + 1 >= m) {
                 // end of the cycle: least squares, update, true residual on the
-                // first j + 1 columns
+                // first j + 1 columns.  The step enqueued ahead (j + 1) is not
+                // part of the method's work: its metered traffic is taken back.
+                if (ahead) {
+                    meter.bytes -= step_bytes[(j + 1) & 1];
+                    meter.flops -= step_flops[(j + 1) & 1];
+                }
                 launch_lsq(kd, s, j + 1);
                 launch_update(N, S->Z.as<cx<double>>(), N, kd, u, 1, s, j + 1);
                 S->op<double>(0, MODE_RESID, false, u, f, rr, s);
@@ -1284,8 +1352,9 @@ void SolveRun::step() {
             return;
         }
         case P_FINAL: {
-            for (int l = 1; l < S->Lz && l < 16; ++l)
-                if (S->pin_i[32 + l]) throw Err{HH_EHIP, "grid barrier of an inner Arnoldi kernel timed out"};
+            exchange_timeout = S->pin_i[31] != 0;
+            for (int l = 1; l < S->Lz && l < 16; ++l) exchange_timeout = exchange_timeout || S->pin_i[32 + l] != 0;
+            if (exchange_timeout) throw Err{HH_EHIP, "grid barrier of an Arnoldi kernel timed out"};
             const double rtrue = std::sqrt(S->pin_d[3]);
             auto t1 = std::chrono::steady_clock::now();
             inf.iters = iters;
@@ -1298,6 +1367,8 @@ void SolveRun::step() {
             inf.op_ms_total = S->tcollect(&cnt);
             inf.op_launches = cnt;
             inf.op_bytes_per_launch = cnt ? S->ev_bytes / cnt : 0.0;
+            inf.model_bytes = meter.bytes;
+            inf.model_flops = meter.flops;
             status = inf.converged ? HH_OK : HH_ENOCONV;
             waiting = nullptr;
             phase = P_DONE;
@@ -1308,17 +1379,39 @@ void SolveRun::step() {
     }
 }
 
+// A grid-exchange timeout of the resident or cooperative Arnoldi kernels (the
+// grid was not all resident, e.g. other streams held the CUs) ends the solve
+// with HH_EHIP; from a zero initial guess the solve is then run once more with
+// the per-projection kernels, which wait on no other workgroup.
 int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s) {
-    SolveRun run;
-    run.start(this, f, u, use_u0, s);
-    while (run.phase != SolveRun::P_DONE) {
-        HH_HIP(hipEventSynchronize(run.waiting));
-        run.step();
+    for (int attempt = 0;; ++attempt) {
+        SolveRun run;
+        try {
+            run.start(this, f, u, use_u0, s);
+            while (run.phase != SolveRun::P_DONE) {
+                HH_HIP(hipEventSynchronize(run.waiting));
+                run.step();
+            }
+            HH_HIP(hipStreamSynchronize(s));
+        } catch (const Err&) {
+            if (!(run.exchange_timeout && attempt == 0 && !use_u0 && !grid_arnoldi_off)) throw;
+            HH_HIP(hipStreamSynchronize(s));
+            grid_arnoldi_off = true;
+            drop_graphs();
+            continue;
+        }
+        run.inf.status = run.status;
+        run.inf.arnoldi_fallback = attempt;
+        if (info) *info = run.inf;
+        return run.status;
     }
-    HH_HIP(hipStreamSynchronize(s));
-    run.inf.status = run.status;
-    if (info) *info = run.inf;
-    return run.status;
+}
+
+void SolverImpl::set_spin_limit(int spins) {
+    kd.spin_limit = spins;
+    for (auto& lv : lev) lv->kd.spin_limit = spins;
+    grid_arnoldi_off = false;
+    drop_graphs();
 }
 
 template void SolverImpl::op<double>(int, int, bool, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t,

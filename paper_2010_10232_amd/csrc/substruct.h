@@ -19,11 +19,18 @@ struct SymMat {
     int map0;     // first entry of its index map
 };
 
-// y[map[..]] = A x[map[..]] for every matrix of the batch (also y2 if set).
-// rowpart / colpart: tiles x 128 complex partial sums.
-void launch_symv_batch(const SymMat* mats_dev, int nmat, long long tiles, int rows, const double* P,
-                       const int* map, const cx<double>* x, cx<double>* rowpart, cx<double>* colpart,
-                       cx<double>* y, cx<double>* y2, hipStream_t s);
+// y[map[..]] = A x[map[..]] for every matrix of the batch (also y2 if set), in
+// two launches: the tile products (partial sums per tile, rowpart / colpart:
+// tiles x 128 complex) and their reduction per tile row.
+void launch_symv_batch_tiles(const SymMat* mats_dev, int nmat, long long tiles, int rows, const double* P,
+                             const int* map, const cx<double>* x, cx<double>* rowpart, cx<double>* colpart,
+                             hipStream_t s);
+void launch_symv_batch_reduce(const SymMat* mats_dev, int nmat, int rows, const int* map,
+                              const cx<double>* rowpart, const cx<double>* colpart, cx<double>* y, cx<double>* y2,
+                              hipStream_t s);
+// algorithmic bytes of one tile launch (every stored tile once, its partial
+// sums written, the mapped inputs)
+double symv_batch_tile_bytes(long long tiles);
 
 // Cuts tried at set-up (cheapest first) until one passes the check; refinement
 // steps allowed for the best one.

@@ -236,11 +236,23 @@ void roc_check(rocblas_status st, const char* what) {
 
 }  // namespace
 
-void launch_symv_batch(const SymMat* mats_dev, int nmat, long long tiles, int rows, const double* P, const int* map,
-                       const cx<double>* x, cx<double>* rowpart, cx<double>* colpart, cx<double>* y, cx<double>* y2,
-                       hipStream_t s) {
+double symv_batch_tile_bytes(long long tiles) {
+    return 8.0 * TSTRIDE * tiles + 2.0 * 16.0 * T128 * tiles + 2.0 * 16.0 * T128 * tiles;
+}
+
+void launch_symv_batch_tiles(const SymMat* mats_dev, int nmat, long long tiles, int rows, const double* P,
+                             const int* map, const cx<double>* x, cx<double>* rowpart, cx<double>* colpart,
+                             hipStream_t s) {
+    meter(symv_batch_tile_bytes(tiles), 8.0 * TSTRIDE * tiles);
     hipLaunchKernelGGL(symvb_tiles_kernel, dim3((unsigned)tiles), dim3(256), 0, s, mats_dev, nmat, P, map, x, rowpart,
                        colpart);
+}
+
+void launch_symv_batch_reduce(const SymMat* mats_dev, int nmat, int rows, const int* map,
+                              const cx<double>* rowpart, const cx<double>* colpart, cx<double>* y, cx<double>* y2,
+                              hipStream_t s) {
+    // the partial sums of every tile row read back, the outputs written
+    meter(2.0 * 16.0 * T128 * (double)rows * 8 + 16.0 * T128 * rows, 0.0);
     hipLaunchKernelGGL(symvb_reduce_kernel, dim3((unsigned)rows), dim3(T128 * RG), 0, s, mats_dev, nmat, map,
                        rowpart, colpart, y, y2);
 }

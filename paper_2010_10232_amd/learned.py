@@ -38,6 +38,19 @@ def training_specs(n_problems=4, p=4, kh_max=0.625, kbar_range=(100.0 / 0.7, 500
     return specs
 
 
+def field_specs(n_el, p, n_problems=2, kbar_range=(100.0 / 0.7, 500.0 / 1.3), seed=11):
+    """Training problems on the application's own grid: seeded random fields
+    k = kbar (1 + 0.3 g) with kbar ~ U[kbar_range] (k within [100, 500]), field
+    seeds 1000 + i (the workloads' own field is seed 0) and sources ~ U(0.3, 0.7)^2."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(n_problems):
+        kbar = float(rng.uniform(*kbar_range))
+        x0 = tuple(float(v) for v in rng.uniform(0.3, 0.7, size=2))
+        specs.append(dict(p=p, n_el=n_el, kbar=kbar, k_elem=W.grf_k(n_el, kbar=kbar, seed=1000 + i), x0=x0))
+    return specs
+
+
 def capture(specs, per_problem=24, maxit=60, solver_opts=None, log=None):
     """Plain solves of the training problems; returns [(problem, solver, samples)]
     with samples a device tensor [n, N] of finest-level V-cycle inputs.  A spec

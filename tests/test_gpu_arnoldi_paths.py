@@ -93,3 +93,36 @@ def test_one_reduction_arnoldi_matches_mgs(p, n_el, k, extra, bounds, label):
     _say(f"[one-reduction] {label}: one sum per step")
     u0, i0 = B.Solver(prob, ortho=0, **opts).solve(f)
     _compare(f"[one-reduction] {label}", u0, i0, u1, i1, bounds)
+
+
+def test_exchange_timeout_falls_back_and_recovers():
+    """A grid-exchange wait that gives up (forced from the host with a spin limit
+    of one poll, so every kernel still exits through its bounded wait) is
+    reported, and a solve from zero is redone with the per-projection kernels:
+    same iterations and iterates as the grid form up to rounding.  Restoring the
+    limit brings back the grid kernels: bit-identical to a fresh solver."""
+    import torch
+
+    from paper_2010_10232_amd import binding as B
+    # N = 4,225 > 4,096: the grid Arnoldi kernel; two-level deflation with an
+    # exact E^-1, so the preconditioner is linear
+    prob = B.Problem(2, 3, 64, k=20.0)
+    f = prob.point_source((0.45, 0.55))
+    ref = B.Solver(prob, defl_mode=1)
+    u_ref, i_ref = ref.solve(f)
+    assert i_ref["converged"] == 1 and i_ref["arnoldi_fallback"] == 0
+    s = B.Solver(prob, defl_mode=1)
+    s.debug_set_spin_limit(1)
+    _say("[timeout] solve with a one-poll spin limit")
+    u1, i1 = s.solve(f)
+    assert i1["arnoldi_fallback"] == 1 and i1["converged"] == 1
+    _compare("fallback vs grid", u1, i1, u_ref, i_ref, LINEAR)
+    # from a nonzero initial guess the timeout is reported, not retried
+    s.debug_set_spin_limit(1)
+    with pytest.raises(B.HHError) as ei:
+        s.solve(f, u=torch.zeros_like(f), use_u0=True)
+    assert ei.value.code == B.HH_EHIP and "timed out" in str(ei.value)
+    s.debug_set_spin_limit(0)
+    u2, i2 = s.solve(f)
+    assert i2["arnoldi_fallback"] == 0 and i2["iters"] == i_ref["iters"]
+    assert torch.equal(u2, u_ref)

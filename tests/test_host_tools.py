@@ -154,3 +154,15 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout.strip() == ""
+
+
+def test_field_specs_span_k_100_500_on_the_application_grid():
+    from paper_2010_10232_amd import workloads as W
+    specs = learned.field_specs(48, 4, n_problems=3)
+    test_field = W.grf_k(48, kbar=300.0, seed=0)
+    for s in specs:
+        k = s["k_elem"]
+        assert s["n_el"] == 48 and s["p"] == 4 and k.shape == (48, 48)
+        assert k.min() >= 100.0 - 1e-9 and k.max() <= 500.0 + 1e-9
+        assert not np.array_equal(k / s["kbar"], test_field / 300.0)
+        assert all(0.3 <= v <= 0.7 for v in s["x0"])
