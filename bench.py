@@ -111,18 +111,18 @@ def cpu_baseline(w, seconds_cap=20.0):
         t0 = time.perf_counter()
         op = hz.Problem(w["dim"], w["p"], w["n_el"], w.get("k", 1.0), k_elem=k_field(w))
         f = hz.point_source_rhs(op, w["x0"])
+        s = osv.Solver(op, osv.Options(maxit=1, **w["opts"]))
+        t_setup = time.perf_counter() - t0
 
         def run(maxit):
-            s = osv.Solver(op, osv.Options(maxit=maxit, **w["opts"]))
+            s.opts.maxit = maxit
             t1 = time.perf_counter()
             _, info = s.solve(f)
-            return s, info, time.perf_counter() - t1
+            return info, time.perf_counter() - t1
 
-        s, info, dt = run(1)
-        t_setup = time.perf_counter() - t0 - dt
+        info, dt = run(1)
         if dt < seconds_cap / 2:
-            more = max(2, min(int(seconds_cap / max(dt, 1e-6)), 200))
-            s, info, dt = run(more)
+            info, dt = run(max(2, min(int(seconds_cap / max(dt, 1e-6)), 200)))
     N = s.levels[0].N
     return {"value": N * info.iters / dt, "unit": "DoF-iter/s", "cores": 1, "kind": "oracle",
             "sample": f"{info.iters} outer FGMRES iteration(s) of the same solve from zero "
@@ -329,11 +329,22 @@ def main():
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (PMC traffic calibration)")
     ap.add_argument("--plain-only", action="store_true", help="time the plain FP64 form only (profiling runs)")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="print the CPU oracle baseline of the workload as JSON and exit (no GPU use)")
     ARGS = args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(WORKLOADS[args.workload])), flush=True)
+        return
+    # the CPU oracle runs in a child process (CPU only) while the GPU is measured
+    baseline_proc = None
+    if not args.no_cpu_baseline and "batch" not in WORKLOADS[args.workload]:
+        import subprocess
+        baseline_proc = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--workload", args.workload,
+                                          "--cpu-baseline-only"], stdout=subprocess.PIPE, text=True)
 
     import torch
 
@@ -403,8 +414,13 @@ def main():
         "roofline": roof,
         "forms": forms,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+    if baseline_proc is not None:
+        log("[bench] waiting for the CPU oracle baseline")
+        txt, _ = baseline_proc.communicate()
+        try:
+            out["cpu_baseline"] = json.loads(txt.strip().splitlines()[-1])
+        except (ValueError, IndexError):
+            out["cpu_baseline"] = {"error": f"oracle baseline process ended with status {baseline_proc.returncode}"}
     print(json.dumps(out), flush=True)
 
 

@@ -28,14 +28,15 @@ import subprocess
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
-def source_hash():
-    """sha256 over the library sources (name and contents, sorted by name)."""
+def source_hash(files=None):
+    """sha256 over library sources (name and contents, sorted by name): the given
+    files of csrc/ (those that define the profiled kernel), or all of them."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            h.update(name.encode())
-            with open(os.path.join(CSRC, name), "rb") as fh:
-                h.update(fh.read())
+    names = sorted(files) if files else sorted(n for n in os.listdir(CSRC) if n.endswith((".hip", ".h", ".cpp")))
+    for name in names:
+        h.update(name.encode())
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -80,7 +81,7 @@ def summarize(fetch_csv, write_csv, kernel, copy_mib, grid=None):
                 f_write=f_write, traffic=traffic)
 
 
-def write_summary(out, kernel, workload, command, s):
+def write_summary(out, kernel, workload, command, s, sources=None):
     lines = [
         f"# HBM traffic of `{kernel}` on {workload}",
         "",
@@ -104,7 +105,8 @@ def write_summary(out, kernel, workload, command, s):
         "",
         f"traffic_bytes_per_launch: {s['traffic']:.0f}",
         f"kernel_regex: {kernel}",
-        f"source_sha256: {source_hash()}",
+        f"sources: {','.join(sorted(sources)) if sources else 'all'}",
+        f"source_sha256: {source_hash(sources)}",
         "",
     ]
     with open(out, "w") as fh:
@@ -118,10 +120,11 @@ def read_summary(path):
     vals = {}
     with open(path) as fh:
         for line in fh:
-            m = re.match(r"^(traffic_bytes_per_launch|kernel_regex|source_sha256): (.+)$", line.strip())
+            m = re.match(r"^(traffic_bytes_per_launch|kernel_regex|sources|source_sha256): (.+)$", line.strip())
             if m:
                 vals[m.group(1)] = m.group(2)
-    if vals.get("source_sha256") != source_hash() or "traffic_bytes_per_launch" not in vals:
+    files = None if vals.get("sources", "all") == "all" else vals["sources"].split(",")
+    if vals.get("source_sha256") != source_hash(files) or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"]), vals.get("kernel_regex")
 
@@ -181,7 +184,7 @@ def write_stats(stats_csv, title, command, out, top=18, rows=None):
              "| kernel | calls | total ms | avg us | min us | max us | % of GPU time |",
              "|---|---|---|---|---|---|---|"]
     for r in rows[:top]:
-        name = _demangle(r["Name"]).split("(")[0].replace("void ", "")
+        name = _demangle(r["Name"]).replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
         if len(name) > 72:
             name = name[:72] + "..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
@@ -207,6 +210,7 @@ def main():
     ap.add_argument("--kernel", help="regular expression matching the kernel name")
     ap.add_argument("--grid", type=int, help="only dispatches of this grid size (threads)")
     ap.add_argument("--copy-mib", type=float)
+    ap.add_argument("--sources", help="comma-separated csrc/ files that define the kernel (hash scope)")
     ap.add_argument("--workload")
     ap.add_argument("--command", required=True)
     ap.add_argument("--out", required=True)
@@ -220,7 +224,7 @@ def main():
         return
     s = summarize(a.fetch, a.write, a.kernel, a.copy_mib, a.grid)
     s["grid"] = a.grid
-    write_summary(a.out, a.kernel, a.workload, a.command, s)
+    write_summary(a.out, a.kernel, a.workload, a.command, s, a.sources.split(",") if a.sources else None)
     print(s)
 
 
