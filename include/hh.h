@@ -110,6 +110,13 @@ typedef struct {
                                 inverse per subdomain) and the separator Schur complement
                                 is inverted densely; HH_EINVAL if no such cut exists.  All
                                 three are exact factorisations of E (section 3). */
+    int mg_coarse;           /* coarse multigrid operators when k varies: 0 (default) Galerkin
+                                P^T M_beta P; 1 rediscretised on the coarse elements with k^2 of
+                                a coarse element the mean over its children (the one or two
+                                elements per direction of the next finer level), a cheaper
+                                coarse-grid variant of the CSLP (section 3).  Only the V-cycle
+                                changes: the deflation matrices stay Galerkin.  Constant k:
+                                both are the same operator. */
 } hh_solver_opts;
 
 typedef struct {
@@ -163,6 +170,8 @@ typedef struct {
 #define HH_OP_VCYCLE   5   /* y = V-cycle(s) from level l applied to x */
 #define HH_OP_T        6   /* y = T_l x: deflated CSLP preconditioner at level l */
 #define HH_OP_EINV     7   /* y = E^-1 x at deflation level l >= 1 (direct or inner FGMRES) */
+#define HH_OP_K        8   /* y = K_l x (stiffness, section 2.3; Galerkin = rediscretised) */
+#define HH_OP_MK       9   /* y = M_k,l x (k^2-weighted mass of A_l = K_l - M_k,l; Galerkin) */
 
 /* Fills *o with the defaults listed above. */
 void hh_default_opts(hh_solver_opts* o);

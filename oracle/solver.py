@@ -11,6 +11,10 @@ step written as the paper states it (section 3) with the readings below.
     levels come from knot halving; the transfer is the exact knot-insertion
     prolongation P and restriction P^T; coarse operators are Galerkin
     P^T (.) P for K and M_k separately; the coarsest level is solved by dense LU.
+    Option mg_coarse = 1 (the paper's "coarse-grid variant" of the CSLP read
+    as a rediscretisation): the multigrid operators use M_k assembled on the
+    coarse elements, with k^2 of a coarse element the mean of its children;
+    the deflation matrices stay Galerkin.
   * Deflation (section 3, equation for P = I - AQ): Q = Z E^-1 Z^T with
     E = Z^T A Z and Z the same knot-insertion prolongation.  It is combined
     with the CSLP additively as a right preconditioner
@@ -29,7 +33,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import bspline as bs
-from .helmholtz import fine_operators
+from .helmholtz import fine_operators, weighted_mass_1d, weighted_mass_2d
 
 
 class Options:
@@ -37,7 +41,7 @@ class Options:
 
     def __init__(self, beta=(1.0, 0.5), omega=0.8, nu_pre=1, nu_post=1, n_vcycles=1,
                  mg_min_elems=8, coarse_damping=1, defl_mode=2, defl_direct_max=16384,
-                 defl_inner_its=(8, 4, 2, 1, 1, 1, 1, 1), restart=50, maxit=1000, tol=1e-7):
+                 defl_inner_its=(8, 4, 2, 1, 1, 1, 1, 1), restart=50, maxit=1000, tol=1e-7, mg_coarse=0):
         self.beta = complex(beta[0], beta[1])
         self.omega = float(omega)
         self.nu_pre = int(nu_pre)
@@ -51,6 +55,7 @@ class Options:
         self.restart = int(restart)
         self.maxit = int(maxit)
         self.tol = float(tol)
+        self.mg_coarse = int(mg_coarse)
 
 
 class Level:
@@ -84,17 +89,45 @@ def build_hierarchy(prob, opts):
         lv.K = (P.T @ prev.K @ P).tocsr()
         lv.Mk = (P.T @ prev.Mk @ P).tocsr()
         levels.append(lv)
+    k2 = prob.k2_elem
     for l, lv in enumerate(levels):
         lv.n = [len(b) - 1 + p - 2 for b in lv.bks]
         lv.N = int(np.prod(lv.n))
         lv.A = (lv.K - lv.Mk).tocsr()
-        lv.Mb = (lv.K - opts.beta * lv.Mk).tocsr()
+        lv.Mk_mg = lv.Mk
+        if opts.mg_coarse == 1 and k2 is not None and l > 0:
+            k2 = coarse_mean(k2)
+            lv.Mk_mg = rediscretised_mass(lv.bks, p, k2, prob.dim)
+        lv.Mb = (lv.K - opts.beta * lv.Mk_mg).tocsr()
         lv.D = lv.Mb.diagonal().copy()
         lv.gersh = gershgorin_bound(lv.Mb, lv.D)
         lv.omega = smoother_damping(l, lv.gersh, opts)
     # coarsest multigrid level: dense LU of M_beta
     levels[-1].Mb_lu = sla.lu_factor(levels[-1].Mb.toarray())
     return levels
+
+
+def coarse_mean(k2):
+    """k^2 of the next coarser level's elements: the mean over each one's children.
+
+    Knot halving keeps the breakpoints of even index (and the last), so coarse
+    element E covers fine elements 2E and 2E + 1 (only 2E at the end of an odd
+    count).  k2: array [n_el_y][n_el_x] (1D: [n_el])."""
+    k2 = np.atleast_2d(k2)
+    ny, nx = k2.shape
+    cy, cx = (ny + 1) // 2, (nx + 1) // 2
+    out = np.zeros((cy, cx))
+    for E2 in range(cy):
+        for E1 in range(cx):
+            out[E2, E1] = k2[2 * E2:2 * E2 + 2, 2 * E1:2 * E1 + 2].mean()
+    return out
+
+
+def rediscretised_mass(bks, p, k2, dim):
+    """M_k assembled on the elements of breakpoints bks with weights k2 per element."""
+    if dim == 1:
+        return weighted_mass_1d(bks[0], p, np.ravel(k2))
+    return weighted_mass_2d(bks[0], bks[1], p, k2)
 
 
 def gershgorin_bound(Mb, D):

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libhh.so")
 HH_OK, HH_ENOCONV = 0, 1
 HH_EINVAL, HH_ENOMEM, HH_EHIP, HH_ENUMERIC = -1, -2, -3, -4
 
-OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 5, "T": 6, "EINV": 7}
+OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 5, "T": 6, "EINV": 7, "K": 8, "MK": 9}
 
 EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
             "hh_point_spans", "hh_rhs_point_source", "hh_rhs_point_source_noalloc", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
@@ -39,7 +39,8 @@ class SolverOpts(ctypes.Structure):
                 ("defl_mode", ctypes.c_int), ("defl_direct_max", ctypes.c_int),
                 ("defl_inner_its", ctypes.c_int * 8), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("time_kernels", ctypes.c_int),
-                ("autotune", ctypes.c_int), ("ortho", ctypes.c_int), ("defl_direct_solver", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("ortho", ctypes.c_int), ("defl_direct_solver", ctypes.c_int),
+                ("mg_coarse", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

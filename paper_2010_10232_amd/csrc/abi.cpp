@@ -55,6 +55,7 @@ void hh_default_opts(hh_solver_opts* o) {
     o->autotune = 1;
     o->ortho = 0;
     o->defl_direct_solver = 0;
+    o->mg_coarse = 0;
 }
 
 const char* hh_last_error(void) { return g_err.c_str(); }
@@ -494,6 +495,10 @@ hh_status hh_apply(hh_solver* s, int op, int level, const void* x_dev, void* y_d
             break;
         case HH_OP_VCYCLE: S.precond_vcycle(level, x, y, st); break;
         case HH_OP_T: S.T_apply(level, x, y, st); break;
+        case HH_OP_K: S.op_alpha<double>(level, MODE_APPLY, 0.0, 0.0, x, nullptr, y, st, nullptr, nullptr, false); break;
+        case HH_OP_MK:
+            S.op_alpha<double>(level, MODE_APPLY, -1.0, 0.0, x, nullptr, y, st, nullptr, nullptr, false, true);
+            break;
         case HH_OP_EINV:
             if (S.Lz == 0 || level < 1 || level > S.Lz) throw Err{HH_EINVAL, "not a deflation level"};
             S.coarse_solve(level, x, y, st);

@@ -157,6 +157,10 @@ Axis make_trivial_axis();
 void make_transfer(Axis& fine, const Axis& coarse);
 // Element-wise k^2-weighted Galerkin mass of `level` as a full stencil, SoA
 // [(2px+1)(2py+1)][N] (k2: finest-element k^2, [nel_fine_y][nel_fine_x]).
+// Coarse-level k^2 as the mean of the children, and the mass rediscretised
+// with it (mg_coarse = REDISC_AVG).
+void coarse_k2_mean(const std::vector<double>& k2, int nx, int ny, int ncx, int ncy, std::vector<double>& out);
+void redisc_mass_stencil(const Axis& ax, const Axis& ay, const std::vector<double>& k2l, std::vector<double>& S);
 void galerkin_mass_stencil(const Axis& ax, const Axis& ay, const std::vector<double>& k2,
                            std::vector<double>& S);
 void basis_values(const std::vector<double>& U, int p, int span, double x, double* N, double* dN);

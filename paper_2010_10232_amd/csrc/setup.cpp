@@ -8,6 +8,7 @@
 // knot spans: they keep every second breakpoint plus the last one when the
 // element count is odd, so the spaces are nested and only the last element of
 // a level can be short.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -326,6 +327,67 @@ void galerkin_mass_stencil(const Axis& ax, const Axis& ay, const std::vector<dou
                     for (int d1 = 0; d1 < bx; ++d1) {
                         double v = B[(size_t)I1 * bx + d1];
                         if (v != 0.0) S[(size_t)(d2 * bx + d1) * N + (long long)I2 * ax.n + I1] += gyv * v;
+                    }
+            }
+        }
+    }
+}
+
+// k^2 of every element of the next coarser level as the mean of its children:
+// the one or two elements of this level inside it per direction (knot halving
+// keeps the even breakpoints and the last one).  k2 [ny][nx] -> out [ncy][ncx].
+void coarse_k2_mean(const std::vector<double>& k2, int nx, int ny, int ncx, int ncy, std::vector<double>& out) {
+    out.assign((size_t)ncx * ncy, 0.0);
+    for (int E2 = 0; E2 < ncy; ++E2)
+        for (int E1 = 0; E1 < ncx; ++E1) {
+            double s = 0.0;
+            int c = 0;
+            for (int c2 = 2 * E2; c2 < std::min(2 * E2 + 2, ny); ++c2)
+                for (int c1 = 2 * E1; c1 < std::min(2 * E1 + 2, nx); ++c1) {
+                    s += k2[(size_t)c2 * nx + c1];
+                    ++c;
+                }
+            out[(size_t)E2 * ncx + E1] = s / c;
+        }
+}
+
+// k^2-weighted mass of one level rediscretised on its own elements, weights
+// k2l [nel_y][nel_x]: sum over elements E of k2l[E] (Me_y[E2] (x) Me_x[E1]), as a
+// stencil in the layout of galerkin_mass_stencil.
+void redisc_mass_stencil(const Axis& ax, const Axis& ay, const std::vector<double>& k2l, std::vector<double>& S) {
+    const int px = ax.p, py = ay.p, qx = px + 1, qy = py + 1;
+    const int bx = 2 * px + 1, by = 2 * py + 1;
+    const long long N = (long long)ax.n * ay.n;
+    S.assign((size_t)bx * by * N, 0.0);
+    std::vector<double> B((size_t)ax.n * bx);
+    for (int E2 = 0; E2 < ay.nel; ++E2) {
+        std::fill(B.begin(), B.end(), 0.0);
+        for (int E1 = 0; E1 < ax.nel; ++E1) {
+            const double w = k2l[(size_t)E2 * ax.nel + E1];
+            const double* m = &ax.Me[(size_t)E1 * qx * qx];
+            for (int a1 = 0; a1 < qx; ++a1) {
+                const int I1 = E1 + a1 - ax.off;
+                if (I1 < 0 || I1 >= ax.n) continue;
+                for (int c1 = 0; c1 < qx; ++c1) {
+                    const int J1 = E1 + c1 - ax.off;
+                    if (J1 < 0 || J1 >= ax.n) continue;
+                    B[(size_t)I1 * bx + (c1 - a1 + px)] += w * m[a1 * qx + c1];
+                }
+            }
+        }
+        const double* my = &ay.Me[(size_t)E2 * qy * qy];
+        for (int a2 = 0; a2 < qy; ++a2) {
+            const int I2 = E2 + a2 - ay.off;
+            if (I2 < 0 || I2 >= ay.n) continue;
+            for (int c2 = 0; c2 < qy; ++c2) {
+                const int J2 = E2 + c2 - ay.off;
+                if (J2 < 0 || J2 >= ay.n) continue;
+                const double g = my[a2 * qy + c2];
+                const int d2 = c2 - a2 + py;
+                for (int I1 = 0; I1 < ax.n; ++I1)
+                    for (int d1 = 0; d1 < bx; ++d1) {
+                        const double v = B[(size_t)I1 * bx + d1];
+                        if (v != 0.0) S[(size_t)(d2 * bx + d1) * N + (long long)I2 * ax.n + I1] += g * v;
                     }
             }
         }

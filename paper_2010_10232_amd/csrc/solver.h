@@ -28,6 +28,7 @@ struct LevelDev {
     int ty64 = 0, ty32 = 0;   // level-operator strip height (0: fixed rule), FP64 / FP32
     DevBuf Kx, Mx, Ky, My;
     DevBuf S64, S32;
+    DevBuf S64a;              // Galerkin stencil of A_l when the multigrid one is rediscretised
     DevBuf k2, Mex, Mey;
     DevBuf Dinv64, Dinv32;
     // transfer to the next-coarser level (this level = fine side)
@@ -162,9 +163,12 @@ struct SolverImpl {
     // capture of finest-level V-cycle inputs (training samples)
     cx<double>* cap_buf = nullptr;
     int cap_max = 0, cap_n = 0;
+    // mg: the multigrid operator (rediscretised under mg_coarse = 1), else the
+    // deflation operator A_l; mass_only: y = -alpha M_k x (zero stiffness bands)
     template <class T>
     void op_alpha(int l, int mode, double are, double aim, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s,
-                  cx<T>* xo = nullptr, const cx<T>* yadd = nullptr);
+                  cx<T>* xo = nullptr, const cx<T>* yadd = nullptr, bool mg = true, bool mass_only = false);
+    DevBuf zero_bands;           // zero band table of the widest level (mass-only applies)
     int solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s);
 };
 

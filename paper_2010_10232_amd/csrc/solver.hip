@@ -209,6 +209,7 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(o.nu_pre >= 1 && o.nu_post >= 0 && o.n_vcycles >= 1, "bad smoothing counts");
     HH_REQUIRE(o.ortho == 0 || o.ortho == 1, "ortho is 0 or 1");
     HH_REQUIRE(o.defl_direct_solver >= 0 && o.defl_direct_solver <= 2, "defl_direct_solver is 0, 1 or 2");
+    HH_REQUIRE(o.mg_coarse == 0 || o.mg_coarse == 1, "mg_coarse is 0 (Galerkin) or 1 (rediscretised, averaged k^2)");
     HH_REQUIRE(o.mg_min_elems >= 2, "mg_min_elems must be >= 2");
     HH_REQUIRE(o.defl_mode >= 0 && o.defl_mode <= 2, "defl_mode must be 0, 1 or 2");
     HH_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
@@ -236,7 +237,13 @@ void SolverImpl::setup(hipStream_t s) {
     const bool const_k = P.k_mode == 0;
     const double k2c = const_k ? P.k * P.k : 0.0;
     const zd beta(o.beta[0], o.beta[1]);
-    std::vector<std::vector<double>> Sh(lev.size());
+    // Sh: the mass stencil of each coarse level's multigrid operator; Shg: the
+    // Galerkin one of its deflation operator A_l where they differ (mg_coarse =
+    // REDISC_AVG rediscretises the multigrid operators with averaged k^2)
+    std::vector<std::vector<double>> Sh(lev.size()), Shg(lev.size());
+    const bool redisc = !const_k && o.mg_coarse == 1;
+    std::vector<double> k2l = P.k2;
+    int knx = P.nel[0], kny = P.dim == 2 ? P.nel[1] : 1;
 
     for (int l = 0; l <= L; ++l) {
         LevelDev& lv = *lev[l];
@@ -249,6 +256,15 @@ void SolverImpl::setup(hipStream_t s) {
         upload(lv.Ky, lv.ay.Kb);
         upload(lv.My, lv.ay.Mb);
         if (!const_k) galerkin_mass_stencil(lv.ax, lv.ay, P.k2, Sh[l]);
+        if (redisc && l > 0) {
+            std::vector<double> k2c;
+            coarse_k2_mean(k2l, knx, kny, lv.ax.nel, lv.ay.nel, k2c);
+            k2l.swap(k2c);
+            knx = lv.ax.nel;
+            kny = lv.ay.nel;
+            Shg[l] = std::move(Sh[l]);
+            redisc_mass_stencil(lv.ax, lv.ay, k2l, Sh[l]);
+        }
         // Jacobi diagonal of M_beta and the Gershgorin bound of D^-1 M_beta
         std::vector<cx<double>> dinv((size_t)lv.N);
         std::vector<cx<float>> dinv32((size_t)lv.N);
@@ -280,6 +296,7 @@ void SolverImpl::setup(hipStream_t s) {
             upload(lv.S64, Sh[l]);
             std::vector<float> s32(Sh[l].begin(), Sh[l].end());
             upload(lv.S32, s32);
+            if (!Shg[l].empty()) upload(lv.S64a, Shg[l]);
         }
         const size_t v64 = (size_t)lv.N * 16, v32 = (size_t)lv.N * 8;
         lv.b64.alloc(v64);
@@ -563,7 +580,7 @@ void SolverImpl::setup(hipStream_t s) {
         // a Dirichlet resonance of the Helmholtz operator, so the cheapest cuts
         // are tried in turn until one passes the set-up check; the best one is
         // kept, with iterative refinement where it still falls short.
-        const std::vector<double>& Sz = Sh[Lz];
+        const std::vector<double>& Sz = Shg[Lz].empty() ? Sh[Lz] : Shg[Lz];
         std::unique_ptr<SubstructE> best;
         for (const auto& bxy : cands) {
             sub = std::make_unique<SubstructE>();
@@ -602,7 +619,8 @@ void SolverImpl::setup(hipStream_t s) {
         std::vector<std::pair<long long, double>> row;
         for (long long I = 0; I < lz.N; ++I) {
             row.clear();
-            visit_row(lz.ax, lz.ay, const_k, k2c, Sh[Lz], I, [&](long long J, double kv, double mv) {
+            visit_row(lz.ax, lz.ay, const_k, k2c, Shg[Lz].empty() ? Sh[Lz] : Shg[Lz], I,
+                      [&](long long J, double kv, double mv) {
                 for (auto& e : row)
                     if (e.first == J) {
                         e.second += kv - mv;
@@ -712,6 +730,11 @@ void SolverImpl::setup(hipStream_t s) {
             }
         upload(feat, c);
     }
+    {
+        const int nmax = std::max(lev[0]->n1, lev[0]->n2);
+        zero_bands.alloc((size_t)nmax * (2 * P.p + 1) * sizeof(double));
+        HH_HIP(hipMemsetAsync(zero_bands.p, 0, zero_bands.bytes, s));
+    }
     // outer FGMRES workspace
     m_outer = o.restart;
     const size_t v0 = (size_t)lev[0]->N * 16;
@@ -798,20 +821,21 @@ void SolverImpl::autotune_ops(hipStream_t s) {
 template <class T>
 void SolverImpl::op(int l, int mode, bool cslp, const cx<T>* x, const cx<T>* b, cx<T>* y, hipStream_t s, cx<T>* xo,
                     const cx<T>* yadd) {
-    op_alpha<T>(l, mode, cslp ? o.beta[0] : 1.0, cslp ? o.beta[1] : 0.0, x, b, y, s, xo, yadd);
+    op_alpha<T>(l, mode, cslp ? o.beta[0] : 1.0, cslp ? o.beta[1] : 0.0, x, b, y, s, xo, yadd, cslp);
 }
 
 // y = K x - alpha M_k x at level l, with the residual / Jacobi epilogues (mode)
 template <class T>
 void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* x, const cx<T>* b, cx<T>* y,
-                          hipStream_t s, cx<T>* xo, const cx<T>* yadd) {
+                          hipStream_t s, cx<T>* xo, const cx<T>* yadd, bool mg, bool mass_only) {
     LevelDev& lv = *lev[l];
     OpArgs<T> a{};
     a.n1 = lv.n1;
     a.n2 = lv.n2;
-    a.Kx = lv.Kx.as<double>();
+    // mass_only: zero stiffness bands, so y = -alpha M_k x exactly
+    a.Kx = mass_only ? zero_bands.as<double>() : lv.Kx.as<double>();
     a.Mx = lv.Mx.as<double>();
-    a.Ky = lv.Ky.as<double>();
+    a.Ky = mass_only ? zero_bands.as<double>() : lv.Ky.as<double>();
     a.My = lv.My.as<double>();
     a.k2c = prob->k_mode == 0 ? prob->k * prob->k : 0.0;
     a.k2 = lv.k2.as<double>();
@@ -821,7 +845,8 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
     a.off2 = lv.ay.off;
     a.Mex = lv.Mex.as<double>();
     a.Mey = lv.Mey.as<double>();
-    a.S = pick<T>(lv.S64, lv.S32).template as<T>();
+    // the deflation operator A_l of a rediscretised level keeps its Galerkin stencil
+    a.S = (!mg && sizeof(T) == 8 && lv.S64a.p) ? lv.S64a.template as<T>() : pick<T>(lv.S64, lv.S32).template as<T>();
     a.are = (T)are;
     a.aim = (T)aim;
     a.x = x;
@@ -1419,7 +1444,7 @@ template void SolverImpl::op<double>(int, int, bool, const cx<double>*, const cx
 template void SolverImpl::op<float>(int, int, bool, const cx<float>*, const cx<float>*, cx<float>*, hipStream_t,
                                     cx<float>*, const cx<float>*);
 template void SolverImpl::op_alpha<double>(int, int, double, double, const cx<double>*, const cx<double>*, cx<double>*,
-                                           hipStream_t, cx<double>*, const cx<double>*);
+                                           hipStream_t, cx<double>*, const cx<double>*, bool, bool);
 template bool SolverImpl::vcycle<double>(int, const cx<double>*, cx<double>*, hipStream_t, bool, cx<double>*,
                                          const cx<double>*);
 template bool SolverImpl::vcycle<float>(int, const cx<float>*, cx<float>*, hipStream_t, bool, cx<float>*,

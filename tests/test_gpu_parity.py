@@ -76,6 +76,10 @@ CASES = {
     "2d_grf_p2_400_stencil": dict(dim=2, p=2, n_el=400, grf=60.0, x0=(0.5, 0.5), opts=dict(defl_mode=1)),
     # constant k, 200^2 elements, p = 2: level 0 (40,000 unknowns) takes the row-marching strip kernel
     "2d_const_p2_200_strip": dict(dim=2, p=2, n_el=200, k=40.0, x0=(0.5, 0.5), opts=dict()),
+    # coarse multigrid operators rediscretised with averaged k^2 (mg_coarse = 1); odd counts
+    "2d_grf_p3_redisc": dict(dim=2, p=3, n_el=33, grf=10.0, x0=(0.5, 0.5),
+                             opts=dict(defl_direct_max=100, mg_coarse=1)),
+    "1d_rand_p2_redisc": dict(dim=1, p=2, n_el=75, rand=30.0, x0=(0.3,), opts=dict(defl_direct_max=20, mg_coarse=1)),
     # MP 2-A at k = 100, p = 3 on 160 x 160 elements with the default (two-level) deflation
     "mp2a_k100_p3_160": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict()),
 }
@@ -153,6 +157,11 @@ def test_level_operators(name):
         e = rel(to_host(gs.apply("A", l, xd)), lv.A @ x)
         assert e <= 1e-13, e
         e = rel(to_host(gs.apply("MBETA", l, xd)), lv.Mb @ x)
+        assert e <= 1e-13, e
+        # stiffness and (Galerkin) k^2-weighted mass of the level on their own
+        e = rel(to_host(gs.apply("K", l, xd)), lv.K @ x)
+        assert e <= 1e-13, e
+        e = rel(to_host(gs.apply("MK", l, xd)), lv.Mk @ x)
         assert e <= 1e-13, e
         # D is the diagonal of the Galerkin M_beta whose products are held to 1e-13 above; the
         # two sides sum its entries over the finest elements in different orders

@@ -18,6 +18,7 @@ import scipy.sparse.linalg as spla
 from oracle import bspline as bs
 from oracle import helmholtz as hz
 from oracle import solver as osv
+from paper_2010_10232_amd import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -573,3 +574,54 @@ def test_exact_factor_solves_large_deflation_matrix():
     c = rng.standard_normal(E.shape[0]) + 1j * rng.standard_normal(E.shape[0])
     e = solve(c)
     assert np.linalg.norm(E @ e - c) <= 1e-11 * np.linalg.norm(c) * np.linalg.norm(e) / np.linalg.norm(c) * 1e3
+
+
+def test_redisc_coarse_mean_odd_counts():
+    """Children of coarse element E under knot halving: fine elements 2E and 2E+1
+    (only 2E at the end of an odd count)."""
+    k2 = np.arange(15, dtype=float).reshape(3, 5)
+    m = osv.coarse_mean(k2)
+    assert m.shape == (2, 3)
+    assert m[0, 0] == np.mean([0, 1, 5, 6]) and m[0, 2] == np.mean([4, 9])
+    assert m[1, 0] == np.mean([10, 11]) and m[1, 2] == 14.0
+
+
+@pytest.mark.parametrize("dim,p,n_el", [(2, 2, 16), (2, 3, 24), (1, 4, 40)])
+def test_redisc_equals_galerkin_for_blockwise_constant_k(dim, p, n_el):
+    """k constant on each element of the coarsest level: every coarse level's
+    rediscretised M_k is that level's Galerkin P^T M_k P (nested spline spaces,
+    exact Gauss quadrature for element-constant weights), so mg_coarse = 1 and
+    mg_coarse = 0 give the same multigrid operators; the deflation A is Galerkin
+    in both."""
+    L = 0
+    n = n_el
+    while n > 8:
+        n = (n + 1) // 2
+        L += 1
+    blk = 2 ** L
+    assert n_el % blk == 0
+    rng = np.random.default_rng(5)
+    nb = n_el // blk
+    coarse = 10.0 * (1.0 + 0.3 * rng.random((nb, nb) if dim == 2 else nb))
+    ke = np.kron(coarse, np.ones((blk, blk))) if dim == 2 else np.repeat(coarse, blk)
+    op = hz.Problem(dim, p, n_el, 1.0, k_elem=ke)
+    g = osv.Solver(op, osv.Options(defl_mode=0))
+    r = osv.Solver(op, osv.Options(defl_mode=0, mg_coarse=1))
+    assert len(g.levels) == len(r.levels) == L + 1
+    for lg, lr in zip(g.levels[1:], r.levels[1:]):
+        d = abs(lr.Mb - lg.Mb).max() / abs(lg.Mb).max()
+        assert d <= 1e-13, d
+        assert (lr.A != lg.A).nnz == 0
+
+
+def test_redisc_changes_only_multigrid_operators():
+    """Generic k: the rediscretised coarse M_k differs from Galerkin (the weights
+    are averages, not integrals over the children), while A_l is unchanged."""
+    ke = W.grf_k(20, kbar=12.0, seed=3)
+    op = hz.Problem(2, 2, 20, 1.0, k_elem=ke)
+    g = osv.Solver(op, osv.Options(defl_mode=0))
+    r = osv.Solver(op, osv.Options(defl_mode=0, mg_coarse=1))
+    assert (r.levels[0].Mb != g.levels[0].Mb).nnz == 0
+    lg, lr = g.levels[1], r.levels[1]
+    assert abs(lr.Mb - lg.Mb).max() > 1e-6 * abs(lg.Mb).max()
+    assert (lr.A != lg.A).nnz == 0
