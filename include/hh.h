@@ -180,8 +180,10 @@ void hh_default_opts(hh_solver_opts* o);
 const char* hh_last_error(void);
 
 /* Builds the problem: knot vectors, element matrices (Gauss-Legendre,
- * p+1 points), k^2 per element (section 2.3).  Host work plus small uploads. */
-hh_status hh_assemble(const hh_problem_desc* d, hh_problem** out);
+ * p+1 points), k^2 per element (section 2.3).  Host work, plus the upload of
+ * the k^2 field (k_mode 1) to the current device, ordered on `stream`; returns
+ * after the stream has drained. */
+hh_status hh_assemble(const hh_problem_desc* d, void* stream, hh_problem** out);
 
 /* Idempotent on NULL. */
 hh_status hh_problem_destroy(hh_problem* pr);
@@ -311,6 +313,29 @@ hh_status hh_cnn_loss_grad(hh_cnn* c, hh_solver* s, const void* r_dev, double* l
 hh_status hh_cnn_set_fused(hh_cnn* c, int fused);
 /* One Adam step (beta 0.9 / 0.999) with learning rate lr on the loss above. */
 hh_status hh_cnn_train_step(hh_cnn* c, hh_solver* s, const void* r_dev, double lr, double* loss, void* stream);
+/* Training on captured V-cycle inputs (hh_solver_capture): Adam steps over the
+ * (problem, sample) pairs of n problems in an order drawn from `seed`
+ * (Fisher-Yates with SplitMix64), each step the loss and gradient above plus
+ * one Adam update.  samples[i]: device, counts[i] finest-level vectors of
+ * solvers[i] back to back.  loss_before / loss_after (may be NULL): the mean
+ * loss over all pairs before and after.  out_weights (may be NULL): the
+ * trained parameters are also written to that file (hh_cnn_save format).
+ * HH_ENUMERIC if a loss is not finite (the parameters then hold the last
+ * finite step). */
+typedef struct {
+    int steps;                /* Adam steps; <= 0: 800 */
+    double lr;                /* learning rate; <= 0: 3e-4 */
+    unsigned long long seed;  /* order of the pairs */
+} hh_cnn_train_opts;
+hh_status hh_cnn_train(hh_cnn* c, const hh_cnn_train_opts* o, hh_solver* const* solvers,
+                       const void* const* samples, const int* counts, int n, double* loss_before,
+                       double* loss_after, const char* out_weights, void* stream);
+/* Weight files: 8 bytes "HHCNNv1\0", int32 n (floats), n float32 parameters
+ * (as hh_cnn_get_params), uint64 FNV-1a hash of those n * 4 bytes; little
+ * endian.  hh_cnn_load creates a network from such a file (HH_EINVAL for a
+ * file of another format, size or hash). */
+hh_status hh_cnn_save(const hh_cnn* c, const char* path);
+hh_status hh_cnn_load(const char* path, hh_cnn** out);
 /* Uses the network as the finest-level smoother of s (NULL: damped Jacobi).
  * The network must outlive its use by s. */
 hh_status hh_solver_set_smoother(hh_solver* s, hh_cnn* c);

@@ -23,7 +23,7 @@ EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destr
             "hh_level_info", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched", "hh_cnn_create",
             "hh_cnn_destroy", "hh_cnn_num_params", "hh_cnn_get_params", "hh_cnn_set_params", "hh_cnn_set_fused", "hh_cnn_loss_grad",
             "hh_cnn_train_step", "hh_solver_set_smoother", "hh_solver_capture", "hh_solver_captured",
-            "hh_debug_set_spin_limit"]
+            "hh_debug_set_spin_limit", "hh_cnn_train", "hh_cnn_save", "hh_cnn_load"]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -55,6 +55,10 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class CnnTrainOpts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("lr", ctypes.c_double), ("seed", ctypes.c_ulonglong)]
+
+
 class LevelStats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 2), ("n_el", ctypes.c_int * 2), ("N", ctypes.c_longlong),
                 ("omega", ctypes.c_double), ("gersh", ctypes.c_double), ("n_levels", ctypes.c_int),
@@ -78,7 +82,7 @@ def load(path=LIB_PATH):
     lib.hh_default_opts.argtypes = [ctypes.POINTER(SolverOpts)]
     lib.hh_default_opts.restype = None
     lib.hh_last_error.restype = ctypes.c_char_p
-    lib.hh_assemble.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(vp)]
+    lib.hh_assemble.argtypes = [ctypes.POINTER(ProblemDesc), vp, ctypes.POINTER(vp)]
     lib.hh_problem_destroy.argtypes = [vp]
     lib.hh_problem_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.hh_point_spans.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
@@ -102,6 +106,11 @@ def load(path=LIB_PATH):
     lib.hh_cnn_loss_grad.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double), fp, ip, vp]
     lib.hh_cnn_train_step.argtypes = [vp, vp, vp, dp, ctypes.POINTER(ctypes.c_double), vp]
     lib.hh_solver_set_smoother.argtypes = [vp, vp]
+    lib.hh_cnn_train.argtypes = [vp, ctypes.POINTER(CnnTrainOpts), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                 ctypes.POINTER(ctypes.c_int), ip, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.c_char_p, vp]
+    lib.hh_cnn_save.argtypes = [vp, ctypes.c_char_p]
+    lib.hh_cnn_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
     lib.hh_solver_capture.argtypes = [vp, vp, ip]
     lib.hh_solver_captured.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.hh_solve_batched.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -130,6 +139,11 @@ def _stream(stream=None):
         return ctypes.c_void_p(stream)
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _has_gpu():
+    import torch
+    return torch.cuda.is_available()
 
 
 def _ptr(t):
@@ -174,7 +188,7 @@ class Problem:
         else:
             d.k_mode, d.k = 0, float(k)
         h = ctypes.c_void_p()
-        _check(lib.hh_assemble(ctypes.byref(d), ctypes.byref(h)))
+        _check(lib.hh_assemble(ctypes.byref(d), _stream() if _has_gpu() else ctypes.c_void_p(None), ctypes.byref(h)))
         self._h = h
         n = (ctypes.c_int * 2)()
         _check(lib.hh_problem_size(h, n))
@@ -316,9 +330,13 @@ def solve_batched(solvers, fs, us=None):
 class Cnn:
     """Learned finest-level smoother network (weights on the device)."""
 
-    def __init__(self, seed=0):
+    def __init__(self, seed=0, path=None):
+        """A network with seeded random parameters, or the one in the weight file `path`."""
         h = ctypes.c_void_p()
-        _check(load().hh_cnn_create(ctypes.c_ulonglong(seed), ctypes.byref(h)))
+        if path is not None:
+            _check(load().hh_cnn_load(os.fsencode(path), ctypes.byref(h)))
+        else:
+            _check(load().hh_cnn_create(ctypes.c_ulonglong(seed), ctypes.byref(h)))
         self._h = h
         n = ctypes.c_int()
         _check(load().hh_cnn_num_params(h, ctypes.byref(n)))
@@ -343,6 +361,26 @@ class Cnn:
         _check(load().hh_cnn_loss_grad(self._h, solver._h, _ptr(r), ctypes.byref(loss),
                                        g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), self.n_floats, _stream()))
         return loss.value, g
+
+    def save(self, path):
+        """hh_cnn_save: the parameters to a weight file."""
+        _check(load().hh_cnn_save(self._h, os.fsencode(path)))
+
+    def train(self, solvers, samples, steps=800, lr=3e-4, seed=0, out_weights=None):
+        """hh_cnn_train over the captured samples (device [n_i, N_i] tensors) of the solvers;
+        returns (mean loss before, mean loss after)."""
+        n = len(solvers)
+        S = (ctypes.c_void_p * n)(*[s._h.value for s in solvers])
+        X = (ctypes.c_void_p * n)(*[smp.data_ptr() if smp.shape[0] else None for smp in samples])
+        for smp in samples:
+            if smp.shape[0]:
+                _ptr(smp)
+        C = (ctypes.c_int * n)(*[int(smp.shape[0]) for smp in samples])
+        o = CnnTrainOpts(int(steps), float(lr), ctypes.c_ulonglong(seed))
+        l0, l1 = ctypes.c_double(), ctypes.c_double()
+        _check(load().hh_cnn_train(self._h, ctypes.byref(o), S, X, C, n, ctypes.byref(l0), ctypes.byref(l1),
+                                   os.fsencode(out_weights) if out_weights else None, _stream()))
+        return l0.value, l1.value
 
     def train_step(self, solver, r, lr):
         loss = ctypes.c_double()

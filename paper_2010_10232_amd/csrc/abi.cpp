@@ -1,5 +1,8 @@
 // C ABI entry points (include/hh.h): argument checks, error capture, dispatch.
 #include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <memory>
 #include <cstring>
 #include <mutex>
 #include <algorithm>
@@ -60,14 +63,23 @@ void hh_default_opts(hh_solver_opts* o) {
 
 const char* hh_last_error(void) { return g_err.c_str(); }
 
-hh_status hh_assemble(const hh_problem_desc* d, hh_problem** out) {
+hh_status hh_assemble(const hh_problem_desc* d, void* stream, hh_problem** out) {
     HH_TRY
     if (!out) throw Err{HH_EINVAL, "out is NULL"};
     *out = nullptr;
-    ProblemImpl* P = build_problem(d);
+    std::unique_ptr<ProblemImpl> P(build_problem(d));
+    int ndev = 0;
+    if (!P->k2.empty() && hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+        // the finest-level k^2 field, read by the operator kernels of level 0
+        // (host-only uses - spans, CSR export - need no device; hh_setup
+        // uploads it if it is not there yet)
+        hipStream_t s = (hipStream_t)stream;
+        P->k2_dev.alloc(P->k2.size() * sizeof(double));
+        HH_HIP(hipMemcpyAsync(P->k2_dev.p, P->k2.data(), P->k2.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        HH_HIP(hipStreamSynchronize(s));
+    }
     auto* h = new hh_problem();
     h->impl = std::move(*P);
-    delete P;
     *out = h;
     set_error("");
     return HH_OK;
@@ -390,6 +402,124 @@ hh_status hh_cnn_train_step(hh_cnn* c, hh_solver* s, const void* r_dev, double l
     c->impl->adam_step(lr, st);
     HH_HIP(hipStreamSynchronize(st));
     if (loss) *loss = L;
+    return HH_OK;
+    HH_CATCH
+}
+
+namespace {
+// SplitMix64 step (a counter-based generator: state += golden gamma, then mix)
+uint64_t splitmix64(uint64_t& st) {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < n; ++i) h = (h ^ p[i]) * 0x100000001b3ull;
+    return h;
+}
+
+const char kWeightMagic[8] = {'H', 'H', 'C', 'N', 'N', 'v', '1', '\0'};
+
+void save_weights(const CnnImpl& c, const char* path) {
+    std::vector<float> v((size_t)2 * c.nparam);
+    HH_HIP(hipDeviceSynchronize());
+    HH_HIP(hipMemcpy(v.data(), c.theta.p, v.size() * 4, hipMemcpyDeviceToHost));
+    const int32_t n = (int32_t)v.size();
+    const uint64_t sum = fnv1a((const unsigned char*)v.data(), v.size() * 4);
+    FILE* f = std::fopen(path, "wb");
+    if (!f) throw Err{HH_EINVAL, std::string("cannot open ") + path + " for writing"};
+    const bool ok = std::fwrite(kWeightMagic, 1, 8, f) == 8 && std::fwrite(&n, 4, 1, f) == 1 &&
+                    std::fwrite(v.data(), 4, v.size(), f) == v.size() && std::fwrite(&sum, 8, 1, f) == 1;
+    const bool closed = std::fclose(f) == 0;
+    if (!ok || !closed) throw Err{HH_EINVAL, std::string("write to ") + path + " failed"};
+}
+}  // namespace
+
+hh_status hh_cnn_train(hh_cnn* c, const hh_cnn_train_opts* o, hh_solver* const* solvers,
+                       const void* const* samples, const int* counts, int n, double* loss_before, double* loss_after,
+                       const char* out_weights, void* stream) {
+    HH_TRY
+    if (!c || !o || !solvers || !samples || !counts || n < 1) throw Err{HH_EINVAL, "NULL argument or n < 1"};
+    const int steps = o->steps > 0 ? o->steps : 800;
+    const double lr = o->lr > 0.0 ? o->lr : 3e-4;
+    if (!std::isfinite(lr)) throw Err{HH_EINVAL, "learning rate must be finite"};
+    hipStream_t st = (hipStream_t)stream;
+    // every (problem, sample) pair, visited in a seeded order (Fisher-Yates)
+    std::vector<std::pair<int, int>> pairs;
+    for (int i = 0; i < n; ++i) {
+        if (!solvers[i] || (counts[i] > 0 && !samples[i])) throw Err{HH_EINVAL, "NULL solver or sample buffer"};
+        if (counts[i] < 0) throw Err{HH_EINVAL, "negative sample count"};
+        for (int j = 0; j < counts[i]; ++j) pairs.emplace_back(i, j);
+    }
+    if (pairs.empty()) throw Err{HH_EINVAL, "no training samples"};
+    std::vector<int> order(pairs.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    uint64_t rs = o->seed;
+    for (size_t i = order.size() - 1; i > 0; --i) std::swap(order[i], order[splitmix64(rs) % (i + 1)]);
+    CnnImpl& net = *c->impl;
+    auto loss_of = [&](const std::pair<int, int>& pr) {
+        SolverImpl& S = *solvers[pr.first]->impl;
+        const LevelDev& l0 = *S.lev[0];
+        const cx<double>* r = (const cx<double>*)samples[pr.first] + (size_t)pr.second * l0.N;
+        return net.loss_grad(l0.n2, l0.n1, r, S.feat.as<float>(), l0.Dinv64.as<cx<double>>(), l0.omega,
+                             finest_mbeta(S, st), st);
+    };
+    auto mean_loss = [&]() {
+        double sum = 0.0;
+        for (const auto& pr : pairs) sum += loss_of(pr);
+        return sum / (double)pairs.size();
+    };
+    const double l0 = mean_loss();
+    for (int it = 0; it < steps; ++it) {
+        const double L = loss_of(pairs[order[it % order.size()]]);
+        if (!std::isfinite(L)) throw Err{HH_ENUMERIC, "training loss is not finite"};
+        net.adam_step(lr, st);
+    }
+    const double l1 = mean_loss();
+    HH_HIP(hipStreamSynchronize(st));
+    if (loss_before) *loss_before = l0;
+    if (loss_after) *loss_after = l1;
+    if (out_weights) save_weights(net, out_weights);
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_cnn_save(const hh_cnn* c, const char* path) {
+    HH_TRY
+    if (!c || !path) throw Err{HH_EINVAL, "NULL argument"};
+    save_weights(*c->impl, path);
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_cnn_load(const char* path, hh_cnn** out) {
+    HH_TRY
+    if (!path || !out) throw Err{HH_EINVAL, "NULL argument"};
+    *out = nullptr;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) throw Err{HH_EINVAL, std::string("cannot open ") + path};
+    char magic[8] = {0};
+    int32_t n = 0;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kWeightMagic, 8) == 0 &&
+              std::fread(&n, 4, 1, f) == 1 && n > 0 && n <= (1 << 24);
+    std::vector<float> v(ok ? (size_t)n : 0);
+    uint64_t sum = 0;
+    ok = ok && std::fread(v.data(), 4, v.size(), f) == v.size() && std::fread(&sum, 8, 1, f) == 1 &&
+         std::fgetc(f) == EOF;
+    std::fclose(f);
+    if (!ok) throw Err{HH_EINVAL, std::string(path) + " is not a weight file of this library"};
+    if (fnv1a((const unsigned char*)v.data(), v.size() * 4) != sum)
+        throw Err{HH_EINVAL, std::string(path) + ": checksum mismatch"};
+    auto net = std::make_unique<CnnImpl>(0ull);
+    if (n != 2 * net->nparam) throw Err{HH_EINVAL, std::string(path) + ": parameter count of another network"};
+    net->set_params(v.data(), n);
+    auto* c = new hh_cnn();
+    c->impl = std::move(net);
+    *out = c;
     return HH_OK;
     HH_CATCH
 }

@@ -15,6 +15,7 @@ struct ProblemImpl {
     int k_mode = 0;
     double k = 0.0;
     std::vector<double> k2;   // k^2 per finest element [nel_y][nel_x] (1D: [1][nel_x])
+    mutable DevBuf k2_dev;    // the same on the device (uploaded by hh_assemble on its stream, else by hh_setup)
     Axis ax0, ay0;            // finest-level axes
     long long N() const { return (long long)ax0.n * ay0.n; }
 };

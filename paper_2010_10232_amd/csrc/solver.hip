@@ -288,7 +288,12 @@ void SolverImpl::setup(hipStream_t s) {
         upload(lv.Dinv64, dinv);
         upload(lv.Dinv32, dinv32);
         if (!const_k && l == 0) {
-            upload(lv.k2, P.k2);
+            if (!P.k2_dev.p) {
+                P.k2_dev.alloc(P.k2.size() * sizeof(double));
+                HH_HIP(hipMemcpyAsync(P.k2_dev.p, P.k2.data(), P.k2.size() * sizeof(double), hipMemcpyHostToDevice,
+                                      s));
+                HH_HIP(hipStreamSynchronize(s));
+            }
             upload(lv.Mex, lv.ax.Me);
             upload(lv.Mey, lv.ay.Me);
         }
@@ -838,7 +843,7 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
     a.Ky = mass_only ? zero_bands.as<double>() : lv.Ky.as<double>();
     a.My = lv.My.as<double>();
     a.k2c = prob->k_mode == 0 ? prob->k * prob->k : 0.0;
-    a.k2 = lv.k2.as<double>();
+    a.k2 = prob->k2_dev.as<double>();
     a.nel1 = lv.ax.nel;
     a.nel2 = lv.ay.nel;
     a.off1 = lv.ax.off;

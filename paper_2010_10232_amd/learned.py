@@ -73,27 +73,19 @@ def capture(specs, per_problem=24, maxit=60, solver_opts=None, log=None):
     return out
 
 
-def train(net, data, steps=800, lr=3e-4, log=None):
-    """Adam steps cycling over (problem, sample) in a seeded order; returns (mean
-    loss before, mean loss after, seconds)."""
+def train(net, data, steps=800, lr=3e-4, seed=0, log=None, out_weights=None):
+    """Adam steps over the (problem, sample) pairs in a seeded order, in the library
+    (hh_cnn_train); returns (mean loss before, mean loss after, seconds)."""
     import torch
-    pairs = [(sol, smp[i]) for _, sol, smp in data for i in range(smp.shape[0])]
-    order = np.random.default_rng(0).permutation(len(pairs))
-
-    def mean_loss():
-        return float(np.mean([net.loss_grad(sol, r)[0] for sol, r in pairs]))
-
-    l0 = mean_loss()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for it in range(steps):
-        sol, r = pairs[order[it % len(pairs)]]
-        net.train_step(sol, r, lr)
-        if log and (it + 1) % 200 == 0:
-            log(f"[train] step {it + 1}/{steps}")
+    l0, l1 = net.train([sol for _, sol, _ in data], [smp.contiguous() for _, _, smp in data], steps=steps, lr=lr,
+                       seed=seed, out_weights=out_weights)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return l0, mean_loss(), dt
+    if log:
+        log(f"[train] {steps} steps in {dt:.1f} s (mean loss over the samples included)")
+    return l0, l1, dt
 
 
 def trained_smoother(specs=None, steps=800, lr=3e-4, init_scale=0.05, seed=1, log=None, **capture_kw):

@@ -181,7 +181,11 @@ def test_learned_vcycle_vs_oracle(name):
     assert e <= 1e-2
 
 
-def test_capture_train_and_solve():
+def test_capture_train_and_solve(tmp_path):
+    """Capture, training in the library (hh_cnn_train, weights also written to a
+    file), then the learned smoother in the mixed form: the solve converges, takes
+    no more iterations than with Jacobi, and at tol 1e-10 stays within 1e-6 of the
+    oracle's FP64 solution (the mixed-precision bar)."""
     from paper_2010_10232_amd import binding as B
     import torch
     c, op, osol, gp, gs = build("2d_grf_p2_90")
@@ -199,21 +203,51 @@ def test_capture_train_and_solve():
     net = B.Cnn()
     net.set_params(flat(f32_params(17, 0.05)))
     L0 = np.mean([net.loss_grad(gs, samples[i])[0] for i in range(n)])
-    for it in range(60):
-        net.train_step(gs, samples[it % n], 2e-3)
-    L1 = np.mean([net.loss_grad(gs, samples[i])[0] for i in range(n)])
-    _say(f"[cnn train] mean loss {L0:.4e} -> {L1:.4e}")
-    assert L1 < L0
+    wpath = tmp_path / "net.hhw"
+    l0, l1 = net.train([gs], [samples], steps=200, lr=2e-3, seed=0, out_weights=str(wpath))
+    _say(f"[cnn train] mean loss {l0:.4e} -> {l1:.4e}")
+    assert abs(l0 - L0) <= 1e-9 * L0 and l1 < 0.9 * l0
+    assert np.array_equal(B.Cnn(path=str(wpath)).get_params(), net.get_params())
     gs.set_smoother(net)
     try:
         u2, info_l = gs.solve(f)
     finally:
         gs.set_smoother(None)
     _say(f"[cnn train] learned-smoother solve its {info_l['iters']} (Jacobi {info_j['iters']})")
-    assert info_l["converged"]
+    assert info_l["converged"] and info_l["iters"] <= info_j["iters"]
     A = osol.levels[0].A
     fh, uh = to_host(f), to_host(u2)
     assert np.linalg.norm(fh - A @ uh) <= 1.01e-7 * np.linalg.norm(fh)
+    # mixed form (FP32 V-cycle) with the network against the oracle's FP64 solution, tol 1e-10
+    g32 = B.Solver(gp, defl_mode=1, precision=1, tol=1e-10)
+    g32.set_smoother(net)
+    u32, i32 = g32.solve(f)
+    ref, _ = osv.Solver(op, osv.Options(defl_mode=1, tol=1e-10)).solve(fh)
+    e = float(np.linalg.norm(to_host(u32) - ref) / np.linalg.norm(ref))
+    _say(f"[cnn train] mixed + learned at tol 1e-10: {i32['iters']} iterations, rel. difference {e:.2e}")
+    assert i32["converged"] == 1 and e <= 1e-6
+
+
+def test_weight_file_round_trip_and_rejects(tmp_path):
+    from paper_2010_10232_amd import binding as B
+    net = B.Cnn(seed=3)
+    p = tmp_path / "w.hhw"
+    net.save(str(p))
+    back = B.Cnn(path=str(p))
+    assert np.array_equal(back.get_params(), net.get_params())
+    raw = bytearray(p.read_bytes())
+    assert raw[:8] == b"HHCNNv1\x00" and len(raw) == 8 + 4 + 4 * net.n_floats + 8
+    bad = bytearray(raw)
+    bad[100] ^= 0x01
+    (tmp_path / "bad.hhw").write_bytes(bytes(bad))
+    with pytest.raises(B.HHError) as ei:
+        B.Cnn(path=str(tmp_path / "bad.hhw"))
+    assert ei.value.code == B.HH_EINVAL and "checksum" in str(ei.value)
+    (tmp_path / "short.hhw").write_bytes(bytes(raw[:-3]))
+    with pytest.raises(B.HHError):
+        B.Cnn(path=str(tmp_path / "short.hhw"))
+    with pytest.raises(B.HHError):
+        B.Cnn(path=str(tmp_path / "missing.hhw"))
 
 
 @pytest.mark.parametrize("name", list(CASES))
