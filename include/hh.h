@@ -246,16 +246,18 @@ hh_status hh_solver_destroy(hh_solver* s);
 hh_status hh_solve(hh_solver* s, const void* f_dev, void* u_dev, int use_u0,
                    hh_solve_info* info, void* stream);
 
-/* Batched solve: n independent problems, each with
- * its own solver (problems may differ in size, degree and wave number), advance
- * in lockstep - one FGMRES step of every unfinished problem per batch
- * iteration - on a pool of up to eight HIP streams (largest problems first,
- * each to the stream with the fewest unknowns so far), so that the many small
- * kernels of different problems run concurrently.  s, f, u, infos: arrays of n entries;
- * f[i], u[i] device vectors of problem i (as in hh_solve, zero initial guess).
- * Per-problem results and status are in infos[i]; the return value is the
- * first negative status, HH_ENOCONV if some problem did not converge, else
- * HH_OK.  The call returns after all work has finished. */
+/* Batched solve: n independent problems, each with its own solver (problems
+ * may differ in size, degree and wave number), solved concurrently by up to
+ * four host workers, each on its own HIP stream of a pool (default priority):
+ * a worker takes the largest problem not yet started, runs its solve as
+ * hh_solve does, then the next.  The small, latency-bound solves of a batch
+ * thus overlap on the GPU.  s, f, u, infos:
+ * arrays of n entries; f[i], u[i] device vectors of problem i (as in hh_solve,
+ * zero initial guess).  The pool streams wait for the work already on `stream`,
+ * and `stream` waits for them before the call returns.  Per-problem results and
+ * status are in infos[i]; the return value is the first negative status (its
+ * message names the problem), HH_ENOCONV if some problem did not converge, else
+ * HH_OK.  The solvers must not be used elsewhere during the call. */
 hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, void* const* u,
                            hh_solve_info* infos, void* stream);
 

@@ -2074,8 +2074,8 @@ bool launch_arnoldi_grid(long long N, int j, cx<double>* w, const cx<double>* V,
     // A cooperative launch guarantees that all blocks are resident, but the
     // runtime serves it from a separate hardware queue: two cross-queue hand-offs
     // per step.  A grid small enough that `concurrent` such grids (at most that
-    // many Arnoldi steps run at once: 4 for single solves, 16 in batched mode,
-    // whose pools have 8 streams) fit in the blocks the device holds at once is
+    // many Arnoldi steps run at once: four, the workers of a batched solve) fit
+    // in the blocks the device holds at once is
     // launched on the stream's own queue instead: its blocks are placed as soon
     // as CUs are free, and since the exchange's waits are bounded a shortage of
     // CUs can only end in the timeout flag, never a hang.  Otherwise the

@@ -150,14 +150,6 @@ struct SolverImpl {
     // kernels (no wait on other workgroups) from then on
     bool grid_arnoldi_off = false;
     void set_spin_limit(int spins);
-    // batched mode: Arnoldi step j (T, operator, MGS, scalar copies) captured
-    // once into a HIP graph and replayed (no timing, learned smoother or sample
-    // capture in that mode; the graphs bake in this solver's buffers)
-    bool use_graphs = false;
-    std::vector<hipGraphExec_t> step_graphs;
-    std::vector<Meter> step_graph_meter;   // what each captured step meters when replayed
-    void drop_graphs();
-    bool graphs_allowed() const { return !allow_coop && o.time_kernels == 0 && cnn == nullptr && cap_buf == nullptr; }
     // learned fine-level smoother (null: damped Jacobi everywhere)
     CnnImpl* cnn = nullptr;
     DevBuf feat;                 // network feature c = k^2 h^2 per finest-level unknown (FP32)

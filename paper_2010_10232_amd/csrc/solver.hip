@@ -148,15 +148,7 @@ static DevBuf& pick(DevBuf& a64, DevBuf& a32) {
     return sizeof(T) == 8 ? a64 : a32;
 }
 
-void SolverImpl::drop_graphs() {
-    for (hipGraphExec_t g : step_graphs)
-        if (g) (void)hipGraphExecDestroy(g);
-    step_graphs.clear();
-    step_graph_meter.clear();
-}
-
 SolverImpl::~SolverImpl() {
-    drop_graphs();
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     if (pin_d) (void)hipHostFree(pin_d);
     if (pin_i) (void)hipHostFree(pin_i);
@@ -1051,7 +1043,7 @@ bool SolverImpl::arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, Kryl
         launch_arnoldi_small(N, j, w, Vb, N, k, s);
         return k.hstep != nullptr;
     }
-    if (!grid_arnoldi_off && launch_arnoldi_grid(N, j, w, Vb, N, k, s, allow_coop ? 4 : 16, allow_coop, o.ortho == 0))
+    if (!grid_arnoldi_off && launch_arnoldi_grid(N, j, w, Vb, N, k, s, 4, allow_coop, o.ortho == 0))
         return k.hstep != nullptr;
     for (int i = 0; i <= j; ++i) launch_mgs(N, i, j, w, Vb, N, k, s);
     launch_norm_givens(N, j, w, Vb, N, k, s);
@@ -1239,51 +1231,19 @@ void SolveRun::enqueue_step(int jj) {
     cx<double>* zj = Zb + (size_t)jj * N;
     cx<double>* w = Vb + (size_t)(jj + 1) * N;
     const int slot = jj & 1;
-    auto body = [&]() {
-        S->T_apply(0, vj, zj, s);
-        S->op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
-        // MGS + norm + Givens + normalisation of w; algorithmic bytes: each
-        // basis vector v_0..v_jj read once, w read once and written once
-        S->tstart(3, s);
-        const bool published = S->arnoldi(N, jj, w, Vb, kd, s);
-        S->tstop(3, 16.0 * (jj + 3) * N, s);
-        // the fused step kernels store |g_{j+1}| and the flags in the pinned slot
-        // themselves; otherwise scal[0..7] and ints[0..5] (adjacent on the
-        // device) are copied in one transfer
-        if (!published)
-            HH_HIP(hipMemcpyAsync(S->pin_step + 128 * slot, kd.scal, 8 * sizeof(double) + 6 * sizeof(int),
-                                  hipMemcpyDeviceToHost, s));
-    };
-    if (S->use_graphs && S->graphs_allowed()) {
-        if ((int)S->step_graphs.size() <= jj) {
-            S->step_graphs.resize(jj + 1, nullptr);
-            S->step_graph_meter.resize(jj + 1);
-        }
-        if (!S->step_graphs[jj]) {
-            Meter cap;
-            MeterScope ms(&cap);
-            hipGraph_t g = nullptr;
-            HH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            try {
-                body();
-            } catch (...) {
-                (void)hipStreamEndCapture(s, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            HH_HIP(hipStreamEndCapture(s, &g));
-            hipGraphExec_t ge = nullptr;
-            const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) throw Err{HH_EHIP, std::string("graph instantiation: ") + hipGetErrorString(e)};
-            S->step_graphs[jj] = ge;
-            S->step_graph_meter[jj] = cap;
-        }
-        HH_HIP(hipGraphLaunch(S->step_graphs[jj], s));
-        hh::meter(S->step_graph_meter[jj].bytes, S->step_graph_meter[jj].flops);
-    } else {
-        body();
-    }
+    S->T_apply(0, vj, zj, s);
+    S->op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
+    // MGS + norm + Givens + normalisation of w; algorithmic bytes: each basis
+    // vector v_0..v_jj read once, w read once and written once
+    S->tstart(3, s);
+    const bool published = S->arnoldi(N, jj, w, Vb, kd, s);
+    S->tstop(3, 16.0 * (jj + 3) * N, s);
+    // the fused step kernels store |g_{j+1}| and the flags in the pinned slot
+    // themselves; otherwise scal[0..7] and ints[0..5] (adjacent on the device)
+    // are copied in one transfer
+    if (!published)
+        HH_HIP(hipMemcpyAsync(S->pin_step + 128 * slot, kd.scal, 8 * sizeof(double) + 6 * sizeof(int),
+                              hipMemcpyDeviceToHost, s));
     HH_HIP(hipEventRecord(S->ev_slot[slot], s));
     step_bytes[slot] = meter.bytes - before.bytes;
     step_flops[slot] = meter.flops - before.flops;
@@ -1427,8 +1387,7 @@ int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_i
             if (!(run.exchange_timeout && attempt == 0 && !use_u0 && !grid_arnoldi_off)) throw;
             HH_HIP(hipStreamSynchronize(s));
             grid_arnoldi_off = true;
-            drop_graphs();
-            continue;
+                    continue;
         }
         run.inf.status = run.status;
         run.inf.arnoldi_fallback = attempt;
@@ -1441,7 +1400,6 @@ void SolverImpl::set_spin_limit(int spins) {
     kd.spin_limit = spins;
     for (auto& lv : lev) lv->kd.spin_limit = spins;
     grid_arnoldi_off = false;
-    drop_graphs();
 }
 
 template void SolverImpl::op<double>(int, int, bool, const cx<double>*, const cx<double>*, cx<double>*, hipStream_t,

@@ -1,4 +1,4 @@
-"""Batched solves (uneven sizes and degrees in lockstep on a stream pool) against
+"""Batched solves (uneven sizes and degrees, concurrent host workers on a stream pool) against
 single solves and the oracle."""
 import sys
 
@@ -72,11 +72,11 @@ def test_batched_rejects_duplicates():
         B.solve_batched([s, s], [f, f.clone()])
 
 
-def test_batched_graph_replays_match_single():
-    """In batched mode every Arnoldi step is a captured HIP graph.  A short
-    restart replays each graph several times per solve; three batched calls
-    with eager single solves between them must all reproduce the single
-    solves (same iterations, solutions to 1e-10)."""
+def test_batched_repeated_calls_match_single():
+    """A short restart (several cycles per solve) and three batched calls with
+    eager single solves (timing switched on and off) between them: every call
+    reproduces the single solves (same iterations and restarts, solutions to
+    1e-10)."""
     import torch
     from paper_2010_10232_amd import binding as B
     draws = _batch_problems(n=5, seed=21)
@@ -87,7 +87,7 @@ def test_batched_graph_replays_match_single():
     ref = [s.solve(f) for s, f in zip(solvers, fs)]
     assert max(r[1]["restarts"] for r in ref) >= 1
     for call in range(3):
-        _say(f"[graph replays] batched call {call + 1}")
+        _say(f"[repeated batches] batched call {call + 1}")
         us, infos = B.solve_batched(solvers, fs)
         torch.cuda.synchronize()
         for i, (u, info) in enumerate(zip(us, infos)):
@@ -96,7 +96,6 @@ def test_batched_graph_replays_match_single():
             assert info["iters"] == info1["iters"], (call, i)
             d = (torch.linalg.norm(u - u1) / torch.linalg.norm(u1)).item()
             assert d <= 1e-10, (call, i, d)
-        # eager work between replays (single solves, timing switched on and off)
         solvers[call].set_kernel_timing(3)
         solvers[call].solve(fs[call])
         solvers[call].set_kernel_timing(0)
