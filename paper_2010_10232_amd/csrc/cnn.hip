@@ -16,6 +16,7 @@
 // 64-pixel row segment; its three input rows are staged in LDS, the packed
 // weights sit in registers.  The smoother step runs all layers in one kernel
 // (cnn_fused_kernel).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -322,60 +323,128 @@ __global__ __launch_bounds__(FUSED_TB) void cnn_fused_kernel(
 
 // --------------------------------------------------------------------------
 // Weight gradient: G[tap][co][ci] = sum_p gY[p][co] X[p + off(tap)][ci] and
-// Gb[co] = sum_p gY[p][co], as per-workgroup partial sums over an 8 x 64 pixel
-// tile, reduced afterwards in block order (deterministic).
+// Gb[co] = sum_p gY[p][co].  A GEMM with a small output (M = output channels,
+// N = input channels, per tap) and K = all pixels, on v_mfma_f32_16x16x32_bf16:
+// A[co][k] = gY[pixel k][co], B[k][ci] = X[pixel k + off][ci], 32 pixels per
+// MFMA.  A workgroup walks 4 x 64-pixel tiles (grid-stride) with its
+// accumulators in registers; a tile is staged transposed in LDS, channel-major,
+// with one copy of X per horizontal tap offset, so that a lane's 8 consecutive
+// pixels are one aligned 16-byte read.  The bias sums use a B operand of ones.
+// Per-workgroup partial sums are then added in workgroup order (deterministic).
 // --------------------------------------------------------------------------
 constexpr int WG_TH = 4, WG_TW = 64;
+constexpr int WG_MAXBLK = 1024;   // workgroups (and partial sums per output)
 
 template <int CINP, int COUTP>
 __global__ __launch_bounds__(256) void wgrad_kernel(int H, int Wd, int ci_n, int co_n, const __bf16* __restrict__ X,
                                                     const __bf16* __restrict__ gY, float* __restrict__ part) {
-    __shared__ __bf16 xs[WG_TH + 2][WG_TW + 2][CINP];
-    __shared__ __bf16 gs[WG_TH][WG_TW][COUTP > 16 ? COUTP : 16];
-    const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * WG_TW, h0 = blockIdx.y * WG_TH;
-    for (int idx = tid; idx < (WG_TH + 2) * (WG_TW + 2) * CINP; idx += 256) {
-        const int c = idx % CINP, rest = idx / CINP;
-        const int px = rest % (WG_TW + 2), r = rest / (WG_TW + 2);
-        const int hh = h0 + r - 1, ww = x0 + px - 1;
-        __bf16 v = (__bf16)0.0f;
-        if (hh >= 0 && hh < H && ww >= 0 && ww < Wd) v = X[((size_t)hh * Wd + ww) * CINP + c];
-        xs[r][px][c] = v;
-    }
-    for (int idx = tid; idx < WG_TH * WG_TW * co_n; idx += 256) {
-        const int c = idx % co_n, rest = idx / co_n;
-        const int px = rest % WG_TW, r = rest / WG_TW;
-        const int hh = h0 + r, ww = x0 + px;
-        __bf16 v = (__bf16)0.0f;
-        if (hh < H && ww < Wd) v = gY[((size_t)hh * Wd + ww) * COUTP + c];
-        gs[r][px][c] = v;
-    }
-    __syncthreads();
-    const int nw = 9 * co_n * ci_n;
-    const int nout = nw + co_n;
-    const size_t base = (size_t)(blockIdx.y * gridDim.x + blockIdx.x) * nout;
-    for (int o = tid; o < nout; o += 256) {
-        float acc = 0.0f;
-        if (o < nw) {
-            const int ci = o % ci_n, rest = o / ci_n;
-            const int co = rest % co_n, tap = rest / co_n;
-            const int dy = tap / 3, dx = tap - 3 * dy;
-            for (int r = 0; r < WG_TH; ++r)
-                for (int px = 0; px < WG_TW; ++px) acc += (float)gs[r][px][co] * (float)xs[r + dy][px + dx][ci];
-        } else {
-            const int co = o - nw;
-            for (int r = 0; r < WG_TH; ++r)
-                for (int px = 0; px < WG_TW; ++px) acc += (float)gs[r][px][co];
+    constexpr int NCI = CINP >= 16 ? CINP : 16;     // input channels padded to MFMA tiles
+    constexpr int NCO = COUTP >= 16 ? COUTP : 16;   // output channels padded
+    constexpr int TCI = NCI / 16, TCO = NCO / 16;
+    constexpr int NT = 9 * TCO * TCI;               // output tiles (tap, co tile, ci tile)
+    constexpr int PER_WAVE = (NT + 3) / 4;
+    __shared__ __attribute__((aligned(16))) __bf16 xsT[3][NCI][WG_TH + 2][WG_TW];
+    __shared__ __attribute__((aligned(16))) __bf16 gsT[NCO][WG_TH][WG_TW];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int g = lane >> 4, col = lane & 15;
+    const int tiles_x = (Wd + WG_TW - 1) / WG_TW, tiles = tiles_x * ((H + WG_TH - 1) / WG_TH);
+    f32x4 acc[PER_WAVE], accb[TCO];
+#pragma unroll
+    for (int q = 0; q < PER_WAVE; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < TCO; ++q) accb[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 ones;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+    for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int x0 = (t % tiles_x) * WG_TW, h0 = (t / tiles_x) * WG_TH;
+        // X over the tile grown by one pixel, into the three tap-shifted copies
+        for (int idx = tid; idx < (WG_TH + 2) * (WG_TW + 2) * NCI; idx += 256) {
+            const int c = idx % NCI, rest = idx / NCI;
+            const int px = rest % (WG_TW + 2), r = rest / (WG_TW + 2);
+            const int hh = h0 + r - 1, ww = x0 + px - 1;
+            __bf16 v = (__bf16)0.0f;
+            if (c < ci_n && hh >= 0 && hh < H && ww >= 0 && ww < Wd) v = X[((size_t)hh * Wd + ww) * CINP + c];
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int q = px - dx;
+                if (q >= 0 && q < WG_TW) xsT[dx][c][r][q] = v;
+            }
         }
-        part[base + o] = acc;
+        for (int idx = tid; idx < WG_TH * WG_TW * NCO; idx += 256) {
+            const int c = idx % NCO, rest = idx / NCO;
+            const int px = rest % WG_TW, r = rest / WG_TW;
+            const int hh = h0 + r, ww = x0 + px;
+            __bf16 v = (__bf16)0.0f;
+            if (c < co_n && hh < H && ww < Wd) v = gY[((size_t)hh * Wd + ww) * COUTP + c];
+            gsT[c][r][px] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ch = 0; ch < WG_TH * WG_TW / 32; ++ch) {
+            const int r = ch >> 1, px = (ch & 1) * 32 + 8 * g;
+            bf16x8 a[TCO];
+#pragma unroll
+            for (int ct = 0; ct < TCO; ++ct) a[ct] = *(const bf16x8*)&gsT[ct * 16 + col][r][px];
+            if (wave == 0) {
+#pragma unroll
+                for (int ct = 0; ct < TCO; ++ct)
+                    accb[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ct], ones, accb[ct], 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < PER_WAVE; ++q) {
+                const int ot = wave + 4 * q;
+                if (ot >= NT) break;
+                const int tap = ot / (TCO * TCI), ct = (ot / TCI) % TCO, it = ot % TCI;
+                const int dy = tap / 3, dx = tap - 3 * dy;
+                const bf16x8 b = *(const bf16x8*)&xsT[dx][it * 16 + col][r + dy][px];
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ct], b, acc[q], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D layout: lane holds n = col (input channel), m = 4 g + i (output channel)
+    const int nw = 9 * co_n * ci_n;
+    float* out = part + (size_t)blockIdx.x * (nw + co_n);
+#pragma unroll
+    for (int q = 0; q < PER_WAVE; ++q) {
+        const int ot = wave + 4 * q;
+        if (ot >= NT) break;
+        const int tap = ot / (TCO * TCI), ct = (ot / TCI) % TCO, it = ot % TCI;
+        const int ci = it * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co = ct * 16 + 4 * g + i;
+            if (co < co_n && ci < ci_n) out[((size_t)tap * co_n + co) * ci_n + ci] = acc[q][i];
+        }
+    }
+    if (wave == 0 && col == 0) {
+#pragma unroll
+        for (int ct = 0; ct < TCO; ++ct)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = ct * 16 + 4 * g + i;
+                if (co < co_n) out[nw + co] = accb[ct][i];
+            }
     }
 }
 
+// out[o] = sum over the nblk workgroup partials of o, in workgroup order; four
+// partials in flight per thread.
 __global__ void reduce_parts_kernel(int nblk, int nout, const float* __restrict__ part, float* __restrict__ out) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= nout) return;
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * nout + o];
+    int b = 0;
+    for (; b + 3 < nblk; b += 4) {
+        const float v0 = part[(size_t)b * nout + o], v1 = part[(size_t)(b + 1) * nout + o];
+        const float v2 = part[(size_t)(b + 2) * nout + o], v3 = part[(size_t)(b + 3) * nout + o];
+        s += v0;
+        s += v1;
+        s += v2;
+        s += v3;
+    }
+    for (; b < nblk; ++b) s += part[(size_t)b * nout + o];
     out[o] = s;
 }
 
@@ -658,7 +727,7 @@ void CnnImpl::ensure(int H, int Wd) {
     rbuf.alloc(P * 16);
     ybuf.alloc(P * 16);
     scal.alloc(8 * (8 + kNormParts));   // [0] ||r||^2, [1] ||r'||^2 (loss); [8..] partial sums
-    const int nblk = ((Wd + WG_TW - 1) / WG_TW) * ((H + WG_TH - 1) / WG_TH);
+    const int nblk = std::min(((Wd + WG_TW - 1) / WG_TW) * ((H + WG_TH - 1) / WG_TH), WG_MAXBLK);
     part.alloc((size_t)nblk * (9 * 32 * 32 + 32) * 4);
     gfull.alloc((size_t)(9 * 32 * 32 + 32) * 4);
 }
@@ -712,8 +781,9 @@ template void CnnImpl::step<double>(int, int, const cx<double>*, const float*, c
 
 void CnnImpl::wgrad(int l, int H, int Wd, const __bf16* X, int cinp, const __bf16* gY, int coutp, int ci_n, int co_n,
                     hipStream_t s) {
-    dim3 grid((Wd + WG_TW - 1) / WG_TW, (H + WG_TH - 1) / WG_TH);
-    const int nblk = grid.x * grid.y;
+    const int tiles = ((Wd + WG_TW - 1) / WG_TW) * ((H + WG_TH - 1) / WG_TH);
+    const int nblk = std::min(tiles, WG_MAXBLK);
+    const dim3 grid(nblk);
     const int nout = 9 * ci_n * co_n + co_n;
     if (cinp == 8 && coutp == 32)
         hipLaunchKernelGGL((wgrad_kernel<8, 32>), grid, dim3(256), 0, s, H, Wd, ci_n, co_n, X, gY, part.as<float>());
