@@ -23,6 +23,11 @@ step written as the paper states it (section 3) with the readings below.
     itself.  Multilevel deflation solves E by a fixed number of inner FGMRES
     iterations preconditioned by the next level's T; the deepest deflation
     level is solved by dense LU.
+  * Option defl_z = 1: the deflation vectors of the adapted deflation
+    preconditioner (ADP, section 3): Z interpolates from the coarse unknowns
+    by the quadratic rational Bezier curve (weights 1/2, 3/2, 1/2 at t = 1/2),
+    optionally with the weight parameter eps on the coincident fine unknown;
+    two-level only, E = Z^T A Z solved exactly.  See adp_deflation_1d.
   * Outer Krylov solver (sections 3 and 4.3): restarted flexible GMRES with
     modified Gram-Schmidt, complex Givens rotations, x0 = 0, stopping when the
     true relative residual ||f - A u|| / ||f|| is at most tol.
@@ -41,7 +46,8 @@ class Options:
 
     def __init__(self, beta=(1.0, 0.5), omega=0.8, nu_pre=1, nu_post=1, n_vcycles=1,
                  mg_min_elems=8, coarse_damping=1, defl_mode=2, defl_direct_max=16384,
-                 defl_inner_its=(8, 4, 2, 1, 1, 1, 1, 1), restart=50, maxit=1000, tol=1e-7, mg_coarse=0):
+                 defl_inner_its=(8, 4, 2, 1, 1, 1, 1, 1), restart=50, maxit=1000, tol=1e-7, mg_coarse=0,
+                 defl_z=0, defl_eps=0.0):
         self.beta = complex(beta[0], beta[1])
         self.omega = float(omega)
         self.nu_pre = int(nu_pre)
@@ -56,6 +62,8 @@ class Options:
         self.maxit = int(maxit)
         self.tol = float(tol)
         self.mg_coarse = int(mg_coarse)
+        self.defl_z = int(defl_z)
+        self.defl_eps = float(defl_eps)
 
 
 class Level:
@@ -168,6 +176,48 @@ def deflation_levels(levels, opts):
     return L
 
 
+def adp_deflation_1d(nf, eps=0.0):
+    """ADP deflation vectors along one direction (section 3), an nf x nc matrix.
+
+    The paper's stencil is stated for 1-based unknowns: with nc = nf // 2 coarse
+    unknowns, coarse unknown i sits at fine unknown 2i.  A fine unknown of even
+    index j takes the quadratic rational Bezier curve through the coarse
+    unknowns j/2 - 1, j/2, j/2 + 1 (Bernstein polynomials of degree 2, weights
+    1/2, 3/2, 1/2, evaluated at t = 1/2), its centre weight lowered by eps / 8
+    in the weighted variant; a fine unknown of odd index j is the mean of the
+    coarse unknowns (j - 1)/2 and (j + 1)/2 (linear interpolation).  Coarse
+    unknowns beyond either end are zero (homogeneous Dirichlet condition).
+    """
+    nc = nf // 2
+    # the even-index weights from the curve itself
+    t = 0.5
+    w = np.array([0.5, 1.5, 0.5])
+    b = np.array([(1 - t) ** 2, 2 * t * (1 - t), t ** 2])
+    even = w * b / np.dot(w, b)
+    even[1] -= eps / 8.0
+    rows, cols, vals = [], [], []
+    for j in range(1, nf + 1):
+        if j % 2 == 0:
+            taps = ((j // 2 - 1, even[0]), (j // 2, even[1]), (j // 2 + 1, even[2]))
+        else:
+            taps = (((j - 1) // 2, 0.5), ((j + 1) // 2, 0.5))
+        for i, v in taps:
+            if 1 <= i <= nc:
+                rows.append(j - 1)
+                cols.append(i - 1)
+                vals.append(v)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
+
+
+def adp_deflation(prob_n, dim, eps=0.0):
+    """ADP deflation matrix of the finest level: Z_x (1D) or Z_y (x) Z_x (2D,
+    x fastest), prob_n the interior unknowns per direction."""
+    Zx = adp_deflation_1d(prob_n[0], eps)
+    if dim == 1:
+        return Zx
+    return sp.kron(adp_deflation_1d(prob_n[1], eps), Zx).tocsr()
+
+
 # Deflation matrices up to this many unknowns are factored densely; larger ones
 # (the 58k-unknown levels of the 480^2 and 960^2 workloads would need 27 GB
 # dense) by a sparse LU.  Both are an exact factorisation of the same E, so E^-1 c
@@ -199,7 +249,15 @@ class Solver:
         self.cnn_params = cnn_params
         self.levels = build_hierarchy(prob, self.opts)
         self.Lz = deflation_levels(self.levels, self.opts)
-        if self.Lz > 0:
+        self.Zadp = None
+        if self.opts.defl_z == 1:
+            if self.opts.defl_mode != 1:
+                raise ValueError("ADP deflation vectors are two-level only (defl_mode = 1)")
+            lv0 = self.levels[0]
+            self.Zadp = adp_deflation(lv0.n, prob.dim, self.opts.defl_eps)
+            self.Eadp = (self.Zadp.T @ lv0.A @ self.Zadp).tocsr()
+            self.E_lu = exact_factor(self.Eadp)
+        elif self.Lz > 0:
             self.E_lu = exact_factor(self.levels[self.Lz].A)
 
     # ---- multigrid on the CSLP --------------------------------------------
@@ -257,6 +315,13 @@ class Solver:
 
     def T(self, l, v):
         """Preconditioner at level l: Mtilde^-1 (v - A Q v) + Q v, Q = P E^-1 P^T."""
+        if self.Zadp is not None:
+            if l > 0:
+                return self.vcycle(l, v)
+            Z = self.Zadp
+            q = Z @ self.E_lu(Z.T @ v)
+            w = v - self.levels[0].A @ q
+            return self.vcycle(0, w) + q
         if self.Lz == 0 or l >= self.Lz:
             return self.vcycle(l, v)
         Pn = self.levels[l + 1].P

@@ -625,3 +625,107 @@ def test_redisc_changes_only_multigrid_operators():
     lg, lr = g.levels[1], r.levels[1]
     assert abs(lr.Mb - lg.Mb).max() > 1e-6 * abs(lg.Mb).max()
     assert (lr.A != lg.A).nnz == 0
+
+
+# ------------------------------------------- ADP deflation vectors ---------
+
+def test_adp_stencil_values_printed_in_the_paper():
+    """Section 3 prints the quadratic approximation's result: (1/8)(1, 6, 1) on an even fine
+    unknown, (1/2)(1, 1) on an odd one, and the restriction (1/8)(1, 4, 6, 4, 1) of Z^T (the
+    second '2j + 1' of the printed Z^T read as 2j - 1, the transpose of the printed Z)."""
+    Z = osv.adp_deflation_1d(21).toarray()
+    # 1-based fine j = 10 (even) is coarse 5; j = 11 (odd) lies between coarse 5 and 6
+    assert np.allclose(Z[9, 3:6] * 8, [1, 6, 1]) and np.count_nonzero(Z[9]) == 3
+    assert np.allclose(Z[10, 4:6] * 2, [1, 1]) and np.count_nonzero(Z[10]) == 2
+    col = Z[:, 4]   # coarse 5: fine 8 .. 12
+    assert np.allclose(col[7:12] * 8, [1, 4, 6, 4, 1]) and np.count_nonzero(col) == 5
+
+
+def test_adp_interior_column_equals_cubic_knot_insertion():
+    """Away from the boundary the ADP vectors (eps = 0) are the cubic B-spline subdivision
+    columns: the p = 3 knot-insertion prolongation (built by Boehm-style knot insertion in
+    the oracle's B-spline module) has the same interior columns."""
+    Z = osv.adp_deflation_1d(33).toarray()
+    bf = bs.uniform_breakpoints(32)
+    P = bs.knot_insertion_prolongation(bf, bs.halve_breakpoints(bf), 3)
+    pc = P[:, 9]
+    pc = pc[np.abs(pc) > 1e-14]
+    for i in range(3, 12):
+        zc = Z[:, i]
+        assert np.allclose(zc[np.abs(zc) > 0], pc, atol=1e-15)
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.3])
+def test_adp_reproduces_linear_functions(eps):
+    """Coarse unknown i sits at fine unknown 2i (1-based): Z maps samples of a linear g at
+    the coarse positions to its samples at the fine positions j/2, on every row whose
+    coarse neighbours are interior; with eps the coincident rows are scaled by 1 - eps/8."""
+    nf = 41
+    Z = osv.adp_deflation_1d(nf, eps).toarray()
+    nc = Z.shape[1]
+    assert nc == nf // 2
+    g = lambda x: 0.7 - 0.31 * x
+    y = Z @ g(np.arange(1, nc + 1, dtype=float))
+    for j in range(3, nf - 2):
+        expect = g(j / 2.0) * ((1 - eps / 8) if j % 2 == 0 else 1.0)
+        assert abs(y[j - 1] - expect) < 1e-14
+
+
+def test_adp_weight_changes_only_coincident_entries():
+    Z0 = osv.adp_deflation_1d(17).toarray()
+    Ze = osv.adp_deflation_1d(17, 0.4).toarray()
+    D = Ze - Z0
+    expect = np.zeros_like(D)
+    for i in range(8):
+        expect[2 * i + 1, i] = -0.05
+    assert np.allclose(D, expect, atol=1e-15)
+
+
+def test_adp_2d_is_the_tensor_product_x_fastest():
+    """Z (2D) applied to a separable coarse field g(i1) h(i2) is (Z_x g)(Z_y h), stored
+    [i2][i1] with i1 fastest, like the unknowns."""
+    nx, ny = 11, 8
+    Z = osv.adp_deflation((nx, ny), 2, 0.2)
+    zx, zy = osv.adp_deflation_1d(nx, 0.2), osv.adp_deflation_1d(ny, 0.2)
+    rng = np.random.default_rng(3)
+    g, h = rng.random(nx // 2), rng.random(ny // 2)
+    out = Z @ np.outer(h, g).ravel()
+    assert np.allclose(out.reshape(ny, nx), np.outer(zy @ h, zx @ g), atol=1e-15)
+
+
+@pytest.mark.parametrize("dim,p,n_el,k,eps", [(1, 2, 40, 20.0, 0.0), (2, 3, 12, 9.0, 0.3)])
+def test_adp_deflation_identities(dim, p, n_el, k, eps):
+    """With E = Z^T A Z solved exactly: P_D A Z = 0 and Q A Z = Z for the ADP vectors, and
+    the preconditioner maps A Z c to Z c (A T(A Z c) = A Z c)."""
+    prob = hz.Problem(dim, p, n_el, k)
+    s = osv.Solver(prob, osv.Options(defl_mode=1, defl_z=1, defl_eps=eps, mg_min_elems=3))
+    A = s.levels[0].A.toarray()
+    Z = s.Zadp.toarray()
+    Q = Z @ np.linalg.solve(Z.T @ A @ Z, Z.T)
+    I = np.eye(A.shape[0])
+    assert np.abs((I - A @ Q) @ A @ Z).max() < 1e-9 * np.abs(A).max()
+    assert np.abs(Q @ A @ Z - Z).max() < 1e-9
+    c = np.random.default_rng(0).random(Z.shape[1]) + 0.25j
+    v = A @ Z @ c
+    assert np.allclose(s.T(0, v) - s.vcycle(0, np.zeros_like(v)), Z @ c, atol=1e-9 * np.abs(Z @ c).max())
+    assert np.allclose(A @ s.T(0, v), v, atol=1e-9 * np.abs(v).max())
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_adp_solver_matches_direct_solve(dim):
+    if dim == 1:
+        prob, x0 = hz.Problem(1, 3, 80, 40.0), (0.37,)
+    else:
+        prob, x0 = hz.Problem(2, 2, 24, 15.0), (0.5, 0.3)
+    s = osv.Solver(prob, osv.Options(defl_mode=1, defl_z=1, defl_eps=0.2))
+    f = hz.point_source_rhs(prob, x0)
+    u, info = s.solve(f)
+    assert info.converged and info.relres_true <= 1e-7
+    A = s.levels[0].A.toarray()
+    ud = np.linalg.solve(A, f)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) <= np.linalg.cond(A) * 1e-7
+
+
+def test_adp_is_two_level_only():
+    with pytest.raises(ValueError):
+        osv.Solver(hz.Problem(1, 2, 40, 10.0), osv.Options(defl_mode=2, defl_z=1))
