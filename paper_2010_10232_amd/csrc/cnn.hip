@@ -429,23 +429,38 @@ __global__ __launch_bounds__(256) void wgrad_kernel(int H, int Wd, int ci_n, int
     }
 }
 
-// out[o] = sum over the nblk workgroup partials of o, in workgroup order; four
-// partials in flight per thread.
-__global__ void reduce_parts_kernel(int nblk, int nout, const float* __restrict__ part, float* __restrict__ out) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= nout) return;
+// out[o] = sum over the nblk workgroup partials of o.  A workgroup of RP_WAVES
+// waves owns 64 outputs (lane = output, coalesced rows): wave w adds partials
+// w, w + RP_WAVES, ... in that order, four loads in flight, and wave 0 adds
+// the waves' sums in wave order (a fixed order: the same bits every run).
+constexpr int RP_WAVES = 16;
+__global__ __launch_bounds__(64 * RP_WAVES) void reduce_parts_kernel(int nblk, int nout, const float* __restrict__ part,
+                                                                     float* __restrict__ out) {
+    __shared__ float sh[RP_WAVES][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + lane;
     float s = 0.0f;
-    int b = 0;
-    for (; b + 3 < nblk; b += 4) {
-        const float v0 = part[(size_t)b * nout + o], v1 = part[(size_t)(b + 1) * nout + o];
-        const float v2 = part[(size_t)(b + 2) * nout + o], v3 = part[(size_t)(b + 3) * nout + o];
-        s += v0;
-        s += v1;
-        s += v2;
-        s += v3;
+    if (o < nout) {
+        int b = w;
+        for (; b + 3 * RP_WAVES < nblk; b += 4 * RP_WAVES) {
+            const float v0 = part[(size_t)b * nout + o];
+            const float v1 = part[(size_t)(b + RP_WAVES) * nout + o];
+            const float v2 = part[(size_t)(b + 2 * RP_WAVES) * nout + o];
+            const float v3 = part[(size_t)(b + 3 * RP_WAVES) * nout + o];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; b < nblk; b += RP_WAVES) s += part[(size_t)b * nout + o];
     }
-    for (; b < nblk; ++b) s += part[(size_t)b * nout + o];
-    out[o] = s;
+    sh[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && o < nout) {
+        float t = sh[0][lane];
+        for (int q = 1; q < RP_WAVES; ++q) t += sh[q][lane];
+        out[o] = t;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -612,22 +627,10 @@ __global__ __launch_bounds__(256) void norm2_parts_kernel(long long N, const cx<
     if (threadIdx.x == 0) parts[blockIdx.x] = sh[0];
 }
 
-// ||x||^2 in one workgroup (FP64 accumulation, deterministic)
-template <class TV>
-__global__ __launch_bounds__(1024) void norm2_small_kernel(long long N, const cx<TV>* __restrict__ x, double* out) {
-    __shared__ double sh[1024];
-    double s = 0.0;
-    for (long long t = threadIdx.x; t < N; t += 1024) {
-        const cx<TV> v = x[t];
-        s += (double)v.re * v.re + (double)v.im * v.im;
-    }
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = sh[0];
+// The total of norm2_parts_kernel's partial sums (one wave, fixed order)
+__global__ __launch_bounds__(64) void norm2_total_kernel(const double* __restrict__ parts, int nparts, double* out) {
+    const double s = sum_parts(parts, nparts);
+    if (threadIdx.x == 0) *out = s;
 }
 
 static inline unsigned g1(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -791,8 +794,8 @@ void CnnImpl::wgrad(int l, int H, int Wd, const __bf16* X, int cinp, const __bf1
         hipLaunchKernelGGL((wgrad_kernel<32, 32>), grid, dim3(256), 0, s, H, Wd, ci_n, co_n, X, gY, part.as<float>());
     else
         hipLaunchKernelGGL((wgrad_kernel<32, 8>), grid, dim3(256), 0, s, H, Wd, ci_n, co_n, X, gY, part.as<float>());
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(g1(nout, 256)), dim3(256), 0, s, nblk, nout, part.as<float>(),
-                       gfull.as<float>());
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(g1(nout, 64)), dim3(64 * RP_WAVES), 0, s, nblk, nout,
+                       part.as<float>(), gfull.as<float>());
     const LayerInfo& L = layers[l];
     LayerDims d{L.cin, L.cout, L.cinp, L.coutp, L.off};
     const int nf = L.cout * L.cin * 9 + L.cout;
@@ -811,14 +814,19 @@ double CnnImpl::loss_grad(int H, int Wd, const cx<double>* r, const float* feat,
     const long long N = (long long)H * Wd;
     double* nr2 = scal.as<double>();
     double* rn2 = nr2 + 1;
-    hipLaunchKernelGGL(norm2_small_kernel<double>, dim3(1), dim3(1024), 0, s, N, r, nr2);
+    // ||r||^2 and ||r'||^2: partial sums over up to 64 workgroups, then their total
+    double* parts = nr2 + 8;
+    const int np = (int)std::min<long long>(kNormParts, (N + 255) / 256);
+    hipLaunchKernelGGL(norm2_parts_kernel<double>, dim3(np), dim3(256), 0, s, N, r, parts);
+    hipLaunchKernelGGL(norm2_total_kernel, dim3(1), dim3(64), 0, s, parts, np, nr2);
     hipLaunchKernelGGL(pack_input_kernel<double>, dim3(g1(N, 256)), dim3(256), 0, s, N, r, nr2, 1, feat,
                        x0.as<__bf16>());
     forward(H, Wd, s);
     hipLaunchKernelGGL(scale_out_kernel, dim3(g1(N, 256)), dim3(256), 0, s, N, out.as<float>(), nr2, r, dinv, omega,
                        sbuf.as<cx<double>>());
     mbeta(sbuf.as<cx<double>>(), r, rbuf.as<cx<double>>(), 0);          // r' = r - M s
-    hipLaunchKernelGGL(norm2_small_kernel<double>, dim3(1), dim3(1024), 0, s, N, rbuf.as<cx<double>>(), rn2);
+    hipLaunchKernelGGL(norm2_parts_kernel<double>, dim3(np), dim3(256), 0, s, N, rbuf.as<cx<double>>(), parts);
+    hipLaunchKernelGGL(norm2_total_kernel, dim3(1), dim3(64), 0, s, parts, np, rn2);
     mbeta(rbuf.as<cx<double>>(), nullptr, ybuf.as<cx<double>>(), 1);   // y = conj(M) r'
     hipLaunchKernelGGL(loss_grad_pack_kernel, dim3(g1(N, 256)), dim3(256), 0, s, N, ybuf.as<cx<double>>(), nr2,
                        gOut.as<__bf16>());
