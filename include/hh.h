@@ -117,6 +117,17 @@ typedef struct {
                                 coarse-grid variant of the CSLP (section 3).  Only the V-cycle
                                 changes: the deflation matrices stay Galerkin.  Constant k:
                                 both are the same operator. */
+    int defl_z;              /* deflation vectors: 0 (default) the knot-insertion prolongation
+                                of the multigrid hierarchy (Z = P, any defl_mode); 1 the
+                                adapted deflation preconditioner's (ADP, section 3): along
+                                each direction nc = nf / 2 coarse unknowns, coarse c (0-based)
+                                at fine 2c + 1 with weights (1, 6 - defl_eps, 1) / 8 there
+                                (quadratic rational Bezier curve) and (1, 1) / 2 on the fine
+                                unknowns between; 2D: Z_y (x) Z_x.  E = Z^T A Z (a band of
+                                half-width (p + 4) / 2 per direction) is solved exactly.
+                                Two-level only: defl_mode must be 1 (HH_EINVAL otherwise). */
+    double defl_eps;         /* the ADP weight parameter epsilon (section 3); default 0.  The
+                                paper takes its value from an earlier work without printing it. */
 } hh_solver_opts;
 
 typedef struct {
@@ -149,7 +160,10 @@ typedef struct {
     double omega;            /* Jacobi damping used at this level */
     double gersh;            /* Gershgorin bound g_l of D^-1 M_beta,l */
     int n_levels;            /* multigrid levels (finest = 0) */
-    int defl_direct_level;   /* L_z: deflation level solved directly (0: no deflation) */
+    int defl_direct_level;   /* L_z: deflation level solved directly (0: no deflation).  With
+                                the ADP vectors (defl_z = 1) it is n_levels: a level of its
+                                own, outside the multigrid hierarchy, that hh_level_info and
+                                hh_apply (HH_OP_A, HH_OP_K, HH_OP_MK, HH_OP_EINV) accept */
     int op_rows[2];          /* strip height (rows) of the level-operator kernel, FP64 / FP32 */
     int defl_sub[2];         /* substructured E^-1 (defl_direct_solver): subdomains per
                                 direction at the direct deflation level, else 0 */
@@ -172,6 +186,10 @@ typedef struct {
 #define HH_OP_EINV     7   /* y = E^-1 x at deflation level l >= 1 (direct or inner FGMRES) */
 #define HH_OP_K        8   /* y = K_l x (stiffness, section 2.3; Galerkin = rediscretised) */
 #define HH_OP_MK       9   /* y = M_k,l x (k^2-weighted mass of A_l = K_l - M_k,l; Galerkin) */
+#define HH_OP_ZT      10   /* y = Z^T x: deflation restriction from level l to the next
+                              deflation level (defl_z = 0: P^T, as HH_OP_RESTRICT; defl_z = 1:
+                              the ADP vectors, level 0 only) */
+#define HH_OP_Z       11   /* y = Z x: the matching deflation prolongation */
 
 /* Fills *o with the defaults listed above. */
 void hh_default_opts(hh_solver_opts* o);
@@ -261,7 +279,7 @@ hh_status hh_solve(hh_solver* s, const void* f_dev, void* u_dev, int use_u0,
 hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, void* const* u,
                            hh_solve_info* infos, void* stream);
 
-/* Level sizes and parameters; level in [0, n_levels). */
+/* Level sizes and parameters; level in [0, n_levels), or defl_direct_level. */
 hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out);
 
 /* Selects the kernel class timed during later hh_solve calls (values as for

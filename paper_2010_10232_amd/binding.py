@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libhh.so")
 HH_OK, HH_ENOCONV = 0, 1
 HH_EINVAL, HH_ENOMEM, HH_EHIP, HH_ENUMERIC = -1, -2, -3, -4
 
-OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 5, "T": 6, "EINV": 7, "K": 8, "MK": 9}
+OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 5, "T": 6, "EINV": 7, "K": 8, "MK": 9, "ZT": 10, "Z": 11}
 
 EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
             "hh_point_spans", "hh_rhs_point_source", "hh_rhs_point_source_noalloc", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
@@ -40,7 +40,9 @@ class SolverOpts(ctypes.Structure):
                 ("defl_inner_its", ctypes.c_int * 8), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("tol", ctypes.c_double), ("precision", ctypes.c_int), ("time_kernels", ctypes.c_int),
                 ("autotune", ctypes.c_int), ("ortho", ctypes.c_int), ("defl_direct_solver", ctypes.c_int),
-                ("mg_coarse", ctypes.c_int)]
+                ("mg_coarse", ctypes.c_int),
+                ("defl_z", ctypes.c_int),
+                ("defl_eps", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -280,7 +282,8 @@ class Solver:
         _check(load().hh_debug_set_spin_limit(self._h, int(spins)))
 
     def set_kernel_timing(self, cls):
-        """0 off, 1 finest-level operator, 2 dense E^-1 product, 3 outer MGS kernels."""
+        """0 off, 1 finest-level operator, 2 exact E^-1 solve, 3 outer Arnoldi step, 4 tiled
+        stored-stencil operator, 5 tile product of the substructured E^-1."""
         _check(load().hh_set_kernel_timing(self._h, int(cls)))
 
     def solve(self, f, u=None, use_u0=False):
@@ -295,7 +298,9 @@ class Solver:
     def apply(self, op, level, x, out_level=None):
         import torch
         lvl = level if out_level is None else out_level
-        y = torch.empty(self.levels[lvl]["N"], dtype=torch.complex128, device=x.device)
+        # the ADP deflation level lies outside the multigrid levels
+        n = self.levels[lvl]["N"] if lvl < len(self.levels) else self.level_info(lvl)["N"]
+        y = torch.empty(n, dtype=torch.complex128, device=x.device)
         _check(load().hh_apply(self._h, OPS[op], int(level), _ptr(x), _ptr(y), _stream()))
         return y
 

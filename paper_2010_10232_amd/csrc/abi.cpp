@@ -61,6 +61,8 @@ void hh_default_opts(hh_solver_opts* o) {
     o->ortho = 0;
     o->defl_direct_solver = 0;
     o->mg_coarse = 0;
+    o->defl_z = 0;
+    o->defl_eps = 0.0;
 }
 
 const char* hh_last_error(void) { return g_err.c_str(); }
@@ -585,7 +587,7 @@ hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out) {
     HH_TRY
     if (!s || !out) throw Err{HH_EINVAL, "NULL argument"};
     const SolverImpl& S = *s->impl;
-    if (level < 0 || level > S.L) throw Err{HH_EINVAL, "level out of range"};
+    if (level < 0 || (level > S.L && !(S.zadp && level == S.Lz))) throw Err{HH_EINVAL, "level out of range"};
     const LevelDev& lv = *S.lev[level];
     out->n[0] = lv.n1;
     out->n[1] = lv.n2;
@@ -614,7 +616,12 @@ hh_status hh_apply(hh_solver* s, int op, int level, const void* x_dev, void* y_d
     if (x_dev == y_dev) throw Err{HH_EINVAL, "x and y must not alias"};
     SolverImpl& S = *s->impl;
     hipStream_t st = (hipStream_t)stream;
-    if (level < 0 || level > S.L) throw Err{HH_EINVAL, "level out of range"};
+    // the ADP deflation level (outside the multigrid hierarchy) takes its own
+    // operators and E^-1 only
+    const bool adp_level = S.zadp && level == S.Lz;
+    if (level < 0 || (level > S.L && !adp_level)) throw Err{HH_EINVAL, "level out of range"};
+    if (adp_level && op != HH_OP_A && op != HH_OP_K && op != HH_OP_MK && op != HH_OP_EINV)
+        throw Err{HH_EINVAL, "the ADP deflation level takes A, K, M_k and E^-1 only"};
     auto x = (const cx<double>*)x_dev;
     auto y = (cx<double>*)y_dev;
     LevelDev& lv = *S.lev[level];
@@ -638,8 +645,19 @@ hh_status hh_apply(hh_solver* s, int op, int level, const void* x_dev, void* y_d
         case HH_OP_MK:
             S.op_alpha<double>(level, MODE_APPLY, -1.0, 0.0, x, nullptr, y, st, nullptr, nullptr, false, true);
             break;
+        case HH_OP_ZT:
+        case HH_OP_Z: {
+            if (S.Lz == 0 || level >= S.defl_end()) throw Err{HH_EINVAL, "no deflation level below this one"};
+            const Transfer& tr = S.zadp ? S.ztr : lv.tr;
+            if (op == HH_OP_ZT)
+                launch_restrict<double>(tr, x, y, st);
+            else
+                launch_prolong<double>(tr, x, y, 0, st);
+            break;
+        }
         case HH_OP_EINV:
-            if (S.Lz == 0 || level < 1 || level > S.Lz) throw Err{HH_EINVAL, "not a deflation level"};
+            if (S.Lz == 0 || level < 1 || level > S.Lz || (S.zadp && level != S.Lz))
+                throw Err{HH_EINVAL, "not a deflation level"};
             S.coarse_solve(level, x, y, st);
             break;
         default: throw Err{HH_EINVAL, "unknown operator"};

@@ -169,6 +169,12 @@ void gauss_legendre(int n, double* x, double* w);
 Axis make_axis(int p, int nel_fine, int level);
 Axis make_trivial_axis();
 void make_transfer(Axis& fine, const Axis& coarse);
+// ADP deflation vectors along one direction (zf: their tables on the fine
+// side, coarse: the pseudo-axis of Z^T K Z and Z^T M Z), and the coarse stencil
+// Z^T S Z of a full fine-level stencil S.
+void make_adp(const Axis& fine, double eps, Axis& zf, Axis& coarse);
+void galerkin_stencil_z(const Axis& ax, const Axis& ay, const std::vector<double>& S, const Axis& zfx,
+                        const Axis& zfy, const Axis& cxa, const Axis& cya, std::vector<double>& Sc);
 // Element-wise k^2-weighted Galerkin mass of `level` as a full stencil, SoA
 // [(2px+1)(2py+1)][N] (k2: finest-element k^2, [nel_fine_y][nel_fine_x]).
 // Coarse-level k^2 as the mean of the children, and the mass rediscretised

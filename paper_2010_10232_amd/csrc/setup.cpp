@@ -205,6 +205,46 @@ static PRow row_combine(double a, const PRow& x, double b, const PRow& y) {
 // with a_i = (t - U_i)/(U_{i+p} - U_i) (s-p < i <= s), c_{i-1} (i > s).  Run on
 // the identity it yields, row by row, the fine coefficients of every coarse
 // B-spline (convex combinations only, so it is exact to rounding).
+// Row and column tables of an interior transfer matrix P (nf x nc, entry
+// Pint(i, J)) on the fine side's axis: per fine row a run of at most pw coarse
+// entries, per coarse column a run of at most rw fine entries, each run
+// shifted inward where it would pass the end.
+template <class F>
+static void transfer_tables(Axis& fine, int nf, int nc, int pw, int rw, F&& Pint) {
+    fine.pw = std::min(pw, nc);
+    fine.rw = std::min(rw, nf);
+    fine.prow0.assign(nf, 0);
+    fine.prow.assign((size_t)nf * fine.pw, 0.0);
+    for (int i = 0; i < nf; ++i) {
+        int first = -1, last = -1;
+        for (int J = 0; J < nc; ++J)
+            if (Pint(i, J) != 0.0) {
+                if (first < 0) first = J;
+                last = J;
+            }
+        if (first < 0) first = last = 0;
+        HH_REQUIRE(last - first + 1 <= fine.pw, "transfer row wider than its table");
+        int j0 = std::min(first, nc - fine.pw);
+        fine.prow0[i] = j0;
+        for (int t = 0; t < fine.pw; ++t) fine.prow[(size_t)i * fine.pw + t] = Pint(i, j0 + t);
+    }
+    fine.pcol0.assign(nc, 0);
+    fine.pcol.assign((size_t)nc * fine.rw, 0.0);
+    for (int J = 0; J < nc; ++J) {
+        int first = -1, last = -1;
+        for (int i = 0; i < nf; ++i)
+            if (Pint(i, J) != 0.0) {
+                if (first < 0) first = i;
+                last = i;
+            }
+        if (first < 0) first = last = 0;
+        HH_REQUIRE(last - first + 1 <= fine.rw, "transfer column wider than its table");
+        int i0 = std::min(first, nf - fine.rw);
+        fine.pcol0[J] = i0;
+        for (int t = 0; t < fine.rw; ++t) fine.pcol[(size_t)J * fine.rw + t] = Pint(i0 + t, J);
+    }
+}
+
 void make_transfer(Axis& fine, const Axis& coarse) {
     const int p = fine.p;
     std::vector<double> U = coarse.U;
@@ -251,38 +291,136 @@ void make_transfer(Axis& fine, const Axis& coarse) {
         return std::fabs(v) < 1e-15 ? 0.0 : v;
     };
     // interior part (drop first/last function in both spaces)
-    const int nf = fine.n, nc = coarse.n;
-    fine.pw = std::min(p + 1, nc);
-    fine.rw = std::min(p + 2, nf);
-    fine.prow0.assign(nf, 0);
-    fine.prow.assign((size_t)nf * fine.pw, 0.0);
-    for (int i = 0; i < nf; ++i) {
-        int first = -1, last = -1;
-        for (int J = 0; J < nc; ++J)
-            if (Pint(i, J) != 0.0) {
-                if (first < 0) first = J;
-                last = J;
-            }
-        if (first < 0) first = last = 0;
-        HH_REQUIRE(last - first + 1 <= fine.pw, "prolongation row wider than p+1");
-        int j0 = std::min(first, nc - fine.pw);
-        fine.prow0[i] = j0;
-        for (int t = 0; t < fine.pw; ++t) fine.prow[(size_t)i * fine.pw + t] = Pint(i, j0 + t);
+    transfer_tables(fine, fine.n, coarse.n, p + 1, p + 2, Pint);
+}
+
+// Deflation vectors of the adapted deflation preconditioner (ADP, section 3)
+// along one direction: nc = nf / 2 coarse unknowns, coarse c (0-based) at fine
+// unknown 2c + 1.  That fine unknown takes the quadratic rational Bezier curve
+// through coarse c - 1, c, c + 1 at t = 1/2 (Bernstein polynomials of degree
+// 2 with weights 1/2, 3/2, 1/2: (1, 6, 1) / 8), its centre weight lowered by
+// eps / 8 in the weighted form; fine unknown 2c is the mean of coarse c - 1
+// and c.  Coarse unknowns past either end are zero (Dirichlet).
+static double adp_entry(int nc, double eps, int i, int J) {
+    if (J < 0 || J >= nc) return 0.0;
+    if (i & 1) {
+        const double b[3] = {0.25, 0.5, 0.25}, w[3] = {0.5, 1.5, 0.5};
+        const double den = w[0] * b[0] + w[1] * b[1] + w[2] * b[2];
+        const int d = J - (i - 1) / 2;
+        if (d == 0) return w[1] * b[1] / den - eps / 8.0;
+        if (d == -1) return w[0] * b[0] / den;
+        if (d == 1) return w[2] * b[2] / den;
+        return 0.0;
     }
-    fine.pcol0.assign(nc, 0);
-    fine.pcol.assign((size_t)nc * fine.rw, 0.0);
-    for (int J = 0; J < nc; ++J) {
-        int first = -1, last = -1;
-        for (int i = 0; i < nf; ++i)
-            if (Pint(i, J) != 0.0) {
-                if (first < 0) first = i;
-                last = i;
+    return (J == i / 2 - 1 || J == i / 2) ? 0.5 : 0.0;
+}
+
+void make_adp(const Axis& fine, double eps, Axis& zf, Axis& coarse) {
+    const int nf = fine.n, nc = nf / 2, p = fine.p, bf = 2 * p + 1;
+    HH_REQUIRE(nc >= 1, "too few unknowns for ADP deflation vectors");
+    auto Z = [&](int i, int J) { return adp_entry(nc, eps, i, J); };
+    transfer_tables(zf, nf, nc, 3, 5, Z);
+    // coarse pseudo-axis: the Galerkin products Z^T K Z and Z^T M Z as bands
+    // of half-width q (Z's columns span 5 fine unknowns, K and M 2p + 1)
+    const int q = (p + 4) / 2, bq = 2 * q + 1;
+    coarse = Axis{};
+    coarse.p = q;
+    coarse.n = nc;
+    coarse.nel = std::max(1, fine.nel / 2);
+    coarse.off = 0;
+    coarse.nel_fine = fine.nel_fine;
+    coarse.level = fine.level + 1;
+    coarse.Kb.assign((size_t)nc * bq, 0.0);
+    coarse.Mb.assign((size_t)nc * bq, 0.0);
+    for (int a = 0; a < nc; ++a)
+        for (int t = 0; t < zf.rw; ++t) {
+            const int i = zf.pcol0[a] + t;
+            const double za = Z(i, a);
+            if (za == 0.0) continue;
+            for (int d = -p; d <= p; ++d) {
+                const int i2 = i + d;
+                if (i2 < 0 || i2 >= nf) continue;
+                const double kv = fine.Kb[(size_t)i * bf + d + p], mv = fine.Mb[(size_t)i * bf + d + p];
+                for (int u = 0; u < zf.pw; ++u) {
+                    const int b = zf.prow0[i2] + u;
+                    const double zb = Z(i2, b);
+                    if (zb == 0.0) continue;
+                    HH_REQUIRE(std::abs(b - a) <= q, "ADP Galerkin band wider than expected");
+                    coarse.Kb[(size_t)a * bq + b - a + q] += za * kv * zb;
+                    coarse.Mb[(size_t)a * bq + b - a + q] += za * mv * zb;
+                }
             }
-        if (first < 0) first = last = 0;
-        HH_REQUIRE(last - first + 1 <= fine.rw, "prolongation column wider than p+2");
-        int i0 = std::min(first, nf - fine.rw);
-        fine.pcol0[J] = i0;
-        for (int t = 0; t < fine.rw; ++t) fine.pcol[(size_t)J * fine.rw + t] = Pint(i0 + t, J);
+        }
+}
+
+// Sc = Z^T S Z for the tensor-product deflation vectors Z = Z_y (x) Z_x, S a
+// full stencil of the fine level (SoA [(2px+1)(2py+1)][N]) and Sc one of the
+// coarse pseudo-axes (cx, cy), formed as Z^T (S Z) one fine row at a time.
+void galerkin_stencil_z(const Axis& ax, const Axis& ay, const std::vector<double>& S, const Axis& zfx,
+                        const Axis& zfy, const Axis& cxa, const Axis& cya, std::vector<double>& Sc) {
+    const int n1 = ax.n, n2 = ay.n, px = ax.p, py = ay.p, bx = 2 * px + 1;
+    const long long N = (long long)n1 * n2;
+    const int m1 = cxa.n, m2 = cya.n, qx = cxa.p, qy = cya.p, cbx = 2 * qx + 1, cby = 2 * qy + 1;
+    const long long Nc = (long long)m1 * m2;
+    Sc.assign((size_t)cbx * cby * Nc, 0.0);
+    // coarse columns touched from fine row j: those of Z's rows j - p .. j + p
+    auto span = [](const Axis& zf, int n, int p, int j, int& lo, int& hi) {
+        lo = zf.prow0[std::max(j - p, 0)];
+        hi = zf.prow0[std::min(j + p, n - 1)] + zf.pw - 1;
+    };
+    std::vector<double> T;
+    for (int j2 = 0; j2 < n2; ++j2) {
+        int lo2, hi2;
+        span(zfy, n2, py, j2, lo2, hi2);
+        for (int j1 = 0; j1 < n1; ++j1) {
+            int lo1, hi1;
+            span(zfx, n1, px, j1, lo1, hi1);
+            const int w1 = hi1 - lo1 + 1, w2 = hi2 - lo2 + 1;
+            T.assign((size_t)w1 * w2, 0.0);
+            const long long J = (long long)j2 * n1 + j1;
+            // T[b] = sum over the stencil of fine row J of S[J, J'] Z[J', b]
+            for (int d2 = -py; d2 <= py; ++d2) {
+                const int k2 = j2 + d2;
+                if (k2 < 0 || k2 >= n2) continue;
+                for (int d1 = -px; d1 <= px; ++d1) {
+                    const int k1 = j1 + d1;
+                    if (k1 < 0 || k1 >= n1) continue;
+                    const double sv = S[(size_t)((d2 + py) * bx + d1 + px) * N + J];
+                    if (sv == 0.0) continue;
+                    for (int u2 = 0; u2 < zfy.pw; ++u2) {
+                        const double zy = zfy.prow[(size_t)k2 * zfy.pw + u2];
+                        if (zy == 0.0) continue;
+                        const int b2 = zfy.prow0[k2] + u2;
+                        for (int u1 = 0; u1 < zfx.pw; ++u1) {
+                            const double zx = zfx.prow[(size_t)k1 * zfx.pw + u1];
+                            if (zx == 0.0) continue;
+                            const int b1 = zfx.prow0[k1] + u1;
+                            T[(size_t)(b2 - lo2) * w1 + (b1 - lo1)] += sv * zy * zx;
+                        }
+                    }
+                }
+            }
+            // Sc[a, b] += Z[J, a] T[b] over the coarse a of Z's row J
+            for (int u2 = 0; u2 < zfy.pw; ++u2) {
+                const double zy = zfy.prow[(size_t)j2 * zfy.pw + u2];
+                if (zy == 0.0) continue;
+                const int a2 = zfy.prow0[j2] + u2;
+                for (int u1 = 0; u1 < zfx.pw; ++u1) {
+                    const double zx = zfx.prow[(size_t)j1 * zfx.pw + u1];
+                    if (zx == 0.0) continue;
+                    const int a1 = zfx.prow0[j1] + u1;
+                    const long long A = (long long)a2 * m1 + a1;
+                    for (int b2 = lo2; b2 <= hi2; ++b2)
+                        for (int b1 = lo1; b1 <= hi1; ++b1) {
+                            const double tv = T[(size_t)(b2 - lo2) * w1 + (b1 - lo1)];
+                            if (tv == 0.0) continue;
+                            const int e1 = b1 - a1, e2 = b2 - a2;
+                            HH_REQUIRE(std::abs(e1) <= qx && std::abs(e2) <= qy, "ADP stencil wider than expected");
+                            Sc[(size_t)((e2 + qy) * cbx + e1 + qx) * Nc + A] += zy * zx * tv;
+                        }
+                }
+            }
+        }
     }
 }
 

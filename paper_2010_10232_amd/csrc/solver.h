@@ -79,6 +79,14 @@ struct SolverImpl {
     hh_solver_opts o{};
     int L = 0;      // coarsest multigrid level
     int Lz = 0;     // deflation level solved directly (0: none)
+    // ADP deflation vectors (defl_z = 1): two-level, the deflation level is
+    // lev[Lz], Lz = L + 1, outside the multigrid hierarchy; ztr maps level 0 to it
+    bool zadp = false;
+    Transfer ztr{};
+    DevBuf zprow0x, zprowx, zpcol0x, zpcolx, zprow0y, zprowy, zpcol0y, zpcoly;
+    // levels l < defl_end() are deflated (a deflation level lies below them);
+    // 1 .. defl_end() - 1 are the inner FGMRES levels
+    int defl_end() const { return zadp ? 1 : Lz; }
     std::vector<std::unique_ptr<LevelDev>> lev;
     DevBuf Minv64, Minv32;   // dense inverse of M_beta at level L (complex)
     DevBuf Einv;             // dense inverse of A at level Lz (real; variable k)

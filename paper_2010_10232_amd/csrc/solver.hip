@@ -202,6 +202,9 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(o.ortho == 0 || o.ortho == 1, "ortho is 0 or 1");
     HH_REQUIRE(o.defl_direct_solver >= 0 && o.defl_direct_solver <= 2, "defl_direct_solver is 0, 1 or 2");
     HH_REQUIRE(o.mg_coarse == 0 || o.mg_coarse == 1, "mg_coarse is 0 (Galerkin) or 1 (rediscretised, averaged k^2)");
+    HH_REQUIRE(o.defl_z == 0 || o.defl_z == 1, "defl_z is 0 (knot insertion) or 1 (ADP)");
+    HH_REQUIRE(o.defl_z == 0 || o.defl_mode == 1, "ADP deflation vectors (defl_z = 1) are two-level only (defl_mode = 1)");
+    HH_REQUIRE(std::isfinite(o.defl_eps), "defl_eps must be finite");
     HH_REQUIRE(o.mg_min_elems >= 2, "mg_min_elems must be >= 2");
     HH_REQUIRE(o.defl_mode >= 0 && o.defl_mode <= 2, "defl_mode must be 0, 1 or 2");
     HH_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
@@ -534,6 +537,65 @@ void SolverImpl::setup(hipStream_t s) {
                 break;
             }
     }
+    // ADP deflation vectors: a deflation level of their own after the
+    // multigrid levels, with E = Z^T A Z as Galerkin bands (constant k: separable)
+    // or bands plus the coarse mass stencil Z^T M_k Z (variable k)
+    std::vector<double> Sadp;
+    zadp = o.defl_z == 1;
+    if (zadp) {
+        auto lz = std::make_unique<LevelDev>();
+        const LevelDev& l0 = *lev[0];
+        Axis zfx, zfy;
+        make_adp(l0.ax, o.defl_eps, zfx, lz->ax);
+        if (is2d) {
+            make_adp(l0.ay, o.defl_eps, zfy, lz->ay);
+        } else {
+            zfy = make_trivial_axis();
+            lz->ay = make_trivial_axis();
+        }
+        lz->n1 = lz->ax.n;
+        lz->n2 = lz->ay.n;
+        lz->N = (long long)lz->n1 * lz->n2;
+        lz->kind = const_k ? KIND_SEP : KIND_STENCIL;
+        upload(lz->Kx, lz->ax.Kb);
+        upload(lz->Mx, lz->ax.Mb);
+        upload(lz->Ky, lz->ay.Kb);
+        upload(lz->My, lz->ay.Mb);
+        if (!const_k) {
+            galerkin_stencil_z(l0.ax, l0.ay, Sh[0], zfx, zfy, lz->ax, lz->ay, Sadp);
+            upload(lz->S64, Sadp);
+        }
+        upload(zprow0x, zfx.prow0);
+        upload(zprowx, zfx.prow);
+        upload(zpcol0x, zfx.pcol0);
+        upload(zpcolx, zfx.pcol);
+        upload(zprow0y, zfy.prow0);
+        upload(zprowy, zfy.prow);
+        upload(zpcol0y, zfy.pcol0);
+        upload(zpcoly, zfy.pcol);
+        Transfer& t = ztr;
+        t.nf1 = l0.n1;
+        t.nf2 = l0.n2;
+        t.nc1 = lz->n1;
+        t.nc2 = lz->n2;
+        t.pw1 = zfx.pw;
+        t.pw2 = zfy.pw;
+        t.rw1 = zfx.rw;
+        t.rw2 = zfy.rw;
+        t.prow0x = zprow0x.as<int>();
+        t.prowx = zprowx.as<double>();
+        t.prow0y = zprow0y.as<int>();
+        t.prowy = zprowy.as<double>();
+        t.pcol0x = zpcol0x.as<int>();
+        t.pcolx = zpcolx.as<double>();
+        t.pcol0y = zpcol0y.as<int>();
+        t.pcoly = zpcoly.as<double>();
+        lev.push_back(std::move(lz));
+        Lz = L + 1;
+    }
+    // the direct deflation level's mass stencil (variable k)
+    const std::vector<double>& Sz =
+        zadp ? Sadp : (Lz > 0 && !Shg[Lz].empty() ? Shg[Lz] : Sh[std::min(Lz, L)]);
     if (Lz > 0 && const_k) {
         // separable E: exact inverse by fast diagonalisation, no dense matrix
         LevelDev& lz = *lev[Lz];
@@ -577,7 +639,6 @@ void SolverImpl::setup(hipStream_t s) {
         // a Dirichlet resonance of the Helmholtz operator, so the cheapest cuts
         // are tried in turn until one passes the set-up check; the best one is
         // kept, with iterative refinement where it still falls short.
-        const std::vector<double>& Sz = Shg[Lz].empty() ? Sh[Lz] : Shg[Lz];
         std::unique_ptr<SubstructE> best;
         for (const auto& bxy : cands) {
             sub = std::make_unique<SubstructE>();
@@ -616,8 +677,7 @@ void SolverImpl::setup(hipStream_t s) {
         std::vector<std::pair<long long, double>> row;
         for (long long I = 0; I < lz.N; ++I) {
             row.clear();
-            visit_row(lz.ax, lz.ay, const_k, k2c, Shg[Lz].empty() ? Sh[Lz] : Shg[Lz], I,
-                      [&](long long J, double kv, double mv) {
+            visit_row(lz.ax, lz.ay, const_k, k2c, Sz, I, [&](long long J, double kv, double mv) {
                 for (auto& e : row)
                     if (e.first == J) {
                         e.second += kv - mv;
@@ -693,14 +753,14 @@ void SolverImpl::setup(hipStream_t s) {
         }
     }
     if (Lz > 0) {
-        for (int l = 0; l < Lz; ++l) {
+        for (int l = 0; l < defl_end(); ++l) {
             LevelDev& lv = *lev[l];
             const size_t v64 = (size_t)lv.N * 16;
             lv.tq.alloc(v64);
             lv.tw.alloc(v64);
             lv.ts.alloc(v64);
         }
-        for (int l = 1; l <= Lz; ++l) {
+        for (int l = zadp ? Lz : 1; l <= Lz; ++l) {
             LevelDev& lv = *lev[l];
             const size_t v64 = (size_t)lv.N * 16;
             lv.tc.alloc(v64);
@@ -729,7 +789,7 @@ void SolverImpl::setup(hipStream_t s) {
     }
     {
         const int nmax = std::max(lev[0]->n1, lev[0]->n2);
-        zero_bands.alloc((size_t)nmax * (2 * P.p + 1) * sizeof(double));
+        zero_bands.alloc((size_t)nmax * (2 * std::max(P.p, lev[Lz]->ax.p) + 1) * sizeof(double));
         HH_HIP(hipMemsetAsync(zero_bands.p, 0, zero_bands.bytes, s));
     }
     // outer FGMRES workspace
@@ -854,13 +914,14 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
     a.xo = xo;
     a.yadd = mode == MODE_SMOOTH ? yadd : nullptr;
     a.ty = sizeof(T) == 8 ? lv.ty64 : lv.ty32;
-    const int py = prob->dim == 2 ? prob->p : 0;
+    // band half-widths of the level (the degree p, or wider on the ADP level)
+    const int px = lv.ax.p, py = prob->dim == 2 ? lv.ay.p : 0;
     double st_bytes = 0.0;
     {
         // operands once: x, y, b (residual / sweep), D^-1 (sweep), the first-sweep
         // and added vectors, and the mass coefficients: the stored stencil or
         // k^2 per finest element
-        const int p = prob->p, bx = 2 * p + 1, by = py ? 2 * py + 1 : 1;
+        const int p = px, bx = 2 * p + 1, by = py ? 2 * py + 1 : 1;
         const double v = (double)lv.N * sizeof(cx<T>);
         double bytes = 2 * v + (mode != MODE_APPLY ? v : 0.0) + (mode == MODE_SMOOTH || xo ? v : 0.0) +
                        (xo ? v : 0.0) + (a.yadd ? v : 0.0);
@@ -880,7 +941,7 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
     const bool st_kernel = lv.kind == KIND_STENCIL && py > 0 && lv.N > kOpDirectMax;
     if (st_kernel) tstart(4, s);
     if (l == 0) tstart(1, s);
-    launch_op<T>(lv.kind, mode, prob->p, py, a, s);
+    launch_op<T>(lv.kind, mode, px, py, a, s);
     if (l == 0) tstop(1, st_bytes, s);
     if (st_kernel) tstop(4, st_bytes, s);
 }
@@ -1009,15 +1070,17 @@ bool SolverImpl::precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipSt
 }
 
 void SolverImpl::T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t s) {
-    if (Lz == 0 || l >= Lz) {
+    if (l >= defl_end()) {
         precond_vcycle(l, v, z, s);
         return;
     }
     LevelDev& lv = *lev[l];
-    LevelDev& lc = *lev[l + 1];
-    launch_restrict<double>(lv.tr, v, lc.tc.as<cx<double>>(), s);
-    coarse_solve(l + 1, lc.tc.as<cx<double>>(), lc.te.as<cx<double>>(), s);
-    launch_prolong<double>(lv.tr, lc.te.as<cx<double>>(), lv.tq.as<cx<double>>(), 0, s);
+    const int lnext = zadp ? Lz : l + 1;
+    LevelDev& lc = *lev[lnext];
+    const Transfer& tr = zadp ? ztr : lv.tr;
+    launch_restrict<double>(tr, v, lc.tc.as<cx<double>>(), s);
+    coarse_solve(lnext, lc.tc.as<cx<double>>(), lc.te.as<cx<double>>(), s);
+    launch_prolong<double>(tr, lc.te.as<cx<double>>(), lv.tq.as<cx<double>>(), 0, s);
     // w = v - A q; with an FP64 V-cycle that starts with one Jacobi sweep on
     // separate kernels, the same kernel also forms that sweep (x = omega D^-1 w)
     const bool fuse = o.precision == 0 && o.nu_pre == 1 && !(cnn && l == 0) && l < tail_start && l < L;
@@ -1205,7 +1268,7 @@ void SolveRun::start(SolverImpl* S_, const cx<double>* f_, cx<double>* u_, int u
     // a grid-exchange timeout of an earlier solve is reported there: this
     // solve starts with the flags of its Krylov states clear
     HH_HIP(hipMemsetAsync(&kd.ints[5], 0, sizeof(int), s));
-    for (int l = 1; l < S->Lz; ++l)
+    for (int l = 1; l < S->defl_end(); ++l)
         if (S->lev[l]->m_inner > 0) HH_HIP(hipMemsetAsync(&S->lev[l]->kd.ints[5], 0, sizeof(int), s));
     launch_dot_norm2(N, f, &kd.scal[3], &kd.ints[2], kd.partials, s);
     HH_HIP(hipMemcpyAsync(S->pin_d, kd.scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1251,7 +1314,7 @@ void SolveRun::enqueue_step(int jj) {
 
 void SolveRun::enqueue_final() {
     KrylovDev& kd = S->kd;
-    for (int l = 1; l < S->Lz && l < 16; ++l)
+    for (int l = 1; l < S->defl_end() && l < 16; ++l)
         HH_HIP(hipMemcpyAsync(&S->pin_i[32 + l], &S->lev[l]->kd.ints[5], sizeof(int), hipMemcpyDeviceToHost, s));
     // the outer flag once more after the last step: a block that timed out in
     // the step's last exchange sets it after block 0 has published the step
@@ -1343,7 +1406,7 @@ void SolveRun::step() {
         }
         case P_FINAL: {
             exchange_timeout = S->pin_i[31] != 0;
-            for (int l = 1; l < S->Lz && l < 16; ++l) exchange_timeout = exchange_timeout || S->pin_i[32 + l] != 0;
+            for (int l = 1; l < S->defl_end() && l < 16; ++l) exchange_timeout = exchange_timeout || S->pin_i[32 + l] != 0;
             if (exchange_timeout) throw Err{HH_EHIP, "grid barrier of an Arnoldi kernel timed out"};
             const double rtrue = std::sqrt(S->pin_d[3]);
             auto t1 = std::chrono::steady_clock::now();
