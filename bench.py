@@ -58,6 +58,14 @@ WORKLOADS = {
     "wedge_k150_p4_480": dict(dim=2, p=4, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=65536)),
     # MP 2-A mesh of the paper's table (k = 100, p = 3, 160 x 160 elements)
     "mp2a_k100_p3_160": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict()),
+    # the same with the adapted deflation preconditioner's vectors (ADP, section 3; two-level,
+    # E^-1 by fast diagonalisation): D C_MG^1 and D_eps C_MG^1 of the paper's tables
+    "mp2a_k100_p3_160_adp": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict(defl_mode=1, defl_z=1)),
+    "mp2a_k100_p3_160_adp_eps": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5),
+                                     opts=dict(defl_mode=1, defl_z=1, defl_eps=0.25)),
+    # wedge, p = 3, 480^2, ADP vectors: 57,600 unknowns on the ADP level, substructured E^-1
+    "wedge_k150_p3_480_adp": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95),
+                                  opts=dict(defl_mode=1, defl_z=1)),
     # MP 1-B: 1D, k = 50, p = 2, 80 elements, two-level deflation
     "mp1b_k50_p2_80": dict(dim=1, p=2, n_el=80, k=50.0, x0=(0.5,), opts=dict(defl_mode=1)),
     # 64 independent constant-k problems, k ~ U[50, 400], n_el = ceil(k / 0.625),
@@ -123,10 +131,16 @@ def cpu_baseline(w, seconds_cap=20.0):
         info, dt = run(1)
         if dt < seconds_cap / 2:
             info, dt = run(max(2, min(int(seconds_cap / max(dt, 1e-6)), 200)))
+        # a solve that converges well inside the cap is repeated whole
+        iters, spent, reps = info.iters, dt, 1
+        while spent < seconds_cap / 2 and info.converged and reps < 1000:
+            info, dt = run(info.iters)
+            iters, spent, reps = iters + info.iters, spent + dt, reps + 1
     N = s.levels[0].N
-    return {"value": N * info.iters / dt, "unit": "DoF-iter/s", "cores": 1, "kind": "oracle",
-            "sample": f"{info.iters} outer FGMRES iteration(s) of the same solve from zero "
-                      f"({dt:.1f} s; oracle set-up of {t_setup:.0f} s excluded)",
+    what = (f"{info.iters} outer FGMRES iteration(s) of the same solve from zero" if reps == 1 else
+            f"{reps} whole solves of {info.iters} outer FGMRES iterations each")
+    return {"value": N * iters / spent, "unit": "DoF-iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what} ({spent:.1f} s; oracle set-up of {t_setup:.0f} s excluded)",
             "iters": info.iters}
 
 
