@@ -201,6 +201,90 @@ __global__ void schur_sub_kernel(int h, int hm, const double* __restrict__ C, co
     if (i < h) S[(long long)hs[j] * ld + hs[i]] -= C[(long long)j * hm + i];
 }
 
+// Batched Gram blocks on the FP64 matrix cores: C_b = A_b^T B_b for every batch
+// member b (A_b: K x M, B_b: K x N, C_b: M x N, all column-major, so the
+// contraction index K is contiguous in both operands).  The Schur complement
+// needs two such products per subdomain, W_d = (E_dd^-1)^T B_d and
+// C_d = B_d^T W_d (E_dd^-1 symmetric: W_d = E_dd^-1 B_d to rounding).  A
+// workgroup of four waves owns a 64 x 64 tile of C, each wave a 32 x 32 quarter
+// as 2 x 2 fragments of v_mfma_f64_16x16x4f64 (operand lane l: row or column
+// l mod 16 of the fragment, contraction index l / 16; result lane l: rows
+// l / 16 + 4 r, column l mod 16).  K advances in slabs of 16: both operand
+// tiles are staged in LDS (rows padded to 17 doubles), entries past M, N or K
+// read as zero.
+constexpr int GB_T = 64, GB_K = 16;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void gram_tn_kernel(int M, int N, int K, const double* __restrict__ A, int lda,
+                                                      long long sA, const double* __restrict__ B, int ldb,
+                                                      long long sB, double* __restrict__ C, int ldc, long long sC) {
+    __shared__ double As[GB_T][GB_K + 1];
+    __shared__ double Bs[GB_T][GB_K + 1];
+    A += (long long)blockIdx.z * sA;
+    B += (long long)blockIdx.z * sB;
+    C += (long long)blockIdx.z * sC;
+    const int m0 = blockIdx.x * GB_T, n0 = blockIdx.y * GB_T;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    // staging: thread t loads 4 consecutive k of column t / 4 of each tile
+    const int sc = t >> 2, sk = (t & 3) * 4;
+    const bool am = m0 + sc < M, bn = n0 + sc < N;
+    const double* Ap = A + (long long)(am ? m0 + sc : 0) * lda;
+    const double* Bp = B + (long long)(bn ? n0 + sc : 0) * ldb;
+    v4d acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += GB_K) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = k0 + sk + r;
+            av[r] = (am && k < K) ? Ap[k] : 0.0;
+            bv[r] = (bn && k < K) ? Bp[k] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            As[sc][sk + r] = av[r];
+            Bs[sc][sk + r] = bv[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GB_K; kk += 4) {
+            double a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = As[wm + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = Bs[wn + j * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + wn + j * 16 + (lane & 15);
+            if (n >= N) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+                if (m < M) C[(long long)n * ldc + m] = acc[i][j][r];
+            }
+        }
+}
+
+void launch_gram_tn(int M, int N, int K, const double* A, int lda, long long sA, const double* B, int ldb,
+                    long long sB, double* C, int ldc, long long sC, int batch, hipStream_t s) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    HH_REQUIRE(batch <= 65535, "too many Gram blocks in one launch");
+    const dim3 grid((M + GB_T - 1) / GB_T, (N + GB_T - 1) / GB_T, batch);
+    hipLaunchKernelGGL(gram_tn_kernel, grid, dim3(256), 0, s, M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC);
+    HH_HIP(hipGetLastError());
+}
+
 std::vector<int> split(int n, int B, int q) {
     const int tot = n - (B - 1) * q;
     if (B < 1 || tot < B) return {};
@@ -448,17 +532,11 @@ void substruct_build(SubstructE& E, int n1, int n2, int px, int py, int bx, int 
         std::vector<double>().swap(B);
         dW.alloc((size_t)E.nsub * ndm * hm * sizeof(double));
         dC.alloc((size_t)E.nsub * hm * hm * sizeof(double));
-        const double one = 1.0, zero = 0.0;
-        roc_check(rocblas_dgemm_strided_batched(rh.h, rocblas_operation_none, rocblas_operation_none, ndm, hm, ndm,
-                                                &one, dA.as<double>(), ndm, (rocblas_stride)ndm * ndm,
-                                                dB.as<double>(), ndm, (rocblas_stride)ndm * hm, &zero,
-                                                dW.as<double>(), ndm, (rocblas_stride)ndm * hm, E.nsub),
-                  "rocblas_dgemm_strided_batched (E_dd^-1 B)");
-        roc_check(rocblas_dgemm_strided_batched(rh.h, rocblas_operation_transpose, rocblas_operation_none, hm, hm,
-                                                ndm, &one, dB.as<double>(), ndm, (rocblas_stride)ndm * hm,
-                                                dW.as<double>(), ndm, (rocblas_stride)ndm * hm, &zero,
-                                                dC.as<double>(), hm, (rocblas_stride)hm * hm, E.nsub),
-                  "rocblas_dgemm_strided_batched (B^T E_dd^-1 B)");
+        // W_d = (E_dd^-1)^T B_d, then the Gram blocks C_d = B_d^T W_d (FP64 MFMA)
+        launch_gram_tn(ndm, hm, ndm, dA.as<double>(), ndm, (long long)ndm * ndm, dB.as<double>(), ndm,
+                       (long long)ndm * hm, dW.as<double>(), ndm, (long long)ndm * hm, E.nsub, s);
+        launch_gram_tn(hm, hm, ndm, dB.as<double>(), ndm, (long long)ndm * hm, dW.as<double>(), ndm,
+                       (long long)ndm * hm, dC.as<double>(), hm, (long long)hm * hm, E.nsub, s);
         std::vector<int> hs;
         std::vector<int> h0(E.nsub);
         for (int d = 0; d < E.nsub; ++d) {
