@@ -28,6 +28,10 @@ step written as the paper states it (section 3) with the readings below.
     by the quadratic rational Bezier curve (weights 1/2, 3/2, 1/2 at t = 1/2),
     optionally with the weight parameter eps on the coincident fine unknown;
     two-level only, E = Z^T A Z solved exactly.  See adp_deflation_1d.
+  * Option precond = 1: the paper's comparison preconditioner C_ex (sections
+    4.3 and 4.4): the CSLP with a small imaginary shift, M_ex = K - (1 + i
+    beta2) M_k, inverted exactly (sparse LU), without multigrid or deflation;
+    beta2 = 1/k in 1D and 1/(3k) in 2D unless given (cex_beta2).
   * Outer Krylov solver (sections 3 and 4.3): restarted flexible GMRES with
     modified Gram-Schmidt, complex Givens rotations, x0 = 0, stopping when the
     true relative residual ||f - A u|| / ||f|| is at most tol.
@@ -47,7 +51,7 @@ class Options:
     def __init__(self, beta=(1.0, 0.5), omega=0.8, nu_pre=1, nu_post=1, n_vcycles=1,
                  mg_min_elems=8, coarse_damping=1, defl_mode=2, defl_direct_max=16384,
                  defl_inner_its=(8, 4, 2, 1, 1, 1, 1, 1), restart=50, maxit=1000, tol=1e-7, mg_coarse=0,
-                 defl_z=0, defl_eps=0.0):
+                 defl_z=0, defl_eps=0.0, precond=0, cex_beta2=0.0):
         self.beta = complex(beta[0], beta[1])
         self.omega = float(omega)
         self.nu_pre = int(nu_pre)
@@ -64,6 +68,8 @@ class Options:
         self.mg_coarse = int(mg_coarse)
         self.defl_z = int(defl_z)
         self.defl_eps = float(defl_eps)
+        self.precond = int(precond)
+        self.cex_beta2 = float(cex_beta2)
 
 
 class Level:
@@ -250,6 +256,15 @@ class Solver:
         self.levels = build_hierarchy(prob, self.opts)
         self.Lz = deflation_levels(self.levels, self.opts)
         self.Zadp = None
+        self.Mex_lu = None
+        if self.opts.precond == 1:
+            if prob.k_elem is not None:
+                raise ValueError("C_ex is built for constant k only")
+            b2 = self.opts.cex_beta2 or (1.0 / prob.k if prob.dim == 1 else 1.0 / (3.0 * prob.k))
+            self.cex_beta2 = b2
+            lv0 = self.levels[0]
+            self.Mex = (lv0.K - (1.0 + 1j * b2) * lv0.Mk).tocsc()
+            self.Mex_lu = spla.splu(self.Mex)
         if self.opts.defl_z == 1:
             if self.opts.defl_mode != 1:
                 raise ValueError("ADP deflation vectors are two-level only (defl_mode = 1)")
@@ -315,6 +330,8 @@ class Solver:
 
     def T(self, l, v):
         """Preconditioner at level l: Mtilde^-1 (v - A Q v) + Q v, Q = P E^-1 P^T."""
+        if self.Mex_lu is not None:
+            return self.Mex_lu.solve(np.asarray(v, dtype=np.complex128))
         if self.Zadp is not None:
             if l > 0:
                 return self.vcycle(l, v)

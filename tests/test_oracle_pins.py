@@ -729,3 +729,30 @@ def test_adp_solver_matches_direct_solve(dim):
 def test_adp_is_two_level_only():
     with pytest.raises(ValueError):
         osv.Solver(hz.Problem(1, 2, 40, 10.0), osv.Options(defl_mode=2, defl_z=1))
+
+
+# ------------------------------------------------ C_ex comparator ----------
+
+@pytest.mark.parametrize("dim,p,n_el,k", [(1, 2, 30, 20.0), (2, 3, 8, 6.0)])
+def test_cex_spectrum_on_the_half_circle(dim, p, n_el, k):
+    """With M_ex = K - (1 + i b) M_k and K v = theta M_k v, the eigenvalues of M_ex^-1 A are
+    z / (z - i b), z = theta - 1 real: all on the circle |mu - 1/2| = 1/2 whatever b (the
+    shifted-Laplacian result behind the CSLP, section 3)."""
+    prob = hz.Problem(dim, p, n_el, k)
+    s = osv.Solver(prob, osv.Options(precond=1, defl_mode=0))
+    A = s.levels[0].A.toarray()
+    mu = np.linalg.eigvals(np.linalg.solve(s.Mex.toarray(), A))
+    assert np.allclose(np.abs(mu - 0.5), 0.5, atol=1e-9)
+    # the shift is the paper's: 1/k in 1D, 1/(3k) in 2D (tables 2, 3 and 5)
+    assert s.cex_beta2 == (1.0 / k if dim == 1 else 1.0 / (3.0 * k))
+
+
+def test_cex_is_exact_and_tiny_shift_converges_in_one_step():
+    prob = hz.Problem(2, 2, 10, 7.0)
+    s = osv.Solver(prob, osv.Options(precond=1, defl_mode=0, cex_beta2=0.2))
+    x = np.random.default_rng(4).random(s.levels[0].N) + 0.3j
+    assert np.allclose(s.T(0, s.Mex @ x), x, atol=1e-12)
+    # b -> 0: M_ex -> A, an exact preconditioner: one FGMRES step
+    t = osv.Solver(prob, osv.Options(precond=1, defl_mode=0, cex_beta2=1e-13, tol=1e-9))
+    u, info = t.solve(hz.point_source_rhs(prob, (0.3, 0.6)))
+    assert info.converged and info.iters == 1
