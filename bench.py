@@ -63,6 +63,9 @@ WORKLOADS = {
     "mp2a_k100_p3_160_adp": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict(defl_mode=1, defl_z=1)),
     "mp2a_k100_p3_160_adp_eps": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5),
                                      opts=dict(defl_mode=1, defl_z=1, defl_eps=0.25)),
+    # the paper's comparison preconditioner C_ex on the same mesh: the CSLP with shift 1/(3k),
+    # inverted exactly (fast diagonalisation of the finest level), no multigrid or deflation
+    "mp2a_k100_p3_160_cex": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict(precond=1, defl_mode=0)),
     # wedge, p = 3, 480^2, ADP vectors: 57,600 unknowns on the ADP level, substructured E^-1
     "wedge_k150_p3_480_adp": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95),
                                   opts=dict(defl_mode=1, defl_z=1)),

@@ -128,6 +128,13 @@ typedef struct {
                                 Two-level only: defl_mode must be 1 (HH_EINVAL otherwise). */
     double defl_eps;         /* the ADP weight parameter epsilon (section 3); default 0.  The
                                 paper takes its value from an earlier work without printing it. */
+    int precond;             /* 0 (default): the deflated, multigrid-approximated CSLP above;
+                                1: the paper's comparison preconditioner C_ex (sections 4.3,
+                                4.4): M_ex = K - (1 + i cex_beta2) M_k inverted exactly by
+                                fast diagonalisation of the finest level (constant k only:
+                                HH_EINVAL otherwise); multigrid and deflation options are not
+                                used by the solve */
+    double cex_beta2;        /* C_ex shift; 0 (default): the paper's, 1/k in 1D, 1/(3k) in 2D */
 } hh_solver_opts;
 
 typedef struct {

@@ -42,7 +42,9 @@ class SolverOpts(ctypes.Structure):
                 ("autotune", ctypes.c_int), ("ortho", ctypes.c_int), ("defl_direct_solver", ctypes.c_int),
                 ("mg_coarse", ctypes.c_int),
                 ("defl_z", ctypes.c_int),
-                ("defl_eps", ctypes.c_double)]
+                ("defl_eps", ctypes.c_double),
+                ("precond", ctypes.c_int),
+                ("cex_beta2", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -63,6 +63,8 @@ void hh_default_opts(hh_solver_opts* o) {
     o->mg_coarse = 0;
     o->defl_z = 0;
     o->defl_eps = 0.0;
+    o->precond = 0;
+    o->cex_beta2 = 0.0;
 }
 
 const char* hh_last_error(void) { return g_err.c_str(); }

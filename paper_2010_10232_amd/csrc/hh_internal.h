@@ -349,9 +349,11 @@ template <class T>
 void launch_vcycle_tail(const TailDesc<T>* desc, const void* img, int img16, const cx<T>* minv, int P, int l0,
                         int lds_bytes, const cx<T>* b, cx<T>* x,
                         hipStream_t s);   // P: degree of 2D levels (unrolled form), 0: any
-// e = (Vy (x) Vx) diag(dinv) (Vy (x) Vx)^T c on an [n2][n1] grid (t1, t2: N-vector scratch)
+// e = (Vy (x) Vx) diag(dinv) (Vy (x) Vx)^T c on an [n2][n1] grid (t1, t2: N-vector scratch);
+// with cdinv the diagonal is complex (cdinv used, dinv ignored)
 void launch_fdm_solve(int n2, int n1, const double* Vx, const double* VxT, const double* Vy, const double* dinv,
-                      const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s);
+                      const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s,
+                      const cx<double>* cdinv = nullptr);
 // Krylov kernels
 int reduction_blocks(long long N);
 void launch_norm_init(long long N, const cx<double>* r, KrylovDev& k, hipStream_t s);  // beta = ||r||, g = [beta,0..], state reset

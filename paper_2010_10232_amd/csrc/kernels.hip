@@ -435,7 +435,8 @@ constexpr int FDM_KC = 64;
 template <bool LEFT_REAL>
 __global__ __launch_bounds__(256) void fdm_gemm_kernel(int M, int N, int K, const double* __restrict__ W, int wsr,
                                                        int wsc, const cx<double>* __restrict__ X, int xsr, int xsc,
-                                                       const double* __restrict__ scale, cx<double>* __restrict__ Y) {
+                                                       const double* __restrict__ scale,
+                                                       const cx<double>* __restrict__ cscale, cx<double>* __restrict__ Y) {
     // LEFT_REAL: Ws[m][k] (32 x KC), Xs[k][n] (KC x 32); else Xs[m][k], Ws[k][n]
     constexpr int WR = LEFT_REAL ? 32 : FDM_KC, WC = LEFT_REAL ? FDM_KC : 32;
     constexpr int XR = LEFT_REAL ? FDM_KC : 32, XC = LEFT_REAL ? 32 : FDM_KC;
@@ -503,8 +504,13 @@ __global__ __launch_bounds__(256) void fdm_gemm_kernel(int M, int N, int K, cons
             const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * jj;
             if (m >= M || n >= N) continue;
             const size_t o = (size_t)m * N + n;
-            const double d = scale ? scale[o] : 1.0;
-            Y[o] = {ar[i][jj] * d, ai[i][jj] * d};
+            if (cscale) {
+                const cx<double> d = cscale[o];
+                Y[o] = {ar[i][jj] * d.re - ai[i][jj] * d.im, ar[i][jj] * d.im + ai[i][jj] * d.re};
+            } else {
+                const double d = scale ? scale[o] : 1.0;
+                Y[o] = {ar[i][jj] * d, ai[i][jj] * d};
+            }
         }
 }
 
@@ -520,6 +526,7 @@ __global__ __launch_bounds__(FDM2_TB) void fdm_pass_kernel(int n2, int n1, const
                                                            int lsc, const cx<double>* __restrict__ X,
                                                            const double* __restrict__ R,
                                                            const double* __restrict__ scale,
+                                                           const cx<double>* __restrict__ cscale,
                                                            cx<double>* __restrict__ Y) {
     __shared__ double Ls[FDM2_RB][FDM2_NMAX];
     __shared__ cx<double> P[FDM2_NMAX / FDM2_CH][FDM2_RB][FDM2_NMAX];
@@ -588,33 +595,41 @@ __global__ __launch_bounds__(FDM2_TB) void fdm_pass_kernel(int n2, int n1, const
                 ai += P[gg][r][c].im;
             }
             const size_t o = (size_t)row * n1 + c;
-            const double d = scale ? scale[o] : 1.0;
-            Y[o] = {ar * d, ai * d};
+            if (cscale) {
+                const cx<double> d = cscale[o];
+                Y[o] = {ar * d.re - ai * d.im, ar * d.im + ai * d.re};
+            } else {
+                const double d = scale ? scale[o] : 1.0;
+                Y[o] = {ar * d, ai * d};
+            }
         }
     }
 }
 
 void launch_fdm_solve(int n2, int n1, const double* Vx, const double* VxT, const double* Vy, const double* dinv,
-                      const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s) {
-    meter(40.0 * n1 * (double)n2 + 8.0 * ((double)n1 * n1 + (double)n2 * n2),
-          8.0 * n1 * (double)n2 * (n1 + n2) + 8.0 * n1 * (double)n2);
+                      const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s,
+                      const cx<double>* cdinv) {
+    // c, e, 1/D (complex: twice the bytes) and both eigenvector matrices once
+    meter((cdinv ? 48.0 : 40.0) * n1 * (double)n2 + 8.0 * ((double)n1 * n1 + (double)n2 * n2),
+          8.0 * n1 * (double)n2 * (n1 + n2) + (cdinv ? 16.0 : 8.0) * n1 * (double)n2);
+    const double* rd = cdinv ? nullptr : dinv;
     if (n1 <= FDM2_NMAX && n2 <= FDM2_NMAX) {
         const dim3 g((unsigned)((n2 + FDM2_RB - 1) / FDM2_RB)), b(FDM2_TB);
         // T2 = (Vy^T C Vx) ./ D
-        hipLaunchKernelGGL(fdm_pass_kernel, g, b, 0, s, n2, n1, Vy, 1, n2, c, Vx, dinv, t2);
+        hipLaunchKernelGGL(fdm_pass_kernel, g, b, 0, s, n2, n1, Vy, 1, n2, c, Vx, rd, cdinv, t2);
         // e = Vy T2 Vx^T
-        hipLaunchKernelGGL(fdm_pass_kernel, g, b, 0, s, n2, n1, Vy, n2, 1, t2, VxT, nullptr, e);
+        hipLaunchKernelGGL(fdm_pass_kernel, g, b, 0, s, n2, n1, Vy, n2, 1, t2, VxT, nullptr, nullptr, e);
         return;
     }
     const dim3 g((unsigned)((n1 + 31) / 32), (unsigned)((n2 + 31) / 32)), b(256);
     // T1 = C Vx
-    hipLaunchKernelGGL(fdm_gemm_kernel<false>, g, b, 0, s, n2, n1, n1, Vx, n1, 1, c, n1, 1, nullptr, t1);
+    hipLaunchKernelGGL(fdm_gemm_kernel<false>, g, b, 0, s, n2, n1, n1, Vx, n1, 1, c, n1, 1, nullptr, nullptr, t1);
     // T2 = (Vy^T T1) ./ D
-    hipLaunchKernelGGL(fdm_gemm_kernel<true>, g, b, 0, s, n2, n1, n2, Vy, 1, n2, t1, n1, 1, dinv, t2);
+    hipLaunchKernelGGL(fdm_gemm_kernel<true>, g, b, 0, s, n2, n1, n2, Vy, 1, n2, t1, n1, 1, rd, cdinv, t2);
     // T1 = T2 Vx^T
-    hipLaunchKernelGGL(fdm_gemm_kernel<false>, g, b, 0, s, n2, n1, n1, Vx, 1, n1, t2, n1, 1, nullptr, t1);
+    hipLaunchKernelGGL(fdm_gemm_kernel<false>, g, b, 0, s, n2, n1, n1, Vx, 1, n1, t2, n1, 1, nullptr, nullptr, t1);
     // e = Vy T1
-    hipLaunchKernelGGL(fdm_gemm_kernel<true>, g, b, 0, s, n2, n1, n2, Vy, n2, 1, t1, n1, 1, nullptr, e);
+    hipLaunchKernelGGL(fdm_gemm_kernel<true>, g, b, 0, s, n2, n1, n2, Vy, n2, 1, t1, n1, 1, nullptr, nullptr, e);
 }
 
 // --------------------------------------------------------------------------

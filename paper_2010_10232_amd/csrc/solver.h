@@ -84,6 +84,11 @@ struct SolverImpl {
     bool zadp = false;
     Transfer ztr{};
     DevBuf zprow0x, zprowx, zpcol0x, zpcolx, zprow0y, zprowy, zpcol0y, zpcoly;
+    // C_ex (precond = 1): exact inverse of K - (1 + i beta2) M_k on the finest
+    // level by fast diagonalisation (eigenvectors of level 0, complex 1 / D)
+    bool cex = false;
+    double cex_b2 = 0.0;
+    DevBuf cexVx, cexVxT, cexVy, cexDinv, cexT1, cexT2;
     // levels l < defl_end() are deflated (a deflation level lies below them);
     // 1 .. defl_end() - 1 are the inner FGMRES levels
     int defl_end() const { return zadp ? 1 : Lz; }

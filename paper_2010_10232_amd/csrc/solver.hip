@@ -205,6 +205,9 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(o.defl_z == 0 || o.defl_z == 1, "defl_z is 0 (knot insertion) or 1 (ADP)");
     HH_REQUIRE(o.defl_z == 0 || o.defl_mode == 1, "ADP deflation vectors (defl_z = 1) are two-level only (defl_mode = 1)");
     HH_REQUIRE(std::isfinite(o.defl_eps), "defl_eps must be finite");
+    HH_REQUIRE(o.precond == 0 || o.precond == 1, "precond is 0 (deflated multigrid CSLP) or 1 (C_ex)");
+    HH_REQUIRE(o.precond == 0 || P.k_mode == 0, "C_ex (precond = 1) is built for constant k only");
+    HH_REQUIRE(std::isfinite(o.cex_beta2) && o.cex_beta2 >= 0.0, "cex_beta2 must be finite and >= 0");
     HH_REQUIRE(o.mg_min_elems >= 2, "mg_min_elems must be >= 2");
     HH_REQUIRE(o.defl_mode >= 0 && o.defl_mode <= 2, "defl_mode must be 0, 1 or 2");
     HH_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
@@ -536,6 +539,32 @@ void SolverImpl::setup(hipStream_t s) {
                 Lz = l;
                 break;
             }
+    }
+    // C_ex: M_ex = K - (1 + i beta2) k^2 M is separable like E, so its exact
+    // inverse is a fast diagonalisation of the finest level with complex 1 / D
+    cex = o.precond == 1;
+    if (cex) {
+        const LevelDev& l0 = *lev[0];
+        cex_b2 = o.cex_beta2 > 0.0 ? o.cex_beta2 : (is2d ? 1.0 / (3.0 * P.k) : 1.0 / P.k);
+        std::vector<double> Vx, Vy, lx, ly;
+        axis_eigen(l0.ax, Vx, lx);
+        axis_eigen(l0.ay, Vy, ly);
+        const zd g(k2c, cex_b2 * k2c);
+        std::vector<cx<double>> dinv((size_t)l0.N);
+        for (int a = 0; a < l0.n2; ++a)
+            for (int b = 0; b < l0.n1; ++b) {
+                const zd d = 1.0 / (zd(ly[a] + lx[b]) - g);
+                dinv[(size_t)a * l0.n1 + b] = {d.real(), d.imag()};
+            }
+        std::vector<double> VxT(Vx.size());
+        for (int a = 0; a < l0.n1; ++a)
+            for (int b = 0; b < l0.n1; ++b) VxT[(size_t)b * l0.n1 + a] = Vx[(size_t)a * l0.n1 + b];
+        upload(cexVx, Vx);
+        upload(cexVxT, VxT);
+        upload(cexVy, Vy);
+        upload(cexDinv, dinv);
+        cexT1.alloc((size_t)l0.N * 16);
+        cexT2.alloc((size_t)l0.N * 16);
     }
     // ADP deflation vectors: a deflation level of their own after the
     // multigrid levels, with E = Z^T A Z as Galerkin bands (constant k: separable)
@@ -1070,6 +1099,12 @@ bool SolverImpl::precond_vcycle(int l, const cx<double>* b, cx<double>* x, hipSt
 }
 
 void SolverImpl::T_apply(int l, const cx<double>* v, cx<double>* z, hipStream_t s) {
+    if (cex && l == 0) {
+        const LevelDev& l0 = *lev[0];
+        launch_fdm_solve(l0.n2, l0.n1, cexVx.as<double>(), cexVxT.as<double>(), cexVy.as<double>(), nullptr, v,
+                         cexT1.as<cx<double>>(), cexT2.as<cx<double>>(), z, s, cexDinv.as<cx<double>>());
+        return;
+    }
     if (l >= defl_end()) {
         precond_vcycle(l, v, z, s);
         return;
