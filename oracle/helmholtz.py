@@ -8,6 +8,13 @@ matrix.  The paper prints the variational form with the opposite sign of the
 k^2 term; the model problems and the eigenvalues j^2 pi^2 - k^2 it gives for
 MP 1-B (section 3) fix the sign used here.
 
+MP 1-A (section 2.1, option sommerfeld=True, 1D, constant k): u(0) = u0 and the
+radiation condition u' - i k u = 0 at x = 1.  The first basis function is
+eliminated (its coefficient is u0, moved to the right-hand side), the last one
+is kept, and the boundary term of the weak form adds -i k phi_i(1) phi_j(1):
+A = K - k^2 M - i k B with B = e_n e_n^T (only the last function is nonzero at
+x = 1).
+
 A non-constant wave number is constant on each element of the finest mesh
 (its value at the element centroid); M_k = sum_e k_e^2 (m_e^y (x) m_e^x).
 Vectors are ordered with x fastest: index i2 * n1 + i1 over interior
@@ -26,9 +33,12 @@ class Problem:
     (n_el_y, n_el_x) in 2D or (n_el,) in 1D; otherwise the constant k is used.
     """
 
-    def __init__(self, dim, p, n_el, k, k_elem=None):
+    def __init__(self, dim, p, n_el, k, k_elem=None, sommerfeld=False):
         if dim not in (1, 2):
             raise ValueError("dim must be 1 or 2")
+        if sommerfeld and (dim != 1 or k_elem is not None):
+            raise ValueError("the radiation condition (MP 1-A) is built for 1D, constant k")
+        self.sommerfeld = bool(sommerfeld)
         self.dim = dim
         self.p = int(p)
         self.n_el = [int(n_el)] * dim if np.isscalar(n_el) else [int(v) for v in n_el]
@@ -45,10 +55,49 @@ class Problem:
         return None if self.k_elem is None else self.k_elem ** 2
 
 
-def matrices_1d(b, p):
-    """Interior (Dirichlet-eliminated) 1D stiffness and mass as sparse matrices."""
+def matrices_1d(b, p, keep_last=False):
+    """Interior (Dirichlet-eliminated) 1D stiffness and mass as sparse matrices;
+    keep_last: only the first function is eliminated (radiation condition at x = 1)."""
     K, M = bs.assemble_full(b, p)
+    if keep_last:
+        return sp.csr_matrix(K[1:, 1:]), sp.csr_matrix(M[1:, 1:])
     return sp.csr_matrix(bs.interior(K)), sp.csr_matrix(bs.interior(M))
+
+
+def boundary_operator(prob):
+    """B of the radiation condition (MP 1-A): 1 on the last unknown, else None."""
+    if not prob.sommerfeld:
+        return None
+    n = prob.n_el[0] + prob.p - 1
+    return sp.csr_matrix(([1.0], ([n - 1], [n - 1])), shape=(n, n))
+
+
+def dirichlet_lift_rhs(prob, u0=1.0):
+    """MP 1-A: f = -u0 (K - k^2 M)[:, 0] on the unknowns (the eliminated first function
+    carries the boundary value u0; the equation itself has no source)."""
+    b = bs.uniform_breakpoints(prob.n_el[0])
+    K, M = bs.assemble_full(b, prob.p)
+    col = K[1:, 0] - prob.k ** 2 * M[1:, 0]
+    return (-u0 * col).astype(np.complex128)
+
+
+def l2_error_1d(prob, u, exact, u0=1.0, nq=None):
+    """Continuous L2 norm of (u_h - exact) on [0, 1], u_h = u0 phi_0 + sum_i u_i phi_i."""
+    p = prob.p
+    nq = nq or (p + 4)
+    b = bs.uniform_breakpoints(prob.n_el[0])
+    U = np.zeros(prob.n_el[0] + p, dtype=np.complex128)
+    U[0] = u0
+    U[1:1 + len(u)] = u
+    gx, gw = bs.gauss_legendre(nq)
+    err2 = 0.0
+    for e in range(prob.n_el[0]):
+        lo, hi = b[e], b[e + 1]
+        jac = 0.5 * (hi - lo)
+        for x, w in zip(lo + (gx + 1) * jac, gw * jac):
+            uh = bs.basis_all(b, p, x, elem=e) @ U
+            err2 += w * abs(uh - exact(x)) ** 2
+    return float(np.sqrt(err2))
 
 
 def weighted_mass_1d(b, p, w_elem):
@@ -100,7 +149,7 @@ def fine_operators(prob):
     p = prob.p
     if prob.dim == 1:
         b = bs.uniform_breakpoints(prob.n_el[0])
-        K, M = matrices_1d(b, p)
+        K, M = matrices_1d(b, p, keep_last=prob.sommerfeld)
         if prob.k_elem is None:
             Mk = prob.k ** 2 * M
         else:

@@ -42,7 +42,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from . import bspline as bs
-from .helmholtz import fine_operators, weighted_mass_1d, weighted_mass_2d
+from .helmholtz import boundary_operator, fine_operators, weighted_mass_1d, weighted_mass_2d
 
 
 class Options:
@@ -90,11 +90,14 @@ def build_hierarchy(prob, opts):
     levels = []
     lv = Level()
     lv.bks, lv.K, lv.Mk, lv.P = bks, K, Mk, None
+    lv.B = boundary_operator(prob)
     levels.append(lv)
     while max(len(b) - 1 for b in levels[-1].bks) > opts.mg_min_elems:
         prev = levels[-1]
         cb = [bs.halve_breakpoints(b) for b in prev.bks]
-        Ps = [sp.csr_matrix(bs.knot_insertion_prolongation(fb, c, p)[1:-1, 1:-1])
+        # interior rows and columns (radiation condition: the last function is kept)
+        hi = None if prob.sommerfeld else -1
+        Ps = [sp.csr_matrix(bs.knot_insertion_prolongation(fb, c, p)[1:hi, 1:hi])
               for fb, c in zip(prev.bks, cb)]
         P = Ps[0] if prob.dim == 1 else sp.kron(Ps[1], Ps[0]).tocsr()
         lv = Level()
@@ -102,17 +105,20 @@ def build_hierarchy(prob, opts):
         lv.P = P
         lv.K = (P.T @ prev.K @ P).tocsr()
         lv.Mk = (P.T @ prev.Mk @ P).tocsr()
+        lv.B = None if prev.B is None else (P.T @ prev.B @ P).tocsr()
         levels.append(lv)
     k2 = prob.k2_elem
     for l, lv in enumerate(levels):
-        lv.n = [len(b) - 1 + p - 2 for b in lv.bks]
+        lv.n = [len(b) - 1 + p - (1 if prob.sommerfeld else 2) for b in lv.bks]
         lv.N = int(np.prod(lv.n))
-        lv.A = (lv.K - lv.Mk).tocsr()
+        # radiation condition: the unshifted boundary term -i k B in A and in M_beta
+        rad = 0 if lv.B is None else -1j * prob.k * lv.B
+        lv.A = (lv.K - lv.Mk + rad).tocsr()
         lv.Mk_mg = lv.Mk
         if opts.mg_coarse == 1 and k2 is not None and l > 0:
             k2 = coarse_mean(k2)
             lv.Mk_mg = rediscretised_mass(lv.bks, p, k2, prob.dim)
-        lv.Mb = (lv.K - opts.beta * lv.Mk_mg).tocsr()
+        lv.Mb = (lv.K - opts.beta * lv.Mk_mg + rad).tocsr()
         lv.D = lv.Mb.diagonal().copy()
         lv.gersh = gershgorin_bound(lv.Mb, lv.D)
         lv.omega = smoother_damping(l, lv.gersh, opts)
@@ -234,10 +240,14 @@ DENSE_E_MAX = 4096
 def exact_factor(E):
     """A function c -> E^-1 c for the real matrix E (complex c: real and imaginary
     parts solved separately, E being real): dense LU with partial pivoting for small E,
-    SuperLU (scipy.sparse.linalg.splu) otherwise."""
+    SuperLU (scipy.sparse.linalg.splu) otherwise.  A complex E (radiation condition)
+    is factored as it is."""
     if E.shape[0] <= DENSE_E_MAX:
         lu = sla.lu_factor(E.toarray())
         return lambda c: sla.lu_solve(lu, c)
+    if np.iscomplexobj(E.data):
+        lu = spla.splu(sp.csc_matrix(E))
+        return lambda c: lu.solve(np.asarray(c, dtype=np.complex128))
     lu = spla.splu(sp.csc_matrix(E))
     return lambda c: lu.solve(np.ascontiguousarray(c.real)) + 1j * lu.solve(np.ascontiguousarray(c.imag))
 
