@@ -50,8 +50,10 @@ TRAFFIC_PREFIX = {1: "fine_op", 3: "arnoldi", 4: "stencil_op", 5: "symvb_tiles"}
 
 WORKLOADS = {
     # Gaussian random field k = 300 (1 + 0.3 g), p = 4, 960 x 960 elements: the default
-    # (direct deflation level 2, 58,564 unknowns, substructured E^-1)
-    "grf_k300_p4_960": dict(dim=2, p=4, n_el=960, grf=300.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=65536)),
+    # (direct deflation level 2, 58,564 unknowns, substructured E^-1; two inner FGMRES steps on
+    # deflation level 1; multigrid down to 30 elements per side, 1,089 unknowns solved densely)
+    "grf_k300_p4_960": dict(dim=2, p=4, n_el=960, grf=300.0, x0=(0.5, 0.5),
+                            opts=dict(defl_direct_max=65536, defl_inner_its=(2, 4, 2, 1, 1, 1, 1, 1), mg_min_elems=30)),
     # three-layer wedge, k0 = 150, p = 2 / 3 / 4, 480 x 480 elements (direct deflation level 1)
     "wedge_k150_p2_480": dict(dim=2, p=2, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=65536)),
     "wedge_k150_p3_480": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=65536)),

@@ -166,3 +166,13 @@ def test_field_specs_span_k_100_500_on_the_application_grid():
         assert k.min() >= 100.0 - 1e-9 and k.max() <= 500.0 + 1e-9
         assert not np.array_equal(k / s["kbar"], test_field / 300.0)
         assert all(0.3 <= v <= 0.7 for v in s["x0"])
+
+
+def test_bench_and_full_size_references_share_the_workload_options():
+    """The full-size oracle references are taken with the options the bench times."""
+    import sys
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    import make_full_size as MF
+    bench = _bench_module()
+    for name in ("grf_k300_p4_960", "wedge_k150_p2_480", "wedge_k150_p3_480", "wedge_k150_p4_480"):
+        assert bench.WORKLOADS[name]["opts"] == MF.WORKLOADS[name]["opts"], name
