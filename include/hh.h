@@ -48,7 +48,8 @@ typedef struct hh_cnn hh_cnn;
 
 /* Problem statement (section 2): unit interval / square, uniform open knot
  * vectors of degree p (ends repeated p+1 times, section 2.3.1), homogeneous
- * Dirichlet conditions, constant or element-wise wave number. */
+ * Dirichlet conditions, constant or element-wise wave number; optionally (MP
+ * 1-A, section 2.1) a radiation condition at the right end of a 1D problem. */
 typedef struct {
     int dim;               /* 1 or 2 */
     int p;                 /* B-spline degree, 1..5 */
@@ -58,6 +59,12 @@ typedef struct {
     const double* k_elem;  /* k_mode 1: HOST array of k (not k^2) per element,
                               x fastest, n_el[0] * n_el[1] values (n_el[0] in 1D);
                               copied, the caller may free it on return */
+    int bc_right;          /* 0: Dirichlet at x = 1; 1: the radiation condition u' - i k u = 0 at
+                              x = 1 (MP 1-A; dim 1 and constant k only, else HH_EINVAL): the last
+                              basis function is kept (n_el + p - 1 unknowns) and the boundary
+                              term -i k phi_i(1) phi_j(1) joins A and M_beta (unshifted) on every
+                              level; the left end stays Dirichlet (its value enters through
+                              hh_rhs_dirichlet_lift) */
 } hh_problem_desc;
 
 /* Preconditioner and Krylov parameters (hh_default_opts fills the defaults). */
@@ -226,6 +233,12 @@ hh_status hh_point_spans(const hh_problem* pr, const double* x0, int* spans);
 hh_status hh_rhs_point_source(const hh_problem* pr, const double* x0, double amp,
                               void* f_dev, void* stream);
 
+/* MP 1-A (section 2.1): the right-hand side of the boundary value u(0) = u0 with no
+ * source, f_i = -u0 (K - k^2 M)_{i,0}: the eliminated first basis function's
+ * column moved to the right-hand side.  Problems with bc_right = 1 only
+ * (HH_EINVAL otherwise).  f_dev: device, N complex doubles, overwritten. */
+hh_status hh_rhs_dirichlet_lift(const hh_problem* pr, double u0, void* f_dev, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc): the same load as
  * hh_rhs_point_source, bit-identical, with no device or heap allocation.  The
@@ -246,7 +259,8 @@ hh_status hh_rhs_point_source_noalloc(const hh_problem* pr, const double* x0, do
  * every entry of the tensor-product band (|i1 - j1| <= p and |i2 - j2| <= p in
  * range) is stored, columns ascending within a row.  Call with row_ptr NULL to
  * get *nnz only; otherwise row_ptr (N + 1), col_idx and val (capacity entries
- * each, host) are filled and HH_EINVAL is returned if capacity < nnz. */
+ * each, host) are filled and HH_EINVAL is returned if capacity < nnz.  Under the
+ * radiation condition (bc_right = 1) A is complex: which = 2 gives HH_EINVAL. */
 hh_status hh_export_csr(const hh_problem* pr, int which, long long* nnz, long long* row_ptr, int* col_idx,
                         double* val, long long capacity);
 

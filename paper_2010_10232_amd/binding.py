@@ -19,7 +19,7 @@ HH_EINVAL, HH_ENOMEM, HH_EHIP, HH_ENUMERIC = -1, -2, -3, -4
 OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 5, "T": 6, "EINV": 7, "K": 8, "MK": 9, "ZT": 10, "Z": 11}
 
 EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
-            "hh_point_spans", "hh_rhs_point_source", "hh_rhs_point_source_noalloc", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
+            "hh_point_spans", "hh_rhs_point_source", "hh_rhs_point_source_noalloc", "hh_rhs_dirichlet_lift", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
             "hh_level_info", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched", "hh_cnn_create",
             "hh_cnn_destroy", "hh_cnn_num_params", "hh_cnn_get_params", "hh_cnn_set_params", "hh_cnn_set_fused", "hh_cnn_loss_grad",
             "hh_cnn_train_step", "hh_solver_set_smoother", "hh_solver_capture", "hh_solver_captured",
@@ -29,7 +29,7 @@ EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destr
 class ProblemDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("p", ctypes.c_int), ("n_el", ctypes.c_int * 2),
                 ("k_mode", ctypes.c_int), ("k", ctypes.c_double),
-                ("k_elem", ctypes.POINTER(ctypes.c_double))]
+                ("k_elem", ctypes.POINTER(ctypes.c_double)), ("bc_right", ctypes.c_int)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -92,6 +92,7 @@ def load(path=LIB_PATH):
     lib.hh_point_spans.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.hh_rhs_point_source.argtypes = [vp, ctypes.POINTER(ctypes.c_double), dp, vp, vp]
     lib.hh_rhs_point_source_noalloc.argtypes = [vp, ctypes.POINTER(ctypes.c_double), dp, vp, vp]
+    lib.hh_rhs_dirichlet_lift.argtypes = [vp, dp, vp, vp]
     lib.hh_export_csr.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_longlong), vp, vp, vp, ctypes.c_longlong]
     lib.hh_setup.argtypes = [vp, ctypes.POINTER(SolverOpts), vp, ctypes.POINTER(vp)]
     lib.hh_solver_destroy.argtypes = [vp]
@@ -178,10 +179,11 @@ class Problem:
     """A Helmholtz problem on (0,1)^dim: degree p, n_el elements per direction,
     constant k or k_elem (k per finest element, x fastest)."""
 
-    def __init__(self, dim, p, n_el, k=None, k_elem=None):
+    def __init__(self, dim, p, n_el, k=None, k_elem=None, sommerfeld=False):
         lib = load()
         d = ProblemDesc()
         d.dim, d.p = int(dim), int(p)
+        d.bc_right = 1 if sommerfeld else 0
         ne = [int(n_el)] * 2 if np.isscalar(n_el) else [int(v) for v in n_el] + [1]
         d.n_el[0], d.n_el[1] = ne[0], ne[1]
         self._k_arr = None
@@ -224,6 +226,14 @@ class Problem:
             out = torch.empty(self.N, dtype=torch.complex128, device="cuda")
         x = (ctypes.c_double * 2)(*(list(x0) + [0.0] * (2 - len(x0))))
         _check(load().hh_rhs_point_source(self._h, x, float(amp), _ptr(out), _stream()))
+        return out
+
+    def dirichlet_lift(self, u0=1.0, out=None):
+        """MP 1-A right-hand side of the boundary value u(0) = u0 (problems with sommerfeld=True)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.complex128, device="cuda")
+        _check(load().hh_rhs_dirichlet_lift(self._h, float(u0), _ptr(out), _stream()))
         return out
 
     def point_source_noalloc(self, x0, out, amp=1.0):

@@ -129,6 +129,7 @@ hh_status hh_export_csr(const hh_problem* pr, int which, long long* nnz, long lo
     if (!pr || !nnz) throw Err{HH_EINVAL, "NULL argument"};
     if (which < 0 || which > 2) throw Err{HH_EINVAL, "which must be 0 (K), 1 (M_k) or 2 (A)"};
     const ProblemImpl& P = pr->impl;
+    if (P.somm && which == 2) throw Err{HH_EINVAL, "A is complex under the radiation condition (export K and M_k)"};
     const bool const_k = P.k_mode == 0;
     std::vector<double> S;
     if (!const_k) galerkin_mass_stencil(P.ax0, P.ay0, P.k2, S);
@@ -160,6 +161,14 @@ hh_status hh_rhs_point_source(const hh_problem* pr, const double* x0, double amp
     HH_TRY
     if (!pr || !x0 || !f_dev) throw Err{HH_EINVAL, "NULL argument"};
     rhs_point_source(pr->impl, x0, amp, (cx<double>*)f_dev, (hipStream_t)stream);
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_rhs_dirichlet_lift(const hh_problem* pr, double u0, void* f_dev, void* stream) {
+    HH_TRY
+    if (!pr || !f_dev) throw Err{HH_EINVAL, "NULL argument"};
+    rhs_dirichlet_lift(pr->impl, u0, (cx<double>*)f_dev, (hipStream_t)stream);
     return HH_OK;
     HH_CATCH
 }

@@ -130,6 +130,7 @@ struct Axis {
     std::vector<double> U;   // full open knot vector
     std::vector<double> Kb, Mb;  // interior bands [n][2p+1] (entry (i, i+d) at i*(2p+1)+d+p)
     std::vector<double> Me;      // element mass blocks [nel][(p+1)^2]
+    std::vector<double> K0, M0;  // first element: function 0 against functions 0..p (Dirichlet lift)
     std::vector<double> G;       // mass blocks of this level's basis on every finest element
     // prolongation from the next-coarser level (this axis is the fine side):
     int pw = 1, rw = 1;          // row width (coarse entries per fine row), column width
@@ -166,7 +167,8 @@ inline void visit_row(const Axis& ax, const Axis& ay, bool const_k, double k2c, 
 
 // Host-side builders (setup.cpp).
 void gauss_legendre(int n, double* x, double* w);
-Axis make_axis(int p, int nel_fine, int level);
+// keep_last: only the first function is eliminated (radiation condition at the right end)
+Axis make_axis(int p, int nel_fine, int level, bool keep_last = false);
 Axis make_trivial_axis();
 void make_transfer(Axis& fine, const Axis& coarse);
 // ADP deflation vectors along one direction (zf: their tables on the fine
@@ -220,6 +222,9 @@ struct OpArgs {
     T omega;
     cx<T>* xo;             // MODE_RESID: if set, also xo = omega D^-1 y (a first sweep on y)
     const cx<T>* yadd;     // MODE_SMOOTH: if set, y = the swept x + yadd
+    // radiation condition: y[bnd_I] += i bnd_im x[bnd_I] (bnd_I < 0: none)
+    long long bnd_I;
+    T bnd_im;
 };
 
 struct Transfer {

@@ -236,6 +236,11 @@ __global__ __launch_bounds__(64) void op_kernel(OpArgs<T> a, int ty) {
                 yr -= are * vr[0] - aim * vi[0];
                 yi -= are * vi[0] + aim * vr[0];
             }
+            if ((long long)I == a.bnd_I) {   // radiation condition: + i bnd_im x on the last unknown
+                const cx<T> xb = a.x[I];
+                yr -= a.bnd_im * xb.im;
+                yi += a.bnd_im * xb.re;
+            }
             cx<T> out;
             if (MODE == MODE_APPLY) {
                 out = {yr, yi};
@@ -341,6 +346,11 @@ __global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
     if (KIND == KIND_STENCIL) {
         yr -= are * vr - aim * vi;
         yi -= are * vi + aim * vr;
+    }
+    if (I == a.bnd_I) {   // radiation condition: + i bnd_im x on the last unknown
+        const cx<T> xb = a.x[I];
+        yr -= a.bnd_im * xb.im;
+        yi += a.bnd_im * xb.re;
     }
     cx<T> out;
     if (MODE == MODE_APPLY) {

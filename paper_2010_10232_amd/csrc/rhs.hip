@@ -123,4 +123,18 @@ void rhs_point_source_noalloc(const ProblemImpl& P, const double* x0, double amp
     HH_HIP(hipStreamSynchronize(s));
 }
 
+// MP 1-A: the boundary value u(0) = u0 carried by the eliminated first basis
+// function, moved to the right-hand side: f_{j-1} = -u0 (K - k^2 M)_{j,0} for the
+// functions j = 1..p that share the first element with it (zero elsewhere).
+void rhs_dirichlet_lift(const ProblemImpl& P, double u0, cx<double>* f, hipStream_t s) {
+    if (!P.somm) throw Err{HH_EINVAL, "the Dirichlet lift is defined for problems with bc_right = 1"};
+    if (!std::isfinite(u0)) throw Err{HH_EINVAL, "u0 must be finite"};
+    const Axis& a = P.ax0;
+    std::vector<cx<double>> h((size_t)a.n, cx<double>{0.0, 0.0});
+    const double k2 = P.k * P.k;
+    for (int j = 1; j <= P.p && j - 1 < a.n; ++j) h[j - 1] = {-u0 * (a.K0[j] - k2 * a.M0[j]), 0.0};
+    HH_HIP(hipMemcpyAsync(f, h.data(), h.size() * sizeof(cx<double>), hipMemcpyHostToDevice, s));
+    HH_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace hh

@@ -109,13 +109,13 @@ Axis make_trivial_axis() {
     return a;
 }
 
-Axis make_axis(int p, int nel_fine, int level) {
+Axis make_axis(int p, int nel_fine, int level, bool keep_last) {
     Axis a;
     a.p = p;
     a.level = level;
     a.nel_fine = nel_fine;
     a.nel = level_elems(nel_fine, level);
-    a.n = a.nel + p - 2;
+    a.n = a.nel + p - (keep_last ? 1 : 2);
     a.off = 1;
     // breakpoints: finest indices j * 2^level (j < nel) and the last one
     std::vector<int> idx;
@@ -145,6 +145,10 @@ Axis make_axis(int p, int nel_fine, int level) {
                     me[i * q + j] += gw[g] * jac * N[i] * N[j];
                 }
         }
+        if (e == 0) {
+            a.K0.assign(ke, ke + q);
+            a.M0.assign(me, me + q);
+        }
         for (int i = 0; i < q; ++i)
             for (int j = 0; j < q; ++j) {
                 Kf[(size_t)(e + i) * bw + (j - i + p)] += ke[i * q + j];
@@ -152,7 +156,8 @@ Axis make_axis(int p, int nel_fine, int level) {
                 a.Me[(size_t)e * q * q + i * q + j] = me[i * q + j];
             }
     }
-    // interior bands: drop the first and last function (homogeneous Dirichlet)
+    // interior bands: drop the first and last function (homogeneous Dirichlet; with
+    // keep_last only the first)
     a.Kb.assign((size_t)a.n * bw, 0.0);
     a.Mb.assign((size_t)a.n * bw, 0.0);
     for (int i = 0; i < a.n; ++i)

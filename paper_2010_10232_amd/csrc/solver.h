@@ -14,6 +14,7 @@ struct ProblemImpl {
     int dim = 2, p = 3, nel[2] = {1, 1};
     int k_mode = 0;
     double k = 0.0;
+    bool somm = false;        // radiation condition at x = 1 (1D, constant k; MP 1-A)
     std::vector<double> k2;   // k^2 per finest element [nel_y][nel_x] (1D: [1][nel_x])
     mutable DevBuf k2_dev;    // the same on the device (uploaded by hh_assemble on its stream, else by hh_setup)
     Axis ax0, ay0;            // finest-level axes
@@ -26,6 +27,9 @@ struct LevelDev {
     long long N = 1;
     double omega = 0.8, gersh = 0.0;
     int kind = KIND_SEP;
+    // radiation condition: the boundary term i bnd_im x on unknown bnd_I (-1: none)
+    long long bnd_I = -1;
+    double bnd_im = 0.0;
     int ty64 = 0, ty32 = 0;   // level-operator strip height (0: fixed rule), FP64 / FP32
     DevBuf Kx, Mx, Ky, My;
     DevBuf S64, S32;
@@ -95,6 +99,7 @@ struct SolverImpl {
     std::vector<std::unique_ptr<LevelDev>> lev;
     DevBuf Minv64, Minv32;   // dense inverse of M_beta at level L (complex)
     DevBuf Einv;             // dense inverse of A at level Lz (real; variable k)
+    DevBuf EinvC;            // dense inverse of the complex E (radiation condition), row-major
     // constant k: E^-1 at level Lz by fast diagonalisation (1D eigenvectors and 1 / D)
     bool fdm = false;
     DevBuf fdmVx, fdmVxT, fdmVy, fdmDinv, fdmT1, fdmT2;
@@ -184,6 +189,8 @@ ProblemImpl* build_problem(const hh_problem_desc* d);
 // the fixed staging array (no allocation).
 void rhs_point_source(const ProblemImpl& P, const double* x0, double amp, cx<double>* f, hipStream_t s);
 void rhs_point_source_noalloc(const ProblemImpl& P, const double* x0, double amp, cx<double>* f, hipStream_t s);
+// f = -u0 (K - k^2 M)_{:,0} (MP 1-A: the boundary value at x = 0 moved to the right-hand side)
+void rhs_dirichlet_lift(const ProblemImpl& P, double u0, cx<double>* f, hipStream_t s);
 
 }  // namespace hh
 

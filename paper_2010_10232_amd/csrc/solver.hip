@@ -36,7 +36,11 @@ ProblemImpl* build_problem(const hh_problem_desc* d) {
     HH_REQUIRE(nx >= 2 && (d->dim == 1 || ny >= 2), "at least 2 elements per direction");
     HH_REQUIRE(nx <= (1 << 20) && ny <= (1 << 20), "too many elements");
     HH_REQUIRE(d->k_mode == 0 || d->k_mode == 1, "k_mode must be 0 or 1");
+    HH_REQUIRE(d->bc_right == 0 || d->bc_right == 1, "bc_right must be 0 (Dirichlet) or 1 (radiation condition)");
+    HH_REQUIRE(d->bc_right == 0 || (d->dim == 1 && d->k_mode == 0),
+               "the radiation condition (bc_right = 1) is built for 1D problems with constant k");
     auto* P = new ProblemImpl();
+    P->somm = d->bc_right == 1;
     P->dim = d->dim;
     P->p = d->p;
     P->nel[0] = nx;
@@ -63,7 +67,7 @@ ProblemImpl* build_problem(const hh_problem_desc* d) {
             P->k2[i] = kv * kv;
         }
     }
-    P->ax0 = make_axis(P->p, nx, 0);
+    P->ax0 = make_axis(P->p, nx, 0, P->somm);
     P->ay0 = d->dim == 2 ? make_axis(P->p, ny, 0) : make_trivial_axis();
     return P;
 }
@@ -208,6 +212,8 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(o.precond == 0 || o.precond == 1, "precond is 0 (deflated multigrid CSLP) or 1 (C_ex)");
     HH_REQUIRE(o.precond == 0 || P.k_mode == 0, "C_ex (precond = 1) is built for constant k only");
     HH_REQUIRE(std::isfinite(o.cex_beta2) && o.cex_beta2 >= 0.0, "cex_beta2 must be finite and >= 0");
+    HH_REQUIRE(!P.somm || (o.precond == 0 && o.defl_z == 0),
+               "the radiation condition is built with the knot-insertion deflation and the multigrid CSLP");
     HH_REQUIRE(o.mg_min_elems >= 2, "mg_min_elems must be >= 2");
     HH_REQUIRE(o.defl_mode >= 0 && o.defl_mode <= 2, "defl_mode must be 0, 1 or 2");
     HH_REQUIRE(o.precision == 0 || o.precision == 1, "precision must be 0 or 1");
@@ -220,7 +226,7 @@ void SolverImpl::setup(hipStream_t s) {
     // multigrid levels by knot halving
     for (int l = 0;; ++l) {
         auto lv = std::make_unique<LevelDev>();
-        lv->ax = l == 0 ? P.ax0 : make_axis(p, P.nel[0], l);
+        lv->ax = l == 0 ? P.ax0 : make_axis(p, P.nel[0], l, P.somm);
         lv->ay = is2d ? (l == 0 ? P.ay0 : make_axis(p, P.nel[1], l)) : make_trivial_axis();
         const int mx = std::max(lv->ax.nel, is2d ? lv->ay.nel : 0);
         HH_REQUIRE(lv->ax.n >= 1 && lv->ay.n >= 1, "level without interior unknowns");
@@ -263,6 +269,12 @@ void SolverImpl::setup(hipStream_t s) {
             Shg[l] = std::move(Sh[l]);
             redisc_mass_stencil(lv.ax, lv.ay, k2l, Sh[l]);
         }
+        // radiation condition (MP 1-A): -i k on the last unknown of every level (the
+        // Galerkin image of e_n e_n^T, the last function being interpolatory at x = 1)
+        if (P.somm) {
+            lv.bnd_I = lv.N - 1;
+            lv.bnd_im = -P.k;
+        }
         // Jacobi diagonal of M_beta and the Gershgorin bound of D^-1 M_beta
         std::vector<cx<double>> dinv((size_t)lv.N);
         std::vector<cx<float>> dinv32((size_t)lv.N);
@@ -271,7 +283,8 @@ void SolverImpl::setup(hipStream_t s) {
             zd diag = 0.0;
             double rowsum = 0.0;
             visit_row(lv.ax, lv.ay, const_k, k2c, Sh[l], I, [&](long long J, double kv, double mv) {
-                const zd e = kv - beta * mv;
+                zd e = kv - beta * mv;
+                if (J == I && I == lv.bnd_I) e += zd(0.0, lv.bnd_im);
                 rowsum += std::abs(e);
                 if (J == I) diag = e;
             });
@@ -355,6 +368,7 @@ void SolverImpl::setup(hipStream_t s) {
         for (long long I = 0; I < lc.N; ++I)
             visit_row(lc.ax, lc.ay, const_k, k2c, Sh[L], I,
                       [&](long long J, double kv, double mv) { A[(size_t)I * nL + J] += kv - beta * mv; });
+        if (lc.bnd_I >= 0) A[(size_t)lc.bnd_I * nL + lc.bnd_I] += zd(0.0, lc.bnd_im);
         invert_complex(nL, A);
         std::vector<cx<double>> m64((size_t)nL * nL);
         std::vector<cx<float>> m32((size_t)nL * nL);
@@ -388,7 +402,9 @@ void SolverImpl::setup(hipStream_t s) {
                    al16(8LL * t.nf1 * t.pw1) + al16(4LL * t.nf2) + al16(8LL * t.nf2 * t.pw2) + al16(4LL * t.nc1) +
                    al16(8LL * t.nc1 * t.rw1) + al16(4LL * t.nc2) + al16(8LL * t.nc2 * t.rw2);
         };
-        for (int l = 1; l < L && L < kTailLevels; ++l) {
+        // (the tail has no boundary term: problems with the radiation condition run
+        // every level as separate kernels)
+        for (int l = 1; l < L && L < kTailLevels && !P.somm; ++l) {
             long long bytes = 0;
             for (int m = l; m <= L; ++m) bytes += 3 * lev[m]->N * (long long)sizeof(cx<double>) + coef_bytes(m);
             // measured on MP 2-A: a level of 1681 unknowns runs faster as separate
@@ -625,7 +641,22 @@ void SolverImpl::setup(hipStream_t s) {
     // the direct deflation level's mass stencil (variable k)
     const std::vector<double>& Sz =
         zadp ? Sadp : (Lz > 0 && !Shg[Lz].empty() ? Shg[Lz] : Sh[std::min(Lz, L)]);
-    if (Lz > 0 && const_k) {
+    if (Lz > 0 && P.somm) {
+        // radiation condition: E = Z^T A Z is complex (boundary term on its last
+        // unknown) and not separable; its dense inverse, formed on the host
+        LevelDev& lz = *lev[Lz];
+        nZ = (int)lz.N;
+        HH_REQUIRE(nZ <= 4096, "direct deflation level too large for the radiation condition (at most 4096 unknowns)");
+        std::vector<zd> Ez((size_t)nZ * nZ, 0.0);
+        for (long long I = 0; I < lz.N; ++I)
+            visit_row(lz.ax, lz.ay, const_k, k2c, Sz, I,
+                      [&](long long J, double kv, double mv) { Ez[(size_t)I * nZ + J] += kv - mv; });
+        Ez[(size_t)lz.bnd_I * nZ + lz.bnd_I] += zd(0.0, lz.bnd_im);
+        invert_complex(nZ, Ez);
+        std::vector<cx<double>> ez((size_t)nZ * nZ);
+        for (size_t i = 0; i < Ez.size(); ++i) ez[i] = {Ez[i].real(), Ez[i].imag()};
+        upload(EinvC, ez);
+    } else if (Lz > 0 && const_k) {
         // separable E: exact inverse by fast diagonalisation, no dense matrix
         LevelDev& lz = *lev[Lz];
         nZ = (int)lz.N;
@@ -694,7 +725,7 @@ void SolverImpl::setup(hipStream_t s) {
             sub->self_check = m ? substruct_check(s) : c0;
         }
     }
-    if (Lz > 0 && !const_k && !sub) {
+    if (Lz > 0 && !const_k && !sub && !P.somm) {
         // variable k: dense inverse of E, assembled on the device from its
         // nonzeros (E and its inverse are symmetric, so row- and column-major
         // storage coincide)
@@ -943,6 +974,10 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
     a.xo = xo;
     a.yadd = mode == MODE_SMOOTH ? yadd : nullptr;
     a.ty = sizeof(T) == 8 ? lv.ty64 : lv.ty32;
+    // the radiation condition's boundary term belongs to A and M_beta, not to K or M_k alone
+    const bool with_bnd = !mass_only && (are != 0.0 || aim != 0.0);
+    a.bnd_I = with_bnd ? lv.bnd_I : -1;
+    a.bnd_im = (T)lv.bnd_im;
     // band half-widths of the level (the degree p, or wider on the ADP level)
     const int px = lv.ax.p, py = prob->dim == 2 ? lv.ay.p : 0;
     double st_bytes = 0.0;
@@ -1223,7 +1258,10 @@ double SolverImpl::substruct_check(hipStream_t s) {
 void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStream_t s) {
     if (l == Lz) {
         tstart(2, s);
-        if (fdm) {
+        if (EinvC.p) {
+            launch_gemv<cx<double>, double>(nZ, EinvC.as<cx<double>>(), c, e, s);
+            tstop(2, 16.0 * nZ * (double)nZ + 32.0 * nZ, s);
+        } else if (fdm) {
             const LevelDev& lz = *lev[Lz];
             launch_fdm_solve(lz.n2, lz.n1, fdmVx.as<double>(), fdmVxT.as<double>(), fdmVy.as<double>(),
                              fdmDinv.as<double>(), c, fdmT1.as<cx<double>>(), fdmT2.as<cx<double>>(), e, s);
