@@ -71,6 +71,11 @@ WORKLOADS = {
     # wedge, p = 3, 480^2, ADP vectors: 57,600 unknowns on the ADP level, substructured E^-1
     "wedge_k150_p3_480_adp": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95),
                                   opts=dict(defl_mode=1, defl_z=1)),
+    # MP 1-A: 1D, u(0) = 1, radiation condition at x = 1, no source (right-hand side from the
+    # boundary value), k h = 0.625; multilevel deflation, complex E^-1 at the first level of at
+    # most 512 unknowns
+    "mp1a_k100_p3_160": dict(dim=1, p=3, n_el=160, k=100.0, sommerfeld=True, opts=dict(defl_direct_max=512)),
+    "mp1a_k1000_p3_1600": dict(dim=1, p=3, n_el=1600, k=1000.0, sommerfeld=True, opts=dict(defl_direct_max=512)),
     # MP 1-B: 1D, k = 50, p = 2, 80 elements, two-level deflation
     "mp1b_k50_p2_80": dict(dim=1, p=2, n_el=80, k=50.0, x0=(0.5,), opts=dict(defl_mode=1)),
     # 64 independent constant-k problems, k ~ U[50, 400], n_el = ceil(k / 0.625),
@@ -122,8 +127,9 @@ def cpu_baseline(w, seconds_cap=20.0):
     from oracle import solver as osv
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        op = hz.Problem(w["dim"], w["p"], w["n_el"], w.get("k", 1.0), k_elem=k_field(w))
-        f = hz.point_source_rhs(op, w["x0"])
+        op = hz.Problem(w["dim"], w["p"], w["n_el"], w.get("k", 1.0), k_elem=k_field(w),
+                        sommerfeld=w.get("sommerfeld", False))
+        f = hz.dirichlet_lift_rhs(op) if op.sommerfeld else hz.point_source_rhs(op, w["x0"])
         s = osv.Solver(op, osv.Options(maxit=1, **w["opts"]))
         t_setup = time.perf_counter() - t0
 
@@ -382,9 +388,10 @@ def main():
     copy_gbs = None if args.calibrate_copy_mb else measure_copy_gbs()
     w = WORKLOADS[args.workload]
     t0 = time.perf_counter()
-    prob = B.Problem(w["dim"], w["p"], w["n_el"], k=w.get("k"), k_elem=k_field(w))
+    prob = B.Problem(w["dim"], w["p"], w["n_el"], k=w.get("k"), k_elem=k_field(w),
+                     sommerfeld=w.get("sommerfeld", False))
     solver = B.Solver(prob, **w["opts"])
-    f = prob.point_source(w["x0"])
+    f = prob.dirichlet_lift(1.0) if w.get("sommerfeld") else prob.point_source(w["x0"])
     u = torch.empty_like(f)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
@@ -404,7 +411,8 @@ def main():
         forms["mixed"] = form_record("mixed (FP32 V-cycle), damped Jacobi", N, sec_m, infos_m, sec)
         del mixed
         log(f"[bench] mixed: {forms['mixed']['iters_per_solve']} iterations, {forms['mixed']['ms_per_solve']:.2f} ms")
-        if not args.no_learned:
+        # the learned smoother's training problems carry point sources on Dirichlet problems
+        if not args.no_learned and not w.get("sommerfeld"):
             try:
                 forms["mixed_learned"] = run_learned(args, w, prob, f, sec)
                 log(f"[bench] mixed + learned: {forms['mixed_learned']['iters_per_solve']} iterations, "

@@ -95,8 +95,10 @@ typedef struct {
                                 the substructured E^-1 */
     int autotune;            /* 1 (default): at setup, time the strip level-operator kernel
                                 of every level that uses it (FP64 and FP32; levels of at
-                                most 32768 unknowns with constant k or a stored stencil use
-                                a one-thread-per-unknown kernel instead) with strip heights
+                                most 32768 unknowns with constant k use a one-thread-per-
+                                unknown kernel instead, 2D stored-stencil levels a tiled
+                                kernel from 2048 unknowns on, below it the one-thread-per-
+                                unknown kernel) with strip heights
                                 4..64 rows and keep the fastest; 0: a fixed rule (the
                                 tallest strip that still gives 2048 waves).  Results do
                                 not depend on it. */

@@ -196,6 +196,10 @@ enum OpKind { KIND_SEP = 0, KIND_VARFINE = 1, KIND_STENCIL = 2 };
 // on MP 2-A (levels of 25,921 / 6,561 / 1,681 unknowns): 5.78 ms per solve with
 // this bound, 5.93 ms with 16384, 6.03 ms with the strip kernel only.
 constexpr long long kOpDirectMax = 32768;
+// 2D stored-stencil levels from this many unknowns use the tiled kernel (its
+// coefficient loads are all in flight before use; the one-thread-per-unknown
+// kernel leaves most of the device idle on such levels)
+constexpr long long kStencilTiledMin = 2048;
 
 enum OpMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_SMOOTH = 2 };
 

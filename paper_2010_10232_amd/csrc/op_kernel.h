@@ -480,7 +480,9 @@ inline int op_rows_per_strip(int n1, int n2, int py) {
 
 template <int PX, int PY, int KIND, int MODE, class T>
 static void launch_op_t(const OpArgs<T>& a, hipStream_t s) {
-    if (KIND == KIND_STENCIL && PY > 0 && (long long)a.n1 * a.n2 > kOpDirectMax) {
+    // stored stencils: the tiled kernel from kStencilTiledMin unknowns on (a fixed
+    // size rule, not a timed choice: the two kernels round differently)
+    if (KIND == KIND_STENCIL && PY > 0 && (long long)a.n1 * a.n2 >= kStencilTiledMin) {
         const long long tiles = (long long)((a.n1 + 63) / 64) * ((a.n2 + STC_ROWS - 1) / STC_ROWS);
         hipLaunchKernelGGL((op_stencil_kernel<PX, PY, MODE, T>), dim3((unsigned)tiles), dim3(256), 0, s, a);
         return;

@@ -924,8 +924,10 @@ void SolverImpl::autotune_ops(hipStream_t s) {
     const bool timing = o.time_kernels;
     o.time_kernels = 0;
     for (int l = 0; l <= last; ++l) {
-        // small constant-k / stencil levels use the direct kernel (no strips)
+        // small constant-k levels use the direct kernel, stored stencils the
+        // direct or the tiled kernel (no strips in either)
         if (lev[l]->N <= kOpDirectMax && lev[l]->kind != KIND_VARFINE) continue;
+        if (lev[l]->kind == KIND_STENCIL) continue;
         tune(l, double{});
         tune(l, float{});
     }
@@ -1000,9 +1002,9 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
         meter(bytes, 4.0 * macs * lv.N + (mode == MODE_SMOOTH ? 10.0 : 2.0) * lv.N);
         st_bytes = bytes;
     }
-    // timing class 4: the tiled stored-stencil kernel (coarse variable-k levels
-    // above the one-thread-per-unknown bound)
-    const bool st_kernel = lv.kind == KIND_STENCIL && py > 0 && lv.N > kOpDirectMax;
+    // timing class 4: the tiled stored-stencil kernel (2D coarse variable-k levels
+    // of at least kStencilTiledMin unknowns)
+    const bool st_kernel = lv.kind == KIND_STENCIL && py > 0 && lv.N >= kStencilTiledMin;
     if (st_kernel) tstart(4, s);
     if (l == 0) tstart(1, s);
     launch_op<T>(lv.kind, mode, px, py, a, s);
