@@ -129,16 +129,20 @@ def read_summary(path):
     return float(vals["traffic_bytes_per_launch"]), vals.get("kernel_regex")
 
 
-def stats_from_trace(trace_csv, after):
+def stats_from_trace(trace_csv, after, exclude=None):
     """Rows in the form of a rocprofv3 --stats summary, built from a kernel trace
     and counting only the dispatches that start after the last one whose name
-    matches the regular expression `after` (one phase of a run)."""
+    matches the regular expression `after` (one phase of a run), without those
+    matching `exclude` (for instance a set-up that falls inside the phase)."""
     with open(trace_csv) as fh:
         tr = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
     pat = re.compile(after)
+    skip = re.compile(exclude) if exclude else None
     last = max((i for i, r in enumerate(tr) if pat.search(r["Kernel_Name"])), default=-1)
     per = {}
     for r in tr[last + 1:]:
+        if skip and skip.search(r["Kernel_Name"]):
+            continue
         d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
         per.setdefault(r["Kernel_Name"], []).append(d)
     total = sum(sum(v) for v in per.values()) or 1
@@ -204,6 +208,7 @@ def main():
     ap.add_argument("--stats", help="rocprofv3 kernel_stats.csv: write a kernel table instead")
     ap.add_argument("--trace", help="rocprofv3 kernel_trace.csv: write a kernel table of the dispatches after --after")
     ap.add_argument("--after", help="regular expression: the table starts after its last dispatch")
+    ap.add_argument("--exclude", help="regular expression: kernels left out of the --trace table")
     ap.add_argument("--title")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
@@ -220,7 +225,7 @@ def main():
         return
     if a.trace:
         write_stats(None, a.title or "Kernel statistics", a.command, a.out,
-                    rows=stats_from_trace(a.trace, a.after or "^$"))
+                    rows=stats_from_trace(a.trace, a.after or "^$", a.exclude))
         return
     s = summarize(a.fetch, a.write, a.kernel, a.copy_mib, a.grid)
     s["grid"] = a.grid
