@@ -144,6 +144,9 @@ typedef struct {
                                 HH_EINVAL otherwise); multigrid and deflation options are not
                                 used by the solve */
     double cex_beta2;        /* C_ex shift; 0 (default): the paper's, 1/k in 1D, 1/(3k) in 2D */
+    int defl_refine;         /* iterative refinement steps of the substructured E^-1: -1 (default)
+                                as many as bring the set-up check below 1e-12 (at most 3);
+                                0..3: that many */
 } hh_solver_opts;
 
 typedef struct {

@@ -44,7 +44,8 @@ class SolverOpts(ctypes.Structure):
                 ("defl_z", ctypes.c_int),
                 ("defl_eps", ctypes.c_double),
                 ("precond", ctypes.c_int),
-                ("cex_beta2", ctypes.c_double)]
+                ("cex_beta2", ctypes.c_double),
+                ("defl_refine", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

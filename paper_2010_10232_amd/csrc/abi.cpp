@@ -65,6 +65,7 @@ void hh_default_opts(hh_solver_opts* o) {
     o->defl_eps = 0.0;
     o->precond = 0;
     o->cex_beta2 = 0.0;
+    o->defl_refine = -1;
 }
 
 const char* hh_last_error(void) { return g_err.c_str(); }

@@ -210,6 +210,7 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(o.defl_z == 0 || o.defl_mode == 1, "ADP deflation vectors (defl_z = 1) are two-level only (defl_mode = 1)");
     HH_REQUIRE(std::isfinite(o.defl_eps), "defl_eps must be finite");
     HH_REQUIRE(o.precond == 0 || o.precond == 1, "precond is 0 (deflated multigrid CSLP) or 1 (C_ex)");
+    HH_REQUIRE(o.defl_refine >= -1 && o.defl_refine <= kSubMaxRefine, "defl_refine must be in -1..3");
     HH_REQUIRE(o.precond == 0 || P.k_mode == 0, "C_ex (precond = 1) is built for constant k only");
     HH_REQUIRE(std::isfinite(o.cex_beta2) && o.cex_beta2 >= 0.0, "cex_beta2 must be finite and >= 0");
     HH_REQUIRE(!P.somm || (o.precond == 0 && o.defl_z == 0),
@@ -721,6 +722,7 @@ void SolverImpl::setup(hipStream_t s) {
             // each refinement step multiplies the residual by about c0
             int m = 0;
             for (double r = c0; r > kSubCheckTol && m < kSubMaxRefine; r *= c0) ++m;
+            if (o.defl_refine >= 0) m = o.defl_refine;
             sub->refine = m;
             sub->self_check = m ? substruct_check(s) : c0;
         }

@@ -101,7 +101,7 @@ def k_field(c):
 _cache = {}
 
 # options of the library that select an implementation, not the method: the oracle has none of them
-GPU_ONLY = ("defl_direct_solver", "autotune", "ortho", "time_kernels")
+GPU_ONLY = ("defl_direct_solver", "autotune", "ortho", "time_kernels", "defl_refine")
 
 
 def oracle_opts(opts):
