@@ -305,6 +305,13 @@ hh_status hh_solve(hh_solver* s, const void* f_dev, void* u_dev, int use_u0,
 hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, void* const* u,
                            hh_solve_info* infos, void* stream);
 
+/* Residual history of the last completed hh_solve (or batched solve) on this solver:
+ * the estimated relative residual |g_{j+1}| / ||f|| of every Arnoldi step in order,
+ * across restarts (section 4.3 stops on it within a cycle; the true residual is
+ * recomputed at every cycle's end).  *n receives the count; with out non-NULL,
+ * min(capacity, count) values are copied to the HOST array out. */
+hh_status hh_solve_history(const hh_solver* s, double* out, int capacity, int* n);
+
 /* Level sizes and parameters; level in [0, n_levels), or defl_direct_level. */
 hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out);
 

@@ -20,7 +20,7 @@ OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 
 
 EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
             "hh_point_spans", "hh_rhs_point_source", "hh_rhs_point_source_noalloc", "hh_rhs_dirichlet_lift", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
-            "hh_level_info", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched", "hh_cnn_create",
+            "hh_level_info", "hh_solve_history", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched", "hh_cnn_create",
             "hh_cnn_destroy", "hh_cnn_num_params", "hh_cnn_get_params", "hh_cnn_set_params", "hh_cnn_set_fused", "hh_cnn_loss_grad",
             "hh_cnn_train_step", "hh_solver_set_smoother", "hh_solver_capture", "hh_solver_captured",
             "hh_debug_set_spin_limit", "hh_cnn_train", "hh_cnn_save", "hh_cnn_load"]
@@ -99,6 +99,7 @@ def load(path=LIB_PATH):
     lib.hh_solver_destroy.argtypes = [vp]
     lib.hh_solve.argtypes = [vp, vp, vp, ip, ctypes.POINTER(SolveInfo), vp]
     lib.hh_level_info.argtypes = [vp, ip, ctypes.POINTER(LevelStats)]
+    lib.hh_solve_history.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ip, ctypes.POINTER(ctypes.c_int)]
     lib.hh_apply.argtypes = [vp, ip, ip, vp, vp, vp]
     lib.hh_set_kernel_timing.argtypes = [vp, ip]
     lib.hh_debug_set_spin_limit.argtypes = [vp, ip]
@@ -274,6 +275,16 @@ class Solver:
                 "defl_direct_level": st.defl_direct_level, "op_rows": (st.op_rows[0], st.op_rows[1]),
                 "defl_sub": (st.defl_sub[0], st.defl_sub[1]), "defl_sep": st.defl_sep, "defl_check": st.defl_check,
                 "defl_refine": st.defl_refine}
+
+    def history(self):
+        """Estimated relative residual |g_{j+1}| / ||f|| of every Arnoldi step of the last solve."""
+        lib = load()
+        n = ctypes.c_int()
+        _check(lib.hh_solve_history(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.float64)
+        _check(lib.hh_solve_history(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n.value,
+                                    ctypes.byref(n)))
+        return out
 
     def set_smoother(self, cnn):
         """cnn: a Cnn (learned finest-level smoother) or None (damped Jacobi)."""

@@ -595,6 +595,17 @@ hh_status hh_debug_set_spin_limit(hh_solver* s, int spins) {
     HH_CATCH
 }
 
+hh_status hh_solve_history(const hh_solver* s, double* out, int capacity, int* n) {
+    HH_TRY
+    if (!s || !n) throw Err{HH_EINVAL, "NULL argument"};
+    if (capacity < 0) throw Err{HH_EINVAL, "capacity must be >= 0"};
+    const std::vector<double>& h = s->impl->last_hist;
+    *n = (int)h.size();
+    if (out) std::copy(h.begin(), h.begin() + std::min<size_t>(h.size(), (size_t)capacity), out);
+    return HH_OK;
+    HH_CATCH
+}
+
 hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out) {
     HH_TRY
     if (!s || !out) throw Err{HH_EINVAL, "NULL argument"};

@@ -68,6 +68,7 @@ struct SolveRun {
     bool exchange_timeout = false;  // the error thrown was a grid-exchange timeout
     Meter meter;                    // algorithmic bytes / flops of the work this solve used
     double step_bytes[2] = {0, 0}, step_flops[2] = {0, 0};   // per Arnoldi-step slot
+    std::vector<double> hist;       // |g_{j+1}| of every Arnoldi step, in order
     hh_solve_info inf{};
     std::chrono::steady_clock::time_point t0;
     void start(SolverImpl* S, const cx<double>* f, cx<double>* u, int use_u0, hipStream_t s);
@@ -181,6 +182,8 @@ struct SolverImpl {
                   cx<T>* xo = nullptr, const cx<T>* yadd = nullptr, bool mg = true, bool mass_only = false);
     DevBuf zero_bands;           // zero band table of the widest level (mass-only applies)
     int solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s);
+    // the last completed solve's estimated relative residuals |g_{j+1}| / ||f||, one per step
+    std::vector<double> last_hist;
 };
 
 ProblemImpl* build_problem(const hh_problem_desc* d);

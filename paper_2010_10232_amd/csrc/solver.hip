@@ -1452,6 +1452,7 @@ void SolveRun::step() {
             const double* pd = (const double*)(S->pin_step + 128 * slot);
             const int* pi = (const int*)(S->pin_step + 128 * slot + 8 * sizeof(double));
             gabs = pd[2];
+            hist.push_back(gabs);
             ++iters;
             if (pi[5]) {
                 exchange_timeout = true;
@@ -1531,6 +1532,8 @@ int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_i
         }
         run.inf.status = run.status;
         run.inf.arnoldi_fallback = attempt;
+        last_hist.assign(run.hist.size(), 0.0);
+        for (size_t i = 0; i < run.hist.size(); ++i) last_hist[i] = run.nf > 0.0 ? run.hist[i] / run.nf : 0.0;
         if (info) *info = run.inf;
         return run.status;
     }
