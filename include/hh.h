@@ -147,6 +147,11 @@ typedef struct {
     int defl_refine;         /* iterative refinement steps of the substructured E^-1: -1 (default)
                                 as many as bring the set-up check below 1e-12 (at most 3);
                                 0..3: that many */
+    double defl_kh_max;      /* multilevel deflation: the direct level is also never coarser than
+                                the last level l >= 1 with k_max h_l <= defl_kh_max (k_max the
+                                largest wave number, h_l the level's longest element); coarser
+                                deflation levels no longer hold A's near-null space and the inner
+                                solves stall.  Default 2.0; 0 turns the rule off */
 } hh_solver_opts;
 
 typedef struct {

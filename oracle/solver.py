@@ -51,7 +51,7 @@ class Options:
     def __init__(self, beta=(1.0, 0.5), omega=0.8, nu_pre=1, nu_post=1, n_vcycles=1,
                  mg_min_elems=8, coarse_damping=1, defl_mode=2, defl_direct_max=16384,
                  defl_inner_its=(8, 4, 2, 1, 1, 1, 1, 1), restart=50, maxit=1000, tol=1e-7, mg_coarse=0,
-                 defl_z=0, defl_eps=0.0, precond=0, cex_beta2=0.0):
+                 defl_z=0, defl_eps=0.0, precond=0, cex_beta2=0.0, defl_kh_max=2.0):
         self.beta = complex(beta[0], beta[1])
         self.omega = float(omega)
         self.nu_pre = int(nu_pre)
@@ -70,6 +70,7 @@ class Options:
         self.defl_eps = float(defl_eps)
         self.precond = int(precond)
         self.cex_beta2 = float(cex_beta2)
+        self.defl_kh_max = float(defl_kh_max)
 
 
 class Level:
@@ -171,21 +172,34 @@ def smoother_damping(l, gersh, opts):
     return min(opts.omega, 2.0 / gersh)
 
 
-def deflation_levels(levels, opts):
+def deflation_levels(levels, opts, kmax=None):
     """Index L_z of the deflation level solved directly (0 when deflation is off).
 
     two-level: L_z = 1.  multilevel: the first level l >= 1 with at most
-    defl_direct_max unknowns (never deeper than the coarsest multigrid level).
+    defl_direct_max unknowns (never deeper than the coarsest multigrid level),
+    and, with defl_kh_max > 0, not coarser than the last level l >= 1 whose
+    largest k h_l (kmax the largest wave number, h_l the longest element of the
+    level in either direction) is at most defl_kh_max: deflation levels too
+    coarse to resolve the waves no longer hold A's near-null space.
     """
     L = len(levels) - 1
     if opts.defl_mode == 0 or L == 0:
         return 0
     if opts.defl_mode == 1:
         return 1
+    lz = L
     for l in range(1, L + 1):
         if levels[l].N <= opts.defl_direct_max:
-            return l
-    return L
+            lz = l
+            break
+    if opts.defl_kh_max > 0 and kmax is not None:
+        lkh = 1
+        for l in range(1, L + 1):
+            h = max(float(np.max(np.diff(b))) for b in levels[l].bks)
+            if kmax * h <= opts.defl_kh_max:
+                lkh = l
+        lz = min(lz, lkh)
+    return lz
 
 
 def adp_deflation_1d(nf, eps=0.0):
@@ -264,7 +278,8 @@ class Solver:
         self.opts = opts or Options()
         self.cnn_params = cnn_params
         self.levels = build_hierarchy(prob, self.opts)
-        self.Lz = deflation_levels(self.levels, self.opts)
+        kmax = prob.k if prob.k_elem is None else float(np.max(prob.k_elem))
+        self.Lz = deflation_levels(self.levels, self.opts, kmax)
         self.Zadp = None
         self.Mex_lu = None
         if self.opts.precond == 1:

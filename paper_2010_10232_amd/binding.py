@@ -45,7 +45,8 @@ class SolverOpts(ctypes.Structure):
                 ("defl_eps", ctypes.c_double),
                 ("precond", ctypes.c_int),
                 ("cex_beta2", ctypes.c_double),
-                ("defl_refine", ctypes.c_int)]
+                ("defl_refine", ctypes.c_int),
+                ("defl_kh_max", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -66,6 +66,7 @@ void hh_default_opts(hh_solver_opts* o) {
     o->precond = 0;
     o->cex_beta2 = 0.0;
     o->defl_refine = -1;
+    o->defl_kh_max = 2.0;
 }
 
 const char* hh_last_error(void) { return g_err.c_str(); }

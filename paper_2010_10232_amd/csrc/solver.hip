@@ -211,6 +211,7 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(std::isfinite(o.defl_eps), "defl_eps must be finite");
     HH_REQUIRE(o.precond == 0 || o.precond == 1, "precond is 0 (deflated multigrid CSLP) or 1 (C_ex)");
     HH_REQUIRE(o.defl_refine >= -1 && o.defl_refine <= kSubMaxRefine, "defl_refine must be in -1..3");
+    HH_REQUIRE(std::isfinite(o.defl_kh_max) && o.defl_kh_max >= 0.0, "defl_kh_max must be finite and >= 0");
     HH_REQUIRE(o.precond == 0 || P.k_mode == 0, "C_ex (precond = 1) is built for constant k only");
     HH_REQUIRE(std::isfinite(o.cex_beta2) && o.cex_beta2 >= 0.0, "cex_beta2 must be finite and >= 0");
     HH_REQUIRE(!P.somm || (o.precond == 0 && o.defl_z == 0),
@@ -556,6 +557,26 @@ void SolverImpl::setup(hipStream_t s) {
                 Lz = l;
                 break;
             }
+        // not coarser than the last level that still resolves the waves:
+        // k_max h_l <= defl_kh_max, h_l the level's longest element
+        if (o.defl_kh_max > 0.0) {
+            double kmax = P.k;
+            if (!const_k) {
+                kmax = 0.0;
+                for (double v : P.k2) kmax = std::max(kmax, std::sqrt(v));
+            }
+            auto hmax = [](const Axis& a) {
+                double h = 0.0;
+                for (size_t i = 0; i + 1 < a.bk.size(); ++i) h = std::max(h, a.bk[i + 1] - a.bk[i]);
+                return h;
+            };
+            int lkh = 1;
+            for (int l = 1; l <= L; ++l) {
+                const double h = is2d ? std::max(hmax(lev[l]->ax), hmax(lev[l]->ay)) : hmax(lev[l]->ax);
+                if (kmax * h <= o.defl_kh_max) lkh = l;
+            }
+            Lz = std::min(Lz, lkh);
+        }
     }
     // C_ex: M_ex = K - (1 + i beta2) k^2 M is separable like E, so its exact
     // inverse is a fast diagonalisation of the finest level with complex 1 / D

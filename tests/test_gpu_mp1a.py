@@ -46,9 +46,9 @@ CASES = {
     "k1_p5_8": dict(p=5, n_el=8, k=1.0, opts=dict(defl_mode=1)),
     "k50_p2_80": dict(p=2, n_el=80, k=50.0, opts=dict()),
     # multilevel deflation: inner FGMRES on levels 1..3, direct (complex dense) at level 4
-    "k100_p3_160_multi": dict(p=3, n_el=160, k=100.0, opts=dict(defl_direct_max=20)),
+    "k100_p3_160_multi": dict(p=3, n_el=160, k=100.0, opts=dict(defl_direct_max=20, defl_kh_max=0)),
     "k200_p4_321": dict(p=4, n_el=321, k=200.0, opts=dict(defl_mode=1)),
-    "k100_p1_160": dict(p=1, n_el=160, k=100.0, opts=dict(defl_direct_max=40)),
+    "k100_p1_160": dict(p=1, n_el=160, k=100.0, opts=dict(defl_direct_max=40, defl_kh_max=0)),
 }
 
 _cache = {}

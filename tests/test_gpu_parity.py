@@ -50,12 +50,12 @@ def rvec(n, seed):
 
 CASES = {
     "1d_p2_k50_2lev": dict(dim=1, p=2, n_el=80, k=50.0, x0=(0.5,), opts=dict(defl_mode=1)),
-    "1d_p3_odd_multi": dict(dim=1, p=3, n_el=75, k=40.0, x0=(0.3,), opts=dict(defl_direct_max=20)),
+    "1d_p3_odd_multi": dict(dim=1, p=3, n_el=75, k=40.0, x0=(0.3,), opts=dict(defl_direct_max=20, defl_kh_max=0)),
     "2d_p1_k10": dict(dim=2, p=1, n_el=16, k=10.0, x0=(0.5, 0.5), opts=dict()),
     # degree 1 with enough levels for the one-workgroup coarse tail (levels 1-3)
     "2d_p1_k25_tail": dict(dim=2, p=1, n_el=40, k=25.0, x0=(0.45, 0.6), opts=dict()),
-    "2d_p2_odd_multi": dict(dim=2, p=2, n_el=21, k=13.0, x0=(0.4, 0.55), opts=dict(defl_direct_max=100)),
-    "2d_p3_multi": dict(dim=2, p=3, n_el=24, k=15.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=100)),
+    "2d_p2_odd_multi": dict(dim=2, p=2, n_el=21, k=13.0, x0=(0.4, 0.55), opts=dict(defl_direct_max=100, defl_kh_max=0)),
+    "2d_p3_multi": dict(dim=2, p=3, n_el=24, k=15.0, x0=(0.5, 0.5), opts=dict(defl_direct_max=100, defl_kh_max=0)),
     "2d_p4_odd": dict(dim=2, p=4, n_el=19, k=12.0, x0=(0.5, 0.95), opts=dict()),
     "2d_p5": dict(dim=2, p=5, n_el=20, k=12.0, x0=(0.25, 0.5), opts=dict()),
     "2d_wedge_p2": dict(dim=2, p=2, n_el=20, wedge=6.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=100)),
@@ -79,7 +79,8 @@ CASES = {
     # coarse multigrid operators rediscretised with averaged k^2 (mg_coarse = 1); odd counts
     "2d_grf_p3_redisc": dict(dim=2, p=3, n_el=33, grf=10.0, x0=(0.5, 0.5),
                              opts=dict(defl_direct_max=100, mg_coarse=1)),
-    "1d_rand_p2_redisc": dict(dim=1, p=2, n_el=75, rand=30.0, x0=(0.3,), opts=dict(defl_direct_max=20, mg_coarse=1)),
+    "1d_rand_p2_redisc": dict(dim=1, p=2, n_el=75, rand=30.0, x0=(0.3,), opts=dict(defl_direct_max=20, mg_coarse=1,
+                                                                                   defl_kh_max=0)),
     # MP 2-A at k = 100, p = 3 on 160 x 160 elements with the default (two-level) deflation
     "mp2a_k100_p3_160": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict()),
 }

@@ -391,7 +391,7 @@ def test_multilevel_with_exact_inner_equals_two_level():
     two = osv.Solver(prob, osv.Options(defl_mode=1, mg_min_elems=3))
     N1 = two.levels[1].N
     multi = osv.Solver(prob, osv.Options(defl_mode=2, mg_min_elems=3, defl_direct_max=30,
-                                          defl_inner_its=(N1, 100, 100)))
+                                          defl_inner_its=(N1, 100, 100), defl_kh_max=0))
     assert multi.Lz >= 2
     v = np.random.default_rng(2).random(two.levels[0].N) + 0.5j
     a, b = two.T(0, v), multi.T(0, v)
@@ -820,3 +820,14 @@ def test_mp1a_operators_and_solver():
     assert info.converged
     assert np.linalg.norm(u - ud) / np.linalg.norm(ud) <= 1e-4
     assert hz.l2_error_1d(prob, u, lambda x: np.exp(100j * x)) < 1e-3
+
+
+def test_direct_level_not_coarser_than_the_waves_allow():
+    """Multilevel deflation: with defl_kh_max the direct level stops at the last level with
+    k_max h_l <= defl_kh_max (MP 2-A, k = 200 on 320^2 elements: level 1, k h = 1.25; level 2
+    would have k h = 2.5), whatever defl_direct_max allows; 0 turns the rule off."""
+    prob = hz.Problem(2, 2, 32, 20.0)   # k h = 0.625 at level 0, 1.25 at 1, 2.5 at 2
+    lv = osv.build_hierarchy(prob, osv.Options(mg_min_elems=3))
+    assert osv.deflation_levels(lv, osv.Options(defl_direct_max=30), 20.0) == 1
+    assert osv.deflation_levels(lv, osv.Options(defl_direct_max=30, defl_kh_max=0), 20.0) >= 2
+    assert osv.deflation_levels(lv, osv.Options(defl_direct_max=30, defl_kh_max=2.6), 20.0) == 2
