@@ -56,9 +56,12 @@ WORKLOADS = {
                             opts=dict(defl_direct_max=65536, defl_inner_its=(2, 4, 2, 1, 1, 1, 1, 1), mg_min_elems=30,
                                       defl_refine=0)),
     # three-layer wedge, k0 = 150, p = 2 / 3 / 4, 480 x 480 elements (direct deflation level 1)
-    "wedge_k150_p2_480": dict(dim=2, p=2, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=65536)),
-    "wedge_k150_p3_480": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=65536)),
-    "wedge_k150_p4_480": dict(dim=2, p=4, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=65536)),
+    "wedge_k150_p2_480": dict(dim=2, p=2, n_el=480, wedge=150.0, x0=(0.5, 0.95),
+                              opts=dict(defl_direct_max=65536, defl_refine=0)),
+    "wedge_k150_p3_480": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95),
+                              opts=dict(defl_direct_max=65536, defl_refine=0)),
+    "wedge_k150_p4_480": dict(dim=2, p=4, n_el=480, wedge=150.0, x0=(0.5, 0.95),
+                              opts=dict(defl_direct_max=65536, defl_refine=0)),
     # MP 2-A mesh of the paper's table (k = 100, p = 3, 160 x 160 elements)
     "mp2a_k100_p3_160": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict()),
     # the same with the adapted deflation preconditioner's vectors (ADP, section 3; two-level,

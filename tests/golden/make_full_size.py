@@ -41,9 +41,12 @@ def _batch_member(rank):
 
 
 WORKLOADS = {
-    "wedge_k150_p2_480": dict(dim=2, p=2, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=65536)),
-    "wedge_k150_p3_480": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=65536)),
-    "wedge_k150_p4_480": dict(dim=2, p=4, n_el=480, wedge=150.0, x0=(0.5, 0.95), opts=dict(defl_direct_max=65536)),
+    "wedge_k150_p2_480": dict(dim=2, p=2, n_el=480, wedge=150.0, x0=(0.5, 0.95),
+                              opts=dict(defl_direct_max=65536, defl_refine=0)),
+    "wedge_k150_p3_480": dict(dim=2, p=3, n_el=480, wedge=150.0, x0=(0.5, 0.95),
+                              opts=dict(defl_direct_max=65536, defl_refine=0)),
+    "wedge_k150_p4_480": dict(dim=2, p=4, n_el=480, wedge=150.0, x0=(0.5, 0.95),
+                              opts=dict(defl_direct_max=65536, defl_refine=0)),
     "grf_k300_p4_960": dict(dim=2, p=4, n_el=960, grf=300.0, x0=(0.5, 0.5),
                             opts=dict(defl_direct_max=65536, defl_inner_its=(2, 4, 2, 1, 1, 1, 1, 1), mg_min_elems=30,
                                       defl_refine=0)),
