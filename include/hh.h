@@ -152,6 +152,12 @@ typedef struct {
                                 largest wave number, h_l the level's longest element); coarser
                                 deflation levels no longer hold A's near-null space and the inner
                                 solves stall.  Default 2.0; 0 turns the rule off */
+    int use_graph;           /* 1: every outer Arnoldi step (the preconditioner T with its inner
+                                solves, A z and the MGS/Givens step) is captured once per step
+                                index into a HIP graph on a stream of the solver's own and
+                                replayed by later steps and solves (same kernels, same results);
+                                not while a kernel class is timed or samples are captured, and
+                                without cooperative launches.  0 (default): launched one by one */
 } hh_solver_opts;
 
 typedef struct {

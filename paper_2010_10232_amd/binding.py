@@ -46,7 +46,8 @@ class SolverOpts(ctypes.Structure):
                 ("precond", ctypes.c_int),
                 ("cex_beta2", ctypes.c_double),
                 ("defl_refine", ctypes.c_int),
-                ("defl_kh_max", ctypes.c_double)]
+                ("defl_kh_max", ctypes.c_double),
+                ("use_graph", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -67,6 +67,7 @@ void hh_default_opts(hh_solver_opts* o) {
     o->cex_beta2 = 0.0;
     o->defl_refine = -1;
     o->defl_kh_max = 2.0;
+    o->use_graph = 0;
 }
 
 const char* hh_last_error(void) { return g_err.c_str(); }
@@ -555,6 +556,7 @@ hh_status hh_solver_set_smoother(hh_solver* s, hh_cnn* c) {
     HH_TRY
     if (!s) throw Err{HH_EINVAL, "NULL solver"};
     s->impl->cnn = c ? c->impl.get() : nullptr;
+    s->impl->drop_graphs();   // the smoother changes the captured step
     return HH_OK;
     HH_CATCH
 }

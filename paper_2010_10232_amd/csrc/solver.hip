@@ -153,6 +153,11 @@ static DevBuf& pick(DevBuf& a64, DevBuf& a32) {
 }
 
 SolverImpl::~SolverImpl() {
+    for (hipGraphExec_t g : gexec)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (hipEvent_t e : {gfork, gjoin})
+        if (e) (void)hipEventDestroy(e);
+    if (gstream) (void)hipStreamDestroy(gstream);
     for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     if (pin_d) (void)hipHostFree(pin_d);
     if (pin_i) (void)hipHostFree(pin_i);
@@ -212,6 +217,7 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(o.precond == 0 || o.precond == 1, "precond is 0 (deflated multigrid CSLP) or 1 (C_ex)");
     HH_REQUIRE(o.defl_refine >= -1 && o.defl_refine <= kSubMaxRefine, "defl_refine must be in -1..3");
     HH_REQUIRE(std::isfinite(o.defl_kh_max) && o.defl_kh_max >= 0.0, "defl_kh_max must be finite and >= 0");
+    HH_REQUIRE(o.use_graph == 0 || o.use_graph == 1, "use_graph is 0 or 1");
     HH_REQUIRE(o.precond == 0 || P.k_mode == 0, "C_ex (precond = 1) is built for constant k only");
     HH_REQUIRE(std::isfinite(o.cex_beta2) && o.cex_beta2 >= 0.0, "cex_beta2 must be finite and >= 0");
     HH_REQUIRE(!P.somm || (o.precond == 0 && o.defl_z == 0),
@@ -898,6 +904,13 @@ void SolverImpl::setup(hipStream_t s) {
         (void)hipGetLastError();
     for (hipEvent_t* e : {&ev_slot[0], &ev_slot[1], &ev_misc})
         HH_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    if (o.use_graph) {
+        // graphs are captured on a stream of the solver's own (the caller's may
+        // be the legacy default stream, which cannot capture); default priority
+        HH_HIP(hipStreamCreateWithFlags(&gstream, hipStreamNonBlocking));
+        HH_HIP(hipEventCreateWithFlags(&gfork, hipEventDisableTiming));
+        HH_HIP(hipEventCreateWithFlags(&gjoin, hipEventDisableTiming));
+    }
     HH_HIP(hipStreamSynchronize(s));
 }
 
@@ -1201,7 +1214,7 @@ bool SolverImpl::arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, Kryl
         launch_arnoldi_small(N, j, w, Vb, N, k, s);
         return k.hstep != nullptr;
     }
-    if (!grid_arnoldi_off && launch_arnoldi_grid(N, j, w, Vb, N, k, s, 4, allow_coop, o.ortho == 0))
+    if (!grid_arnoldi_off && launch_arnoldi_grid(N, j, w, Vb, N, k, s, 4, allow_coop && !graphs_on(), o.ortho == 0))
         return k.hstep != nullptr;
     for (int i = 0; i <= j; ++i) launch_mgs(N, i, j, w, Vb, N, k, s);
     launch_norm_givens(N, j, w, Vb, N, k, s);
@@ -1392,19 +1405,54 @@ void SolveRun::enqueue_step(int jj) {
     cx<double>* zj = Zb + (size_t)jj * N;
     cx<double>* w = Vb + (size_t)(jj + 1) * N;
     const int slot = jj & 1;
-    S->T_apply(0, vj, zj, s);
-    S->op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
-    // MGS + norm + Givens + normalisation of w; algorithmic bytes: each basis
-    // vector v_0..v_jj read once, w read once and written once
-    S->tstart(3, s);
-    const bool published = S->arnoldi(N, jj, w, Vb, kd, s);
-    S->tstop(3, 16.0 * (jj + 3) * N, s);
-    // the fused step kernels store |g_{j+1}| and the flags in the pinned slot
-    // themselves; otherwise scal[0..7] and ints[0..5] (adjacent on the device)
-    // are copied in one transfer
-    if (!published)
-        HH_HIP(hipMemcpyAsync(S->pin_step + 128 * slot, kd.scal, 8 * sizeof(double) + 6 * sizeof(int),
-                              hipMemcpyDeviceToHost, s));
+    auto body = [&]() {
+        S->T_apply(0, vj, zj, s);
+        S->op<double>(0, MODE_APPLY, false, zj, nullptr, w, s);
+        // MGS + norm + Givens + normalisation of w; algorithmic bytes: each basis
+        // vector v_0..v_jj read once, w read once and written once
+        S->tstart(3, s);
+        const bool published = S->arnoldi(N, jj, w, Vb, kd, s);
+        S->tstop(3, 16.0 * (jj + 3) * N, s);
+        // the fused step kernels store |g_{j+1}| and the flags in the pinned slot
+        // themselves; otherwise scal[0..7] and ints[0..5] (adjacent on the device)
+        // are copied in one transfer
+        if (!published)
+            HH_HIP(hipMemcpyAsync(S->pin_step + 128 * slot, kd.scal, 8 * sizeof(double) + 6 * sizeof(int),
+                                  hipMemcpyDeviceToHost, s));
+    };
+    if (S->graphs_on()) {
+        // the step's launches depend on jj only (pointers into V and Z, the step
+        // index); the Arnoldi kernels take their exchange tags from a device
+        // counter, so a replayed graph is the same work as the launches
+        if ((int)S->gexec.size() <= jj) {
+            S->gexec.resize(jj + 1, nullptr);
+            S->gbytes.resize(jj + 1, 0.0);
+            S->gflops.resize(jj + 1, 0.0);
+        }
+        if (!S->gexec[jj]) {
+            hipGraph_t g = nullptr;
+            HH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+            try {
+                body();
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            HH_HIP(hipStreamEndCapture(s, &g));
+            const hipError_t e = hipGraphInstantiate(&S->gexec[jj], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HH_HIP(e);
+            S->gbytes[jj] = meter.bytes - before.bytes;
+            S->gflops[jj] = meter.flops - before.flops;
+        } else {
+            meter.bytes += S->gbytes[jj];
+            meter.flops += S->gflops[jj];
+        }
+        HH_HIP(hipGraphLaunch(S->gexec[jj], s));
+    } else {
+        body();
+    }
     HH_HIP(hipEventRecord(S->ev_slot[slot], s));
     step_bytes[slot] = meter.bytes - before.bytes;
     step_flops[slot] = meter.flops - before.flops;
@@ -1535,7 +1583,14 @@ void SolveRun::step() {
 // grid was not all resident, e.g. other streams held the CUs) ends the solve
 // with HH_EHIP; from a zero initial guess the solve is then run once more with
 // the per-projection kernels, which wait on no other workgroup.
-int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s) {
+int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_info* info, hipStream_t s_caller) {
+    // graphed solves run on the solver's own stream, after the caller's work
+    hipStream_t s = s_caller;
+    if (graphs_on()) {
+        HH_HIP(hipEventRecord(gfork, s_caller));
+        HH_HIP(hipStreamWaitEvent(gstream, gfork, 0));
+        s = gstream;
+    }
     for (int attempt = 0;; ++attempt) {
         SolveRun run;
         try {
@@ -1549,7 +1604,12 @@ int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_i
             if (!(run.exchange_timeout && attempt == 0 && !use_u0 && !grid_arnoldi_off)) throw;
             HH_HIP(hipStreamSynchronize(s));
             grid_arnoldi_off = true;
+            drop_graphs();   // the steps now use the per-projection kernels
                     continue;
+        }
+        if (s != s_caller) {
+            HH_HIP(hipEventRecord(gjoin, s));
+            HH_HIP(hipStreamWaitEvent(s_caller, gjoin, 0));
         }
         run.inf.status = run.status;
         run.inf.arnoldi_fallback = attempt;
@@ -1561,6 +1621,7 @@ int SolverImpl::solve(const cx<double>* f, cx<double>* u, int use_u0, hh_solve_i
 }
 
 void SolverImpl::set_spin_limit(int spins) {
+    drop_graphs();   // the spin limit is a kernel argument
     kd.spin_limit = spins;
     for (auto& lv : lev) lv->kd.spin_limit = spins;
     grid_arnoldi_off = false;
