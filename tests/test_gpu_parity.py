@@ -83,6 +83,8 @@ CASES = {
                                                                                    defl_kh_max=0)),
     # MP 2-A at k = 100, p = 3 on 160 x 160 elements with the default (two-level) deflation
     "mp2a_k100_p3_160": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict()),
+    # the same as the bench times it: multigrid to 40 elements, a dense coarsest solve of 1,849 unknowns
+    "mp2a_k100_p3_160_mg40": dict(dim=2, p=3, n_el=160, k=100.0, x0=(0.5, 0.5), opts=dict(mg_min_elems=40)),
 }
 
 
