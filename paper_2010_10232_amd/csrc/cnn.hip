@@ -143,7 +143,7 @@ __device__ __forceinline__ double sum_parts(const double* __restrict__ parts, in
 // four separate launches; stage pixels outside the grid are stored as zero, the
 // padding the separate launches read.
 // --------------------------------------------------------------------------
-constexpr int FT_H = 8, FT_W = 16, FUSED_TB = 512;
+constexpr int FT_H = 16, FT_W = 32, FUSED_TB = 512;
 // LDS (BF16 elements): packed weights of layers 0..3, then two activation
 // regions used alternately (input tile / layer-1 output, layer-0 / layer-2 output)
 constexpr int FW0 = 9 * 32 * 8, FW1 = 9 * 32 * 32, FW3 = 9 * 16 * 32;
@@ -221,22 +221,29 @@ __device__ __forceinline__ void fused_stage(const __bf16* in, __bf16* outs, int 
             for (int nt = 0; nt < NT; ++nt)
                 acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][nt], acc[nt], 0, 0, 0);
         }
-        // D: output channel nt*16 + col for pixels mt*16 + 4g .. + 3
+        // D: output channel nt*16 + col for pixels mt*16 + 4g .. + 3 (their region
+        // rows and columns from one division: C >= 4, so at most one row break)
+        const int pb = mt * 16 + 4 * g;
+        const int rb = pb / C, cb = pb - rb * C;
+        bool ing[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int wrap = (cb + i >= C) ? 1 : 0;
+            const int gr = gr0 + rb + wrap, gc = gc0 + cb + i - wrap * C;
+            ing[i] = gr >= 0 && gr < H && gc >= 0 && gc < Wd;
+        }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int co = nt * 16 + col;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int po = mt * 16 + 4 * g + i;
+                const int po = pb + i;
                 if (po >= npx) continue;
-                const int ro = po / C, cc = po - ro * C;
-                const int gr = gr0 + ro, gc = gc0 + cc;
-                const bool in_grid = gr >= 0 && gr < H && gc >= 0 && gc < Wd;
                 const float v = acc[nt][i];
                 if (LAST) {
-                    if (co < 2 && in_grid) Y[po * 2 + co] = v + bias[co];
+                    if (co < 2 && ing[i]) Y[po * 2 + co] = v + bias[co];
                 } else {
-                    outs[po * COUTP + co] = in_grid ? (__bf16)fmaxf(v + bias[co], 0.0f) : (__bf16)0.0f;
+                    outs[po * COUTP + co] = ing[i] ? (__bf16)fmaxf(v + bias[co], 0.0f) : (__bf16)0.0f;
                 }
             }
         }
@@ -272,9 +279,7 @@ __global__ __launch_bounds__(FUSED_TB) void cnn_fused_kernel(
         // packed input tile (r / rms, c, 0...), zero outside the grid (values
         // read at a clamped valid pixel)
         constexpr int RI = FT_H + 8, CI = FT_W + 8;
-        static_assert(RI * CI <= FUSED_TB, "one input pixel per thread");
-        const int e = threadIdx.x;
-        if (e < RI * CI) {
+        for (int e = threadIdx.x; e < RI * CI; e += FUSED_TB) {
             const int rr = e / CI, cc = e - rr * CI;
             const int gr = r0 - 4 + rr, gc = c0 - 4 + cc;
             const bool ok = gr >= 0 && gr < H && gc >= 0 && gc < Wd;
