@@ -310,7 +310,8 @@ hh_status hh_solve(hh_solver* s, const void* f_dev, void* u_dev, int use_u0,
  * arrays of n entries; f[i], u[i] device vectors of problem i (as in hh_solve,
  * zero initial guess).  The pool streams wait for the work already on `stream`,
  * and `stream` waits for them before the call returns.  Per-problem results and
- * status are in infos[i]; the return value is the first negative status (its
+ * status are in infos[i] (use_graph is not applied inside a batch: the steps
+ * are launched one by one); the return value is the first negative status (its
  * message names the problem), HH_ENOCONV if some problem did not converge, else
  * HH_OK.  The solvers must not be used elsewhere during the call. */
 hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, void* const* u,

@@ -284,7 +284,13 @@ hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, voi
     // per-projection kernels when it does not fit (runs whose workers launched
     // cooperative grids on the pool streams ended in a segmentation fault at
     // process exit)
-    for (int i = 0; i < n; ++i) s[i]->impl->allow_coop = false;
+    // nor step graphs: four workers replaying graphs measured slower than the
+    // same steps launched one by one (64 point-source problems, k 50..400,
+    // p 2..4: 321 ms against 261 ms)
+    for (int i = 0; i < n; ++i) {
+        s[i]->impl->allow_coop = false;
+        s[i]->impl->in_batch = true;
+    }
     std::vector<int> status(n, HH_OK);
     std::vector<std::string> errs(n);
     std::atomic<int> next{0};
@@ -313,7 +319,10 @@ hh_status hh_solve_batched(hh_solver* const* s, int n, const void* const* f, voi
         worker(0);
         for (auto& t : pool) t.join();
     }
-    for (int i = 0; i < n; ++i) s[i]->impl->allow_coop = true;
+    for (int i = 0; i < n; ++i) {
+        s[i]->impl->allow_coop = true;
+        s[i]->impl->in_batch = false;
+    }
     // the caller's stream continues after every pool stream
     for (int k = 0; k < ns; ++k) {
         Event join;

@@ -165,13 +165,14 @@ struct SolverImpl {
     // true when the step's kernel stored the host's scalars in the pinned slot itself
     bool arnoldi(long long N, int j, cx<double>* w, cx<double>* Vb, KrylovDev& k, hipStream_t s);
     bool allow_coop = true;
+    bool in_batch = false;   // set by the batched solve: steps launched one by one
     // step graphs (use_graph): one executable graph per outer step index, its
     // metered work, and the stream the graphed solves run on
     hipStream_t gstream = nullptr;
     hipEvent_t gfork = nullptr, gjoin = nullptr;
     std::vector<hipGraphExec_t> gexec;
     std::vector<double> gbytes, gflops;
-    bool graphs_on() const { return o.use_graph && !o.time_kernels && !cap_buf; }
+    bool graphs_on() const { return o.use_graph && !o.time_kernels && !cap_buf && !in_batch; }
     // forget the captured steps (the kernel sequence or its arguments changed)
     void drop_graphs() {
         for (hipGraphExec_t& g : gexec)

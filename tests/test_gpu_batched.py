@@ -99,3 +99,34 @@ def test_batched_repeated_calls_match_single():
         solvers[call].set_kernel_timing(3)
         solvers[call].solve(fs[call])
         solvers[call].set_kernel_timing(0)
+
+
+def test_batched_with_graph_solvers():
+    """Solvers set up with step graphs (and already replaying them) inside a
+    batch: the batch launches their steps one by one, so its results equal a
+    batch of the same solvers without graphs bit for bit; single solves after
+    the batch replay the graphs again and reproduce the single solves before
+    it."""
+    import torch
+    from paper_2010_10232_amd import binding as B
+    draws = _batch_problems(n=5, seed=31)
+    opts = dict(defl_direct_max=400)
+    probs = [B.Problem(2, d["p"], d["n_el"], k=d["k"]) for d in draws]
+    fs = [pr.point_source(d["x0"]) for pr, d in zip(probs, draws)]
+    plain = [B.Solver(pr, **opts) for pr in probs]
+    graphed = [B.Solver(pr, use_graph=1, **opts) for pr in probs]
+    _say("[batched graph solvers] single solves with graphs")
+    before = [s.solve(f) for s, f in zip(graphed, fs)]
+    _say("[batched graph solvers] batch of plain solvers")
+    u0, i0 = B.solve_batched(plain, fs)
+    _say("[batched graph solvers] batch of graph solvers")
+    u1, i1 = B.solve_batched(graphed, fs)
+    torch.cuda.synchronize()
+    for i in range(len(draws)):
+        assert i1[i]["status"] == 0 and i1[i]["iters"] == i0[i]["iters"], i
+        assert torch.equal(u1[i], u0[i]), i
+    _say("[batched graph solvers] single solves with graphs after the batch")
+    for i, (s, f) in enumerate(zip(graphed, fs)):
+        u, info = s.solve(f)
+        assert info["iters"] == before[i][1]["iters"], i
+        assert torch.equal(u, before[i][0]), i
