@@ -83,7 +83,7 @@ def build_hierarchy(prob, opts):
     Level l+1 is made from level l by knot halving in every direction; the
     coarsening stops once every direction has at most mg_min_elems elements.
     lev[l].P (l >= 1) maps level-l coefficients to level l-1 (interior rows and
-    columns of the knot-insertion matrix; 2D: P_y (x) P_x).
+    columns of the knot-insertion matrix; 2D: P_y (x) P_x; 3D: P_z (x) P_y (x) P_x).
     """
     p = prob.p
     bks = [bs.uniform_breakpoints(n) for n in prob.n_el]
@@ -100,7 +100,10 @@ def build_hierarchy(prob, opts):
         hi = None if prob.sommerfeld else -1
         Ps = [sp.csr_matrix(bs.knot_insertion_prolongation(fb, c, p)[1:hi, 1:hi])
               for fb, c in zip(prev.bks, cb)]
-        P = Ps[0] if prob.dim == 1 else sp.kron(Ps[1], Ps[0]).tocsr()
+        P = Ps[0]
+        for Pd in Ps[1:]:            # x fastest: P_z (x) P_y (x) P_x
+            P = sp.kron(Pd, P)
+        P = sp.csr_matrix(P)
         lv = Level()
         lv.bks = cb
         lv.P = P
@@ -282,6 +285,8 @@ class Solver:
         self.Lz = deflation_levels(self.levels, self.opts, kmax)
         self.Zadp = None
         self.Mex_lu = None
+        if prob.dim == 3 and (self.opts.precond != 0 or self.opts.defl_z != 0 or cnn_params is not None):
+            raise ValueError("the unit cube is built with the knot-insertion deflation and the multigrid CSLP")
         if self.opts.precond == 1:
             if prob.k_elem is not None:
                 raise ValueError("C_ex is built for constant k only")
