@@ -125,7 +125,7 @@ def build_hierarchy(prob, opts):
         lv.Mb = (lv.K - opts.beta * lv.Mk_mg + rad).tocsr()
         lv.D = lv.Mb.diagonal().copy()
         lv.gersh = gershgorin_bound(lv.Mb, lv.D)
-        lv.omega = smoother_damping(l, lv.gersh, opts)
+        lv.omega = smoother_damping(l, lv.gersh, opts, prob.dim)
     # coarsest multigrid level: dense LU of M_beta
     levels[-1].Mb_lu = sla.lu_factor(levels[-1].Mb.toarray())
     return levels
@@ -160,7 +160,7 @@ def gershgorin_bound(Mb, D):
     return float(np.max(rowsum / np.abs(D)))
 
 
-def smoother_damping(l, gersh, opts):
+def smoother_damping(l, gersh, opts, dim=2):
     """Jacobi damping at level l.
 
     The finest level uses omega as given.  On coarse levels the k^2-weighted
@@ -168,9 +168,12 @@ def smoother_damping(l, gersh, opts):
     2/omega, so omega-Jacobi would amplify instead of smooth; with
     coarse_damping on, coarse levels use omega_l = min(omega, 2 / g_l), g_l the
     Gershgorin bound above (keeps |1 - omega_l lambda| bounded for every
-    eigenvalue lambda of D^-1 M_beta in the disc the bound gives).
+    eigenvalue lambda of D^-1 M_beta in the disc the bound gives).  On the unit
+    cube the three-fold tensor product of 1D masses already puts the finest
+    level's D^-1 M_beta beyond 2/omega (the V-cycle then diverges for p >= 2 at
+    k h below 1), so there the rule covers the finest level as well.
     """
-    if l == 0 or opts.coarse_damping == 0:
+    if (l == 0 and dim != 3) or opts.coarse_damping == 0:
         return opts.omega
     return min(opts.omega, 2.0 / gersh)
 

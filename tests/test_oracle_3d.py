@@ -137,3 +137,24 @@ def test_3d_rejects_variable_k_and_other_preconditioners():
         osv.Solver(prob, osv.Options(precond=1))
     with pytest.raises(ValueError):
         osv.Solver(prob, osv.Options(defl_mode=1, defl_z=1))
+
+
+@pytest.mark.parametrize("p,n_el,k", [(2, (20, 8, 10), 6.0), (3, 12, 6.0)])
+def test_3d_finest_level_damping_keeps_the_vcycle_contracting(p, n_el, k):
+    """On the cube D^-1 M_beta of the finest level reaches beyond 2/omega (omega = 0.8): with the
+    coarse levels damped and the finest one not, the V-cycle iteration x <- x - V(M_beta x)
+    grows; with omega_0 = min(omega, 2/g_0) on the finest level as well it contracts."""
+    prob = hz.Problem(3, p, n_el, k)
+    s = osv.Solver(prob, osv.Options(defl_mode=0, mg_min_elems=3))
+    lv = s.levels[0]
+    assert 2.0 / lv.gersh < 0.8 and lv.omega == 2.0 / lv.gersh
+    rng = np.random.default_rng(2)
+    x1 = rng.standard_normal(lv.N) + 0j
+    growth = {}
+    for om in (0.8, lv.omega):
+        lv.omega = om
+        x = x1.copy()
+        for _ in range(15):
+            x = x - s.vcycle(0, lv.Mb @ x)
+        growth[om] = np.linalg.norm(x) / np.linalg.norm(x1)
+    assert growth[0.8] > 1.0 and growth[lv.omega] < 0.5, growth
