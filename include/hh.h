@@ -2,7 +2,7 @@
  * hh.h - C ABI of the MI355X (gfx950) isogeometric Helmholtz solver.
  *
  * Solves A u = f for the B-spline Galerkin discretisation of
- *     -Lap u - k^2 u = f  on (0,1)^d, d = 1 or 2, u = 0 on the boundary
+ *     -Lap u - k^2 u = f  on (0,1)^d, d = 1, 2 or 3, u = 0 on the boundary
  * (the model problems MP 1-B, MP 2-A and MP 2-B, section 2 of Dwarka, Tielen,
  * Moeller and Vuik, "Towards accuracy and scalability: combining isogeometric
  * analysis with deflation ...").  A = K - M_k with K the stiffness matrix and
@@ -14,9 +14,10 @@
  *
  * Conventions
  *  - Vectors are complex double (interleaved re, im; 16 bytes per entry) in
- *    DEVICE memory owned by the caller, indexed i2 * n1 + i1 over interior
- *    control points (x fastest; 1D uses n2 = 1).  n_d = n_el_d + p - 2 at the
- *    finest level; coarse levels are reported by hh_level_info.
+ *    DEVICE memory owned by the caller, indexed (i3 * n2 + i2) * n1 + i1 over
+ *    interior control points (x fastest; 1D uses n2 = n3 = 1, 2D n3 = 1).
+ *    n_d = n_el_d + p - 2 at the finest level; coarse levels are reported by
+ *    hh_level_info.
  *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.
  *    Calls enqueue on that stream; hh_solve, hh_setup and hh_assemble return
  *    after the stream has drained.
@@ -49,9 +50,13 @@ typedef struct hh_cnn hh_cnn;
 /* Problem statement (section 2): unit interval / square, uniform open knot
  * vectors of degree p (ends repeated p+1 times, section 2.3.1), homogeneous
  * Dirichlet conditions, constant or element-wise wave number; optionally (MP
- * 1-A, section 2.1) a radiation condition at the right end of a 1D problem. */
+ * 1-A, section 2.1) a radiation condition at the right end of a 1D problem.
+ * dim = 3: the unit cube with the tensor-product basis phi_i(x) phi_j(y) phi_l(z)
+ * (section 2.3 carried to three directions; section 4.3 expects the method's
+ * advantage to grow there): constant k and Dirichlet conditions only,
+ * K = Mz (x) My (x) Kx + Mz (x) Ky (x) Mx + Kz (x) My (x) Mx, M = Mz (x) My (x) Mx. */
 typedef struct {
-    int dim;               /* 1 or 2 */
+    int dim;               /* 1, 2 or 3 */
     int p;                 /* B-spline degree, 1..5 */
     int n_el[2];           /* elements in x and y (n_el[1] ignored when dim == 1); >= 2 */
     int k_mode;            /* 0: constant k; 1: one k per finest element */
@@ -65,6 +70,7 @@ typedef struct {
                               term -i k phi_i(1) phi_j(1) joins A and M_beta (unshifted) on every
                               level; the left end stays Dirichlet (its value enters through
                               hh_rhs_dirichlet_lift) */
+    int n_el_z;            /* dim 3: elements in z (>= 2); ignored otherwise */
 } hh_problem_desc;
 
 /* Preconditioner and Krylov parameters (hh_default_opts fills the defaults). */
@@ -75,7 +81,8 @@ typedef struct {
     int n_vcycles;           /* V-cycles per preconditioner application; default 1 */
     int mg_min_elems;        /* coarsen while some direction has more elements; default 8 */
     int coarse_damping;      /* 1: coarse levels use min(omega, 2/g_l), g_l the Gershgorin
-                                bound of D^-1 M_beta,l; 0: omega everywhere; default 1 */
+                                bound of D^-1 M_beta,l (3D: the finest level too); 0: omega
+                                everywhere; default 1 */
     int defl_mode;           /* 0 none, 1 two-level, 2 multilevel; default 2 */
     int defl_direct_max;     /* multilevel: first level with at most this many unknowns is
                                 solved directly; 1..65536, default 16384 (variable k: a
@@ -186,7 +193,7 @@ typedef struct {
 typedef struct {
     int n[2];                /* interior unknowns per direction at this level */
     int n_el[2];             /* elements per direction */
-    long long N;             /* n[0] * n[1] */
+    long long N;             /* n[0] * n[1] * n_z */
     double omega;            /* Jacobi damping used at this level */
     double gersh;            /* Gershgorin bound g_l of D^-1 M_beta,l */
     int n_levels;            /* multigrid levels (finest = 0) */
@@ -203,6 +210,9 @@ typedef struct {
     int defl_refine;         /* iterative refinement steps per substructured E^-1 (set-up
                                 chooses 0..3 from the residual of one pass; each step costs
                                 one more pass) */
+    int n_z;                 /* interior unknowns in z at this level (1 unless dim == 3);
+                                N = n[0] * n[1] * n_z */
+    int n_el_z;              /* elements in z (1 unless dim == 3) */
 } hh_level_stats;
 
 /* Debug / parity operators of hh_apply. */
@@ -236,16 +246,22 @@ hh_status hh_assemble(const hh_problem_desc* d, void* stream, hh_problem** out);
 /* Idempotent on NULL. */
 hh_status hh_problem_destroy(hh_problem* pr);
 
-/* Interior unknowns per direction at the finest level (n[1] = 1 in 1D). */
+/* Interior unknowns per direction at the finest level (n[1] = 1 in 1D).
+ * HH_EINVAL for a 3D problem (use hh_problem_size3). */
 hh_status hh_problem_size(const hh_problem* pr, int n[2]);
+
+/* The same for every dimension: n[0..2], with 1 for the directions a 1D or 2D
+ * problem does not have. */
+hh_status hh_problem_size3(const hh_problem* pr, int n[3]);
 
 /* Element (knot-span) index holding x0 per direction: floor(x0 * n_el), with
  * x0 == 1 mapped to the last element (the half-open span rule of section
- * 2.3.1).  x0 outside [0,1] -> HH_EINVAL. */
+ * 2.3.1).  x0 outside [0,1] -> HH_EINVAL.  x0 and spans hold dim entries. */
 hh_status hh_point_spans(const hh_problem* pr, const double* x0, int* spans);
 
 /* Point source load f_i = amp * Phi_i(x0) (the Galerkin load of amp * delta(x - x0),
- * MP 1-B / MP 2-A / MP 2-B).  f_dev: device, N complex doubles, overwritten. */
+ * MP 1-B / MP 2-A / MP 2-B; x0 holds dim coordinates).  f_dev: device, N complex
+ * doubles, overwritten. */
 hh_status hh_rhs_point_source(const hh_problem* pr, const double* x0, double amp,
                               void* f_dev, void* stream);
 
@@ -258,9 +274,9 @@ hh_status hh_rhs_dirichlet_lift(const hh_problem* pr, double u0, void* f_dev, vo
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc): the same load as
  * hh_rhs_point_source, bit-identical, with no device or heap allocation.  The
- * two 1D basis factors are staged in a fixed device array of 65536 doubles
+ * 1D basis factors are staged in a fixed device array of 65536 doubles
  * (512 KB) that each device keeps for the life of the process; HH_EINVAL if
- * n[0] + n[1] of the finest level exceeds 65536.  The current device must be
+ * n[0] + n[1] (+ n[2] in 3D) of the finest level exceeds 65536.  The current device must be
  * the one that holds f_dev and stream.  Every call on a device shares that
  * array (the last call's contents stay in it): calls that overlap on one
  * device race; within one process they are serialised by a lock, from several
@@ -272,8 +288,8 @@ hh_status hh_rhs_point_source_noalloc(const hh_problem* pr, const double* x0, do
  * stiffness, k^2-weighted mass and A = K - M_k after Dirichlet elimination),
  * for exact comparisons of sparsity and values on small meshes; host only.
  * which: 0 K, 1 M_k, 2 A.  Rows and columns are interior indices (x fastest);
- * every entry of the tensor-product band (|i1 - j1| <= p and |i2 - j2| <= p in
- * range) is stored, columns ascending within a row.  Call with row_ptr NULL to
+ * every entry of the tensor-product band (|i1 - j1| <= p and |i2 - j2| <= p,
+ * and |i3 - j3| <= p in 3D, in range) is stored, columns ascending within a row.  Call with row_ptr NULL to
  * get *nnz only; otherwise row_ptr (N + 1), col_idx and val (capacity entries
  * each, host) are filled and HH_EINVAL is returned if capacity < nnz.  Under the
  * radiation condition (bc_right = 1) A is complex: which = 2 gives HH_EINVAL. */
@@ -287,8 +303,11 @@ hh_status hh_export_csr(const hh_problem* pr, int which, long long* nnz, long lo
  * E = My (x) Kx + Ky (x) Mx - k^2 My (x) Mx is diagonalised by the generalised
  * eigenvectors of the two 1D pencils (K, M) (fast diagonalisation: four small
  * dense passes per solve, no N_z x N_z matrix); for variable k, a dense inverse
- * (LU).  HH_ENUMERIC if E is singular.  The solver keeps a reference to the
- * problem, which must outlive it. */
+ * (LU).  HH_ENUMERIC if E is singular.  3D problems: multigrid with two-level
+ * deflation or none (defl_mode 0 or 1; HH_EINVAL for 2), E diagonalised by the
+ * three 1D pencils (six dense passes), no coarse one-workgroup tail, and neither
+ * the ADP vectors, C_ex nor a learned smoother.  The solver keeps a reference to
+ * the problem, which must outlive it. */
 hh_status hh_setup(const hh_problem* pr, const hh_solver_opts* o, void* stream,
                    hh_solver** out);
 

@@ -19,7 +19,7 @@ HH_EINVAL, HH_ENOMEM, HH_EHIP, HH_ENUMERIC = -1, -2, -3, -4
 OPS = {"A": 0, "MBETA": 1, "JACOBI0": 2, "RESTRICT": 3, "PROLONG": 4, "VCYCLE": 5, "T": 6, "EINV": 7, "K": 8, "MK": 9, "ZT": 10, "Z": 11}
 
 EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destroy", "hh_problem_size",
-            "hh_point_spans", "hh_rhs_point_source", "hh_rhs_point_source_noalloc", "hh_rhs_dirichlet_lift", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
+            "hh_problem_size3",            "hh_point_spans", "hh_rhs_point_source", "hh_rhs_point_source_noalloc", "hh_rhs_dirichlet_lift", "hh_export_csr", "hh_setup", "hh_solver_destroy", "hh_solve",
             "hh_level_info", "hh_solve_history", "hh_apply", "hh_set_kernel_timing", "hh_solve_batched", "hh_cnn_create",
             "hh_cnn_destroy", "hh_cnn_num_params", "hh_cnn_get_params", "hh_cnn_set_params", "hh_cnn_set_fused", "hh_cnn_loss_grad",
             "hh_cnn_train_step", "hh_solver_set_smoother", "hh_solver_capture", "hh_solver_captured",
@@ -29,7 +29,7 @@ EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destr
 class ProblemDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("p", ctypes.c_int), ("n_el", ctypes.c_int * 2),
                 ("k_mode", ctypes.c_int), ("k", ctypes.c_double),
-                ("k_elem", ctypes.POINTER(ctypes.c_double)), ("bc_right", ctypes.c_int)]
+                ("k_elem", ctypes.POINTER(ctypes.c_double)), ("bc_right", ctypes.c_int), ("n_el_z", ctypes.c_int)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -71,7 +71,7 @@ class LevelStats(ctypes.Structure):
                 ("omega", ctypes.c_double), ("gersh", ctypes.c_double), ("n_levels", ctypes.c_int),
                 ("defl_direct_level", ctypes.c_int), ("op_rows", ctypes.c_int * 2),
                 ("defl_sub", ctypes.c_int * 2), ("defl_sep", ctypes.c_longlong), ("defl_check", ctypes.c_double),
-                ("defl_refine", ctypes.c_int)]
+                ("defl_refine", ctypes.c_int), ("n_z", ctypes.c_int), ("n_el_z", ctypes.c_int)]
 
 
 _lib = None
@@ -92,6 +92,7 @@ def load(path=LIB_PATH):
     lib.hh_assemble.argtypes = [ctypes.POINTER(ProblemDesc), vp, ctypes.POINTER(vp)]
     lib.hh_problem_destroy.argtypes = [vp]
     lib.hh_problem_size.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.hh_problem_size3.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.hh_point_spans.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.hh_rhs_point_source.argtypes = [vp, ctypes.POINTER(ctypes.c_double), dp, vp, vp]
     lib.hh_rhs_point_source_noalloc.argtypes = [vp, ctypes.POINTER(ctypes.c_double), dp, vp, vp]
@@ -180,16 +181,17 @@ def default_opts(**kw):
 
 
 class Problem:
-    """A Helmholtz problem on (0,1)^dim: degree p, n_el elements per direction,
-    constant k or k_elem (k per finest element, x fastest)."""
+    """A Helmholtz problem on (0,1)^dim (dim 1, 2 or 3): degree p, n_el elements per
+    direction, constant k or k_elem (k per finest element, x fastest; not in 3D)."""
 
     def __init__(self, dim, p, n_el, k=None, k_elem=None, sommerfeld=False):
         lib = load()
         d = ProblemDesc()
         d.dim, d.p = int(dim), int(p)
         d.bc_right = 1 if sommerfeld else 0
-        ne = [int(n_el)] * 2 if np.isscalar(n_el) else [int(v) for v in n_el] + [1]
+        ne = [int(n_el)] * 3 if np.isscalar(n_el) else [int(v) for v in n_el] + [1, 1]
         d.n_el[0], d.n_el[1] = ne[0], ne[1]
+        d.n_el_z = ne[2] if int(dim) == 3 else 0
         self._k_arr = None
         if k_elem is not None:
             self._k_arr = np.ascontiguousarray(np.asarray(k_elem, dtype=np.float64).ravel())
@@ -200,15 +202,18 @@ class Problem:
         h = ctypes.c_void_p()
         _check(lib.hh_assemble(ctypes.byref(d), _stream() if _has_gpu() else ctypes.c_void_p(None), ctypes.byref(h)))
         self._h = h
-        n = (ctypes.c_int * 2)()
-        _check(lib.hh_problem_size(h, n))
-        self.n = (n[0], n[1])
-        self.N = n[0] * n[1]
+        n = (ctypes.c_int * 3)()
+        _check(lib.hh_problem_size3(h, n))
+        self.n = (n[0], n[1], n[2]) if int(dim) == 3 else (n[0], n[1])
+        self.N = n[0] * n[1] * n[2]
         self.dim = dim
 
+    def _point(self, x0):
+        return (ctypes.c_double * 3)(*(list(x0) + [0.0] * (3 - len(x0))))
+
     def spans(self, x0):
-        x = (ctypes.c_double * 2)(*(list(x0) + [0.0] * (2 - len(x0))))
-        out = (ctypes.c_int * 2)()
+        x = self._point(x0)
+        out = (ctypes.c_int * 3)()
         _check(load().hh_point_spans(self._h, x, out))
         return [out[i] for i in range(self.dim)]
 
@@ -228,8 +233,7 @@ class Problem:
         import torch
         if out is None:
             out = torch.empty(self.N, dtype=torch.complex128, device="cuda")
-        x = (ctypes.c_double * 2)(*(list(x0) + [0.0] * (2 - len(x0))))
-        _check(load().hh_rhs_point_source(self._h, x, float(amp), _ptr(out), _stream()))
+        _check(load().hh_rhs_point_source(self._h, self._point(x0), float(amp), _ptr(out), _stream()))
         return out
 
     def dirichlet_lift(self, u0=1.0, out=None):
@@ -242,8 +246,7 @@ class Problem:
 
     def point_source_noalloc(self, x0, out, amp=1.0):
         """hh_rhs_point_source_noalloc: the same load into the caller's `out`, no allocation."""
-        x = (ctypes.c_double * 2)(*(list(x0) + [0.0] * (2 - len(x0))))
-        _check(load().hh_rhs_point_source_noalloc(self._h, x, float(amp), _ptr(out), _stream()))
+        _check(load().hh_rhs_point_source_noalloc(self._h, self._point(x0), float(amp), _ptr(out), _stream()))
         return out
 
     def close(self):
@@ -272,7 +275,10 @@ class Solver:
     def level_info(self, level):
         st = LevelStats()
         _check(load().hh_level_info(self._h, int(level), ctypes.byref(st)))
-        return {"n": (st.n[0], st.n[1]), "n_el": (st.n_el[0], st.n_el[1]), "N": st.N,
+        three = self.problem.dim == 3
+        n = (st.n[0], st.n[1], st.n_z) if three else (st.n[0], st.n[1])
+        n_el = (st.n_el[0], st.n_el[1], st.n_el_z) if three else (st.n_el[0], st.n_el[1])
+        return {"n": n, "n_el": n_el, "N": st.N,
                 "omega": st.omega, "gersh": st.gersh, "n_levels": st.n_levels,
                 "defl_direct_level": st.defl_direct_level, "op_rows": (st.op_rows[0], st.op_rows[1]),
                 "defl_sub": (st.defl_sub[0], st.defl_sub[1]), "defl_sep": st.defl_sep, "defl_check": st.defl_check,

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhh.so")
 SOURCES = ["op_p4.hip", "op_p3.hip", "op_p5.hip", "op_p2.hip", "op_p1.hip", "kernels.hip", "solver.hip",
-           "cnn.hip", "rhs.hip", "substruct.hip", "setup.cpp", "abi.cpp"]
+           "cnn.hip", "rhs.hip", "substruct.hip", "op3d.hip", "setup.cpp", "abi.cpp"]
 ARCH = os.environ.get("HH_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]

@@ -103,8 +103,19 @@ hh_status hh_problem_destroy(hh_problem* pr) {
 hh_status hh_problem_size(const hh_problem* pr, int n[2]) {
     HH_TRY
     if (!pr || !n) throw Err{HH_EINVAL, "NULL argument"};
+    if (pr->impl.dim == 3) throw Err{HH_EINVAL, "a 3D problem has three sizes (hh_problem_size3)"};
     n[0] = pr->impl.ax0.n;
     n[1] = pr->impl.ay0.n;
+    return HH_OK;
+    HH_CATCH
+}
+
+hh_status hh_problem_size3(const hh_problem* pr, int n[3]) {
+    HH_TRY
+    if (!pr || !n) throw Err{HH_EINVAL, "NULL argument"};
+    n[0] = pr->impl.ax0.n;
+    n[1] = pr->impl.ay0.n;
+    n[2] = pr->impl.az0.n;
     return HH_OK;
     HH_CATCH
 }
@@ -138,10 +149,15 @@ hh_status hh_export_csr(const hh_problem* pr, int which, long long* nnz, long lo
     if (!const_k) galerkin_mass_stencil(P.ax0, P.ay0, P.k2, S);
     const double k2c = const_k ? P.k * P.k : 0.0;
     const long long N = P.N();
+    // rows of the tensor-product band (2D / 1D: visit_row; the cube: visit_row3)
+    auto row = [&](long long I, auto&& f) {
+        if (P.dim == 3)
+            visit_row3(P.ax0, P.ay0, P.az0, k2c, I, f);
+        else
+            visit_row(P.ax0, P.ay0, const_k, k2c, S, I, f);
+    };
     long long count = 0;
-    for (long long I = 0; I < N; ++I) visit_row(P.ax0, P.ay0, const_k, k2c, S, I, [&](long long, double, double) {
-        ++count;
-    });
+    for (long long I = 0; I < N; ++I) row(I, [&](long long, double, double) { ++count; });
     *nnz = count;
     if (!row_ptr) return HH_OK;
     if (!col_idx || !val) throw Err{HH_EINVAL, "NULL col_idx or val"};
@@ -149,7 +165,7 @@ hh_status hh_export_csr(const hh_problem* pr, int which, long long* nnz, long lo
     long long k = 0;
     for (long long I = 0; I < N; ++I) {
         row_ptr[I] = k;
-        visit_row(P.ax0, P.ay0, const_k, k2c, S, I, [&](long long J, double kv, double mv) {
+        row(I, [&](long long J, double kv, double mv) {
             col_idx[k] = (int)J;
             val[k] = which == 0 ? kv : which == 1 ? mv : kv - mv;
             ++k;
@@ -564,6 +580,7 @@ hh_status hh_cnn_load(const char* path, hh_cnn** out) {
 hh_status hh_solver_set_smoother(hh_solver* s, hh_cnn* c) {
     HH_TRY
     if (!s) throw Err{HH_EINVAL, "NULL solver"};
+    if (c && s->impl->prob->dim == 3) throw Err{HH_EINVAL, "the learned smoother is built for 1D and 2D problems"};
     s->impl->cnn = c ? c->impl.get() : nullptr;
     s->impl->drop_graphs();   // the smoother changes the captured step
     return HH_OK;
@@ -641,6 +658,8 @@ hh_status hh_level_info(const hh_solver* s, int level, hh_level_stats* out) {
     out->defl_sep = sub_here ? S.sub->nS : 0;
     out->defl_check = sub_here ? S.sub->self_check : -1.0;
     out->defl_refine = sub_here ? S.sub->refine : 0;
+    out->n_z = lv.n3;
+    out->n_el_z = lv.az.nel;
     return HH_OK;
     HH_CATCH
 }

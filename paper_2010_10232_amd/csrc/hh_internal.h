@@ -143,6 +143,32 @@ struct Axis {
 // ------------------------------------------------------------- host math --
 // Visits the nonzero stencil entries of row I of level data (K entries from
 // the bands; M_k entries from k^2 (constant) or the stored stencil S).
+// Unit cube (constant k): the (2p+1)^3 entries of row I,
+// K = Mz (x) My (x) Kx + Mz (x) Ky (x) Mx + Kz (x) My (x) Mx and M_k = k^2 Mz (x) My (x) Mx.
+template <class F>
+inline void visit_row3(const Axis& ax, const Axis& ay, const Axis& az, double k2c, long long I, F&& f) {
+    const int px = ax.p, py = ay.p, pz = az.p, bx = 2 * px + 1, by = 2 * py + 1, bz = 2 * pz + 1;
+    const int n1 = ax.n, n2 = ay.n, n3 = az.n;
+    const int I1 = (int)(I % n1), I2 = (int)((I / n1) % n2), I3 = (int)(I / ((long long)n1 * n2));
+    for (int d3 = -pz; d3 <= pz; ++d3) {
+        const int J3 = I3 + d3;
+        if (J3 < 0 || J3 >= n3) continue;
+        const double mz = az.Mb[(size_t)I3 * bz + d3 + pz], kz = az.Kb[(size_t)I3 * bz + d3 + pz];
+        for (int d2 = -py; d2 <= py; ++d2) {
+            const int J2 = I2 + d2;
+            if (J2 < 0 || J2 >= n2) continue;
+            const double my = ay.Mb[(size_t)I2 * by + d2 + py], ky = ay.Kb[(size_t)I2 * by + d2 + py];
+            for (int d1 = -px; d1 <= px; ++d1) {
+                const int J1 = I1 + d1;
+                if (J1 < 0 || J1 >= n1) continue;
+                const double mx = ax.Mb[(size_t)I1 * bx + d1 + px], kx = ax.Kb[(size_t)I1 * bx + d1 + px];
+                const double kv = mz * (my * kx + ky * mx) + kz * my * mx;
+                f(((long long)J3 * n2 + J2) * n1 + J1, kv, k2c * mz * my * mx);
+            }
+        }
+    }
+}
+
 template <class F>
 inline void visit_row(const Axis& ax, const Axis& ay, bool const_k, double k2c, const std::vector<double>& S,
                       long long I, F&& f) {
@@ -229,6 +255,10 @@ struct OpArgs {
     // radiation condition: y[bnd_I] += i bnd_im x[bnd_I] (bnd_I < 0: none)
     long long bnd_I;
     T bnd_im;
+    // unit cube (constant k): n3 >= 1 slices in z with bands Kz, Mz; 0 for 1D / 2D
+    int n3;
+    const double* Kz;
+    const double* Mz;
 };
 
 struct Transfer {
@@ -242,6 +272,12 @@ struct Transfer {
     const double* pcolx;
     const int* pcol0y;
     const double* pcoly;
+    // unit cube: the z factor of P = P_z (x) P_y (x) P_x; nf3 = 0 for 1D / 2D
+    int nf3, nc3, pw3, rw3;
+    const int* prow0z;
+    const double* prowz;
+    const int* pcol0z;
+    const double* pcolz;
 };
 
 // State of one FGMRES instance (device memory), m = max Arnoldi steps.
@@ -358,6 +394,21 @@ template <class T>
 void launch_vcycle_tail(const TailDesc<T>* desc, const void* img, int img16, const cx<T>* minv, int P, int l0,
                         int lds_bytes, const cx<T>* b, cx<T>* x,
                         hipStream_t s);   // P: degree of 2D levels (unrolled form), 0: any
+// Unit cube (constant k): level operator, transfers and the fast-diagonalisation
+// E^-1 (op3d.hip).  launch_op, launch_restrict and launch_prolong_add hand
+// levels with a.n3 > 0 / t.nf3 > 0 to these.
+template <class T>
+void launch_op3d(int mode, int p, const OpArgs<T>& a, hipStream_t s);
+template <class T>
+void launch_restrict3(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s, const cx<T>* dinv, T omega,
+                      cx<T>* xs);
+template <class T>
+void launch_prolong_add3(const Transfer& t, const cx<T>* e, const cx<T>* xin, cx<T>* xout, hipStream_t s);
+// e = V diag(dinv) V^T c, V = Vz (x) Vy (x) Vx on an [n3][n2][n1] grid (VdT: V_d transposed,
+// all row-major; t1, t2: N-vector scratch)
+void launch_fdm3_solve(int n3, int n2, int n1, const double* Vx, const double* VxT, const double* Vy,
+                       const double* VyT, const double* Vz, const double* VzT, const double* dinv,
+                       const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s);
 // e = (Vy (x) Vx) diag(dinv) (Vy (x) Vx)^T c on an [n2][n1] grid (t1, t2: N-vector scratch);
 // with cdinv the diagonal is complex (cdinv used, dinv ignored)
 void launch_fdm_solve(int n2, int n1, const double* Vx, const double* VxT, const double* Vy, const double* dinv,

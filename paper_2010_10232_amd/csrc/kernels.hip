@@ -22,6 +22,10 @@ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
 // --------------------------------------------------------------------------
 template <class T>
 void launch_op(int kind, int mode, int px, int py, const OpArgs<T>& a, hipStream_t s) {
+    if (a.n3 > 0) {
+        if (kind != KIND_SEP || py != px) throw Err{HH_EINVAL, "3D levels are constant-k with one degree"};
+        return launch_op3d<T>(mode, px, a, s);
+    }
     if (a.n1 <= 0 || a.n2 <= 0) return;
     if (py != 0 && py != px) throw Err{HH_EINVAL, "unsupported degree pair"};
     switch (px) {
@@ -204,6 +208,7 @@ thread_local Meter* g_meter = nullptr;
 template <class T>
 void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s, const cx<T>* dinv, T omega,
                      cx<T>* xs) {
+    if (t.nf3 > 0) return launch_restrict3<T>(t, r, c, s, dinv, omega, xs);
     const long long Nc = (long long)t.nc1 * t.nc2;
     if (Nc <= 0) return;
     meter(sizeof(cx<T>) * ((double)t.nf1 * t.nf2 + Nc * (dinv ? 3.0 : 1.0)),
@@ -214,6 +219,7 @@ void launch_restrict(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s,
 }
 template <class T>
 void launch_prolong_add(const Transfer& t, const cx<T>* e, const cx<T>* xin, cx<T>* xout, hipStream_t s) {
+    if (t.nf3 > 0) return launch_prolong_add3<T>(t, e, xin, xout, s);
     const long long Nf = (long long)t.nf1 * t.nf2;
     if (Nf <= 0) return;
     meter(sizeof(cx<T>) * ((double)t.nc1 * t.nc2 + Nf * (xin ? 2.0 : 1.0)),

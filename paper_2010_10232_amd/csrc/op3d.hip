@@ -1,0 +1,372 @@
+// Unit-cube kernels for gfx950 (CDNA4, wave64): the level operator, the
+// knot-insertion transfers and the fast-diagonalisation E^-1 of 3D
+// tensor-product B-spline levels with constant k (section 2.3 carried to three
+// directions; section 3's multigrid CSLP and two-level deflation on top).
+//
+// Level operator.  With the 1D bands K_d, M_d of each direction,
+//   y = K x - alpha k^2 M x
+//     = Mz (x) [My (x) Kx + Ky (x) Mx - alpha k^2 My (x) Mx] x + Kz (x) [My (x) Mx] x,
+// so every z-slice J3 of x enters through two 2D products, B2 (the bracket) and
+// M2 (the 2D mass), combined through the z bands:
+//   y_{i3} = sum_{J3} mz[i3][J3 - i3] B2(x_{J3}) + kz[i3][J3 - i3] M2(x_{J3}).
+// A workgroup of 256 threads owns a 32 (x) by 8 (y) column tile and a run of
+// tz output slices.  It walks the tz + 2p input slices once: each slice tile
+// plus its p-wide halo is staged in LDS (the next slice is already in flight
+// in registers), the x bands are applied once per staged row (sum
+// factorisation: Kx x and Mx x per row into LDS), then every thread forms B2
+// and M2 of its column through the y bands and adds them into a window of
+// 2p + 1 running output slices held in registers (mz, kz as weights).  After
+// input slice J3, output slice J3 - p is complete and is written with the
+// residual / Jacobi epilogue of the 2D kernels.  Per unknown and slice this is
+// 2(2p+1) + 3(2p+1) + 2(2p+1) complex-by-real multiply-adds instead of the
+// (2p+1)^3 of a point-wise stencil.
+#include <algorithm>
+#include <climits>
+
+#include "hh_internal.h"
+
+namespace hh {
+
+namespace {
+
+constexpr int O3_TX = 32, O3_TY = 8, O3_TB = O3_TX * O3_TY;
+
+template <int P, int MODE, class T>
+__global__ __launch_bounds__(O3_TB) void op3d_kernel(OpArgs<T> a, int tz) {
+    constexpr int B = 2 * P + 1;
+    constexpr int LW = O3_TX + 2 * P, LH = O3_TY + 2 * P;
+    constexpr int NL = (LH * LW + O3_TB - 1) / O3_TB;   // staged values per thread
+    __shared__ cx<T> xs[LH][LW];
+    __shared__ cx<T> us[2][LH][O3_TX];                   // Kx x, Mx x of every staged row
+
+    const int n1 = a.n1, n2 = a.n2, n3 = a.n3;
+    const int tiles_x = (n1 + O3_TX - 1) / O3_TX, tiles_y = (n2 + O3_TY - 1) / O3_TY;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = b % tiles_x, rest = b / tiles_x;
+    const int C0 = bx * O3_TX, R0 = (rest % tiles_y) * O3_TY, Z0 = (rest / tiles_y) * tz;
+    const int tid = threadIdx.x;
+    const int c = tid % O3_TX, r = tid / O3_TX;
+    const int I1 = C0 + c, I2 = R0 + r;
+    const int I1c = I1 < n1 ? I1 : n1 - 1, I2c = I2 < n2 ? I2 : n2 - 1;
+    T kx[B], mx[B], ky[B], my[B];
+#pragma unroll
+    for (int d = 0; d < B; ++d) {
+        kx[d] = (T)a.Kx[(size_t)I1c * B + d];
+        mx[d] = (T)a.Mx[(size_t)I1c * B + d];
+        ky[d] = (T)a.Ky[(size_t)I2c * B + d];
+        my[d] = (T)a.My[(size_t)I2c * B + d];
+    }
+    cx<T> pre[NL];
+    auto fetch = [&](int J3) {
+        const bool zok = J3 >= 0 && J3 < n3;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int e = tid + O3_TB * q;
+            cx<T> v = {T(0), T(0)};
+            if (zok && e < LH * LW) {
+                const int rr = e / LW, cc = e - rr * LW;
+                const int J2 = R0 - P + rr, J1 = C0 - P + cc;
+                if (J2 >= 0 && J2 < n2 && J1 >= 0 && J1 < n1) v = a.x[((size_t)J3 * n2 + J2) * n1 + J1];
+            }
+            pre[q] = v;
+        }
+    };
+    const int zend = Z0 + tz < n3 ? Z0 + tz : n3;
+    const int s0 = Z0 - P, s1 = zend - 1 + P;
+    T wr[B], wi[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) wr[k] = wi[k] = T(0);
+    const T are = a.are, aim = a.aim;
+    const T k2c = (T)a.k2c;
+    const bool active = I1 < n1 && I2 < n2;
+
+    fetch(s0);
+#pragma unroll 1
+    for (int J3 = s0; J3 <= s1; ++J3) {
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int e = tid + O3_TB * q;
+            if (e < LH * LW) xs[e / LW][e % LW] = pre[q];
+        }
+        __syncthreads();
+        if (J3 < s1) fetch(J3 + 1);
+        // x bands once per staged row (every item of this thread has column c)
+        for (int e = tid; e < LH * O3_TX; e += O3_TB) {
+            const int rr = e / O3_TX;
+            T u1r = 0, u1i = 0, u2r = 0, u2i = 0;
+#pragma unroll
+            for (int d = 0; d < B; ++d) {
+                const cx<T> v = xs[rr][c + d];
+                u1r += kx[d] * v.re;
+                u1i += kx[d] * v.im;
+                u2r += mx[d] * v.re;
+                u2i += mx[d] * v.im;
+            }
+            us[0][rr][c] = {u1r, u1i};
+            us[1][rr][c] = {u2r, u2i};
+        }
+        __syncthreads();
+        if (J3 >= 0 && J3 < n3) {
+            // B2 and M2 of this column through the y bands
+            T br = 0, bi = 0, mr = 0, mi = 0;
+#pragma unroll
+            for (int d2 = 0; d2 < B; ++d2) {
+                const cx<T> u1 = us[0][r + d2][c], u2 = us[1][r + d2][c];
+                const T cr = u1.re - k2c * (are * u2.re - aim * u2.im);
+                const T ci = u1.im - k2c * (are * u2.im + aim * u2.re);
+                br += my[d2] * cr + ky[d2] * u2.re;
+                bi += my[d2] * ci + ky[d2] * u2.im;
+                mr += my[d2] * u2.re;
+                mi += my[d2] * u2.im;
+            }
+            // window entry k is output slice J3 - p + k, coupled at offset J3 - i3 = p - k
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                int i3 = J3 - P + k;
+                i3 = i3 < 0 ? 0 : (i3 >= n3 ? n3 - 1 : i3);
+                const T mz = (T)a.Mz[(size_t)i3 * B + 2 * P - k], kz = (T)a.Kz[(size_t)i3 * B + 2 * P - k];
+                wr[k] += mz * br + kz * mr;
+                wi[k] += mz * bi + kz * mi;
+            }
+        }
+        // output slice J3 - p has all its input slices
+        const int i3 = J3 - P;
+        if (active && i3 >= Z0 && i3 < zend) {
+            const size_t I = ((size_t)i3 * n2 + I2) * n1 + I1;
+            const T yr = wr[0], yi = wi[0];
+            cx<T> out;
+            if (MODE == MODE_APPLY) {
+                out = {yr, yi};
+            } else {
+                const cx<T> bv = a.b[I];
+                const T rr = bv.re - yr, ri = bv.im - yi;
+                if (MODE == MODE_RESID) {
+                    out = {rr, ri};
+                    if (a.xo) {
+                        const cx<T> d = a.dinv[I];
+                        a.xo[I] = {a.omega * (d.re * rr - d.im * ri), a.omega * (d.re * ri + d.im * rr)};
+                    }
+                } else {
+                    const cx<T> dv = a.dinv[I], xv = a.x[I];
+                    out = {xv.re + a.omega * (dv.re * rr - dv.im * ri), xv.im + a.omega * (dv.re * ri + dv.im * rr)};
+                    if (a.yadd) {
+                        const cx<T> q = a.yadd[I];
+                        out = {out.re + q.re, out.im + q.im};
+                    }
+                }
+            }
+            a.y[I] = out;
+        }
+#pragma unroll
+        for (int k = 0; k + 1 < B; ++k) {
+            wr[k] = wr[k + 1];
+            wi[k] = wi[k + 1];
+        }
+        wr[B - 1] = wi[B - 1] = T(0);
+    }
+}
+
+// Output slices per workgroup: a tuned value (a power of two in 2..64), else
+// the longest of 16, 8, 4, 2 that still gives 1024 workgroups (four per CU).
+inline int op3d_slices(int n1, int n2, int n3, int tuned) {
+    if (tuned >= 2 && tuned <= 64 && (tuned & (tuned - 1)) == 0) return tuned;
+    const long long tiles = (long long)((n1 + O3_TX - 1) / O3_TX) * ((n2 + O3_TY - 1) / O3_TY);
+    int tz = 16;
+    while (tz > 2 && tiles * ((n3 + tz - 1) / tz) < 1024) tz >>= 1;
+    return tz;
+}
+
+template <int P, class T>
+void launch_op3d_p(int mode, const OpArgs<T>& a, hipStream_t s) {
+    const int tz = op3d_slices(a.n1, a.n2, a.n3, a.ty);
+    const long long blocks = (long long)((a.n1 + O3_TX - 1) / O3_TX) * ((a.n2 + O3_TY - 1) / O3_TY) *
+                             ((a.n3 + tz - 1) / tz);
+    if (blocks > INT_MAX) throw Err{HH_EINVAL, "level too large for the 3D operator"};
+    switch (mode) {
+        case MODE_APPLY:
+            hipLaunchKernelGGL((op3d_kernel<P, MODE_APPLY, T>), dim3((unsigned)blocks), dim3(O3_TB), 0, s, a, tz);
+            return;
+        case MODE_RESID:
+            hipLaunchKernelGGL((op3d_kernel<P, MODE_RESID, T>), dim3((unsigned)blocks), dim3(O3_TB), 0, s, a, tz);
+            return;
+        case MODE_SMOOTH:
+            hipLaunchKernelGGL((op3d_kernel<P, MODE_SMOOTH, T>), dim3((unsigned)blocks), dim3(O3_TB), 0, s, a, tz);
+            return;
+    }
+    throw Err{HH_EINVAL, "bad operator mode"};
+}
+
+// ------------------------------------------------------------- transfers --
+// c = P^T r and x (+)= P e with P = P_z (x) P_y (x) P_x, each factor stored as
+// per-row / per-column runs (as in the 2D transfers); one thread per output.
+template <class T>
+__global__ void restrict3_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* __restrict__ c,
+                                 const cx<T>* __restrict__ dinv, T omega, cx<T>* __restrict__ xs) {
+    const long long Nc = (long long)t.nc1 * t.nc2 * t.nc3;
+    const long long idx = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= Nc) return;
+    const int J1 = (int)(idx % t.nc1), J2 = (int)((idx / t.nc1) % t.nc2), J3 = (int)(idx / ((long long)t.nc1 * t.nc2));
+    const int i0x = t.pcol0x[J1], i0y = t.pcol0y[J2], i0z = t.pcol0z[J3];
+    T sr = 0, si = 0;
+    for (int a3 = 0; a3 < t.rw3; ++a3) {
+        const T wz = (T)t.pcolz[(size_t)J3 * t.rw3 + a3];
+        if (wz == T(0)) continue;
+        const cx<T>* plane = r + (size_t)(i0z + a3) * t.nf2 * t.nf1;
+        T pr = 0, pi = 0;
+        for (int a2 = 0; a2 < t.rw2; ++a2) {
+            const T wy = (T)t.pcoly[(size_t)J2 * t.rw2 + a2];
+            if (wy == T(0)) continue;
+            const cx<T>* row = plane + (size_t)(i0y + a2) * t.nf1 + i0x;
+            T rr = 0, ri = 0;
+            for (int a1 = 0; a1 < t.rw1; ++a1) {
+                const T wx = (T)t.pcolx[(size_t)J1 * t.rw1 + a1];
+                const cx<T> v = row[a1];
+                rr += wx * v.re;
+                ri += wx * v.im;
+            }
+            pr += wy * rr;
+            pi += wy * ri;
+        }
+        sr += wz * pr;
+        si += wz * pi;
+    }
+    c[idx] = {sr, si};
+    if (dinv) {
+        const cx<T> d = dinv[idx];
+        xs[idx] = {omega * (d.re * sr - d.im * si), omega * (d.re * si + d.im * sr)};
+    }
+}
+
+template <class T>
+__global__ void prolong3_kernel(Transfer t, const cx<T>* __restrict__ e, const cx<T>* xin, cx<T>* x) {
+    const long long Nf = (long long)t.nf1 * t.nf2 * t.nf3;
+    const long long idx = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= Nf) return;
+    const int I1 = (int)(idx % t.nf1), I2 = (int)((idx / t.nf1) % t.nf2), I3 = (int)(idx / ((long long)t.nf1 * t.nf2));
+    const int j0x = t.prow0x[I1], j0y = t.prow0y[I2], j0z = t.prow0z[I3];
+    T sr = 0, si = 0;
+    for (int b3 = 0; b3 < t.pw3; ++b3) {
+        const T wz = (T)t.prowz[(size_t)I3 * t.pw3 + b3];
+        if (wz == T(0)) continue;
+        const cx<T>* plane = e + (size_t)(j0z + b3) * t.nc2 * t.nc1;
+        T pr = 0, pi = 0;
+        for (int b2 = 0; b2 < t.pw2; ++b2) {
+            const T wy = (T)t.prowy[(size_t)I2 * t.pw2 + b2];
+            if (wy == T(0)) continue;
+            const cx<T>* row = plane + (size_t)(j0y + b2) * t.nc1 + j0x;
+            T rr = 0, ri = 0;
+            for (int b1 = 0; b1 < t.pw1; ++b1) {
+                const T wx = (T)t.prowx[(size_t)I1 * t.pw1 + b1];
+                const cx<T> v = row[b1];
+                rr += wx * v.re;
+                ri += wx * v.im;
+            }
+            pr += wy * rr;
+            pi += wy * ri;
+        }
+        sr += wz * pr;
+        si += wz * pi;
+    }
+    if (xin) {
+        const cx<T> o = xin[idx];
+        x[idx] = {o.re + sr, o.im + si};
+    } else {
+        x[idx] = {sr, si};
+    }
+}
+
+// --------------------------------------------------- fast diagonalisation --
+// out = (A along one axis) in: out[.., i, ..] = sum_j A[i][j] in[.., j, ..]
+// (A row-major n_a x n_a), times scale[idx] when scale is given.
+__global__ void fdm3_pass_kernel(int n1, int n2, int n3, int axis, const double* __restrict__ A,
+                                 const cx<double>* __restrict__ in, cx<double>* __restrict__ out,
+                                 const double* __restrict__ scale) {
+    const long long N = (long long)n1 * n2 * n3;
+    const long long idx = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= N) return;
+    const int i1 = (int)(idx % n1), i2 = (int)((idx / n1) % n2), i3 = (int)(idx / ((long long)n1 * n2));
+    const int na = axis == 0 ? n1 : axis == 1 ? n2 : n3;
+    const int i = axis == 0 ? i1 : axis == 1 ? i2 : i3;
+    const long long stride = axis == 0 ? 1 : axis == 1 ? n1 : (long long)n1 * n2;
+    const cx<double>* src = in + (idx - (long long)i * stride);
+    const double* row = A + (size_t)i * na;
+    double sr = 0, si = 0;
+    for (int j = 0; j < na; ++j) {
+        const double w = row[j];
+        const cx<double> v = src[(size_t)j * stride];
+        sr += w * v.re;
+        si += w * v.im;
+    }
+    if (scale) {
+        const double g = scale[idx];
+        sr *= g;
+        si *= g;
+    }
+    out[idx] = {sr, si};
+}
+
+inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+template <class T>
+void launch_op3d(int mode, int p, const OpArgs<T>& a, hipStream_t s) {
+    if (a.n1 <= 0 || a.n2 <= 0 || a.n3 <= 0) return;
+    switch (p) {
+        case 1: return launch_op3d_p<1, T>(mode, a, s);
+        case 2: return launch_op3d_p<2, T>(mode, a, s);
+        case 3: return launch_op3d_p<3, T>(mode, a, s);
+        case 4: return launch_op3d_p<4, T>(mode, a, s);
+        case 5: return launch_op3d_p<5, T>(mode, a, s);
+    }
+    throw Err{HH_EINVAL, "unsupported degree"};
+}
+template void launch_op3d<double>(int, int, const OpArgs<double>&, hipStream_t);
+template void launch_op3d<float>(int, int, const OpArgs<float>&, hipStream_t);
+
+template <class T>
+void launch_restrict3(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s, const cx<T>* dinv, T omega,
+                      cx<T>* xs) {
+    const long long Nc = (long long)t.nc1 * t.nc2 * t.nc3, Nf = (long long)t.nf1 * t.nf2 * t.nf3;
+    if (Nc <= 0) return;
+    if (Nc > INT_MAX || Nf > INT_MAX) throw Err{HH_EINVAL, "level too large for a transfer"};
+    meter(sizeof(cx<T>) * ((double)Nf + Nc * (dinv ? 3.0 : 1.0)),
+          4.0 * t.rw1 * t.rw2 * t.rw3 * (double)Nc + (dinv ? 8.0 * Nc : 0.0));
+    hipLaunchKernelGGL(restrict3_kernel<T>, dim3(blocks_for(Nc, 256)), dim3(256), 0, s, t, r, c, dinv, omega, xs);
+}
+template <class T>
+void launch_prolong_add3(const Transfer& t, const cx<T>* e, const cx<T>* xin, cx<T>* xout, hipStream_t s) {
+    const long long Nc = (long long)t.nc1 * t.nc2 * t.nc3, Nf = (long long)t.nf1 * t.nf2 * t.nf3;
+    if (Nf <= 0) return;
+    if (Nc > INT_MAX || Nf > INT_MAX) throw Err{HH_EINVAL, "level too large for a transfer"};
+    meter(sizeof(cx<T>) * ((double)Nc + Nf * (xin ? 2.0 : 1.0)),
+          4.0 * t.pw1 * t.pw2 * t.pw3 * (double)Nf + (xin ? 2.0 * Nf : 0.0));
+    hipLaunchKernelGGL(prolong3_kernel<T>, dim3(blocks_for(Nf, 256)), dim3(256), 0, s, t, e, xin, xout);
+}
+template void launch_restrict3<double>(const Transfer&, const cx<double>*, cx<double>*, hipStream_t,
+                                       const cx<double>*, double, cx<double>*);
+template void launch_restrict3<float>(const Transfer&, const cx<float>*, cx<float>*, hipStream_t, const cx<float>*,
+                                      float, cx<float>*);
+template void launch_prolong_add3<double>(const Transfer&, const cx<double>*, const cx<double>*, cx<double>*,
+                                          hipStream_t);
+template void launch_prolong_add3<float>(const Transfer&, const cx<float>*, const cx<float>*, cx<float>*,
+                                         hipStream_t);
+
+void launch_fdm3_solve(int n3, int n2, int n1, const double* Vx, const double* VxT, const double* Vy,
+                       const double* VyT, const double* Vz, const double* VzT, const double* dinv,
+                       const cx<double>* c, cx<double>* t1, cx<double>* t2, cx<double>* e, hipStream_t s) {
+    const long long N = (long long)n1 * n2 * n3;
+    if (N <= 0) return;
+    if (N > INT_MAX) throw Err{HH_EINVAL, "deflation level too large"};
+    meter(6.0 * 32.0 * N + 8.0 * N, 4.0 * N * ((double)n1 + n2 + n3) * 2.0);
+    const unsigned g = blocks_for(N, 256);
+    // V^T c along x, y, z (the last scaled by 1 / D), then V along z, y, x
+    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 0, VxT, c, t1, nullptr);
+    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 1, VyT, t1, t2, nullptr);
+    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 2, VzT, t2, t1, dinv);
+    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 2, Vz, t1, t2, nullptr);
+    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 1, Vy, t2, t1, nullptr);
+    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 0, Vx, t1, e, nullptr);
+}
+
+}  // namespace hh

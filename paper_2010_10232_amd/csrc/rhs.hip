@@ -1,9 +1,11 @@
 // Point-source load on the device (MP 1-B, MP 2-A, MP 2-B: the Galerkin load of
 // amp * delta(x - x0) is f_i = amp * Phi_i(x0), section 2.3).  Phi_i is a tensor
 // product, so the host evaluates the p + 1 nonzero B-splines per direction at
-// x0 (a few flops), stages the two 1D factor vectors fx[n1], fy[n2] in device
-// memory, and one kernel writes f[i2][i1] = (amp * fy[i2]) * fx[i1] over the
-// whole grid.  Only n1 + n2 values cross the host link instead of N.
+// x0 (a few flops), stages the 1D factor vectors fx[n1], fy[n2] (and fz[n3] on
+// the unit cube) in device memory, and one kernel writes
+// f[i3][i2][i1] = ((amp * fz[i3]) * fy[i2]) * fx[i1] over the whole grid (fz = 1
+// without a z direction).  Only n1 + n2 (+ n3) values cross the host link
+// instead of N.
 #include <cmath>
 #include <mutex>
 
@@ -13,15 +15,20 @@ namespace hh {
 
 namespace {
 
-__global__ void __launch_bounds__(256) point_source_kernel(int n1, long long N, const double* __restrict__ stage,
-                                                            double amp, cx<double>* __restrict__ f) {
+__global__ void __launch_bounds__(256) point_source_kernel(int n1, int n2, int has_z, long long N,
+                                                            const double* __restrict__ stage, double amp,
+                                                            cx<double>* __restrict__ f) {
     const double* fx = stage;
     const double* fy = stage + n1;
+    const double* fz = stage + n1 + n2;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
-        const int i2 = (int)(i / n1);
-        const int i1 = (int)(i - (long long)i2 * n1);
-        f[i] = cx<double>{amp * fy[i2] * fx[i1], 0.0};
+        const long long i23 = i / n1;
+        const int i1 = (int)(i - i23 * n1);
+        const int i3 = (int)(i23 / n2);
+        const int i2 = (int)(i23 - (long long)i3 * n2);
+        const double az = has_z ? amp * fz[i3] : amp;
+        f[i] = cx<double>{az * fy[i2] * fx[i1], 0.0};
     }
 }
 
@@ -30,12 +37,16 @@ int span_of(double x, int nel) {
     return e < nel - 1 ? e : nel - 1;
 }
 
+// Staged values: n1 + n2, and n3 more on the unit cube.
+int stage_size(const ProblemImpl& P) { return P.ax0.n + P.ay0.n + (P.dim == 3 ? P.az0.n : 0); }
+
 // The 1D factors of Phi(x0) over the interior unknowns: stage[0..n1) in x,
-// stage[n1..n1+n2) in y (1D problems: fy = [1]).  stage must hold n1 + n2
-// doubles; everything but the p + 1 supported entries per direction is zero.
+// stage[n1..n1+n2) in y (1D problems: fy = [1]), stage[n1+n2..n1+n2+n3) in z on
+// the unit cube.  stage must hold stage_size(P) doubles; everything but the
+// p + 1 supported entries per direction is zero.
 void point_factors(const ProblemImpl& P, const double* x0, double* stage) {
     const int n1 = P.ax0.n, n2 = P.ay0.n, p = P.p;
-    for (int i = 0; i < n1 + n2; ++i) stage[i] = 0.0;
+    for (int i = 0; i < stage_size(P); ++i) stage[i] = 0.0;
     double Nv[8];
     const int s1 = span_of(x0[0], P.nel[0]);
     basis_values(P.ax0.U, p, s1 + p, x0[0], Nv, nullptr);
@@ -43,7 +54,7 @@ void point_factors(const ProblemImpl& P, const double* x0, double* stage) {
         const int i = s1 + a - 1;
         if (i >= 0 && i < n1) stage[i] = Nv[a];
     }
-    if (P.dim == 2) {
+    if (P.dim >= 2) {
         const int s2 = span_of(x0[1], P.nel[1]);
         basis_values(P.ay0.U, p, s2 + p, x0[1], Nv, nullptr);
         for (int a = 0; a <= p; ++a) {
@@ -52,6 +63,15 @@ void point_factors(const ProblemImpl& P, const double* x0, double* stage) {
         }
     } else {
         stage[n1] = 1.0;
+    }
+    if (P.dim == 3) {
+        const int n3 = P.az0.n;
+        const int s3 = span_of(x0[2], P.nel[2]);
+        basis_values(P.az0.U, p, s3 + p, x0[2], Nv, nullptr);
+        for (int a = 0; a <= p; ++a) {
+            const int i = s3 + a - 1;
+            if (i >= 0 && i < n3) stage[n1 + n2 + i] = Nv[a];
+        }
     }
 }
 
@@ -64,12 +84,12 @@ void launch_point_source(const ProblemImpl& P, const double* stage_dev, double a
                          hipStream_t s) {
     const long long N = P.N();
     const int blocks = (int)std::min<long long>((N + 255) / 256, 8192);
-    point_source_kernel<<<blocks, 256, 0, s>>>(P.ax0.n, N, stage_dev, amp, f);
+    point_source_kernel<<<blocks, 256, 0, s>>>(P.ax0.n, P.ay0.n, P.dim == 3 ? 1 : 0, N, stage_dev, amp, f);
     HH_HIP(hipGetLastError());
 }
 
 // ---- allocation-free variant: the staging lives in a fixed device array ----
-// Capacity of the staging array in doubles (n1 + n2 of the finest level).
+// Capacity of the staging array in doubles (n1 + n2 (+ n3) of the finest level).
 constexpr int kStageMax = 65536;
 static __device__ __align__(256) double scratch[kStageMax];
 // In host code `scratch` names a host-side stand-in; its device address is
@@ -97,7 +117,7 @@ double* scratch_on_current_device() {
 // Regular path: the staging buffer is allocated by the library for the call.
 void rhs_point_source(const ProblemImpl& P, const double* x0, double amp, cx<double>* f, hipStream_t s) {
     check_point(P, x0);
-    const int n = P.ax0.n + P.ay0.n;
+    const int n = stage_size(P);
     std::vector<double> stage((size_t)n);
     point_factors(P, x0, stage.data());
     DevBuf d;
@@ -111,9 +131,9 @@ void rhs_point_source(const ProblemImpl& P, const double* x0, double amp, cx<dou
 // allocation.  Calls overlapping on one device share the array and race.
 void rhs_point_source_noalloc(const ProblemImpl& P, const double* x0, double amp, cx<double>* f, hipStream_t s) {
     check_point(P, x0);
-    const int n = P.ax0.n + P.ay0.n;
+    const int n = stage_size(P);
     if (n > kStageMax)
-        throw Err{HH_EINVAL, "n1 + n2 = " + std::to_string(n) + " exceeds the staging capacity of " +
+        throw Err{HH_EINVAL, "n1 + n2 (+ n3) = " + std::to_string(n) + " exceeds the staging capacity of " +
                                  std::to_string(kStageMax) + " values"};
     std::lock_guard<std::mutex> lk(g_scratch_mu);
     double* stage_dev = scratch_on_current_device();

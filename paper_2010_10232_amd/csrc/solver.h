@@ -11,19 +11,19 @@
 namespace hh {
 
 struct ProblemImpl {
-    int dim = 2, p = 3, nel[2] = {1, 1};
+    int dim = 2, p = 3, nel[3] = {1, 1, 1};
     int k_mode = 0;
     double k = 0.0;
     bool somm = false;        // radiation condition at x = 1 (1D, constant k; MP 1-A)
     std::vector<double> k2;   // k^2 per finest element [nel_y][nel_x] (1D: [1][nel_x])
     mutable DevBuf k2_dev;    // the same on the device (uploaded by hh_assemble on its stream, else by hh_setup)
-    Axis ax0, ay0;            // finest-level axes
-    long long N() const { return (long long)ax0.n * ay0.n; }
+    Axis ax0, ay0, az0;       // finest-level axes (az0 trivial unless dim == 3)
+    long long N() const { return (long long)ax0.n * ay0.n * az0.n; }
 };
 
 struct LevelDev {
-    Axis ax, ay;
-    int n1 = 1, n2 = 1;
+    Axis ax, ay, az;          // az: trivial unless dim == 3
+    int n1 = 1, n2 = 1, n3 = 1;
     long long N = 1;
     double omega = 0.8, gersh = 0.0;
     int kind = KIND_SEP;
@@ -31,13 +31,14 @@ struct LevelDev {
     long long bnd_I = -1;
     double bnd_im = 0.0;
     int ty64 = 0, ty32 = 0;   // level-operator strip height (0: fixed rule), FP64 / FP32
-    DevBuf Kx, Mx, Ky, My;
+    DevBuf Kx, Mx, Ky, My, Kz, Mz;
     DevBuf S64, S32;
     DevBuf S64a;              // Galerkin stencil of A_l when the multigrid one is rediscretised
     DevBuf k2, Mex, Mey;
     DevBuf Dinv64, Dinv32;
     // transfer to the next-coarser level (this level = fine side)
     DevBuf prow0x, prowx, pcol0x, pcolx, prow0y, prowy, pcol0y, pcoly;
+    DevBuf prow0z, prowz, pcol0z, pcolz;
     Transfer tr{};
     // multigrid work vectors
     DevBuf b64, x64, r64, t64, vr64, vx64;
@@ -104,6 +105,7 @@ struct SolverImpl {
     // constant k: E^-1 at level Lz by fast diagonalisation (1D eigenvectors and 1 / D)
     bool fdm = false;
     DevBuf fdmVx, fdmVxT, fdmVy, fdmDinv, fdmT1, fdmT2;
+    DevBuf fdmVyT, fdmVz, fdmVzT;   // unit cube: the y and z factors of the same form
     // levels >= tail_start (all small) run their V-cycle in one workgroup
     int tail_start = 1 << 30;
     int tail_lds = 0, tail_lds32 = 0;   // dynamic LDS bytes (FP64 / FP32 tail)
@@ -143,6 +145,8 @@ struct SolverImpl {
     ~SolverImpl();
 
     void setup(hipStream_t s);
+    void setup_levels_3d(hipStream_t s);   // unit cube: levels, transfers, coarsest inverse, E^-1
+    void setup_finish(hipStream_t s);      // deflation, Krylov and host-side state (every dimension)
     void autotune_ops(hipStream_t s);
     // building blocks
     template <class T>

@@ -30,11 +30,14 @@ using zd = std::complex<double>;
 // ---------------------------------------------------------------- problem --
 ProblemImpl* build_problem(const hh_problem_desc* d) {
     HH_REQUIRE(d != nullptr, "null problem descriptor");
-    HH_REQUIRE(d->dim == 1 || d->dim == 2, "dim must be 1 or 2");
+    HH_REQUIRE(d->dim >= 1 && d->dim <= 3, "dim must be 1, 2 or 3");
     HH_REQUIRE(d->p >= 1 && d->p <= 5, "p must be in 1..5");
-    const int nx = d->n_el[0], ny = d->dim == 2 ? d->n_el[1] : 1;
-    HH_REQUIRE(nx >= 2 && (d->dim == 1 || ny >= 2), "at least 2 elements per direction");
-    HH_REQUIRE(nx <= (1 << 20) && ny <= (1 << 20), "too many elements");
+    const int nx = d->n_el[0], ny = d->dim >= 2 ? d->n_el[1] : 1, nz = d->dim == 3 ? d->n_el_z : 1;
+    HH_REQUIRE(nx >= 2 && (d->dim == 1 || ny >= 2) && (d->dim < 3 || nz >= 2), "at least 2 elements per direction");
+    HH_REQUIRE(nx <= (1 << 20) && ny <= (1 << 20) && nz <= (1 << 20), "too many elements");
+    HH_REQUIRE(d->dim < 3 || d->k_mode == 0, "3D problems are built for constant k");
+    HH_REQUIRE(d->dim < 3 || (long long)(nx + d->p) * (ny + d->p) * (nz + d->p) < (1LL << 31),
+               "3D problem too large (at most 2^31 unknowns)");
     HH_REQUIRE(d->k_mode == 0 || d->k_mode == 1, "k_mode must be 0 or 1");
     HH_REQUIRE(d->bc_right == 0 || d->bc_right == 1, "bc_right must be 0 (Dirichlet) or 1 (radiation condition)");
     HH_REQUIRE(d->bc_right == 0 || (d->dim == 1 && d->k_mode == 0),
@@ -45,6 +48,7 @@ ProblemImpl* build_problem(const hh_problem_desc* d) {
     P->p = d->p;
     P->nel[0] = nx;
     P->nel[1] = ny;
+    P->nel[2] = nz;
     P->k_mode = d->k_mode;
     P->k = d->k;
     if (d->k_mode == 0) {
@@ -68,7 +72,8 @@ ProblemImpl* build_problem(const hh_problem_desc* d) {
         }
     }
     P->ax0 = make_axis(P->p, nx, 0, P->somm);
-    P->ay0 = d->dim == 2 ? make_axis(P->p, ny, 0) : make_trivial_axis();
+    P->ay0 = d->dim >= 2 ? make_axis(P->p, ny, 0) : make_trivial_axis();
+    P->az0 = d->dim == 3 ? make_axis(P->p, nz, 0) : make_trivial_axis();
     return P;
 }
 
@@ -229,6 +234,11 @@ void SolverImpl::setup(hipStream_t s) {
     HH_REQUIRE(o.defl_direct_max >= 1 && o.defl_direct_max <= 65536, "defl_direct_max must be in 1..65536");
     for (int i = 0; i < 8; ++i) HH_REQUIRE(o.defl_inner_its[i] >= 1 && o.defl_inner_its[i] <= 64, "defl_inner_its in 1..64");
 
+    if (P.dim == 3) {
+        setup_levels_3d(s);
+        setup_finish(s);
+        return;
+    }
     const int p = P.p;
     const bool is2d = P.dim == 2;
     // multigrid levels by knot halving
@@ -841,6 +851,186 @@ void SolverImpl::setup(hipStream_t s) {
             sym = true;
         }
     }
+    setup_finish(s);
+}
+
+// Unit cube (constant k, Dirichlet): the multigrid levels by knot halving in
+// all three directions, their transfers P_z (x) P_y (x) P_x, Jacobi diagonals
+// and damping, the dense inverse of the coarsest M_beta, and the two-level
+// deflation matrix E = A_1 by fast diagonalisation (the three 1D pencils).
+void SolverImpl::setup_levels_3d(hipStream_t s) {
+    const ProblemImpl& P = *prob;
+    HH_REQUIRE(P.k_mode == 0, "3D problems are built for constant k");
+    HH_REQUIRE(o.defl_mode == 0 || o.defl_mode == 1, "3D problems take defl_mode 0 or 1 (two-level deflation)");
+    HH_REQUIRE(o.precond == 0 && o.defl_z == 0,
+               "3D problems are built with the knot-insertion deflation and the multigrid CSLP");
+    const int p = P.p;
+    for (int l = 0;; ++l) {
+        auto lv = std::make_unique<LevelDev>();
+        lv->ax = l == 0 ? P.ax0 : make_axis(p, P.nel[0], l);
+        lv->ay = l == 0 ? P.ay0 : make_axis(p, P.nel[1], l);
+        lv->az = l == 0 ? P.az0 : make_axis(p, P.nel[2], l);
+        HH_REQUIRE(lv->ax.n >= 1 && lv->ay.n >= 1 && lv->az.n >= 1, "level without interior unknowns");
+        const int mx = std::max({lv->ax.nel, lv->ay.nel, lv->az.nel});
+        lev.push_back(std::move(lv));
+        if (mx <= o.mg_min_elems) break;
+    }
+    L = (int)lev.size() - 1;
+    for (int l = 0; l < L; ++l) {
+        make_transfer(lev[l]->ax, lev[l + 1]->ax);
+        make_transfer(lev[l]->ay, lev[l + 1]->ay);
+        make_transfer(lev[l]->az, lev[l + 1]->az);
+    }
+    const double k2c = P.k * P.k;
+    const zd beta(o.beta[0], o.beta[1]);
+    for (int l = 0; l <= L; ++l) {
+        LevelDev& lv = *lev[l];
+        lv.n1 = lv.ax.n;
+        lv.n2 = lv.ay.n;
+        lv.n3 = lv.az.n;
+        lv.N = (long long)lv.n1 * lv.n2 * lv.n3;
+        lv.kind = KIND_SEP;
+        upload(lv.Kx, lv.ax.Kb);
+        upload(lv.Mx, lv.ax.Mb);
+        upload(lv.Ky, lv.ay.Kb);
+        upload(lv.My, lv.ay.Mb);
+        upload(lv.Kz, lv.az.Kb);
+        upload(lv.Mz, lv.az.Mb);
+        std::vector<cx<double>> dinv((size_t)lv.N);
+        std::vector<cx<float>> dinv32((size_t)lv.N);
+        double g = 0.0;
+        for (long long I = 0; I < lv.N; ++I) {
+            zd diag = 0.0;
+            double rowsum = 0.0;
+            visit_row3(lv.ax, lv.ay, lv.az, k2c, I, [&](long long J, double kv, double mv) {
+                const zd e = kv - beta * mv;
+                rowsum += std::abs(e);
+                if (J == I) diag = e;
+            });
+            HH_REQUIRE(std::abs(diag) > 0.0, "zero Jacobi diagonal");
+            g = std::max(g, rowsum / std::abs(diag));
+            const zd di = 1.0 / diag;
+            dinv[I] = {di.real(), di.imag()};
+            dinv32[I] = {(float)di.real(), (float)di.imag()};
+        }
+        lv.gersh = g;
+        // the Gershgorin-bounded damping on every level, the finest included: the
+        // three-fold product of 1D masses puts D^-1 M_beta of the finest level
+        // beyond 2 / omega already
+        lv.omega = o.coarse_damping == 0 ? o.omega : std::min(o.omega, 2.0 / g);
+        upload(lv.Dinv64, dinv);
+        upload(lv.Dinv32, dinv32);
+        const size_t v64 = (size_t)lv.N * 16, v32 = (size_t)lv.N * 8;
+        for (DevBuf* b : {&lv.b64, &lv.x64, &lv.r64, &lv.t64}) b->alloc(v64);
+        for (DevBuf* b : {&lv.b32, &lv.x32, &lv.r32, &lv.t32}) b->alloc(v32);
+        if (o.n_vcycles > 1) {
+            lv.vr64.alloc(v64);
+            lv.vx64.alloc(v64);
+            lv.vr32.alloc(v32);
+            lv.vx32.alloc(v32);
+        }
+    }
+    for (int l = 0; l < L; ++l) {
+        LevelDev& lv = *lev[l];
+        const LevelDev& lc = *lev[l + 1];
+        upload(lv.prow0x, lv.ax.prow0);
+        upload(lv.prowx, lv.ax.prow);
+        upload(lv.pcol0x, lv.ax.pcol0);
+        upload(lv.pcolx, lv.ax.pcol);
+        upload(lv.prow0y, lv.ay.prow0);
+        upload(lv.prowy, lv.ay.prow);
+        upload(lv.pcol0y, lv.ay.pcol0);
+        upload(lv.pcoly, lv.ay.pcol);
+        upload(lv.prow0z, lv.az.prow0);
+        upload(lv.prowz, lv.az.prow);
+        upload(lv.pcol0z, lv.az.pcol0);
+        upload(lv.pcolz, lv.az.pcol);
+        Transfer& t = lv.tr;
+        t.nf1 = lv.n1;
+        t.nf2 = lv.n2;
+        t.nf3 = lv.n3;
+        t.nc1 = lc.n1;
+        t.nc2 = lc.n2;
+        t.nc3 = lc.n3;
+        t.pw1 = lv.ax.pw;
+        t.pw2 = lv.ay.pw;
+        t.pw3 = lv.az.pw;
+        t.rw1 = lv.ax.rw;
+        t.rw2 = lv.ay.rw;
+        t.rw3 = lv.az.rw;
+        t.prow0x = lv.prow0x.as<int>();
+        t.prowx = lv.prowx.as<double>();
+        t.prow0y = lv.prow0y.as<int>();
+        t.prowy = lv.prowy.as<double>();
+        t.prow0z = lv.prow0z.as<int>();
+        t.prowz = lv.prowz.as<double>();
+        t.pcol0x = lv.pcol0x.as<int>();
+        t.pcolx = lv.pcolx.as<double>();
+        t.pcol0y = lv.pcol0y.as<int>();
+        t.pcoly = lv.pcoly.as<double>();
+        t.pcol0z = lv.pcol0z.as<int>();
+        t.pcolz = lv.pcolz.as<double>();
+    }
+    {
+        LevelDev& lc = *lev[L];
+        nL = (int)lc.N;
+        HH_REQUIRE(nL <= 4096, "coarsest multigrid level too large (raise the coarsening: mg_min_elems)");
+        std::vector<zd> A((size_t)nL * nL, 0.0);
+        for (long long I = 0; I < lc.N; ++I)
+            visit_row3(lc.ax, lc.ay, lc.az, k2c, I,
+                       [&](long long J, double kv, double mv) { A[(size_t)I * nL + J] += kv - beta * mv; });
+        invert_complex(nL, A);
+        std::vector<cx<double>> m64((size_t)nL * nL);
+        std::vector<cx<float>> m32((size_t)nL * nL);
+        for (size_t i = 0; i < A.size(); ++i) {
+            m64[i] = {A[i].real(), A[i].imag()};
+            m32[i] = {(float)A[i].real(), (float)A[i].imag()};
+        }
+        upload(Minv64, m64);
+        upload(Minv32, m32);
+    }
+    Lz = (o.defl_mode == 1 && L >= 1) ? 1 : 0;
+    if (Lz > 0) {
+        const LevelDev& lz = *lev[Lz];
+        nZ = (int)lz.N;
+        std::vector<double> V[3], lam[3];
+        axis_eigen(lz.ax, V[0], lam[0]);
+        axis_eigen(lz.ay, V[1], lam[1]);
+        axis_eigen(lz.az, V[2], lam[2]);
+        double scale = k2c;
+        for (auto& l : lam)
+            for (double v : l) scale = std::max(scale, std::fabs(v));
+        std::vector<double> dinv((size_t)nZ);
+        for (int c = 0; c < lz.n3; ++c)
+            for (int a = 0; a < lz.n2; ++a)
+                for (int b = 0; b < lz.n1; ++b) {
+                    const double d = lam[2][c] + lam[1][a] + lam[0][b] - k2c;
+                    if (!(std::fabs(d) > 1e-14 * scale)) throw Err{HH_ENUMERIC, "deflation matrix E is singular"};
+                    dinv[((size_t)c * lz.n2 + a) * lz.n1 + b] = 1.0 / d;
+                }
+        auto transpose = [](const std::vector<double>& M, int n) {
+            std::vector<double> T(M.size());
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) T[(size_t)b * n + a] = M[(size_t)a * n + b];
+            return T;
+        };
+        upload(fdmVx, V[0]);
+        upload(fdmVxT, transpose(V[0], lz.n1));
+        upload(fdmVy, V[1]);
+        upload(fdmVyT, transpose(V[1], lz.n2));
+        upload(fdmVz, V[2]);
+        upload(fdmVzT, transpose(V[2], lz.n3));
+        upload(fdmDinv, dinv);
+        fdmT1.alloc((size_t)nZ * 16);
+        fdmT2.alloc((size_t)nZ * 16);
+        fdm = true;
+    }
+}
+
+void SolverImpl::setup_finish(hipStream_t s) {
+    const ProblemImpl& P = *prob;
+    const bool const_k = P.k_mode == 0;
+    const double k2c = const_k ? P.k * P.k : 0.0;
     if (Lz > 0) {
         for (int l = 0; l < defl_end(); ++l) {
             LevelDev& lv = *lev[l];
@@ -864,7 +1054,7 @@ void SolverImpl::setup(hipStream_t s) {
     }
     // feature of the learned smoother: c = k^2 h^2 of the finest element with the
     // unknown's (clamped) index
-    {
+    if (P.dim <= 2) {   // the learned smoother's feature (2D and 1D)
         const LevelDev& l0 = *lev[0];
         std::vector<float> c((size_t)l0.N);
         const double h2 = 1.0 / ((double)P.nel[0] * P.nel[0]);
@@ -877,7 +1067,7 @@ void SolverImpl::setup(hipStream_t s) {
         upload(feat, c);
     }
     {
-        const int nmax = std::max(lev[0]->n1, lev[0]->n2);
+        const int nmax = std::max({lev[0]->n1, lev[0]->n2, lev[0]->n3});
         zero_bands.alloc((size_t)nmax * (2 * std::max(P.p, lev[Lz]->ax.p) + 1) * sizeof(double));
         HH_HIP(hipMemsetAsync(zero_bands.p, 0, zero_bands.bytes, s));
     }
@@ -1016,8 +1206,13 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
     const bool with_bnd = !mass_only && (are != 0.0 || aim != 0.0);
     a.bnd_I = with_bnd ? lv.bnd_I : -1;
     a.bnd_im = (T)lv.bnd_im;
+    if (prob->dim == 3) {
+        a.n3 = lv.n3;
+        a.Kz = mass_only ? zero_bands.as<double>() : lv.Kz.as<double>();
+        a.Mz = lv.Mz.as<double>();
+    }
     // band half-widths of the level (the degree p, or wider on the ADP level)
-    const int px = lv.ax.p, py = prob->dim == 2 ? lv.ay.p : 0;
+    const int px = lv.ax.p, py = prob->dim >= 2 ? lv.ay.p : 0;
     double st_bytes = 0.0;
     {
         // operands once: x, y, b (residual / sweep), D^-1 (sweep), the first-sweep
@@ -1028,6 +1223,7 @@ void SolverImpl::op_alpha(int l, int mode, double are, double aim, const cx<T>* 
         double bytes = 2 * v + (mode != MODE_APPLY ? v : 0.0) + (mode == MODE_SMOOTH || xo ? v : 0.0) +
                        (xo ? v : 0.0) + (a.yadd ? v : 0.0);
         double macs = 2.0 * bx * by + 2.0 * by;
+        if (prob->dim == 3) macs = 7.0 * bx;   // sum factorised: x, y and z passes
         if (lv.kind == KIND_STENCIL) {
             bytes += (double)lv.N * bx * by * sizeof(T);
             macs += bx * by;
@@ -1299,6 +1495,13 @@ void SolverImpl::coarse_solve(int l, const cx<double>* c, cx<double>* e, hipStre
         if (EinvC.p) {
             launch_gemv<cx<double>, double>(nZ, EinvC.as<cx<double>>(), c, e, s);
             tstop(2, 16.0 * nZ * (double)nZ + 32.0 * nZ, s);
+        } else if (fdm && prob->dim == 3) {
+            const LevelDev& lz = *lev[Lz];
+            launch_fdm3_solve(lz.n3, lz.n2, lz.n1, fdmVx.as<double>(), fdmVxT.as<double>(), fdmVy.as<double>(),
+                              fdmVyT.as<double>(), fdmVz.as<double>(), fdmVzT.as<double>(), fdmDinv.as<double>(), c,
+                              fdmT1.as<cx<double>>(), fdmT2.as<cx<double>>(), e, s);
+            // c, e, 1/D and the six eigenvector matrices once
+            tstop(2, 40.0 * nZ + 16.0 * ((double)lz.n1 * lz.n1 + (double)lz.n2 * lz.n2 + (double)lz.n3 * lz.n3), s);
         } else if (fdm) {
             const LevelDev& lz = *lev[Lz];
             launch_fdm_solve(lz.n2, lz.n1, fdmVx.as<double>(), fdmVxT.as<double>(), fdmVy.as<double>(),

@@ -36,7 +36,9 @@ def test_default_opts():
     assert o.precision == 0 and o.time_kernels == 0 and o.autotune == 1 and o.ortho == 0
 
 
-@pytest.mark.parametrize("kw", [dict(dim=3, p=2, n_el=8, k=1.0), dict(dim=2, p=0, n_el=8, k=1.0),
+@pytest.mark.parametrize("kw", [dict(dim=4, p=2, n_el=8, k=1.0), dict(dim=2, p=0, n_el=8, k=1.0),
+                                dict(dim=3, p=2, n_el=(8, 8, 1), k=1.0),
+                                dict(dim=3, p=2, n_el=4, k_elem=np.ones((4, 4, 4))),
                                 dict(dim=2, p=6, n_el=8, k=1.0), dict(dim=2, p=2, n_el=1, k=1.0),
                                 dict(dim=2, p=2, n_el=8, k=-1.0), dict(dim=2, p=2, n_el=8, k=float("nan"))])
 def test_assemble_rejects_invalid(kw):
@@ -52,13 +54,23 @@ def test_assemble_rejects_bad_k_field():
         B.Problem(2, 2, 4, k_elem=k)
 
 
-@pytest.mark.parametrize("dim,p,n", [(1, 2, 80), (2, 3, 160), (2, 4, 7), (2, 1, 5)])
+@pytest.mark.parametrize("dim,p,n", [(1, 2, 80), (2, 3, 160), (2, 4, 7), (2, 1, 5), (3, 2, 9), (3, 5, 4)])
 def test_problem_sizes(dim, p, n):
     pr = B.Problem(dim, p, n, k=10.0)
     if dim == 1:
         assert pr.n == (n + p - 2, 1)
-    else:
+    elif dim == 2:
         assert pr.n == (n + p - 2, n + p - 2)
+    else:
+        assert pr.n == (n + p - 2,) * 3 and pr.N == (n + p - 2) ** 3
+        with pytest.raises(B.HHError):      # two sizes cannot describe the cube
+            B._check(B.load().hh_problem_size(pr._h, (ctypes.c_int * 2)()))
+
+
+def test_problem_sizes_3d_anisotropic():
+    pr = B.Problem(3, 3, (5, 7, 6), k=4.0)
+    assert pr.n == (6, 8, 7) and pr.N == 6 * 8 * 7
+    assert pr.spans((0.23, 0.61, 0.82)) == [1, 4, 4]
 
 
 @pytest.mark.parametrize("x0", [(0.5, 0.95), (0.0, 1.0), (1.0, 0.5), (0.3, 0.7), (0.999999, 1e-9),
@@ -84,10 +96,13 @@ _CSR_CASES = [
     dict(dim=2, p=3, n_el=12, k=9.0),
     dict(dim=2, p=2, n_el=9, rand=True),
     dict(dim=2, p=4, n_el=11, rand=True),
+    dict(dim=3, p=1, n_el=(4, 3, 5), k=2.0),
+    dict(dim=3, p=2, n_el=(3, 4, 2), k=5.0),
+    dict(dim=3, p=3, n_el=(4, 3, 3), k=3.0),
 ]
 
 
-@pytest.mark.parametrize("c", _CSR_CASES, ids=lambda c: f"d{c['dim']}p{c['p']}n{c['n_el']}{'rand' if c.get('rand') else ''}")
+@pytest.mark.parametrize("c", _CSR_CASES, ids=lambda c: f"d{c['dim']}p{c['p']}n{'x'.join(map(str, np.atleast_1d(c['n_el'])))}{'rand' if c.get('rand') else ''}")
 def test_export_csr_matches_oracle(c):
     """Finest-level K, M_k and A exported by the library (host) against the
     oracle's scipy assembly: identical sparsity (row pointers and column
