@@ -83,6 +83,14 @@ WORKLOADS = {
     "mp1a_k1000_p3_1600": dict(dim=1, p=3, n_el=1600, k=1000.0, sommerfeld=True, opts=dict(defl_direct_max=512)),
     # MP 1-B: 1D, k = 50, p = 2, 80 elements, two-level deflation
     "mp1b_k50_p2_80": dict(dim=1, p=2, n_el=80, k=50.0, x0=(0.5,), opts=dict(defl_mode=1)),
+    # unit cube (3D tensor product), k = 62.5, p = 3, 100^3 elements (k h = 0.625, 1,030,301
+    # unknowns: the largest cube whose Arnoldi vectors fit the register-resident grid kernel),
+    # point source at the centre, two-level deflation (E^-1 on 132,651 unknowns by fast
+    # diagonalisation), multigrid down to 7 elements per side (512 unknowns solved densely).
+    # The CPU oracle cannot assemble this size in minutes: its baseline runs the same problem
+    # family on 32^3 elements (k = 20, the same k h)
+    "cube_k62_p3_100": dict(dim=3, p=3, n_el=100, k=62.5, x0=(0.5, 0.5, 0.5),
+                            opts=dict(defl_mode=1, mg_min_elems=7), cpu_sample_n_el=32),
     # 64 independent constant-k problems, k ~ U[50, 400], n_el = ceil(k / 0.625),
     # p ~ U{2, 3, 4}, random interior sources; FP32 V-cycle, FP64 Krylov and deflation
     "batch64_k50_400": dict(batch=64, seed=0, opts=dict(precision=1, maxit=400)),
@@ -130,9 +138,12 @@ def cpu_baseline(w, seconds_cap=20.0):
 
     from oracle import helmholtz as hz
     from oracle import solver as osv
+    n_el, k = w["n_el"], w.get("k", 1.0)
+    if w.get("cpu_sample_n_el"):   # a smaller mesh of the same family, k h kept
+        n_el, k = w["cpu_sample_n_el"], k * w["cpu_sample_n_el"] / w["n_el"]
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        op = hz.Problem(w["dim"], w["p"], w["n_el"], w.get("k", 1.0), k_elem=k_field(w),
+        op = hz.Problem(w["dim"], w["p"], n_el, k, k_elem=k_field(w),
                         sommerfeld=w.get("sommerfeld", False))
         f = hz.dirichlet_lift_rhs(op) if op.sommerfeld else hz.point_source_rhs(op, w["x0"])
         # implementation options of the library (not the method's) are not the oracle's
@@ -157,6 +168,8 @@ def cpu_baseline(w, seconds_cap=20.0):
     N = s.levels[0].N
     what = (f"{info.iters} outer FGMRES iteration(s) of the same solve from zero" if reps == 1 else
             f"{reps} whole solves of {info.iters} outer FGMRES iterations each")
+    if w.get("cpu_sample_n_el"):
+        what += f" on {n_el} elements per side with k = {k:g} (the same k h; N = {N})"
     return {"value": N * iters / spent, "unit": "DoF-iter/s", "cores": 1, "kind": "oracle",
             "sample": f"{what} ({spent:.1f} s; oracle set-up of {t_setup:.0f} s excluded)",
             "iters": info.iters}
@@ -252,7 +265,10 @@ def roofline(solver, f, u, N):
     bpl = inf["op_bytes_per_launch"]
     achieved = bpl * n / (ms * 1e-3) / 1e9 if ms > 0 else None
     tr = profiling.read_summary(os.path.join(ROOT, "profiles", f"{TRAFFIC_PREFIX[dom]}_{ARGS.workload}_traffic.md"))
-    return {"bound": "hbm", "kernel": CLASS_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    name = CLASS_NAMES[dom]
+    if dom == 1 and solver.problem.dim == 3:
+        name = "finest-level operator (op3d_kernel, slice-marching)"
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": tr[0] if tr else None,
             "launches_per_solve": n, "avg_us": ms * 1e3 / n if n else None, "bytes_per_launch": bpl,
             "class_ms_per_solve": {CLASS_NAMES[c]: round(per[c]["op_ms_total"], 4) for c in CLASS_NAMES}}
@@ -419,7 +435,7 @@ def main():
         del mixed
         log(f"[bench] mixed: {forms['mixed']['iters_per_solve']} iterations, {forms['mixed']['ms_per_solve']:.2f} ms")
         # the learned smoother's training problems carry point sources on Dirichlet problems
-        if not args.no_learned and not w.get("sommerfeld"):
+        if not args.no_learned and not w.get("sommerfeld") and w["dim"] <= 2:
             try:
                 forms["mixed_learned"] = run_learned(args, w, prob, f, sec)
                 log(f"[bench] mixed + learned: {forms['mixed_learned']['iters_per_solve']} iterations, "

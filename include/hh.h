@@ -107,7 +107,10 @@ typedef struct {
                                 kernel from 2048 unknowns on, below it the one-thread-per-
                                 unknown kernel) with strip heights
                                 4..64 rows and keep the fastest; 0: a fixed rule (the
-                                tallest strip that still gives 2048 waves).  Results do
+                                tallest strip that still gives 2048 waves).  3D: the output
+                                slices per workgroup of the slice-marching operator (2..32;
+                                fixed rule: the longest of 16..2 that gives 1024
+                                workgroups) on every level above the coarsest.  Results do
                                 not depend on it. */
     int ortho;               /* Arnoldi orthogonalisation, modified Gram-Schmidt in both forms:
                                 0 (default): where the restart length is at most 50 and

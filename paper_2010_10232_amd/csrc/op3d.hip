@@ -10,11 +10,12 @@
 // M2 (the 2D mass), combined through the z bands:
 //   y_{i3} = sum_{J3} mz[i3][J3 - i3] B2(x_{J3}) + kz[i3][J3 - i3] M2(x_{J3}).
 // A workgroup of 256 threads owns a 32 (x) by 8 (y) column tile and a run of
-// tz output slices.  It walks the tz + 2p input slices once: each slice tile
-// plus its p-wide halo is staged in LDS (the next slice is already in flight
-// in registers), the x bands are applied once per staged row (sum
-// factorisation: Kx x and Mx x per row into LDS), then every thread forms B2
-// and M2 of its column through the y bands and adds them into a window of
+// tz output slices.  It walks the tz + 2p input slices once, as a three-stage
+// pipeline over double-buffered LDS with one barrier per step: slice t (tile
+// plus its p-wide halo) is staged from registers (slice t + 1 is already in
+// flight), slice t - 1 gets its x bands once per staged row (sum
+// factorisation: Kx x and Mx x per row), and for slice t - 2 every thread forms
+// B2 and M2 of its column through the y bands and adds them into a window of
 // 2p + 1 running output slices held in registers (mz, kz as weights).  After
 // input slice J3, output slice J3 - p is complete and is written with the
 // residual / Jacobi epilogue of the 2D kernels.  Per unknown and slice this is
@@ -30,14 +31,18 @@ namespace hh {
 namespace {
 
 constexpr int O3_TX = 32, O3_TY = 8, O3_TB = O3_TX * O3_TY;
+constexpr int O3_TZMAX = 32;   // output slices per workgroup, at most
 
 template <int P, int MODE, class T>
 __global__ __launch_bounds__(O3_TB) void op3d_kernel(OpArgs<T> a, int tz) {
     constexpr int B = 2 * P + 1;
     constexpr int LW = O3_TX + 2 * P, LH = O3_TY + 2 * P;
     constexpr int NL = (LH * LW + O3_TB - 1) / O3_TB;   // staged values per thread
-    __shared__ cx<T> xs[LH][LW];
-    __shared__ cx<T> us[2][LH][O3_TX];                   // Kx x, Mx x of every staged row
+    // double buffers: slice t is staged while slice t - 1 gets its x bands and
+    // slice t - 2 its y and z bands, one barrier per step
+    __shared__ cx<T> xs[2][LH][LW];
+    __shared__ cx<T> us[2][2][LH][O3_TX];                // [buffer][Kx x, Mx x][row][column]
+    __shared__ T mzS[O3_TZMAX][B], kzS[O3_TZMAX][B];     // z bands of the workgroup's output slices
 
     const int n1 = a.n1, n2 = a.n2, n3 = a.n3;
     const int tiles_x = (n1 + O3_TX - 1) / O3_TX, tiles_y = (n2 + O3_TY - 1) / O3_TY;
@@ -56,23 +61,31 @@ __global__ __launch_bounds__(O3_TB) void op3d_kernel(OpArgs<T> a, int tz) {
         ky[d] = (T)a.Ky[(size_t)I2c * B + d];
         my[d] = (T)a.My[(size_t)I2c * B + d];
     }
+    // the next slice in flight: every value is loaded from a valid address (its own
+    // or element 0) and masked when it is staged, so no wait sits between the
+    // loads and the work of the current step
     cx<T> pre[NL];
+    bool pok[NL];
     auto fetch = [&](int J3) {
         const bool zok = J3 >= 0 && J3 < n3;
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             const int e = tid + O3_TB * q;
-            cx<T> v = {T(0), T(0)};
-            if (zok && e < LH * LW) {
-                const int rr = e / LW, cc = e - rr * LW;
-                const int J2 = R0 - P + rr, J1 = C0 - P + cc;
-                if (J2 >= 0 && J2 < n2 && J1 >= 0 && J1 < n1) v = a.x[((size_t)J3 * n2 + J2) * n1 + J1];
-            }
-            pre[q] = v;
+            const int rr = e / LW, cc = e - rr * LW;
+            const int J2 = R0 - P + rr, J1 = C0 - P + cc;
+            const bool ok = zok && e < LH * LW && J2 >= 0 && J2 < n2 && J1 >= 0 && J1 < n1;
+            pre[q] = a.x[ok ? ((size_t)J3 * n2 + J2) * n1 + J1 : 0];
+            pok[q] = ok;
         }
     };
     const int zend = Z0 + tz < n3 ? Z0 + tz : n3;
     const int s0 = Z0 - P, s1 = zend - 1 + P;
+    // (visible after the first barrier of the slice loop)
+    for (int e = tid; e < (zend - Z0) * B; e += O3_TB) {
+        const int q = e / B, d = e - q * B;
+        mzS[q][d] = (T)a.Mz[(size_t)(Z0 + q) * B + d];
+        kzS[q][d] = (T)a.Kz[(size_t)(Z0 + q) * B + d];
+    }
     T wr[B], wi[B];
 #pragma unroll
     for (int k = 0; k < B; ++k) wr[k] = wi[k] = T(0);
@@ -82,94 +95,107 @@ __global__ __launch_bounds__(O3_TB) void op3d_kernel(OpArgs<T> a, int tz) {
 
     fetch(s0);
 #pragma unroll 1
-    for (int J3 = s0; J3 <= s1; ++J3) {
+    for (int t = s0; t <= s1 + 2; ++t) {
+        if (t <= s1) {
+            // stage slice t (tile + halo), then put slice t + 1 in flight
+            const int bf = t & 1;
 #pragma unroll
-        for (int q = 0; q < NL; ++q) {
-            const int e = tid + O3_TB * q;
-            if (e < LH * LW) xs[e / LW][e % LW] = pre[q];
-        }
-        __syncthreads();
-        if (J3 < s1) fetch(J3 + 1);
-        // x bands once per staged row (every item of this thread has column c)
-        for (int e = tid; e < LH * O3_TX; e += O3_TB) {
-            const int rr = e / O3_TX;
-            T u1r = 0, u1i = 0, u2r = 0, u2i = 0;
-#pragma unroll
-            for (int d = 0; d < B; ++d) {
-                const cx<T> v = xs[rr][c + d];
-                u1r += kx[d] * v.re;
-                u1i += kx[d] * v.im;
-                u2r += mx[d] * v.re;
-                u2i += mx[d] * v.im;
+            for (int q = 0; q < NL; ++q) {
+                const int e = tid + O3_TB * q;
+                if (e < LH * LW) xs[bf][e / LW][e % LW] = pok[q] ? pre[q] : cx<T>{T(0), T(0)};
             }
-            us[0][rr][c] = {u1r, u1i};
-            us[1][rr][c] = {u2r, u2i};
+            if (t < s1) fetch(t + 1);
         }
-        __syncthreads();
-        if (J3 >= 0 && J3 < n3) {
-            // B2 and M2 of this column through the y bands
-            T br = 0, bi = 0, mr = 0, mi = 0;
+        if (t - 1 >= s0 && t - 1 <= s1) {
+            // x bands of slice t - 1, once per staged row (every item of this thread has column c)
+            const int bf = (t - 1) & 1;
+            for (int e = tid; e < LH * O3_TX; e += O3_TB) {
+                const int rr = e / O3_TX;
+                T u1r = 0, u1i = 0, u2r = 0, u2i = 0;
 #pragma unroll
-            for (int d2 = 0; d2 < B; ++d2) {
-                const cx<T> u1 = us[0][r + d2][c], u2 = us[1][r + d2][c];
-                const T cr = u1.re - k2c * (are * u2.re - aim * u2.im);
-                const T ci = u1.im - k2c * (are * u2.im + aim * u2.re);
-                br += my[d2] * cr + ky[d2] * u2.re;
-                bi += my[d2] * ci + ky[d2] * u2.im;
-                mr += my[d2] * u2.re;
-                mi += my[d2] * u2.im;
-            }
-            // window entry k is output slice J3 - p + k, coupled at offset J3 - i3 = p - k
-#pragma unroll
-            for (int k = 0; k < B; ++k) {
-                int i3 = J3 - P + k;
-                i3 = i3 < 0 ? 0 : (i3 >= n3 ? n3 - 1 : i3);
-                const T mz = (T)a.Mz[(size_t)i3 * B + 2 * P - k], kz = (T)a.Kz[(size_t)i3 * B + 2 * P - k];
-                wr[k] += mz * br + kz * mr;
-                wi[k] += mz * bi + kz * mi;
+                for (int d = 0; d < B; ++d) {
+                    const cx<T> v = xs[bf][rr][c + d];
+                    u1r += kx[d] * v.re;
+                    u1i += kx[d] * v.im;
+                    u2r += mx[d] * v.re;
+                    u2i += mx[d] * v.im;
+                }
+                us[bf][0][rr][c] = {u1r, u1i};
+                us[bf][1][rr][c] = {u2r, u2i};
             }
         }
-        // output slice J3 - p has all its input slices
-        const int i3 = J3 - P;
-        if (active && i3 >= Z0 && i3 < zend) {
-            const size_t I = ((size_t)i3 * n2 + I2) * n1 + I1;
-            const T yr = wr[0], yi = wi[0];
-            cx<T> out;
-            if (MODE == MODE_APPLY) {
-                out = {yr, yi};
-            } else {
-                const cx<T> bv = a.b[I];
-                const T rr = bv.re - yr, ri = bv.im - yi;
-                if (MODE == MODE_RESID) {
-                    out = {rr, ri};
-                    if (a.xo) {
-                        const cx<T> d = a.dinv[I];
-                        a.xo[I] = {a.omega * (d.re * rr - d.im * ri), a.omega * (d.re * ri + d.im * rr)};
-                    }
-                } else {
-                    const cx<T> dv = a.dinv[I], xv = a.x[I];
-                    out = {xv.re + a.omega * (dv.re * rr - dv.im * ri), xv.im + a.omega * (dv.re * ri + dv.im * rr)};
-                    if (a.yadd) {
-                        const cx<T> q = a.yadd[I];
-                        out = {out.re + q.re, out.im + q.im};
+        const int J3 = t - 2;
+        if (J3 >= s0) {
+            if (J3 >= 0 && J3 < n3) {
+                // B2 and M2 of this column through the y bands
+                const int bf = J3 & 1;
+                T br = 0, bi = 0, mr = 0, mi = 0;
+#pragma unroll
+                for (int d2 = 0; d2 < B; ++d2) {
+                    const cx<T> u1 = us[bf][0][r + d2][c], u2 = us[bf][1][r + d2][c];
+                    const T cr = u1.re - k2c * (are * u2.re - aim * u2.im);
+                    const T ci = u1.im - k2c * (are * u2.im + aim * u2.re);
+                    br += my[d2] * cr + ky[d2] * u2.re;
+                    bi += my[d2] * ci + ky[d2] * u2.im;
+                    mr += my[d2] * u2.re;
+                    mi += my[d2] * u2.im;
+                }
+                // window entry k is output slice J3 - p + k, coupled at offset J3 - i3 = p - k
+                // (slices outside this workgroup's outputs are never written: no weight)
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    const int q = J3 - P + k - Z0;
+                    if (q >= 0 && q < zend - Z0) {
+                        const T mz = mzS[q][2 * P - k], kz = kzS[q][2 * P - k];
+                        wr[k] += mz * br + kz * mr;
+                        wi[k] += mz * bi + kz * mi;
                     }
                 }
             }
-            a.y[I] = out;
-        }
+            // output slice J3 - p has all its input slices
+            const int i3 = J3 - P;
+            if (active && i3 >= Z0 && i3 < zend) {
+                const size_t I = ((size_t)i3 * n2 + I2) * n1 + I1;
+                const T yr = wr[0], yi = wi[0];
+                cx<T> out;
+                if (MODE == MODE_APPLY) {
+                    out = {yr, yi};
+                } else {
+                    const cx<T> bv = a.b[I];
+                    const T rr = bv.re - yr, ri = bv.im - yi;
+                    if (MODE == MODE_RESID) {
+                        out = {rr, ri};
+                        if (a.xo) {
+                            const cx<T> d = a.dinv[I];
+                            a.xo[I] = {a.omega * (d.re * rr - d.im * ri), a.omega * (d.re * ri + d.im * rr)};
+                        }
+                    } else {
+                        const cx<T> dv = a.dinv[I], xv = a.x[I];
+                        out = {xv.re + a.omega * (dv.re * rr - dv.im * ri),
+                               xv.im + a.omega * (dv.re * ri + dv.im * rr)};
+                        if (a.yadd) {
+                            const cx<T> q = a.yadd[I];
+                            out = {out.re + q.re, out.im + q.im};
+                        }
+                    }
+                }
+                a.y[I] = out;
+            }
 #pragma unroll
-        for (int k = 0; k + 1 < B; ++k) {
-            wr[k] = wr[k + 1];
-            wi[k] = wi[k + 1];
+            for (int k = 0; k + 1 < B; ++k) {
+                wr[k] = wr[k + 1];
+                wi[k] = wi[k + 1];
+            }
+            wr[B - 1] = wi[B - 1] = T(0);
         }
-        wr[B - 1] = wi[B - 1] = T(0);
+        __syncthreads();
     }
 }
 
-// Output slices per workgroup: a tuned value (a power of two in 2..64), else
+// Output slices per workgroup: a tuned value (a power of two in 2..32), else
 // the longest of 16, 8, 4, 2 that still gives 1024 workgroups (four per CU).
 inline int op3d_slices(int n1, int n2, int n3, int tuned) {
-    if (tuned >= 2 && tuned <= 64 && (tuned & (tuned - 1)) == 0) return tuned;
+    if (tuned >= 2 && tuned <= O3_TZMAX && (tuned & (tuned - 1)) == 0) return tuned;
     const long long tiles = (long long)((n1 + O3_TX - 1) / O3_TX) * ((n2 + O3_TY - 1) / O3_TY);
     int tz = 16;
     while (tz > 2 && tiles * ((n3 + tz - 1) / tz) < 1024) tz >>= 1;

@@ -1111,7 +1111,10 @@ void SolverImpl::setup_finish(hipStream_t s) {
 // keep the fastest.  Each output row sums its 2p+1 input rows in the same order
 // whatever the strip height, so the choice changes speed only.
 void SolverImpl::autotune_ops(hipStream_t s) {
-    if (prob->dim != 2) return;
+    if (prob->dim == 1) return;
+    // 2D: strip height of the row-marching kernel (64..4 rows); 3D: output slices
+    // per workgroup of the slice-marching kernel (32..2); either gives the same bits
+    const bool cube = prob->dim == 3;
     hipEvent_t e0, e1;
     HH_HIP(hipEventCreate(&e0));
     HH_HIP(hipEventCreate(&e1));
@@ -1126,7 +1129,7 @@ void SolverImpl::autotune_ops(hipStream_t s) {
         HH_HIP(hipMemsetAsync(b, 0, (size_t)lv.N * sizeof(cx<T>), s));
         float best = 1e30f;
         int best_ty = 0;
-        for (int ty = 64; ty >= 4; ty >>= 1) {
+        for (int ty = cube ? 32 : 64; ty >= (cube ? 2 : 4); ty >>= 1) {
             slot = ty;
             op<T>(l, MODE_RESID, true, x, b, y, s);
             float t_min = 1e30f;
@@ -1152,7 +1155,7 @@ void SolverImpl::autotune_ops(hipStream_t s) {
     for (int l = 0; l <= last; ++l) {
         // small constant-k levels use the direct kernel, stored stencils the
         // direct or the tiled kernel (no strips in either)
-        if (lev[l]->N <= kOpDirectMax && lev[l]->kind != KIND_VARFINE) continue;
+        if (!cube && lev[l]->N <= kOpDirectMax && lev[l]->kind != KIND_VARFINE) continue;
         if (lev[l]->kind == KIND_STENCIL) continue;
         tune(l, double{});
         tune(l, float{});

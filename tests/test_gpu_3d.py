@@ -225,3 +225,23 @@ def test_3d_graphs_and_rejections():
     for bad in (dict(defl_mode=2), dict(defl_mode=1, precond=1), dict(defl_mode=1, defl_z=1)):
         with pytest.raises(B.HHError):
             B.Solver(gp, **bad)
+
+
+def test_3d_autotuned_slices_do_not_change_results():
+    """The slices per workgroup (tuned or by rule) change the schedule, not the sums."""
+    import torch
+    from paper_2010_10232_amd import binding as B
+    c = CASES["3d_p2_aniso"]
+    gp = B.Problem(3, c["p"], c["n_el"], k=c["k"])
+    f = gp.point_source(c["x0"])
+    tuned = B.Solver(gp, autotune=1, **c["opts"])
+    fixed = B.Solver(gp, autotune=0, **c["opts"])
+    _say("[3d autotune] slices", [lv["op_rows"] for lv in tuned.levels])
+    x = to_dev(rvec(gp.N, 9))
+    for opname in ("A", "MBETA"):
+        assert torch.equal(tuned.apply(opname, 0, x), fixed.apply(opname, 0, x))
+    for prec in (0, 1):
+        t = B.Solver(gp, autotune=1, precision=prec, **c["opts"])
+        u = B.Solver(gp, autotune=0, precision=prec, **c["opts"])
+        (u1, i1), (u2, i2) = t.solve(f), u.solve(f)
+        assert i1["iters"] == i2["iters"] and torch.equal(u1, u2)
