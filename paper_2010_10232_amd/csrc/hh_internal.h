@@ -278,6 +278,12 @@ struct Transfer {
     const double* prowz;
     const int* pcol0z;
     const double* pcolz;
+    // unit cube: the two intermediate grids of the one-direction passes,
+    // nf3 x nf2 x nc1 and nf3 x nc2 x nc1 entries, per precision
+    cx<double>* tmpa64;
+    cx<double>* tmpb64;
+    cx<float>* tmpa32;
+    cx<float>* tmpb32;
 };
 
 // State of one FGMRES instance (device memory), m = max Arnoldi steps.

@@ -223,81 +223,48 @@ void launch_op3d_p(int mode, const OpArgs<T>& a, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- transfers --
-// c = P^T r and x (+)= P e with P = P_z (x) P_y (x) P_x, each factor stored as
-// per-row / per-column runs (as in the 2D transfers); one thread per output.
+// c = P^T r and x (+)= P e with P = P_z (x) P_y (x) P_x, each 1D factor stored
+// as per-row / per-column runs (as in the 2D transfers), applied one direction
+// at a time (sum factorisation: (p+2) + (p+2) + (p+2) terms per coarse unknown
+// instead of (p+2)^3, through two intermediate grids).  One pass:
+//   out[.., o, ..] = sum_{k < w} wt[o][k] in[.., i0[o] + k, ..]
+// along direction `axis` of an m1 x m2 x m3 input (x fastest), n_out entries
+// along that direction in the output.  The last pass of a restriction also
+// forms the coarse level's first damped Jacobi sweep (xs = omega D^-1 c); the
+// last pass of a prolongation adds xin.
 template <class T>
-__global__ void restrict3_kernel(Transfer t, const cx<T>* __restrict__ r, cx<T>* __restrict__ c,
-                                 const cx<T>* __restrict__ dinv, T omega, cx<T>* __restrict__ xs) {
-    const long long Nc = (long long)t.nc1 * t.nc2 * t.nc3;
+__global__ void axis_pass_kernel(int m1, int m2, int m3, int axis, int n_out, const int* __restrict__ i0,
+                                 const double* __restrict__ wt, int w, const cx<T>* __restrict__ in,
+                                 cx<T>* __restrict__ out, const cx<T>* __restrict__ dinv, T omega,
+                                 cx<T>* __restrict__ xs, const cx<T>* xin) {
+    const int o1 = axis == 0 ? n_out : m1, o2 = axis == 1 ? n_out : m2, o3 = axis == 2 ? n_out : m3;
+    const long long No = (long long)o1 * o2 * o3;
     const long long idx = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (idx >= Nc) return;
-    const int J1 = (int)(idx % t.nc1), J2 = (int)((idx / t.nc1) % t.nc2), J3 = (int)(idx / ((long long)t.nc1 * t.nc2));
-    const int i0x = t.pcol0x[J1], i0y = t.pcol0y[J2], i0z = t.pcol0z[J3];
+    if (idx >= No) return;
+    const int j1 = (int)(idx % o1), j2 = (int)((idx / o1) % o2), j3 = (int)(idx / ((long long)o1 * o2));
+    const int o = axis == 0 ? j1 : axis == 1 ? j2 : j3;
+    const long long stride = axis == 0 ? 1 : axis == 1 ? m1 : (long long)m1 * m2;
+    // the input entry with coordinate i0[o] along the axis and j elsewhere
+    const long long base = (axis == 0 ? 0 : (long long)j1) + (axis == 1 ? 0 : (long long)j2 * m1) +
+                           (axis == 2 ? 0 : (long long)j3 * m1 * m2) + (long long)i0[o] * stride;
+    const cx<T>* src = in + base;
+    const double* wr = wt + (size_t)o * w;
     T sr = 0, si = 0;
-    for (int a3 = 0; a3 < t.rw3; ++a3) {
-        const T wz = (T)t.pcolz[(size_t)J3 * t.rw3 + a3];
-        if (wz == T(0)) continue;
-        const cx<T>* plane = r + (size_t)(i0z + a3) * t.nf2 * t.nf1;
-        T pr = 0, pi = 0;
-        for (int a2 = 0; a2 < t.rw2; ++a2) {
-            const T wy = (T)t.pcoly[(size_t)J2 * t.rw2 + a2];
-            if (wy == T(0)) continue;
-            const cx<T>* row = plane + (size_t)(i0y + a2) * t.nf1 + i0x;
-            T rr = 0, ri = 0;
-            for (int a1 = 0; a1 < t.rw1; ++a1) {
-                const T wx = (T)t.pcolx[(size_t)J1 * t.rw1 + a1];
-                const cx<T> v = row[a1];
-                rr += wx * v.re;
-                ri += wx * v.im;
-            }
-            pr += wy * rr;
-            pi += wy * ri;
-        }
-        sr += wz * pr;
-        si += wz * pi;
+    for (int k = 0; k < w; ++k) {
+        const T g = (T)wr[k];
+        const cx<T> v = src[(size_t)k * stride];
+        sr += g * v.re;
+        si += g * v.im;
     }
-    c[idx] = {sr, si};
+    if (xin) {
+        const cx<T> q = xin[idx];
+        sr = q.re + sr;
+        si = q.im + si;
+    }
+    out[idx] = {sr, si};
     if (dinv) {
         const cx<T> d = dinv[idx];
         xs[idx] = {omega * (d.re * sr - d.im * si), omega * (d.re * si + d.im * sr)};
-    }
-}
-
-template <class T>
-__global__ void prolong3_kernel(Transfer t, const cx<T>* __restrict__ e, const cx<T>* xin, cx<T>* x) {
-    const long long Nf = (long long)t.nf1 * t.nf2 * t.nf3;
-    const long long idx = (long long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (idx >= Nf) return;
-    const int I1 = (int)(idx % t.nf1), I2 = (int)((idx / t.nf1) % t.nf2), I3 = (int)(idx / ((long long)t.nf1 * t.nf2));
-    const int j0x = t.prow0x[I1], j0y = t.prow0y[I2], j0z = t.prow0z[I3];
-    T sr = 0, si = 0;
-    for (int b3 = 0; b3 < t.pw3; ++b3) {
-        const T wz = (T)t.prowz[(size_t)I3 * t.pw3 + b3];
-        if (wz == T(0)) continue;
-        const cx<T>* plane = e + (size_t)(j0z + b3) * t.nc2 * t.nc1;
-        T pr = 0, pi = 0;
-        for (int b2 = 0; b2 < t.pw2; ++b2) {
-            const T wy = (T)t.prowy[(size_t)I2 * t.pw2 + b2];
-            if (wy == T(0)) continue;
-            const cx<T>* row = plane + (size_t)(j0y + b2) * t.nc1 + j0x;
-            T rr = 0, ri = 0;
-            for (int b1 = 0; b1 < t.pw1; ++b1) {
-                const T wx = (T)t.prowx[(size_t)I1 * t.pw1 + b1];
-                const cx<T> v = row[b1];
-                rr += wx * v.re;
-                ri += wx * v.im;
-            }
-            pr += wy * rr;
-            pi += wy * ri;
-        }
-        sr += wz * pr;
-        si += wz * pi;
-    }
-    if (xin) {
-        const cx<T> o = xin[idx];
-        x[idx] = {o.re + sr, o.im + si};
-    } else {
-        x[idx] = {sr, si};
     }
 }
 
@@ -351,23 +318,49 @@ template void launch_op3d<double>(int, int, const OpArgs<double>&, hipStream_t);
 template void launch_op3d<float>(int, int, const OpArgs<float>&, hipStream_t);
 
 template <class T>
+static cx<T>* tmp_a(const Transfer& t) {
+    if constexpr (sizeof(T) == 8) return t.tmpa64; else return t.tmpa32;
+}
+template <class T>
+static cx<T>* tmp_b(const Transfer& t) {
+    if constexpr (sizeof(T) == 8) return t.tmpb64; else return t.tmpb32;
+}
+template <class T>
+static void axis_pass(int m1, int m2, int m3, int axis, int n_out, const int* i0, const double* wt, int w,
+                      const cx<T>* in, cx<T>* out, hipStream_t s, const cx<T>* dinv = nullptr, T omega = T(0),
+                      cx<T>* xs = nullptr, const cx<T>* xin = nullptr) {
+    const long long No = (long long)(axis == 0 ? n_out : m1) * (axis == 1 ? n_out : m2) * (axis == 2 ? n_out : m3);
+    hipLaunchKernelGGL(axis_pass_kernel<T>, dim3(blocks_for(No, 256)), dim3(256), 0, s, m1, m2, m3, axis, n_out, i0,
+                       wt, w, in, out, dinv, omega, xs, xin);
+}
+
+template <class T>
 void launch_restrict3(const Transfer& t, const cx<T>* r, cx<T>* c, hipStream_t s, const cx<T>* dinv, T omega,
                       cx<T>* xs) {
     const long long Nc = (long long)t.nc1 * t.nc2 * t.nc3, Nf = (long long)t.nf1 * t.nf2 * t.nf3;
     if (Nc <= 0) return;
     if (Nc > INT_MAX || Nf > INT_MAX) throw Err{HH_EINVAL, "level too large for a transfer"};
+    if (!tmp_a<T>(t) || !tmp_b<T>(t)) throw Err{HH_EINVAL, "3D transfer without its intermediate grids"};
     meter(sizeof(cx<T>) * ((double)Nf + Nc * (dinv ? 3.0 : 1.0)),
           4.0 * t.rw1 * t.rw2 * t.rw3 * (double)Nc + (dinv ? 8.0 * Nc : 0.0));
-    hipLaunchKernelGGL(restrict3_kernel<T>, dim3(blocks_for(Nc, 256)), dim3(256), 0, s, t, r, c, dinv, omega, xs);
+    // x: [nf3][nf2][nf1] -> [nf3][nf2][nc1]; y: -> [nf3][nc2][nc1]; z: -> [nc3][nc2][nc1]
+    axis_pass<T>(t.nf1, t.nf2, t.nf3, 0, t.nc1, t.pcol0x, t.pcolx, t.rw1, r, tmp_a<T>(t), s);
+    axis_pass<T>(t.nc1, t.nf2, t.nf3, 1, t.nc2, t.pcol0y, t.pcoly, t.rw2, tmp_a<T>(t), tmp_b<T>(t), s);
+    axis_pass<T>(t.nc1, t.nc2, t.nf3, 2, t.nc3, t.pcol0z, t.pcolz, t.rw3, tmp_b<T>(t), c, s, dinv, omega, xs);
 }
 template <class T>
 void launch_prolong_add3(const Transfer& t, const cx<T>* e, const cx<T>* xin, cx<T>* xout, hipStream_t s) {
     const long long Nc = (long long)t.nc1 * t.nc2 * t.nc3, Nf = (long long)t.nf1 * t.nf2 * t.nf3;
     if (Nf <= 0) return;
     if (Nc > INT_MAX || Nf > INT_MAX) throw Err{HH_EINVAL, "level too large for a transfer"};
+    if (!tmp_a<T>(t) || !tmp_b<T>(t)) throw Err{HH_EINVAL, "3D transfer without its intermediate grids"};
     meter(sizeof(cx<T>) * ((double)Nc + Nf * (xin ? 2.0 : 1.0)),
           4.0 * t.pw1 * t.pw2 * t.pw3 * (double)Nf + (xin ? 2.0 * Nf : 0.0));
-    hipLaunchKernelGGL(prolong3_kernel<T>, dim3(blocks_for(Nf, 256)), dim3(256), 0, s, t, e, xin, xout);
+    // z: [nc3][nc2][nc1] -> [nf3][nc2][nc1]; y: -> [nf3][nf2][nc1]; x: -> [nf3][nf2][nf1] (+ xin)
+    axis_pass<T>(t.nc1, t.nc2, t.nc3, 2, t.nf3, t.prow0z, t.prowz, t.pw3, e, tmp_b<T>(t), s);
+    axis_pass<T>(t.nc1, t.nc2, t.nf3, 1, t.nf2, t.prow0y, t.prowy, t.pw2, tmp_b<T>(t), tmp_a<T>(t), s);
+    axis_pass<T>(t.nc1, t.nf2, t.nf3, 0, t.nf1, t.prow0x, t.prowx, t.pw1, tmp_a<T>(t), xout, s, nullptr, T(0),
+                 nullptr, xin);
 }
 template void launch_restrict3<double>(const Transfer&, const cx<double>*, cx<double>*, hipStream_t,
                                        const cx<double>*, double, cx<double>*);

@@ -39,6 +39,7 @@ struct LevelDev {
     // transfer to the next-coarser level (this level = fine side)
     DevBuf prow0x, prowx, pcol0x, pcolx, prow0y, prowy, pcol0y, pcoly;
     DevBuf prow0z, prowz, pcol0z, pcolz;
+    DevBuf tra64, trb64, tra32, trb32;   // unit cube: intermediate grids of the transfer passes
     Transfer tr{};
     // multigrid work vectors
     DevBuf b64, x64, r64, t64, vr64, vx64;

@@ -970,6 +970,15 @@ void SolverImpl::setup_levels_3d(hipStream_t s) {
         t.pcoly = lv.pcoly.as<double>();
         t.pcol0z = lv.pcol0z.as<int>();
         t.pcolz = lv.pcolz.as<double>();
+        const size_t na = (size_t)lv.n3 * lv.n2 * lc.n1, nb = (size_t)lv.n3 * lc.n2 * lc.n1;
+        lv.tra64.alloc(na * sizeof(cx<double>));
+        lv.trb64.alloc(nb * sizeof(cx<double>));
+        lv.tra32.alloc(na * sizeof(cx<float>));
+        lv.trb32.alloc(nb * sizeof(cx<float>));
+        t.tmpa64 = lv.tra64.as<cx<double>>();
+        t.tmpb64 = lv.trb64.as<cx<double>>();
+        t.tmpa32 = lv.tra32.as<cx<float>>();
+        t.tmpb32 = lv.trb32.as<cx<float>>();
     }
     {
         LevelDev& lc = *lev[L];
