@@ -298,6 +298,63 @@ __global__ void fdm3_pass_kernel(int n1, int n2, int n3, int axis, const double*
     out[idx] = {sr, si};
 }
 
+// The same product for lines of at most FL_MAXN entries, staged in LDS: a
+// workgroup takes FL_TL lines (along x: FL_TL consecutive rows; along y or z:
+// FL_TL consecutive x positions at one z or y), loads them and the matrix
+// once with coalesced reads, and forms every output of those lines from LDS
+// (the sum over j in the same order as fdm3_pass_kernel).
+constexpr int FL_TL = 16, FL_MAXN = 72;
+__global__ __launch_bounds__(256) void fdm3_lines_kernel(int n1, int n2, int n3, int axis, const double* __restrict__ A,
+                                                         const cx<double>* __restrict__ in,
+                                                         cx<double>* __restrict__ out,
+                                                         const double* __restrict__ scale) {
+    __shared__ double As[FL_MAXN * FL_MAXN];
+    __shared__ cx<double> ls[FL_MAXN][FL_TL];
+    const int na = axis == 0 ? n1 : axis == 1 ? n2 : n3;
+    const long long stride = axis == 0 ? 1 : axis == 1 ? n1 : (long long)n1 * n2;
+    const int tid = threadIdx.x, b = blockIdx.x;
+    long long base;   // line t starts at base + t * lstep (valid while t < nlines)
+    int nlines, lstep;
+    if (axis == 0) {
+        const long long L0 = (long long)b * FL_TL, total = (long long)n2 * n3;
+        base = L0 * n1;
+        lstep = n1;
+        nlines = (int)(total - L0 < FL_TL ? total - L0 : FL_TL);
+    } else {
+        const int xt = (n1 + FL_TL - 1) / FL_TL;
+        const int x0 = (b % xt) * FL_TL, o = b / xt;   // o: z (axis 1) or y (axis 2)
+        base = (axis == 1 ? (long long)o * n1 * n2 : (long long)o * n1) + x0;
+        lstep = 1;
+        nlines = n1 - x0 < FL_TL ? n1 - x0 : FL_TL;
+    }
+    for (int e = tid; e < na * na; e += 256) As[e] = A[e];
+    for (int e = tid; e < na * FL_TL; e += 256) {
+        // along x the entries of a row are adjacent, along y / z the lines
+        const int t = axis == 0 ? e / na : e % FL_TL, j = axis == 0 ? e % na : e / FL_TL;
+        ls[j][t] = t < nlines ? in[base + (long long)t * lstep + (long long)j * stride] : cx<double>{0.0, 0.0};
+    }
+    __syncthreads();
+    for (int e = tid; e < na * FL_TL; e += 256) {
+        const int t = axis == 0 ? e / na : e % FL_TL, i = axis == 0 ? e % na : e / FL_TL;
+        if (t >= nlines) continue;
+        const double* row = As + i * na;
+        double sr = 0, si = 0;
+        for (int j = 0; j < na; ++j) {
+            const double w = row[j];
+            const cx<double> v = ls[j][t];
+            sr += w * v.re;
+            si += w * v.im;
+        }
+        const long long idx = base + (long long)t * lstep + (long long)i * stride;
+        if (scale) {
+            const double g = scale[idx];
+            sr *= g;
+            si *= g;
+        }
+        out[idx] = {sr, si};
+    }
+}
+
 inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -378,14 +435,25 @@ void launch_fdm3_solve(int n3, int n2, int n1, const double* Vx, const double* V
     if (N <= 0) return;
     if (N > INT_MAX) throw Err{HH_EINVAL, "deflation level too large"};
     meter(6.0 * 32.0 * N + 8.0 * N, 4.0 * N * ((double)n1 + n2 + n3) * 2.0);
+    const bool lines = std::max({n1, n2, n3}) <= FL_MAXN;
     const unsigned g = blocks_for(N, 256);
+    auto pass = [&](int axis, const double* M, const cx<double>* in, cx<double>* out, const double* sc) {
+        if (lines) {
+            const long long nb = axis == 0 ? ((long long)n2 * n3 + FL_TL - 1) / FL_TL
+                                           : (long long)((n1 + FL_TL - 1) / FL_TL) * (axis == 1 ? n3 : n2);
+            hipLaunchKernelGGL(fdm3_lines_kernel, dim3((unsigned)nb), dim3(256), 0, s, n1, n2, n3, axis, M, in, out,
+                               sc);
+        } else {
+            hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, axis, M, in, out, sc);
+        }
+    };
     // V^T c along x, y, z (the last scaled by 1 / D), then V along z, y, x
-    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 0, VxT, c, t1, nullptr);
-    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 1, VyT, t1, t2, nullptr);
-    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 2, VzT, t2, t1, dinv);
-    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 2, Vz, t1, t2, nullptr);
-    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 1, Vy, t2, t1, nullptr);
-    hipLaunchKernelGGL(fdm3_pass_kernel, dim3(g), dim3(256), 0, s, n1, n2, n3, 0, Vx, t1, e, nullptr);
+    pass(0, VxT, c, t1, nullptr);
+    pass(1, VyT, t1, t2, nullptr);
+    pass(2, VzT, t2, t1, dinv);
+    pass(2, Vz, t1, t2, nullptr);
+    pass(1, Vy, t2, t1, nullptr);
+    pass(0, Vx, t1, e, nullptr);
 }
 
 }  // namespace hh
