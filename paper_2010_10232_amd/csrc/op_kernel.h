@@ -292,23 +292,31 @@ __global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
     const int I = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (I >= N) return;
     const int I1 = I % n1, I2 = I / n1;
+    // all (2p+1)^2 neighbour loads in flight at once, except in FP64 from degree
+    // 5 (or with a stored stencil from degree 4): that many values no longer fit
+    // the registers (the compiler staged them through private memory), so the
+    // rows go one after another, 2p+1 loads in flight each, and the y bands are
+    // read per row (a private array indexed by the row would live in memory)
+    constexpr bool ROWWISE = sizeof(T) == 8 && (PY >= 5 || (KIND == KIND_STENCIL && PY >= 4));
     T kx[BX], mx[BX], ky[BY], my[BY];
 #pragma unroll
     for (int d = 0; d < BX; ++d) {
         kx[d] = (T)a.Kx[(size_t)I1 * BX + d];
         mx[d] = (T)a.Mx[(size_t)I1 * BX + d];
     }
+    if constexpr (!ROWWISE) {
 #pragma unroll
-    for (int d = 0; d < BY; ++d) {
-        ky[d] = (T)a.Ky[(size_t)I2 * BY + d];
-        my[d] = (T)a.My[(size_t)I2 * BY + d];
+        for (int d = 0; d < BY; ++d) {
+            ky[d] = (T)a.Ky[(size_t)I2 * BY + d];
+            my[d] = (T)a.My[(size_t)I2 * BY + d];
+        }
     }
     const T are = a.are, aim = a.aim;
     const T k2c = (T)a.k2c;
     T wr = 0, wi = 0, vr = 0, vi = 0;
     // every neighbour is loaded from a valid (clamped) address and replaced by
     // zero when it lies outside the level, so no load waits behind a branch
-#pragma unroll
+#pragma unroll ROWWISE ? 1 : BY
     for (int d2 = 0; d2 < BY; ++d2) {
         const int J2 = I2 + d2 - PY;
         const bool ok2 = (unsigned)J2 < (unsigned)n2;
@@ -339,8 +347,10 @@ __global__ __launch_bounds__(256) void op_direct_kernel(OpArgs<T> a) {
             u1r = cr;
             u1i = ci;
         }
-        wr += my[d2] * u1r + ky[d2] * u2r;
-        wi += my[d2] * u1i + ky[d2] * u2i;
+        const T myv = ROWWISE ? (T)a.My[(size_t)I2 * BY + d2] : my[d2];
+        const T kyv = ROWWISE ? (T)a.Ky[(size_t)I2 * BY + d2] : ky[d2];
+        wr += myv * u1r + kyv * u2r;
+        wi += myv * u1i + kyv * u2i;
     }
     T yr = wr, yi = wi;
     if (KIND == KIND_STENCIL) {
