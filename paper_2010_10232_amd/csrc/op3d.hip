@@ -14,7 +14,7 @@
 // pipeline over double-buffered LDS with one barrier per step: slice t (tile
 // plus its p-wide halo) is staged from registers (slice t + 1 is already in
 // flight), slice t - 1 gets its x bands once per staged row (sum
-// factorisation: Kx x and Mx x per row), and for slice t - 2 every thread forms
+// factorisation: Kx x - alpha k^2 Mx x and Mx x per row), and for slice t - 2 every thread forms
 // B2 and M2 of its column through the y bands and adds them into a window of
 // 2p + 1 running output slices held in registers (mz, kz as weights).  After
 // input slice J3, output slice J3 - p is complete and is written with the
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(O3_TB) void op3d_kernel(OpArgs<T> a, int tz) {
     // double buffers: slice t is staged while slice t - 1 gets its x bands and
     // slice t - 2 its y and z bands, one barrier per step
     __shared__ cx<T> xs[2][LH][LW];
-    __shared__ cx<T> us[2][2][LH][O3_TX];                // [buffer][Kx x, Mx x][row][column]
+    __shared__ cx<T> us[2][2][LH][O3_TX];                // [buffer][Kx x - alpha k^2 Mx x, Mx x][row][column]
     __shared__ T mzS[O3_TZMAX][B], kzS[O3_TZMAX][B];     // z bands of the workgroup's output slices
 
     const int n1 = a.n1, n2 = a.n2, n3 = a.n3;
@@ -107,7 +107,8 @@ __global__ __launch_bounds__(O3_TB) void op3d_kernel(OpArgs<T> a, int tz) {
             if (t < s1) fetch(t + 1);
         }
         if (t - 1 >= s0 && t - 1 <= s1) {
-            // x bands of slice t - 1, once per staged row (every item of this thread has column c)
+            // x bands of slice t - 1, once per staged row (every item of this thread has
+            // column c): Kx x - alpha k^2 Mx x and Mx x
             const int bf = (t - 1) & 1;
             for (int e = tid; e < LH * O3_TX; e += O3_TB) {
                 const int rr = e / O3_TX;
@@ -120,7 +121,9 @@ __global__ __launch_bounds__(O3_TB) void op3d_kernel(OpArgs<T> a, int tz) {
                     u2r += mx[d] * v.re;
                     u2i += mx[d] * v.im;
                 }
-                us[bf][0][rr][c] = {u1r, u1i};
+                const T cr = u1r - k2c * (are * u2r - aim * u2i);
+                const T ci = u1i - k2c * (are * u2i + aim * u2r);
+                us[bf][0][rr][c] = {cr, ci};
                 us[bf][1][rr][c] = {u2r, u2i};
             }
         }
@@ -133,10 +136,8 @@ __global__ __launch_bounds__(O3_TB) void op3d_kernel(OpArgs<T> a, int tz) {
 #pragma unroll
                 for (int d2 = 0; d2 < B; ++d2) {
                     const cx<T> u1 = us[bf][0][r + d2][c], u2 = us[bf][1][r + d2][c];
-                    const T cr = u1.re - k2c * (are * u2.re - aim * u2.im);
-                    const T ci = u1.im - k2c * (are * u2.im + aim * u2.re);
-                    br += my[d2] * cr + ky[d2] * u2.re;
-                    bi += my[d2] * ci + ky[d2] * u2.im;
+                    br += my[d2] * u1.re + ky[d2] * u2.re;
+                    bi += my[d2] * u1.im + ky[d2] * u2.im;
                     mr += my[d2] * u2.re;
                     mi += my[d2] * u2.im;
                 }
