@@ -1746,6 +1746,99 @@ __global__ __launch_bounds__(RB) void arnoldi_reg_kernel(long long N, int j, cx<
     }
 }
 
+// LDS-resident variant for the vectors past the register kernels (N up to
+// 256 * RB * R): every thread keeps its R entries of w in the LDS of its block
+// (dynamic, R * RB complex) and the current basis vector in registers; the next
+// basis vector is loaded after w's update (no room for a second register
+// copy).  Same MGS order and one grid-wide exchange per projection as
+// arnoldi_coop_kernel, but V and w cross HBM once per step instead of V twice
+// and w three times per projection.
+constexpr int kLdsR = 36;
+template <int R>
+__global__ __launch_bounds__(RB) void arnoldi_lds_kernel(long long N, int j, cx<double>* __restrict__ w,
+                                                         const cx<double>* __restrict__ V, long long ldv,
+                                                         KrylovDev k) {
+    extern __shared__ cx<double> wl[];            // [R][RB]: this block's entries of w
+    __shared__ double sh[2 * (RB / 64)];
+    __shared__ double shb[2];
+    __shared__ cx<double> shc[kMaxRestart + 1];   // block 0: column j of H
+    __shared__ double scs[kMaxRestart];            // block 0: rotations 0..j-1
+    __shared__ cx<double> ssn[kMaxRestart];
+    const long long stride = (long long)gridDim.x * RB;
+    const long long t0 = (long long)blockIdx.x * RB + threadIdx.x;
+    const int ldh = k.m + 1;
+    const int epoch = step_epoch(k);
+    cx<double> gj = {0.0, 0.0};
+    int broke = 0;
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < j; i += RB) {
+            scs[i] = k.cs[i];
+            ssn[i] = k.sn[i];
+        }
+        if (threadIdx.x == 0) {
+            gj = k.g[j];
+            broke = k.ints[1];
+        }
+    }
+    cx<double> vr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const long long t = t0 + r * stride;
+        wl[r * RB + threadIdx.x] = t < N ? w[t] : cx<double>{0.0, 0.0};
+        vr[r] = t < N ? V[t] : cx<double>{0.0, 0.0};
+    }
+    int round = 0;
+    for (int i = 0; i <= j; ++i, ++round) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const cx<double> wv = wl[r * RB + threadIdx.x];
+            sr += vr[r].re * wv.re + vr[r].im * wv.im;
+            si += vr[r].re * wv.im - vr[r].im * wv.re;
+        }
+        const cx<double> h = grid_sum_reg(sr, si, step_tag(epoch, round), k, sh, shb);
+        if (blockIdx.x == 0 && threadIdx.x == 0) shc[i] = h;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cx<double> wv = wl[r * RB + threadIdx.x];
+            wv.re -= h.re * vr[r].re - h.im * vr[r].im;
+            wv.im -= h.re * vr[r].im + h.im * vr[r].re;
+            wl[r * RB + threadIdx.x] = wv;
+        }
+        if (i < j) {
+            const cx<double>* vi1 = V + (size_t)(i + 1) * ldv;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const long long t = t0 + r * stride;
+                vr[r] = t < N ? vi1[t] : cx<double>{0.0, 0.0};
+            }
+        }
+    }
+    double nr = 0.0, zero = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const cx<double> wv = wl[r * RB + threadIdx.x];
+        nr += wv.re * wv.re + wv.im * wv.im;
+    }
+    const double hn = sqrt(grid_sum_reg(nr, zero, step_tag(epoch, round), k, sh, shb).re);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int tmo = __hip_atomic_load(&k.ints[5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        double c;
+        cx<double> sg;
+        givens_rotate(shc, scs, ssn, j, hn, c, sg);
+        for (int i = 0; i <= j + 1; ++i) k.H[(size_t)j * ldh + i] = shc[i];
+        const double gabs = givens_finish(k, j, hn, c, sg, gj, broke);
+        if (k.hstep) publish_step(k, j, gabs, (broke || hn == 0.0) ? 1 : 0, tmo);
+    }
+    next_epoch(k, epoch);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const long long t = t0 + r * stride;
+        const cx<double> wv = wl[r * RB + threadIdx.x];
+        if (t < N) w[t] = hn == 0.0 ? cx<double>{0.0, 0.0} : cx<double>{wv.re / hn, wv.im / hn};
+    }
+}
+
 // One Arnoldi step in the one-reduction form of modified Gram-Schmidt (the
 // inverse compact-WY form of Swirydowicz, Langou, Ananthan, Yang and Thomas,
 // 2020).  MGS subtracts the projections in order, so its coefficients satisfy
@@ -2046,7 +2139,7 @@ __global__ __launch_bounds__(RB) void arnoldi_onered_kernel(long long N, int j, 
 
 // Blocks of RB threads of kernel fn that the current device holds at once
 // (cached per device and kernel).
-static long long resident_capacity(const void* fn) {
+static long long resident_capacity(const void* fn, size_t shm = 0) {
     static std::mutex mu;
     static std::map<std::pair<int, const void*>, long long> cache;
     int dev = 0;
@@ -2054,8 +2147,10 @@ static long long resident_capacity(const void* fn) {
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find({dev, fn});
     if (it != cache.end()) return it->second;
+    if (shm > 0)   // dynamic LDS beyond the default limit, allowed once per kernel and device
+        HH_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     int per_cu = 0, cus = 0;
-    HH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, RB, 0));
+    HH_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, RB, shm));
     HH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const long long cap = (long long)per_cu * cus;
     cache[{dev, fn}] = cap;
@@ -2091,6 +2186,13 @@ bool launch_arnoldi_grid(long long N, int j, cx<double>* w, const cx<double>* V,
     pick(4, (const void*)arnoldi_reg_kernel<4>);
     pick(8, (const void*)arnoldi_reg_kernel<8>);
     pick(16, (const void*)arnoldi_reg_kernel<16>);
+    // past the register kernels: w in LDS, kLdsR entries per thread, one block per CU
+    size_t shm = 0;
+    if (fn == (const void*)arnoldi_coop_kernel && N <= 256LL * RB * kLdsR) {
+        fn = (const void*)arnoldi_lds_kernel<kLdsR>;
+        blocks = std::max(1LL, (N + (long long)RB * kLdsR - 1) / ((long long)RB * kLdsR));
+        shm = (size_t)RB * kLdsR * sizeof(cx<double>);
+    }
     if (blocks > kSlotBlocks) throw Err{HH_EINVAL, "cooperative Arnoldi grid exceeds the exchange slots"};
     // A cooperative launch guarantees that all blocks are resident, but the
     // runtime serves it from a separate hardware queue: two cross-queue hand-offs
@@ -2101,12 +2203,13 @@ bool launch_arnoldi_grid(long long N, int j, cx<double>* w, const cx<double>* V,
     // as CUs are free, and since the exchange's waits are bounded a shortage of
     // CUs can only end in the timeout flag, never a hang.  Otherwise the
     // cooperative launch when allowed; else nothing is launched (false).
-    if (blocks * concurrent <= resident_capacity(fn)) {
-        HH_HIP(hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(RB), args, 0, s));
+    const long long cap = resident_capacity(fn, shm);
+    if (blocks * concurrent <= cap) {
+        HH_HIP(hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(RB), args, shm, s));
         return true;
     }
-    if (!coop_ok) return false;
-    hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)blocks), dim3(RB), args, 0, s);
+    if (!coop_ok || blocks > cap) return false;
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)blocks), dim3(RB), args, shm, s);
     if (e != hipSuccess) throw Err{HH_EHIP, std::string("cooperative Arnoldi launch: ") + hipGetErrorString(e)};
     return true;
 }

@@ -51,12 +51,17 @@ def _compare(tag, u_a, i_a, u_b, i_b, bounds):
     # N = 270,400 > 262,144: 133 workgroups of 8 entries, cooperative launch;
     # inner FGMRES on level 1 (68,121 unknowns)
     (2, 520, 100.0, {}, INNER_KRYLOV, "cooperative grid"),
+    # N = 1,210,000 > 2^20: past the register kernels, w kept in LDS (132 workgroups
+    # of 36 entries per thread, one per CU); two-level deflation
+    (2, 1100, 687.5, {"defl_mode": 1}, LINEAR, "LDS-resident grid"),
 ])
 def test_fused_arnoldi_matches_per_projection_kernels(p, n_el, k, extra, bounds, form):
     from paper_2010_10232_amd import binding as B
     prob = B.Problem(2, p, n_el, k=k)
     if form == "cooperative grid":
         assert prob.N > 262144
+    if form == "LDS-resident grid":
+        assert 1 << 20 < prob.N <= 256 * 256 * 36
     opts = dict(maxit=12, ortho=1)
     opts.update(extra)
     s1 = B.Solver(prob, **opts)
