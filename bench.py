@@ -83,14 +83,13 @@ WORKLOADS = {
     "mp1a_k1000_p3_1600": dict(dim=1, p=3, n_el=1600, k=1000.0, sommerfeld=True, opts=dict(defl_direct_max=512)),
     # MP 1-B: 1D, k = 50, p = 2, 80 elements, two-level deflation
     "mp1b_k50_p2_80": dict(dim=1, p=2, n_el=80, k=50.0, x0=(0.5,), opts=dict(defl_mode=1)),
-    # unit cube (3D tensor product), k = 62.5, p = 3, 100^3 elements (k h = 0.625, 1,030,301
-    # unknowns: the largest cube whose Arnoldi vectors fit the register-resident grid kernel),
-    # point source at the centre, two-level deflation (E^-1 on 132,651 unknowns by fast
-    # diagonalisation), multigrid down to 7 elements per side (512 unknowns solved densely).
+    # unit cube (3D tensor product), k = 80, p = 3, 128^3 elements (k h = 0.625, 2,146,689
+    # unknowns), point source at the centre, two-level deflation (E^-1 on 274,625 unknowns by fast
+    # diagonalisation), multigrid down to 4 elements per side (125 unknowns solved densely).
     # The CPU oracle cannot assemble this size in minutes: its baseline runs the same problem
     # family on 32^3 elements (k = 20, the same k h)
-    "cube_k62_p3_100": dict(dim=3, p=3, n_el=100, k=62.5, x0=(0.5, 0.5, 0.5),
-                            opts=dict(defl_mode=1, mg_min_elems=7), cpu_sample_n_el=32),
+    "cube_k80_p3_128": dict(dim=3, p=3, n_el=128, k=80.0, x0=(0.5, 0.5, 0.5),
+                            opts=dict(defl_mode=1, mg_min_elems=4), cpu_sample_n_el=32),
     # 64 independent constant-k problems, k ~ U[50, 400], n_el = ceil(k / 0.625),
     # p ~ U{2, 3, 4}, random interior sources; FP32 V-cycle, FP64 Krylov and deflation
     "batch64_k50_400": dict(batch=64, seed=0, opts=dict(precision=1, maxit=400)),

@@ -272,16 +272,16 @@ def test_3d_point_source_noalloc_and_batched_solves():
 
 
 def test_3d_full_size_sampled_rows_and_solve():
-    """The bench's cube (100^3 elements, p = 3, k = 62.5; 1,030,301 unknowns) at full size: A and
+    """The bench's cube (128^3 elements, p = 3, k = 80; 2,146,689 unknowns) at full size: A and
     M_beta of the finest level on 3000 sampled rows (faces, edges, corners and random interior
     rows) against rows formed from the oracle's 1D matrices by the tensor-product rule that the
     3D pins fix; at tol 1e-10 the FP64 solve converges with its true residual recomputed here,
     and the mixed form agrees with it within 1e-6."""
     import torch
     from paper_2010_10232_amd import binding as B
-    p, ne, k = 3, 100, 62.5
+    p, ne, k = 3, 128, 80.0
     gp = B.Problem(3, p, ne, k=k)
-    gs = B.Solver(gp, defl_mode=1, mg_min_elems=7)
+    gs = B.Solver(gp, defl_mode=1, mg_min_elems=4)
     n = ne + p - 2
     from oracle import bspline as bs
     K1, M1 = (m.toarray() for m in hz.matrices_1d(bs.uniform_breakpoints(ne), p))
@@ -313,12 +313,12 @@ def test_3d_full_size_sampled_rows_and_solve():
         assert e <= 1e-13, (opname, e)
     f = gp.point_source((0.5, 0.5, 0.5))
     _say("[3d full size] FP64 solve")
-    u, info = B.Solver(gp, defl_mode=1, mg_min_elems=7, tol=1e-10, maxit=400).solve(f)
+    u, info = B.Solver(gp, defl_mode=1, mg_min_elems=4, tol=1e-10, maxit=400).solve(f)
     assert info["converged"] == 1
     r = f - gs.apply("A", 0, u)
     rel_true = (torch.linalg.norm(r) / torch.linalg.norm(f)).item()
     assert rel_true <= 1e-10 and abs(rel_true - info["relres_true"]) <= 1e-3 * rel_true
     _say("[3d full size] mixed solve")
-    um, im = B.Solver(gp, defl_mode=1, mg_min_elems=7, precision=1, tol=1e-10, maxit=400).solve(f)
+    um, im = B.Solver(gp, defl_mode=1, mg_min_elems=4, precision=1, tol=1e-10, maxit=400).solve(f)
     assert im["converged"] == 1
     assert (torch.linalg.norm(um - u) / torch.linalg.norm(u)).item() <= 1e-6
