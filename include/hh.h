@@ -204,7 +204,8 @@ typedef struct {
                                 the ADP vectors (defl_z = 1) it is n_levels: a level of its
                                 own, outside the multigrid hierarchy, that hh_level_info and
                                 hh_apply (HH_OP_A, HH_OP_K, HH_OP_MK, HH_OP_EINV) accept */
-    int op_rows[2];          /* strip height (rows) of the level-operator kernel, FP64 / FP32 */
+    int op_rows[2];          /* strip height (rows) of the level-operator kernel, FP64 / FP32
+                                (3D: output slices per workgroup); 0: the fixed rule */
     int defl_sub[2];         /* substructured E^-1 (defl_direct_solver): subdomains per
                                 direction at the direct deflation level, else 0 */
     long long defl_sep;      /* separator unknowns of that cut (0 if not substructured) */
