@@ -87,10 +87,11 @@ def forward(params, z, c, keep=False):
     return (out, acts, pre) if keep else out
 
 
-def feature(k2_elem, n_el, n):
-    """c[i2, i1] = k^2 h^2 of the finest element (min(i2, n_el-1), min(i1, n_el-1))."""
+def feature(k2_elem, n_el, n, length=1.0):
+    """c[i2, i1] = k^2 h^2 of the finest element (min(i2, n_el-1), min(i1, n_el-1)),
+    h = length / n_el the x extent of an element."""
     n2, n1 = n
-    h = 1.0 / n_el
+    h = length / n_el
     i2 = np.minimum(np.arange(n2), k2_elem.shape[0] - 1)
     i1 = np.minimum(np.arange(n1), k2_elem.shape[1] - 1)
     return k2_elem[np.ix_(i2, i1)] * h * h

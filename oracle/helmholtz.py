@@ -20,6 +20,12 @@ A non-constant wave number is constant on each element of the finest mesh
 Vectors are ordered with x fastest: index i2 * n1 + i1 over interior
 control points.  All matrices are scipy.sparse in float64.
 
+Domain extents (option lengths): the geometry map F of section 2.3 taken as the
+axis-aligned scaling F(xi) = (L_1 xi_1, ..., L_d xi_d) of the parametric unit
+square; the basis is built on the physical breakpoints L_d i / n_el, so K and
+M carry the Jacobian (1D: K scales by 1/L, M by L), k is a physical wave
+number and source points are physical.  Default: the unit interval / square / cube.
+
 The unit cube (dim = 3, constant k, Dirichlet everywhere): the tensor-product
 extension of section 2.3 to three directions, the setting where section 4.3
 expects the cost advantage it measures in 2D to grow (section 3 names 2D and
@@ -38,9 +44,10 @@ class Problem:
 
     k_elem (optional) holds k (not k^2) per finest element, x fastest, shape
     (n_el_y, n_el_x) in 2D or (n_el,) in 1D; otherwise the constant k is used.
+    lengths (optional): the domain's extent per direction (default 1 each).
     """
 
-    def __init__(self, dim, p, n_el, k, k_elem=None, sommerfeld=False):
+    def __init__(self, dim, p, n_el, k, k_elem=None, sommerfeld=False, lengths=None):
         if dim not in (1, 2, 3):
             raise ValueError("dim must be 1, 2 or 3")
         if sommerfeld and (dim != 1 or k_elem is not None):
@@ -57,6 +64,17 @@ class Problem:
             shape = tuple(self.n_el[::-1]) if dim == 2 else (self.n_el[0],)
             k_elem = k_elem.reshape(shape)
         self.k_elem = k_elem
+        self.lengths = [1.0] * dim if lengths is None else [float(v) for v in lengths]
+        if len(self.lengths) != dim or not all(np.isfinite(v) and v > 0 for v in self.lengths):
+            raise ValueError("lengths: one positive extent per direction")
+
+    def breakpoints(self, d):
+        """Physical breakpoints of direction d: L_d i / n_el."""
+        return self.lengths[d] * bs.uniform_breakpoints(self.n_el[d])
+
+    def span(self, d, x):
+        """Element of direction d holding the physical coordinate x (span rule on x / L_d)."""
+        return bs.uniform_span(x / self.lengths[d], self.n_el[d])
 
     @property
     def k2_elem(self):
@@ -84,17 +102,17 @@ def boundary_operator(prob):
 def dirichlet_lift_rhs(prob, u0=1.0):
     """MP 1-A: f = -u0 (K - k^2 M)[:, 0] on the unknowns (the eliminated first function
     carries the boundary value u0; the equation itself has no source)."""
-    b = bs.uniform_breakpoints(prob.n_el[0])
+    b = prob.breakpoints(0)
     K, M = bs.assemble_full(b, prob.p)
     col = K[1:, 0] - prob.k ** 2 * M[1:, 0]
     return (-u0 * col).astype(np.complex128)
 
 
 def l2_error_1d(prob, u, exact, u0=1.0, nq=None):
-    """Continuous L2 norm of (u_h - exact) on [0, 1], u_h = u0 phi_0 + sum_i u_i phi_i."""
+    """Continuous L2 norm of (u_h - exact) on [0, L], u_h = u0 phi_0 + sum_i u_i phi_i."""
     p = prob.p
     nq = nq or (p + 4)
-    b = bs.uniform_breakpoints(prob.n_el[0])
+    b = prob.breakpoints(0)
     U = np.zeros(prob.n_el[0] + p, dtype=np.complex128)
     U[0] = u0
     U[1:1 + len(u)] = u
@@ -157,7 +175,7 @@ def fine_operators(prob):
     """Level-0 stiffness K and k^2-weighted mass M_k (sparse, interior)."""
     p = prob.p
     if prob.dim == 1:
-        b = bs.uniform_breakpoints(prob.n_el[0])
+        b = prob.breakpoints(0)
         K, M = matrices_1d(b, p, keep_last=prob.sommerfeld)
         if prob.k_elem is None:
             Mk = prob.k ** 2 * M
@@ -165,12 +183,12 @@ def fine_operators(prob):
             Mk = weighted_mass_1d(b, p, prob.k2_elem)
         return K.tocsr(), Mk.tocsr()
     if prob.dim == 3:
-        (Kx, Mx), (Ky, My), (Kz, Mz) = [matrices_1d(bs.uniform_breakpoints(n), p) for n in prob.n_el]
+        (Kx, Mx), (Ky, My), (Kz, Mz) = [matrices_1d(prob.breakpoints(d), p) for d in range(3)]
         K = sp.kron(Mz, sp.kron(My, Kx)) + sp.kron(Mz, sp.kron(Ky, Mx)) + sp.kron(Kz, sp.kron(My, Mx))
         Mk = prob.k ** 2 * sp.kron(Mz, sp.kron(My, Mx))
         return K.tocsr(), Mk.tocsr()
-    bx = bs.uniform_breakpoints(prob.n_el[0])
-    by = bs.uniform_breakpoints(prob.n_el[1])
+    bx = prob.breakpoints(0)
+    by = prob.breakpoints(1)
     Kx, Mx = matrices_1d(bx, p)
     Ky, My = matrices_1d(by, p)
     K = sp.kron(My, Kx) + sp.kron(Ky, Mx)
@@ -189,17 +207,16 @@ def point_source_rhs(prob, x0, amp=1.0):
     """
     p = prob.p
     if prob.dim == 1:
-        b = bs.uniform_breakpoints(prob.n_el[0])
-        e = bs.uniform_span(x0[0], prob.n_el[0])
+        b = prob.breakpoints(0)
+        e = prob.span(0, x0[0])
         return amp * bs.basis_all(b, p, x0[0], elem=e)[1:-1].astype(np.complex128)
     if prob.dim == 3:
-        f = [bs.basis_all(bs.uniform_breakpoints(n), p, x0[d], elem=bs.uniform_span(x0[d], n))[1:-1]
-             for d, n in enumerate(prob.n_el)]
+        f = [bs.basis_all(prob.breakpoints(d), p, x0[d], elem=prob.span(d, x0[d]))[1:-1] for d in range(3)]
         return amp * np.kron(f[2], np.kron(f[1], f[0])).astype(np.complex128)
-    bx = bs.uniform_breakpoints(prob.n_el[0])
-    by = bs.uniform_breakpoints(prob.n_el[1])
-    ex = bs.uniform_span(x0[0], prob.n_el[0])
-    ey = bs.uniform_span(x0[1], prob.n_el[1])
+    bx = prob.breakpoints(0)
+    by = prob.breakpoints(1)
+    ex = prob.span(0, x0[0])
+    ey = prob.span(1, x0[1])
     fx = bs.basis_all(bx, p, x0[0], elem=ex)[1:-1]
     fy = bs.basis_all(by, p, x0[1], elem=ey)[1:-1]
     return amp * np.kron(fy, fx).astype(np.complex128)
@@ -207,7 +224,7 @@ def point_source_rhs(prob, x0, amp=1.0):
 
 def source_spans(prob, x0):
     """Element indices (per direction) that hold the source point (span rule)."""
-    return [bs.uniform_span(x0[d], prob.n_el[d]) for d in range(prob.dim)]
+    return [prob.span(d, x0[d]) for d in range(prob.dim)]
 
 
 def manufactured_rhs_2d(prob, a, bfreq, nq=None):

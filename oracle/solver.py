@@ -86,7 +86,7 @@ def build_hierarchy(prob, opts):
     columns of the knot-insertion matrix; 2D: P_y (x) P_x; 3D: P_z (x) P_y (x) P_x).
     """
     p = prob.p
-    bks = [bs.uniform_breakpoints(n) for n in prob.n_el]
+    bks = [prob.breakpoints(d) for d in range(prob.dim)]
     K, Mk = fine_operators(prob)
     levels = []
     lv = Level()
@@ -326,9 +326,9 @@ class Solver:
         p = self.prob
         if p.dim == 2:
             k2 = p.k2_elem if p.k_elem is not None else np.full((p.n_el[1], p.n_el[0]), p.k ** 2)
-            return cnn.feature(k2, p.n_el[0], (lv.n[1], lv.n[0]))
+            return cnn.feature(k2, p.n_el[0], (lv.n[1], lv.n[0]), p.lengths[0])
         k2 = (p.k2_elem if p.k_elem is not None else np.full(p.n_el[0], p.k ** 2))[None, :]
-        return cnn.feature(k2, p.n_el[0], (1, lv.n[0]))
+        return cnn.feature(k2, p.n_el[0], (1, lv.n[0]), p.lengths[0])
 
     def vcycle_once(self, l, b):
         """One V(nu_pre, nu_post) cycle on M_beta,l from a zero initial guess."""
