@@ -71,6 +71,12 @@ typedef struct {
                               level; the left end stays Dirichlet (its value enters through
                               hh_rhs_dirichlet_lift) */
     int n_el_z;            /* dim 3: elements in z (>= 2); ignored otherwise */
+    double length[3];      /* extent of the domain per direction, (0, L_d): the geometry map
+                              F(xi) = (L_1 xi_1, ...) of section 2.3 applied to the parametric
+                              unit square (the basis lives on the physical breakpoints L_d i /
+                              n_el, k is a physical wave number, source points are physical
+                              coordinates in [0, L_d]); 0 means 1, negative or non-finite
+                              values are HH_EINVAL */
 } hh_problem_desc;
 
 /* Preconditioner and Krylov parameters (hh_default_opts fills the defaults). */
@@ -258,9 +264,9 @@ hh_status hh_problem_size(const hh_problem* pr, int n[2]);
  * problem does not have. */
 hh_status hh_problem_size3(const hh_problem* pr, int n[3]);
 
-/* Element (knot-span) index holding x0 per direction: floor(x0 * n_el), with
- * x0 == 1 mapped to the last element (the half-open span rule of section
- * 2.3.1).  x0 outside [0,1] -> HH_EINVAL.  x0 and spans hold dim entries. */
+/* Element (knot-span) index holding x0 per direction: floor(x0 / L * n_el), with
+ * x0 == L mapped to the last element (the half-open span rule of section
+ * 2.3.1).  x0 outside [0,L] -> HH_EINVAL.  x0 and spans hold dim entries. */
 hh_status hh_point_spans(const hh_problem* pr, const double* x0, int* spans);
 
 /* Point source load f_i = amp * Phi_i(x0) (the Galerkin load of amp * delta(x - x0),

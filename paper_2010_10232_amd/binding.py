@@ -29,7 +29,8 @@ EXPORTED = ["hh_default_opts", "hh_last_error", "hh_assemble", "hh_problem_destr
 class ProblemDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("p", ctypes.c_int), ("n_el", ctypes.c_int * 2),
                 ("k_mode", ctypes.c_int), ("k", ctypes.c_double),
-                ("k_elem", ctypes.POINTER(ctypes.c_double)), ("bc_right", ctypes.c_int), ("n_el_z", ctypes.c_int)]
+                ("k_elem", ctypes.POINTER(ctypes.c_double)), ("bc_right", ctypes.c_int), ("n_el_z", ctypes.c_int),
+                ("length", ctypes.c_double * 3)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -181,12 +182,15 @@ def default_opts(**kw):
 
 
 class Problem:
-    """A Helmholtz problem on (0,1)^dim (dim 1, 2 or 3): degree p, n_el elements per
-    direction, constant k or k_elem (k per finest element, x fastest; not in 3D)."""
+    """A Helmholtz problem on (0,1)^dim (dim 1, 2 or 3), or on the box with the given
+    lengths: degree p, n_el elements per direction, constant k or k_elem (k per finest
+    element, x fastest; not in 3D)."""
 
-    def __init__(self, dim, p, n_el, k=None, k_elem=None, sommerfeld=False):
+    def __init__(self, dim, p, n_el, k=None, k_elem=None, sommerfeld=False, lengths=None):
         lib = load()
         d = ProblemDesc()
+        for i, v in enumerate(lengths or ()):
+            d.length[i] = float(v)
         d.dim, d.p = int(dim), int(p)
         d.bc_right = 1 if sommerfeld else 0
         ne = [int(n_el)] * 3 if np.isscalar(n_el) else [int(v) for v in n_el] + [1, 1]

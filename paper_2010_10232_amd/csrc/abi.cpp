@@ -130,8 +130,8 @@ hh_status hh_point_spans(const hh_problem* pr, const double* x0, int* spans) {
     if (!pr || !x0 || !spans) throw Err{HH_EINVAL, "NULL argument"};
     const ProblemImpl& P = pr->impl;
     for (int d = 0; d < P.dim; ++d) {
-        if (!(x0[d] >= 0.0 && x0[d] <= 1.0)) throw Err{HH_EINVAL, "source point outside [0,1]^d"};
-        spans[d] = span_of(x0[d], P.nel[d]);
+        if (!(x0[d] >= 0.0 && x0[d] <= P.len[d])) throw Err{HH_EINVAL, "source point outside the domain"};
+        spans[d] = span_of(x0[d] / P.len[d], P.nel[d]);
     }
     return HH_OK;
     HH_CATCH

@@ -194,7 +194,8 @@ inline void visit_row(const Axis& ax, const Axis& ay, bool const_k, double k2c, 
 // Host-side builders (setup.cpp).
 void gauss_legendre(int n, double* x, double* w);
 // keep_last: only the first function is eliminated (radiation condition at the right end)
-Axis make_axis(int p, int nel_fine, int level, bool keep_last = false);
+// len: the direction's extent (breakpoints len * i / nel_fine)
+Axis make_axis(int p, int nel_fine, int level, bool keep_last = false, double len = 1.0);
 Axis make_trivial_axis();
 void make_transfer(Axis& fine, const Axis& coarse);
 // ADP deflation vectors along one direction (zf: their tables on the fine

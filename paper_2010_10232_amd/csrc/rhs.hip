@@ -48,14 +48,14 @@ void point_factors(const ProblemImpl& P, const double* x0, double* stage) {
     const int n1 = P.ax0.n, n2 = P.ay0.n, p = P.p;
     for (int i = 0; i < stage_size(P); ++i) stage[i] = 0.0;
     double Nv[8];
-    const int s1 = span_of(x0[0], P.nel[0]);
+    const int s1 = span_of(x0[0] / P.len[0], P.nel[0]);
     basis_values(P.ax0.U, p, s1 + p, x0[0], Nv, nullptr);
     for (int a = 0; a <= p; ++a) {
         const int i = s1 + a - 1;
         if (i >= 0 && i < n1) stage[i] = Nv[a];
     }
     if (P.dim >= 2) {
-        const int s2 = span_of(x0[1], P.nel[1]);
+        const int s2 = span_of(x0[1] / P.len[1], P.nel[1]);
         basis_values(P.ay0.U, p, s2 + p, x0[1], Nv, nullptr);
         for (int a = 0; a <= p; ++a) {
             const int i = s2 + a - 1;
@@ -66,7 +66,7 @@ void point_factors(const ProblemImpl& P, const double* x0, double* stage) {
     }
     if (P.dim == 3) {
         const int n3 = P.az0.n;
-        const int s3 = span_of(x0[2], P.nel[2]);
+        const int s3 = span_of(x0[2] / P.len[2], P.nel[2]);
         basis_values(P.az0.U, p, s3 + p, x0[2], Nv, nullptr);
         for (int a = 0; a <= p; ++a) {
             const int i = s3 + a - 1;
@@ -77,7 +77,7 @@ void point_factors(const ProblemImpl& P, const double* x0, double* stage) {
 
 void check_point(const ProblemImpl& P, const double* x0) {
     for (int d = 0; d < P.dim; ++d)
-        HH_REQUIRE(x0[d] >= 0.0 && x0[d] <= 1.0, "source point outside [0,1]^d");
+        HH_REQUIRE(x0[d] >= 0.0 && x0[d] <= P.len[d], "source point outside the domain");
 }
 
 void launch_point_source(const ProblemImpl& P, const double* stage_dev, double amp, cx<double>* f,

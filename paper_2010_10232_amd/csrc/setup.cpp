@@ -109,7 +109,7 @@ Axis make_trivial_axis() {
     return a;
 }
 
-Axis make_axis(int p, int nel_fine, int level, bool keep_last) {
+Axis make_axis(int p, int nel_fine, int level, bool keep_last, double len) {
     Axis a;
     a.p = p;
     a.level = level;
@@ -121,7 +121,7 @@ Axis make_axis(int p, int nel_fine, int level, bool keep_last) {
     std::vector<int> idx;
     for (int j = 0; j < a.nel; ++j) idx.push_back(j << level);
     idx.push_back(nel_fine);
-    for (int i : idx) a.bk.push_back(i / (double)nel_fine);
+    for (int i : idx) a.bk.push_back(len * (i / (double)nel_fine));
     for (int i = 0; i < p; ++i) a.U.push_back(a.bk.front());
     for (double v : a.bk) a.U.push_back(v);
     for (int i = 0; i < p; ++i) a.U.push_back(a.bk.back());
@@ -172,7 +172,7 @@ Axis make_axis(int p, int nel_fine, int level, bool keep_last) {
     a.G.assign((size_t)nel_fine * q * q, 0.0);
     for (int e = 0; e < nel_fine; ++e) {
         int E = e >> level;
-        double lo = e / (double)nel_fine, hi = (e + 1) / (double)nel_fine, jac = 0.5 * (hi - lo);
+        double lo = len * (e / (double)nel_fine), hi = len * ((e + 1) / (double)nel_fine), jac = 0.5 * (hi - lo);
         double* blk = &a.G[(size_t)e * q * q];
         for (int g = 0; g < q; ++g) {
             double x = lo + (gx[g] + 1.0) * jac;

@@ -12,6 +12,7 @@ namespace hh {
 
 struct ProblemImpl {
     int dim = 2, p = 3, nel[3] = {1, 1, 1};
+    double len[3] = {1.0, 1.0, 1.0};   // domain extent per direction
     int k_mode = 0;
     double k = 0.0;
     bool somm = false;        // radiation condition at x = 1 (1D, constant k; MP 1-A)

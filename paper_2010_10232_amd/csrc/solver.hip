@@ -49,6 +49,14 @@ ProblemImpl* build_problem(const hh_problem_desc* d) {
     P->nel[0] = nx;
     P->nel[1] = ny;
     P->nel[2] = nz;
+    for (int dd = 0; dd < 3; ++dd) {
+        const double L = d->length[dd];
+        if (!(std::isfinite(L) && L >= 0.0)) {
+            delete P;
+            throw Err{HH_EINVAL, "length must be finite and >= 0 (0: the unit extent)"};
+        }
+        P->len[dd] = (dd < d->dim && L > 0.0) ? L : 1.0;
+    }
     P->k_mode = d->k_mode;
     P->k = d->k;
     if (d->k_mode == 0) {
@@ -71,9 +79,9 @@ ProblemImpl* build_problem(const hh_problem_desc* d) {
             P->k2[i] = kv * kv;
         }
     }
-    P->ax0 = make_axis(P->p, nx, 0, P->somm);
-    P->ay0 = d->dim >= 2 ? make_axis(P->p, ny, 0) : make_trivial_axis();
-    P->az0 = d->dim == 3 ? make_axis(P->p, nz, 0) : make_trivial_axis();
+    P->ax0 = make_axis(P->p, nx, 0, P->somm, P->len[0]);
+    P->ay0 = d->dim >= 2 ? make_axis(P->p, ny, 0, false, P->len[1]) : make_trivial_axis();
+    P->az0 = d->dim == 3 ? make_axis(P->p, nz, 0, false, P->len[2]) : make_trivial_axis();
     return P;
 }
 
@@ -244,8 +252,8 @@ void SolverImpl::setup(hipStream_t s) {
     // multigrid levels by knot halving
     for (int l = 0;; ++l) {
         auto lv = std::make_unique<LevelDev>();
-        lv->ax = l == 0 ? P.ax0 : make_axis(p, P.nel[0], l, P.somm);
-        lv->ay = is2d ? (l == 0 ? P.ay0 : make_axis(p, P.nel[1], l)) : make_trivial_axis();
+        lv->ax = l == 0 ? P.ax0 : make_axis(p, P.nel[0], l, P.somm, P.len[0]);
+        lv->ay = is2d ? (l == 0 ? P.ay0 : make_axis(p, P.nel[1], l, false, P.len[1])) : make_trivial_axis();
         const int mx = std::max(lv->ax.nel, is2d ? lv->ay.nel : 0);
         HH_REQUIRE(lv->ax.n >= 1 && lv->ay.n >= 1, "level without interior unknowns");
         lev.push_back(std::move(lv));
@@ -867,9 +875,9 @@ void SolverImpl::setup_levels_3d(hipStream_t s) {
     const int p = P.p;
     for (int l = 0;; ++l) {
         auto lv = std::make_unique<LevelDev>();
-        lv->ax = l == 0 ? P.ax0 : make_axis(p, P.nel[0], l);
-        lv->ay = l == 0 ? P.ay0 : make_axis(p, P.nel[1], l);
-        lv->az = l == 0 ? P.az0 : make_axis(p, P.nel[2], l);
+        lv->ax = l == 0 ? P.ax0 : make_axis(p, P.nel[0], l, false, P.len[0]);
+        lv->ay = l == 0 ? P.ay0 : make_axis(p, P.nel[1], l, false, P.len[1]);
+        lv->az = l == 0 ? P.az0 : make_axis(p, P.nel[2], l, false, P.len[2]);
         HH_REQUIRE(lv->ax.n >= 1 && lv->ay.n >= 1 && lv->az.n >= 1, "level without interior unknowns");
         const int mx = std::max({lv->ax.nel, lv->ay.nel, lv->az.nel});
         lev.push_back(std::move(lv));
@@ -1066,7 +1074,7 @@ void SolverImpl::setup_finish(hipStream_t s) {
     if (P.dim <= 2) {   // the learned smoother's feature (2D and 1D)
         const LevelDev& l0 = *lev[0];
         std::vector<float> c((size_t)l0.N);
-        const double h2 = 1.0 / ((double)P.nel[0] * P.nel[0]);
+        const double hx = P.len[0] / P.nel[0], h2 = hx * hx;   // the x extent of an element
         for (int i2 = 0; i2 < l0.n2; ++i2)
             for (int i1 = 0; i1 < l0.n1; ++i1) {
                 const int e2 = std::min(i2, l0.ay.nel - 1), e1 = std::min(i1, l0.ax.nel - 1);

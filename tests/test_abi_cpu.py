@@ -96,6 +96,10 @@ _CSR_CASES = [
     dict(dim=2, p=3, n_el=12, k=9.0),
     dict(dim=2, p=2, n_el=9, rand=True),
     dict(dim=2, p=4, n_el=11, rand=True),
+    dict(dim=1, p=3, n_el=17, k=5.0, lengths=(2.5,)),
+    dict(dim=2, p=2, n_el=(9, 6), k=3.0, lengths=(2.0, 0.75)),
+    dict(dim=2, p=3, n_el=(8, 10), rand=True, lengths=(0.5, 1.5)),
+    dict(dim=3, p=2, n_el=(3, 4, 2), k=4.0, lengths=(1.5, 0.5, 2.0)),
     dict(dim=3, p=1, n_el=(4, 3, 5), k=2.0),
     dict(dim=3, p=2, n_el=(3, 4, 2), k=5.0),
     dict(dim=3, p=3, n_el=(4, 3, 3), k=3.0),
@@ -112,11 +116,11 @@ def test_export_csr_matches_oracle(c):
     ke = None
     if c.get("rand"):
         rng = np.random.default_rng(5)
-        shape = (c["n_el"],) * c["dim"]
+        shape = tuple(np.atleast_1d(c["n_el"])[::-1]) if not np.isscalar(c["n_el"]) else (c["n_el"],) * c["dim"]
         ke = 4.0 * (1.0 + 0.5 * rng.random(shape))
     k = c.get("k", 1.0)
-    gp = B.Problem(c["dim"], c["p"], c["n_el"], k=k, k_elem=ke)
-    op = hz.Problem(c["dim"], c["p"], c["n_el"], k, k_elem=ke)
+    gp = B.Problem(c["dim"], c["p"], c["n_el"], k=k, k_elem=ke, lengths=c.get("lengths"))
+    op = hz.Problem(c["dim"], c["p"], c["n_el"], k, k_elem=ke, lengths=c.get("lengths"))
     K, Mk = hz.fine_operators(op)
     for which, ref in ((0, K), (1, Mk), (2, (K - Mk))):
         ref = ref.tocsr()
@@ -140,3 +144,21 @@ def test_export_csr_capacity_checked():
     assert lib.hh_export_csr(gp._h, 0, ctypes.byref(nnz), ptr.ctypes.data, idx.ctypes.data, val.ctypes.data,
                              nnz.value - 1) < 0
     assert lib.hh_export_csr(gp._h, 3, ctypes.byref(nnz), None, None, None, 0) < 0
+
+
+
+@pytest.mark.parametrize("x0", [(0.0, 0.0), (2.0, 0.75), (1.3, 0.2), (0.999, 0.5), (1e-9, 0.7499999)])
+def test_point_spans_on_a_rectangle_bit_exact(x0):
+    pr = B.Problem(2, 3, (10, 7), k=4.0, lengths=(2.0, 0.75))
+    op = hz.Problem(2, 3, (10, 7), 4.0, lengths=(2.0, 0.75))
+    assert pr.spans(x0) == hz.source_spans(op, x0)
+
+
+def test_lengths_checked():
+    with pytest.raises(B.HHError):
+        B.Problem(2, 2, 8, k=1.0, lengths=(1.0, -2.0))
+    with pytest.raises(B.HHError):
+        B.Problem(2, 2, 8, k=1.0, lengths=(float("nan"), 1.0))
+    pr = B.Problem(2, 2, 8, k=1.0, lengths=(2.0, 0.5))
+    with pytest.raises(B.HHError):
+        pr.spans((1.0, 0.6))   # outside [0, 2] x [0, 0.5]
