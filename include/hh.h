@@ -2,7 +2,8 @@
  * hh.h - C ABI of the MI355X (gfx950) isogeometric Helmholtz solver.
  *
  * Solves A u = f for the B-spline Galerkin discretisation of
- *     -Lap u - k^2 u = f  on (0,1)^d, d = 1, 2 or 3, u = 0 on the boundary
+ *     -Lap u - k^2 u = f  on (0,1)^d, d = 1, 2 or 3 (or a box (0,L_1) x ... x (0,L_d)),
+ *     u = 0 on the boundary
  * (the model problems MP 1-B, MP 2-A and MP 2-B, section 2 of Dwarka, Tielen,
  * Moeller and Vuik, "Towards accuracy and scalability: combining isogeometric
  * analysis with deflation ...").  A = K - M_k with K the stiffness matrix and
