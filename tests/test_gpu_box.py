@@ -142,3 +142,24 @@ def test_box_mixed_precision_within_1e6():
     u, info = B.Solver(gp, precision=1, **opts).solve(gp.point_source(c["x0"]))
     assert info["converged"] == 1
     assert rel(to_host(u), u_ref) <= 1e-6
+
+
+def test_box_radiation_condition_on_a_longer_interval():
+    """MP 1-A on (0, 2): u(0) = 1, u' - i k u = 0 at x = 2; the lifted right-hand side and
+    the solve against the oracle, and the L2 error against e^{ikx} equal to the oracle's."""
+    from paper_2010_10232_amd import binding as B
+    p, n_el, k, L = 3, 120, 30.0, 2.0
+    op = hz.Problem(1, p, n_el, k, sommerfeld=True, lengths=(L,))
+    osol = osv.Solver(op, osv.Options(defl_direct_max=256, tol=1e-10))
+    f_ref = hz.dirichlet_lift_rhs(op)
+    gp = B.Problem(1, p, n_el, k=k, sommerfeld=True, lengths=(L,))
+    f = gp.dirichlet_lift(1.0)
+    assert np.max(np.abs(to_host(f) - f_ref)) <= 1e-13 * np.max(np.abs(f_ref))
+    u_ref, info_ref = osol.solve(f_ref)
+    u, info = B.Solver(gp, defl_direct_max=256, tol=1e-10).solve(f)
+    u = to_host(u)
+    assert info["converged"] == 1 and info["iters"] == info_ref.iters
+    assert rel(u, u_ref) <= 1e-10
+    exact = lambda x: np.exp(1j * k * x)
+    e_gpu, e_ref = hz.l2_error_1d(op, u, exact), hz.l2_error_1d(op, u_ref, exact)
+    assert abs(e_gpu - e_ref) <= 1e-6 * e_ref and e_ref < 1e-3
