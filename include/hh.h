@@ -314,10 +314,10 @@ hh_status hh_export_csr(const hh_problem* pr, int which, long long* nnz, long lo
  * E = My (x) Kx + Ky (x) Mx - k^2 My (x) Mx is diagonalised by the generalised
  * eigenvectors of the two 1D pencils (K, M) (fast diagonalisation: four small
  * dense passes per solve, no N_z x N_z matrix); for variable k, a dense inverse
- * (LU).  HH_ENUMERIC if E is singular.  3D problems: multigrid with two-level
- * deflation or none (defl_mode 0 or 1; HH_EINVAL for 2), E diagonalised by the
- * three 1D pencils (six dense passes), no coarse one-workgroup tail, and neither
- * the ADP vectors, C_ex nor a learned smoother.  The solver keeps a reference to
+ * (LU).  HH_ENUMERIC if E is singular.  3D problems: multigrid with two-level,
+ * multilevel or no deflation, E diagonalised by the three 1D pencils (six dense
+ * passes), no coarse one-workgroup tail, and neither the ADP vectors, C_ex nor a
+ * learned smoother.  The solver keeps a reference to
  * the problem, which must outlive it. */
 hh_status hh_setup(const hh_problem* pr, const hh_solver_opts* o, void* stream,
                    hh_solver** out);

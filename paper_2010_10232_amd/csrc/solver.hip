@@ -864,12 +864,12 @@ void SolverImpl::setup(hipStream_t s) {
 
 // Unit cube (constant k, Dirichlet): the multigrid levels by knot halving in
 // all three directions, their transfers P_z (x) P_y (x) P_x, Jacobi diagonals
-// and damping, the dense inverse of the coarsest M_beta, and the two-level
-// deflation matrix E = A_1 by fast diagonalisation (the three 1D pencils).
+// and damping, the dense inverse of the coarsest M_beta, and the deflation
+// matrix E = A_Lz of the direct deflation level by fast diagonalisation (the
+// three 1D pencils); the levels between 1 and Lz - 1 get inner FGMRES solves.
 void SolverImpl::setup_levels_3d(hipStream_t s) {
     const ProblemImpl& P = *prob;
     HH_REQUIRE(P.k_mode == 0, "3D problems are built for constant k");
-    HH_REQUIRE(o.defl_mode == 0 || o.defl_mode == 1, "3D problems take defl_mode 0 or 1 (two-level deflation)");
     HH_REQUIRE(o.precond == 0 && o.defl_z == 0,
                "3D problems are built with the knot-insertion deflation and the multigrid CSLP");
     const int p = P.p;
@@ -1006,7 +1006,31 @@ void SolverImpl::setup_levels_3d(hipStream_t s) {
         upload(Minv64, m64);
         upload(Minv32, m32);
     }
-    Lz = (o.defl_mode == 1 && L >= 1) ? 1 : 0;
+    // deflation levels as in 2D: two-level (level 1), or multilevel with the first level
+    // of at most defl_direct_max unknowns solved directly, not coarser than the last
+    // level that still resolves the waves (k h_l <= defl_kh_max)
+    Lz = (o.defl_mode >= 1 && L >= 1) ? 1 : 0;
+    if (o.defl_mode == 2 && L >= 1) {
+        Lz = L;
+        for (int l = 1; l <= L; ++l)
+            if (lev[l]->N <= o.defl_direct_max) {
+                Lz = l;
+                break;
+            }
+        if (o.defl_kh_max > 0.0) {
+            auto hmax = [](const Axis& a) {
+                double h = 0.0;
+                for (size_t i = 0; i + 1 < a.bk.size(); ++i) h = std::max(h, a.bk[i + 1] - a.bk[i]);
+                return h;
+            };
+            int lkh = 1;
+            for (int l = 1; l <= L; ++l) {
+                const double h = std::max({hmax(lev[l]->ax), hmax(lev[l]->ay), hmax(lev[l]->az)});
+                if (P.k * h <= o.defl_kh_max) lkh = l;
+            }
+            Lz = std::min(Lz, lkh);
+        }
+    }
     if (Lz > 0) {
         const LevelDev& lz = *lev[Lz];
         nZ = (int)lz.N;

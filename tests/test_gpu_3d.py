@@ -49,6 +49,9 @@ CASES = {
     "3d_p1_nodefl": dict(p=1, n_el=(20, 22, 18), k=8.0, x0=(0.3, 0.7, 0.6), opts=dict(defl_mode=0, mg_min_elems=5)),
     "3d_p4_small": dict(p=4, n_el=(10, 9, 12), k=6.0, x0=(0.2, 0.5, 0.9), opts=dict(defl_mode=1, mg_min_elems=3)),
     "3d_p5_small": dict(p=5, n_el=(8, 10, 9), k=5.0, x0=(0.6, 0.35, 0.5), opts=dict(defl_mode=1, mg_min_elems=3)),
+    # multilevel deflation: inner FGMRES on level 1 (1,680 unknowns), E^-1 on level 2
+    "3d_p2_multi": dict(p=2, n_el=(24, 20, 28), k=10.0, x0=(0.4, 0.55, 0.3),
+                        opts=dict(defl_direct_max=500, defl_kh_max=0, mg_min_elems=3)),
 }
 
 _cache = {}
@@ -133,10 +136,10 @@ def test_3d_vcycle_einv_and_preconditioner(name):
     _say(f"[3d case {name}] V-cycle level 0")
     e = rel(to_host(gs.apply("VCYCLE", 0, xd)), osol.vcycle(0, x))
     assert e <= 1e-11, e
-    if osol.Lz:
-        x1 = rvec(osol.levels[1].N, 31)
-        _say(f"[3d case {name}] E^-1 at level 1 (fast diagonalisation)")
-        e = rel(to_host(gs.apply("EINV", 1, to_dev(x1))), osol.coarse_solve(1, x1))
+    for l in range(1, osol.Lz + 1):
+        xl = rvec(osol.levels[l].N, 30 + l)
+        _say(f"[3d case {name}] E^-1 at deflation level {l} (inner FGMRES or fast diagonalisation)")
+        e = rel(to_host(gs.apply("EINV", l, to_dev(xl))), osol.coarse_solve(l, xl))
         assert e <= 1e-10, e
     _say(f"[3d case {name}] T level 0")
     e = rel(to_host(gs.apply("T", 0, xd)), osol.T(0, x))
@@ -145,7 +148,7 @@ def test_3d_vcycle_einv_and_preconditioner(name):
 
 # degrees 4 and 5 need hundreds of steps on the cube (the Gershgorin-damped Jacobi
 # smoother weakens with p): their parity is held on the building blocks above
-SOLVE_CASES = ["3d_p2_aniso", "3d_p3_cube", "3d_p1_nodefl"]
+SOLVE_CASES = ["3d_p2_aniso", "3d_p3_cube", "3d_p1_nodefl", "3d_p2_multi"]
 
 
 def oracle_sensitivity(osol, f, u_ref, delta=1e-13):
@@ -222,7 +225,7 @@ def test_3d_graphs_and_rejections():
     for _ in range(2):
         u1, i1 = gs.solve(f)
         assert i1["iters"] == i0["iters"] and torch.equal(u1, u0)
-    for bad in (dict(defl_mode=2), dict(defl_mode=1, precond=1), dict(defl_mode=1, defl_z=1)):
+    for bad in (dict(defl_mode=1, precond=1), dict(defl_mode=1, defl_z=1)):
         with pytest.raises(B.HHError):
             B.Solver(gp, **bad)
 
