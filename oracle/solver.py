@@ -242,12 +242,12 @@ def adp_deflation_1d(nf, eps=0.0):
 
 
 def adp_deflation(prob_n, dim, eps=0.0):
-    """ADP deflation matrix of the finest level: Z_x (1D) or Z_y (x) Z_x (2D,
-    x fastest), prob_n the interior unknowns per direction."""
-    Zx = adp_deflation_1d(prob_n[0], eps)
-    if dim == 1:
-        return Zx
-    return sp.kron(adp_deflation_1d(prob_n[1], eps), Zx).tocsr()
+    """ADP deflation matrix of the finest level: Z_x (1D), Z_y (x) Z_x (2D) or
+    Z_z (x) Z_y (x) Z_x (3D), x fastest, prob_n the interior unknowns per direction."""
+    Z = adp_deflation_1d(prob_n[0], eps)
+    for d in range(1, dim):
+        Z = sp.kron(adp_deflation_1d(prob_n[d], eps), Z)
+    return sp.csr_matrix(Z)
 
 
 # Deflation matrices up to this many unknowns are factored densely; larger ones
@@ -288,8 +288,8 @@ class Solver:
         self.Lz = deflation_levels(self.levels, self.opts, kmax)
         self.Zadp = None
         self.Mex_lu = None
-        if prob.dim == 3 and (self.opts.precond != 0 or self.opts.defl_z != 0 or cnn_params is not None):
-            raise ValueError("the unit cube is built with the knot-insertion deflation and the multigrid CSLP")
+        if prob.dim == 3 and (self.opts.precond != 0 or cnn_params is not None):
+            raise ValueError("the unit cube is built with the multigrid CSLP (no C_ex, no learned smoother)")
         if self.opts.precond == 1:
             if prob.k_elem is not None:
                 raise ValueError("C_ex is built for constant k only")

@@ -135,8 +135,7 @@ def test_3d_rejects_variable_k_and_other_preconditioners():
     prob = hz.Problem(3, 2, 4, 2.0)
     with pytest.raises(ValueError):
         osv.Solver(prob, osv.Options(precond=1))
-    with pytest.raises(ValueError):
-        osv.Solver(prob, osv.Options(defl_mode=1, defl_z=1))
+
 
 
 @pytest.mark.parametrize("p,n_el,k", [(2, (20, 8, 10), 6.0), (3, 12, 6.0)])
@@ -158,3 +157,28 @@ def test_3d_finest_level_damping_keeps_the_vcycle_contracting(p, n_el, k):
             x = x - s.vcycle(0, lv.Mb @ x)
         growth[om] = np.linalg.norm(x) / np.linalg.norm(x1)
     assert growth[0.8] > 1.0 and growth[lv.omega] < 0.5, growth
+
+
+
+def test_3d_adp_vectors_are_the_tensor_product_and_deflate():
+    """ADP on the cube: Z = Z_z (x) Z_y (x) Z_x with x fastest (each column the product of three
+    1D columns), and the deflation identities P_D A Z = 0, Q A Z = Z hold."""
+    prob = hz.Problem(3, 3, (10, 8, 12), 6.0)
+    n = [m + 1 for m in prob.n_el]
+    Z = osv.adp_deflation(n, 3, 0.2).toarray()
+    Zs = [osv.adp_deflation_1d(m, 0.2).toarray() for m in n]
+    nc = [z.shape[1] for z in Zs]
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        J = [int(rng.integers(0, c)) for c in nc]
+        col = Z[:, (J[2] * nc[1] + J[1]) * nc[0] + J[0]].reshape(n[2], n[1], n[0])
+        ref = np.einsum("k,j,i->kji", Zs[2][:, J[2]], Zs[1][:, J[1]], Zs[0][:, J[0]])
+        assert np.array_equal(col, ref)
+    s = osv.Solver(prob, osv.Options(defl_mode=1, defl_z=1, defl_eps=0.2, mg_min_elems=3))
+    A = s.levels[0].A
+    AZ = (A @ s.Zadp).toarray()
+    E = s.Eadp.toarray()
+    Q_AZ = s.Zadp @ np.linalg.solve(E, s.Zadp.T @ AZ)
+    assert np.abs(Q_AZ - s.Zadp.toarray()).max() <= 1e-9
+    PAZ = AZ - A @ Q_AZ
+    assert np.abs(PAZ).max() <= 1e-9 * np.abs(AZ).max()
