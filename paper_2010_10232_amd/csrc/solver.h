@@ -92,6 +92,7 @@ struct SolverImpl {
     bool zadp = false;
     Transfer ztr{};
     DevBuf zprow0x, zprowx, zpcol0x, zpcolx, zprow0y, zprowy, zpcol0y, zpcoly;
+    DevBuf zprow0z, zprowz, zpcol0z, zpcolz, ztra64, ztrb64;   // unit cube
     // C_ex (precond = 1): exact inverse of K - (1 + i beta2) M_k on the finest
     // level by fast diagonalisation (eigenvectors of level 0, complex 1 / D)
     bool cex = false;

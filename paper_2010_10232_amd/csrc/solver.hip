@@ -870,8 +870,7 @@ void SolverImpl::setup(hipStream_t s) {
 void SolverImpl::setup_levels_3d(hipStream_t s) {
     const ProblemImpl& P = *prob;
     HH_REQUIRE(P.k_mode == 0, "3D problems are built for constant k");
-    HH_REQUIRE(o.precond == 0 && o.defl_z == 0,
-               "3D problems are built with the knot-insertion deflation and the multigrid CSLP");
+    HH_REQUIRE(o.precond == 0, "3D problems are built with the multigrid CSLP (no C_ex)");
     const int p = P.p;
     for (int l = 0;; ++l) {
         auto lv = std::make_unique<LevelDev>();
@@ -1030,6 +1029,72 @@ void SolverImpl::setup_levels_3d(hipStream_t s) {
             }
             Lz = std::min(Lz, lkh);
         }
+    }
+    // ADP deflation vectors (two-level): Z = Z_z (x) Z_y (x) Z_x from level 0 to a
+    // deflation level of its own, lev[L + 1]
+    zadp = o.defl_z == 1;
+    if (zadp) {
+        auto lz = std::make_unique<LevelDev>();
+        const LevelDev& l0 = *lev[0];
+        Axis zf[3];
+        make_adp(l0.ax, o.defl_eps, zf[0], lz->ax);
+        make_adp(l0.ay, o.defl_eps, zf[1], lz->ay);
+        make_adp(l0.az, o.defl_eps, zf[2], lz->az);
+        lz->n1 = lz->ax.n;
+        lz->n2 = lz->ay.n;
+        lz->n3 = lz->az.n;
+        lz->N = (long long)lz->n1 * lz->n2 * lz->n3;
+        lz->kind = KIND_SEP;
+        upload(lz->Kx, lz->ax.Kb);
+        upload(lz->Mx, lz->ax.Mb);
+        upload(lz->Ky, lz->ay.Kb);
+        upload(lz->My, lz->ay.Mb);
+        upload(lz->Kz, lz->az.Kb);
+        upload(lz->Mz, lz->az.Mb);
+        upload(zprow0x, zf[0].prow0);
+        upload(zprowx, zf[0].prow);
+        upload(zpcol0x, zf[0].pcol0);
+        upload(zpcolx, zf[0].pcol);
+        upload(zprow0y, zf[1].prow0);
+        upload(zprowy, zf[1].prow);
+        upload(zpcol0y, zf[1].pcol0);
+        upload(zpcoly, zf[1].pcol);
+        upload(zprow0z, zf[2].prow0);
+        upload(zprowz, zf[2].prow);
+        upload(zpcol0z, zf[2].pcol0);
+        upload(zpcolz, zf[2].pcol);
+        Transfer& t = ztr;
+        t.nf1 = l0.n1;
+        t.nf2 = l0.n2;
+        t.nf3 = l0.n3;
+        t.nc1 = lz->n1;
+        t.nc2 = lz->n2;
+        t.nc3 = lz->n3;
+        t.pw1 = zf[0].pw;
+        t.pw2 = zf[1].pw;
+        t.pw3 = zf[2].pw;
+        t.rw1 = zf[0].rw;
+        t.rw2 = zf[1].rw;
+        t.rw3 = zf[2].rw;
+        t.prow0x = zprow0x.as<int>();
+        t.prowx = zprowx.as<double>();
+        t.prow0y = zprow0y.as<int>();
+        t.prowy = zprowy.as<double>();
+        t.prow0z = zprow0z.as<int>();
+        t.prowz = zprowz.as<double>();
+        t.pcol0x = zpcol0x.as<int>();
+        t.pcolx = zpcolx.as<double>();
+        t.pcol0y = zpcol0y.as<int>();
+        t.pcoly = zpcoly.as<double>();
+        t.pcol0z = zpcol0z.as<int>();
+        t.pcolz = zpcolz.as<double>();
+        // the deflation passes run in FP64 only (no FP32 intermediate grids)
+        ztra64.alloc((size_t)l0.n3 * l0.n2 * lz->n1 * sizeof(cx<double>));
+        ztrb64.alloc((size_t)l0.n3 * lz->n2 * lz->n1 * sizeof(cx<double>));
+        t.tmpa64 = ztra64.as<cx<double>>();
+        t.tmpb64 = ztrb64.as<cx<double>>();
+        lev.push_back(std::move(lz));
+        Lz = L + 1;
     }
     if (Lz > 0) {
         const LevelDev& lz = *lev[Lz];

@@ -225,7 +225,7 @@ def test_3d_graphs_and_rejections():
     for _ in range(2):
         u1, i1 = gs.solve(f)
         assert i1["iters"] == i0["iters"] and torch.equal(u1, u0)
-    for bad in (dict(defl_mode=1, precond=1), dict(defl_mode=1, defl_z=1)):
+    for bad in (dict(defl_mode=1, precond=1), dict(defl_mode=2, defl_z=1)):
         with pytest.raises(B.HHError):
             B.Solver(gp, **bad)
 
@@ -325,3 +325,39 @@ def test_3d_full_size_sampled_rows_and_solve():
     um, im = B.Solver(gp, defl_mode=1, mg_min_elems=4, precision=1, tol=1e-10, maxit=400).solve(f)
     assert im["converged"] == 1
     assert (torch.linalg.norm(um - u) / torch.linalg.norm(u)).item() <= 1e-6
+
+
+@pytest.mark.parametrize("p,n_el,eps", [(3, (16, 12, 14), 0.2), (2, (12, 18, 10), 0.0)])
+def test_3d_adp_deflation(p, n_el, eps):
+    """The ADP vectors on the cube (Z = Z_z (x) Z_y (x) Z_x, a deflation level of its own):
+    Z^T and Z element-wise, E = Z^T A Z, E^-1 (fast diagonalisation), T and the solve against
+    the oracle (equal iterations; bar as for the other solves)."""
+    from paper_2010_10232_amd import binding as B
+    k, x0 = 8.0, (0.45, 0.6, 0.35)
+    opts = dict(defl_mode=1, defl_z=1, defl_eps=eps, mg_min_elems=3)
+    op = hz.Problem(3, p, n_el, k)
+    osol = osv.Solver(op, osv.Options(**opts))
+    gp = B.Problem(3, p, n_el, k=k)
+    gs = B.Solver(gp, **opts)
+    lz = gs.levels[0]["defl_direct_level"]
+    assert lz == len(gs.levels) == len(osol.levels)
+    Z = osol.Zadp
+    info = gs.level_info(lz)
+    assert info["N"] == Z.shape[1] and info["n"] == tuple(m // 2 for m in osol.levels[0].n)
+    x, xc = rvec(Z.shape[0], 5), rvec(Z.shape[1], 6)
+    _say(f"[3d adp p={p}] Z^T / Z / E / E^-1 / T")
+    for got, ref in ((to_host(gs.apply("ZT", 0, to_dev(x), out_level=lz)), Z.T @ x),
+                     (to_host(gs.apply("Z", 0, to_dev(xc))), Z @ xc)):
+        assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+    assert rel(to_host(gs.apply("A", lz, to_dev(xc))), osol.Eadp @ xc) <= 1e-13
+    assert rel(to_host(gs.apply("EINV", lz, to_dev(xc))), osol.E_lu(xc)) <= 1e-10
+    assert rel(to_host(gs.apply("T", 0, to_dev(x))), osol.T(0, x)) <= 1e-10
+    f = hz.point_source_rhs(op, x0)
+    u_ref, info_ref = osol.solve(f, history=True)
+    sens, _ = oracle_sensitivity(osol, f, u_ref)
+    bar = max(1e-10, 3.0 * sens)
+    u, inf = gs.solve(to_dev(f))
+    u = to_host(u)
+    _say(f"[3d adp p={p}] iters {inf['iters']} / {info_ref.iters}, rel diff {rel(u, u_ref):.2e}, bar {bar:.1e}")
+    assert inf["converged"] == 1 and inf["iters"] == info_ref.iters
+    assert rel(u, u_ref) <= bar
