@@ -415,23 +415,55 @@ __global__ __launch_bounds__(256) void op_stencil_kernel(OpArgs<T> a) {
     T c[BY * BX];
 #pragma unroll
     for (int q = 0; q < BY * BX; ++q) c[q] = a.S[(size_t)q * N + I];
-    // stage x (tile + halo) and the bands
-    for (int e = threadIdx.x; e < LH * LW; e += 256) {
+    // then x of the tile and its halo, the bands and the epilogue's operands, all
+    // loaded into registers before the first LDS store, so that the workgroup
+    // waits for memory once rather than once per staging step
+    constexpr int XPT = (LH * LW + 255) / 256, DPW = (BX + 3) / 4;
+    cx<T> xv[XPT];
+#pragma unroll
+    for (int r = 0; r < XPT; ++r) {
+        const int e = threadIdx.x + 256 * r;
         const int rr = e / LW, cc = e % LW;
         const int J2 = R0 - PY + rr, J1 = C0 - PX + cc;
-        xs[rr][cc] = (J2 >= 0 && J2 < n2 && J1 >= 0 && J1 < n1) ? a.x[(size_t)J2 * n1 + J1] : cx<T>{T(0), T(0)};
+        xv[r] = (e < LH * LW && J2 >= 0 && J2 < n2 && J1 >= 0 && J1 < n1) ? a.x[(size_t)J2 * n1 + J1]
+                                                                           : cx<T>{T(0), T(0)};
     }
+    T kxv[DPW], mxv[DPW], kyv = 0, myv = 0;
     {
         const int I1c = I1 < n1 ? I1 : n1 - 1;
-        for (int d = w; d < BX; d += 4) {
-            kxS[d][lane] = (T)a.Kx[(size_t)I1c * BX + d];
-            mxS[d][lane] = (T)a.Mx[(size_t)I1c * BX + d];
+#pragma unroll
+        for (int r = 0; r < DPW; ++r) {
+            const int d = w + 4 * r;
+            kxv[r] = d < BX ? (T)a.Kx[(size_t)I1c * BX + d] : T(0);
+            mxv[r] = d < BX ? (T)a.Mx[(size_t)I1c * BX + d] : T(0);
         }
         if (lane < BY) {
             const int I2c = I2 < n2 ? I2 : n2 - 1;
-            kyS[w][lane] = (T)a.Ky[(size_t)I2c * BY + lane];
-            myS[w][lane] = (T)a.My[(size_t)I2c * BY + lane];
+            kyv = (T)a.Ky[(size_t)I2c * BY + lane];
+            myv = (T)a.My[(size_t)I2c * BY + lane];
         }
+    }
+    cx<T> bv{T(0), T(0)}, dv{T(0), T(0)};
+    if (MODE != MODE_APPLY && active) {
+        bv = a.b[I];
+        if (MODE == MODE_SMOOTH || a.xo) dv = a.dinv[I];
+    }
+#pragma unroll
+    for (int r = 0; r < XPT; ++r) {
+        const int e = threadIdx.x + 256 * r;
+        if (e < LH * LW) xs[e / LW][e % LW] = xv[r];
+    }
+#pragma unroll
+    for (int r = 0; r < DPW; ++r) {
+        const int d = w + 4 * r;
+        if (d < BX) {
+            kxS[d][lane] = kxv[r];
+            mxS[d][lane] = mxv[r];
+        }
+    }
+    if (lane < BY) {
+        kyS[w][lane] = kyv;
+        myS[w][lane] = myv;
     }
     __syncthreads();
     if (!active) return;
@@ -461,14 +493,13 @@ __global__ __launch_bounds__(256) void op_stencil_kernel(OpArgs<T> a) {
     if (MODE == MODE_APPLY) {
         out = {yr, yi};
     } else {
-        const cx<T> bv = a.b[I];
         const T rr = bv.re - yr, ri = bv.im - yi;
         if (MODE == MODE_RESID) {
             out = {rr, ri};
-            if (a.xo) a.xo[I] = first_sweep(a, I, out);
+            if (a.xo) a.xo[I] = {a.omega * (dv.re * rr - dv.im * ri), a.omega * (dv.re * ri + dv.im * rr)};
         } else {
-            const cx<T> dv = a.dinv[I], xv = xs[w + PY][lane + PX];
-            out = {xv.re + a.omega * (dv.re * rr - dv.im * ri), xv.im + a.omega * (dv.re * ri + dv.im * rr)};
+            const cx<T> x0 = xs[w + PY][lane + PX];
+            out = {x0.re + a.omega * (dv.re * rr - dv.im * ri), x0.im + a.omega * (dv.re * ri + dv.im * rr)};
             if (a.yadd) {
                 const cx<T> q = a.yadd[I];
                 out = {out.re + q.re, out.im + q.im};
