@@ -176,3 +176,17 @@ def test_bench_and_full_size_references_share_the_workload_options():
     bench = _bench_module()
     for name in ("grf_k300_p4_960", "wedge_k150_p2_480", "wedge_k150_p3_480", "wedge_k150_p4_480"):
         assert bench.WORKLOADS[name]["opts"] == MF.WORKLOADS[name]["opts"], name
+
+
+def test_committed_traffic_summaries_match_the_current_sources():
+    """Every HBM-traffic summary under profiles/ was taken on the sources it names:
+    read_summary hands its figure to the bench only while their hash is unchanged,
+    so a kernel edit without new counter runs shows up here rather than as a silent
+    null in the bench line."""
+    import glob
+    paths = sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md")))
+    assert paths
+    for path in paths:
+        got = profiling.read_summary(path)
+        assert got is not None, os.path.basename(path)
+        assert got[0] > 0 and got[1]
