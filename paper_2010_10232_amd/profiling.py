@@ -153,6 +153,43 @@ def stats_from_trace(trace_csv, after, exclude=None):
     return rows
 
 
+def grid_rows(trace_csv, after, kernel):
+    """Launch durations of the kernels matching `kernel`, split by launch shape
+    (one row per kernel name and grid: the levels of a multilevel solve), over the
+    dispatches after the last one matching `after`; largest grid first."""
+    with open(trace_csv) as fh:
+        tr = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
+    pat, kpat = re.compile(after), re.compile(kernel)
+    last = max((i for i, r in enumerate(tr) if pat.search(r["Kernel_Name"])), default=-1)
+    per = {}
+    for r in tr[last + 1:]:
+        if not kpat.search(r["Kernel_Name"]):
+            continue
+        wg = max(1, int(r["Workgroup_Size_X"]) * int(r.get("Workgroup_Size_Y") or 1) * int(r.get("Workgroup_Size_Z") or 1))
+        grid = int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y") or 1) * int(r.get("Grid_Size_Z") or 1)
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        per.setdefault((r["Kernel_Name"], grid // wg, wg), []).append(d)
+    rows = []
+    for (name, wgs, wg), v in per.items():
+        v.sort()
+        rows.append({"name": name, "workgroups": wgs, "wg_size": wg, "calls": len(v), "avg_us": sum(v) / len(v),
+                     "median_us": v[len(v) // 2], "min_us": v[0], "max_us": v[-1]})
+    rows.sort(key=lambda r: (-r["workgroups"], r["name"]))
+    return rows
+
+
+def write_grid_table(rows, title, command, out):
+    lines = [f"# {title}", "", "Command (repository root on the GPU host):", "", "```", command, "```", "",
+             "| kernel | workgroups | threads each | calls | avg us | median us | min us | max us |",
+             "|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        name = _demangle(r["name"]).replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        lines.append(f"| `{name}` | {r['workgroups']} | {r['wg_size']} | {r['calls']} | {r['avg_us']:.2f} | "
+                     f"{r['median_us']:.2f} | {r['min_us']:.2f} | {r['max_us']:.2f} |")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def _demangle(name):
     """Readable form of a mangled kernel name: c++filt when installed and able,
     else the nested name of `_ZN<len><id>...` with `<...>` for template arguments."""
@@ -209,6 +246,8 @@ def main():
     ap.add_argument("--trace", help="rocprofv3 kernel_trace.csv: write a kernel table of the dispatches after --after")
     ap.add_argument("--after", help="regular expression: the table starts after its last dispatch")
     ap.add_argument("--exclude", help="regular expression: kernels left out of the --trace table")
+    ap.add_argument("--per-grid", action="store_true",
+                    help="with --trace and --kernel: one row per launch shape of the matching kernels")
     ap.add_argument("--title")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
@@ -222,6 +261,10 @@ def main():
     a = ap.parse_args()
     if a.stats:
         write_stats(a.stats, a.title or "Kernel statistics", a.command, a.out)
+        return
+    if a.trace and a.per_grid:
+        write_grid_table(grid_rows(a.trace, a.after or "^$", a.kernel or "."), a.title or "Launches by shape",
+                         a.command, a.out)
         return
     if a.trace:
         write_stats(None, a.title or "Kernel statistics", a.command, a.out,

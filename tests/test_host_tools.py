@@ -190,3 +190,30 @@ def test_committed_traffic_summaries_match_the_current_sources():
         got = profiling.read_summary(path)
         assert got is not None, os.path.basename(path)
         assert got[0] > 0 and got[1]
+
+
+def test_kernel_launches_by_shape(tmp_path):
+    """--per-grid: one row per kernel and launch shape, only after the phase marker."""
+    p = tmp_path / "trace.csv"
+    fields = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Workgroup_Size_X", "Workgroup_Size_Y",
+              "Workgroup_Size_Z", "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z"]
+    rows = [("hh::k(int)", 0, 100, 256, 2560), ("setup_end", 200, 210, 64, 64)]
+    t = 1000
+    for grid, dur in ((2560, 3000), (2560, 5000), (2560, 4000), (512, 700), (2560, 9000)):
+        rows.append(("hh::k(int)", t, t + dur, 256, grid))
+        t += 10000
+    rows.append(("hh::other(int)", t, t + 50, 256, 256))
+    with open(p, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=fields)
+        w.writeheader()
+        for name, s, e, wg, grid in rows:
+            w.writerow({"Kernel_Name": name, "Start_Timestamp": s, "End_Timestamp": e, "Workgroup_Size_X": wg,
+                        "Workgroup_Size_Y": 1, "Workgroup_Size_Z": 1, "Grid_Size_X": grid, "Grid_Size_Y": 1,
+                        "Grid_Size_Z": 1})
+    got = profiling.grid_rows(str(p), "setup_end", r"hh::k\(")
+    assert [(r["workgroups"], r["calls"]) for r in got] == [(10, 4), (2, 1)]
+    assert got[0]["avg_us"] == 5.25 and got[0]["median_us"] == 5.0
+    assert got[0]["min_us"] == 3.0 and got[0]["max_us"] == 9.0 and got[1]["avg_us"] == 0.7
+    out = tmp_path / "g.md"
+    profiling.write_grid_table(got, "T", "cmd", str(out))
+    assert "| `hh::k` | 10 | 256 | 4 | 5.25 | 5.00 | 3.00 | 9.00 |" in out.read_text()
