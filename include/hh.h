@@ -149,8 +149,9 @@ typedef struct {
                                 each direction nc = nf / 2 coarse unknowns, coarse c (0-based)
                                 at fine 2c + 1 with weights (1, 6 - defl_eps, 1) / 8 there
                                 (quadratic rational Bezier curve) and (1, 1) / 2 on the fine
-                                unknowns between; 2D: Z_y (x) Z_x.  E = Z^T A Z (a band of
-                                half-width (p + 4) / 2 per direction) is solved exactly.
+                                unknowns between; 2D: Z_y (x) Z_x, 3D: Z_z (x) Z_y (x) Z_x.
+                                E = Z^T A Z (a band of half-width (p + 4) / 2 per direction)
+                                is solved exactly.
                                 Two-level only: defl_mode must be 1 (HH_EINVAL otherwise). */
     double defl_eps;         /* the ADP weight parameter epsilon (section 3); default 0.  The
                                 paper takes its value from an earlier work without printing it. */
@@ -316,8 +317,8 @@ hh_status hh_export_csr(const hh_problem* pr, int which, long long* nnz, long lo
  * dense passes per solve, no N_z x N_z matrix); for variable k, a dense inverse
  * (LU).  HH_ENUMERIC if E is singular.  3D problems: multigrid with two-level,
  * multilevel or no deflation, E diagonalised by the three 1D pencils (six dense
- * passes), no coarse one-workgroup tail, and neither the ADP vectors, C_ex nor a
- * learned smoother.  The solver keeps a reference to
+ * passes; with the ADP vectors the pencils of their Galerkin bands), no coarse
+ * one-workgroup tail, and neither C_ex nor a learned smoother.  The solver keeps a reference to
  * the problem, which must outlive it. */
 hh_status hh_setup(const hh_problem* pr, const hh_solver_opts* o, void* stream,
                    hh_solver** out);
