@@ -90,6 +90,10 @@ WORKLOADS = {
     # family on 32^3 elements (k = 20, the same k h)
     "cube_k80_p3_128": dict(dim=3, p=3, n_el=128, k=80.0, x0=(0.5, 0.5, 0.5),
                             opts=dict(defl_mode=1, mg_min_elems=4), cpu_sample_n_el=32),
+    # the same cube with the ADP vectors (two-level, section 3 carried to three directions:
+    # 64^3 = 262,144 unknowns on the ADP level, E^-1 by fast diagonalisation of its Galerkin bands)
+    "cube_k80_p3_128_adp": dict(dim=3, p=3, n_el=128, k=80.0, x0=(0.5, 0.5, 0.5),
+                                opts=dict(defl_mode=1, defl_z=1, mg_min_elems=4), cpu_sample_n_el=32),
     # 64 independent constant-k problems, k ~ U[50, 400], n_el = ceil(k / 0.625),
     # p ~ U{2, 3, 4}, random interior sources; FP32 V-cycle, FP64 Krylov and deflation
     "batch64_k50_400": dict(batch=64, seed=0, opts=dict(precision=1, maxit=400)),
