@@ -361,3 +361,61 @@ def test_3d_adp_deflation(p, n_el, eps):
     _say(f"[3d adp p={p}] iters {inf['iters']} / {info_ref.iters}, rel diff {rel(u, u_ref):.2e}, bar {bar:.1e}")
     assert inf["converged"] == 1 and inf["iters"] == info_ref.iters
     assert rel(u, u_ref) <= bar
+
+
+def test_3d_adp_full_size_sampled_entries_and_solve():
+    """The bench's ADP cube (128^3 elements, p = 3, k = 80; 64^3 unknowns on the ADP level) at
+    full size: Z^T x and Z c on 2000 sampled entries each (corners, faces and random ones) against
+    sums over the oracle's 1D ADP columns (the tensor-product rule its 3D pin fixes); at tol
+    1e-10 the FP64 solve converges with its true residual recomputed here."""
+    import torch
+    from paper_2010_10232_amd import binding as B
+    p, ne, k = 3, 128, 80.0
+    opts = dict(defl_mode=1, defl_z=1, mg_min_elems=4)
+    gp = B.Problem(3, p, ne, k=k)
+    gs = B.Solver(gp, **opts)
+    n = ne + p - 2
+    Z1 = osv.adp_deflation_1d(n, 0.0).tocsc()
+    nc = Z1.shape[1]
+    lz = gs.levels[0]["defl_direct_level"]
+    assert gs.level_info(lz)["n"] == (nc, nc, nc)
+    cols = [(Z1.indices[Z1.indptr[j]:Z1.indptr[j + 1]], Z1.data[Z1.indptr[j]:Z1.indptr[j + 1]]) for j in range(nc)]
+    Zr = Z1.tocsr()
+    rows = [(Zr.indices[Zr.indptr[i]:Zr.indptr[i + 1]], Zr.data[Zr.indptr[i]:Zr.indptr[i + 1]]) for i in range(n)]
+    rng = np.random.default_rng(29)
+    x = rvec(gp.N, 31)
+    X = x.reshape(n, n, n)
+    _say("[3d adp full size] Z^T sampled entries")
+    y = to_host(gs.apply("ZT", 0, to_dev(x), out_level=lz)).reshape(nc, nc, nc)
+    ends = (0, 1, nc // 2, nc - 2, nc - 1)
+    picks = [(a, b_, c) for a in ends for b_ in ends for c in ends]
+    picks += [tuple(int(v) for v in rng.integers(0, nc, 3)) for _ in range(2000 - len(picks))]
+    ref, got = [], []
+    for (j3, j2, j1) in picks:
+        (i3, w3), (i2, w2), (i1, w1) = cols[j3], cols[j2], cols[j1]
+        ref.append(np.einsum("k,j,i,kji->", w3, w2, w1, X[np.ix_(i3, i2, i1)]))
+        got.append(y[j3, j2, j1])
+    ref, got = np.array(ref), np.array(got)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+    _say("[3d adp full size] Z sampled entries")
+    xc = rvec(nc ** 3, 37)
+    XC = xc.reshape(nc, nc, nc)
+    y = to_host(gs.apply("Z", 0, to_dev(xc))).reshape(n, n, n)
+    ends = (0, 1, 2, n // 2, n - 2, n - 1)
+    picks = [(a, b_, c) for a in ends for b_ in ends for c in ends]
+    picks += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(2000 - len(picks))]
+    ref, got = [], []
+    for (i3, i2, i1) in picks:
+        (j3, w3), (j2, w2), (j1, w1) = rows[i3], rows[i2], rows[i1]
+        ref.append(np.einsum("k,j,i,kji->", w3, w2, w1, XC[np.ix_(j3, j2, j1)]) if len(j3) * len(j2) * len(j1) else 0.0)
+        got.append(y[i3, i2, i1])
+    ref, got = np.array(ref), np.array(got)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+    f = gp.point_source((0.5, 0.5, 0.5))
+    _say("[3d adp full size] FP64 solve")
+    u, info = B.Solver(gp, **opts, tol=1e-10, maxit=800).solve(f)
+    assert info["converged"] == 1
+    r = f - gs.apply("A", 0, u)
+    rel_true = (torch.linalg.norm(r) / torch.linalg.norm(f)).item()
+    _say(f"[3d adp full size] iters {info['iters']}, true relative residual {rel_true:.2e}")
+    assert rel_true <= 1e-10 and abs(rel_true - info["relres_true"]) <= 1e-3 * rel_true
