@@ -116,10 +116,11 @@ def test_3d_galerkin_equals_rediscretisation(p):
     assert lev[1].P.shape == (lev[0].N, lev[1].N)
 
 
-@pytest.mark.parametrize("defl_mode", [0, 1])
+@pytest.mark.parametrize("defl_mode", [0, 1, 2])
 def test_3d_solver_matches_direct_solve(defl_mode):
     prob = hz.Problem(3, 2, (12, 10, 14), 8.0)
-    s = osv.Solver(prob, osv.Options(defl_mode=defl_mode, mg_min_elems=3, tol=1e-10))
+    extra = dict(defl_direct_max=64, defl_kh_max=0) if defl_mode == 2 else {}
+    s = osv.Solver(prob, osv.Options(defl_mode=defl_mode, mg_min_elems=3, tol=1e-10, **extra))
     f = hz.point_source_rhs(prob, (0.4, 0.55, 0.3))
     u, info = s.solve(f)
     assert info.converged and info.relres_true <= 1e-10
@@ -127,6 +128,10 @@ def test_3d_solver_matches_direct_solve(defl_mode):
     assert np.linalg.norm(u - ud) / np.linalg.norm(ud) <= 1e-7
     if defl_mode == 1:
         assert s.Lz == 1
+    if defl_mode == 2:
+        # multilevel: an inner FGMRES on level 1, the exact solve further down (the k h rule is
+        # off, so that on this small mesh the deflation reaches past level 1)
+        assert s.Lz >= 2 and s.levels[s.Lz].N <= 64 < s.levels[1].N
 
 
 def test_3d_rejects_variable_k_and_other_preconditioners():
