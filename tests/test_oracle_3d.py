@@ -167,7 +167,8 @@ def test_3d_finest_level_damping_keeps_the_vcycle_contracting(p, n_el, k):
 
 def test_3d_adp_vectors_are_the_tensor_product_and_deflate():
     """ADP on the cube: Z = Z_z (x) Z_y (x) Z_x with x fastest (each column the product of three
-    1D columns), and the deflation identities P_D A Z = 0, Q A Z = Z hold."""
+    1D columns), the deflation identities P_D A Z = 0, Q A Z = Z hold, and the ADP-deflated
+    solve reaches the direct solution."""
     prob = hz.Problem(3, 3, (10, 8, 12), 6.0)
     n = [m + 1 for m in prob.n_el]
     Z = osv.adp_deflation(n, 3, 0.2).toarray()
@@ -179,7 +180,7 @@ def test_3d_adp_vectors_are_the_tensor_product_and_deflate():
         col = Z[:, (J[2] * nc[1] + J[1]) * nc[0] + J[0]].reshape(n[2], n[1], n[0])
         ref = np.einsum("k,j,i->kji", Zs[2][:, J[2]], Zs[1][:, J[1]], Zs[0][:, J[0]])
         assert np.array_equal(col, ref)
-    s = osv.Solver(prob, osv.Options(defl_mode=1, defl_z=1, defl_eps=0.2, mg_min_elems=3))
+    s = osv.Solver(prob, osv.Options(defl_mode=1, defl_z=1, defl_eps=0.2, mg_min_elems=3, tol=1e-10))
     A = s.levels[0].A
     AZ = (A @ s.Zadp).toarray()
     E = s.Eadp.toarray()
@@ -187,3 +188,8 @@ def test_3d_adp_vectors_are_the_tensor_product_and_deflate():
     assert np.abs(Q_AZ - s.Zadp.toarray()).max() <= 1e-9
     PAZ = AZ - A @ Q_AZ
     assert np.abs(PAZ).max() <= 1e-9 * np.abs(AZ).max()
+    f = hz.point_source_rhs(prob, (0.3, 0.65, 0.45))
+    u, info = s.solve(f)
+    assert info.converged and info.relres_true <= 1e-10
+    ud = spla.spsolve(A.tocsc().astype(complex), f)
+    assert np.linalg.norm(u - ud) / np.linalg.norm(ud) <= 1e-7
