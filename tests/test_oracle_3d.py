@@ -15,11 +15,11 @@ from oracle import helmholtz as hz
 from oracle import solver as osv
 
 
-def _full_3d_galerkin(n_el, p):
-    """K and M of the full 3D tensor basis by Gauss quadrature over every element:
-    K = int grad Phi_I . grad Phi_J, M = int Phi_I Phi_J, with Phi_I at index
-    (i3 * m2 + i2) * m1 + i1 (m_d = n_el_d + p functions per direction)."""
-    bks = [bs.uniform_breakpoints(n) for n in n_el]
+def _full_3d_galerkin(n_el, p, lengths=(1.0, 1.0, 1.0)):
+    """K and M of the full 3D tensor basis by Gauss quadrature over every element of the box
+    [0, L1] x [0, L2] x [0, L3]: K = int grad Phi_I . grad Phi_J, M = int Phi_I Phi_J, with Phi_I
+    at index (i3 * m2 + i2) * m1 + i1 (m_d = n_el_d + p functions per direction)."""
+    bks = [np.linspace(0.0, L, n + 1) for n, L in zip(n_el, lengths)]
     m = [n + p for n in n_el]
     gx, gw = bs.gauss_legendre(p + 2)
     Ntot = m[0] * m[1] * m[2]
@@ -64,6 +64,17 @@ def test_3d_operators_equal_brute_force_quadrature(p, n_el):
     K, Mk = hz.fine_operators(hz.Problem(3, p, n_el, k))
     Kr, Mr = _full_3d_galerkin(n_el, p)
     assert K.shape == Kr.shape
+    assert np.allclose(K.toarray(), Kr, rtol=1e-12, atol=1e-12 * np.abs(Kr).max())
+    assert np.allclose(Mk.toarray(), k * k * Mr, rtol=1e-12, atol=1e-12 * k * k * np.abs(Mr).max())
+
+
+def test_3d_box_operators_equal_brute_force_quadrature():
+    """On [0, 1.4] x [0, 0.6] x [0, 1.0] (three different lengths, meshes of different sizes):
+    a length applied to the wrong direction changes K (M depends on the lengths' product only, and
+    pins that)."""
+    p, n_el, L, k = 2, (3, 2, 4), (1.4, 0.6, 1.0), 1.5
+    K, Mk = hz.fine_operators(hz.Problem(3, p, n_el, k, lengths=L))
+    Kr, Mr = _full_3d_galerkin(n_el, p, L)
     assert np.allclose(K.toarray(), Kr, rtol=1e-12, atol=1e-12 * np.abs(Kr).max())
     assert np.allclose(Mk.toarray(), k * k * Mr, rtol=1e-12, atol=1e-12 * k * k * np.abs(Mr).max())
 
