@@ -114,6 +114,21 @@ def test_physical_source_point():
     assert abs(c @ f - uh) <= 1e-12 * max(1.0, abs(uh))
 
 
+def test_physical_source_point_3d():
+    """c . f = u_h(x0) at a physical point of [0, 1] x [0, 0.6] x [0, 0.8]; spans from x0 / L."""
+    p, n_el, L = 2, (6, 5, 7), (1.0, 0.6, 0.8)
+    prob = hz.Problem(3, p, n_el, 4.0, lengths=L)
+    x0 = (0.7, 0.2, 0.5)
+    assert hz.source_spans(prob, x0) == [int(np.floor(x0[d] / L[d] * n_el[d])) for d in range(3)]
+    f = hz.point_source_rhs(prob, x0).real
+    n = [m + p - 2 for m in n_el]
+    c = np.random.default_rng(4).standard_normal(n[0] * n[1] * n[2])
+    v = [bs.basis_all(np.linspace(0, L[d], n_el[d] + 1), p, x0[d])[1:-1] for d in range(3)]
+    uh = np.einsum("kji,k,j,i->", c.reshape(n[2], n[1], n[0]), v[2], v[1], v[0])
+    assert abs(c @ f - uh) <= 1e-12 * max(1.0, abs(uh))
+    assert np.count_nonzero(f) == (p + 1) ** 3
+
+
 @pytest.mark.parametrize("dim,n_el,L", [(1, 60, (3.0,)), (2, (24, 12), (2.0, 1.0)), (3, (12, 8, 10), (1.0, 0.6, 0.8))])
 def test_solver_on_a_box_matches_direct_solve(dim, n_el, L):
     prob = hz.Problem(dim, 2, n_el, 8.0, lengths=L)
